@@ -1,0 +1,152 @@
+/*
+ * quake.h - C ABI of the MI355X partitioned vector index.
+ *
+ * The library answers the problem of Sec. 2.1 of "Quake: Adaptive Indexing
+ * for Vector Search" (Mohoney et al., OSDI'25): given a query q, return the
+ * top-k nearest neighbours of q in the vector set X, while batched inserts
+ * and deletes change X.  X is kept in disjoint partitions, each with a
+ * centroid (Sec. 3, index structure); a search ranks the centroids, scans the
+ * vectors of the chosen partitions and merges a per-query top-k.  The number
+ * of partitions scanned is either fixed (nprobe) or chosen per query by
+ * Adaptive Partition Scanning (Sec. 5, Algorithm "Adaptive Partition
+ * Scanning"), which stops once its recall model (Eqs. aps-pi, aps-p0,
+ * aps-pi-final) says the recall target is met.
+ *
+ * Conventions for every entry point:
+ *  - Return value: QUAKE_OK (0) or a negative QUAKE_E_* code; the message of
+ *    the last failure on the calling thread is quake_last_error().
+ *  - Array arguments are DEVICE pointers (HIP device memory on the current
+ *    device) owned by the caller; the library reads or writes them during the
+ *    call only and never frees them.  Outputs are caller-allocated.
+ *  - Matrices are row-major and dense: x[n][d], q[nq][d] float32.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  The call enqueues
+ *    its work on that stream and returns after the results are written
+ *    (search and update calls synchronise the stream before returning).
+ *  - An index handle is not thread-safe: one caller at a time.
+ *  - The index owns all of its device state and releases it in quake_free.
+ */
+#ifndef QUAKE_H
+#define QUAKE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct quake_index quake_index;
+
+enum {
+  QUAKE_OK = 0,
+  QUAKE_E_INVALID = -1,   /* bad argument (sizes, k, modes, non-finite input) */
+  QUAKE_E_NOMEM = -2,     /* the index would exceed its HBM budget, or hipMalloc failed */
+  QUAKE_E_NOTFOUND = -3,  /* a delete batch names an id that is absent; nothing applied */
+  QUAKE_E_DUPLICATE = -4, /* an insert batch repeats an id or names a present one; nothing applied */
+  QUAKE_E_DEVICE = -5,    /* a HIP call failed */
+  QUAKE_E_STATE = -6      /* the handle is not usable (NULL, freed, wrong level count) */
+};
+
+enum { QUAKE_L2 = 0, QUAKE_IP = 1 };
+enum { QUAKE_F32 = 0, QUAKE_BF16 = 1, QUAKE_F16 = 2 };
+enum { QUAKE_SCAN_PLAIN = 0, QUAKE_SCAN_BATCHED = 1 };
+
+/* Build parameters (Sec. 3 index structure; k-means partitioning, Sec. 1). */
+typedef struct {
+  int32_t metric;          /* QUAKE_L2 (squared Euclidean) or QUAKE_IP (inner product; rows
+                              should be unit-norm, centroids are renormalised: spherical k-means) */
+  int32_t storage_dtype;   /* extra reduced-precision copy of the vectors: QUAKE_F32 = none,
+                              QUAKE_BF16 or QUAKE_F16 (used by scan_dtype != QUAKE_F32) */
+  int32_t n_levels;        /* 1, or 2 (level 1 partitions the level-0 centroids) */
+  int32_t kmeans_iters;    /* Lloyd iterations (>= 0) when centroids are not given */
+  int64_t nlist;           /* level-0 partitions, 1 <= nlist <= n */
+  int64_t nlist_top;       /* level-1 partitions when n_levels == 2 */
+  uint64_t seed;           /* k-means initialisation */
+  const float* centroids;  /* optional device [nlist][d]: use these centroids (no k-means) */
+  size_t hbm_budget_bytes; /* 0 = unlimited; else every device allocation of the index counts */
+  double capacity_slack;   /* extra partition capacity for inserts, fraction of size (>= 0) */
+} quake_build_params;
+
+/* Search parameters.  Exactly one of nprobe > 0 (fixed number of partitions)
+ * or 0 < recall_target <= 1 (Adaptive Partition Scanning) must be set. */
+typedef struct {
+  int32_t k;               /* 1 <= k <= 256 */
+  int32_t nprobe;          /* fixed-nprobe mode: scan the nprobe nearest partitions */
+  double recall_target;    /* APS mode: tau_R of Alg. "Adaptive Partition Scanning" */
+  double f_M;              /* APS initial candidate fraction (paper: 1%..10%); 0 -> 0.05 */
+  double tau_rho;          /* APS recompute threshold (paper: 1%); 0 -> 0.01 */
+  double upper_recall_target; /* two-level: level-1 target (paper fixes 99%); 0 -> 0.99 */
+  double upper_f_M;        /* two-level: level-1 candidate fraction; 0 -> 0.25 */
+  int32_t scan_mode;       /* QUAKE_SCAN_PLAIN: per-(query, partition) scans;
+                              QUAKE_SCAN_BATCHED: queries grouped per partition (Sec. 7.5) */
+  int32_t scan_dtype;      /* QUAKE_F32, or the index's reduced-precision copy */
+  int32_t rerank_factor;   /* reduced precision: keep rerank_factor*k candidates, rerank in FP32;
+                              0 -> 4 */
+  int32_t window;          /* first-round speculation window (partitions per query); 0 -> auto */
+} quake_search_params;
+
+/* Build an index over x[n][d] (device, float32) with ids[n] (device int64,
+ * unique, >= 0; NULL -> 0..n-1).  Runs k-means on the device unless
+ * params->centroids is given; every vector is then placed in its nearest
+ * centroid's partition.  *out receives the new handle.
+ * Errors: INVALID (n < 1, d < 1 or > 4096, nlist out of range, bad enums),
+ * DUPLICATE (repeated ids), NOMEM, DEVICE. */
+int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d,
+                const quake_build_params* params, void* stream, quake_index** out);
+
+/* Search nq queries q[nq][d] (device float32).  Writes out_ids[nq][k]
+ * (device int64) and out_dist[nq][k] (device float32): squared L2 distances
+ * ascending, or inner products descending; ties go to the lower id; missing
+ * results are id -1 with +inf (L2) / -inf (IP).  Optional outputs (NULL to
+ * skip): out_nscanned[nq] (device int32, partitions scanned at level 0) and
+ * out_recall[nq] (device float64, the recall estimate at stop; 1 in nprobe mode).
+ * Errors: INVALID (nq < 0, k, both/neither of nprobe / recall_target,
+ * scan_dtype without a matching copy), NOMEM, DEVICE. */
+int quake_search(quake_index* index, const float* q, int64_t nq, const quake_search_params* params,
+                 int64_t* out_ids, float* out_dist, int32_t* out_nscanned, double* out_recall,
+                 void* stream);
+
+/* Insert n vectors x[n][d] (device float32) with ids[n] (device int64) as one
+ * batch (Sec. 2.1 updates; Sec. 3: each vector goes top-down to its nearest
+ * leaf partition and is appended there).  Centroids do not move.
+ * Errors: DUPLICATE (repeated id or id already present; nothing applied),
+ * INVALID, NOMEM, DEVICE. */
+int quake_insert(quake_index* index, const float* x, const int64_t* ids, int64_t n, void* stream);
+
+/* Delete the vectors with ids[n] (device int64) as one batch (Sec. 3: found
+ * through the id map and removed).  Errors: NOTFOUND (an id is absent or
+ * repeated; nothing applied), INVALID, DEVICE. */
+int quake_delete(quake_index* index, const int64_t* ids, int64_t n, void* stream);
+
+/* Host-side counters: live vectors, level-0 partitions, device bytes held. */
+int quake_stats(const quake_index* index, int64_t* n_live, int64_t* n_partitions, size_t* device_bytes);
+
+/* Export the level-0 partitioning for checking: centroids[nlist][d] (device
+ * float32), and for every live vector its id and partition (device int64
+ * ids[n_live], int32 part[n_live], in store order).  Any pointer may be NULL. */
+int quake_export(const quake_index* index, float* centroids, int64_t* ids, int32_t* part, void* stream);
+
+/* Export the level-1 partitioning of a two-level index: top centroids
+ * [nlist_top][d] (device float32) and the top partition of every level-0
+ * centroid, top_of[nlist] (device int32). */
+int quake_export_top(const quake_index* index, float* top_centroids, int32_t* top_of, void* stream);
+
+/* Candidate order of Adaptive Partition Scanning for nq queries, without
+ * scanning: order[nq][M] (device int32, c_0 first, then ascending bisector
+ * distance) and h[nq][M] (device float32, h[.][0] = 0).  M = ceil(f_M * nlist)
+ * clamped to [1, nlist]; *out_M receives it.  Single-level indexes only. */
+int quake_candidates(quake_index* index, const float* q, int64_t nq, double f_M,
+                     int32_t* order, float* h, int32_t* out_M, void* stream);
+
+/* The recall model's cap-volume table for dimension d (host memory): the
+ * volume share of a d-ball beyond a hyperplane at distance t, at the 1,024
+ * points t_j = j / 1023 (Sec. 5.3).  Host-only, no device needed. */
+int quake_cap_table(int32_t d, double* out_1024);
+
+void quake_free(quake_index* index);
+const char* quake_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QUAKE_H */

@@ -1,0 +1,21 @@
+"""MI355X partitioned vector index: adaptive partition scanning on gfx950.
+
+The compute path is the HIP library libquake_mi355x.so (C ABI in
+include/quake.h); ``quake`` is its Python binding.
+"""
+
+from .quake import (  # noqa: F401
+    Index,
+    QuakeError,
+    load_library,
+    quake_build,
+    quake_candidates,
+    quake_cap_table,
+    quake_delete,
+    quake_export,
+    quake_export_top,
+    quake_free,
+    quake_insert,
+    quake_search,
+    quake_stats,
+)

@@ -1,0 +1,175 @@
+// Device-side building blocks shared by the kernels: the (key, id) total
+// order of results, a wave-wide sorted top-k list, an LDS bitonic sort and a
+// co-rank merge of two sorted lists.
+//
+// Result order: a result is a pair (key, id) with key = squared L2 distance,
+// or the negated inner product, so that smaller is better for both metrics;
+// equal keys are ordered by the lower id.  Empty slots are (+inf, -1).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "index.hpp"
+
+namespace qk {
+
+constexpr int WAVE = 64;
+constexpr float KEY_EMPTY = __builtin_inff();
+
+__device__ __forceinline__ bool kv_less(float ak, int64_t ai, float bk, int64_t bi) {
+  return ak < bk || (ak == bk && ai < bi);
+}
+
+// Order-preserving map of a float to uint32 (finite values and +-inf).
+__device__ __forceinline__ uint32_t float_order(float f) {
+  uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__device__ __forceinline__ int64_t shfl_up_i64(int64_t v, int delta) {
+  int lo = __shfl_up((int)(uint32_t)(uint64_t)v, delta);
+  int hi = __shfl_up((int)(uint32_t)((uint64_t)v >> 32), delta);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int lane) {
+  uint32_t lo = __builtin_amdgcn_readlane((uint32_t)(uint64_t)v, lane);
+  uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), lane);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+  return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), lane));
+}
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  uint64_t b = (uint64_t)__double_as_longlong(v);
+  uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, lane);
+  uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_prod_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ float wave_sum_f(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// A sorted list of up to 64*KPL results spread over the lanes of one wave:
+// position p = t*64 + lane lives in slot t of that lane.  The list keeps the
+// best results seen; `thr` is the entry a new result must beat: the k-th
+// entry once k results exist, else the seed the list started from.
+template <int KPL>
+struct WaveTopK {
+  float key[KPL];
+  int64_t id[KPL];
+  float tk;
+  int64_t ti;
+  float seed_k;
+  int64_t seed_i;
+  int k;
+
+  __device__ void init(int k_, float sk, int64_t si) {
+    k = k_;
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) { key[t] = KEY_EMPTY; id[t] = -1; }
+    seed_k = sk; seed_i = si;
+    tk = sk; ti = si;
+  }
+
+  // Insert a wave-uniform candidate that beats thr.
+  __device__ void insert(float ck, int64_t ci) {
+    const int lane = lane_id();
+    int pos = 0;
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) pos += __popcll(__ballot(kv_less(key[t], id[t], ck, ci)));
+    float nk[KPL];
+    int64_t ni[KPL];
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) {
+      float uk = __shfl_up(key[t], 1);
+      int64_t ui = shfl_up_i64(id[t], 1);
+      if (t > 0) {
+        float ck2 = readlane_f(key[t - 1], WAVE - 1);
+        int64_t ci2 = readlane_i64(id[t - 1], WAVE - 1);
+        if (lane == 0) { uk = ck2; ui = ci2; }
+      }
+      const int p = t * WAVE + lane;
+      nk[t] = key[t]; ni[t] = id[t];
+      if (p > pos) { nk[t] = uk; ni[t] = ui; }
+      else if (p == pos) { nk[t] = ck; ni[t] = ci; }
+    }
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) { key[t] = nk[t]; id[t] = ni[t]; }
+    const int kt = (k - 1) / WAVE, kl = (k - 1) % WAVE;
+    float kk = KEY_EMPTY;
+    int64_t ki = -1;
+#pragma unroll
+    for (int t = 0; t < KPL; ++t)
+      if (t == kt) { kk = readlane_f(key[t], kl); ki = readlane_i64(id[t], kl); }
+    if (ki >= 0) { tk = kk; ti = ki; }
+  }
+
+  __device__ void store(float* ok, int64_t* oi) const {
+    const int lane = lane_id();
+#pragma unroll
+    for (int t = 0; t < KPL; ++t) {
+      const int p = t * WAVE + lane;
+      if (p < k) { ok[p] = key[t]; oi[p] = id[t]; }
+    }
+  }
+};
+
+// Bitonic sort of n (power of two) uint64 keys in LDS, ascending; all
+// threads of the block take part.
+__device__ inline void bitonic_sort_u64(uint64_t* s, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int i = threadIdx.x; i < (n >> 1); i += blockDim.x) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = ((lo & size) == 0);
+        uint64_t a = s[lo], b = s[hi];
+        if ((a > b) == up) { s[lo] = b; s[hi] = a; }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Number of entries of the sorted list (bk, bi)[0..n) that precede (k, i)
+// (strict = true) or that do not follow it (strict = false).
+__device__ __forceinline__ int corank(const float* bk, const int64_t* bi, int n, float k, int64_t i, bool strict) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    const bool before = strict ? kv_less(bk[mid], bi[mid], k, i) : !kv_less(k, i, bk[mid], bi[mid]);
+    if (before) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Merge the sorted lists A and B (length n each, padded with empties) into
+// the first n entries of their union, written to O.  One wave.  A's entries
+// go before B's on exact equality, which only empties can have.
+__device__ inline void wave_merge(const float* ak, const int64_t* ai, const float* bk, const int64_t* bi,
+                                  float* ok, int64_t* oi, int n) {
+  for (int e = lane_id(); e < n; e += WAVE) {
+    const int pa = e + corank(bk, bi, n, ak[e], ai[e], true);
+    if (pa < n) { ok[pa] = ak[e]; oi[pa] = ai[e]; }
+    const int pb = e + corank(ak, ai, n, bk[e], bi[e], false);
+    if (pb < n) { ok[pb] = bk[e]; oi[pb] = bi[e]; }
+  }
+}
+
+}  // namespace qk

@@ -1,0 +1,167 @@
+// Host-side index state, device memory accounting and kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "quake.h"
+
+namespace qk {
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define QK_HIP(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      throw ::qk::Error{QUAKE_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+#define QK_CHECK(cond, code, msg) \
+  do {                            \
+    if (!(cond)) throw ::qk::Error{code, std::string(msg)}; \
+  } while (0)
+
+constexpr int TILE = 64;          // vectors per store tile: one per lane of a wave
+constexpr int KMAX = 256;         // largest k of the search path
+constexpr int CAP_TABLE_POINTS = 1024;
+constexpr int MAX_DIM = 4096;
+constexpr int MAX_CANDIDATES = 4096;   // APS candidate set M (and nprobe) upper bound
+
+// Device allocations of one index, counted against an optional budget.
+class DeviceMemory {
+ public:
+  size_t used = 0;
+  size_t budget = 0;  // 0 = unlimited
+  template <class T>
+  T* alloc(size_t count) { return static_cast<T*>(raw_alloc(count * sizeof(T))); }
+  void* raw_alloc(size_t bytes);
+  void release(void* p);
+  ~DeviceMemory();
+
+ private:
+  struct Block { void* p; size_t bytes; };
+  std::vector<Block> blocks_;
+};
+
+// One level's partitions.  Vectors of partition p occupy tiles
+// [off[p], off[p] + cap[p]/64) of the arena; the first size[p] slots are
+// filled.  Within a tile, FP32 data is laid out [dp/4][64 lanes][4] and the
+// 16-bit copy [dp/8][64 lanes][8], so that a wave reading one 16-byte chunk
+// of 64 consecutive vectors touches one contiguous 1 KiB span.
+struct Store {
+  int32_t d = 0, dp = 0;
+  int64_t nlist = 0;
+  float* centroids = nullptr;   // [nlist][dp]
+  int64_t* d_off = nullptr;     // [nlist] first tile of each partition
+  int32_t* d_size = nullptr;    // [nlist] filled slots (deleted slots hold id -1)
+  int32_t* d_cap = nullptr;     // [nlist] slots (multiple of 64)
+  std::vector<int64_t> off;
+  std::vector<int32_t> size, cap;
+  int64_t tiles = 0;            // arena tiles allocated
+  int64_t used_tiles = 0;       // arena tiles handed out
+  float* v32 = nullptr;
+  uint16_t* v16 = nullptr;      // BF16 or FP16 copy, or null
+  int64_t* ids = nullptr;       // [tiles * 64], -1 = empty or deleted
+  int64_t live = 0;
+};
+
+struct Workspace {
+  int64_t nq_cap = 0, scores_cap = 0, cand_cap = 0, k_cap = 0, items_cap = 0, kk_cap = 0;
+  float* q = nullptr;           // [nq][dp] queries, zero padded
+  double* qn2 = nullptr;        // [nq] |q|^2
+  float* scores = nullptr;      // [nq][ncent]
+  int32_t* sel = nullptr;       // [nq][M] nearest centroids by (value, id)
+  int32_t* cand = nullptr;      // [nq][M] candidate partitions in scan order
+  float* h = nullptr;           // [nq][M] bisector distances in scan order
+  int32_t* st_m = nullptr;      // committed partitions
+  int32_t* st_w = nullptr;      // window of the current round
+  int32_t* st_done = nullptr;
+  int64_t* st_item = nullptr;   // first work item of the round
+  int64_t* st_demand = nullptr;
+  double* st_rho = nullptr;
+  double* st_p0 = nullptr;
+  double* st_V = nullptr;
+  double* st_vsum = nullptr;
+  double* st_r = nullptr;
+  float* rk = nullptr;          // [nq][kk] committed results
+  int64_t* ri = nullptr;
+  int4* items = nullptr;        // (query, partition, first tile, end tile)
+  float* pk = nullptr;          // [items][kk] partial results
+  int64_t* pi = nullptr;
+  int64_t* total = nullptr;     // device counter
+  int64_t* h_total = nullptr;   // pinned host mirror
+};
+
+}  // namespace qk
+
+struct quake_index {
+  uint32_t magic = 0x51554b45u;
+  int32_t metric = QUAKE_L2;
+  int32_t storage = QUAKE_F32;
+  int32_t n_levels = 1;
+  int32_t d = 0, dp = 0;
+  qk::DeviceMemory mem;
+  qk::Store L0;                 // level 0: the vectors
+  qk::Store L1;                 // level 1 (two-level): the level-0 centroids
+  int32_t* top_of = nullptr;    // [L0.nlist] level-1 partition of each level-0 centroid
+  double* cap_table = nullptr;  // [1024] device copy of the recall model table
+  std::vector<double> h_cap_table;
+  qk::Workspace ws;
+};
+
+namespace qk {
+
+// cap_table.cpp
+void cap_fraction_table(int d, double* out /*[CAP_TABLE_POINTS]*/);
+double cap_fraction(double t, int d);
+
+// kernels: centroids and candidates (k_centroids.hip)
+void launch_pad_rows(const float* x, int64_t n, int d, int dp, float* out, double* norm2, hipStream_t s);
+void launch_scores(const float* q, int64_t nq, const float* c, int64_t nc, int dp, int metric, float* out,
+                   hipStream_t s);
+void launch_select(const float* scores, int64_t nq, int64_t nc, int M, int metric, int32_t* cand,
+                   hipStream_t s);
+void launch_geometry(const float* q, const float* c, int64_t nq, int dp, int M, int metric, const int32_t* sel,
+                     int32_t* order, float* h, hipStream_t s);
+void launch_assign(const float* x, int64_t n, int dp, const float* c, int64_t nc, int metric, int32_t* assign,
+                   hipStream_t s);
+void launch_kmeans_accumulate(const float* x, int64_t n, int dp, const int32_t* assign, float* sums,
+                              int32_t* counts, hipStream_t s);
+void launch_kmeans_update(const float* sums, const int32_t* counts, int64_t nc, int dp, int normalise,
+                          float* c, hipStream_t s);
+void launch_gather_rows(const float* x, int d, const int64_t* rows, int64_t nr, int dp, float* out,
+                        hipStream_t s);
+
+// kernels: store (k_store.hip)
+void launch_scatter(const float* x, int64_t n, int d, int dp, const int64_t* ids, const int64_t* slot,
+                    float* v32, uint16_t* v16, int dtype16, int64_t* sid, hipStream_t s);
+void launch_export(const Store& st, int64_t* ids, int32_t* part, const int64_t* part_first_out,
+                   hipStream_t s);
+
+// kernels: the scan rounds (k_scan.hip)
+struct RoundArgs {
+  int64_t nq;
+  int M;             // candidates per query
+  int k;             // results kept (k, or the rerank pool)
+  int aps;           // 1: adaptive; 0: fixed nprobe
+  int chunk_tiles;   // tiles per work item
+  int wmax;
+  int metric;
+  int dim;           // d, for nothing but documentation of the table
+  double tau_r, tau_rho;
+  int64_t items_cap;
+};
+void launch_round_init(Workspace& ws, const RoundArgs& a, int w0, hipStream_t s);
+void launch_demand(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
+void launch_emit(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
+void launch_scan_f32(Workspace& ws, const Store& st, const RoundArgs& a, int64_t nitems, hipStream_t s);
+void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const double* table, hipStream_t s);
+void launch_finalize(Workspace& ws, const RoundArgs& a, int64_t* out_ids, float* out_dist,
+                     int32_t* out_nscanned, double* out_recall, hipStream_t s);
+
+}  // namespace qk

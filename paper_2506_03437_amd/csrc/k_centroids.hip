@@ -1,0 +1,371 @@
+// Centroid-side kernels: query padding, centroid scoring, candidate selection,
+// bisector geometry for the recall model, and the k-means build steps.
+//
+// Distances are squared Euclidean in the difference form sum (a_i - b_i)^2,
+// never |a|^2 - 2ab + |b|^2: near neighbours sit far from the origin in these
+// workloads and the expansion would cancel most of the FP32 significand.
+// Sums over the dimension are blocked: 32-dimension partial sums are added to
+// a running total, which bounds the relative rounding error by about
+// (32 + d/32) * 2^-24 instead of d * 2^-24.
+#include "common.hpp"
+#include "index.hpp"
+
+namespace qk {
+
+// ---------------------------------------------------------------- padding
+
+__global__ __launch_bounds__(256) void k_pad_rows(const float* __restrict__ x, int64_t n, int d, int dp,
+                                                   float* __restrict__ out, double* __restrict__ norm2) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double acc = 0.0;
+  for (int j = lane; j < dp; j += WAVE) {
+    const float v = (j < d) ? x[row * d + j] : 0.0f;
+    out[row * dp + j] = v;
+    acc += (double)v * (double)v;
+  }
+  acc = wave_sum_d(acc);
+  if (norm2 && lane == 0) norm2[row] = acc;
+}
+
+void launch_pad_rows(const float* x, int64_t n, int d, int dp, float* out, double* norm2, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, x, n, d, dp, out, norm2);
+}
+
+// ---------------------------------------------------------------- scoring
+
+constexpr int ST = 64;      // rows / columns per score tile
+constexpr int SK = 32;      // dimensions per LDS stage (one blocked partial sum)
+constexpr int SLD = SK + 4; // LDS row stride (floats): 16-byte aligned, spreads banks
+
+// Stage a 64 x 32 slab of a row-major [rows][dp] matrix into LDS [64][SLD].
+__device__ __forceinline__ void stage_slab(float (*dst)[SLD], const float* __restrict__ src, int64_t row0,
+                                           int64_t rows, int dp, int k0) {
+  for (int e = threadIdx.x; e < ST * (SK / 4); e += 256) {
+    const int r = e >> 3, k4 = (e & 7) * 4;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t g = row0 + r;
+    if (g < rows && k0 + k4 < dp) v = *reinterpret_cast<const float4*>(src + g * dp + k0 + k4);
+    *reinterpret_cast<float4*>(&dst[r][k4]) = v;
+  }
+}
+
+// acc[i][j] += sum over the staged 32 dims of f(a[row ty+16i], b[row tx+16j]).
+template <int METRIC>
+__device__ __forceinline__ void tile_stage(const float (*qs)[SLD], const float (*cs)[SLD], int tx, int ty,
+                                           float acc[4][4]) {
+  float part[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) part[i][j] = 0.f;
+#pragma unroll 2
+  for (int kk = 0; kk < SK; kk += 4) {
+    float4 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const float4*>(&qs[ty + 16 * i][kk]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const float4*>(&cs[tx + 16 * j][kk]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (METRIC == QUAKE_L2) {
+          float t;
+          t = a[i].x - b[j].x; part[i][j] = fmaf(t, t, part[i][j]);
+          t = a[i].y - b[j].y; part[i][j] = fmaf(t, t, part[i][j]);
+          t = a[i].z - b[j].z; part[i][j] = fmaf(t, t, part[i][j]);
+          t = a[i].w - b[j].w; part[i][j] = fmaf(t, t, part[i][j]);
+        } else {
+          part[i][j] = fmaf(a[i].x, b[j].x, part[i][j]);
+          part[i][j] = fmaf(a[i].y, b[j].y, part[i][j]);
+          part[i][j] = fmaf(a[i].z, b[j].z, part[i][j]);
+          part[i][j] = fmaf(a[i].w, b[j].w, part[i][j]);
+        }
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] += part[i][j];
+}
+
+// S[q][c] = |q - c|^2 (L2) or q . c (IP) for a 64 x 64 tile per block.
+template <int METRIC>
+__global__ __launch_bounds__(256) void k_scores(const float* __restrict__ q, int64_t nq,
+                                                 const float* __restrict__ c, int64_t nc, int dp,
+                                                 float* __restrict__ out) {
+  __shared__ float qs[ST][SLD];
+  __shared__ float cs[ST][SLD];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t c0 = (int64_t)blockIdx.x * ST, q0 = (int64_t)blockIdx.y * ST;
+  float acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+  for (int k0 = 0; k0 < dp; k0 += SK) {
+    stage_slab(qs, q, q0, nq, dp, k0);
+    stage_slab(cs, c, c0, nc, dp, k0);
+    __syncthreads();
+    tile_stage<METRIC>(qs, cs, tx, ty, acc);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t qi = q0 + ty + 16 * i;
+    if (qi >= nq) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t ci = c0 + tx + 16 * j;
+      if (ci < nc) out[qi * nc + ci] = acc[i][j];
+    }
+  }
+}
+
+void launch_scores(const float* q, int64_t nq, const float* c, int64_t nc, int dp, int metric, float* out,
+                   hipStream_t s) {
+  if (nq <= 0 || nc <= 0) return;
+  dim3 grid((unsigned)((nc + ST - 1) / ST), (unsigned)((nq + ST - 1) / ST));
+  if (metric == QUAKE_L2)
+    hipLaunchKernelGGL(k_scores<QUAKE_L2>, grid, dim3(256), 0, s, q, nq, c, nc, dp, out);
+  else
+    hipLaunchKernelGGL(k_scores<QUAKE_IP>, grid, dim3(256), 0, s, q, nq, c, nc, dp, out);
+}
+
+// Nearest centroid of every row (k-means assignment and the build's final
+// placement).  Lower centroid index wins exact ties.
+template <int METRIC>
+__global__ __launch_bounds__(256) void k_assign(const float* __restrict__ x, int64_t n,
+                                                 const float* __restrict__ c, int64_t nc, int dp,
+                                                 int32_t* __restrict__ assign) {
+  __shared__ float qs[ST][SLD];
+  __shared__ float cs[ST][SLD];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * ST;
+  float best[4];
+  int32_t bidx[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) { best[i] = KEY_EMPTY; bidx[i] = 0x7fffffff; }
+  for (int64_t c0 = 0; c0 < nc; c0 += ST) {
+    float acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+    for (int k0 = 0; k0 < dp; k0 += SK) {
+      stage_slab(qs, x, r0, n, dp, k0);
+      stage_slab(cs, c, c0, nc, dp, k0);
+      __syncthreads();
+      tile_stage<METRIC>(qs, cs, tx, ty, acc);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t ci = c0 + tx + 16 * j;
+      if (ci >= nc) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float key = (METRIC == QUAKE_L2) ? acc[i][j] : -acc[i][j];
+        if (key < best[i] || (key == best[i] && (int32_t)ci < bidx[i])) { best[i] = key; bidx[i] = (int32_t)ci; }
+      }
+    }
+  }
+  // the 16 lanes tx = 0..15 of a row group hold different columns: reduce
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    for (int o = 8; o > 0; o >>= 1) {
+      const float ob = __shfl_xor(best[i], o);
+      const int32_t oi = __shfl_xor(bidx[i], o);
+      if (ob < best[i] || (ob == best[i] && oi < bidx[i])) { best[i] = ob; bidx[i] = oi; }
+    }
+    const int64_t row = r0 + ty + 16 * i;
+    if (tx == 0 && row < n) assign[row] = bidx[i];
+  }
+}
+
+void launch_assign(const float* x, int64_t n, int dp, const float* c, int64_t nc, int metric, int32_t* assign,
+                   hipStream_t s) {
+  if (n <= 0) return;
+  dim3 grid((unsigned)((n + ST - 1) / ST));
+  if (metric == QUAKE_L2)
+    hipLaunchKernelGGL(k_assign<QUAKE_L2>, grid, dim3(256), 0, s, x, n, c, nc, dp, assign);
+  else
+    hipLaunchKernelGGL(k_assign<QUAKE_IP>, grid, dim3(256), 0, s, x, n, c, nc, dp, assign);
+}
+
+// ---------------------------------------------------------------- selection
+
+constexpr int SORT_N = 4096;
+
+__device__ __forceinline__ uint64_t composite(float key, uint32_t idx) {
+  return ((uint64_t)float_order(key) << 32) | idx;
+}
+
+__device__ __forceinline__ float float_unorder(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+// The M best centroids of every query by (key, centroid id), ascending.
+__global__ __launch_bounds__(256) void k_select(const float* __restrict__ scores, int64_t nc, int M, int ip,
+                                                 int32_t* __restrict__ cand) {
+  __shared__ uint64_t buf[SORT_N];
+  const int64_t qi = blockIdx.x;
+  const float* s = scores + qi * nc;
+  int keep = 1;
+  while (keep < M) keep <<= 1;
+  int64_t next = 0;
+  int filled = 0;
+  bool first = true;
+  while (first || next < nc) {
+    const int base = first ? 0 : keep;
+    int64_t take = nc - next;
+    if (take > SORT_N - base) take = SORT_N - base;
+    int n = base + (int)take;
+    int p2 = 1;
+    while (p2 < n) p2 <<= 1;
+    for (int e = threadIdx.x; e < p2 - base; e += 256) {
+      uint64_t v = ~0ull;
+      if (e < take) {
+        const float raw = s[next + e];
+        v = composite(ip ? -raw : raw, (uint32_t)(next + e));
+      }
+      buf[base + e] = v;
+    }
+    next += take;
+    filled = n;
+    bitonic_sort_u64(buf, p2);
+    first = false;
+  }
+  (void)filled;
+  for (int i = threadIdx.x; i < M; i += 256) cand[qi * M + i] = (int32_t)(uint32_t)(buf[i] & 0xffffffffu);
+}
+
+void launch_select(const float* scores, int64_t nq, int64_t nc, int M, int metric, int32_t* cand,
+                   hipStream_t s) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(k_select, dim3((unsigned)nq), dim3(256), 0, s, scores, nc, M, metric == QUAKE_IP ? 1 : 0,
+                     cand);
+}
+
+// ---------------------------------------------------------------- geometry
+
+// Distance h_i from the query to the bisector hyperplane of c_0 and c_i,
+// evaluated as the projection (c_0 - c_i) . (q - (c_0 + c_i)/2) / |c_0 - c_i|
+// for L2 and q . (c_0 - c_i) / |c_0 - c_i| for inner product (the boundary
+// of the two inner-product cells), then the candidates after c_0 are put in
+// ascending h order; ties keep the (key, id) order of the selection.
+__global__ __launch_bounds__(256) void k_geometry(const float* __restrict__ q, const float* __restrict__ c, int dp,
+                                                   int M, int ip, const int32_t* __restrict__ sel,
+                                                   int32_t* __restrict__ order, float* __restrict__ hout) {
+  __shared__ uint64_t buf[SORT_N];
+  const int64_t qi = blockIdx.x;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t* cq = sel + qi * M;
+  const int c0 = cq[0];
+  const float* qv = q + qi * dp;
+  const float* c0v = c + (int64_t)c0 * dp;
+  for (int i = 1 + w; i < M; i += 4) {
+    const float* civ = c + (int64_t)cq[i] * dp;
+    float num = 0.f, sep = 0.f;
+    for (int j = lane; j < dp; j += WAVE) {
+      const float a = c0v[j], b = civ[j], x = qv[j];
+      const float diff = a - b;
+      sep = fmaf(diff, diff, sep);
+      num = ip ? fmaf(x, diff, num) : fmaf(diff, (x - a) + (x - b), num);
+    }
+    num = wave_sum_f(num);
+    sep = wave_sum_f(sep);
+    float h = 0.f;
+    if (sep > 0.f) h = ip ? num / sqrtf(sep) : num / (2.0f * sqrtf(sep));
+    h = fmaxf(h, 0.f);
+    if (lane == 0) buf[i - 1] = composite(h, (uint32_t)i);
+  }
+  int p2 = 1;
+  while (p2 < M - 1) p2 <<= 1;
+  for (int e = M - 1 + threadIdx.x; e < p2; e += 256) buf[e] = ~0ull;
+  if (M > 1) bitonic_sort_u64(buf, p2);
+  else __syncthreads();
+  for (int t = threadIdx.x; t < M; t += 256) {
+    if (t == 0) {
+      order[qi * M] = c0;
+      hout[qi * M] = 0.f;
+    } else {
+      const uint64_t e = buf[t - 1];
+      order[qi * M + t] = cq[(uint32_t)(e & 0xffffffffu)];
+      hout[qi * M + t] = float_unorder((uint32_t)(e >> 32));
+    }
+  }
+}
+
+void launch_geometry(const float* q, const float* c, int64_t nq, int dp, int M, int metric, const int32_t* sel,
+                      int32_t* order, float* h, hipStream_t s) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(k_geometry, dim3((unsigned)nq), dim3(256), 0, s, q, c, dp, M, metric == QUAKE_IP ? 1 : 0,
+                     sel, order, h);
+}
+
+// ---------------------------------------------------------------- k-means
+
+__global__ __launch_bounds__(256) void k_kmeans_accumulate(const float* __restrict__ x, int64_t n, int dp,
+                                                            const int32_t* __restrict__ assign,
+                                                            float* __restrict__ sums, int32_t* __restrict__ counts) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t row = e / dp;
+  const int j = (int)(e - row * dp);
+  if (row >= n) return;
+  const int a = assign[row];
+  atomicAdd(&sums[(int64_t)a * dp + j], x[row * dp + j]);
+  if (j == 0) atomicAdd(&counts[a], 1);
+}
+
+void launch_kmeans_accumulate(const float* x, int64_t n, int dp, const int32_t* assign, float* sums,
+                              int32_t* counts, hipStream_t s) {
+  const int64_t total = n * dp;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_kmeans_accumulate, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, x, n, dp, assign,
+                     sums, counts);
+}
+
+// c = sums / count for non-empty clusters (renormalised for spherical k-means).
+__global__ __launch_bounds__(64) void k_kmeans_update(const float* __restrict__ sums,
+                                                       const int32_t* __restrict__ counts, int dp, int normalise,
+                                                       float* __restrict__ c) {
+  const int64_t j = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int cnt = counts[j];
+  if (cnt == 0) return;
+  const float inv = 1.0f / (float)cnt;
+  float nrm = 0.f;
+  for (int t = lane; t < dp; t += WAVE) {
+    const float v = sums[j * dp + t] * inv;
+    nrm = fmaf(v, v, nrm);
+  }
+  nrm = wave_sum_f(nrm);
+  const float scale = (normalise && nrm > 0.f) ? inv / sqrtf(nrm) : inv;
+  for (int t = lane; t < dp; t += WAVE) c[j * dp + t] = sums[j * dp + t] * scale;
+}
+
+void launch_kmeans_update(const float* sums, const int32_t* counts, int64_t nc, int dp, int normalise, float* c,
+                          hipStream_t s) {
+  if (nc <= 0) return;
+  hipLaunchKernelGGL(k_kmeans_update, dim3((unsigned)nc), dim3(64), 0, s, sums, counts, dp, normalise, c);
+}
+
+__global__ __launch_bounds__(64) void k_gather_rows(const float* __restrict__ x, int d,
+                                                     const int64_t* __restrict__ rows, int dp,
+                                                     float* __restrict__ out) {
+  const int64_t r = blockIdx.x;
+  const int64_t src = rows[r];
+  for (int j = threadIdx.x; j < dp; j += WAVE) out[r * dp + j] = (j < d) ? x[src * d + j] : 0.f;
+}
+
+void launch_gather_rows(const float* x, int d, const int64_t* rows, int64_t nr, int dp, float* out,
+                        hipStream_t s) {
+  if (nr <= 0) return;
+  hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)nr), dim3(64), 0, s, x, d, rows, dp, out);
+}
+
+}  // namespace qk

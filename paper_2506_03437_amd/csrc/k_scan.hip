@@ -1,0 +1,450 @@
+// Scan rounds of a batched search.
+//
+// A search runs in rounds.  In each round every unfinished query names a
+// window of its next candidate partitions; the windows are cut into work
+// items of at most `chunk_tiles` store tiles; one wave scans one item and
+// keeps the item's best results; then one wave per query commits the items
+// in candidate order.  Committing follows Algorithm "Adaptive Partition
+// Scanning" (Sec. 5.2) one partition at a time: merge that partition's
+// results into the query's top-k, take rho from the k-th result, recompute
+// the recall model when rho moved by more than tau_rho, and stop once the
+// estimated recall reaches the target.  Partitions scanned past the stop
+// point are discarded, so the result is the one of the sequential algorithm;
+// scanning ahead only trades extra reads for fewer rounds.  With a fixed
+// nprobe the window is the whole candidate list and one round suffices.
+//
+// Recall model (Sec. 5.1, Eqs. aps-pi, aps-p0, aps-pi-final): with t_i =
+// h_i / rho, v_i is the volume share of the ball B(q, rho) beyond the
+// bisector of c_0 and c_i (looked up in the 1,024-point table of Sec. 5.3
+// with linear interpolation, 0 for t >= 1); p_0 = prod (1 - v_i) uses the raw
+// shares and the remaining 1 - p_0 is split in proportion to v_i, so the
+// estimate after scanning c_0 and the next m - 1 candidates is
+//   r = p_0 + (1 - p_0) * (v_1 + ... + v_{m-1}) / (v_1 + ... + v_{M-1}).
+// Until k results exist rho = +inf (all t = 0) and r is held at 0.  The
+// model is evaluated in FP64; it is the only FP64 on the device.
+#include "common.hpp"
+#include "index.hpp"
+
+namespace qk {
+
+__device__ __forceinline__ int item_chunks(int32_t size, int chunk_tiles) {
+  const int tiles = (size + TILE - 1) / TILE;
+  const int c = (tiles + chunk_tiles - 1) / chunk_tiles;
+  return c > 0 ? c : 1;
+}
+
+// ---------------------------------------------------------------- state
+
+__global__ __launch_bounds__(256) void k_round_init(int64_t nq, int kk, int w0, int32_t* __restrict__ st_m,
+                                                     int32_t* __restrict__ st_w, int32_t* __restrict__ st_done,
+                                                     double* __restrict__ rho, double* __restrict__ p0,
+                                                     double* __restrict__ V, double* __restrict__ vsum,
+                                                     double* __restrict__ r, float* __restrict__ rk,
+                                                     int64_t* __restrict__ ri) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < nq) {
+    st_m[e] = 0; st_w[e] = w0; st_done[e] = 0;
+    rho[e] = __builtin_inf(); p0[e] = 1.0; V[e] = 0.0; vsum[e] = 0.0; r[e] = 0.0;
+  }
+  if (e < nq * kk) { rk[e] = KEY_EMPTY; ri[e] = -1; }
+}
+
+void launch_round_init(Workspace& ws, const RoundArgs& a, int w0, hipStream_t s) {
+  const int64_t n = a.nq * a.k;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_round_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.nq, a.k, w0, ws.st_m,
+                     ws.st_w, ws.st_done, ws.st_rho, ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri);
+}
+
+// ---------------------------------------------------------------- planning
+
+// Work items each query needs for its window this round.
+__global__ __launch_bounds__(256) void k_demand(int64_t nq, int M, int chunk_tiles,
+                                                 const int32_t* __restrict__ cand, const int32_t* __restrict__ psize,
+                                                 const int32_t* __restrict__ st_m, int32_t* __restrict__ st_w,
+                                                 const int32_t* __restrict__ st_done, int64_t* __restrict__ demand) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= nq) return;
+  int64_t dmd = 0;
+  if (!st_done[q]) {
+    const int m = st_m[q];
+    int w = st_w[q];
+    if (w > M - m) w = M - m;
+    for (int j = 0; j < w; ++j) dmd += item_chunks(psize[cand[q * M + m + j]], chunk_tiles);
+    st_w[q] = w;
+  } else {
+    st_w[q] = 0;
+  }
+  demand[q] = dmd;
+}
+
+// Exclusive prefix sum of the demands (one block).  Queries whose items would
+// not fit in the item buffer sit this round out (window 0); the buffer always
+// holds the first unfinished query's window, so every round makes progress.
+__global__ __launch_bounds__(1024) void k_prefix(int64_t nq, int64_t cap, const int64_t* __restrict__ demand,
+                                                  int64_t* __restrict__ first, int32_t* __restrict__ st_w,
+                                                  int64_t* __restrict__ total) {
+  __shared__ int64_t part[1024];
+  __shared__ int64_t overflow_at;
+  const int t = threadIdx.x;
+  const int64_t per = (nq + 1023) / 1024;
+  const int64_t lo = t * per;
+  const int64_t hi = (lo + per < nq) ? lo + per : nq;
+  int64_t s = 0;
+  for (int64_t i = lo; i < hi; ++i) s += demand[i];
+  part[t] = s;
+  if (t == 0) overflow_at = nq;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t v = (t >= o) ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = part[t] - s;
+  for (int64_t i = lo; i < hi; ++i) {
+    first[i] = run;
+    if (run + demand[i] > cap) atomicMin((unsigned long long*)&overflow_at, (unsigned long long)i);
+    run += demand[i];
+  }
+  __syncthreads();
+  const int64_t cut = overflow_at;
+  for (int64_t i = lo; i < hi; ++i)
+    if (i >= cut) st_w[i] = 0;
+  if (t == 0) *total = (cut < nq) ? first[cut] : part[1023];
+}
+
+void launch_demand(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_demand, dim3((unsigned)((a.nq + 255) / 256)), dim3(256), 0, s, a.nq, a.M, a.chunk_tiles,
+                     ws.cand, st.d_size, ws.st_m, ws.st_w, ws.st_done, ws.st_demand);
+  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(1024), 0, s, a.nq, a.items_cap, ws.st_demand, ws.st_item, ws.st_w,
+                     ws.total);
+}
+
+// Write the work items of each query's window, in candidate order.
+__global__ __launch_bounds__(256) void k_emit(int64_t nq, int M, int chunk_tiles, const int32_t* __restrict__ cand,
+                                               const int32_t* __restrict__ psize, const int32_t* __restrict__ st_m,
+                                               const int32_t* __restrict__ st_w, const int64_t* __restrict__ first,
+                                               int4* __restrict__ items) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (q >= nq) return;
+  const int w = st_w[q];
+  if (w == 0) return;
+  const int m = st_m[q];
+  int64_t pos = first[q];
+  for (int j = 0; j < w; ++j) {
+    const int p = cand[q * M + m + j];
+    const int size = psize[p];
+    const int tiles = (size + TILE - 1) / TILE;
+    const int nch = item_chunks(size, chunk_tiles);
+    for (int c = lane; c < nch; c += WAVE) {
+      const int t0 = c * chunk_tiles;
+      const int t1 = (t0 + chunk_tiles < tiles) ? t0 + chunk_tiles : tiles;
+      items[pos + c] = make_int4((int)q, p, t0, t1);
+    }
+    pos += nch;
+  }
+}
+
+void launch_emit(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)((a.nq + 3) / 4)), dim3(256), 0, s, a.nq, a.M, a.chunk_tiles, ws.cand,
+                     st.d_size, ws.st_m, ws.st_w, ws.st_item, ws.items);
+}
+
+// ---------------------------------------------------------------- FP32 scan
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) f32x4 const_float4;
+
+// Distance of the query to the 64 vectors of one tile, one vector per lane.
+// The query is read through the scalar unit (one copy for the whole wave);
+// the tile through 16-byte loads that cover 1 KiB contiguous per wave.  Eight
+// partial sums (one per dimension modulo 8) are combined pairwise at the end.
+template <int METRIC>
+__device__ __forceinline__ float tile_distance(const float4* __restrict__ xp, const_float4* qs, int nch4) {
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f;
+#pragma unroll 4
+  for (int c = 0; c < nch4; c += 2) {
+    const float4 x = xp[(int64_t)c * WAVE];
+    const float4 y = xp[(int64_t)(c + 1) * WAVE];
+    const f32x4 qa = qs[c];
+    const f32x4 qb = qs[c + 1];
+    if (METRIC == QUAKE_L2) {
+      float t;
+      t = x.x - qa.x; a0 = fmaf(t, t, a0);
+      t = x.y - qa.y; a1 = fmaf(t, t, a1);
+      t = x.z - qa.z; a2 = fmaf(t, t, a2);
+      t = x.w - qa.w; a3 = fmaf(t, t, a3);
+      t = y.x - qb.x; a4 = fmaf(t, t, a4);
+      t = y.y - qb.y; a5 = fmaf(t, t, a5);
+      t = y.z - qb.z; a6 = fmaf(t, t, a6);
+      t = y.w - qb.w; a7 = fmaf(t, t, a7);
+    } else {
+      a0 = fmaf(x.x, qa.x, a0); a1 = fmaf(x.y, qa.y, a1);
+      a2 = fmaf(x.z, qa.z, a2); a3 = fmaf(x.w, qa.w, a3);
+      a4 = fmaf(y.x, qb.x, a4); a5 = fmaf(y.y, qb.y, a5);
+      a6 = fmaf(y.z, qb.z, a6); a7 = fmaf(y.w, qb.w, a7);
+    }
+  }
+  const float s = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
+  return METRIC == QUAKE_L2 ? s : -s;
+}
+
+template <int METRIC, int KPL>
+__global__ __launch_bounds__(256) void k_scan_f32(const int4* __restrict__ items, int64_t nitems,
+                                                   const float* __restrict__ qpad, int dp,
+                                                   const float* __restrict__ v32, const int64_t* __restrict__ sid,
+                                                   const int64_t* __restrict__ poff,
+                                                   const int32_t* __restrict__ psize,
+                                                   const float* __restrict__ rk, const int64_t* __restrict__ ri,
+                                                   int kk, float* __restrict__ pk, int64_t* __restrict__ pi) {
+  const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (it >= nitems) return;
+  const int4 item = items[it];
+  const int q = __builtin_amdgcn_readfirstlane(item.x);
+  const int p = __builtin_amdgcn_readfirstlane(item.y);
+  const int t0 = __builtin_amdgcn_readfirstlane(item.z);
+  const int t1 = __builtin_amdgcn_readfirstlane(item.w);
+  const float seed_k = rk[(int64_t)q * kk + kk - 1];
+  const int64_t seed_i = ri[(int64_t)q * kk + kk - 1];
+  WaveTopK<KPL> top;
+  top.init(kk, seed_k, seed_i);
+  const int64_t tile0 = poff[p];
+  const int size = psize[p];
+  const int nch4 = dp >> 2;
+  const_float4* qs = (const_float4*)(qpad + (int64_t)q * dp);
+  for (int t = t0; t < t1; ++t) {
+    const int64_t slot = (tile0 + t) * TILE + lane;
+    const float4* xp = reinterpret_cast<const float4*>(v32) + (tile0 + t) * (int64_t)nch4 * WAVE + lane;
+    const float key = tile_distance<METRIC>(xp, qs, nch4);
+    const bool valid = (t * TILE + lane) < size;
+    bool pass = false;
+    int64_t myid = -1;
+    if (valid && !(key > top.tk)) {
+      myid = sid[slot];
+      pass = myid >= 0 && kv_less(key, myid, top.tk, top.ti);
+    }
+    uint64_t mask = __ballot(pass);
+    while (mask) {
+      const int src = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      const float ck = readlane_f(key, src);
+      const int64_t ci = readlane_i64(myid, src);
+      if (kv_less(ck, ci, top.tk, top.ti)) top.insert(ck, ci);
+    }
+  }
+  top.store(pk + it * kk, pi + it * kk);
+}
+
+template <int METRIC>
+static void scan_f32_k(Workspace& ws, const Store& st, const RoundArgs& a, int64_t nitems, hipStream_t s) {
+  const dim3 grid((unsigned)((nitems + 3) / 4));
+  if (a.k <= 64)
+    hipLaunchKernelGGL((k_scan_f32<METRIC, 1>), grid, dim3(256), 0, s, ws.items, nitems, ws.q, st.dp, st.v32, st.ids,
+                       st.d_off, st.d_size, ws.rk, ws.ri, a.k, ws.pk, ws.pi);
+  else if (a.k <= 128)
+    hipLaunchKernelGGL((k_scan_f32<METRIC, 2>), grid, dim3(256), 0, s, ws.items, nitems, ws.q, st.dp, st.v32, st.ids,
+                       st.d_off, st.d_size, ws.rk, ws.ri, a.k, ws.pk, ws.pi);
+  else
+    hipLaunchKernelGGL((k_scan_f32<METRIC, 4>), grid, dim3(256), 0, s, ws.items, nitems, ws.q, st.dp, st.v32, st.ids,
+                       st.d_off, st.d_size, ws.rk, ws.ri, a.k, ws.pk, ws.pi);
+}
+
+void launch_scan_f32(Workspace& ws, const Store& st, const RoundArgs& a, int64_t nitems, hipStream_t s) {
+  if (nitems <= 0) return;
+  if (a.metric == QUAKE_L2) scan_f32_k<QUAKE_L2>(ws, st, a, nitems, s);
+  else scan_f32_k<QUAKE_IP>(ws, st, a, nitems, s);
+}
+
+// ---------------------------------------------------------------- commit
+
+__device__ __forceinline__ double cap_share(const double* __restrict__ table, double t) {
+  if (!(t < 1.0)) return 0.0;
+  if (t < 0.0) t = 0.0;
+  const double pos = t * (double)(CAP_TABLE_POINTS - 1);
+  int j = (int)pos;
+  if (j > CAP_TABLE_POINTS - 2) j = CAP_TABLE_POINTS - 2;
+  const double f = pos - (double)j;
+  const double a = table[j], b = table[j + 1];
+  return a + f * (b - a);
+}
+
+// Euclidean distance to a result key: sqrt of the squared L2 distance, or for
+// inner product on unit-norm data sqrt(|q|^2 + 1 - 2 s) with s = -key.
+__device__ __forceinline__ double key_radius(float key, int ip, double qn2) {
+  if (ip) {
+    const double v = qn2 + 1.0 + 2.0 * (double)key;
+    return sqrt(v > 0.0 ? v : 0.0);
+  }
+  return sqrt((double)(key > 0.f ? key : 0.f));
+}
+
+struct Model {
+  double rho, p0, V, vsum;
+};
+
+// p_0, V = sum v_i and the committed mass v_1 + ... + v_{m-1} for radius rho.
+__device__ void recompute_model(Model& md, double rho, const float* __restrict__ hq, int M, int committed,
+                                const double* __restrict__ table) {
+  const int lane = lane_id();
+  double vs = 0.0, pr = 1.0, vc = 0.0;
+  const bool inf = __builtin_isinf(rho);
+  for (int i = 1 + lane; i < M; i += WAVE) {
+    const double t = inf ? 0.0 : (double)hq[i] / rho;
+    const double v = cap_share(table, t);
+    vs += v;
+    pr *= (1.0 - v);
+    if (i < committed) vc += v;
+  }
+  md.rho = rho;
+  md.V = wave_sum_d(vs);
+  md.p0 = wave_prod_d(pr);
+  md.vsum = wave_sum_d(vc);
+  if (!(md.V > 0.0)) { md.p0 = 1.0; md.V = 0.0; md.vsum = 0.0; }
+}
+
+__device__ __forceinline__ double model_recall(const Model& md) {
+  if (!(md.V > 0.0)) return md.p0;
+  return md.p0 + (1.0 - md.p0) * (md.vsum / md.V);
+}
+
+// Smallest number of further candidates, from position `from`, after which
+// the current model reaches the target; M - from if it never does.
+__device__ int predict_window(const Model& md, const float* __restrict__ hq, int M, int from, double target,
+                              const double* __restrict__ table) {
+  if (!(md.V > 0.0)) return 1;
+  const double need = (target - md.p0) * md.V / (1.0 - md.p0) - md.vsum;
+  if (need <= 0.0) return 1;
+  const int lane = lane_id();
+  const bool inf = __builtin_isinf(md.rho);
+  double run = 0.0;
+  for (int base = from; base < M; base += WAVE) {
+    const int i = base + lane;
+    double v = 0.0;
+    if (i < M) v = cap_share(table, inf ? 0.0 : (double)hq[i] / md.rho);
+    // inclusive scan over the wave
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const double u = __shfl_up(v, o);
+      if (lane >= o) v += u;
+    }
+    const uint64_t hit = __ballot(i < M && run + v >= need);
+    if (hit) return base - from + __builtin_ctzll(hit) + 1;
+    run += readlane_d(v, WAVE - 1);
+  }
+  return M - from;
+}
+
+template <int KPL>
+__global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, int k, int kk, int aps, int ip, int chunk_tiles,
+                                                int wmax, double tau_r, double tau_rho,
+                                                const int32_t* __restrict__ cand, const float* __restrict__ hcand,
+                                                const int32_t* __restrict__ psize, const double* __restrict__ qn2,
+                                                const float* __restrict__ pk, const int64_t* __restrict__ pi,
+                                                const double* __restrict__ table, int32_t* __restrict__ st_m,
+                                                int32_t* __restrict__ st_w, int32_t* __restrict__ st_done,
+                                                const int64_t* __restrict__ st_item, double* __restrict__ st_rho,
+                                                double* __restrict__ st_p0, double* __restrict__ st_V,
+                                                double* __restrict__ st_vsum, double* __restrict__ st_r,
+                                                float* __restrict__ rk, int64_t* __restrict__ ri) {
+  __shared__ float Ak[KMAX], Bk[KMAX], Ok[KMAX];
+  __shared__ int64_t Ai[KMAX], Bi[KMAX], Oi[KMAX];
+  const int64_t q = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int w = st_w[q];
+  if (st_done[q] || w == 0) return;
+  for (int e = lane; e < kk; e += WAVE) { Ak[e] = rk[q * kk + e]; Ai[e] = ri[q * kk + e]; }
+  const int m0 = st_m[q];
+  int64_t it = st_item[q];
+  Model md{st_rho[q], st_p0[q], st_V[q], st_vsum[q]};
+  const double qn = ip ? qn2[q] : 0.0;
+  const float* hq = hcand + q * M;
+  double r = st_r[q];
+  int committed = m0;
+  bool stop = false;
+  for (int j = 0; j < w && !stop; ++j) {
+    const int p = cand[q * M + m0 + j];
+    const int nch = item_chunks(psize[p], chunk_tiles);
+    for (int c = 0; c < nch; ++c, ++it) {
+      for (int e = lane; e < kk; e += WAVE) { Bk[e] = pk[it * kk + e]; Bi[e] = pi[it * kk + e]; }
+      __syncthreads();
+      wave_merge(Ak, Ai, Bk, Bi, Ok, Oi, kk);
+      __syncthreads();
+      for (int e = lane; e < kk; e += WAVE) { Ak[e] = Ok[e]; Ai[e] = Oi[e]; }
+      __syncthreads();
+    }
+    committed = m0 + j + 1;
+    if (!aps) continue;
+    const bool full = Ai[k - 1] >= 0;
+    const double rho_new = full ? key_radius(Ak[k - 1], ip, qn) : __builtin_inf();
+    if (committed == 1) {
+      recompute_model(md, rho_new, hq, M, committed, table);
+    } else {
+      const bool redo = __builtin_isinf(md.rho) ? !__builtin_isinf(rho_new)
+                                                 : fabs(rho_new - md.rho) > tau_rho * md.rho;
+      if (redo) {
+        recompute_model(md, rho_new, hq, M, committed, table);
+      } else if (md.V > 0.0) {
+        const double t = __builtin_isinf(md.rho) ? 0.0 : (double)hq[committed - 1] / md.rho;
+        md.vsum += cap_share(table, t);
+      }
+    }
+    r = full ? model_recall(md) : 0.0;
+    if (r >= tau_r) stop = true;
+  }
+  const bool done = stop || committed >= M;
+  int wn = 0;
+  if (!done) {
+    if (aps && Ai[k - 1] >= 0) wn = predict_window(md, hq, M, committed, tau_r, table);
+    else wn = 2 * w;
+    if (wn < 1) wn = 1;
+    if (wn > wmax) wn = wmax;
+  }
+  for (int e = lane; e < kk; e += WAVE) { rk[q * kk + e] = Ak[e]; ri[q * kk + e] = Ai[e]; }
+  if (lane == 0) {
+    st_m[q] = committed;
+    st_w[q] = wn;
+    st_done[q] = done ? 1 : 0;
+    st_rho[q] = md.rho; st_p0[q] = md.p0; st_V[q] = md.V; st_vsum[q] = md.vsum;
+    st_r[q] = aps ? r : 1.0;
+  }
+}
+
+void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const double* table, hipStream_t s) {
+  hipLaunchKernelGGL((k_commit<1>), dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.M, a.k /*k*/, a.k, a.aps,
+                     a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.tau_r, a.tau_rho, ws.cand, ws.h,
+                     st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_item, ws.st_rho,
+                     ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri);
+}
+
+// ---------------------------------------------------------------- outputs
+
+__global__ __launch_bounds__(256) void k_finalize(int64_t nq, int k, int kk, int ip, const float* __restrict__ rk,
+                                                   const int64_t* __restrict__ ri, const int32_t* __restrict__ st_m,
+                                                   const double* __restrict__ st_r, int64_t* __restrict__ out_ids,
+                                                   float* __restrict__ out_dist, int32_t* __restrict__ out_ns,
+                                                   double* __restrict__ out_r) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= nq * k) return;
+  const int64_t q = e / k;
+  const int j = (int)(e - q * k);
+  const float key = rk[q * kk + j];
+  out_ids[e] = ri[q * kk + j];
+  out_dist[e] = ip ? -key : key;
+  if (j == 0) {
+    if (out_ns) out_ns[q] = st_m[q];
+    if (out_r) out_r[q] = st_r[q];
+  }
+}
+
+void launch_finalize(Workspace& ws, const RoundArgs& a, int64_t* out_ids, float* out_dist, int32_t* out_nscanned,
+                     double* out_recall, hipStream_t s) {
+  const int64_t n = a.nq * a.k;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.nq, a.k, a.k,
+                     a.metric == QUAKE_IP ? 1 : 0, ws.rk, ws.ri, ws.st_m, ws.st_r, out_ids, out_dist, out_nscanned,
+                     out_recall);
+}
+
+}  // namespace qk

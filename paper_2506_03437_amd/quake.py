@@ -1,0 +1,243 @@
+"""Python binding of the C ABI in include/quake.h (argument marshalling only).
+
+Every function here has the name of the C entry point it calls.  Device
+buffers are torch tensors on the current HIP device; the current torch
+stream is passed as the stream argument.  Nothing is computed in Python:
+a missing library raises instead of falling back to anything else.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libquake_mi355x.so")
+
+OK, E_INVALID, E_NOMEM, E_NOTFOUND, E_DUPLICATE, E_DEVICE, E_STATE = 0, -1, -2, -3, -4, -5, -6
+L2, IP = 0, 1
+F32, BF16, F16 = 0, 1, 2
+SCAN_PLAIN, SCAN_BATCHED = 0, 1
+
+_METRIC = {"l2": L2, "ip": IP}
+_DTYPE = {"f32": F32, "bf16": BF16, "f16": F16}
+_MODE = {"plain": SCAN_PLAIN, "batched": SCAN_BATCHED}
+
+EXPORTED = ("quake_build", "quake_search", "quake_insert", "quake_delete", "quake_stats", "quake_export",
+            "quake_export_top", "quake_candidates", "quake_cap_table", "quake_free", "quake_last_error")
+
+
+class QuakeError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"quake error {code}: {msg}")
+        self.code = code
+
+
+class BuildParams(ctypes.Structure):
+    _fields_ = [("metric", ctypes.c_int32), ("storage_dtype", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("kmeans_iters", ctypes.c_int32), ("nlist", ctypes.c_int64), ("nlist_top", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("centroids", ctypes.c_void_p), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("capacity_slack", ctypes.c_double)]
+
+
+class SearchParams(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("nprobe", ctypes.c_int32), ("recall_target", ctypes.c_double),
+                ("f_M", ctypes.c_double), ("tau_rho", ctypes.c_double), ("upper_recall_target", ctypes.c_double),
+                ("upper_f_M", ctypes.c_double), ("scan_mode", ctypes.c_int32), ("scan_dtype", ctypes.c_int32),
+                ("rerank_factor", ctypes.c_int32), ("window", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2506_03437_amd.build_lib`")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    lib.quake_build.argtypes = [vp, vp, i64, i32, ctypes.POINTER(BuildParams), vp, ctypes.POINTER(vp)]
+    lib.quake_search.argtypes = [vp, vp, i64, ctypes.POINTER(SearchParams), vp, vp, vp, vp, vp]
+    lib.quake_insert.argtypes = [vp, vp, vp, i64, vp]
+    lib.quake_delete.argtypes = [vp, vp, i64, vp]
+    lib.quake_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)]
+    lib.quake_export.argtypes = [vp, vp, vp, vp, vp]
+    lib.quake_export_top.argtypes = [vp, vp, vp, vp]
+    lib.quake_candidates.argtypes = [vp, vp, i64, f64, vp, vp, ctypes.POINTER(i32), vp]
+    lib.quake_cap_table.argtypes = [i32, ctypes.POINTER(f64)]
+    lib.quake_free.argtypes = [vp]
+    lib.quake_free.restype = None
+    lib.quake_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("quake_free", "quake_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        msg = load_library().quake_last_error()
+        raise QuakeError(rc, msg.decode() if msg else "")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _dev(t, dtype):
+    import torch
+    assert t.is_cuda and t.dtype == dtype and t.is_contiguous(), f"need a contiguous CUDA {dtype} tensor"
+    return t
+
+
+def quake_cap_table(d: int) -> np.ndarray:
+    out = np.zeros(1024, dtype=np.float64)
+    _check(load_library().quake_cap_table(d, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def quake_build(x, ids=None, *, metric="l2", nlist=256, storage="f32", n_levels=1, nlist_top=0, kmeans_iters=10,
+                seed=0, centroids=None, hbm_budget_bytes=0, capacity_slack=0.0) -> int:
+    import torch
+    _dev(x, torch.float32)
+    if ids is not None:
+        _dev(ids, torch.int64)
+    if centroids is not None:
+        _dev(centroids, torch.float32)
+    p = BuildParams(_METRIC[metric], _DTYPE[storage], n_levels, kmeans_iters, nlist, nlist_top, seed,
+                    _ptr(centroids), hbm_budget_bytes, capacity_slack)
+    h = ctypes.c_void_p()
+    _check(load_library().quake_build(_ptr(x), _ptr(ids), x.shape[0], x.shape[1], ctypes.byref(p), _stream(),
+                                      ctypes.byref(h)))
+    return h.value
+
+
+def quake_search(handle: int, q, *, k=10, nprobe=0, recall_target=0.0, f_M=0.0, tau_rho=0.0,
+                 upper_recall_target=0.0, upper_f_M=0.0, scan_mode="plain", scan_dtype="f32", rerank_factor=0,
+                 window=0, outputs=None):
+    """Returns (ids int64 [nq,k], dist f32 [nq,k], nscanned int32 [nq], recall f64 [nq])."""
+    import torch
+    _dev(q, torch.float32)
+    nq = q.shape[0]
+    if outputs is None:
+        dev = q.device
+        outputs = (torch.empty((nq, k), dtype=torch.int64, device=dev),
+                   torch.empty((nq, k), dtype=torch.float32, device=dev),
+                   torch.empty((nq,), dtype=torch.int32, device=dev),
+                   torch.empty((nq,), dtype=torch.float64, device=dev))
+    ids, dist, ns, rec = outputs
+    p = SearchParams(k, nprobe, recall_target, f_M, tau_rho, upper_recall_target, upper_f_M, _MODE[scan_mode],
+                     _DTYPE[scan_dtype], rerank_factor, window)
+    _check(load_library().quake_search(handle, _ptr(q), nq, ctypes.byref(p), _ptr(ids), _ptr(dist), _ptr(ns),
+                                       _ptr(rec), _stream()))
+    return ids, dist, ns, rec
+
+
+def quake_insert(handle: int, x, ids):
+    import torch
+    _dev(x, torch.float32)
+    _dev(ids, torch.int64)
+    _check(load_library().quake_insert(handle, _ptr(x), _ptr(ids), x.shape[0], _stream()))
+
+
+def quake_delete(handle: int, ids):
+    import torch
+    _dev(ids, torch.int64)
+    _check(load_library().quake_delete(handle, _ptr(ids), ids.shape[0], _stream()))
+
+
+def quake_stats(handle: int):
+    n_live, nparts, nbytes = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+    _check(load_library().quake_stats(handle, ctypes.byref(n_live), ctypes.byref(nparts), ctypes.byref(nbytes)))
+    return n_live.value, nparts.value, nbytes.value
+
+
+def quake_export(handle: int, d: int):
+    """(centroids f32 [nlist, d], ids int64 [n_live], partition int32 [n_live]) as torch tensors."""
+    import torch
+    n_live, nlist, _ = quake_stats(handle)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    C = torch.empty((nlist, d), dtype=torch.float32, device=dev)
+    ids = torch.empty((max(n_live, 1),), dtype=torch.int64, device=dev)
+    part = torch.empty((max(n_live, 1),), dtype=torch.int32, device=dev)
+    _check(load_library().quake_export(handle, _ptr(C), _ptr(ids), _ptr(part), _stream()))
+    return C, ids[:n_live], part[:n_live]
+
+
+def quake_export_top(handle: int, d: int, nlist_top: int):
+    import torch
+    _, nlist, _ = quake_stats(handle)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    C1 = torch.empty((nlist_top, d), dtype=torch.float32, device=dev)
+    top_of = torch.empty((nlist,), dtype=torch.int32, device=dev)
+    _check(load_library().quake_export_top(handle, _ptr(C1), _ptr(top_of), _stream()))
+    return C1, top_of
+
+
+def quake_candidates(handle: int, q, f_M: float):
+    """(order int32 [nq, M], h f32 [nq, M]) of adaptive scanning, without scanning."""
+    import torch
+    _dev(q, torch.float32)
+    _, nlist, _ = quake_stats(handle)
+    M = ctypes.c_int32()
+    _check(load_library().quake_candidates(handle, None, 0, f_M, None, None, ctypes.byref(M), _stream()))
+    nq = q.shape[0]
+    order = torch.empty((nq, M.value), dtype=torch.int32, device=q.device)
+    h = torch.empty((nq, M.value), dtype=torch.float32, device=q.device)
+    _check(load_library().quake_candidates(handle, _ptr(q), nq, f_M, _ptr(order), _ptr(h), None, _stream()))
+    return order, h
+
+
+def quake_free(handle: int):
+    if handle:
+        load_library().quake_free(handle)
+
+
+class Index:
+    """Owning wrapper around a quake_index handle."""
+
+    def __init__(self, x, ids=None, **build_kw):
+        self.d = x.shape[1]
+        self.metric = build_kw.get("metric", "l2")
+        self.handle = quake_build(x, ids, **build_kw)
+
+    def search(self, q, **kw):
+        return quake_search(self.handle, q, **kw)
+
+    def insert(self, x, ids):
+        quake_insert(self.handle, x, ids)
+
+    def delete(self, ids):
+        quake_delete(self.handle, ids)
+
+    def stats(self):
+        return quake_stats(self.handle)
+
+    def export(self):
+        return quake_export(self.handle, self.d)
+
+    def candidates(self, q, f_M=0.05):
+        return quake_candidates(self.handle, q, f_M)
+
+    def free(self):
+        quake_free(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                self.free()
+        except Exception:
+            pass

@@ -9,3 +9,7 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) and the built HIP library")
     config.addinivalue_line("markers", "slow: large CPU-side oracle work")
+
+
+def pytest_runtest_logstart(nodeid, location):
+    print(f"\n[start] {nodeid}", flush=True)
