@@ -143,6 +143,43 @@ int quake_candidates(quake_index* index, const float* q, int64_t nq, double f_M,
  * points t_j = j / 1023 (Sec. 5.3).  Host-only, no device needed. */
 int quake_cap_table(int32_t d, double* out_1024);
 
+/* Scheduling knobs of the search; 0 keeps the built-in default.  They change
+ * how the work is cut into items and rounds, never the results: partitions
+ * are committed in candidate order whatever the cut.  Errors: INVALID for
+ * negative values, STATE for a bad handle. */
+typedef struct {
+  int32_t chunk_tiles;   /* store tiles (64 vectors each) per work item; default 16 */
+  int32_t first_window;  /* APS: partitions per query in the first round; default 2 */
+  int32_t max_window;    /* APS: most partitions per query in one round; default 32 */
+  int32_t reserved;
+  int64_t max_items;     /* work items per round (bounds the scratch memory); default from nq */
+} quake_tuning;
+int quake_set_tuning(quake_index* index, const quake_tuning* tuning);
+
+/* Kernel timing of searches, for roofline measurement.  With enable = 1 the
+ * library records HIP events on the search stream around each kernel class
+ * and, after the search completes, adds the elapsed times to per-class
+ * totals; it also adds the algorithmic bytes and flops of each launch (bytes:
+ * vectors scanned * d * element size for scans, centroid rows for scoring).
+ * reset = 1 zeroes the totals.  out (host, QUAKE_PROF_KINDS entries) receives
+ * the totals when not NULL. */
+enum {
+  QUAKE_PROF_CENTROIDS = 0, /* centroid scoring */
+  QUAKE_PROF_SELECT = 1,    /* candidate selection and bisector geometry */
+  QUAKE_PROF_PLAN = 2,      /* work-item planning */
+  QUAKE_PROF_SCAN = 3,      /* partition scans */
+  QUAKE_PROF_COMMIT = 4,    /* in-order commit and recall model */
+  QUAKE_PROF_RERANK = 5,    /* FP32 rerank of reduced-precision candidates */
+  QUAKE_PROF_KINDS = 8
+};
+typedef struct {
+  int64_t launches;
+  double milliseconds;
+  double bytes;
+  double flops;
+} quake_kernel_profile;
+int quake_profile(quake_index* index, int32_t enable, int32_t reset, quake_kernel_profile* out);
+
 void quake_free(quake_index* index);
 const char* quake_last_error(void);
 

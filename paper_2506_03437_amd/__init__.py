@@ -16,6 +16,8 @@ from .quake import (  # noqa: F401
     quake_export_top,
     quake_free,
     quake_insert,
+    quake_profile,
     quake_search,
+    quake_set_tuning,
     quake_stats,
 )

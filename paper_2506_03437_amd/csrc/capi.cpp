@@ -83,6 +83,47 @@ DeviceMemory::~DeviceMemory() {
   for (auto& b : blocks_) (void)hipFree(b.p);
 }
 
+hipEvent_t Profiler::event() {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  QK_HIP(hipEventCreate(&e));
+  return e;
+}
+
+void Profiler::begin(int kind, hipStream_t s) {
+  if (!on) return;
+  Span sp{kind, event(), event()};
+  QK_HIP(hipEventRecord(sp.a, s));
+  pending.push_back(sp);
+}
+
+void Profiler::end(hipStream_t s) {
+  if (!on || pending.empty()) return;
+  (void)hipEventRecord(pending.back().b, s);
+}
+
+void Profiler::collect() {
+  for (auto& sp : pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, sp.a, sp.b) == hipSuccess) {
+      acc[sp.kind].milliseconds += ms;
+      acc[sp.kind].launches += 1;
+    }
+    pool.push_back(sp.a);
+    pool.push_back(sp.b);
+  }
+  pending.clear();
+}
+
+Profiler::~Profiler() {
+  for (auto& sp : pending) { pool.push_back(sp.a); pool.push_back(sp.b); }
+  for (auto e : pool) (void)hipEventDestroy(e);
+}
+
 }  // namespace qk
 
 namespace {
@@ -260,11 +301,12 @@ Resolved resolve(const quake_index* idx, const Store& st, const quake_search_par
   r.tau_rho = p->tau_rho > 0 ? p->tau_rho : 0.01;
   const int64_t N = st.nlist;
   const int64_t cap_m = N > 4096 ? 2048 : qk::MAX_CANDIDATES;
+  const quake_tuning& tu = idx->tune;
   if (r.aps) {
     r.M = candidate_count(r.f_M, N);
     QK_CHECK(r.M <= cap_m, QUAKE_E_INVALID, "f_M * nlist exceeds the candidate limit");
-    r.w0 = p->window > 0 ? p->window : 2;
-    r.wmax = 32;
+    r.w0 = p->window > 0 ? p->window : (tu.first_window > 0 ? tu.first_window : 2);
+    r.wmax = tu.max_window > 0 ? tu.max_window : 32;
   } else {
     r.M = (int)std::min<int64_t>(p->nprobe, N);
     QK_CHECK(r.M <= cap_m, QUAKE_E_INVALID, "nprobe exceeds the candidate limit");
@@ -282,17 +324,20 @@ void ensure_workspace(quake_index* idx, int64_t nq, int64_t nc, int64_t M, int64
   const int dp = idx->dp;
   if (nq > w.nq_cap || !w.q) {
     const int64_t n = std::max<int64_t>(nq, 1);
-    for (void* p : {(void*)w.q, (void*)w.qn2, (void*)w.st_m, (void*)w.st_w, (void*)w.st_done, (void*)w.st_item,
-                    (void*)w.st_demand, (void*)w.st_rho, (void*)w.st_p0, (void*)w.st_V, (void*)w.st_vsum,
-                    (void*)w.st_r})
+    for (void* p : {(void*)w.q, (void*)w.qn2, (void*)w.st_m, (void*)w.st_w, (void*)w.st_weff, (void*)w.st_done,
+                    (void*)w.st_item,
+                    (void*)w.st_demand, (void*)w.st_vecs, (void*)w.st_rho, (void*)w.st_p0, (void*)w.st_V,
+                    (void*)w.st_vsum, (void*)w.st_r})
       mem.release(p);
     w.q = mem.alloc<float>((size_t)n * dp);
     w.qn2 = mem.alloc<double>(n);
     w.st_m = mem.alloc<int32_t>(n);
     w.st_w = mem.alloc<int32_t>(n);
+    w.st_weff = mem.alloc<int32_t>(n);
     w.st_done = mem.alloc<int32_t>(n);
     w.st_item = mem.alloc<int64_t>(n);
     w.st_demand = mem.alloc<int64_t>(n);
+    w.st_vecs = mem.alloc<int64_t>(n);
     w.st_rho = mem.alloc<double>(n);
     w.st_p0 = mem.alloc<double>(n);
     w.st_V = mem.alloc<double>(n);
@@ -330,8 +375,8 @@ void ensure_workspace(quake_index* idx, int64_t nq, int64_t nc, int64_t M, int64
     w.pi = mem.alloc<int64_t>((size_t)w.items_cap * w.k_cap);
   }
   if (!w.total) {
-    w.total = mem.alloc<int64_t>(1);
-    QK_HIP(hipHostMalloc((void**)&w.h_total, sizeof(int64_t), hipHostMallocDefault));
+    w.total = mem.alloc<int64_t>(2);
+    QK_HIP(hipHostMalloc((void**)&w.h_total, 2 * sizeof(int64_t), hipHostMallocDefault));
   }
 }
 
@@ -339,7 +384,14 @@ void ensure_workspace(quake_index* idx, int64_t nq, int64_t nc, int64_t M, int64
 // adaptive scanning, their order by ascending bisector distance.
 void candidates(quake_index* idx, const Store& st, int64_t nq, int M, bool aps, hipStream_t s) {
   qk::Workspace& w = idx->ws;
-  qk::launch_scores(w.q, nq, st.centroids, st.nlist, idx->dp, idx->metric, w.scores, s);
+  {
+    qk::ProfileScope ps(idx->prof, QUAKE_PROF_CENTROIDS, s);
+    qk::launch_scores(w.q, nq, st.centroids, st.nlist, idx->dp, idx->metric, w.scores, s);
+  }
+  idx->prof.add(QUAKE_PROF_CENTROIDS, (double)st.nlist * idx->dp * 4.0 + (double)nq * idx->dp * 4.0 +
+                                           (double)nq * st.nlist * 4.0,
+                (double)nq * st.nlist * idx->dp * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
+  qk::ProfileScope ps(idx->prof, QUAKE_PROF_SELECT, s);
   if (aps) {
     qk::launch_select(w.scores, nq, st.nlist, M, idx->metric, w.sel, s);
     qk::launch_geometry(w.q, st.centroids, nq, idx->dp, M, idx->metric, w.sel, w.cand, w.h, s);
@@ -460,14 +512,19 @@ int quake_search(quake_index* idx, const float* q, int64_t nq, const quake_searc
   QK_CHECK(params->scan_mode == QUAKE_SCAN_PLAIN && params->scan_dtype == QUAKE_F32, QUAKE_E_INVALID,
            "only the plain FP32 scan is available in this build");
   hipStream_t s = as_stream(stream);
-  const int chunk_tiles = 16;
+  const int chunk_tiles = idx->tune.chunk_tiles > 0 ? idx->tune.chunk_tiles : 16;
   const int64_t kk = r.k;
   const int64_t mc = max_chunks(st, chunk_tiles);
-  const int64_t items = std::max<int64_t>(nq * std::max(r.w0, 4) * 2, (int64_t)r.wmax * mc + 1);
+  // the buffer must hold one full window of the largest partitions (progress)
+  const int64_t floor_items = (int64_t)r.wmax * mc + 1;
+  const int64_t items = std::max<int64_t>(
+      idx->tune.max_items > 0 ? idx->tune.max_items : nq * std::max(r.w0, 4) * 2, floor_items);
   ensure_workspace(idx, nq, st.nlist, r.M, kk, items);
   qk::Workspace& w = idx->ws;
   qk::launch_pad_rows(q, nq, idx->d, idx->dp, w.q, w.qn2, s);
   candidates(idx, st, nq, r.M, r.aps, s);
+  // a smaller requested cap than the buffer already allocated still applies
+  const int64_t items_cap = std::min<int64_t>(w.items_cap, items);
   qk::RoundArgs a{};
   a.nq = nq;
   a.M = r.M;
@@ -479,25 +536,63 @@ int quake_search(quake_index* idx, const float* q, int64_t nq, const quake_searc
   a.dim = idx->d;
   a.tau_r = r.tau_r;
   a.tau_rho = r.tau_rho;
-  a.items_cap = w.items_cap;
+  a.items_cap = items_cap;
   qk::launch_round_init(w, a, r.w0, s);
   // Every round commits at least one partition of the first unfinished
   // query, so the loop ends within nq * M rounds.
   const int64_t max_rounds = nq * (int64_t)r.M + 2;
   for (int64_t round = 0;; ++round) {
     QK_CHECK(round <= max_rounds, QUAKE_E_DEVICE, "search rounds did not converge");
-    qk::launch_demand(w, st, a, s);
-    QK_HIP(hipMemcpyAsync(w.h_total, w.total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    {
+      qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
+      qk::launch_demand(w, st, a, s);
+    }
+    QK_HIP(hipMemcpyAsync(w.h_total, w.total, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     QK_HIP(hipStreamSynchronize(s));
-    const int64_t total = *w.h_total;
+    const int64_t total = w.h_total[0];
+    const int64_t nvec = w.h_total[1];
     if (total == 0) break;
-    qk::launch_emit(w, st, a, s);
-    qk::launch_scan_f32(w, st, a, total, s);
-    qk::launch_commit(w, st, a, idx->cap_table, s);
+    {
+      qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
+      qk::launch_emit(w, st, a, s);
+    }
+    {
+      qk::ProfileScope ps(idx->prof, QUAKE_PROF_SCAN, s);
+      qk::launch_scan_f32(w, st, a, total, s);
+    }
+    idx->prof.add(QUAKE_PROF_SCAN, (double)nvec * idx->d * sizeof(float),
+                  (double)nvec * idx->d * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
+    {
+      qk::ProfileScope ps(idx->prof, QUAKE_PROF_COMMIT, s);
+      qk::launch_commit(w, st, a, idx->cap_table, s);
+    }
   }
-  qk::launch_finalize(w, a, out_ids, out_dist, out_nscanned, out_recall, s);
+  {
+    qk::ProfileScope ps(idx->prof, QUAKE_PROF_COMMIT, s);
+    qk::launch_finalize(w, a, out_ids, out_dist, out_nscanned, out_recall, s);
+  }
   QK_HIP(hipGetLastError());
   QK_HIP(hipStreamSynchronize(s));
+  idx->prof.collect();
+  API_END
+}
+
+int quake_set_tuning(quake_index* idx, const quake_tuning* t) {
+  API_BEGIN
+  check_index(idx);
+  QK_CHECK(t, QUAKE_E_INVALID, "tuning is NULL");
+  QK_CHECK(t->chunk_tiles >= 0 && t->first_window >= 0 && t->max_window >= 0 && t->max_items >= 0,
+           QUAKE_E_INVALID, "tuning values must be >= 0");
+  idx->tune = *t;
+  API_END
+}
+
+int quake_profile(quake_index* idx, int32_t enable, int32_t reset, quake_kernel_profile* out) {
+  API_BEGIN
+  check_index(idx);
+  if (out) std::memcpy(out, idx->prof.acc, sizeof(idx->prof.acc));
+  if (reset) std::memset(idx->prof.acc, 0, sizeof(idx->prof.acc));
+  idx->prof.on = enable != 0;
   API_END
 }
 

@@ -79,7 +79,8 @@ struct Workspace {
   int32_t* cand = nullptr;      // [nq][M] candidate partitions in scan order
   float* h = nullptr;           // [nq][M] bisector distances in scan order
   int32_t* st_m = nullptr;      // committed partitions
-  int32_t* st_w = nullptr;      // window of the current round
+  int32_t* st_w = nullptr;      // window the query asks for in the next round
+  int32_t* st_weff = nullptr;   // window it got in the current round
   int32_t* st_done = nullptr;
   int64_t* st_item = nullptr;   // first work item of the round
   int64_t* st_demand = nullptr;
@@ -93,8 +94,33 @@ struct Workspace {
   int4* items = nullptr;        // (query, partition, first tile, end tile)
   float* pk = nullptr;          // [items][kk] partial results
   int64_t* pi = nullptr;
-  int64_t* total = nullptr;     // device counter
-  int64_t* h_total = nullptr;   // pinned host mirror
+  int64_t* st_vecs = nullptr;   // [nq] vectors in the round's window
+  int64_t* total = nullptr;     // device counters: items, vectors of the round
+  int64_t* h_total = nullptr;   // pinned host mirror (2 entries)
+};
+
+// HIP-event timing of kernel classes on the search stream.
+struct Profiler {
+  bool on = false;
+  quake_kernel_profile acc[QUAKE_PROF_KINDS] = {};
+  struct Span { int kind; hipEvent_t a, b; };
+  std::vector<Span> pending;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t event();
+  void begin(int kind, hipStream_t s);
+  void end(hipStream_t s);
+  void add(int kind, double bytes, double flops) {
+    if (on) { acc[kind].bytes += bytes; acc[kind].flops += flops; }
+  }
+  void collect();  // after the stream is synchronised
+  ~Profiler();
+};
+
+struct ProfileScope {
+  Profiler& p;
+  hipStream_t s;
+  ProfileScope(Profiler& p_, int kind, hipStream_t s_) : p(p_), s(s_) { p.begin(kind, s); }
+  ~ProfileScope() { p.end(s); }
 };
 
 }  // namespace qk
@@ -112,6 +138,8 @@ struct quake_index {
   double* cap_table = nullptr;  // [1024] device copy of the recall model table
   std::vector<double> h_cap_table;
   qk::Workspace ws;
+  qk::Profiler prof;
+  quake_tuning tune{};
 };
 
 namespace qk {

@@ -58,34 +58,43 @@ void launch_round_init(Workspace& ws, const RoundArgs& a, int w0, hipStream_t s)
 
 // ---------------------------------------------------------------- planning
 
-// Work items each query needs for its window this round.
+// Work items each query needs for its window this round.  st_w is the
+// window the query asked for; st_weff is what it gets this round (0 when it
+// is finished or when the item buffer is full, see k_prefix).
 __global__ __launch_bounds__(256) void k_demand(int64_t nq, int M, int chunk_tiles,
                                                  const int32_t* __restrict__ cand, const int32_t* __restrict__ psize,
-                                                 const int32_t* __restrict__ st_m, int32_t* __restrict__ st_w,
-                                                 const int32_t* __restrict__ st_done, int64_t* __restrict__ demand) {
+                                                 const int32_t* __restrict__ st_m, const int32_t* __restrict__ st_w,
+                                                 int32_t* __restrict__ st_weff, const int32_t* __restrict__ st_done,
+                                                 int64_t* __restrict__ demand, int64_t* __restrict__ vecs) {
   const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (q >= nq) return;
-  int64_t dmd = 0;
+  int64_t dmd = 0, nv = 0;
+  int w = 0;
   if (!st_done[q]) {
     const int m = st_m[q];
-    int w = st_w[q];
+    w = st_w[q];
     if (w > M - m) w = M - m;
-    for (int j = 0; j < w; ++j) dmd += item_chunks(psize[cand[q * M + m + j]], chunk_tiles);
-    st_w[q] = w;
-  } else {
-    st_w[q] = 0;
+    for (int j = 0; j < w; ++j) {
+      const int32_t sz = psize[cand[q * M + m + j]];
+      dmd += item_chunks(sz, chunk_tiles);
+      nv += sz;
+    }
   }
+  st_weff[q] = w;
   demand[q] = dmd;
+  vecs[q] = nv;
 }
 
 // Exclusive prefix sum of the demands (one block).  Queries whose items would
-// not fit in the item buffer sit this round out (window 0); the buffer always
-// holds the first unfinished query's window, so every round makes progress.
+// not fit in the item buffer sit this round out (effective window 0, the
+// requested window is kept for the next round); the buffer always holds the
+// first unfinished query's window, so every round makes progress.
 __global__ __launch_bounds__(1024) void k_prefix(int64_t nq, int64_t cap, const int64_t* __restrict__ demand,
-                                                  int64_t* __restrict__ first, int32_t* __restrict__ st_w,
-                                                  int64_t* __restrict__ total) {
+                                                  const int64_t* __restrict__ vecs, int64_t* __restrict__ first,
+                                                  int32_t* __restrict__ st_weff, int64_t* __restrict__ total) {
   __shared__ int64_t part[1024];
   __shared__ int64_t overflow_at;
+  __shared__ unsigned long long nvecs;
   const int t = threadIdx.x;
   const int64_t per = (nq + 1023) / 1024;
   const int64_t lo = t * per;
@@ -93,7 +102,7 @@ __global__ __launch_bounds__(1024) void k_prefix(int64_t nq, int64_t cap, const 
   int64_t s = 0;
   for (int64_t i = lo; i < hi; ++i) s += demand[i];
   part[t] = s;
-  if (t == 0) overflow_at = nq;
+  if (t == 0) { overflow_at = nq; nvecs = 0; }
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
     const int64_t v = (t >= o) ? part[t - o] : 0;
@@ -109,16 +118,24 @@ __global__ __launch_bounds__(1024) void k_prefix(int64_t nq, int64_t cap, const 
   }
   __syncthreads();
   const int64_t cut = overflow_at;
-  for (int64_t i = lo; i < hi; ++i)
-    if (i >= cut) st_w[i] = 0;
-  if (t == 0) *total = (cut < nq) ? first[cut] : part[1023];
+  unsigned long long nv = 0;
+  for (int64_t i = lo; i < hi; ++i) {
+    if (i >= cut) st_weff[i] = 0;
+    else nv += (unsigned long long)vecs[i];
+  }
+  atomicAdd(&nvecs, nv);
+  __syncthreads();
+  if (t == 0) {
+    total[0] = (cut < nq) ? first[cut] : part[1023];
+    total[1] = (int64_t)nvecs;
+  }
 }
 
 void launch_demand(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_demand, dim3((unsigned)((a.nq + 255) / 256)), dim3(256), 0, s, a.nq, a.M, a.chunk_tiles,
-                     ws.cand, st.d_size, ws.st_m, ws.st_w, ws.st_done, ws.st_demand);
-  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(1024), 0, s, a.nq, a.items_cap, ws.st_demand, ws.st_item, ws.st_w,
-                     ws.total);
+                     ws.cand, st.d_size, ws.st_m, ws.st_w, ws.st_weff, ws.st_done, ws.st_demand, ws.st_vecs);
+  hipLaunchKernelGGL(k_prefix, dim3(1), dim3(1024), 0, s, a.nq, a.items_cap, ws.st_demand, ws.st_vecs, ws.st_item,
+                     ws.st_weff, ws.total);
 }
 
 // Write the work items of each query's window, in candidate order.
@@ -149,7 +166,7 @@ __global__ __launch_bounds__(256) void k_emit(int64_t nq, int M, int chunk_tiles
 
 void launch_emit(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_emit, dim3((unsigned)((a.nq + 3) / 4)), dim3(256), 0, s, a.nq, a.M, a.chunk_tiles, ws.cand,
-                     st.d_size, ws.st_m, ws.st_w, ws.st_item, ws.items);
+                     st.d_size, ws.st_m, ws.st_weff, ws.st_item, ws.items);
 }
 
 // ---------------------------------------------------------------- FP32 scan
@@ -344,6 +361,7 @@ __global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, int k, int kk,
                                                 const float* __restrict__ pk, const int64_t* __restrict__ pi,
                                                 const double* __restrict__ table, int32_t* __restrict__ st_m,
                                                 int32_t* __restrict__ st_w, int32_t* __restrict__ st_done,
+                                                const int32_t* __restrict__ st_weff,
                                                 const int64_t* __restrict__ st_item, double* __restrict__ st_rho,
                                                 double* __restrict__ st_p0, double* __restrict__ st_V,
                                                 double* __restrict__ st_vsum, double* __restrict__ st_r,
@@ -352,7 +370,7 @@ __global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, int k, int kk,
   __shared__ int64_t Ai[KMAX], Bi[KMAX], Oi[KMAX];
   const int64_t q = blockIdx.x;
   const int lane = threadIdx.x;
-  const int w = st_w[q];
+  const int w = st_weff[q];
   if (st_done[q] || w == 0) return;
   for (int e = lane; e < kk; e += WAVE) { Ak[e] = rk[q * kk + e]; Ai[e] = ri[q * kk + e]; }
   const int m0 = st_m[q];
@@ -414,7 +432,8 @@ __global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, int k, int kk,
 void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const double* table, hipStream_t s) {
   hipLaunchKernelGGL((k_commit<1>), dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.M, a.k /*k*/, a.k, a.aps,
                      a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.tau_r, a.tau_rho, ws.cand, ws.h,
-                     st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_item, ws.st_rho,
+                     st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_weff, ws.st_item,
+                     ws.st_rho,
                      ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri);
 }
 

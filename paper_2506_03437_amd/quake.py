@@ -27,7 +27,9 @@ _DTYPE = {"f32": F32, "bf16": BF16, "f16": F16}
 _MODE = {"plain": SCAN_PLAIN, "batched": SCAN_BATCHED}
 
 EXPORTED = ("quake_build", "quake_search", "quake_insert", "quake_delete", "quake_stats", "quake_export",
-            "quake_export_top", "quake_candidates", "quake_cap_table", "quake_free", "quake_last_error")
+            "quake_export_top", "quake_candidates", "quake_cap_table", "quake_profile", "quake_set_tuning",
+            "quake_free", "quake_last_error")
+PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "unused6", "unused7")
 
 
 class QuakeError(RuntimeError):
@@ -48,6 +50,16 @@ class SearchParams(ctypes.Structure):
                 ("f_M", ctypes.c_double), ("tau_rho", ctypes.c_double), ("upper_recall_target", ctypes.c_double),
                 ("upper_f_M", ctypes.c_double), ("scan_mode", ctypes.c_int32), ("scan_dtype", ctypes.c_int32),
                 ("rerank_factor", ctypes.c_int32), ("window", ctypes.c_int32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("chunk_tiles", ctypes.c_int32), ("first_window", ctypes.c_int32), ("max_window", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("max_items", ctypes.c_int64)]
+
+
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("milliseconds", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("flops", ctypes.c_double)]
 
 
 _lib = None
@@ -71,6 +83,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.quake_export_top.argtypes = [vp, vp, vp, vp]
     lib.quake_candidates.argtypes = [vp, vp, i64, f64, vp, vp, ctypes.POINTER(i32), vp]
     lib.quake_cap_table.argtypes = [i32, ctypes.POINTER(f64)]
+    lib.quake_profile.argtypes = [vp, i32, i32, vp]
+    lib.quake_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     lib.quake_free.argtypes = [vp]
     lib.quake_free.restype = None
     lib.quake_last_error.restype = ctypes.c_char_p
@@ -200,6 +214,18 @@ def quake_candidates(handle: int, q, f_M: float):
     return order, h
 
 
+def quake_profile(handle: int, enable: bool = True, reset: bool = False):
+    """Per-kernel-class totals {name: (launches, ms, bytes, flops)} before this call."""
+    out = (KernelProfile * 8)()
+    _check(load_library().quake_profile(handle, int(enable), int(reset), ctypes.cast(out, ctypes.c_void_p)))
+    return {n: (o.launches, o.milliseconds, o.bytes, o.flops) for n, o in zip(PROF_KINDS, out)}
+
+
+def quake_set_tuning(handle: int, chunk_tiles=0, first_window=0, max_window=0, max_items=0):
+    t = Tuning(chunk_tiles, first_window, max_window, 0, max_items)
+    _check(load_library().quake_set_tuning(handle, ctypes.byref(t)))
+
+
 def quake_free(handle: int):
     if handle:
         load_library().quake_free(handle)
@@ -230,6 +256,12 @@ class Index:
 
     def candidates(self, q, f_M=0.05):
         return quake_candidates(self.handle, q, f_M)
+
+    def set_tuning(self, **kw):
+        quake_set_tuning(self.handle, **kw)
+
+    def profile(self, enable=True, reset=False):
+        return quake_profile(self.handle, enable, reset)
 
     def free(self):
         quake_free(self.handle)
