@@ -247,9 +247,11 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
   st.used_tiles = tiles;
   st.v32 = idx->mem.alloc<float>((size_t)arena * qk::TILE * st.dp);
   QK_HIP(hipMemsetAsync(st.v32, 0, (size_t)arena * qk::TILE * st.dp * sizeof(float), s));
+  st.dp16 = (int)round_up(st.d, 32);
   if (dtype16 != QUAKE_F32) {
-    st.v16 = idx->mem.alloc<uint16_t>((size_t)arena * qk::TILE * st.dp);
-    QK_HIP(hipMemsetAsync(st.v16, 0, (size_t)arena * qk::TILE * st.dp * sizeof(uint16_t), s));
+    st.v16 = idx->mem.alloc<uint16_t>((size_t)arena * qk::TILE * st.dp16);
+    QK_HIP(hipMemsetAsync(st.v16, 0, (size_t)arena * qk::TILE * st.dp16 * sizeof(uint16_t), s));
+    if (idx->metric == QUAKE_L2) st.v16n = idx->mem.alloc<float>((size_t)arena * qk::TILE);
   }
   st.ids = idx->mem.alloc<int64_t>((size_t)arena * qk::TILE);
   QK_HIP(hipMemsetAsync(st.ids, 0xff, (size_t)arena * qk::TILE * sizeof(int64_t), s));
@@ -262,7 +264,8 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
   {
     Tmp<int64_t> d_slot(idx->mem, n);
     QK_HIP(hipMemcpyAsync(d_slot.p, slot.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    qk::launch_scatter(xin, n, d, st.dp, ids, d_slot.p, st.v32, st.v16, dtype16, st.ids, s);
+    qk::launch_scatter(xin, n, d, st.dp, st.dp16, ids, d_slot.p, st.v32, st.v16, dtype16, st.ids, s);
+    qk::launch_norm16(st, dtype16, s);
     QK_HIP(hipStreamSynchronize(s));
   }
   st.live = n;
@@ -278,7 +281,7 @@ int64_t max_chunks(const Store& st, int chunk_tiles) {
 }
 
 struct Resolved {
-  int k, nprobe, aps, M, w0, wmax;
+  int k, kk, nprobe, aps, M, w0, wmax, batched, dtype16;
   double tau_r, f_M, tau_rho;
 };
 
@@ -295,6 +298,13 @@ Resolved resolve(const quake_index* idx, const Store& st, const quake_search_par
            "scan_dtype needs the matching reduced-precision copy in the index");
   Resolved r{};
   r.k = p->k;
+  r.batched = p->scan_mode == QUAKE_SCAN_BATCHED ? 1 : 0;
+  r.dtype16 = p->scan_dtype;
+  QK_CHECK(r.batched == (p->scan_dtype != QUAKE_F32 ? 1 : 0), QUAKE_E_INVALID,
+           "the batched scan runs on the 16-bit copy (scan_dtype BF16/F16) and the plain scan on FP32");
+  QK_CHECK(p->rerank_factor >= 0, QUAKE_E_INVALID, "rerank_factor must be >= 0");
+  r.kk = r.batched ? std::max(p->rerank_factor > 0 ? p->rerank_factor : 4, 1) * r.k : r.k;
+  QK_CHECK(!r.batched || r.kk <= 64, QUAKE_E_INVALID, "the batched scan keeps at most 64 candidates per query");
   r.aps = has_rt ? 1 : 0;
   r.tau_r = p->recall_target;
   r.f_M = p->f_M > 0 ? p->f_M : 0.05;
@@ -318,7 +328,8 @@ Resolved resolve(const quake_index* idx, const Store& st, const quake_search_par
   return r;
 }
 
-void ensure_workspace(quake_index* idx, int64_t nq, int64_t nc, int64_t M, int64_t kk, int64_t items) {
+void ensure_workspace(quake_index* idx, int64_t nq, int64_t nc, int64_t M, int64_t kk, int64_t items,
+                      int64_t pairs = 0, bool need16 = false) {
   qk::Workspace& w = idx->ws;
   auto& mem = idx->mem;
   const int dp = idx->dp;
@@ -326,8 +337,8 @@ void ensure_workspace(quake_index* idx, int64_t nq, int64_t nc, int64_t M, int64
     const int64_t n = std::max<int64_t>(nq, 1);
     for (void* p : {(void*)w.q, (void*)w.qn2, (void*)w.st_m, (void*)w.st_w, (void*)w.st_weff, (void*)w.st_done,
                     (void*)w.st_item,
-                    (void*)w.st_demand, (void*)w.st_vecs, (void*)w.st_rho, (void*)w.st_p0, (void*)w.st_V,
-                    (void*)w.st_vsum, (void*)w.st_r})
+                    (void*)w.st_demand, (void*)w.st_vecs, (void*)w.st_pair, (void*)w.st_rho, (void*)w.st_p0,
+                    (void*)w.st_V, (void*)w.st_vsum, (void*)w.st_r, (void*)w.q16, (void*)w.qn2f})
       mem.release(p);
     w.q = mem.alloc<float>((size_t)n * dp);
     w.qn2 = mem.alloc<double>(n);
@@ -338,6 +349,9 @@ void ensure_workspace(quake_index* idx, int64_t nq, int64_t nc, int64_t M, int64
     w.st_item = mem.alloc<int64_t>(n);
     w.st_demand = mem.alloc<int64_t>(n);
     w.st_vecs = mem.alloc<int64_t>(n);
+    w.st_pair = mem.alloc<int64_t>(n);
+    w.q16 = nullptr;
+    w.qn2f = mem.alloc<float>(n);
     w.st_rho = mem.alloc<double>(n);
     w.st_p0 = mem.alloc<double>(n);
     w.st_V = mem.alloc<double>(n);
@@ -375,8 +389,27 @@ void ensure_workspace(quake_index* idx, int64_t nq, int64_t nc, int64_t M, int64
     w.pi = mem.alloc<int64_t>((size_t)w.items_cap * w.k_cap);
   }
   if (!w.total) {
-    w.total = mem.alloc<int64_t>(2);
-    QK_HIP(hipHostMalloc((void**)&w.h_total, 2 * sizeof(int64_t), hipHostMallocDefault));
+    w.total = mem.alloc<int64_t>(8);
+    QK_HIP(hipHostMalloc((void**)&w.h_total, 8 * sizeof(int64_t), hipHostMallocDefault));
+  }
+  if (need16 && !w.q16) w.q16 = mem.alloc<uint16_t>((size_t)w.nq_cap * idx->L0.dp16);
+  if (pairs > w.pairs_cap || !w.pair_q) {
+    for (void* p : {(void*)w.pair_q, (void*)w.pair_p, (void*)w.pair_pos, (void*)w.pair_base, (void*)w.sorted})
+      mem.release(p);
+    w.pairs_cap = std::max<int64_t>(pairs, 1);
+    w.pair_q = mem.alloc<int32_t>(w.pairs_cap);
+    w.pair_p = mem.alloc<int32_t>(w.pairs_cap);
+    w.pair_pos = mem.alloc<int32_t>(w.pairs_cap);
+    w.pair_base = mem.alloc<int64_t>(w.pairs_cap);
+    w.sorted = mem.alloc<int32_t>(w.pairs_cap);
+  }
+  if (nc + 1 > w.parts_cap || !w.pcount) {
+    for (void* p : {(void*)w.pcount, (void*)w.pstart, (void*)w.pitem}) mem.release(p);
+    w.parts_cap = nc + 1;
+    w.pcount = mem.alloc<int32_t>(w.parts_cap);
+    w.pstart = mem.alloc<int32_t>(w.parts_cap);
+    w.pitem = mem.alloc<int64_t>(w.parts_cap);
+    QK_HIP(hipMemset(w.pcount, 0, w.parts_cap * sizeof(int32_t)));
   }
 }
 
@@ -509,26 +542,27 @@ int quake_search(quake_index* idx, const float* q, int64_t nq, const quake_searc
   const Resolved r = resolve(idx, st, params);
   if (nq == 0) return QUAKE_OK;
   QK_CHECK(q && out_ids && out_dist, QUAKE_E_INVALID, "q, out_ids and out_dist are required");
-  QK_CHECK(params->scan_mode == QUAKE_SCAN_PLAIN && params->scan_dtype == QUAKE_F32, QUAKE_E_INVALID,
-           "only the plain FP32 scan is available in this build");
   hipStream_t s = as_stream(stream);
   const int chunk_tiles = idx->tune.chunk_tiles > 0 ? idx->tune.chunk_tiles : 16;
-  const int64_t kk = r.k;
+  const int64_t kk = r.kk;
   const int64_t mc = max_chunks(st, chunk_tiles);
   // the buffer must hold one full window of the largest partitions (progress)
   const int64_t floor_items = (int64_t)r.wmax * mc + 1;
   const int64_t items = std::max<int64_t>(
       idx->tune.max_items > 0 ? idx->tune.max_items : nq * std::max(r.w0, 4) * 2, floor_items);
-  ensure_workspace(idx, nq, st.nlist, r.M, kk, items);
+  ensure_workspace(idx, nq, st.nlist, r.M, kk, items, r.batched ? nq * (int64_t)r.wmax : 0, r.batched != 0);
   qk::Workspace& w = idx->ws;
+  QK_HIP(hipMemsetAsync(w.total, 0, 8 * sizeof(int64_t), s));
   qk::launch_pad_rows(q, nq, idx->d, idx->dp, w.q, w.qn2, s);
   candidates(idx, st, nq, r.M, r.aps, s);
+  if (r.batched) qk::launch_queries16(w, nq, idx->dp, st.dp16, r.dtype16, s);
   // a smaller requested cap than the buffer already allocated still applies
   const int64_t items_cap = std::min<int64_t>(w.items_cap, items);
   qk::RoundArgs a{};
   a.nq = nq;
   a.M = r.M;
   a.k = r.k;
+  a.kk = r.kk;
   a.aps = r.aps;
   a.chunk_tiles = chunk_tiles;
   a.wmax = r.wmax;
@@ -538,6 +572,11 @@ int quake_search(quake_index* idx, const float* q, int64_t nq, const quake_searc
   a.tau_rho = r.tau_rho;
   a.items_cap = items_cap;
   qk::launch_round_init(w, a, r.w0, s);
+  if (r.batched && idx->cu_count == 0) {
+    int dev = 0;
+    QK_HIP(hipGetDevice(&dev));
+    QK_HIP(hipDeviceGetAttribute(&idx->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+  }
   // Every round commits at least one partition of the first unfinished
   // query, so the loop ends within nq * M rounds.
   const int64_t max_rounds = nq * (int64_t)r.M + 2;
@@ -547,32 +586,53 @@ int quake_search(quake_index* idx, const float* q, int64_t nq, const quake_searc
       qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
       qk::launch_demand(w, st, a, s);
     }
-    QK_HIP(hipMemcpyAsync(w.h_total, w.total, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipMemcpyAsync(w.h_total, w.total, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     QK_HIP(hipStreamSynchronize(s));
     const int64_t total = w.h_total[0];
     const int64_t nvec = w.h_total[1];
+    const int64_t npairs = w.h_total[2];
     if (total == 0) break;
-    {
-      qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
-      qk::launch_emit(w, st, a, s);
-    }
-    {
+    if (r.batched) {
+      {
+        qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
+        qk::launch_group(w, st, a, npairs, s);
+      }
       qk::ProfileScope ps(idx->prof, QUAKE_PROF_SCAN, s);
-      qk::launch_scan_f32(w, st, a, total, s);
+      qk::launch_scan_mfma(w, st, a, r.dtype16, std::max(idx->cu_count, 8) * 2, s);
+    } else {
+      {
+        qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
+        qk::launch_emit(w, st, a, s);
+      }
+      {
+        qk::ProfileScope ps(idx->prof, QUAKE_PROF_SCAN, s);
+        qk::launch_scan_f32(w, st, a, total, s);
+      }
+      idx->prof.add(QUAKE_PROF_SCAN, (double)nvec * idx->d * sizeof(float),
+                    (double)nvec * idx->d * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
     }
-    idx->prof.add(QUAKE_PROF_SCAN, (double)nvec * idx->d * sizeof(float),
-                  (double)nvec * idx->d * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
     {
       qk::ProfileScope ps(idx->prof, QUAKE_PROF_COMMIT, s);
       qk::launch_commit(w, st, a, idx->cap_table, s);
     }
+  }
+  if (r.batched) {
+    {
+      qk::ProfileScope ps(idx->prof, QUAKE_PROF_RERANK, s);
+      qk::launch_rerank(w, st, a, s);
+    }
+    idx->prof.add(QUAKE_PROF_RERANK, (double)nq * kk * idx->d * sizeof(float), (double)nq * kk * idx->d * 2.0);
   }
   {
     qk::ProfileScope ps(idx->prof, QUAKE_PROF_COMMIT, s);
     qk::launch_finalize(w, a, out_ids, out_dist, out_nscanned, out_recall, s);
   }
   QK_HIP(hipGetLastError());
+  if (r.batched && idx->prof.on)
+    QK_HIP(hipMemcpyAsync(w.h_total + 4, w.total + 4, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   QK_HIP(hipStreamSynchronize(s));
+  if (r.batched)
+    idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[4] * idx->d * 2.0, (double)w.h_total[5] * idx->d * 2.0);
   idx->prof.collect();
   API_END
 }

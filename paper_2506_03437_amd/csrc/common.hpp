@@ -172,4 +172,41 @@ __device__ inline void wave_merge(const float* ak, const int64_t* ai, const floa
   }
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(4))) f32x4 const_float4;
+
+// Distance of the query to the 64 vectors of one tile, one vector per lane.
+// The query is read through the scalar unit (one copy for the whole wave);
+// the tile through 16-byte loads that cover 1 KiB contiguous per wave.  Eight
+// partial sums (one per dimension modulo 8) are combined pairwise at the end.
+template <int METRIC>
+__device__ __forceinline__ float tile_distance(const float4* __restrict__ xp, const_float4* qs, int nch4) {
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f;
+#pragma unroll 4
+  for (int c = 0; c < nch4; c += 2) {
+    const float4 x = xp[(int64_t)c * WAVE];
+    const float4 y = xp[(int64_t)(c + 1) * WAVE];
+    const f32x4 qa = qs[c];
+    const f32x4 qb = qs[c + 1];
+    if (METRIC == QUAKE_L2) {
+      float t;
+      t = x.x - qa.x; a0 = fmaf(t, t, a0);
+      t = x.y - qa.y; a1 = fmaf(t, t, a1);
+      t = x.z - qa.z; a2 = fmaf(t, t, a2);
+      t = x.w - qa.w; a3 = fmaf(t, t, a3);
+      t = y.x - qb.x; a4 = fmaf(t, t, a4);
+      t = y.y - qb.y; a5 = fmaf(t, t, a5);
+      t = y.z - qb.z; a6 = fmaf(t, t, a6);
+      t = y.w - qb.w; a7 = fmaf(t, t, a7);
+    } else {
+      a0 = fmaf(x.x, qa.x, a0); a1 = fmaf(x.y, qa.y, a1);
+      a2 = fmaf(x.z, qa.z, a2); a3 = fmaf(x.w, qa.w, a3);
+      a4 = fmaf(y.x, qb.x, a4); a5 = fmaf(y.y, qb.y, a5);
+      a6 = fmaf(y.z, qb.z, a6); a7 = fmaf(y.w, qb.w, a7);
+    }
+  }
+  const float s = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
+  return METRIC == QUAKE_L2 ? s : -s;
+}
+
 }  // namespace qk

@@ -64,8 +64,10 @@ struct Store {
   std::vector<int32_t> size, cap;
   int64_t tiles = 0;            // arena tiles allocated
   int64_t used_tiles = 0;       // arena tiles handed out
+  int32_t dp16 = 0;             // row length of the 16-bit copy: d rounded up to 32
   float* v32 = nullptr;
-  uint16_t* v16 = nullptr;      // BF16 or FP16 copy, or null
+  uint16_t* v16 = nullptr;      // BF16 or FP16 copy, or null; tiles [dp16/8][64][8]
+  float* v16n = nullptr;        // [tiles * 64] |x|^2 of the 16-bit copy (L2 only)
   int64_t* ids = nullptr;       // [tiles * 64], -1 = empty or deleted
   int64_t live = 0;
 };
@@ -95,8 +97,23 @@ struct Workspace {
   float* pk = nullptr;          // [items][kk] partial results
   int64_t* pi = nullptr;
   int64_t* st_vecs = nullptr;   // [nq] vectors in the round's window
-  int64_t* total = nullptr;     // device counters: items, vectors of the round
-  int64_t* h_total = nullptr;   // pinned host mirror (2 entries)
+  int64_t* st_pair = nullptr;   // [nq] first (query, partition) pair of the round
+  uint16_t* q16 = nullptr;      // [nq][dp16] queries rounded to the 16-bit store type
+  float* qn2f = nullptr;        // [nq] |q|^2
+  int64_t pairs_cap = 0, parts_cap = 0;
+  int32_t* pair_q = nullptr;    // [pairs] query of the pair
+  int32_t* pair_p = nullptr;    // [pairs] partition of the pair
+  int32_t* pair_pos = nullptr;  // [pairs] place among the partition's pairs
+  int64_t* pair_base = nullptr; // [pairs] first partial-list slot of the pair
+  int32_t* sorted = nullptr;    // [pairs] pairs in partition order
+  int32_t* pcount = nullptr;    // [nlist] pairs per partition (kept zeroed between rounds)
+  int32_t* pstart = nullptr;    // [nlist + 1]
+  int64_t* pitem = nullptr;     // [nlist + 1] first batched work item of each partition
+  // device counters: [0] items, [1] vectors, [2] pairs of the round, [3] batched
+  // items of the round, [4] batched vector reads and [5] batched query-vector
+  // products summed over the search
+  int64_t* total = nullptr;
+  int64_t* h_total = nullptr;   // pinned host mirror
 };
 
 // HIP-event timing of kernel classes on the search stream.
@@ -140,6 +157,7 @@ struct quake_index {
   qk::Workspace ws;
   qk::Profiler prof;
   quake_tuning tune{};
+  int cu_count = 0;
 };
 
 namespace qk {
@@ -166,7 +184,7 @@ void launch_gather_rows(const float* x, int d, const int64_t* rows, int64_t nr, 
                         hipStream_t s);
 
 // kernels: store (k_store.hip)
-void launch_scatter(const float* x, int64_t n, int d, int dp, const int64_t* ids, const int64_t* slot,
+void launch_scatter(const float* x, int64_t n, int d, int dp, int dp16, const int64_t* ids, const int64_t* slot,
                     float* v32, uint16_t* v16, int dtype16, int64_t* sid, hipStream_t s);
 void launch_export(const Store& st, int64_t* ids, int32_t* part, const int64_t* part_first_out,
                    hipStream_t s);
@@ -175,7 +193,8 @@ void launch_export(const Store& st, int64_t* ids, int32_t* part, const int64_t* 
 struct RoundArgs {
   int64_t nq;
   int M;             // candidates per query
-  int k;             // results kept (k, or the rerank pool)
+  int k;             // results returned
+  int kk;            // results kept per query while scanning (k, or the rerank pool)
   int aps;           // 1: adaptive; 0: fixed nprobe
   int chunk_tiles;   // tiles per work item
   int wmax;
@@ -191,5 +210,12 @@ void launch_scan_f32(Workspace& ws, const Store& st, const RoundArgs& a, int64_t
 void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const double* table, hipStream_t s);
 void launch_finalize(Workspace& ws, const RoundArgs& a, int64_t* out_ids, float* out_dist,
                      int32_t* out_nscanned, double* out_recall, hipStream_t s);
+
+// kernels: the batched scan (k_batched.hip)
+void launch_queries16(Workspace& ws, int64_t nq, int dp, int dp16, int dtype16, hipStream_t s);
+void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, int64_t npairs, hipStream_t s);
+void launch_scan_mfma(Workspace& ws, const Store& st, const RoundArgs& a, int dtype16, int blocks, hipStream_t s);
+void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
+void launch_norm16(const Store& st, int dtype16, hipStream_t s);
 
 }  // namespace qk

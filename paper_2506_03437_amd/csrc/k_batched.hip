@@ -1,0 +1,416 @@
+// Batched scan: queries that need the same partition in a round share one
+// read of it (multi-query execution: group queries by the partitions they
+// access and scan each partition once per batch, Sec. 7.5).
+//
+// Per round, every query's window of (query, partition) pairs is bucketed by
+// partition.  A work item is (partition, group of up to 16 queries, chunk of
+// tiles).  One wave scores a 64-vector tile against its 16 queries with
+// v_mfma_f32_16x16x32 on the 16-bit store copy (BF16 or FP16 products, FP32
+// accumulation): the queries sit in registers as B operands for the whole
+// item, the tile is read straight from the store into A operands (the store's
+// [chunk][64 vectors][8 elements] tile layout is the A fragment order, so a
+// wave's load of one k-step covers four contiguous 256-byte runs).  The
+// 16 x 64 score block goes through LDS so that each query's 64 scores sit one
+// per lane, where a wave-wide top-k list (one entry per lane) keeps the
+// query's best rerank_factor * k candidates.  Partial lists land in the same
+// per-(query, partition, chunk) slots as the plain scan, so the in-order
+// commit and the recall model are shared.  Candidates carry store slots; after
+// the last round each query's candidates are re-scored in FP32 from the FP32
+// store (the same arithmetic as the plain scan) and the best k are kept.
+#include "common.hpp"
+#include "index.hpp"
+
+namespace qk {
+
+constexpr int G = 16;  // queries per work item (one MFMA column block)
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
+typedef __attribute__((ext_vector_type(4))) uint32_t u32x4;
+
+__device__ __forceinline__ int chunks_of(int32_t size, int chunk_tiles) {
+  const int tiles = (size + TILE - 1) / TILE;
+  const int c = (tiles + chunk_tiles - 1) / chunk_tiles;
+  return c > 0 ? c : 1;
+}
+
+// ---------------------------------------------------------------- queries
+
+__device__ __forceinline__ uint16_t round_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__global__ __launch_bounds__(256) void k_queries16(const float* __restrict__ q, int64_t nq, int dp, int dp16,
+                                                    int f16, const double* __restrict__ qn2, uint16_t* __restrict__ q16,
+                                                    float* __restrict__ qn2f) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t row = e / dp16;
+  if (row >= nq) return;
+  const int j = (int)(e - row * dp16);
+  const float v = j < dp ? q[row * dp + j] : 0.f;
+  q16[e] = f16 ? __builtin_bit_cast(uint16_t, (_Float16)v) : round_bf16(v);
+  if (j == 0) qn2f[row] = (float)qn2[row];
+}
+
+void launch_queries16(Workspace& ws, int64_t nq, int dp, int dp16, int dtype16, hipStream_t s) {
+  const int64_t n = nq * dp16;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_queries16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ws.q, nq, dp, dp16,
+                     dtype16 == QUAKE_F16 ? 1 : 0, ws.qn2, ws.q16, ws.qn2f);
+}
+
+// ---------------------------------------------------------------- grouping
+
+// Record every (query, window slot) pair of the round and count pairs per
+// partition.  pair_base is the first partial-list slot of the pair (the same
+// numbering as the plain scan's work items).
+__global__ __launch_bounds__(256) void k_pairs(int64_t nq, int M, int chunk_tiles, const int32_t* __restrict__ cand,
+                                                const int32_t* __restrict__ psize, const int32_t* __restrict__ st_m,
+                                                const int32_t* __restrict__ st_weff,
+                                                const int64_t* __restrict__ st_item,
+                                                const int64_t* __restrict__ st_pair, int32_t* __restrict__ pcount,
+                                                int32_t* __restrict__ pair_q, int32_t* __restrict__ pair_p,
+                                                int32_t* __restrict__ pair_pos, int64_t* __restrict__ pair_base) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= nq) return;
+  const int w = st_weff[q];
+  if (w == 0) return;
+  const int m = st_m[q];
+  int64_t it = st_item[q];
+  const int64_t pr = st_pair[q];
+  for (int j = 0; j < w; ++j) {
+    const int p = cand[q * M + m + j];
+    pair_q[pr + j] = (int32_t)q;
+    pair_p[pr + j] = p;
+    pair_base[pr + j] = it;
+    pair_pos[pr + j] = atomicAdd(&pcount[p], 1);
+    it += chunks_of(psize[p], chunk_tiles);
+  }
+}
+
+// Per-partition pair offsets and work-item offsets (one block); clears the
+// counts for the next round and adds the round's vector reads and
+// query-vector products to the running totals.
+__global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles, int32_t* __restrict__ pcount,
+                                                       const int32_t* __restrict__ psize, int32_t* __restrict__ pstart,
+                                                       int64_t* __restrict__ pitem, int64_t* __restrict__ counters) {
+  __shared__ int64_t sp[1024], si[1024];
+  __shared__ unsigned long long reads, products;
+  const int t = threadIdx.x;
+  const int64_t per = (N + 1023) / 1024;
+  const int64_t lo = t * per;
+  const int64_t hi = (lo + per < N) ? lo + per : N;
+  int64_t np = 0, ni = 0;
+  unsigned long long rd = 0, pd = 0;
+  for (int64_t p = lo; p < hi; ++p) {
+    const int c = pcount[p];
+    np += c;
+    if (c > 0) {
+      const int groups = (c + G - 1) / G;
+      ni += (int64_t)groups * chunks_of(psize[p], chunk_tiles);
+      rd += (unsigned long long)groups * (unsigned long long)psize[p];
+      pd += (unsigned long long)c * (unsigned long long)psize[p];
+    }
+  }
+  sp[t] = np;
+  si[t] = ni;
+  if (t == 0) { reads = 0; products = 0; }
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t a = (t >= o) ? sp[t - o] : 0;
+    const int64_t b = (t >= o) ? si[t - o] : 0;
+    __syncthreads();
+    sp[t] += a;
+    si[t] += b;
+    __syncthreads();
+  }
+  int64_t rp = sp[t] - np, ri = si[t] - ni;
+  for (int64_t p = lo; p < hi; ++p) {
+    const int c = pcount[p];
+    pstart[p] = (int32_t)rp;
+    pitem[p] = ri;
+    rp += c;
+    if (c > 0) ri += (int64_t)((c + G - 1) / G) * chunks_of(psize[p], chunk_tiles);
+    pcount[p] = 0;
+  }
+  atomicAdd(&reads, rd);
+  atomicAdd(&products, pd);
+  __syncthreads();
+  if (t == 0) {
+    pstart[N] = (int32_t)sp[1023];
+    pitem[N] = si[1023];
+    counters[3] = si[1023];
+    counters[4] += (int64_t)reads;
+    counters[5] += (int64_t)products;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pair_scatter(int64_t npairs, const int32_t* __restrict__ pair_p,
+                                                       const int32_t* __restrict__ pair_pos,
+                                                       const int32_t* __restrict__ pstart,
+                                                       int32_t* __restrict__ sorted) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= npairs) return;
+  sorted[pstart[pair_p[e]] + pair_pos[e]] = (int32_t)e;
+}
+
+void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, int64_t npairs, hipStream_t s) {
+  hipLaunchKernelGGL(k_pairs, dim3((unsigned)((a.nq + 255) / 256)), dim3(256), 0, s, a.nq, a.M, a.chunk_tiles,
+                     ws.cand, st.d_size, ws.st_m, ws.st_weff, ws.st_item, ws.st_pair, ws.pcount, ws.pair_q, ws.pair_p,
+                     ws.pair_pos, ws.pair_base);
+  hipLaunchKernelGGL(k_part_prefix, dim3(1), dim3(1024), 0, s, st.nlist, a.chunk_tiles, ws.pcount, st.d_size,
+                     ws.pstart, ws.pitem, ws.total);
+  if (npairs > 0)
+    hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, s, npairs, ws.pair_p,
+                       ws.pair_pos, ws.pstart, ws.sorted);
+}
+
+// ---------------------------------------------------------------- MFMA scan
+
+template <int F16>
+__device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
+  if constexpr (F16)
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                   0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                    0, 0, 0);
+}
+
+__device__ __forceinline__ bool ks_less(float ak, int32_t as, float bk, int32_t bs) {
+  return ak < bk || (ak == bk && as < bs);
+}
+
+// A sorted candidate list with one entry per lane (up to 64 entries).
+__device__ __forceinline__ void lane_list_insert(float& lk, int32_t& ls, float ck, int32_t cs, int kk, float& tk,
+                                                 int32_t& ts) {
+  const int lane = lane_id();
+  const int pos = __popcll(__ballot(ks_less(lk, ls, ck, cs)));
+  const float uk = __shfl_up(lk, 1);
+  const int32_t us = __shfl_up(ls, 1);
+  if (lane > pos) { lk = uk; ls = us; }
+  else if (lane == pos) { lk = ck; ls = cs; }
+  const int32_t ns = __builtin_amdgcn_readlane(ls, kk - 1);
+  if (ns >= 0) { tk = readlane_f(lk, kk - 1); ts = ns; }
+}
+
+template <int F16, int KSMAX, int IP>
+__global__ __launch_bounds__(256, 2) void k_scan_mfma(
+    const int64_t* __restrict__ counters, const int64_t* __restrict__ pitem, const int32_t* __restrict__ pstart,
+    const int32_t* __restrict__ sorted, const int32_t* __restrict__ pair_q, const int64_t* __restrict__ pair_base,
+    int64_t N, int chunk_tiles, const uint16_t* __restrict__ q16, int dp16, const float* __restrict__ qn2f,
+    const uint16_t* __restrict__ v16, const float* __restrict__ v16n, const int64_t* __restrict__ sid,
+    const int64_t* __restrict__ poff, const int32_t* __restrict__ psize, const float* __restrict__ rk,
+    const int64_t* __restrict__ ri, int kk, float* __restrict__ pk, int64_t* __restrict__ pi) {
+  __shared__ float S[4][G][TILE + 1];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // consecutive logical blocks on one XCD (blocks are dealt to the 8 XCDs in turn)
+  int lb = blockIdx.x;
+  if ((gridDim.x & 7) == 0) lb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  const int64_t total = counters[3];
+  const int64_t stride = (int64_t)gridDim.x * 4;
+  const int KS = dp16 >> 5;
+  const int nc8 = dp16 >> 3;
+  float (*Sw)[TILE + 1] = S[wave];
+  for (int64_t it = (int64_t)lb * 4 + wave; it < total; it += stride) {
+    int64_t lo = 0, hi = N;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (pitem[mid] <= it) lo = mid; else hi = mid;
+    }
+    const int p = __builtin_amdgcn_readfirstlane((int)lo);
+    const int size = psize[p];
+    const int tiles = (size + TILE - 1) / TILE;
+    const int nch = chunks_of(size, chunk_tiles);
+    const int local = (int)(it - pitem[p]);
+    const int g = local / nch, c = local - (local / nch) * nch;
+    const int np = pstart[p + 1] - pstart[p];
+    const int gcount = min(G, np - g * G);
+    const int t0 = c * chunk_tiles;
+    const int t1 = min(tiles, t0 + chunk_tiles);
+    const int j = lane & (G - 1);
+    const bool has = j < gcount;
+    const int pair = has ? sorted[pstart[p] + g * G + j] : 0;
+    const int qj = has ? pair_q[pair] : 0;
+    u32x4 breg[KSMAX];
+#pragma unroll
+    for (int s = 0; s < KSMAX; ++s) {
+      u32x4 b = {0u, 0u, 0u, 0u};
+      if (s < KS && has) b = *reinterpret_cast<const u32x4*>(q16 + (int64_t)qj * dp16 + 32 * s + 8 * (lane >> 4));
+      breg[s] = b;
+    }
+    const float my_qn2 = (IP || !has) ? 0.f : qn2f[qj];
+    float lk[G], tk[G];
+    int32_t ls[G], ts[G];
+#pragma unroll
+    for (int jj = 0; jj < G; ++jj) {
+      lk[jj] = KEY_EMPTY;
+      ls[jj] = -1;
+      tk[jj] = -KEY_EMPTY;
+      ts[jj] = -1;
+      if (jj < gcount) {
+        const int qq = __builtin_amdgcn_readlane(qj, jj);
+        tk[jj] = rk[(int64_t)qq * kk + kk - 1];
+        ts[jj] = (int32_t)ri[(int64_t)qq * kk + kk - 1];
+      }
+    }
+    const int64_t tile0 = poff[p];
+    for (int t = t0; t < t1; ++t) {
+      const int64_t tile = tile0 + t;
+      const u32x4* tb = reinterpret_cast<const u32x4*>(v16) + tile * nc8 * TILE;
+      f32x4 acc[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < KSMAX; ++s) {
+        if (s < KS) {
+          const u32x4* row = tb + (int64_t)(4 * s + (lane >> 4)) * TILE + (lane & 15);
+          u32x4 a[4];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) a[b] = row[16 * b];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[b] = mfma16<F16>(a[b], breg[s], acc[b]);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Sw[j][16 * b + (lane >> 4) * 4 + v] = acc[b][v];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      const bool valid = t * TILE + lane < size;
+      const int32_t slot = (int32_t)(tile * TILE + lane);
+      const float xn = IP ? 0.f : v16n[slot];
+#pragma unroll
+      for (int jj = 0; jj < G; ++jj) {
+        if (jj >= gcount) break;
+        const float dot = Sw[jj][lane];
+        const float key = IP ? -dot : (__shfl(my_qn2, jj) + xn - 2.f * dot);
+        bool pass = valid && !(key > tk[jj]);
+        if (pass) pass = sid[slot] >= 0 && ks_less(key, slot, tk[jj], ts[jj]);
+        uint64_t mask = __ballot(pass);
+        while (mask) {
+          const int src = __builtin_ctzll(mask);
+          mask &= mask - 1;
+          const float ck = readlane_f(key, src);
+          const int32_t cs = (int32_t)(tile * TILE) + src;
+          if (ks_less(ck, cs, tk[jj], ts[jj])) lane_list_insert(lk[jj], ls[jj], ck, cs, kk, tk[jj], ts[jj]);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+#pragma unroll
+    for (int jj = 0; jj < G; ++jj) {
+      if (jj >= gcount) break;
+      const int pr = __builtin_amdgcn_readlane(pair, jj);
+      const int64_t out = (pair_base[pr] + c) * kk;
+      if (lane < kk) {
+        pk[out + lane] = lk[jj];
+        pi[out + lane] = (int64_t)ls[jj];
+      }
+    }
+  }
+}
+
+template <int F16, int IP>
+static void scan_mfma_k(Workspace& ws, const Store& st, const RoundArgs& a, int blocks, hipStream_t s) {
+  const int ks = st.dp16 / 32;
+#define QK_MFMA_LAUNCH(KSM)                                                                                      \
+  hipLaunchKernelGGL((k_scan_mfma<F16, KSM, IP>), dim3(blocks), dim3(256), 0, s, ws.total, ws.pitem, ws.pstart, \
+                     ws.sorted, ws.pair_q, ws.pair_base, st.nlist, a.chunk_tiles, ws.q16, st.dp16, ws.qn2f,     \
+                     st.v16, st.v16n, st.ids, st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi)
+  if (ks <= 4) QK_MFMA_LAUNCH(4);
+  else if (ks <= 8) QK_MFMA_LAUNCH(8);
+  else if (ks <= 16) QK_MFMA_LAUNCH(16);
+  else if (ks <= 24) QK_MFMA_LAUNCH(24);
+  else QK_MFMA_LAUNCH(32);
+#undef QK_MFMA_LAUNCH
+}
+
+void launch_scan_mfma(Workspace& ws, const Store& st, const RoundArgs& a, int dtype16, int blocks, hipStream_t s) {
+  const bool f16 = dtype16 == QUAKE_F16;
+  const bool ip = a.metric == QUAKE_IP;
+  if (f16) { if (ip) scan_mfma_k<1, 1>(ws, st, a, blocks, s); else scan_mfma_k<1, 0>(ws, st, a, blocks, s); }
+  else { if (ip) scan_mfma_k<0, 1>(ws, st, a, blocks, s); else scan_mfma_k<0, 0>(ws, st, a, blocks, s); }
+}
+
+// ---------------------------------------------------------------- rerank
+
+// Re-score each query's candidates (store slots) in FP32 from the FP32 store,
+// with the plain scan's arithmetic, and keep the best k by (distance, id).
+template <int METRIC>
+__global__ __launch_bounds__(64) void k_rerank(int64_t nq, int k, int kk, const float* __restrict__ qpad, int dp,
+                                                const float* __restrict__ v32, const int64_t* __restrict__ sid,
+                                                float* __restrict__ rk, int64_t* __restrict__ ri) {
+  const int64_t q = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int nch4 = dp >> 2;
+  const_float4* qs = (const_float4*)(qpad + q * dp);
+  float key = KEY_EMPTY;
+  int64_t id = -1;
+  const int64_t slot = lane < kk ? ri[q * kk + lane] : -1;
+  if (slot >= 0) {
+    const int64_t tile = slot / TILE;
+    const int tl = (int)(slot - tile * TILE);
+    const float4* xp = reinterpret_cast<const float4*>(v32) + tile * (int64_t)nch4 * TILE + tl;
+    key = tile_distance<METRIC>(xp, qs, nch4);
+    id = sid[slot];
+  }
+  // bitonic sort of the 64 (key, id) pairs across the wave, ascending
+  for (int size = 2; size <= WAVE; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const float ok = __shfl_xor(key, stride);
+      const int64_t oi = (int64_t)(((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)((uint64_t)id >> 32), stride) << 32) |
+                                   (uint32_t)__shfl_xor((int)(uint32_t)(uint64_t)id, stride));
+      const bool up = (lane & size) == 0;
+      const bool lower = (lane & stride) == 0;
+      const bool other_first = kv_less(ok, oi, key, id);
+      const bool take = (lower == up) ? other_first : !other_first;
+      if (take) { key = ok; id = oi; }
+    }
+  }
+  if (lane < k) { rk[q * kk + lane] = key; ri[q * kk + lane] = id; }
+}
+
+void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
+  if (a.nq <= 0) return;
+  if (a.metric == QUAKE_L2)
+    hipLaunchKernelGGL(k_rerank<QUAKE_L2>, dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.k, a.kk, ws.q, st.dp, st.v32,
+                       st.ids, ws.rk, ws.ri);
+  else
+    hipLaunchKernelGGL(k_rerank<QUAKE_IP>, dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.k, a.kk, ws.q, st.dp, st.v32,
+                       st.ids, ws.rk, ws.ri);
+}
+
+// ---------------------------------------------------------------- store norms
+
+// |x|^2 of the 16-bit copy of every slot (for L2 keys from inner products).
+__global__ __launch_bounds__(256) void k_norm16(const uint16_t* __restrict__ v16, int64_t slots, int dp16, int f16,
+                                                 float* __restrict__ out) {
+  const int64_t sl = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (sl >= slots) return;
+  const int64_t tile = sl / TILE;
+  const int lane = (int)(sl - tile * TILE);
+  const int nc8 = dp16 >> 3;
+  float acc = 0.f;
+  for (int c = 0; c < nc8; ++c) {
+    const uint16_t* e = v16 + ((tile * nc8 + c) * TILE + lane) * 8;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const float v = f16 ? (float)__builtin_bit_cast(_Float16, e[u]) : __uint_as_float((uint32_t)e[u] << 16);
+      acc = fmaf(v, v, acc);
+    }
+  }
+  out[sl] = acc;
+}
+
+void launch_norm16(const Store& st, int dtype16, hipStream_t s) {
+  const int64_t slots = st.tiles * TILE;
+  if (slots <= 0 || !st.v16 || !st.v16n) return;
+  hipLaunchKernelGGL(k_norm16, dim3((unsigned)((slots + 255) / 256)), dim3(256), 0, s, st.v16, slots, st.dp16,
+                     dtype16 == QUAKE_F16 ? 1 : 0, st.v16n);
+}
+
+}  // namespace qk

@@ -50,9 +50,9 @@ __global__ __launch_bounds__(256) void k_round_init(int64_t nq, int kk, int w0, 
 }
 
 void launch_round_init(Workspace& ws, const RoundArgs& a, int w0, hipStream_t s) {
-  const int64_t n = a.nq * a.k;
+  const int64_t n = a.nq * a.kk;
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_round_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.nq, a.k, w0, ws.st_m,
+  hipLaunchKernelGGL(k_round_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.nq, a.kk, w0, ws.st_m,
                      ws.st_w, ws.st_done, ws.st_rho, ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri);
 }
 
@@ -91,7 +91,8 @@ __global__ __launch_bounds__(256) void k_demand(int64_t nq, int M, int chunk_til
 // first unfinished query's window, so every round makes progress.
 __global__ __launch_bounds__(1024) void k_prefix(int64_t nq, int64_t cap, const int64_t* __restrict__ demand,
                                                   const int64_t* __restrict__ vecs, int64_t* __restrict__ first,
-                                                  int32_t* __restrict__ st_weff, int64_t* __restrict__ total) {
+                                                  int32_t* __restrict__ st_weff, int64_t* __restrict__ first_pair,
+                                                  int64_t* __restrict__ total) {
   __shared__ int64_t part[1024];
   __shared__ int64_t overflow_at;
   __shared__ unsigned long long nvecs;
@@ -118,16 +119,34 @@ __global__ __launch_bounds__(1024) void k_prefix(int64_t nq, int64_t cap, const 
   }
   __syncthreads();
   const int64_t cut = overflow_at;
+  const int64_t items = (cut < nq) ? first[cut] : part[1023];
   unsigned long long nv = 0;
+  int64_t w = 0;
   for (int64_t i = lo; i < hi; ++i) {
     if (i >= cut) st_weff[i] = 0;
     else nv += (unsigned long long)vecs[i];
+    w += st_weff[i];
   }
   atomicAdd(&nvecs, nv);
   __syncthreads();
+  // second scan: (query, partition) pairs of the queries that run this round
+  part[t] = w;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t v = (t >= o) ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  run = part[t] - w;
+  for (int64_t i = lo; i < hi; ++i) {
+    first_pair[i] = run;
+    run += st_weff[i];
+  }
   if (t == 0) {
-    total[0] = (cut < nq) ? first[cut] : part[1023];
+    total[0] = items;
     total[1] = (int64_t)nvecs;
+    total[2] = part[1023];
   }
 }
 
@@ -135,7 +154,7 @@ void launch_demand(Workspace& ws, const Store& st, const RoundArgs& a, hipStream
   hipLaunchKernelGGL(k_demand, dim3((unsigned)((a.nq + 255) / 256)), dim3(256), 0, s, a.nq, a.M, a.chunk_tiles,
                      ws.cand, st.d_size, ws.st_m, ws.st_w, ws.st_weff, ws.st_done, ws.st_demand, ws.st_vecs);
   hipLaunchKernelGGL(k_prefix, dim3(1), dim3(1024), 0, s, a.nq, a.items_cap, ws.st_demand, ws.st_vecs, ws.st_item,
-                     ws.st_weff, ws.total);
+                     ws.st_weff, ws.st_pair, ws.total);
 }
 
 // Write the work items of each query's window, in candidate order.
@@ -170,43 +189,6 @@ void launch_emit(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t
 }
 
 // ---------------------------------------------------------------- FP32 scan
-
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef const __attribute__((address_space(4))) f32x4 const_float4;
-
-// Distance of the query to the 64 vectors of one tile, one vector per lane.
-// The query is read through the scalar unit (one copy for the whole wave);
-// the tile through 16-byte loads that cover 1 KiB contiguous per wave.  Eight
-// partial sums (one per dimension modulo 8) are combined pairwise at the end.
-template <int METRIC>
-__device__ __forceinline__ float tile_distance(const float4* __restrict__ xp, const_float4* qs, int nch4) {
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f, a6 = 0.f, a7 = 0.f;
-#pragma unroll 4
-  for (int c = 0; c < nch4; c += 2) {
-    const float4 x = xp[(int64_t)c * WAVE];
-    const float4 y = xp[(int64_t)(c + 1) * WAVE];
-    const f32x4 qa = qs[c];
-    const f32x4 qb = qs[c + 1];
-    if (METRIC == QUAKE_L2) {
-      float t;
-      t = x.x - qa.x; a0 = fmaf(t, t, a0);
-      t = x.y - qa.y; a1 = fmaf(t, t, a1);
-      t = x.z - qa.z; a2 = fmaf(t, t, a2);
-      t = x.w - qa.w; a3 = fmaf(t, t, a3);
-      t = y.x - qb.x; a4 = fmaf(t, t, a4);
-      t = y.y - qb.y; a5 = fmaf(t, t, a5);
-      t = y.z - qb.z; a6 = fmaf(t, t, a6);
-      t = y.w - qb.w; a7 = fmaf(t, t, a7);
-    } else {
-      a0 = fmaf(x.x, qa.x, a0); a1 = fmaf(x.y, qa.y, a1);
-      a2 = fmaf(x.z, qa.z, a2); a3 = fmaf(x.w, qa.w, a3);
-      a4 = fmaf(y.x, qb.x, a4); a5 = fmaf(y.y, qb.y, a5);
-      a6 = fmaf(y.z, qb.z, a6); a7 = fmaf(y.w, qb.w, a7);
-    }
-  }
-  const float s = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
-  return METRIC == QUAKE_L2 ? s : -s;
-}
 
 template <int METRIC, int KPL>
 __global__ __launch_bounds__(256) void k_scan_f32(const int4* __restrict__ items, int64_t nitems,
@@ -258,15 +240,15 @@ __global__ __launch_bounds__(256) void k_scan_f32(const int4* __restrict__ items
 template <int METRIC>
 static void scan_f32_k(Workspace& ws, const Store& st, const RoundArgs& a, int64_t nitems, hipStream_t s) {
   const dim3 grid((unsigned)((nitems + 3) / 4));
-  if (a.k <= 64)
+  if (a.kk <= 64)
     hipLaunchKernelGGL((k_scan_f32<METRIC, 1>), grid, dim3(256), 0, s, ws.items, nitems, ws.q, st.dp, st.v32, st.ids,
-                       st.d_off, st.d_size, ws.rk, ws.ri, a.k, ws.pk, ws.pi);
-  else if (a.k <= 128)
+                       st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi);
+  else if (a.kk <= 128)
     hipLaunchKernelGGL((k_scan_f32<METRIC, 2>), grid, dim3(256), 0, s, ws.items, nitems, ws.q, st.dp, st.v32, st.ids,
-                       st.d_off, st.d_size, ws.rk, ws.ri, a.k, ws.pk, ws.pi);
+                       st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi);
   else
     hipLaunchKernelGGL((k_scan_f32<METRIC, 4>), grid, dim3(256), 0, s, ws.items, nitems, ws.q, st.dp, st.v32, st.ids,
-                       st.d_off, st.d_size, ws.rk, ws.ri, a.k, ws.pk, ws.pi);
+                       st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi);
 }
 
 void launch_scan_f32(Workspace& ws, const Store& st, const RoundArgs& a, int64_t nitems, hipStream_t s) {
@@ -430,7 +412,7 @@ __global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, int k, int kk,
 }
 
 void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const double* table, hipStream_t s) {
-  hipLaunchKernelGGL((k_commit<1>), dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.M, a.k /*k*/, a.k, a.aps,
+  hipLaunchKernelGGL((k_commit<1>), dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.M, a.k, a.kk, a.aps,
                      a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.tau_r, a.tau_rho, ws.cand, ws.h,
                      st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_weff, ws.st_item,
                      ws.st_rho,
@@ -461,7 +443,7 @@ void launch_finalize(Workspace& ws, const RoundArgs& a, int64_t* out_ids, float*
                      double* out_recall, hipStream_t s) {
   const int64_t n = a.nq * a.k;
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.nq, a.k, a.k,
+  hipLaunchKernelGGL(k_finalize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a.nq, a.k, a.kk,
                      a.metric == QUAKE_IP ? 1 : 0, ws.rk, ws.ri, ws.st_m, ws.st_r, out_ids, out_dist, out_nscanned,
                      out_recall);
 }

@@ -17,9 +17,10 @@ __device__ __forceinline__ uint16_t to_f16(float f) {
 }
 
 // Row i goes to store slot slot[i] = tile * 64 + lane.  One thread moves one
-// 4-float chunk: FP32 at [tile][chunk/4 .. as float4][lane], the 16-bit copy
-// at [tile][chunk/8][lane][8] (half of an 8-element group per thread).
-__global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ x, int64_t n, int d, int dp,
+// 4-float chunk: FP32 at [tile][chunk][lane][4], the 16-bit copy at
+// [tile][chunk/2][lane][8] (half of an 8-element group per thread; the copy's
+// rows are dp16 long and the chunks past dp stay zero).
+__global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ x, int64_t n, int d, int dp, int dp16,
                                                   const int64_t* __restrict__ ids, const int64_t* __restrict__ slot,
                                                   float* __restrict__ v32, uint16_t* __restrict__ v16, int dtype16,
                                                   int64_t* __restrict__ sid) {
@@ -41,19 +42,19 @@ __global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ x, in
   *dst = make_float4(v[0], v[1], v[2], v[3]);
   if (v16) {
     const int c8 = c4 >> 1, half = c4 & 1;
-    uint16_t* d16 = v16 + ((tile * (dp >> 3) + c8) * TILE + lane) * 8 + half * 4;
+    uint16_t* d16 = v16 + ((tile * (dp16 >> 3) + c8) * TILE + lane) * 8 + half * 4;
 #pragma unroll
     for (int u = 0; u < 4; ++u) d16[u] = dtype16 == QUAKE_F16 ? to_f16(v[u]) : to_bf16(v[u]);
   }
   if (c4 == 0) sid[sl] = ids ? ids[row] : row;
 }
 
-void launch_scatter(const float* x, int64_t n, int d, int dp, const int64_t* ids, const int64_t* slot, float* v32,
-                    uint16_t* v16, int dtype16, int64_t* sid, hipStream_t s) {
+void launch_scatter(const float* x, int64_t n, int d, int dp, int dp16, const int64_t* ids, const int64_t* slot,
+                    float* v32, uint16_t* v16, int dtype16, int64_t* sid, hipStream_t s) {
   const int64_t total = n * (dp >> 2);
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, x, n, d, dp, ids, slot, v32,
-                     v16, dtype16, sid);
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, x, n, d, dp, dp16, ids, slot,
+                     v32, v16, dtype16, sid);
 }
 
 // ids and partition of every filled slot, partition by partition.
