@@ -247,7 +247,7 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
   st.used_tiles = tiles;
   st.v32 = idx->mem.alloc<float>((size_t)arena * qk::TILE * st.dp);
   QK_HIP(hipMemsetAsync(st.v32, 0, (size_t)arena * qk::TILE * st.dp * sizeof(float), s));
-  st.dp16 = (int)round_up(st.d, 32);
+  st.dp16 = qk::padded_dim16(st.d);
   if (dtype16 != QUAKE_F32) {
     st.v16 = idx->mem.alloc<uint16_t>((size_t)arena * qk::TILE * st.dp16);
     QK_HIP(hipMemsetAsync(st.v16, 0, (size_t)arena * qk::TILE * st.dp16 * sizeof(uint16_t), s));
@@ -305,6 +305,7 @@ Resolved resolve(const quake_index* idx, const Store& st, const quake_search_par
   QK_CHECK(p->rerank_factor >= 0, QUAKE_E_INVALID, "rerank_factor must be >= 0");
   r.kk = r.batched ? std::max(p->rerank_factor > 0 ? p->rerank_factor : 4, 1) * r.k : r.k;
   QK_CHECK(!r.batched || r.kk <= 64, QUAKE_E_INVALID, "the batched scan keeps at most 64 candidates per query");
+  QK_CHECK(!r.batched || st.dp16 <= 1024, QUAKE_E_INVALID, "the batched scan supports d <= 1024");
   r.aps = has_rt ? 1 : 0;
   r.tau_r = p->recall_target;
   r.f_M = p->f_M > 0 ? p->f_M : 0.05;

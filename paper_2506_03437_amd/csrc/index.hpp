@@ -29,6 +29,15 @@ struct Error {
 constexpr int TILE = 64;          // vectors per store tile: one per lane of a wave
 constexpr int KMAX = 256;         // largest k of the search path
 constexpr int CAP_TABLE_POINTS = 1024;
+
+// Row length of the 16-bit store copy: d rounded up to 32 * KS for a k-step
+// count KS the MFMA scan is compiled for (2, 4, 8, 12, 16, 24 or 32).
+inline int padded_dim16(int d) {
+  const int need = (d + 31) / 32;
+  for (int ks : {2, 4, 8, 12, 16, 24, 32})
+    if (ks >= need) return 32 * ks;
+  return 32 * need;
+}
 constexpr int MAX_DIM = 4096;
 constexpr int MAX_CANDIDATES = 4096;   // APS candidate set M (and nprobe) upper bound
 

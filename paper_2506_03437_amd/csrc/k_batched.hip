@@ -183,20 +183,43 @@ __device__ __forceinline__ bool ks_less(float ak, int32_t as, float bk, int32_t 
   return ak < bk || (ak == bk && as < bs);
 }
 
-// A sorted candidate list with one entry per lane (up to 64 entries).
-__device__ __forceinline__ void lane_list_insert(float& lk, int32_t& ls, float ck, int32_t cs, int kk, float& tk,
-                                                 int32_t& ts) {
-  const int lane = lane_id();
-  const int pos = __popcll(__ballot(ks_less(lk, ls, ck, cs)));
-  const float uk = __shfl_up(lk, 1);
-  const int32_t us = __shfl_up(ls, 1);
-  if (lane > pos) { lk = uk; ls = us; }
-  else if (lane == pos) { lk = ck; ls = cs; }
-  const int32_t ns = __builtin_amdgcn_readlane(ls, kk - 1);
-  if (ns >= 0) { tk = readlane_f(lk, kk - 1); ts = ns; }
+__device__ __forceinline__ void swap_if(bool take, float& k, int32_t& s, float ok, int32_t os) {
+  if (take) { k = ok; s = os; }
 }
 
-template <int F16, int KSMAX, int IP>
+// One compare-exchange stage of a bitonic network across the wave: lanes
+// `stride` apart swap so that the lower lane of each pair keeps the smaller
+// entry in ascending runs of length `size` (and the larger in descending ones).
+__device__ __forceinline__ void bitonic_step(float& k, int32_t& s, int size, int stride) {
+  const int lane = lane_id();
+  const float ok = __shfl_xor(k, stride);
+  const int32_t os = __shfl_xor(s, stride);
+  const bool up = (lane & size) == 0;
+  const bool lower = (lane & stride) == 0;
+  const bool other_first = ks_less(ok, os, k, s);
+  swap_if((lower == up) ? other_first : (!other_first && (ok != k || os != s)), k, s, ok, os);
+}
+
+// Sort one entry per lane ascending by (key, slot).
+__device__ __forceinline__ void wave_sort64(float& k, int32_t& s) {
+#pragma unroll
+  for (int size = 2; size <= WAVE; size <<= 1)
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) bitonic_step(k, s, size, stride);
+}
+
+// list (ascending, one entry per lane) := the 64 smallest of list and b
+// (b ascending): a bitonic split against b reversed, then a bitonic merge.
+__device__ __forceinline__ void wave_merge64(float& lk, int32_t& ls, float bk, int32_t bs) {
+  const int lane = lane_id();
+  const float rk = __shfl(bk, WAVE - 1 - lane);
+  const int32_t rs = __shfl(bs, WAVE - 1 - lane);
+  swap_if(ks_less(rk, rs, lk, ls), lk, ls, rk, rs);
+#pragma unroll
+  for (int stride = WAVE / 2; stride > 0; stride >>= 1) bitonic_step(lk, ls, WAVE, stride);
+}
+
+template <int F16, int KS, int IP>
 __global__ __launch_bounds__(256, 2) void k_scan_mfma(
     const int64_t* __restrict__ counters, const int64_t* __restrict__ pitem, const int32_t* __restrict__ pstart,
     const int32_t* __restrict__ sorted, const int32_t* __restrict__ pair_q, const int64_t* __restrict__ pair_base,
@@ -205,15 +228,25 @@ __global__ __launch_bounds__(256, 2) void k_scan_mfma(
     const int64_t* __restrict__ poff, const int32_t* __restrict__ psize, const float* __restrict__ rk,
     const int64_t* __restrict__ ri, int kk, float* __restrict__ pk, int64_t* __restrict__ pi) {
   __shared__ float S[4][G][TILE + 1];
+  __shared__ float BK[4][G][WAVE];      // per query: candidates that beat the threshold, not yet merged
+  __shared__ int32_t BS[4][G][WAVE];
+  __shared__ float TK[4][G];            // per query: key and slot a candidate must beat
+  __shared__ int32_t TS[4][G];
+  __shared__ int32_t CN[4][G];          // per query: candidates waiting in BK / BS
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // consecutive logical blocks on one XCD (blocks are dealt to the 8 XCDs in turn)
   int lb = blockIdx.x;
   if ((gridDim.x & 7) == 0) lb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
   const int64_t total = counters[3];
   const int64_t stride = (int64_t)gridDim.x * 4;
-  const int KS = dp16 >> 5;
-  const int nc8 = dp16 >> 3;
+  static_assert(KS >= 2, "the load pipeline runs two k-steps ahead");
+  constexpr int nc8 = KS * 4;  // 8-element chunks per row of the 16-bit copy
   float (*Sw)[TILE + 1] = S[wave];
+  float (*Bk)[WAVE] = BK[wave];
+  int32_t (*Bs)[WAVE] = BS[wave];
+  float* Tk = TK[wave];
+  int32_t* Ts = TS[wave];
+  int32_t* Cn = CN[wave];
   for (int64_t it = (int64_t)lb * 4 + wave; it < total; it += stride) {
     int64_t lo = 0, hi = N;
     while (hi - lo > 1) {
@@ -234,46 +267,80 @@ __global__ __launch_bounds__(256, 2) void k_scan_mfma(
     const bool has = j < gcount;
     const int pair = has ? sorted[pstart[p] + g * G + j] : 0;
     const int qj = has ? pair_q[pair] : 0;
-    u32x4 breg[KSMAX];
+    u32x4 breg[KS];
 #pragma unroll
-    for (int s = 0; s < KSMAX; ++s) {
+    for (int s = 0; s < KS; ++s) {
       u32x4 b = {0u, 0u, 0u, 0u};
-      if (s < KS && has) b = *reinterpret_cast<const u32x4*>(q16 + (int64_t)qj * dp16 + 32 * s + 8 * (lane >> 4));
+      if (has) b = *reinterpret_cast<const u32x4*>(q16 + (int64_t)qj * dp16 + 32 * s + 8 * (lane >> 4));
       breg[s] = b;
     }
     const float my_qn2 = (IP || !has) ? 0.f : qn2f[qj];
-    float lk[G], tk[G];
-    int32_t ls[G], ts[G];
+    // per query: a sorted list of its 64 best (one entry per lane), the
+    // threshold a candidate must beat (the kk-th entry, or the seed from the
+    // query's committed results) and the fill of its LDS buffer
+    float lk[G];
+    int32_t ls[G];
 #pragma unroll
-    for (int jj = 0; jj < G; ++jj) {
-      lk[jj] = KEY_EMPTY;
-      ls[jj] = -1;
-      tk[jj] = -KEY_EMPTY;
-      ts[jj] = -1;
-      if (jj < gcount) {
-        const int qq = __builtin_amdgcn_readlane(qj, jj);
-        tk[jj] = rk[(int64_t)qq * kk + kk - 1];
-        ts[jj] = (int32_t)ri[(int64_t)qq * kk + kk - 1];
+    for (int jj = 0; jj < G; ++jj) { lk[jj] = KEY_EMPTY; ls[jj] = -1; }
+    if (lane < G) {
+      float sk = -KEY_EMPTY;
+      int32_t ss = -1;
+      if (lane < gcount) {
+        sk = rk[(int64_t)qj * kk + kk - 1];
+        ss = (int32_t)ri[(int64_t)qj * kk + kk - 1];
       }
+      Tk[lane] = sk;
+      Ts[lane] = ss;
+      Cn[lane] = 0;
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    auto flush = [&](int jj) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      const int n = Cn[jj];
+      float bk = KEY_EMPTY;
+      int32_t bs = -1;
+      if (lane < n) { bk = Bk[jj][lane]; bs = Bs[jj][lane]; }
+      wave_sort64(bk, bs);
+      wave_merge64(lk[jj], ls[jj], bk, bs);
+      const int32_t ns = __builtin_amdgcn_readlane(ls[jj], kk - 1);
+      const float nk = readlane_f(lk[jj], kk - 1);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      if (lane == 0) {
+        Cn[jj] = 0;
+        if (ns >= 0) { Tk[jj] = nk; Ts[jj] = ns; }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    };
     const int64_t tile0 = poff[p];
+    // A fragments of one k-step: vectors 16b + (lane & 15) of the tile,
+    // elements 32s + 8 (lane >> 4) .. + 7, i.e. 16-byte chunk 4s + (lane >> 4)
+    const int frag = (lane >> 4) * TILE + (lane & 15);
+    auto kstep = [&](const u32x4* tb, int s, u32x4 (&a)[4]) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) a[b] = tb[(int64_t)(4 * s) * TILE + frag + 16 * b];
+    };
+    // Loads run two k-steps ahead of the MFMAs and continue into the next
+    // tile, so its first fragments are in flight during this tile's top-k.
+    const u32x4* tb_cur = reinterpret_cast<const u32x4*>(v16) + (tile0 + t0) * (int64_t)nc8 * TILE;
+    u32x4 pa[2][4];
+    if (t0 < t1) {
+      kstep(tb_cur, 0, pa[0]);
+      kstep(tb_cur, 1, pa[1]);
+    }
     for (int t = t0; t < t1; ++t) {
       const int64_t tile = tile0 + t;
-      const u32x4* tb = reinterpret_cast<const u32x4*>(v16) + tile * nc8 * TILE;
+      const u32x4* tb_next = (t + 1 < t1) ? tb_cur + (int64_t)nc8 * TILE : tb_cur;
       f32x4 acc[4];
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int s = 0; s < KSMAX; ++s) {
-        if (s < KS) {
-          const u32x4* row = tb + (int64_t)(4 * s + (lane >> 4)) * TILE + (lane & 15);
-          u32x4 a[4];
+      for (int s = 0; s < KS; ++s) {
 #pragma unroll
-          for (int b = 0; b < 4; ++b) a[b] = row[16 * b];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[b] = mfma16<F16>(a[b], breg[s], acc[b]);
-        }
+        for (int b = 0; b < 4; ++b) acc[b] = mfma16<F16>(pa[s & 1][b], breg[s], acc[b]);
+        if (s + 2 < KS) kstep(tb_cur, s + 2, pa[s & 1]);
+        else kstep(tb_next, s + 2 - KS, pa[s & 1]);
       }
+      tb_cur = tb_next;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
 #pragma unroll
       for (int b = 0; b < 4; ++b)
@@ -283,20 +350,35 @@ __global__ __launch_bounds__(256, 2) void k_scan_mfma(
       const bool valid = t * TILE + lane < size;
       const int32_t slot = (int32_t)(tile * TILE + lane);
       const float xn = IP ? 0.f : v16n[slot];
+      const bool live = valid && sid[slot] >= 0;
 #pragma unroll
       for (int jj = 0; jj < G; ++jj) {
         if (jj >= gcount) break;
         const float dot = Sw[jj][lane];
         const float key = IP ? -dot : (__shfl(my_qn2, jj) + xn - 2.f * dot);
-        bool pass = valid && !(key > tk[jj]);
-        if (pass) pass = sid[slot] >= 0 && ks_less(key, slot, tk[jj], ts[jj]);
+        const float tkj = Tk[jj];
+        const int32_t tsj = Ts[jj];
+        bool pass = live && ks_less(key, slot, tkj, tsj);
         uint64_t mask = __ballot(pass);
-        while (mask) {
-          const int src = __builtin_ctzll(mask);
-          mask &= mask - 1;
-          const float ck = readlane_f(key, src);
-          const int32_t cs = (int32_t)(tile * TILE) + src;
-          if (ks_less(ck, cs, tk[jj], ts[jj])) lane_list_insert(lk[jj], ls[jj], ck, cs, kk, tk[jj], ts[jj]);
+        if (mask) {
+          int n = __popcll(mask);
+          int c0 = Cn[jj];
+          if (c0 + n > WAVE) {
+            flush(jj);
+            pass = live && ks_less(key, slot, Tk[jj], Ts[jj]);
+            mask = __ballot(pass);
+            n = __popcll(mask);
+            c0 = 0;
+          }
+          const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+          if (pass) {
+            Bk[jj][c0 + rank] = key;
+            Bs[jj][c0 + rank] = slot;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          if (lane == 0) Cn[jj] = c0 + n;
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -304,6 +386,7 @@ __global__ __launch_bounds__(256, 2) void k_scan_mfma(
 #pragma unroll
     for (int jj = 0; jj < G; ++jj) {
       if (jj >= gcount) break;
+      if (Cn[jj] > 0) flush(jj);
       const int pr = __builtin_amdgcn_readlane(pair, jj);
       const int64_t out = (pair_base[pr] + c) * kk;
       if (lane < kk) {
@@ -317,15 +400,20 @@ __global__ __launch_bounds__(256, 2) void k_scan_mfma(
 template <int F16, int IP>
 static void scan_mfma_k(Workspace& ws, const Store& st, const RoundArgs& a, int blocks, hipStream_t s) {
   const int ks = st.dp16 / 32;
-#define QK_MFMA_LAUNCH(KSM)                                                                                      \
-  hipLaunchKernelGGL((k_scan_mfma<F16, KSM, IP>), dim3(blocks), dim3(256), 0, s, ws.total, ws.pitem, ws.pstart, \
-                     ws.sorted, ws.pair_q, ws.pair_base, st.nlist, a.chunk_tiles, ws.q16, st.dp16, ws.qn2f,     \
+#define QK_MFMA_LAUNCH(KS)                                                                                      \
+  hipLaunchKernelGGL((k_scan_mfma<F16, KS, IP>), dim3(blocks), dim3(256), 0, s, ws.total, ws.pitem, ws.pstart, \
+                     ws.sorted, ws.pair_q, ws.pair_base, st.nlist, a.chunk_tiles, ws.q16, st.dp16, ws.qn2f,    \
                      st.v16, st.v16n, st.ids, st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi)
-  if (ks <= 4) QK_MFMA_LAUNCH(4);
-  else if (ks <= 8) QK_MFMA_LAUNCH(8);
-  else if (ks <= 16) QK_MFMA_LAUNCH(16);
-  else if (ks <= 24) QK_MFMA_LAUNCH(24);
-  else QK_MFMA_LAUNCH(32);
+  switch (ks) {
+    case 2: QK_MFMA_LAUNCH(2); break;
+    case 4: QK_MFMA_LAUNCH(4); break;
+    case 8: QK_MFMA_LAUNCH(8); break;
+    case 12: QK_MFMA_LAUNCH(12); break;
+    case 16: QK_MFMA_LAUNCH(16); break;
+    case 24: QK_MFMA_LAUNCH(24); break;
+    case 32: QK_MFMA_LAUNCH(32); break;
+    default: break;  // rows of the 16-bit copy are padded to one of these lengths
+  }
 #undef QK_MFMA_LAUNCH
 }
 
