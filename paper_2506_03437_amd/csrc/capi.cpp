@@ -252,6 +252,8 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
     st.v16 = idx->mem.alloc<uint16_t>((size_t)arena * qk::TILE * st.dp16);
     QK_HIP(hipMemsetAsync(st.v16, 0, (size_t)arena * qk::TILE * st.dp16 * sizeof(uint16_t), s));
     if (idx->metric == QUAKE_L2) st.v16n = idx->mem.alloc<float>((size_t)arena * qk::TILE);
+    st.rows32 = idx->mem.alloc<float>((size_t)arena * qk::TILE * st.dp);
+    QK_HIP(hipMemsetAsync(st.rows32, 0, (size_t)arena * qk::TILE * st.dp * sizeof(float), s));
   }
   st.ids = idx->mem.alloc<int64_t>((size_t)arena * qk::TILE);
   QK_HIP(hipMemsetAsync(st.ids, 0xff, (size_t)arena * qk::TILE * sizeof(int64_t), s));
@@ -264,7 +266,7 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
   {
     Tmp<int64_t> d_slot(idx->mem, n);
     QK_HIP(hipMemcpyAsync(d_slot.p, slot.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    qk::launch_scatter(xin, n, d, st.dp, st.dp16, ids, d_slot.p, st.v32, st.v16, dtype16, st.ids, s);
+    qk::launch_scatter(xin, n, d, st.dp, st.dp16, ids, d_slot.p, st.v32, st.v16, dtype16, st.rows32, st.ids, s);
     qk::launch_norm16(st, dtype16, s);
     QK_HIP(hipStreamSynchronize(s));
   }

@@ -77,6 +77,7 @@ struct Store {
   float* v32 = nullptr;
   uint16_t* v16 = nullptr;      // BF16 or FP16 copy, or null; tiles [dp16/8][64][8]
   float* v16n = nullptr;        // [tiles * 64] |x|^2 of the 16-bit copy (L2 only)
+  float* rows32 = nullptr;      // [tiles * 64][dp] row-major FP32 rows by slot (with a 16-bit copy: rerank)
   int64_t* ids = nullptr;       // [tiles * 64], -1 = empty or deleted
   int64_t live = 0;
 };
@@ -194,7 +195,7 @@ void launch_gather_rows(const float* x, int d, const int64_t* rows, int64_t nr, 
 
 // kernels: store (k_store.hip)
 void launch_scatter(const float* x, int64_t n, int d, int dp, int dp16, const int64_t* ids, const int64_t* slot,
-                    float* v32, uint16_t* v16, int dtype16, int64_t* sid, hipStream_t s);
+                    float* v32, uint16_t* v16, int dtype16, float* rows32, int64_t* sid, hipStream_t s);
 void launch_export(const Store& st, int64_t* ids, int32_t* part, const int64_t* part_first_out,
                    hipStream_t s);
 

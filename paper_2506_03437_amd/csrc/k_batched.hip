@@ -258,8 +258,12 @@ __global__ __launch_bounds__(256, 2) void k_scan_mfma(
     const int tiles = (size + TILE - 1) / TILE;
     const int nch = chunks_of(size, chunk_tiles);
     const int local = (int)(it - pitem[p]);
-    const int g = local / nch, c = local - (local / nch) * nch;
     const int np = pstart[p + 1] - pstart[p];
+    // the query group runs fastest, so that the waves of a block and the
+    // neighbouring blocks on the same XCD score the same tiles together and
+    // share them through L2
+    const int ngroups = (np + G - 1) / G;
+    const int c = local / ngroups, g = local - (local / ngroups) * ngroups;
     const int gcount = min(G, np - g * G);
     const int t0 = c * chunk_tiles;
     const int t1 = min(tiles, t0 + chunk_tiles);
@@ -426,26 +430,46 @@ void launch_scan_mfma(Workspace& ws, const Store& st, const RoundArgs& a, int dt
 
 // ---------------------------------------------------------------- rerank
 
-// Re-score each query's candidates (store slots) in FP32 from the FP32 store,
-// with the plain scan's arithmetic, and keep the best k by (distance, id).
+// Re-score each query's candidates (store slots) in FP32 and keep the best k
+// by (distance, id).  The vectors come from the row-major FP32 copy kept for
+// this purpose (one contiguous row per candidate; the tile-interleaved store
+// would fetch a whole cache line per 16 bytes used); the sum runs in the same
+// order as the plain scan's: eight partial sums over the dimensions modulo 8,
+// added pairwise.  One wave per query, one lane per candidate for the sort;
+// the distance of each candidate is computed by the whole wave.
 template <int METRIC>
 __global__ __launch_bounds__(64) void k_rerank(int64_t nq, int k, int kk, const float* __restrict__ qpad, int dp,
-                                                const float* __restrict__ v32, const int64_t* __restrict__ sid,
+                                                const float* __restrict__ rows, const int64_t* __restrict__ sid,
                                                 float* __restrict__ rk, int64_t* __restrict__ ri) {
   const int64_t q = blockIdx.x;
   const int lane = threadIdx.x;
-  const int nch4 = dp >> 2;
-  const_float4* qs = (const_float4*)(qpad + q * dp);
+  const float* qv = qpad + q * dp;
+  const int64_t myslot = lane < kk ? ri[q * kk + lane] : -1;
   float key = KEY_EMPTY;
   int64_t id = -1;
-  const int64_t slot = lane < kk ? ri[q * kk + lane] : -1;
-  if (slot >= 0) {
-    const int64_t tile = slot / TILE;
-    const int tl = (int)(slot - tile * TILE);
-    const float4* xp = reinterpret_cast<const float4*>(v32) + tile * (int64_t)nch4 * TILE + tl;
-    key = tile_distance<METRIC>(xp, qs, nch4);
-    id = sid[slot];
+  // lanes 8e .. 8e+7 hold the eight partial sums of candidate e (dimension j
+  // goes to partial j mod 8); candidates are handled eight at a time
+  const int part = lane & 7, grp = lane >> 3;
+  for (int e0 = 0; e0 < kk; e0 += 8) {
+    const int e = e0 + grp;
+    const int64_t slot = e < kk ? __shfl(myslot, e) : -1;
+    float acc = 0.f;
+    if (slot >= 0) {
+      const float* xv = rows + slot * (int64_t)dp;
+      for (int jj = part; jj < dp; jj += 8) {
+        const float x = xv[jj], y = qv[jj];
+        acc = METRIC == QUAKE_L2 ? fmaf(x - y, x - y, acc) : fmaf(x, y, acc);
+      }
+    }
+    // pairwise: ((a0+a1)+(a2+a3))+((a4+a5)+(a6+a7))
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    acc += __shfl_xor(acc, 4);
+    const float d = METRIC == QUAKE_L2 ? acc : -acc;
+    const float dk = __shfl(d, (lane - e0) * 8);
+    if (lane >= e0 && lane < e0 + 8 && myslot >= 0) key = dk;
   }
+  if (myslot >= 0) id = sid[myslot];
   // bitonic sort of the 64 (key, id) pairs across the wave, ascending
   for (int size = 2; size <= WAVE; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
@@ -465,11 +489,11 @@ __global__ __launch_bounds__(64) void k_rerank(int64_t nq, int k, int kk, const 
 void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
   if (a.nq <= 0) return;
   if (a.metric == QUAKE_L2)
-    hipLaunchKernelGGL(k_rerank<QUAKE_L2>, dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.k, a.kk, ws.q, st.dp, st.v32,
-                       st.ids, ws.rk, ws.ri);
+    hipLaunchKernelGGL(k_rerank<QUAKE_L2>, dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.k, a.kk, ws.q, st.dp,
+                       st.rows32, st.ids, ws.rk, ws.ri);
   else
-    hipLaunchKernelGGL(k_rerank<QUAKE_IP>, dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.k, a.kk, ws.q, st.dp, st.v32,
-                       st.ids, ws.rk, ws.ri);
+    hipLaunchKernelGGL(k_rerank<QUAKE_IP>, dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.k, a.kk, ws.q, st.dp,
+                       st.rows32, st.ids, ws.rk, ws.ri);
 }
 
 // ---------------------------------------------------------------- store norms

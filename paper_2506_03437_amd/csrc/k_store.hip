@@ -23,7 +23,7 @@ __device__ __forceinline__ uint16_t to_f16(float f) {
 __global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ x, int64_t n, int d, int dp, int dp16,
                                                   const int64_t* __restrict__ ids, const int64_t* __restrict__ slot,
                                                   float* __restrict__ v32, uint16_t* __restrict__ v16, int dtype16,
-                                                  int64_t* __restrict__ sid) {
+                                                  float* __restrict__ rows32, int64_t* __restrict__ sid) {
   const int nch4 = dp >> 2;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t row = e / nch4;
@@ -46,15 +46,16 @@ __global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ x, in
 #pragma unroll
     for (int u = 0; u < 4; ++u) d16[u] = dtype16 == QUAKE_F16 ? to_f16(v[u]) : to_bf16(v[u]);
   }
+  if (rows32) *reinterpret_cast<float4*>(rows32 + sl * dp + c4 * 4) = make_float4(v[0], v[1], v[2], v[3]);
   if (c4 == 0) sid[sl] = ids ? ids[row] : row;
 }
 
 void launch_scatter(const float* x, int64_t n, int d, int dp, int dp16, const int64_t* ids, const int64_t* slot,
-                    float* v32, uint16_t* v16, int dtype16, int64_t* sid, hipStream_t s) {
+                    float* v32, uint16_t* v16, int dtype16, float* rows32, int64_t* sid, hipStream_t s) {
   const int64_t total = n * (dp >> 2);
   if (total <= 0) return;
   hipLaunchKernelGGL(k_scatter, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, x, n, d, dp, dp16, ids, slot,
-                     v32, v16, dtype16, sid);
+                     v32, v16, dtype16, rows32, sid);
 }
 
 // ids and partition of every filled slot, partition by partition.

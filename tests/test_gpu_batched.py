@@ -107,10 +107,16 @@ def test_bf16_rerank_recall_gap(float_ip, tau):
 
 def test_bf16_nprobe_matches_fp32_candidates_closely(float_ip):
     X, Q, idx, ps, truth = float_ip
-    fi, _, _, _ = gu.search(idx, Q, k=10, nprobe=8)
-    bi, _, _, _ = gu.search(idx, Q, k=10, nprobe=8, scan_mode="batched", scan_dtype="bf16", rerank_factor=4)
+    fi, fv, _, _ = gu.search(idx, Q, k=10, nprobe=8)
+    bi, bv, _, _ = gu.search(idx, Q, k=10, nprobe=8, scan_mode="batched", scan_dtype="bf16", rerank_factor=4)
     same = np.mean([len(set(a.tolist()) & set(b.tolist())) / 10.0 for a, b in zip(fi, bi)])
     assert same >= 0.995, same
+    # the rerank sums in the plain scan's order: identical FP32 distances per id
+    for a_i, a_v, b_i, b_v in zip(fi, fv, bi, bv):
+        da = dict(zip(a_i.tolist(), a_v.tolist()))
+        for i, v in zip(b_i.tolist(), b_v.tolist()):
+            if i in da:
+                assert da[i] == v
 
 
 def test_batched_rejects_bad_modes(float_ip):
