@@ -216,6 +216,36 @@ void kmeans(qk::DeviceMemory& mem, const float* xpad, int64_t n, int dp, int64_t
   }
 }
 
+
+// ---------------------------------------------------------------- the store
+
+void alloc_store_arrays(quake_index* idx, Store& st, int64_t tiles, int dtype16, hipStream_t s) {
+  auto& mem = idx->mem;
+  const size_t slots = (size_t)tiles * qk::TILE;
+  st.v32 = mem.alloc<float>(slots * st.dp);
+  QK_HIP(hipMemsetAsync(st.v32, 0, slots * st.dp * sizeof(float), s));
+  if (dtype16 != QUAKE_F32) {
+    st.v16 = mem.alloc<uint16_t>(slots * st.dp16);
+    QK_HIP(hipMemsetAsync(st.v16, 0, slots * st.dp16 * sizeof(uint16_t), s));
+    if (idx->metric == QUAKE_L2) {
+      st.v16n = mem.alloc<float>(slots);
+      QK_HIP(hipMemsetAsync(st.v16n, 0, slots * sizeof(float), s));
+    }
+    st.rows32 = mem.alloc<float>(slots * st.dp);
+    QK_HIP(hipMemsetAsync(st.rows32, 0, slots * st.dp * sizeof(float), s));
+  }
+  st.ids = mem.alloc<int64_t>(slots);
+  QK_HIP(hipMemsetAsync(st.ids, 0xff, slots * sizeof(int64_t), s));
+  st.tiles = tiles;
+}
+
+void upload_table(Store& st, hipStream_t s) {
+  const int64_t N = st.nlist;
+  QK_HIP(hipMemcpyAsync(st.d_off, st.off.data(), N * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  QK_HIP(hipMemcpyAsync(st.d_size, st.size.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  QK_HIP(hipMemcpyAsync(st.d_cap, st.cap.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, s));
+}
+
 // Place rows into a fresh store: partition p gets capacity for its rows plus
 // slack, rounded up to whole tiles; rows keep their input order within a
 // partition.
@@ -226,6 +256,7 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
   QK_HIP(hipStreamSynchronize(s));
   const int64_t N = st.nlist;
   st.size.assign(N, 0);
+  st.tomb.assign(N, 0);
   for (int64_t i = 0; i < n; ++i) st.size[a[i]]++;
   st.cap.resize(N);
   st.off.resize(N);
@@ -236,33 +267,22 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
     st.off[p] = tiles;
     tiles += st.cap[p] / qk::TILE;
   }
+  st.tile_part.assign(std::max<int64_t>(tiles, 1), -1);
+  for (int64_t p = 0; p < N; ++p)
+    for (int64_t t = 0; t < st.cap[p] / qk::TILE; ++t) st.tile_part[st.off[p] + t] = (int32_t)p;
   std::vector<int64_t> slot(n);
   std::vector<int64_t> fill(N, 0);
   for (int64_t i = 0; i < n; ++i) {
     const int p = a[i];
     slot[i] = st.off[p] * qk::TILE + fill[p]++;
   }
-  const int64_t arena = std::max<int64_t>(tiles, 1);
-  st.tiles = arena;
-  st.used_tiles = tiles;
-  st.v32 = idx->mem.alloc<float>((size_t)arena * qk::TILE * st.dp);
-  QK_HIP(hipMemsetAsync(st.v32, 0, (size_t)arena * qk::TILE * st.dp * sizeof(float), s));
   st.dp16 = qk::padded_dim16(st.d);
-  if (dtype16 != QUAKE_F32) {
-    st.v16 = idx->mem.alloc<uint16_t>((size_t)arena * qk::TILE * st.dp16);
-    QK_HIP(hipMemsetAsync(st.v16, 0, (size_t)arena * qk::TILE * st.dp16 * sizeof(uint16_t), s));
-    if (idx->metric == QUAKE_L2) st.v16n = idx->mem.alloc<float>((size_t)arena * qk::TILE);
-    st.rows32 = idx->mem.alloc<float>((size_t)arena * qk::TILE * st.dp);
-    QK_HIP(hipMemsetAsync(st.rows32, 0, (size_t)arena * qk::TILE * st.dp * sizeof(float), s));
-  }
-  st.ids = idx->mem.alloc<int64_t>((size_t)arena * qk::TILE);
-  QK_HIP(hipMemsetAsync(st.ids, 0xff, (size_t)arena * qk::TILE * sizeof(int64_t), s));
+  alloc_store_arrays(idx, st, std::max<int64_t>(tiles, 1), dtype16, s);
+  st.used_tiles = tiles;
   st.d_off = idx->mem.alloc<int64_t>(N);
   st.d_size = idx->mem.alloc<int32_t>(N);
   st.d_cap = idx->mem.alloc<int32_t>(N);
-  QK_HIP(hipMemcpyAsync(st.d_off, st.off.data(), N * sizeof(int64_t), hipMemcpyHostToDevice, s));
-  QK_HIP(hipMemcpyAsync(st.d_size, st.size.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  QK_HIP(hipMemcpyAsync(st.d_cap, st.cap.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  upload_table(st, s);
   {
     Tmp<int64_t> d_slot(idx->mem, n);
     QK_HIP(hipMemcpyAsync(d_slot.p, slot.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
@@ -273,6 +293,96 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
   st.live = n;
 }
 
+// Enlarge the arena to at least `need` tiles (allocates before touching the
+// old arrays, so a failure leaves the store as it was).
+void grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s) {
+  if (need <= st.tiles) return;
+  const int64_t tiles = std::max<int64_t>(need, st.tiles + st.tiles / 2);
+  Store fresh;
+  fresh.d = st.d;
+  fresh.dp = st.dp;
+  fresh.dp16 = st.dp16;
+  alloc_store_arrays(idx, fresh, tiles, st.v16 ? idx->storage : QUAKE_F32, s);
+  const size_t used = (size_t)st.used_tiles * qk::TILE;
+  QK_HIP(hipMemcpyAsync(fresh.v32, st.v32, used * st.dp * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (st.v16) QK_HIP(hipMemcpyAsync(fresh.v16, st.v16, used * st.dp16 * sizeof(uint16_t), hipMemcpyDeviceToDevice, s));
+  if (st.v16n) QK_HIP(hipMemcpyAsync(fresh.v16n, st.v16n, used * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (st.rows32) QK_HIP(hipMemcpyAsync(fresh.rows32, st.rows32, used * st.dp * sizeof(float), hipMemcpyDeviceToDevice, s));
+  QK_HIP(hipMemcpyAsync(fresh.ids, st.ids, used * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  QK_HIP(hipStreamSynchronize(s));
+  for (void* p : {(void*)st.v32, (void*)st.v16, (void*)st.v16n, (void*)st.rows32, (void*)st.ids}) idx->mem.release(p);
+  st.v32 = fresh.v32;
+  st.v16 = fresh.v16;
+  st.v16n = fresh.v16n;
+  st.rows32 = fresh.rows32;
+  st.ids = fresh.ids;
+  st.tiles = tiles;
+  st.tile_part.resize(tiles, -1);
+}
+
+// Copy partition p's filled tiles to `tiles` fresh tiles at the end of the
+// arena (which must have room) and give it capacity `cap`.
+void relocate(Store& st, int64_t p, int32_t cap, hipStream_t s) {
+  const int64_t from = st.off[p], to = st.used_tiles;
+  const int64_t ntiles = (st.size[p] + qk::TILE - 1) / qk::TILE;
+  const size_t n = (size_t)ntiles * qk::TILE;
+  const size_t a = (size_t)from * qk::TILE, b = (size_t)to * qk::TILE;
+  if (n > 0) {
+    QK_HIP(hipMemcpyAsync(st.v32 + b * st.dp, st.v32 + a * st.dp, n * st.dp * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (st.v16)
+      QK_HIP(hipMemcpyAsync(st.v16 + b * st.dp16, st.v16 + a * st.dp16, n * st.dp16 * sizeof(uint16_t),
+                            hipMemcpyDeviceToDevice, s));
+    if (st.v16n) QK_HIP(hipMemcpyAsync(st.v16n + b, st.v16n + a, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (st.rows32)
+      QK_HIP(hipMemcpyAsync(st.rows32 + b * st.dp, st.rows32 + a * st.dp, n * st.dp * sizeof(float),
+                            hipMemcpyDeviceToDevice, s));
+    QK_HIP(hipMemcpyAsync(st.ids + b, st.ids + a, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    // the old slots no longer hold the partition's vectors
+    QK_HIP(hipMemsetAsync(st.ids + a, 0xff, (size_t)st.cap[p] * sizeof(int64_t), s));
+  }
+  for (int64_t t = 0; t < st.cap[p] / qk::TILE; ++t) st.tile_part[from + t] = -1;
+  for (int64_t t = 0; t < cap / qk::TILE; ++t) st.tile_part[to + t] = (int32_t)p;
+  st.off[p] = to;
+  st.cap[p] = cap;
+  st.used_tiles += cap / qk::TILE;
+}
+
+// ---------------------------------------------------------------- id map
+
+void map_rebuild(quake_index* idx, int64_t expect, hipStream_t s) {
+  qk::IdMap& m = idx->idmap;
+  uint64_t cap = 1024;
+  while (cap < (uint64_t)std::max<int64_t>(expect, 1) * 4) cap <<= 1;
+  int64_t* keys = idx->mem.alloc<int64_t>(cap);
+  int64_t* vals;
+  try {
+    vals = idx->mem.alloc<int64_t>(cap);
+  } catch (...) {
+    idx->mem.release(keys);
+    throw;
+  }
+  idx->mem.release(m.keys);
+  idx->mem.release(m.vals);
+  m.keys = keys;
+  m.vals = vals;
+  m.mask = cap - 1;
+  QK_HIP(hipMemsetAsync(m.keys, 0xff, cap * sizeof(int64_t), s));
+  qk::launch_map_insert_store(m, idx->L0.ids, idx->L0.used_tiles * qk::TILE, s);
+  m.used = idx->L0.live;
+}
+
+int64_t count_missing(quake_index* idx, const int64_t* ids, int64_t n, int64_t* slots, hipStream_t s) {
+  Tmp<int64_t> miss(idx->mem, 1);
+  QK_HIP(hipMemsetAsync(miss.p, 0, sizeof(int64_t), s));
+  qk::launch_map_find(idx->idmap, ids, n, slots, miss.p, s);
+  int64_t h = 0;
+  QK_HIP(hipMemcpyAsync(&h, miss.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  return h;
+}
+
+// ---------------------------------------------------------------- searches
+
 int64_t max_chunks(const Store& st, int chunk_tiles) {
   int64_t mx = 1;
   for (int32_t sz : st.size) {
@@ -282,12 +392,14 @@ int64_t max_chunks(const Store& st, int chunk_tiles) {
   return mx;
 }
 
-struct Resolved {
-  int k, kk, nprobe, aps, M, w0, wmax, batched, dtype16;
-  double tau_r, f_M, tau_rho;
+// One search over one store, resolved.
+struct Job {
+  int k = 0, kk = 0, aps = 0, M = 0, w0 = 0, wmax = 0, batched = 0, dtype16 = QUAKE_F32;
+  double tau_r = 0, f_M = 0, tau_rho = 0.01;
+  bool given = false;  // candidate rows already in ws.cand0 / ws.mq0 (level 0 of two levels)
 };
 
-Resolved resolve(const quake_index* idx, const Store& st, const quake_search_params* p) {
+Job resolve(const quake_index* idx, const Store& st, const quake_search_params* p) {
   QK_CHECK(p, QUAKE_E_INVALID, "params is NULL");
   QK_CHECK(p->k >= 1 && p->k <= qk::KMAX, QUAKE_E_INVALID, "k must be in [1, 256]");
   const bool has_np = p->nprobe > 0;
@@ -298,7 +410,10 @@ Resolved resolve(const quake_index* idx, const Store& st, const quake_search_par
            "unknown scan_mode");
   QK_CHECK(p->scan_dtype == QUAKE_F32 || (p->scan_dtype == idx->storage && st.v16), QUAKE_E_INVALID,
            "scan_dtype needs the matching reduced-precision copy in the index");
-  Resolved r{};
+  QK_CHECK(p->f_M >= 0 && p->tau_rho >= 0 && p->upper_f_M >= 0 && p->upper_recall_target >= 0 &&
+               p->upper_recall_target <= 1.0 && p->window >= 0,
+           QUAKE_E_INVALID, "negative or out-of-range search parameter");
+  Job r;
   r.k = p->k;
   r.batched = p->scan_mode == QUAKE_SCAN_BATCHED ? 1 : 0;
   r.dtype16 = p->scan_dtype;
@@ -331,45 +446,55 @@ Resolved resolve(const quake_index* idx, const Store& st, const quake_search_par
   return r;
 }
 
-void ensure_workspace(quake_index* idx, int64_t nq, int64_t nc, int64_t M, int64_t kk, int64_t items,
-                      int64_t pairs = 0, bool need16 = false) {
+void ensure_queries(quake_index* idx, int64_t nq) {
   qk::Workspace& w = idx->ws;
   auto& mem = idx->mem;
   const int dp = idx->dp;
-  if (nq > w.nq_cap || !w.q) {
-    const int64_t n = std::max<int64_t>(nq, 1);
-    for (void* p : {(void*)w.q, (void*)w.qn2, (void*)w.st_m, (void*)w.st_w, (void*)w.st_weff, (void*)w.st_done,
-                    (void*)w.st_item,
-                    (void*)w.st_demand, (void*)w.st_vecs, (void*)w.st_pair, (void*)w.st_rho, (void*)w.st_p0,
-                    (void*)w.st_V, (void*)w.st_vsum, (void*)w.st_r, (void*)w.q16, (void*)w.qn2f})
-      mem.release(p);
-    w.q = mem.alloc<float>((size_t)n * dp);
-    w.qn2 = mem.alloc<double>(n);
-    w.st_m = mem.alloc<int32_t>(n);
-    w.st_w = mem.alloc<int32_t>(n);
-    w.st_weff = mem.alloc<int32_t>(n);
-    w.st_done = mem.alloc<int32_t>(n);
-    w.st_item = mem.alloc<int64_t>(n);
-    w.st_demand = mem.alloc<int64_t>(n);
-    w.st_vecs = mem.alloc<int64_t>(n);
-    w.st_pair = mem.alloc<int64_t>(n);
-    w.q16 = nullptr;
-    w.qn2f = mem.alloc<float>(n);
-    w.st_rho = mem.alloc<double>(n);
-    w.st_p0 = mem.alloc<double>(n);
-    w.st_V = mem.alloc<double>(n);
-    w.st_vsum = mem.alloc<double>(n);
-    w.st_r = mem.alloc<double>(n);
-    w.nq_cap = n;
-    w.scores_cap = w.cand_cap = w.kk_cap = 0;  // dependent sizes re-grow below
-    mem.release(w.scores); w.scores = nullptr;
-    mem.release(w.sel); w.sel = nullptr;
-    mem.release(w.cand); w.cand = nullptr;
-    mem.release(w.h); w.h = nullptr;
-    mem.release(w.rk); w.rk = nullptr;
-    mem.release(w.ri); w.ri = nullptr;
-  }
-  grow(mem, w.scores, w.scores_cap, w.nq_cap * nc);
+  if (nq <= w.nq_cap && w.q) return;
+  const int64_t n = std::max<int64_t>(nq, 1);
+  for (void* p : {(void*)w.q, (void*)w.qn2, (void*)w.st_m, (void*)w.st_w, (void*)w.st_weff, (void*)w.st_done,
+                  (void*)w.st_item, (void*)w.st_demand, (void*)w.st_vecs, (void*)w.st_pair, (void*)w.st_rho,
+                  (void*)w.st_p0, (void*)w.st_V, (void*)w.st_vsum, (void*)w.st_r, (void*)w.q16, (void*)w.qn2f,
+                  (void*)w.mq, (void*)w.mq0})
+    mem.release(p);
+  w.q = mem.alloc<float>((size_t)n * dp);
+  w.qn2 = mem.alloc<double>(n);
+  w.st_m = mem.alloc<int32_t>(n);
+  w.st_w = mem.alloc<int32_t>(n);
+  w.st_weff = mem.alloc<int32_t>(n);
+  w.st_done = mem.alloc<int32_t>(n);
+  w.st_item = mem.alloc<int64_t>(n);
+  w.st_demand = mem.alloc<int64_t>(n);
+  w.st_vecs = mem.alloc<int64_t>(n);
+  w.st_pair = mem.alloc<int64_t>(n);
+  w.q16 = nullptr;
+  w.q16_dim = 0;
+  w.qn2f = mem.alloc<float>(n);
+  w.mq = mem.alloc<int32_t>(n);
+  w.mq0 = mem.alloc<int32_t>(n);
+  w.st_rho = mem.alloc<double>(n);
+  w.st_p0 = mem.alloc<double>(n);
+  w.st_V = mem.alloc<double>(n);
+  w.st_vsum = mem.alloc<double>(n);
+  w.st_r = mem.alloc<double>(n);
+  w.nq_cap = n;
+  // sizes that scale with nq re-grow on demand
+  w.scores_cap = w.cand_cap = w.kk_cap = w.cand0_cap = 0;
+  for (void* p : {(void*)w.scores, (void*)w.sel, (void*)w.cand, (void*)w.h, (void*)w.rk, (void*)w.ri,
+                  (void*)w.cand0})
+    mem.release(p);
+  w.scores = nullptr;
+  w.sel = w.cand = w.cand0 = nullptr;
+  w.h = nullptr;
+  w.rk = nullptr;
+  w.ri = nullptr;
+}
+
+void ensure_workspace(quake_index* idx, int64_t nc, int64_t M, int64_t kk, int64_t items, int64_t pairs,
+                      int dp16, bool scores = true) {
+  qk::Workspace& w = idx->ws;
+  auto& mem = idx->mem;
+  if (scores) grow(mem, w.scores, w.scores_cap, w.nq_cap * nc);
   if (M * w.nq_cap > w.cand_cap || !w.sel) {
     mem.release(w.sel); mem.release(w.cand); mem.release(w.h);
     w.cand_cap = w.nq_cap * M;
@@ -385,6 +510,7 @@ void ensure_workspace(quake_index* idx, int64_t nq, int64_t nc, int64_t M, int64
   }
   if (items > w.items_cap || kk > w.k_cap || !w.items) {
     mem.release(w.items); mem.release(w.pk); mem.release(w.pi);
+    w.items = nullptr; w.pk = nullptr; w.pi = nullptr;
     w.items_cap = std::max(items, w.items_cap);
     w.k_cap = std::max<int64_t>(kk, w.k_cap);
     w.items = mem.alloc<int4>(w.items_cap);
@@ -395,7 +521,11 @@ void ensure_workspace(quake_index* idx, int64_t nq, int64_t nc, int64_t M, int64
     w.total = mem.alloc<int64_t>(8);
     QK_HIP(hipHostMalloc((void**)&w.h_total, 8 * sizeof(int64_t), hipHostMallocDefault));
   }
-  if (need16 && !w.q16) w.q16 = mem.alloc<uint16_t>((size_t)w.nq_cap * idx->L0.dp16);
+  if (dp16 > 0 && (!w.q16 || dp16 > w.q16_dim)) {
+    mem.release(w.q16);
+    w.q16 = mem.alloc<uint16_t>((size_t)w.nq_cap * dp16);
+    w.q16_dim = dp16;
+  }
   if (pairs > w.pairs_cap || !w.pair_q) {
     for (void* p : {(void*)w.pair_q, (void*)w.pair_p, (void*)w.pair_pos, (void*)w.pair_base, (void*)w.sorted})
       mem.release(p);
@@ -416,23 +546,170 @@ void ensure_workspace(quake_index* idx, int64_t nq, int64_t nc, int64_t M, int64
   }
 }
 
-// Candidate partitions of every query: the nearest M centroids and, for
-// adaptive scanning, their order by ascending bisector distance.
-void candidates(quake_index* idx, const Store& st, int64_t nq, int M, bool aps, hipStream_t s) {
-  qk::Workspace& w = idx->ws;
-  {
-    qk::ProfileScope ps(idx->prof, QUAKE_PROF_CENTROIDS, s);
-    qk::launch_scores(w.q, nq, st.centroids, st.nlist, idx->dp, idx->metric, w.scores, s);
+// Point the workspace's query rows at a sub-range for the duration of a scope.
+struct QueryWindow {
+  qk::Workspace& w;
+  float* q;
+  double* qn2;
+  QueryWindow(qk::Workspace& w_, int64_t first, int dp) : w(w_), q(w_.q), qn2(w_.qn2) {
+    w.q += first * dp;
+    w.qn2 += first;
   }
-  idx->prof.add(QUAKE_PROF_CENTROIDS, (double)st.nlist * idx->dp * 4.0 + (double)nq * idx->dp * 4.0 +
-                                           (double)nq * st.nlist * 4.0,
-                (double)nq * st.nlist * idx->dp * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
-  qk::ProfileScope ps(idx->prof, QUAKE_PROF_SELECT, s);
-  if (aps) {
-    qk::launch_select(w.scores, nq, st.nlist, M, idx->metric, w.sel, s);
-    qk::launch_geometry(w.q, st.centroids, nq, idx->dp, M, idx->metric, w.sel, w.cand, w.h, s);
+  ~QueryWindow() {
+    w.q = q;
+    w.qn2 = qn2;
+  }
+};
+
+// Run one resolved search over `st` for the nq queries in ws.q / ws.qn2.
+// Leaves the results in ws.rk / ws.ri ([nq][kk]) and the per-query state in
+// ws.st_*; writes the outputs when out_ids is given.
+void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, int64_t* out_ids, float* out_dist,
+                int32_t* out_nscanned, double* out_recall, hipStream_t s) {
+  int chunk_tiles = idx->tune.chunk_tiles > 0 ? idx->tune.chunk_tiles : 16;
+  // long result lists are scanned by sorting whole items in LDS
+  if (job.kk > qk::KMAX) chunk_tiles = std::min(chunk_tiles, qk::SORTED_ITEM_MAX / qk::TILE);
+  const int64_t mc = max_chunks(st, chunk_tiles);
+  // the buffer must hold one full window of the largest partitions (progress)
+  const int64_t floor_items = (int64_t)job.wmax * mc + 1;
+  const int64_t items =
+      std::max<int64_t>(idx->tune.max_items > 0 ? idx->tune.max_items : nq * std::max(job.w0, 4) * 2, floor_items);
+  ensure_workspace(idx, st.nlist, job.M, job.kk, items, job.batched ? nq * (int64_t)job.wmax : 0,
+                   job.batched ? st.dp16 : 0, !job.given);
+  qk::Workspace& w = idx->ws;
+  QK_HIP(hipMemsetAsync(w.total, 0, 8 * sizeof(int64_t), s));
+  if (job.given) {
+    QK_HIP(hipMemcpyAsync(w.mq, w.mq0, nq * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    qk::ProfileScope ps(idx->prof, QUAKE_PROF_SELECT, s);
+    qk::launch_geometry(w.q, st.centroids, nq, idx->dp, job.M, w.mq, idx->metric, w.cand0, w.cand, w.h, s);
   } else {
-    qk::launch_select(w.scores, nq, st.nlist, M, idx->metric, w.cand, s);
+    qk::launch_fill_i32(w.mq, nq, job.M, s);
+    {
+      qk::ProfileScope ps(idx->prof, QUAKE_PROF_CENTROIDS, s);
+      qk::launch_scores(w.q, nq, st.centroids, st.nlist, idx->dp, idx->metric, w.scores, s);
+    }
+    idx->prof.add(QUAKE_PROF_CENTROIDS, ((double)st.nlist + nq) * idx->dp * 4.0 + (double)nq * st.nlist * 4.0,
+                  (double)nq * st.nlist * idx->dp * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
+    qk::ProfileScope ps(idx->prof, QUAKE_PROF_SELECT, s);
+    if (job.aps) {
+      qk::launch_select(w.scores, nq, st.nlist, job.M, idx->metric, w.sel, s);
+      qk::launch_geometry(w.q, st.centroids, nq, idx->dp, job.M, w.mq, idx->metric, w.sel, w.cand, w.h, s);
+    } else {
+      qk::launch_select(w.scores, nq, st.nlist, job.M, idx->metric, w.cand, s);
+    }
+  }
+  if (job.batched) qk::launch_queries16(w, nq, idx->dp, st.dp16, job.dtype16, s);
+  qk::RoundArgs a{};
+  a.nq = nq;
+  a.M = job.M;
+  a.k = job.k;
+  a.kk = job.kk;
+  a.aps = job.aps;
+  a.chunk_tiles = chunk_tiles;
+  a.wmax = job.wmax;
+  a.metric = idx->metric;
+  a.dim = idx->d;
+  a.tau_r = job.tau_r;
+  a.tau_rho = job.tau_rho;
+  // a smaller requested cap than the buffer already allocated still applies
+  a.items_cap = std::min<int64_t>(w.items_cap, items);
+  qk::launch_round_init(w, a, job.w0, s);
+  if (job.batched && idx->cu_count == 0) {
+    int dev = 0;
+    QK_HIP(hipGetDevice(&dev));
+    QK_HIP(hipDeviceGetAttribute(&idx->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  // Every round commits at least one partition of the first unfinished
+  // query, so the loop ends within nq * M rounds.
+  const int64_t max_rounds = nq * (int64_t)job.M + 2;
+  for (int64_t round = 0;; ++round) {
+    QK_CHECK(round <= max_rounds, QUAKE_E_DEVICE, "search rounds did not converge");
+    {
+      qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
+      qk::launch_demand(w, st, a, s);
+    }
+    QK_HIP(hipMemcpyAsync(w.h_total, w.total, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+    const int64_t total = w.h_total[0];
+    const int64_t nvec = w.h_total[1];
+    const int64_t npairs = w.h_total[2];
+    if (total == 0) break;
+    if (job.batched) {
+      {
+        qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
+        qk::launch_group(w, st, a, npairs, s);
+      }
+      qk::ProfileScope ps(idx->prof, QUAKE_PROF_SCAN, s);
+      qk::launch_scan_mfma(w, st, a, job.dtype16, std::max(idx->cu_count, 8) * 2, s);
+    } else {
+      {
+        qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
+        qk::launch_emit(w, st, a, s);
+      }
+      {
+        qk::ProfileScope ps(idx->prof, QUAKE_PROF_SCAN, s);
+        qk::launch_scan_f32(w, st, a, total, s);
+      }
+      idx->prof.add(QUAKE_PROF_SCAN, (double)nvec * idx->d * sizeof(float),
+                    (double)nvec * idx->d * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
+    }
+    {
+      qk::ProfileScope ps(idx->prof, QUAKE_PROF_COMMIT, s);
+      qk::launch_commit(w, st, a, idx->cap_table, s);
+    }
+  }
+  if (job.batched) {
+    {
+      qk::ProfileScope ps(idx->prof, QUAKE_PROF_RERANK, s);
+      qk::launch_rerank(w, st, a, s);
+    }
+    idx->prof.add(QUAKE_PROF_RERANK, (double)nq * job.kk * idx->d * sizeof(float), (double)nq * job.kk * idx->d * 2.0);
+  }
+  if (out_ids) {
+    qk::ProfileScope ps(idx->prof, QUAKE_PROF_COMMIT, s);
+    qk::launch_finalize(w, a, out_ids, out_dist, out_nscanned, out_recall, s);
+  }
+  QK_HIP(hipGetLastError());
+  if (job.batched && idx->prof.on)
+    QK_HIP(hipMemcpyAsync(w.h_total + 4, w.total + 4, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  if (job.batched)
+    idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[4] * idx->d * 2.0, (double)w.h_total[5] * idx->d * 2.0);
+  idx->prof.collect();
+}
+
+// Level-1 search of a two-level index for queries [0, nq) already in ws.q:
+// the M0 nearest leaf centroids it finds become each query's level-0
+// candidate row in ws.cand0 (count in ws.mq0).
+void upper_level(quake_index* idx, int64_t nq, int M0, const quake_search_params* p, hipStream_t s) {
+  const Store& L1 = idx->L1;
+  Job up;
+  up.k = up.kk = M0;
+  up.aps = 1;
+  up.tau_r = p->upper_recall_target > 0 ? p->upper_recall_target : 0.99;
+  up.f_M = p->upper_f_M > 0 ? p->upper_f_M : 0.25;
+  up.tau_rho = p->tau_rho > 0 ? p->tau_rho : 0.01;
+  up.M = candidate_count(up.f_M, L1.nlist);
+  up.w0 = up.M;  // the upper level is small: scan its candidates in one round
+  up.wmax = up.M;
+  qk::Workspace& w = idx->ws;
+  if ((int64_t)M0 * w.nq_cap > w.cand0_cap || !w.cand0) {
+    idx->mem.release(w.cand0);
+    w.cand0 = nullptr;
+    w.cand0_cap = (int64_t)M0 * w.nq_cap;
+    w.cand0 = idx->mem.alloc<int32_t>(w.cand0_cap);
+  }
+  // bound the upper level's partial lists (M0 entries each) by running it on
+  // slices of the batch
+  const int chunk_tiles = std::min(idx->tune.chunk_tiles > 0 ? idx->tune.chunk_tiles : 16,
+                                   qk::SORTED_ITEM_MAX / qk::TILE);
+  const int64_t per_query = (int64_t)up.M * max_chunks(L1, chunk_tiles);
+  const int64_t slice = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(1 << 17) / std::max<int64_t>(per_query, 1)));
+  for (int64_t q0 = 0; q0 < nq; q0 += slice) {
+    const int64_t n = std::min(slice, nq - q0);
+    QueryWindow win(w, q0, idx->dp);
+    run_search(idx, L1, up, n, nullptr, nullptr, nullptr, nullptr, s);
+    qk::launch_level1_to_candidates(n, M0, up.kk, w.ri, w.cand0 + q0 * M0, w.mq0 + q0, s);
   }
 }
 
@@ -511,6 +788,7 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const 
     qk::launch_assign(xpad, n, dp, L0.centroids, L0.nlist, idx->metric, assign.p, s);
     build_store(idx.get(), L0, x, d, ids, n, assign.p, params->capacity_slack, params->storage_dtype, s);
   }
+  map_rebuild(idx.get(), n, s);
 
   if (idx->n_levels == 2) {
     Store& L1 = idx->L1;
@@ -519,9 +797,9 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const 
     L1.nlist = params->nlist_top;
     L1.centroids = idx->mem.alloc<float>((size_t)L1.nlist * dp);
     kmeans(idx->mem, L0.centroids, L0.nlist, dp, L1.nlist, std::max(params->kmeans_iters, 1),
-           params->seed ^ 0x9e3779b97f4a7c15ull, QUAKE_L2, L1.centroids, s);
+           params->seed ^ 0x9e3779b97f4a7c15ull, idx->metric, L1.centroids, s);
     idx->top_of = idx->mem.alloc<int32_t>(L0.nlist);
-    qk::launch_assign(L0.centroids, L0.nlist, dp, L1.centroids, L1.nlist, QUAKE_L2, idx->top_of, s);
+    qk::launch_assign(L0.centroids, L0.nlist, dp, L1.centroids, L1.nlist, idx->metric, idx->top_of, s);
     build_store(idx.get(), L1, L0.centroids, dp, nullptr, L0.nlist, idx->top_of, 0.0, QUAKE_F32, s);
   }
 
@@ -540,103 +818,22 @@ int quake_search(quake_index* idx, const float* q, int64_t nq, const quake_searc
   API_BEGIN
   check_index(idx);
   QK_CHECK(nq >= 0, QUAKE_E_INVALID, "nq must be >= 0");
-  QK_CHECK(idx->n_levels == 1, QUAKE_E_STATE, "two-level search is not available in this build");
-  const Store& st = idx->L0;
-  const Resolved r = resolve(idx, st, params);
+  const Store& L0 = idx->L0;
+  Job job = resolve(idx, L0, params);
   if (nq == 0) return QUAKE_OK;
   QK_CHECK(q && out_ids && out_dist, QUAKE_E_INVALID, "q, out_ids and out_dist are required");
   hipStream_t s = as_stream(stream);
-  const int chunk_tiles = idx->tune.chunk_tiles > 0 ? idx->tune.chunk_tiles : 16;
-  const int64_t kk = r.kk;
-  const int64_t mc = max_chunks(st, chunk_tiles);
-  // the buffer must hold one full window of the largest partitions (progress)
-  const int64_t floor_items = (int64_t)r.wmax * mc + 1;
-  const int64_t items = std::max<int64_t>(
-      idx->tune.max_items > 0 ? idx->tune.max_items : nq * std::max(r.w0, 4) * 2, floor_items);
-  ensure_workspace(idx, nq, st.nlist, r.M, kk, items, r.batched ? nq * (int64_t)r.wmax : 0, r.batched != 0);
-  qk::Workspace& w = idx->ws;
-  QK_HIP(hipMemsetAsync(w.total, 0, 8 * sizeof(int64_t), s));
-  qk::launch_pad_rows(q, nq, idx->d, idx->dp, w.q, w.qn2, s);
-  candidates(idx, st, nq, r.M, r.aps, s);
-  if (r.batched) qk::launch_queries16(w, nq, idx->dp, st.dp16, r.dtype16, s);
-  // a smaller requested cap than the buffer already allocated still applies
-  const int64_t items_cap = std::min<int64_t>(w.items_cap, items);
-  qk::RoundArgs a{};
-  a.nq = nq;
-  a.M = r.M;
-  a.k = r.k;
-  a.kk = r.kk;
-  a.aps = r.aps;
-  a.chunk_tiles = chunk_tiles;
-  a.wmax = r.wmax;
-  a.metric = idx->metric;
-  a.dim = idx->d;
-  a.tau_r = r.tau_r;
-  a.tau_rho = r.tau_rho;
-  a.items_cap = items_cap;
-  qk::launch_round_init(w, a, r.w0, s);
-  if (r.batched && idx->cu_count == 0) {
-    int dev = 0;
-    QK_HIP(hipGetDevice(&dev));
-    QK_HIP(hipDeviceGetAttribute(&idx->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+  ensure_queries(idx, nq);
+  qk::launch_pad_rows(q, nq, idx->d, idx->dp, idx->ws.q, idx->ws.qn2, s);
+  if (idx->n_levels == 2) {
+    // level 1 picks the level-0 candidates: M0 = ceil(f_M * N0) nearest leaf
+    // centroids it finds; nprobe mode takes the nprobe nearest it finds
+    const int M0 = job.M;
+    QK_CHECK(M0 <= qk::KMAX_LARGE, QUAKE_E_INVALID, "the upper level returns at most 1024 candidates");
+    upper_level(idx, nq, M0, params, s);
+    job.given = true;
   }
-  // Every round commits at least one partition of the first unfinished
-  // query, so the loop ends within nq * M rounds.
-  const int64_t max_rounds = nq * (int64_t)r.M + 2;
-  for (int64_t round = 0;; ++round) {
-    QK_CHECK(round <= max_rounds, QUAKE_E_DEVICE, "search rounds did not converge");
-    {
-      qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
-      qk::launch_demand(w, st, a, s);
-    }
-    QK_HIP(hipMemcpyAsync(w.h_total, w.total, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    QK_HIP(hipStreamSynchronize(s));
-    const int64_t total = w.h_total[0];
-    const int64_t nvec = w.h_total[1];
-    const int64_t npairs = w.h_total[2];
-    if (total == 0) break;
-    if (r.batched) {
-      {
-        qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
-        qk::launch_group(w, st, a, npairs, s);
-      }
-      qk::ProfileScope ps(idx->prof, QUAKE_PROF_SCAN, s);
-      qk::launch_scan_mfma(w, st, a, r.dtype16, std::max(idx->cu_count, 8) * 2, s);
-    } else {
-      {
-        qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
-        qk::launch_emit(w, st, a, s);
-      }
-      {
-        qk::ProfileScope ps(idx->prof, QUAKE_PROF_SCAN, s);
-        qk::launch_scan_f32(w, st, a, total, s);
-      }
-      idx->prof.add(QUAKE_PROF_SCAN, (double)nvec * idx->d * sizeof(float),
-                    (double)nvec * idx->d * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
-    }
-    {
-      qk::ProfileScope ps(idx->prof, QUAKE_PROF_COMMIT, s);
-      qk::launch_commit(w, st, a, idx->cap_table, s);
-    }
-  }
-  if (r.batched) {
-    {
-      qk::ProfileScope ps(idx->prof, QUAKE_PROF_RERANK, s);
-      qk::launch_rerank(w, st, a, s);
-    }
-    idx->prof.add(QUAKE_PROF_RERANK, (double)nq * kk * idx->d * sizeof(float), (double)nq * kk * idx->d * 2.0);
-  }
-  {
-    qk::ProfileScope ps(idx->prof, QUAKE_PROF_COMMIT, s);
-    qk::launch_finalize(w, a, out_ids, out_dist, out_nscanned, out_recall, s);
-  }
-  QK_HIP(hipGetLastError());
-  if (r.batched && idx->prof.on)
-    QK_HIP(hipMemcpyAsync(w.h_total + 4, w.total + 4, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  QK_HIP(hipStreamSynchronize(s));
-  if (r.batched)
-    idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[4] * idx->d * 2.0, (double)w.h_total[5] * idx->d * 2.0);
-  idx->prof.collect();
+  run_search(idx, L0, job, nq, out_ids, out_dist, out_nscanned, out_recall, s);
   API_END
 }
 
@@ -663,6 +860,7 @@ int quake_candidates(quake_index* idx, const float* q, int64_t nq, double f_M, i
                      int32_t* out_M, void* stream) {
   API_BEGIN
   check_index(idx);
+  QK_CHECK(idx->n_levels == 1, QUAKE_E_STATE, "candidate export is for single-level indexes");
   QK_CHECK(nq >= 0 && (nq == 0 || (q && order && h)), QUAKE_E_INVALID, "bad arguments");
   const Store& st = idx->L0;
   const int M = candidate_count(f_M > 0 ? f_M : 0.05, st.nlist);
@@ -670,10 +868,14 @@ int quake_candidates(quake_index* idx, const float* q, int64_t nq, double f_M, i
   if (out_M) *out_M = M;
   if (nq == 0) return QUAKE_OK;
   hipStream_t s = as_stream(stream);
-  ensure_workspace(idx, nq, st.nlist, M, 1, 1);
+  ensure_queries(idx, nq);
+  ensure_workspace(idx, st.nlist, M, 1, 1, 0, 0);
   qk::Workspace& w = idx->ws;
   qk::launch_pad_rows(q, nq, idx->d, idx->dp, w.q, w.qn2, s);
-  candidates(idx, st, nq, M, true, s);
+  qk::launch_fill_i32(w.mq, nq, M, s);
+  qk::launch_scores(w.q, nq, st.centroids, st.nlist, idx->dp, idx->metric, w.scores, s);
+  qk::launch_select(w.scores, nq, st.nlist, M, idx->metric, w.sel, s);
+  qk::launch_geometry(w.q, st.centroids, nq, idx->dp, M, w.mq, idx->metric, w.sel, w.cand, w.h, s);
   QK_HIP(hipMemcpyAsync(order, w.cand, (size_t)nq * M * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   QK_HIP(hipMemcpyAsync(h, w.h, (size_t)nq * M * sizeof(float), hipMemcpyDeviceToDevice, s));
   QK_HIP(hipStreamSynchronize(s));
@@ -683,16 +885,162 @@ int quake_candidates(quake_index* idx, const float* q, int64_t nq, double f_M, i
 int quake_insert(quake_index* idx, const float* x, const int64_t* ids, int64_t n, void* stream) {
   API_BEGIN
   check_index(idx);
-  (void)x; (void)ids; (void)n; (void)stream;
-  throw Error{QUAKE_E_INVALID, "insert is not available in this build"};
+  QK_CHECK(n >= 0, QUAKE_E_INVALID, "n must be >= 0");
+  if (n == 0) return QUAKE_OK;
+  QK_CHECK(x && ids, QUAKE_E_INVALID, "x and ids are required");
+  hipStream_t s = as_stream(stream);
+  Store& st = idx->L0;
+  // the batch is checked whole before anything changes
+  std::vector<int64_t> h_ids(n);
+  QK_HIP(hipMemcpyAsync(h_ids.data(), ids, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  QK_CHECK(std::all_of(h_ids.begin(), h_ids.end(), [](int64_t v) { return v >= 0; }), QUAKE_E_INVALID,
+           "ids must be >= 0");
+  {
+    std::vector<int64_t> sorted(h_ids);
+    std::sort(sorted.begin(), sorted.end());
+    QK_CHECK(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(), QUAKE_E_DUPLICATE,
+             "the batch repeats an id");
+  }
+  QK_CHECK(count_missing(idx, ids, n, nullptr, s) == n, QUAKE_E_DUPLICATE, "the batch names an id already present");
+  const int dp = idx->dp;
+  std::unique_ptr<Tmp<float>> xpad_buf;
+  const float* xpad = x;
+  if (dp != idx->d) {
+    xpad_buf.reset(new Tmp<float>(idx->mem, (size_t)n * dp));
+    qk::launch_pad_rows(x, n, idx->d, dp, xpad_buf->p, nullptr, s);
+    xpad = xpad_buf->p;
+  }
+  // route: nearest leaf, top-down through the upper level when there is one
+  std::vector<int32_t> part(n);
+  if (idx->n_levels == 1) {
+    Tmp<int32_t> assign(idx->mem, n);
+    qk::launch_assign(xpad, n, dp, st.centroids, st.nlist, idx->metric, assign.p, s);
+    QK_HIP(hipMemcpyAsync(part.data(), assign.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+  } else {
+    ensure_queries(idx, n);
+    qk::launch_pad_rows(xpad, n, dp, dp, idx->ws.q, idx->ws.qn2, s);
+    Job route;
+    route.k = route.kk = 1;
+    route.M = route.w0 = route.wmax = 1;  // the nearest top partition, its nearest leaf
+    run_search(idx, idx->L1, route, n, nullptr, nullptr, nullptr, nullptr, s);
+    std::vector<int64_t> leaf(n);
+    QK_HIP(hipMemcpyAsync(leaf.data(), idx->ws.ri, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < n; ++i) {
+      QK_CHECK(leaf[i] >= 0, QUAKE_E_DEVICE, "top-down routing found no leaf");
+      part[i] = (int32_t)leaf[i];
+    }
+  }
+  // room: partitions that overflow move to fresh tiles with 1.5x the need
+  std::vector<int64_t> cnt(st.nlist, 0);
+  for (int64_t i = 0; i < n; ++i) cnt[part[i]]++;
+  std::vector<std::pair<int64_t, int32_t>> moves;
+  int64_t extra = 0;
+  for (int64_t p = 0; p < st.nlist; ++p) {
+    if (cnt[p] == 0 || st.size[p] + cnt[p] <= st.cap[p]) continue;
+    const int64_t want = round_up((int64_t)std::ceil((st.size[p] + cnt[p]) * 1.5), qk::TILE);
+    QK_CHECK(want <= INT32_MAX, QUAKE_E_INVALID, "partition too large");
+    moves.push_back({p, (int32_t)want});
+    extra += want / qk::TILE;
+  }
+  grow_arena(idx, st, st.used_tiles + extra, s);
+  for (auto& mv : moves) relocate(st, mv.first, mv.second, s);
+  std::vector<int64_t> slot(n);
+  std::vector<int64_t> fill(st.nlist, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t p = part[i];
+    slot[i] = st.off[p] * qk::TILE + st.size[p] + fill[p]++;
+  }
+  {
+    Tmp<int64_t> d_slot(idx->mem, n);
+    QK_HIP(hipMemcpyAsync(d_slot.p, slot.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    qk::launch_scatter(x, n, idx->d, dp, st.dp16, ids, d_slot.p, st.v32, st.v16, st.v16 ? idx->storage : QUAKE_F32,
+                       st.rows32, st.ids, s);
+    qk::launch_norm16_slots(st, d_slot.p, n, idx->storage, s);
+    for (int64_t p = 0; p < st.nlist; ++p) st.size[p] += (int32_t)cnt[p];
+    upload_table(st, s);
+    st.live += n;
+    if (!moves.empty() || (idx->idmap.used + n) * 2 > (int64_t)idx->idmap.mask + 1) {
+      map_rebuild(idx, st.live, s);
+    } else {
+      qk::launch_map_insert(idx->idmap, ids, d_slot.p, n, s);
+      idx->idmap.used += n;
+    }
+    QK_HIP(hipStreamSynchronize(s));
+  }
   API_END
 }
 
 int quake_delete(quake_index* idx, const int64_t* ids, int64_t n, void* stream) {
   API_BEGIN
   check_index(idx);
-  (void)ids; (void)n; (void)stream;
-  throw Error{QUAKE_E_INVALID, "delete is not available in this build"};
+  QK_CHECK(n >= 0, QUAKE_E_INVALID, "n must be >= 0");
+  if (n == 0) return QUAKE_OK;
+  QK_CHECK(ids, QUAKE_E_INVALID, "ids are required");
+  hipStream_t s = as_stream(stream);
+  Store& st = idx->L0;
+  std::vector<int64_t> h_ids(n);
+  QK_HIP(hipMemcpyAsync(h_ids.data(), ids, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  {
+    std::vector<int64_t> sorted(h_ids);
+    std::sort(sorted.begin(), sorted.end());
+    QK_CHECK(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(), QUAKE_E_NOTFOUND,
+             "the batch repeats an id");
+  }
+  Tmp<int64_t> slots(idx->mem, n);
+  QK_CHECK(count_missing(idx, ids, n, slots.p, s) == 0, QUAKE_E_NOTFOUND, "the batch names an id that is absent");
+  qk::launch_mark_deleted(st, slots.p, n, s);
+  qk::launch_map_erase(idx->idmap, ids, n, s);
+  std::vector<int64_t> h_slots(n);
+  QK_HIP(hipMemcpyAsync(h_slots.data(), slots.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  st.live -= n;
+  std::vector<char> touched(st.nlist, 0);
+  for (int64_t sl : h_slots) {
+    const int32_t p = st.tile_part[sl / qk::TILE];
+    st.tomb[p]++;
+    touched[p] = 1;
+  }
+  // compaction: a partition with a quarter of its slots deleted has its
+  // holes below the new size filled from its live tail
+  std::vector<int64_t> src, dst, moved_ids;
+  for (int64_t p = 0; p < st.nlist; ++p) {
+    if (!touched[p] || st.tomb[p] * 4 < st.size[p]) continue;
+    const int64_t base = st.off[p] * qk::TILE;
+    const int64_t size = st.size[p];
+    std::vector<int64_t> pid(size);
+    QK_HIP(hipMemcpyAsync(pid.data(), st.ids + base, size * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+    const int64_t keep = size - st.tomb[p];
+    int64_t hole = 0, tail = keep;
+    while (true) {
+      while (hole < keep && pid[hole] >= 0) ++hole;
+      while (tail < size && pid[tail] < 0) ++tail;
+      if (hole >= keep || tail >= size) break;
+      src.push_back(base + tail);
+      dst.push_back(base + hole);
+      moved_ids.push_back(pid[tail]);
+      ++hole;
+      ++tail;
+    }
+    st.size[p] = (int32_t)keep;
+    st.tomb[p] = 0;
+  }
+  if (!src.empty()) {
+    const int64_t m = (int64_t)src.size();
+    Tmp<int64_t> d_src(idx->mem, m), d_dst(idx->mem, m), d_ids(idx->mem, m);
+    QK_HIP(hipMemcpyAsync(d_src.p, src.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    QK_HIP(hipMemcpyAsync(d_dst.p, dst.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    QK_HIP(hipMemcpyAsync(d_ids.p, moved_ids.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    qk::launch_move_slots(st, d_src.p, d_dst.p, m, s);
+    qk::launch_map_update(idx->idmap, d_ids.p, d_dst.p, m, s);
+    QK_HIP(hipStreamSynchronize(s));
+  }
+  upload_table(st, s);
+  QK_HIP(hipStreamSynchronize(s));
   API_END
 }
 
@@ -736,8 +1084,10 @@ int quake_export(const quake_index* cidx, float* centroids, int64_t* ids, int32_
     o_part.reserve(st.live);
     for (int64_t i = 0; i < slots; ++i)
       if (h_ids[i] >= 0) { o_ids.push_back(h_ids[i]); o_part.push_back(h_part[i]); }
-    if (ids) QK_HIP(hipMemcpyAsync(ids, o_ids.data(), o_ids.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    if (part) QK_HIP(hipMemcpyAsync(part, o_part.data(), o_part.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (ids && !o_ids.empty())
+      QK_HIP(hipMemcpyAsync(ids, o_ids.data(), o_ids.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    if (part && !o_part.empty())
+      QK_HIP(hipMemcpyAsync(part, o_part.data(), o_part.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   }
   QK_HIP(hipStreamSynchronize(s));
   API_END

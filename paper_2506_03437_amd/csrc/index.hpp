@@ -27,7 +27,9 @@ struct Error {
   } while (0)
 
 constexpr int TILE = 64;          // vectors per store tile: one per lane of a wave
-constexpr int KMAX = 256;         // largest k of the search path
+constexpr int KMAX = 256;         // largest result list of the wave-list scans
+constexpr int KMAX_LARGE = 1024;  // largest result list at all (upper level of two levels)
+constexpr int SORTED_ITEM_MAX = 1024;  // vectors per item of the sort-based scan (16 tiles)
 constexpr int CAP_TABLE_POINTS = 1024;
 
 // Row length of the 16-bit store copy: d rounded up to 32 * KS for a k-step
@@ -62,6 +64,14 @@ class DeviceMemory {
 // filled.  Within a tile, FP32 data is laid out [dp/4][64 lanes][4] and the
 // 16-bit copy [dp/8][64 lanes][8], so that a wave reading one 16-byte chunk
 // of 64 consecutive vectors touches one contiguous 1 KiB span.
+// id -> slot map (level 0): open addressing, capacity a power of two.
+struct IdMap {
+  int64_t* keys = nullptr;
+  int64_t* vals = nullptr;
+  uint64_t mask = 0;            // capacity - 1
+  int64_t used = 0;             // live + erased entries
+};
+
 struct Store {
   int32_t d = 0, dp = 0;
   int64_t nlist = 0;
@@ -80,6 +90,8 @@ struct Store {
   float* rows32 = nullptr;      // [tiles * 64][dp] row-major FP32 rows by slot (with a 16-bit copy: rerank)
   int64_t* ids = nullptr;       // [tiles * 64], -1 = empty or deleted
   int64_t live = 0;
+  std::vector<int32_t> tomb;     // deleted slots still inside size[p]
+  std::vector<int32_t> tile_part;  // partition owning each arena tile (-1 = unused)
 };
 
 struct Workspace {
@@ -89,6 +101,10 @@ struct Workspace {
   float* scores = nullptr;      // [nq][ncent]
   int32_t* sel = nullptr;       // [nq][M] nearest centroids by (value, id)
   int32_t* cand = nullptr;      // [nq][M] candidate partitions in scan order
+  int32_t* mq = nullptr;        // [nq] candidates of each query (M, or fewer below a two-level index)
+  int32_t* cand0 = nullptr;     // [nq][M0] level-0 candidates found by the level-1 search
+  int32_t* mq0 = nullptr;       // [nq] their number
+  int64_t cand0_cap = 0;
   float* h = nullptr;           // [nq][M] bisector distances in scan order
   int32_t* st_m = nullptr;      // committed partitions
   int32_t* st_w = nullptr;      // window the query asks for in the next round
@@ -109,6 +125,7 @@ struct Workspace {
   int64_t* st_vecs = nullptr;   // [nq] vectors in the round's window
   int64_t* st_pair = nullptr;   // [nq] first (query, partition) pair of the round
   uint16_t* q16 = nullptr;      // [nq][dp16] queries rounded to the 16-bit store type
+  int q16_dim = 0;
   float* qn2f = nullptr;        // [nq] |q|^2
   int64_t pairs_cap = 0, parts_cap = 0;
   int32_t* pair_q = nullptr;    // [pairs] query of the pair
@@ -161,6 +178,7 @@ struct quake_index {
   qk::DeviceMemory mem;
   qk::Store L0;                 // level 0: the vectors
   qk::Store L1;                 // level 1 (two-level): the level-0 centroids
+  qk::IdMap idmap;              // level-0 ids
   int32_t* top_of = nullptr;    // [L0.nlist] level-1 partition of each level-0 centroid
   double* cap_table = nullptr;  // [1024] device copy of the recall model table
   std::vector<double> h_cap_table;
@@ -182,8 +200,8 @@ void launch_scores(const float* q, int64_t nq, const float* c, int64_t nc, int d
                    hipStream_t s);
 void launch_select(const float* scores, int64_t nq, int64_t nc, int M, int metric, int32_t* cand,
                    hipStream_t s);
-void launch_geometry(const float* q, const float* c, int64_t nq, int dp, int M, int metric, const int32_t* sel,
-                     int32_t* order, float* h, hipStream_t s);
+void launch_geometry(const float* q, const float* c, int64_t nq, int dp, int M, const int32_t* mq, int metric,
+                     const int32_t* sel, int32_t* order, float* h, hipStream_t s);
 void launch_assign(const float* x, int64_t n, int dp, const float* c, int64_t nc, int metric, int32_t* assign,
                    hipStream_t s);
 void launch_kmeans_accumulate(const float* x, int64_t n, int dp, const int32_t* assign, float* sums,
@@ -227,5 +245,18 @@ void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, int64_t np
 void launch_scan_mfma(Workspace& ws, const Store& st, const RoundArgs& a, int dtype16, int blocks, hipStream_t s);
 void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
 void launch_norm16(const Store& st, int dtype16, hipStream_t s);
+
+// kernels: updates (k_update.hip)
+void launch_map_insert(IdMap& m, const int64_t* ids, const int64_t* slots, int64_t n, hipStream_t s);
+void launch_map_insert_store(IdMap& m, const int64_t* sid, int64_t slots, hipStream_t s);
+void launch_map_find(const IdMap& m, const int64_t* ids, int64_t n, int64_t* slots, int64_t* missing, hipStream_t s);
+void launch_map_erase(IdMap& m, const int64_t* ids, int64_t n, hipStream_t s);
+void launch_map_update(IdMap& m, const int64_t* ids, const int64_t* slots, int64_t n, hipStream_t s);
+void launch_mark_deleted(Store& st, const int64_t* slots, int64_t n, hipStream_t s);
+void launch_move_slots(Store& st, const int64_t* src, const int64_t* dst, int64_t n, hipStream_t s);
+void launch_norm16_slots(Store& st, const int64_t* slots, int64_t n, int dtype16, hipStream_t s);
+void launch_level1_to_candidates(int64_t nq, int M0, int kk, const int64_t* ri, int32_t* cand0, int32_t* mq,
+                                 hipStream_t s);
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
 }  // namespace qk

@@ -258,12 +258,18 @@ void launch_select(const float* scores, int64_t nq, int64_t nc, int M, int metri
 // of the two inner-product cells), then the candidates after c_0 are put in
 // ascending h order; ties keep the (key, id) order of the selection.
 __global__ __launch_bounds__(256) void k_geometry(const float* __restrict__ q, const float* __restrict__ c, int dp,
-                                                   int M, int ip, const int32_t* __restrict__ sel,
-                                                   int32_t* __restrict__ order, float* __restrict__ hout) {
+                                                   int stride, const int32_t* __restrict__ mq, int ip,
+                                                   const int32_t* __restrict__ sel, int32_t* __restrict__ order,
+                                                   float* __restrict__ hout) {
   __shared__ uint64_t buf[SORT_N];
   const int64_t qi = blockIdx.x;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int32_t* cq = sel + qi * M;
+  const int M = mq[qi];
+  const int32_t* cq = sel + qi * stride;
+  if (M <= 0) {  // no candidate at all (an empty upper-level result)
+    for (int t = threadIdx.x; t < stride; t += 256) { order[qi * stride + t] = -1; hout[qi * stride + t] = 0.f; }
+    return;
+  }
   const int c0 = cq[0];
   const float* qv = q + qi * dp;
   const float* c0v = c + (int64_t)c0 * dp;
@@ -288,22 +294,25 @@ __global__ __launch_bounds__(256) void k_geometry(const float* __restrict__ q, c
   for (int e = M - 1 + threadIdx.x; e < p2; e += 256) buf[e] = ~0ull;
   if (M > 1) bitonic_sort_u64(buf, p2);
   else __syncthreads();
-  for (int t = threadIdx.x; t < M; t += 256) {
+  for (int t = threadIdx.x; t < stride; t += 256) {
     if (t == 0) {
-      order[qi * M] = c0;
-      hout[qi * M] = 0.f;
-    } else {
+      order[qi * stride] = c0;
+      hout[qi * stride] = 0.f;
+    } else if (t < M) {
       const uint64_t e = buf[t - 1];
-      order[qi * M + t] = cq[(uint32_t)(e & 0xffffffffu)];
-      hout[qi * M + t] = float_unorder((uint32_t)(e >> 32));
+      order[qi * stride + t] = cq[(uint32_t)(e & 0xffffffffu)];
+      hout[qi * stride + t] = float_unorder((uint32_t)(e >> 32));
+    } else {
+      order[qi * stride + t] = -1;
+      hout[qi * stride + t] = 0.f;
     }
   }
 }
 
-void launch_geometry(const float* q, const float* c, int64_t nq, int dp, int M, int metric, const int32_t* sel,
-                      int32_t* order, float* h, hipStream_t s) {
+void launch_geometry(const float* q, const float* c, int64_t nq, int dp, int M, const int32_t* mq, int metric,
+                     const int32_t* sel, int32_t* order, float* h, hipStream_t s) {
   if (nq <= 0) return;
-  hipLaunchKernelGGL(k_geometry, dim3((unsigned)nq), dim3(256), 0, s, q, c, dp, M, metric == QUAKE_IP ? 1 : 0,
+  hipLaunchKernelGGL(k_geometry, dim3((unsigned)nq), dim3(256), 0, s, q, c, dp, M, mq, metric == QUAKE_IP ? 1 : 0,
                      sel, order, h);
 }
 

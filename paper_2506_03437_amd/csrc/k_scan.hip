@@ -61,7 +61,7 @@ void launch_round_init(Workspace& ws, const RoundArgs& a, int w0, hipStream_t s)
 // Work items each query needs for its window this round.  st_w is the
 // window the query asked for; st_weff is what it gets this round (0 when it
 // is finished or when the item buffer is full, see k_prefix).
-__global__ __launch_bounds__(256) void k_demand(int64_t nq, int M, int chunk_tiles,
+__global__ __launch_bounds__(256) void k_demand(int64_t nq, int M, int chunk_tiles, const int32_t* __restrict__ mq,
                                                  const int32_t* __restrict__ cand, const int32_t* __restrict__ psize,
                                                  const int32_t* __restrict__ st_m, const int32_t* __restrict__ st_w,
                                                  int32_t* __restrict__ st_weff, const int32_t* __restrict__ st_done,
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void k_demand(int64_t nq, int M, int chunk_til
   if (!st_done[q]) {
     const int m = st_m[q];
     w = st_w[q];
-    if (w > M - m) w = M - m;
+    if (w > mq[q] - m) w = mq[q] - m;
     for (int j = 0; j < w; ++j) {
       const int32_t sz = psize[cand[q * M + m + j]];
       dmd += item_chunks(sz, chunk_tiles);
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(1024) void k_prefix(int64_t nq, int64_t cap, const 
 }
 
 void launch_demand(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_demand, dim3((unsigned)((a.nq + 255) / 256)), dim3(256), 0, s, a.nq, a.M, a.chunk_tiles,
+  hipLaunchKernelGGL(k_demand, dim3((unsigned)((a.nq + 255) / 256)), dim3(256), 0, s, a.nq, a.M, a.chunk_tiles, ws.mq,
                      ws.cand, st.d_size, ws.st_m, ws.st_w, ws.st_weff, ws.st_done, ws.st_demand, ws.st_vecs);
   hipLaunchKernelGGL(k_prefix, dim3(1), dim3(1024), 0, s, a.nq, a.items_cap, ws.st_demand, ws.st_vecs, ws.st_item,
                      ws.st_weff, ws.st_pair, ws.total);
@@ -251,8 +251,72 @@ static void scan_f32_k(Workspace& ws, const Store& st, const RoundArgs& a, int64
                        st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi);
 }
 
+// Items whose result lists are longer than a wave's sorted list holds (the
+// upper level of a two-level index keeps hundreds of centroids per query):
+// one block scores all vectors of the item (at most 16 tiles), then sorts
+// them by (key, id) in LDS and keeps the first kk.
+template <int METRIC>
+__global__ __launch_bounds__(256) void k_scan_f32_sorted(const int4* __restrict__ items, int64_t nitems,
+                                                          const float* __restrict__ qpad, int dp,
+                                                          const float* __restrict__ v32, const int64_t* __restrict__ sid,
+                                                          const int64_t* __restrict__ poff,
+                                                          const int32_t* __restrict__ psize, int kk,
+                                                          float* __restrict__ pk, int64_t* __restrict__ pi) {
+  __shared__ float K[SORTED_ITEM_MAX];
+  __shared__ int64_t I[SORTED_ITEM_MAX];
+  const int64_t it = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int4 item = items[it];
+  const int q = item.x, p = item.y, t0 = item.z, t1 = item.w;
+  const int64_t tile0 = poff[p];
+  const int size = psize[p];
+  const int nch4 = dp >> 2;
+  const_float4* qs = (const_float4*)(qpad + (int64_t)q * dp);
+  for (int e = threadIdx.x; e < SORTED_ITEM_MAX; e += 256) { K[e] = KEY_EMPTY; I[e] = -1; }
+  __syncthreads();
+  for (int t = t0 + wave; t < t1; t += 4) {
+    const int64_t slot = (tile0 + t) * TILE + lane;
+    const float4* xp = reinterpret_cast<const float4*>(v32) + (tile0 + t) * (int64_t)nch4 * WAVE + lane;
+    const float key = tile_distance<METRIC>(xp, qs, nch4);
+    const int e = (t - t0) * TILE + lane;
+    if (e < SORTED_ITEM_MAX && t * TILE + lane < size) {
+      const int64_t id = sid[slot];
+      if (id >= 0) { K[e] = key; I[e] = id; }
+    }
+  }
+  __syncthreads();
+  for (int sz = 2; sz <= SORTED_ITEM_MAX; sz <<= 1) {
+    for (int stride = sz >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < SORTED_ITEM_MAX / 2; i += 256) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & sz) == 0;
+        const bool swap = up ? kv_less(K[hi], I[hi], K[lo], I[lo]) : kv_less(K[lo], I[lo], K[hi], I[hi]);
+        if (swap) {
+          const float tk = K[lo]; K[lo] = K[hi]; K[hi] = tk;
+          const int64_t ti = I[lo]; I[lo] = I[hi]; I[hi] = ti;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = threadIdx.x; e < kk; e += 256) {
+    pk[it * kk + e] = e < SORTED_ITEM_MAX ? K[e] : KEY_EMPTY;
+    pi[it * kk + e] = e < SORTED_ITEM_MAX ? I[e] : -1;
+  }
+}
+
 void launch_scan_f32(Workspace& ws, const Store& st, const RoundArgs& a, int64_t nitems, hipStream_t s) {
   if (nitems <= 0) return;
+  if (a.kk > KMAX) {
+    if (a.metric == QUAKE_L2)
+      hipLaunchKernelGGL(k_scan_f32_sorted<QUAKE_L2>, dim3((unsigned)nitems), dim3(256), 0, s, ws.items, nitems, ws.q,
+                         st.dp, st.v32, st.ids, st.d_off, st.d_size, a.kk, ws.pk, ws.pi);
+    else
+      hipLaunchKernelGGL(k_scan_f32_sorted<QUAKE_IP>, dim3((unsigned)nitems), dim3(256), 0, s, ws.items, nitems, ws.q,
+                         st.dp, st.v32, st.ids, st.d_off, st.d_size, a.kk, ws.pk, ws.pi);
+    return;
+  }
   if (a.metric == QUAKE_L2) scan_f32_k<QUAKE_L2>(ws, st, a, nitems, s);
   else scan_f32_k<QUAKE_IP>(ws, st, a, nitems, s);
 }
@@ -284,7 +348,8 @@ struct Model {
   double rho, p0, V, vsum;
 };
 
-// p_0, V = sum v_i and the committed mass v_1 + ... + v_{m-1} for radius rho.
+// p_0, V = sum v_i and the committed mass v_1 + ... + v_{m-1} for radius rho
+// (candidates 1 .. M - 1 of the query).
 __device__ void recompute_model(Model& md, double rho, const float* __restrict__ hq, int M, int committed,
                                 const double* __restrict__ table) {
   const int lane = lane_id();
@@ -335,8 +400,9 @@ __device__ int predict_window(const Model& md, const float* __restrict__ hq, int
   return M - from;
 }
 
-template <int KPL>
-__global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, int k, int kk, int aps, int ip, int chunk_tiles,
+template <int LMAX>
+__global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, const int32_t* __restrict__ mq, int k, int kk,
+                                                int aps, int ip, int chunk_tiles,
                                                 int wmax, double tau_r, double tau_rho,
                                                 const int32_t* __restrict__ cand, const float* __restrict__ hcand,
                                                 const int32_t* __restrict__ psize, const double* __restrict__ qn2,
@@ -348,14 +414,15 @@ __global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, int k, int kk,
                                                 double* __restrict__ st_p0, double* __restrict__ st_V,
                                                 double* __restrict__ st_vsum, double* __restrict__ st_r,
                                                 float* __restrict__ rk, int64_t* __restrict__ ri) {
-  __shared__ float Ak[KMAX], Bk[KMAX], Ok[KMAX];
-  __shared__ int64_t Ai[KMAX], Bi[KMAX], Oi[KMAX];
+  __shared__ float Ak[LMAX], Bk[LMAX], Ok[LMAX];
+  __shared__ int64_t Ai[LMAX], Bi[LMAX], Oi[LMAX];
   const int64_t q = blockIdx.x;
   const int lane = threadIdx.x;
   const int w = st_weff[q];
   if (st_done[q] || w == 0) return;
   for (int e = lane; e < kk; e += WAVE) { Ak[e] = rk[q * kk + e]; Ai[e] = ri[q * kk + e]; }
   const int m0 = st_m[q];
+  const int Mq = mq[q];
   int64_t it = st_item[q];
   Model md{st_rho[q], st_p0[q], st_V[q], st_vsum[q]};
   const double qn = ip ? qn2[q] : 0.0;
@@ -379,12 +446,12 @@ __global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, int k, int kk,
     const bool full = Ai[k - 1] >= 0;
     const double rho_new = full ? key_radius(Ak[k - 1], ip, qn) : __builtin_inf();
     if (committed == 1) {
-      recompute_model(md, rho_new, hq, M, committed, table);
+      recompute_model(md, rho_new, hq, Mq, committed, table);
     } else {
       const bool redo = __builtin_isinf(md.rho) ? !__builtin_isinf(rho_new)
                                                  : fabs(rho_new - md.rho) > tau_rho * md.rho;
       if (redo) {
-        recompute_model(md, rho_new, hq, M, committed, table);
+        recompute_model(md, rho_new, hq, Mq, committed, table);
       } else if (md.V > 0.0) {
         const double t = __builtin_isinf(md.rho) ? 0.0 : (double)hq[committed - 1] / md.rho;
         md.vsum += cap_share(table, t);
@@ -393,10 +460,10 @@ __global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, int k, int kk,
     r = full ? model_recall(md) : 0.0;
     if (r >= tau_r) stop = true;
   }
-  const bool done = stop || committed >= M;
+  const bool done = stop || committed >= Mq;
   int wn = 0;
   if (!done) {
-    if (aps && Ai[k - 1] >= 0) wn = predict_window(md, hq, M, committed, tau_r, table);
+    if (aps && Ai[k - 1] >= 0) wn = predict_window(md, hq, Mq, committed, tau_r, table);
     else wn = 2 * w;
     if (wn < 1) wn = 1;
     if (wn > wmax) wn = wmax;
@@ -412,11 +479,14 @@ __global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, int k, int kk,
 }
 
 void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const double* table, hipStream_t s) {
-  hipLaunchKernelGGL((k_commit<1>), dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.M, a.k, a.kk, a.aps,
-                     a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.tau_r, a.tau_rho, ws.cand, ws.h,
-                     st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_weff, ws.st_item,
-                     ws.st_rho,
-                     ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri);
+#define QK_COMMIT(L)                                                                                             \
+  hipLaunchKernelGGL((k_commit<L>), dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.M, ws.mq, a.k, a.kk, a.aps,    \
+                     a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.tau_r, a.tau_rho, ws.cand, ws.h,     \
+                     st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_weff, ws.st_item, \
+                     ws.st_rho, ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri)
+  if (a.kk <= KMAX) QK_COMMIT(KMAX);
+  else QK_COMMIT(KMAX_LARGE);
+#undef QK_COMMIT
 }
 
 // ---------------------------------------------------------------- outputs
