@@ -180,6 +180,65 @@ typedef struct {
 } quake_kernel_profile;
 int quake_profile(quake_index* index, int32_t enable, int32_t reset, quake_kernel_profile* out);
 
+/* ------------------------------------------------------------------------
+ * Serving loop.  A server owns a worker thread and a HIP stream on the
+ * index's device and answers single-query search requests and insert /
+ * delete batches submitted from any thread, with host arrays.  Searches are
+ * batched continuously: a query takes a free slot of the running batch at
+ * the next scan round and leaves it when its own adaptive scan stops, so
+ * queries that arrive while others are on the device overlap with them.
+ * The slot count is max_slots, or what hbm_budget_bytes of search
+ * workspace holds (each slot needs the query row, its candidates, its result
+ * lists and its share of the work items).  Updates keep submission order:
+ * admission pauses at an update, the queries already admitted finish, the
+ * batch is applied (an epoch), and admission resumes - so every search
+ * answers as if it ran alone on the index state of its epoch (the
+ * paper's system runs searches and updates serially, Sec. 8).
+ * While a server runs, its index must not be used through other entry
+ * points.  Single-level indexes only.
+ * ---------------------------------------------------------------------- */
+typedef struct quake_server quake_server;
+
+typedef struct {
+  int32_t max_slots;        /* queries in flight at once; 0 -> from hbm_budget_bytes, else 4096 */
+  int32_t reserved;
+  size_t hbm_budget_bytes;  /* device bytes the in-flight searches may use; 0 -> unlimited */
+  quake_search_params search;
+} quake_server_params;
+
+typedef struct {
+  int64_t completed;        /* searches answered */
+  int64_t queued;           /* requests waiting for admission */
+  int64_t in_flight;        /* searches holding a slot */
+  int64_t slots;            /* slot capacity */
+  int64_t max_in_flight;    /* most slots held at once */
+  int64_t epochs;           /* update batches applied */
+  int64_t rounds;           /* scan rounds run */
+  double p50_latency_s;     /* arrival -> answer ready, over completed searches */
+  double p99_latency_s;
+  double mean_latency_s;
+  double qps;               /* completed / (last answer - first arrival) */
+} quake_server_report;
+
+/* Errors: INVALID (bad params, two-level index), STATE, NOMEM, DEVICE. */
+int quake_server_create(quake_index* index, const quake_server_params* params, quake_server** out);
+/* Submit n single-query searches q[n][d] (host float32); tickets are
+ * *first_ticket .. *first_ticket + n - 1. */
+int quake_server_search(quake_server* server, const float* q, int64_t n, uint64_t* first_ticket);
+/* Submit an insert batch x[n][d], ids[n] or a delete batch ids[n] (host). */
+int quake_server_insert(quake_server* server, const float* x, const int64_t* ids, int64_t n, uint64_t* ticket);
+int quake_server_delete(quake_server* server, const int64_t* ids, int64_t n, uint64_t* ticket);
+/* Wait up to timeout_s (< 0: forever) for a ticket.  Searches write k ids
+ * and distances (host) and *nscanned; every ticket writes the request's
+ * status code (QUAKE_OK or the error of an update batch) to *status.
+ * Returns QUAKE_OK when the ticket finished (it is then forgotten),
+ * QUAKE_E_STATE on timeout, QUAKE_E_INVALID for an unknown ticket. */
+int quake_server_wait(quake_server* server, uint64_t ticket, double timeout_s, int64_t* ids, float* dist,
+                      int32_t* nscanned, int32_t* status);
+int quake_server_stats(quake_server* server, quake_server_report* out, int32_t reset);
+/* Answers what was submitted, stops the worker and frees the server. */
+void quake_server_destroy(quake_server* server);
+
 void quake_free(quake_index* index);
 const char* quake_last_error(void);
 

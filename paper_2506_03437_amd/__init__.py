@@ -7,6 +7,7 @@ include/quake.h); ``quake`` is its Python binding.
 from .quake import (  # noqa: F401
     Index,
     QuakeError,
+    Server,
     load_library,
     quake_build,
     quake_candidates,
@@ -18,6 +19,13 @@ from .quake import (  # noqa: F401
     quake_insert,
     quake_profile,
     quake_search,
+    quake_server_create,
+    quake_server_delete,
+    quake_server_destroy,
+    quake_server_insert,
+    quake_server_search,
+    quake_server_stats,
+    quake_server_wait,
     quake_set_tuning,
     quake_stats,
 )

@@ -11,16 +11,21 @@
 #include <string>
 #include <vector>
 
+#include "engine.hpp"
 #include "index.hpp"
 
-namespace {
-
+namespace qk {
 thread_local std::string g_error;
 
-int fail(int code, const std::string& msg) {
+int set_error(int code, const std::string& msg) {
   g_error = msg;
   return code;
 }
+}  // namespace qk
+
+namespace {
+
+int fail(int code, const std::string& msg) { return qk::set_error(code, msg); }
 
 #define API_BEGIN try {
 #define API_END                                                      \
@@ -34,6 +39,14 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+void check_index(const quake_index* idx) {
+  QK_CHECK(idx && idx->magic == 0x51554b45u, QUAKE_E_STATE, "invalid or freed index handle");
+}
+
+}  // namespace
+
+namespace qk {
+
 // Number of candidate partitions for a fraction f of n (ceil, at least 1,
 // at most n; the product is taken with a 1e-9 allowance so that 0.05 * 1000
 // gives 50 and not 51).
@@ -43,14 +56,6 @@ int candidate_count(double f, int64_t n) {
   if (m > (double)n) m = (double)n;
   return (int)m;
 }
-
-void check_index(const quake_index* idx) {
-  QK_CHECK(idx && idx->magic == 0x51554b45u, QUAKE_E_STATE, "invalid or freed index handle");
-}
-
-}  // namespace
-
-namespace qk {
 
 void* DeviceMemory::raw_alloc(size_t bytes) {
   if (bytes == 0) bytes = 256;
@@ -383,6 +388,10 @@ int64_t count_missing(quake_index* idx, const int64_t* ids, int64_t n, int64_t* 
 
 // ---------------------------------------------------------------- searches
 
+}  // namespace
+
+namespace qk {
+
 int64_t max_chunks(const Store& st, int chunk_tiles) {
   int64_t mx = 1;
   for (int32_t sz : st.size) {
@@ -391,13 +400,6 @@ int64_t max_chunks(const Store& st, int chunk_tiles) {
   }
   return mx;
 }
-
-// One search over one store, resolved.
-struct Job {
-  int k = 0, kk = 0, aps = 0, M = 0, w0 = 0, wmax = 0, batched = 0, dtype16 = QUAKE_F32;
-  double tau_r = 0, f_M = 0, tau_rho = 0.01;
-  bool given = false;  // candidate rows already in ws.cand0 / ws.mq0 (level 0 of two levels)
-};
 
 Job resolve(const quake_index* idx, const Store& st, const quake_search_params* p) {
   QK_CHECK(p, QUAKE_E_INVALID, "params is NULL");
@@ -491,7 +493,7 @@ void ensure_queries(quake_index* idx, int64_t nq) {
 }
 
 void ensure_workspace(quake_index* idx, int64_t nc, int64_t M, int64_t kk, int64_t items, int64_t pairs,
-                      int dp16, bool scores = true) {
+                      int dp16, bool scores) {
   qk::Workspace& w = idx->ws;
   auto& mem = idx->mem;
   if (scores) grow(mem, w.scores, w.scores_cap, w.nq_cap * nc);
@@ -545,6 +547,17 @@ void ensure_workspace(quake_index* idx, int64_t nc, int64_t M, int64_t kk, int64
     QK_HIP(hipMemset(w.pcount, 0, w.parts_cap * sizeof(int32_t)));
   }
 }
+
+}  // namespace qk
+
+namespace {
+
+using qk::candidate_count;
+using qk::ensure_queries;
+using qk::ensure_workspace;
+using qk::Job;
+using qk::max_chunks;
+using qk::resolve;
 
 // Point the workspace's query rows at a sub-range for the duration of a scope.
 struct QueryWindow {
@@ -717,7 +730,7 @@ void upper_level(quake_index* idx, int64_t nq, int M0, const quake_search_params
 
 extern "C" {
 
-const char* quake_last_error(void) { return g_error.c_str(); }
+const char* quake_last_error(void) { return qk::g_error.c_str(); }
 
 int quake_cap_table(int32_t d, double* out) {
   API_BEGIN

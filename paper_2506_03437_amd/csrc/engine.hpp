@@ -1,0 +1,30 @@
+// Search-engine internals shared by the C ABI (capi.cpp) and the serving
+// loop (serve.cpp).
+#pragma once
+#include "index.hpp"
+
+namespace qk {
+
+// Records the message quake_last_error returns on this thread; returns code.
+int set_error(int code, const std::string& msg);
+
+// Number of candidate partitions for a fraction f of n (ceil, at least 1,
+// at most n; the product is taken with a 1e-9 allowance so that 0.05 * 1000
+// gives 50 and not 51).
+int candidate_count(double f, int64_t n);
+
+// One search over one store, resolved from quake_search_params.
+struct Job {
+  int k = 0, kk = 0, aps = 0, M = 0, w0 = 0, wmax = 0, batched = 0, dtype16 = QUAKE_F32;
+  double tau_r = 0, f_M = 0, tau_rho = 0.01;
+  bool given = false;  // candidate rows already in ws.cand0 / ws.mq0 (level 0 of two levels)
+};
+
+Job resolve(const quake_index* idx, const Store& st, const quake_search_params* p);
+int64_t max_chunks(const Store& st, int chunk_tiles);
+// Per-query arrays of the workspace for nq queries (reallocates, dropping contents, when it grows).
+void ensure_queries(quake_index* idx, int64_t nq);
+void ensure_workspace(quake_index* idx, int64_t nc, int64_t M, int64_t kk, int64_t items, int64_t pairs, int dp16,
+                      bool scores = true);
+
+}  // namespace qk

@@ -240,10 +240,12 @@ void launch_finalize(Workspace& ws, const RoundArgs& a, int64_t* out_ids, float*
                      int32_t* out_nscanned, double* out_recall, hipStream_t s);
 
 // kernels: the batched scan (k_batched.hip)
-void launch_queries16(Workspace& ws, int64_t nq, int dp, int dp16, int dtype16, hipStream_t s);
+void launch_queries16(Workspace& ws, int64_t nq, int dp, int dp16, int dtype16, hipStream_t s,
+                      const int32_t* slots = nullptr);
 void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, int64_t npairs, hipStream_t s);
 void launch_scan_mfma(Workspace& ws, const Store& st, const RoundArgs& a, int dtype16, int blocks, hipStream_t s);
-void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
+void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s, const int32_t* slots = nullptr,
+                   int64_t nslots = 0);
 void launch_norm16(const Store& st, int dtype16, hipStream_t s);
 
 // kernels: updates (k_update.hip)
@@ -258,5 +260,15 @@ void launch_norm16_slots(Store& st, const int64_t* slots, int64_t n, int dtype16
 void launch_level1_to_candidates(int64_t nq, int M0, int kk, const int64_t* ri, int32_t* cand0, int32_t* mq,
                                  hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+
+// kernels: serving (k_serve.hip)
+void launch_rows_to_slots(const float* x, int64_t n, int d, int dp, const int32_t* slots, float* out, double* norm2,
+                          hipStream_t s);
+void launch_candidates_to_slots(const int32_t* cand, const float* h, int64_t n, int M, const int32_t* slots,
+                                int32_t* cand_out, float* h_out, int32_t* mq, hipStream_t s);
+void launch_init_slots(Workspace& ws, const int32_t* slots, int64_t n, int kk, int w0, hipStream_t s);
+void launch_mark_free(Workspace& ws, int64_t n, hipStream_t s);
+void launch_gather_results(const Workspace& ws, const int32_t* slots, int64_t n, int k, int kk, int metric,
+                           int64_t* ids, float* dist, int32_t* ns, double* rec, hipStream_t s);
 
 }  // namespace qk

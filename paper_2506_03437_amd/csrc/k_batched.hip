@@ -44,21 +44,23 @@ __device__ __forceinline__ uint16_t round_bf16(float f) {
 
 __global__ __launch_bounds__(256) void k_queries16(const float* __restrict__ q, int64_t nq, int dp, int dp16,
                                                     int f16, const double* __restrict__ qn2, uint16_t* __restrict__ q16,
-                                                    float* __restrict__ qn2f) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t row = e / dp16;
-  if (row >= nq) return;
-  const int j = (int)(e - row * dp16);
+                                                    float* __restrict__ qn2f, const int32_t* __restrict__ slots) {
+  const int64_t e0 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = e0 / dp16;
+  if (i >= nq) return;
+  const int j = (int)(e0 - i * dp16);
+  const int64_t row = slots ? slots[i] : i;
+  const int64_t e = row * dp16 + j;
   const float v = j < dp ? q[row * dp + j] : 0.f;
   q16[e] = f16 ? __builtin_bit_cast(uint16_t, (_Float16)v) : round_bf16(v);
   if (j == 0) qn2f[row] = (float)qn2[row];
 }
 
-void launch_queries16(Workspace& ws, int64_t nq, int dp, int dp16, int dtype16, hipStream_t s) {
+void launch_queries16(Workspace& ws, int64_t nq, int dp, int dp16, int dtype16, hipStream_t s, const int32_t* slots) {
   const int64_t n = nq * dp16;
   if (n <= 0) return;
   hipLaunchKernelGGL(k_queries16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ws.q, nq, dp, dp16,
-                     dtype16 == QUAKE_F16 ? 1 : 0, ws.qn2, ws.q16, ws.qn2f);
+                     dtype16 == QUAKE_F16 ? 1 : 0, ws.qn2, ws.q16, ws.qn2f, slots);
 }
 
 // ---------------------------------------------------------------- grouping
@@ -440,8 +442,9 @@ void launch_scan_mfma(Workspace& ws, const Store& st, const RoundArgs& a, int dt
 template <int METRIC>
 __global__ __launch_bounds__(64) void k_rerank(int64_t nq, int k, int kk, const float* __restrict__ qpad, int dp,
                                                 const float* __restrict__ rows, const int64_t* __restrict__ sid,
-                                                float* __restrict__ rk, int64_t* __restrict__ ri) {
-  const int64_t q = blockIdx.x;
+                                                float* __restrict__ rk, int64_t* __restrict__ ri,
+                                                const int32_t* __restrict__ slots) {
+  const int64_t q = slots ? slots[blockIdx.x] : blockIdx.x;
   const int lane = threadIdx.x;
   const float* qv = qpad + q * dp;
   const int64_t myslot = lane < kk ? ri[q * kk + lane] : -1;
@@ -486,14 +489,16 @@ __global__ __launch_bounds__(64) void k_rerank(int64_t nq, int k, int kk, const 
   if (lane < k) { rk[q * kk + lane] = key; ri[q * kk + lane] = id; }
 }
 
-void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
-  if (a.nq <= 0) return;
+void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s, const int32_t* slots,
+                   int64_t nslots) {
+  const int64_t n = slots ? nslots : a.nq;
+  if (n <= 0) return;
   if (a.metric == QUAKE_L2)
-    hipLaunchKernelGGL(k_rerank<QUAKE_L2>, dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.k, a.kk, ws.q, st.dp,
-                       st.rows32, st.ids, ws.rk, ws.ri);
+    hipLaunchKernelGGL(k_rerank<QUAKE_L2>, dim3((unsigned)n), dim3(64), 0, s, a.nq, a.k, a.kk, ws.q, st.dp,
+                       st.rows32, st.ids, ws.rk, ws.ri, slots);
   else
-    hipLaunchKernelGGL(k_rerank<QUAKE_IP>, dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.k, a.kk, ws.q, st.dp,
-                       st.rows32, st.ids, ws.rk, ws.ri);
+    hipLaunchKernelGGL(k_rerank<QUAKE_IP>, dim3((unsigned)n), dim3(64), 0, s, a.nq, a.k, a.kk, ws.q, st.dp,
+                       st.rows32, st.ids, ws.rk, ws.ri, slots);
 }
 
 // ---------------------------------------------------------------- store norms

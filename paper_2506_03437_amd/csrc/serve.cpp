@@ -1,0 +1,538 @@
+// Serving loop: continuous batching of single-query searches, with update
+// batches applied between epochs.
+//
+// The worker thread keeps up to `cap` searches in flight, each in a slot of
+// the index's search workspace.  Every iteration it (1) admits queued
+// searches into free slots - scoring and ordering their candidates and
+// resetting their state - (2) runs one scan round over all slots (finished
+// and free slots do no work), and (3) answers the slots whose adaptive scan
+// stopped in that round and frees them.  A search therefore joins a batch
+// already in progress and its work items share rounds (and, on the batched
+// path, partition reads) with searches admitted earlier.  Per-query results
+// do not depend on the company a query keeps: every step of a query's search
+// reads only that query's own state.  An update request at the head of the
+// queue stops admission until the slots drain, then runs as one batch.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "engine.hpp"
+#include "index.hpp"
+
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+  uint64_t ticket = 0;
+  int kind = 0;  // 0 search, 1 insert, 2 delete
+  std::vector<float> x;
+  std::vector<int64_t> ids;
+  double arrive = 0;
+};
+
+struct Answer {
+  bool ready = false;
+  int status = QUAKE_OK;
+  std::vector<int64_t> ids;
+  std::vector<float> dist;
+  int32_t nscanned = 0;
+};
+
+template <class T>
+T* pinned(size_t n) {
+  void* p = nullptr;
+  QK_HIP(hipHostMalloc(&p, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault));
+  return static_cast<T*>(p);
+}
+
+}  // namespace
+
+struct quake_server {
+  quake_index* idx = nullptr;
+  quake_search_params sp{};
+  qk::Job job;
+  int64_t cap = 0;
+  int device = 0;
+  hipStream_t s = nullptr;
+  int chunk_tiles = 16;
+  int64_t items = 0;
+
+  std::thread worker;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request> fifo;
+  std::unordered_map<uint64_t, Answer> answers;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::string fatal;
+
+  std::vector<uint64_t> slot_ticket;  // 0 = free
+  std::vector<double> slot_arrive;
+  std::vector<int32_t> free_slots;
+  int64_t active = 0, max_active = 0, epochs = 0, rounds = 0, completed = 0;
+  std::vector<double> lat;
+  double first_arrive = -1, last_done = 0;
+
+  // device staging for admission and answers
+  float* d_x = nullptr;
+  float* d_pad = nullptr;
+  double* d_n2 = nullptr;
+  float* d_scores = nullptr;
+  int32_t* d_sel = nullptr;
+  int32_t* d_cand = nullptr;
+  float* d_h = nullptr;
+  int32_t* d_mq = nullptr;
+  int32_t* d_slots = nullptr;
+  int64_t* d_ids = nullptr;
+  float* d_dist = nullptr;
+  int32_t* d_ns = nullptr;
+  double* d_rec = nullptr;
+  // pinned host mirrors
+  float* h_x = nullptr;
+  int32_t* h_slots = nullptr;
+  int32_t* h_done = nullptr;
+  int64_t* h_ids = nullptr;
+  float* h_dist = nullptr;
+  int32_t* h_ns = nullptr;
+  double* h_rec = nullptr;
+
+  const qk::Store& st() const { return idx->L0; }
+
+  qk::RoundArgs args() const {
+    qk::RoundArgs a{};
+    a.nq = cap;
+    a.M = job.M;
+    a.k = job.k;
+    a.kk = job.kk;
+    a.aps = job.aps;
+    a.chunk_tiles = chunk_tiles;
+    a.wmax = job.wmax;
+    a.metric = idx->metric;
+    a.dim = idx->d;
+    a.tau_r = job.tau_r;
+    a.tau_rho = job.tau_rho;
+    a.items_cap = std::min<int64_t>(idx->ws.items_cap, items);
+    return a;
+  }
+
+  // Size the search workspace for cap slots and mark every slot free.
+  void setup() {
+    chunk_tiles = idx->tune.chunk_tiles > 0 ? idx->tune.chunk_tiles : 16;
+    // long result lists are scanned by sorting whole items in LDS
+    if (job.kk > qk::KMAX) chunk_tiles = std::min(chunk_tiles, qk::SORTED_ITEM_MAX / qk::TILE);
+    const int64_t mc = qk::max_chunks(st(), chunk_tiles);
+    items = std::max<int64_t>(cap * std::max(job.w0, 4) * 2, (int64_t)job.wmax * mc + 1);
+    qk::ensure_queries(idx, cap);
+    qk::ensure_workspace(idx, st().nlist, job.M, job.kk, items, job.batched ? cap * (int64_t)job.wmax : 0,
+                         job.batched ? st().dp16 : 0, false);
+    QK_HIP(hipMemsetAsync(idx->ws.total, 0, 8 * sizeof(int64_t), s));
+    qk::launch_mark_free(idx->ws, cap, s);
+    if (job.batched && idx->cu_count == 0)
+      QK_HIP(hipDeviceGetAttribute(&idx->cu_count, hipDeviceAttributeMultiprocessorCount, device));
+    QK_HIP(hipStreamSynchronize(s));
+  }
+
+  void admit(std::vector<Request>& reqs, const std::vector<int32_t>& slots) {
+    const int64_t n = (int64_t)reqs.size();
+    const int d = idx->d, dp = idx->dp;
+    for (int64_t i = 0; i < n; ++i) {
+      std::memcpy(h_x + i * d, reqs[i].x.data(), d * sizeof(float));
+      h_slots[i] = slots[i];
+    }
+    QK_HIP(hipMemcpyAsync(d_x, h_x, n * d * sizeof(float), hipMemcpyHostToDevice, s));
+    QK_HIP(hipMemcpyAsync(d_slots, h_slots, n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    qk::Workspace& w = idx->ws;
+    qk::launch_rows_to_slots(d_x, n, d, dp, d_slots, w.q, w.qn2, s);
+    qk::launch_pad_rows(d_x, n, d, dp, d_pad, d_n2, s);
+    qk::launch_scores(d_pad, n, st().centroids, st().nlist, dp, idx->metric, d_scores, s);
+    if (job.aps) {
+      qk::launch_fill_i32(d_mq, n, job.M, s);
+      qk::launch_select(d_scores, n, st().nlist, job.M, idx->metric, d_sel, s);
+      qk::launch_geometry(d_pad, st().centroids, n, dp, job.M, d_mq, idx->metric, d_sel, d_cand, d_h, s);
+      qk::launch_candidates_to_slots(d_cand, d_h, n, job.M, d_slots, w.cand, w.h, w.mq, s);
+    } else {
+      qk::launch_select(d_scores, n, st().nlist, job.M, idx->metric, d_cand, s);
+      qk::launch_candidates_to_slots(d_cand, nullptr, n, job.M, d_slots, w.cand, w.h, w.mq, s);
+    }
+    if (job.batched) qk::launch_queries16(w, n, dp, st().dp16, job.dtype16, s, d_slots);
+    qk::launch_init_slots(w, d_slots, n, job.kk, job.w0, s);
+  }
+
+  void round() {
+    qk::Workspace& w = idx->ws;
+    qk::RoundArgs a = args();
+    qk::launch_demand(w, st(), a, s);
+    int64_t tot[3];
+    QK_HIP(hipMemcpyAsync(tot, w.total, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+    QK_CHECK(tot[0] > 0, QUAKE_E_DEVICE, "a round found no work for the searches in flight");
+    if (job.batched) {
+      qk::launch_group(w, st(), a, tot[2], s);
+      qk::launch_scan_mfma(w, st(), a, job.dtype16, std::max(idx->cu_count, 8) * 2, s);
+    } else {
+      qk::launch_emit(w, st(), a, s);
+      qk::launch_scan_f32(w, st(), a, tot[0], s);
+    }
+    qk::launch_commit(w, st(), a, idx->cap_table, s);
+    ++rounds;
+  }
+
+  void harvest() {
+    qk::Workspace& w = idx->ws;
+    QK_HIP(hipMemcpyAsync(h_done, w.st_done, cap * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> fin;
+    for (int64_t q = 0; q < cap; ++q)
+      if (slot_ticket[q] != 0 && h_done[q]) fin.push_back((int32_t)q);
+    if (fin.empty()) return;
+    const int64_t n = (int64_t)fin.size();
+    std::memcpy(h_slots, fin.data(), n * sizeof(int32_t));
+    QK_HIP(hipMemcpyAsync(d_slots, h_slots, n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    qk::RoundArgs a = args();
+    if (job.batched) qk::launch_rerank(w, st(), a, s, d_slots, n);
+    qk::launch_gather_results(w, d_slots, n, job.k, job.kk, idx->metric, d_ids, d_dist, d_ns, d_rec, s);
+    const int k = job.k;
+    QK_HIP(hipMemcpyAsync(h_ids, d_ids, n * k * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipMemcpyAsync(h_dist, d_dist, n * k * sizeof(float), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipMemcpyAsync(h_ns, d_ns, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+    const double t = now_s();
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (int64_t i = 0; i < n; ++i) {
+        const int32_t q = fin[i];
+        Answer& an = answers[slot_ticket[q]];
+        an.ids.assign(h_ids + i * k, h_ids + (i + 1) * k);
+        an.dist.assign(h_dist + i * k, h_dist + (i + 1) * k);
+        an.nscanned = h_ns[i];
+        an.status = QUAKE_OK;
+        an.ready = true;
+        lat.push_back(t - slot_arrive[q]);
+        slot_ticket[q] = 0;
+        free_slots.push_back(q);
+        --active;
+        ++completed;
+      }
+      last_done = t;
+    }
+    cv_done.notify_all();
+  }
+
+  void apply_update(Request& r) {
+    const int64_t n = (int64_t)r.ids.size();
+    int rc = QUAKE_OK;
+    int64_t* d_i = idx->mem.alloc<int64_t>(std::max<int64_t>(n, 1));
+    float* d_v = nullptr;
+    try {
+      QK_HIP(hipMemcpyAsync(d_i, r.ids.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+      if (r.kind == 1) {
+        d_v = idx->mem.alloc<float>(std::max<int64_t>(n, 1) * idx->d);
+        QK_HIP(hipMemcpyAsync(d_v, r.x.data(), (size_t)n * idx->d * sizeof(float), hipMemcpyHostToDevice, s));
+        rc = quake_insert(idx, d_v, d_i, n, s);
+      } else {
+        rc = quake_delete(idx, d_i, n, s);
+      }
+    } catch (...) {
+      idx->mem.release(d_i);
+      idx->mem.release(d_v);
+      throw;
+    }
+    idx->mem.release(d_i);
+    idx->mem.release(d_v);
+    setup();  // partition sizes changed: work-item bounds and buffers follow
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      Answer& an = answers[r.ticket];
+      an.status = rc;
+      an.ready = true;
+      ++epochs;
+    }
+    cv_done.notify_all();
+  }
+
+  void run() {
+    try {
+      QK_HIP(hipSetDevice(device));
+      setup();
+      while (true) {
+        std::vector<Request> adm;
+        std::vector<int32_t> slots;
+        Request upd;
+        bool has_upd = false;
+        {
+          std::unique_lock<std::mutex> lk(mu);
+          cv_work.wait(lk, [&] { return stop || !fifo.empty() || active > 0; });
+          if (stop && fifo.empty() && active == 0) break;
+          while (!fifo.empty() && fifo.front().kind == 0 && !free_slots.empty()) {
+            const int32_t q = free_slots.back();
+            free_slots.pop_back();
+            slot_ticket[q] = fifo.front().ticket;
+            slot_arrive[q] = fifo.front().arrive;
+            slots.push_back(q);
+            adm.push_back(std::move(fifo.front()));
+            fifo.pop_front();
+          }
+          active += (int64_t)adm.size();
+          max_active = std::max(max_active, active);
+          if (adm.empty() && active == 0 && !fifo.empty() && fifo.front().kind != 0) {
+            upd = std::move(fifo.front());
+            fifo.pop_front();
+            has_upd = true;
+          }
+        }
+        if (has_upd) {
+          apply_update(upd);
+          continue;
+        }
+        if (!adm.empty()) admit(adm, slots);
+        if (active > 0) {
+          round();
+          harvest();
+        }
+      }
+    } catch (const qk::Error& e) {
+      fail(e.msg);
+    } catch (const std::exception& e) {
+      fail(e.what());
+    }
+  }
+
+  void fail(const std::string& msg) {
+    std::lock_guard<std::mutex> lk(mu);
+    fatal = msg.empty() ? "serving loop failed" : msg;
+    for (auto& kv : answers)
+      if (!kv.second.ready) {
+        kv.second.ready = true;
+        kv.second.status = QUAKE_E_DEVICE;
+      }
+    cv_done.notify_all();
+  }
+
+  uint64_t enqueue(std::vector<Request>& reqs) {
+    std::lock_guard<std::mutex> lk(mu);
+    QK_CHECK(fatal.empty(), QUAKE_E_STATE, "the serving loop stopped: " + fatal);
+    QK_CHECK(!stop, QUAKE_E_STATE, "the server is stopping");
+    const uint64_t first = next_ticket;
+    const double t = now_s();
+    if (first_arrive < 0) first_arrive = t;
+    for (auto& r : reqs) {
+      r.ticket = next_ticket++;
+      r.arrive = t;
+      answers.emplace(r.ticket, Answer{});
+      fifo.push_back(std::move(r));
+    }
+    cv_work.notify_one();
+    return first;
+  }
+
+  void release_buffers() {
+    for (void* p : {(void*)d_x, (void*)d_pad, (void*)d_n2, (void*)d_scores, (void*)d_sel, (void*)d_cand, (void*)d_h,
+                    (void*)d_mq, (void*)d_slots, (void*)d_ids, (void*)d_dist, (void*)d_ns, (void*)d_rec})
+      idx->mem.release(p);
+    for (void* p : {(void*)h_x, (void*)h_slots, (void*)h_done, (void*)h_ids, (void*)h_dist, (void*)h_ns,
+                    (void*)h_rec})
+      if (p) (void)hipHostFree(p);
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+namespace {
+
+int fail_rc(int code, const std::string& msg) { return qk::set_error(code, msg); }
+
+#define SRV_BEGIN try {
+#define SRV_END                                                                            \
+  }                                                                                        \
+  catch (const qk::Error& e) { return fail_rc(e.code, e.msg); }                            \
+  catch (const std::bad_alloc&) { return fail_rc(QUAKE_E_NOMEM, "host allocation failed"); } \
+  catch (const std::exception& e) { return fail_rc(QUAKE_E_DEVICE, e.what()); }            \
+  return QUAKE_OK;
+
+// Device bytes one slot of in-flight work needs (workspace rows, its work
+// items and partial lists, staging).
+int64_t slot_bytes(const quake_index* idx, const qk::Job& job) {
+  const int64_t N = idx->L0.nlist, dp = idx->dp, d = idx->d;
+  int64_t b = dp * 4 + 8 + N * 4 * 2 + (int64_t)job.M * 12 * 2 + (int64_t)job.kk * 12 + 96;
+  b += (int64_t)std::max(job.w0, 4) * 2 * (16 + (int64_t)job.kk * 12);
+  if (job.batched) b += (int64_t)job.wmax * 20 + idx->L0.dp16 * 2 + 4;
+  b += d * 4 + dp * 4 + 8 + (int64_t)job.k * 12 + 16;
+  return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int quake_server_create(quake_index* idx, const quake_server_params* params, quake_server** out) {
+  SRV_BEGIN
+  QK_CHECK(out && params, QUAKE_E_INVALID, "params and out are required");
+  *out = nullptr;
+  QK_CHECK(idx && idx->magic == 0x51554b45u, QUAKE_E_STATE, "invalid index handle");
+  QK_CHECK(idx->n_levels == 1, QUAKE_E_INVALID, "the serving loop runs on single-level indexes");
+  QK_CHECK(params->max_slots >= 0, QUAKE_E_INVALID, "max_slots must be >= 0");
+  std::unique_ptr<quake_server> srv(new quake_server());
+  srv->idx = idx;
+  srv->sp = params->search;
+  srv->job = qk::resolve(idx, idx->L0, &srv->sp);
+  int64_t cap = params->max_slots > 0 ? params->max_slots : 4096;
+  if (params->hbm_budget_bytes > 0) {
+    const int64_t by_budget = (int64_t)(params->hbm_budget_bytes / (size_t)slot_bytes(idx, srv->job));
+    QK_CHECK(by_budget >= 1, QUAKE_E_NOMEM, "the HBM budget does not hold one search slot");
+    cap = params->max_slots > 0 ? std::min<int64_t>(cap, by_budget) : std::min<int64_t>(by_budget, 1 << 16);
+  }
+  srv->cap = cap;
+  QK_HIP(hipGetDevice(&srv->device));
+  QK_HIP(hipStreamCreateWithFlags(&srv->s, hipStreamNonBlocking));
+  auto& mem = idx->mem;
+  const int64_t N = idx->L0.nlist, M = srv->job.M, k = srv->job.k;
+  try {
+    srv->d_x = mem.alloc<float>(cap * idx->d);
+    srv->d_pad = mem.alloc<float>(cap * idx->dp);
+    srv->d_n2 = mem.alloc<double>(cap);
+    srv->d_scores = mem.alloc<float>(cap * N);
+    srv->d_sel = mem.alloc<int32_t>(cap * M);
+    srv->d_cand = mem.alloc<int32_t>(cap * M);
+    srv->d_h = mem.alloc<float>(cap * M);
+    srv->d_mq = mem.alloc<int32_t>(cap);
+    srv->d_slots = mem.alloc<int32_t>(cap);
+    srv->d_ids = mem.alloc<int64_t>(cap * k);
+    srv->d_dist = mem.alloc<float>(cap * k);
+    srv->d_ns = mem.alloc<int32_t>(cap);
+    srv->d_rec = mem.alloc<double>(cap);
+    srv->h_x = pinned<float>(cap * idx->d);
+    srv->h_slots = pinned<int32_t>(cap);
+    srv->h_done = pinned<int32_t>(cap);
+    srv->h_ids = pinned<int64_t>(cap * k);
+    srv->h_dist = pinned<float>(cap * k);
+    srv->h_ns = pinned<int32_t>(cap);
+    srv->h_rec = pinned<double>(cap);
+  } catch (...) {
+    srv->release_buffers();
+    throw;
+  }
+  srv->slot_ticket.assign(cap, 0);
+  srv->slot_arrive.assign(cap, 0.0);
+  for (int64_t q = cap - 1; q >= 0; --q) srv->free_slots.push_back((int32_t)q);
+  quake_server* raw = srv.get();
+  srv->worker = std::thread([raw] { raw->run(); });
+  *out = srv.release();
+  SRV_END
+}
+
+int quake_server_search(quake_server* srv, const float* q, int64_t n, uint64_t* first_ticket) {
+  SRV_BEGIN
+  QK_CHECK(srv && (n == 0 || q) && n >= 0, QUAKE_E_INVALID, "bad arguments");
+  const int d = srv->idx->d;
+  std::vector<Request> reqs(n);
+  for (int64_t i = 0; i < n; ++i) {
+    reqs[i].kind = 0;
+    reqs[i].x.assign(q + i * d, q + (i + 1) * d);
+  }
+  const uint64_t t = srv->enqueue(reqs);
+  if (first_ticket) *first_ticket = t;
+  SRV_END
+}
+
+int quake_server_insert(quake_server* srv, const float* x, const int64_t* ids, int64_t n, uint64_t* ticket) {
+  SRV_BEGIN
+  QK_CHECK(srv && n >= 0 && (n == 0 || (x && ids)), QUAKE_E_INVALID, "bad arguments");
+  std::vector<Request> r(1);
+  r[0].kind = 1;
+  r[0].x.assign(x, x + n * srv->idx->d);
+  r[0].ids.assign(ids, ids + n);
+  const uint64_t t = srv->enqueue(r);
+  if (ticket) *ticket = t;
+  SRV_END
+}
+
+int quake_server_delete(quake_server* srv, const int64_t* ids, int64_t n, uint64_t* ticket) {
+  SRV_BEGIN
+  QK_CHECK(srv && n >= 0 && (n == 0 || ids), QUAKE_E_INVALID, "bad arguments");
+  std::vector<Request> r(1);
+  r[0].kind = 2;
+  r[0].ids.assign(ids, ids + n);
+  const uint64_t t = srv->enqueue(r);
+  if (ticket) *ticket = t;
+  SRV_END
+}
+
+int quake_server_wait(quake_server* srv, uint64_t ticket, double timeout_s, int64_t* ids, float* dist,
+                      int32_t* nscanned, int32_t* status) {
+  SRV_BEGIN
+  QK_CHECK(srv, QUAKE_E_INVALID, "server is NULL");
+  std::unique_lock<std::mutex> lk(srv->mu);
+  auto it = srv->answers.find(ticket);
+  QK_CHECK(it != srv->answers.end(), QUAKE_E_INVALID, "unknown or already collected ticket");
+  auto ready = [&] { return srv->answers[ticket].ready; };
+  if (timeout_s < 0) {
+    srv->cv_done.wait(lk, ready);
+  } else if (!srv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) {
+    return fail_rc(QUAKE_E_STATE, "timed out");
+  }
+  Answer an = std::move(srv->answers[ticket]);
+  srv->answers.erase(ticket);
+  lk.unlock();
+  if (status) *status = an.status;
+  if (nscanned) *nscanned = an.nscanned;
+  if (ids && !an.ids.empty()) std::memcpy(ids, an.ids.data(), an.ids.size() * sizeof(int64_t));
+  if (dist && !an.dist.empty()) std::memcpy(dist, an.dist.data(), an.dist.size() * sizeof(float));
+  SRV_END
+}
+
+int quake_server_stats(quake_server* srv, quake_server_report* out, int32_t reset) {
+  SRV_BEGIN
+  QK_CHECK(srv && out, QUAKE_E_INVALID, "bad arguments");
+  std::lock_guard<std::mutex> lk(srv->mu);
+  std::memset(out, 0, sizeof(*out));
+  out->completed = srv->completed;
+  out->queued = (int64_t)srv->fifo.size();
+  out->in_flight = srv->active;
+  out->slots = srv->cap;
+  out->max_in_flight = srv->max_active;
+  out->epochs = srv->epochs;
+  out->rounds = srv->rounds;
+  if (!srv->lat.empty()) {
+    std::vector<double> l(srv->lat);
+    std::sort(l.begin(), l.end());
+    auto pct = [&](double f) { return l[std::min<size_t>(l.size() - 1, (size_t)(f * (l.size() - 1) + 0.5))]; };
+    out->p50_latency_s = pct(0.50);
+    out->p99_latency_s = pct(0.99);
+    double sum = 0;
+    for (double v : l) sum += v;
+    out->mean_latency_s = sum / l.size();
+    if (srv->last_done > srv->first_arrive) out->qps = srv->completed / (srv->last_done - srv->first_arrive);
+  }
+  if (reset) {
+    srv->lat.clear();
+    srv->completed = 0;
+    srv->max_active = srv->active;
+    srv->rounds = 0;
+    srv->first_arrive = -1;
+  }
+  SRV_END
+}
+
+void quake_server_destroy(quake_server* srv) {
+  if (!srv) return;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stop = true;
+  }
+  srv->cv_work.notify_all();
+  if (srv->worker.joinable()) srv->worker.join();
+  srv->release_buffers();
+  delete srv;
+}
+
+}  // extern "C"

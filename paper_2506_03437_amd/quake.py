@@ -28,7 +28,8 @@ _MODE = {"plain": SCAN_PLAIN, "batched": SCAN_BATCHED}
 
 EXPORTED = ("quake_build", "quake_search", "quake_insert", "quake_delete", "quake_stats", "quake_export",
             "quake_export_top", "quake_candidates", "quake_cap_table", "quake_profile", "quake_set_tuning",
-            "quake_free", "quake_last_error")
+            "quake_free", "quake_last_error", "quake_server_create", "quake_server_search", "quake_server_insert",
+            "quake_server_delete", "quake_server_wait", "quake_server_stats", "quake_server_destroy")
 PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "unused6", "unused7")
 
 
@@ -55,6 +56,18 @@ class SearchParams(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk_tiles", ctypes.c_int32), ("first_window", ctypes.c_int32), ("max_window", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("max_items", ctypes.c_int64)]
+
+
+class ServerParams(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("reserved", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("search", SearchParams)]
+
+
+class ServerReport(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("queued", ctypes.c_int64), ("in_flight", ctypes.c_int64),
+                ("slots", ctypes.c_int64), ("max_in_flight", ctypes.c_int64), ("epochs", ctypes.c_int64),
+                ("rounds", ctypes.c_int64), ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
+                ("mean_latency_s", ctypes.c_double), ("qps", ctypes.c_double)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -85,11 +98,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.quake_cap_table.argtypes = [i32, ctypes.POINTER(f64)]
     lib.quake_profile.argtypes = [vp, i32, i32, vp]
     lib.quake_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.quake_server_create.argtypes = [vp, ctypes.POINTER(ServerParams), ctypes.POINTER(vp)]
+    lib.quake_server_search.argtypes = [vp, vp, i64, u64p]
+    lib.quake_server_insert.argtypes = [vp, vp, vp, i64, u64p]
+    lib.quake_server_delete.argtypes = [vp, vp, i64, u64p]
+    lib.quake_server_wait.argtypes = [vp, ctypes.c_uint64, f64, vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.quake_server_stats.argtypes = [vp, ctypes.POINTER(ServerReport), i32]
+    lib.quake_server_destroy.argtypes = [vp]
+    lib.quake_server_destroy.restype = None
     lib.quake_free.argtypes = [vp]
     lib.quake_free.restype = None
     lib.quake_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("quake_free", "quake_last_error"):
+        if name not in ("quake_free", "quake_last_error", "quake_server_destroy"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -138,6 +160,12 @@ def quake_build(x, ids=None, *, metric="l2", nlist=256, storage="f32", n_levels=
     return h.value
 
 
+def _search_params(k=10, nprobe=0, recall_target=0.0, f_M=0.0, tau_rho=0.0, upper_recall_target=0.0,
+                   upper_f_M=0.0, scan_mode="plain", scan_dtype="f32", rerank_factor=0, window=0) -> SearchParams:
+    return SearchParams(k, nprobe, recall_target, f_M, tau_rho, upper_recall_target, upper_f_M, _MODE[scan_mode],
+                        _DTYPE[scan_dtype], rerank_factor, window)
+
+
 def quake_search(handle: int, q, *, k=10, nprobe=0, recall_target=0.0, f_M=0.0, tau_rho=0.0,
                  upper_recall_target=0.0, upper_f_M=0.0, scan_mode="plain", scan_dtype="f32", rerank_factor=0,
                  window=0, outputs=None):
@@ -152,8 +180,8 @@ def quake_search(handle: int, q, *, k=10, nprobe=0, recall_target=0.0, f_M=0.0, 
                    torch.empty((nq,), dtype=torch.int32, device=dev),
                    torch.empty((nq,), dtype=torch.float64, device=dev))
     ids, dist, ns, rec = outputs
-    p = SearchParams(k, nprobe, recall_target, f_M, tau_rho, upper_recall_target, upper_f_M, _MODE[scan_mode],
-                     _DTYPE[scan_dtype], rerank_factor, window)
+    p = _search_params(k, nprobe, recall_target, f_M, tau_rho, upper_recall_target, upper_f_M, scan_mode, scan_dtype,
+                       rerank_factor, window)
     _check(load_library().quake_search(handle, _ptr(q), nq, ctypes.byref(p), _ptr(ids), _ptr(dist), _ptr(ns),
                                        _ptr(rec), _stream()))
     return ids, dist, ns, rec
@@ -229,6 +257,107 @@ def quake_set_tuning(handle: int, chunk_tiles=0, first_window=0, max_window=0, m
 def quake_free(handle: int):
     if handle:
         load_library().quake_free(handle)
+
+
+def _host(a, dtype, ndim):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    assert a.ndim == ndim, f"need a {ndim}-d host array"
+    return a
+
+
+def quake_server_create(handle: int, *, max_slots=0, hbm_budget_bytes=0, **search_kw) -> int:
+    """Start a serving loop on an index; search_kw as for quake_search."""
+    p = ServerParams(max_slots, 0, hbm_budget_bytes, _search_params(**search_kw))
+    h = ctypes.c_void_p()
+    _check(load_library().quake_server_create(handle, ctypes.byref(p), ctypes.byref(h)))
+    return h.value
+
+
+def quake_server_search(server: int, q) -> int:
+    """Queue the rows of q (host float32 [n, d]); returns the first ticket (tickets are consecutive)."""
+    q = _host(q, np.float32, 2)
+    t = ctypes.c_uint64()
+    _check(load_library().quake_server_search(server, q.ctypes.data, q.shape[0], ctypes.byref(t)))
+    return t.value
+
+
+def quake_server_insert(server: int, x, ids) -> int:
+    x = _host(x, np.float32, 2)
+    ids = _host(ids, np.int64, 1)
+    t = ctypes.c_uint64()
+    _check(load_library().quake_server_insert(server, x.ctypes.data, ids.ctypes.data, ids.shape[0], ctypes.byref(t)))
+    return t.value
+
+
+def quake_server_delete(server: int, ids) -> int:
+    ids = _host(ids, np.int64, 1)
+    t = ctypes.c_uint64()
+    _check(load_library().quake_server_delete(server, ids.ctypes.data, ids.shape[0], ctypes.byref(t)))
+    return t.value
+
+
+def quake_server_wait(server: int, ticket: int, k: int, timeout_s: float = -1.0):
+    """(ids int64 [k], dist f32 [k], nscanned, status) of a finished ticket (host numpy)."""
+    ids = np.full(k, -1, dtype=np.int64)
+    dist = np.full(k, np.inf, dtype=np.float32)
+    ns, st = ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().quake_server_wait(server, ticket, timeout_s, ids.ctypes.data, dist.ctypes.data,
+                                            ctypes.byref(ns), ctypes.byref(st)))
+    return ids, dist, ns.value, st.value
+
+
+def quake_server_stats(server: int, reset: bool = False) -> dict:
+    r = ServerReport()
+    _check(load_library().quake_server_stats(server, ctypes.byref(r), int(reset)))
+    return {name: getattr(r, name) for name, _ in ServerReport._fields_}
+
+
+def quake_server_destroy(server: int):
+    if server:
+        load_library().quake_server_destroy(server)
+
+
+class Server:
+    """Owning wrapper around a quake_server handle (continuous batching over an Index)."""
+
+    def __init__(self, index: "Index", **kw):
+        self.k = kw.get("k", 10)
+        self.index = index
+        self.handle = quake_server_create(index.handle, **kw)
+
+    def search(self, q) -> list:
+        q = _host(q, np.float32, 2)
+        first = quake_server_search(self.handle, q)
+        return list(range(first, first + q.shape[0]))
+
+    def insert(self, x, ids) -> int:
+        return quake_server_insert(self.handle, x, ids)
+
+    def delete(self, ids) -> int:
+        return quake_server_delete(self.handle, ids)
+
+    def wait(self, ticket: int, timeout_s: float = -1.0):
+        return quake_server_wait(self.handle, ticket, self.k, timeout_s)
+
+    def stats(self, reset=False):
+        return quake_server_stats(self.handle, reset)
+
+    def close(self):
+        quake_server_destroy(self.handle)
+        self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                self.close()
+        except Exception:
+            pass
 
 
 class Index:

@@ -64,3 +64,11 @@ def test_host_side_argument_errors():
     assert lib.quake_insert(None, None, None, 1, None) == quake.E_STATE
     assert lib.quake_delete(None, None, 1, None) == quake.E_STATE
     assert lib.quake_cap_table(0, (ctypes.c_double * 1024)()) == quake.E_INVALID
+    srv = ctypes.c_void_p()
+    spp = quake.ServerParams(8, 0, 0, sp)
+    assert lib.quake_server_create(None, ctypes.byref(spp), ctypes.byref(srv)) == quake.E_STATE
+    assert srv.value is None
+    assert lib.quake_server_create(None, None, ctypes.byref(srv)) == quake.E_INVALID
+    assert lib.quake_server_search(None, None, 1, None) == quake.E_INVALID
+    assert lib.quake_server_wait(None, 1, 0.0, None, None, None, None) == quake.E_INVALID
+    lib.quake_server_destroy(None)
