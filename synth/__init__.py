@@ -16,4 +16,5 @@ from .mixture import (  # noqa: F401
     queries,
     leaf_spec_database,
 )
+from .trace import TraceSpec, serving_trace  # noqa: F401
 from .workloads import WORKLOADS, Workload, get_workload  # noqa: F401

@@ -15,6 +15,8 @@ Tolerances (derived from the FP32 arithmetic of the device path):
 
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from oracle import knn
@@ -78,3 +80,73 @@ def check_all(Q, X, ids, gpu_ids, gpu_vals, ref_ids, ref_vals, metric, k):
         except AssertionError as e:
             bad.append(str(e))
     assert not bad, f"{len(bad)} of {Q.shape[0]} queries differ; first: {bad[:3]}"
+
+
+def check_candidate_order(q, C, f_M, metric, order, h_gpu):
+    """The device order is a valid APS order for the oracle, up to near-ties."""
+    from oracle import aps as oaps
+    o_ref, h_ref = oaps.aps_order(q, C, f_M, metric)
+    vals = knn.distances(q[None], C, metric)[0]
+    key = knn.sort_key(vals, metric)
+    scale = abs(key[o_ref[0]]) if metric == "l2" else float(np.linalg.norm(q)) * float(np.linalg.norm(C, axis=1).max())
+    tol = 1e-5 * max(scale, 1e-30) + 1e-6
+    # same candidate set except near-ties at the M-th place
+    if set(order.tolist()) != set(o_ref.tolist()):
+        ks = np.sort(key)
+        M = o_ref.shape[0]
+        assert M < key.shape[0] and abs(ks[M] - ks[M - 1]) <= tol, "candidate set differs"
+        return False
+    if order[0] != o_ref[0]:
+        assert abs(key[order[0]] - key[o_ref[0]]) <= tol, "c0 differs"
+        return False
+    h_of = oaps.bisector_distances(q, C, vals, int(order[0]), order[1:].astype(np.int64), metric)
+    # non-decreasing in the oracle's h, up to FP32 rounding of h
+    htol = 1e-4 * max(float(np.abs(h_of).max(initial=0.0)), 1e-6)
+    assert (np.diff(h_of) >= -htol).all(), "device order is not ascending in h"
+    np.testing.assert_allclose(h_gpu[1:], h_of, atol=htol)
+    return True
+
+
+def replay_margin(res, tau_r, tau_rho, upto):
+    """True when a stop or recompute decision up to step `upto` is too close to call."""
+    for st in res.steps[:upto]:
+        if abs(st.recall - tau_r) < 1e-4:
+            return True
+        if math.isfinite(st.recompute_gap) and abs(st.recompute_gap) < 1e-5 * max(st.rho, 1e-30):
+            return True
+    return False
+
+
+def check_aps(X, Q, ps, gi, gv, ns, rec, order, h, metric, f_M, tau_r, k=10, rows=None):
+    """Adaptive-scan parity for the queries `rows` (default all) of a device
+    search: the results are the top-k over the partitions the device
+    scanned, the candidate order is a valid APS order, and the stop count
+    and recall estimate replay the oracle's, except decisions within the
+    margins (at most 1% of the queries)."""
+    from oracle import aps as oaps
+    from oracle import ivf as oivf
+    rows = np.arange(Q.shape[0]) if rows is None else np.asarray(rows)
+    table = oaps.CapTable(X.shape[1])
+    params = oaps.APSParams(k=k, recall_target=tau_r, f_M=f_M, metric=metric)
+    id_to_row = {int(i): r for r, i in enumerate(ps.ids.tolist())}
+    margin = 0
+    ordered = 0
+    for j, i in enumerate(rows.tolist()):
+        m = int(ns[i])
+        assert 1 <= m <= order.shape[1]
+        # results: exactly the top-k over the partitions the device scanned
+        ri, rv = oivf.scan_partitions(ps, Q[i], order[j, :m], k, metric)
+        check_topk(Q[i], X, id_to_row, gi[i], gv[i], ri, rv, metric, k, f"query {i}")
+        if not check_candidate_order(Q[i], ps.C, f_M, metric, order[j], h[j]):
+            continue
+        ordered += 1
+        vals = knn.distances(Q[i][None], ps.C, metric)[0]
+        h_ref = oaps.bisector_distances(Q[i], ps.C, vals, int(order[j, 0]), order[j, 1:].astype(np.int64), metric)
+        res = oaps.aps_search_one(ps, Q[i], params, table, order=order[j].astype(np.int64), h=h_ref)
+        if res.m != m:
+            assert replay_margin(res, tau_r, 0.01, max(res.m, m)), f"query {i}: device scanned {m}, oracle {res.m}"
+            margin += 1
+        else:
+            assert abs(rec[i] - res.steps[-1].recall) < 1e-4, f"query {i}: recall estimate {rec[i]} vs {res.steps[-1].recall}"
+    assert ordered >= 0.98 * rows.size
+    assert margin <= 0.01 * rows.size, f"{margin} queries decided within the margin"

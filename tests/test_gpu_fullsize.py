@@ -1,0 +1,89 @@
+"""Parity at full size: the 1M x 768 inner-product workload (1,000 k-means
+partitions with power-law sizes, BF16 copy beside FP32), one search call
+over all 10,000 queries, in the launch configuration the throughput
+benchmark times.  Outputs are checked on a seeded sample of query rows that
+the oracle replays one by one over the device index's own partitioning.
+
+* Plain FP32 adaptive scan: results are the top-k over the scanned
+  partitions, the candidate order and the stop counts replay the oracle's.
+* Batched BF16 scan with FP32 rerank: every reported distance is the FP32
+  distance of that id (1e-5), ids come from the scanned partitions, and
+  recall@10 against exact FP64 ground truth stays within 0.005 of the plain
+  path at the same target.
+"""
+
+import numpy as np
+import pytest
+
+import gpu_util as gu
+import parity
+import synth
+from oracle import ivf as oivf
+from oracle import knn as oknn
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+SAMPLE = 40
+TRUTH_SAMPLE = 300
+
+
+@pytest.fixture(scope="module")
+def full():
+    w = synth.get_workload("batched-1m-d768-ip")
+    X = synth.database(w.spec)
+    Q = synth.queries(w.spec, w.nq, noise_std=w.query_noise)
+    print(f"[build] {w.name} n={X.shape[0]} d={X.shape[1]} nlist={w.nlist} storage={w.storage}", flush=True)
+    idx = gu.build(X, metric=w.metric, nlist=w.nlist, storage=w.storage, kmeans_iters=10, seed=1)
+    ps = gu.oracle_view(idx, X)
+    rng = np.random.default_rng(2506)
+    rows = np.sort(rng.choice(w.nq, SAMPLE, replace=False))
+    truth_rows = np.sort(rng.choice(w.nq, TRUTH_SAMPLE, replace=False))
+    truth, _ = oknn.knn_exact(X, np.arange(X.shape[0]), Q[truth_rows], w.k, w.metric)
+    yield w, X, Q, idx, ps, rows, truth_rows, truth
+    idx.free()
+
+
+def _recall(gi, rows, truth, k):
+    return float(oknn.recall_at_k(gi[rows], truth, k).mean())
+
+
+@pytest.mark.parametrize("tau", [0.9, 0.96])
+def test_plain_fp32_full_size(full, tau):
+    w, X, Q, idx, ps, rows, truth_rows, truth = full
+    gi, gv, ns, rec = gu.search(idx, Q, k=w.k, recall_target=tau, f_M=w.f_M)
+    order, h = idx.candidates(gu.to_dev(Q[rows]), w.f_M)
+    parity.check_aps(X, Q, ps, gi, gv, ns, rec, order.cpu().numpy(), h.cpu().numpy(), w.metric, w.f_M, tau,
+                     w.k, rows=rows)
+    print(f"[plain] tau {tau}: recall@10 {_recall(gi, truth_rows, truth, w.k):.4f}, "
+          f"partitions {ns.mean():.2f}", flush=True)
+
+
+@pytest.mark.parametrize("tau", [0.9, 0.96])
+def test_batched_bf16_full_size(full, tau):
+    w, X, Q, idx, ps, rows, truth_rows, truth = full
+    kw = dict(k=w.k, recall_target=tau, f_M=w.f_M)
+    pi, pv, pns, _ = gu.search(idx, Q, **kw)
+    gi, gv, ns, rec = gu.search(idx, Q, scan_mode="batched", scan_dtype=w.storage, rerank_factor=4, **kw)
+    order, _ = idx.candidates(gu.to_dev(Q[rows]), w.f_M)
+    order = order.cpu().numpy()
+    id_to_row = {int(i): r for r, i in enumerate(ps.ids.tolist())}
+    part_of = np.empty(X.shape[0], dtype=np.int64)
+    part_of[ps.ids] = ps.assign
+    for j, i in enumerate(rows.tolist()):
+        live = gi[i][gi[i] >= 0]
+        assert live.size == w.k and len(set(live.tolist())) == w.k
+        tv = parity.true_values(Q[i], X, id_to_row, live, w.metric)
+        tol = parity.value_tol(Q[i], X, w.metric, tv)
+        assert (np.abs(gv[i].astype(np.float64) - tv) <= tol).all(), f"query {i}: reranked distance not FP32-exact"
+        assert (np.diff(-gv[i]) >= 0).all(), f"query {i}: not sorted"
+        scanned = set(order[j, :int(ns[i])].tolist())
+        assert set(part_of[live].tolist()) <= scanned, f"query {i}: id from an unscanned partition"
+        # the exact best over the scanned partitions survives the BF16 ranking (40 candidates kept)
+        ri, rv = oivf.scan_partitions(ps, Q[i], order[j, :int(ns[i])], w.k, w.metric)
+        btol = float(parity.value_tol(Q[i], X, w.metric, rv[:1])[0])
+        assert gi[i][0] == ri[0] or abs(rv[0] - rv[1]) <= btol, f"query {i}: lost the exact best {ri[0]}"
+    rp = _recall(pi, truth_rows, truth, w.k)
+    rb = _recall(gi, truth_rows, truth, w.k)
+    print(f"[batched] tau {tau}: recall@10 plain {rp:.4f} batched {rb:.4f}, partitions plain {pns.mean():.2f} "
+          f"batched {ns.mean():.2f}", flush=True)
+    assert rb >= rp - 0.005

@@ -7,15 +7,12 @@ near-empty partitions, fewer than k reachable results, exact ties, nq = 0;
 nprobe = nlist against exact search; batch-composition independence.
 """
 
-import math
-
 import numpy as np
 import pytest
 
 import gpu_util as gu
 import parity
 import synth
-from oracle import aps as oaps
 from oracle import ivf as oivf
 from oracle import knn as oknn
 
@@ -86,69 +83,10 @@ def test_all_partitions_equals_exact_search(small_l2):
     parity.check_all(Qs, X, ps.ids, gi, gv, ei, ev, "l2", 10)
 
 
-def _check_candidate_order(q, C, f_M, metric, order, h_gpu):
-    """The device order is a valid APS order for the oracle, up to near-ties."""
-    o_ref, h_ref = oaps.aps_order(q, C, f_M, metric)
-    vals = oknn.distances(q[None], C, metric)[0]
-    key = oknn.sort_key(vals, metric)
-    scale = abs(key[o_ref[0]]) if metric == "l2" else float(np.linalg.norm(q)) * float(np.linalg.norm(C, axis=1).max())
-    tol = 1e-5 * max(scale, 1e-30) + 1e-6
-    # same candidate set except near-ties at the M-th place
-    if set(order.tolist()) != set(o_ref.tolist()):
-        ks = np.sort(key)
-        M = o_ref.shape[0]
-        assert M < key.shape[0] and abs(ks[M] - ks[M - 1]) <= tol, "candidate set differs"
-        return False
-    if order[0] != o_ref[0]:
-        assert abs(key[order[0]] - key[o_ref[0]]) <= tol, "c0 differs"
-        return False
-    h_of = oaps.bisector_distances(q, C, vals, int(order[0]), order[1:].astype(np.int64), metric)
-    # non-decreasing in the oracle's h, up to FP32 rounding of h
-    htol = 1e-4 * max(float(np.abs(h_of).max(initial=0.0)), 1e-6)
-    assert (np.diff(h_of) >= -htol).all(), "device order is not ascending in h"
-    np.testing.assert_allclose(h_gpu[1:], h_of, atol=htol)
-    return True
-
-
-def _replay_margin(res, tau_r, tau_rho, upto):
-    """True when a stop or recompute decision up to step `upto` is too close to call."""
-    for st in res.steps[:upto]:
-        if abs(st.recall - tau_r) < 1e-4:
-            return True
-        if math.isfinite(st.recompute_gap) and abs(st.recompute_gap) < 1e-5 * max(st.rho, 1e-30):
-            return True
-    return False
-
-
 def _aps_parity(X, Q, idx, ps, metric, f_M, tau_r, k=10):
     gi, gv, ns, rec = gu.search(idx, Q, k=k, recall_target=tau_r, f_M=f_M)
     order, h = idx.candidates(gu.to_dev(Q), f_M)
-    order = order.cpu().numpy()
-    h = h.cpu().numpy()
-    table = oaps.CapTable(X.shape[1])
-    params = oaps.APSParams(k=k, recall_target=tau_r, f_M=f_M, metric=metric)
-    id_to_row = {int(i): r for r, i in enumerate(ps.ids.tolist())}
-    margin = 0
-    ordered = 0
-    for i in range(Q.shape[0]):
-        m = int(ns[i])
-        assert 1 <= m <= order.shape[1]
-        # results: exactly the top-k over the partitions the device scanned
-        ri, rv = oivf.scan_partitions(ps, Q[i], order[i, :m], k, metric)
-        parity.check_topk(Q[i], X, id_to_row, gi[i], gv[i], ri, rv, metric, k, f"query {i}")
-        if not _check_candidate_order(Q[i], ps.C, f_M, metric, order[i], h[i]):
-            continue
-        ordered += 1
-        vals = oknn.distances(Q[i][None], ps.C, metric)[0]
-        h_ref = oaps.bisector_distances(Q[i], ps.C, vals, int(order[i, 0]), order[i, 1:].astype(np.int64), metric)
-        res = oaps.aps_search_one(ps, Q[i], params, table, order=order[i].astype(np.int64), h=h_ref)
-        if res.m != m:
-            assert _replay_margin(res, tau_r, 0.01, max(res.m, m)), f"query {i}: device scanned {m}, oracle {res.m}"
-            margin += 1
-        else:
-            assert abs(rec[i] - res.steps[-1].recall) < 1e-4, f"query {i}: recall estimate {rec[i]} vs {res.steps[-1].recall}"
-    assert ordered >= 0.98 * Q.shape[0]
-    assert margin <= 0.01 * Q.shape[0], f"{margin} queries decided within the margin"
+    parity.check_aps(X, Q, ps, gi, gv, ns, rec, order.cpu().numpy(), h.cpu().numpy(), metric, f_M, tau_r, k)
     return gi, ns
 
 
