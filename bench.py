@@ -81,6 +81,92 @@ def cpu_baseline_leg(X, Q, sample_rows, idx, workload, seconds):
     return base, truth
 
 
+def serving_leg(idx, w, X, tau, rates, n_requests, hbm_budget):
+    """Continuous batching through the serving loop on the same index: a
+    trace of single-query requests (Zipf(1.2) over the mixture components,
+    popular set re-drawn every 10,000 requests) with a 1% insert batch and a
+    1% delete batch after every 10,000 queries.  Each offered rate replays the
+    trace open-loop with Poisson arrivals; the closed-loop run submits it all
+    at once (the sustained rate).  Latency = arrival (enqueue) to answer ready.
+    Updates are undone between runs so every run starts from the same index."""
+    import numpy as np
+    import synth
+    from paper_2506_03437_amd import Server
+
+    n_live = X.shape[0]
+    ts = synth.TraceSpec(n_requests=n_requests, drift_every=10_000, update_every=10_000, update_frac=0.01,
+                         new_components=10)
+    events = synth.serving_trace(w.spec, np.arange(n_live, dtype=np.int64), ts)
+    kw = dict(k=w.k, recall_target=tau, f_M=w.f_M, scan_mode="batched", scan_dtype=w.storage, rerank_factor=4)
+
+    def replay(rate):
+        rng = np.random.default_rng(11)
+        inserted, deleted = [], []
+        with Server(idx, hbm_budget_bytes=hbm_budget, **kw) as srv:
+            slots = srv.stats()["slots"]
+            tickets, upd = [], []
+            t0 = time.perf_counter()
+            t_next = 0.0
+            for ev in events:
+                if ev[0] == "search":
+                    Qb = ev[1]
+                    if rate is None:
+                        tickets += srv.search(Qb)
+                        continue
+                    arr = t_next + np.cumsum(rng.exponential(1.0 / rate, Qb.shape[0]))
+                    t_next = float(arr[-1])
+                    i = 0
+                    while i < Qb.shape[0]:
+                        now = time.perf_counter() - t0
+                        j = int(np.searchsorted(arr, now, side="right"))
+                        if j > i:
+                            tickets += srv.search(Qb[i:j])
+                            i = j
+                elif ev[0] == "insert":
+                    upd.append(srv.insert(ev[1], ev[2]))
+                    inserted.append(ev[2])
+                else:
+                    upd.append(srv.delete(ev[1]))
+                    deleted.append(ev[1])
+            for t in tickets:
+                srv.wait(t, 120.0)
+            statuses = [srv.wait(t, 120.0)[3] for t in upd]
+            st = srv.stats()
+        assert all(x == 0 for x in statuses), f"update batches failed: {statuses}"
+        # undo the updates: remove what was inserted and is still live, restore what was deleted
+        import torch
+        dev = torch.device("cuda", 0)
+        ins = np.concatenate(inserted) if inserted else np.zeros(0, np.int64)
+        dels = np.concatenate(deleted) if deleted else np.zeros(0, np.int64)
+        still = np.setdiff1d(ins, dels)
+        if still.size:
+            idx.delete(torch.from_numpy(still).to(dev))
+        back = dels[dels < n_live]
+        if back.size:
+            Xb = np.ascontiguousarray(X[back])
+            idx.insert(torch.from_numpy(Xb).to(dev), torch.from_numpy(back).to(dev))
+        torch.cuda.synchronize()
+        assert idx.stats()[0] == n_live
+        return {"offered_qps": rate, "achieved_qps": st["qps"], "p50_ms": st["p50_latency_s"] * 1e3,
+                "p99_ms": st["p99_latency_s"] * 1e3, "mean_ms": st["mean_latency_s"] * 1e3,
+                "completed": st["completed"], "slots": slots, "max_in_flight": st["max_in_flight"],
+                "rounds": st["rounds"], "update_batches": len(statuses)}
+
+    out = {"trace": f"{n_requests} single-query requests, Zipf(1.2) components drifting every 10,000, "
+                    f"1% insert + 1% delete batch every 10,000 queries", "hbm_budget_bytes": hbm_budget,
+           "recall_target": tau, "runs": []}
+    closed = replay(None)
+    out["sustained"] = closed
+    log(f"serving closed-loop: {closed['achieved_qps']:.0f} QPS, p50 {closed['p50_ms']:.2f} ms, "
+        f"p99 {closed['p99_ms']:.2f} ms, slots {closed['slots']}")
+    for r in rates:
+        res = replay(r)
+        out["runs"].append(res)
+        log(f"serving at {r:.0f} QPS offered: {res['achieved_qps']:.0f} QPS, p50 {res['p50_ms']:.2f} ms, "
+            f"p99 {res['p99_ms']:.2f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +177,11 @@ def main():
     ap.add_argument("--recall-sample", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recall-target", type=float, default=0.0, help="skip the sweep and use this target")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy a BYTES-long device buffer 5 times (calibrates HBM byte counters) and exit")
+    ap.add_argument("--serving-requests", type=int, default=40_000, help="0 skips the serving-loop leg")
+    ap.add_argument("--serving-rates", default="20000,100000,400000")
+    ap.add_argument("--serving-hbm-budget", type=int, default=256 << 20)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -99,6 +190,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        dev = torch.device("cuda", 0)
+        src = torch.ones(args.copy_calibration // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4, "copies": 5}), flush=True)
+        return
 
     import synth
     from paper_2506_03437_amd import Index
@@ -184,6 +285,11 @@ def main():
 
     plain = measure("plain_fp32")
     batched = measure("batched_bf16")
+    serving = None
+    if args.serving_requests > 0:
+        rates = [float(r) for r in args.serving_rates.split(",") if r]
+        serving = serving_leg(idx, w, X, batched["recall_target"], rates, args.serving_requests,
+                              args.serving_hbm_budget)
     fb = batched["scan_gbs"] / HBM_PEAK_GBS
     ff = batched["scan_tflops"] / MFMA_BF16_PEAK_TFLOPS
     if ff >= fb:
@@ -219,6 +325,7 @@ def main():
         "roofline": roof,
         "batched_bf16": batched,
         "plain_fp32": plain,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
