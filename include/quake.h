@@ -151,8 +151,10 @@ typedef struct {
   int32_t chunk_tiles;   /* store tiles (64 vectors each) per work item; default 16 */
   int32_t first_window;  /* APS: partitions per query in the first round; default 2 */
   int32_t max_window;    /* APS: most partitions per query in one round; default 32 */
-  int32_t reserved;
+  int32_t blocks_per_cu; /* persistent scan grid, blocks of 4 waves per compute unit; default 2 (MFMA) / 8 (FP32) */
   int64_t max_items;     /* work items per round (bounds the scratch memory); default from nq */
+  int32_t rounds_per_sync; /* rounds enqueued between host checks for completion; default 1, 2, 4, then 8 */
+  int32_t no_graph;      /* 1: launch every round's kernels; default 0 replays captured HIP graphs of rounds */
 } quake_tuning;
 int quake_set_tuning(quake_index* index, const quake_tuning* tuning);
 

@@ -192,25 +192,32 @@ void kmeans(qk::DeviceMemory& mem, const float* xpad, int64_t n, int dp, int64_t
     nt = max_train;
   }
   gather(train, pick_distinct(nt, nc), centroids);
-  Tmp<float> sums(mem, (size_t)nc * dp);
+  Tmp<int64_t> sums(mem, (size_t)nc * dp);
   Tmp<int32_t> counts(mem, (size_t)nc);
   Tmp<int32_t> assign(mem, (size_t)nt);
   std::vector<int32_t> h_counts(nc);
   const int normalise = metric == QUAKE_IP ? 1 : 0;
-  if (normalise) {
-    // unit initial centroids: sums = centroids, counts = 1, update
-    QK_HIP(hipMemcpyAsync(sums.p, centroids, (size_t)nc * dp * sizeof(float), hipMemcpyDeviceToDevice, s));
-    std::vector<int32_t> ones(nc, 1);
-    QK_HIP(hipMemcpyAsync(counts.p, ones.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    qk::launch_kmeans_update(sums.p, counts.p, nc, dp, 1, centroids, s);
+  if (normalise) qk::launch_normalise_rows(centroids, nc, dp, s);
+  // fixed-point scale of the cluster sums: n * max|x| * 2^bits stays below 2^62
+  int frac_bits = 40;
+  {
+    Tmp<uint32_t> amax(mem, 1);
+    QK_HIP(hipMemsetAsync(amax.p, 0, sizeof(uint32_t), s));
+    qk::launch_absmax(train, nt * dp, amax.p, s);
+    uint32_t bits = 0;
+    QK_HIP(hipMemcpyAsync(&bits, amax.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     QK_HIP(hipStreamSynchronize(s));
+    float m;
+    std::memcpy(&m, &bits, sizeof(m));
+    if (m > 0.f) frac_bits = (int)std::floor(62.0 - std::log2((double)nt * (double)m)) - 1;
+    frac_bits = std::max(-60, std::min(frac_bits, 60));
   }
   for (int it = 0; it < iters; ++it) {
     qk::launch_assign(train, nt, dp, centroids, nc, metric, assign.p, s);
-    QK_HIP(hipMemsetAsync(sums.p, 0, (size_t)nc * dp * sizeof(float), s));
+    QK_HIP(hipMemsetAsync(sums.p, 0, (size_t)nc * dp * sizeof(int64_t), s));
     QK_HIP(hipMemsetAsync(counts.p, 0, (size_t)nc * sizeof(int32_t), s));
-    qk::launch_kmeans_accumulate(train, nt, dp, assign.p, sums.p, counts.p, s);
-    qk::launch_kmeans_update(sums.p, counts.p, nc, dp, normalise, centroids, s);
+    qk::launch_kmeans_accumulate(train, nt, dp, assign.p, frac_bits, sums.p, counts.p, s);
+    qk::launch_kmeans_update(sums.p, counts.p, nc, dp, normalise, frac_bits, centroids, s);
     QK_HIP(hipMemcpyAsync(h_counts.data(), counts.p, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     QK_HIP(hipStreamSynchronize(s));
     for (int64_t j = 0; j < nc; ++j) {
@@ -548,6 +555,112 @@ void ensure_workspace(quake_index* idx, int64_t nc, int64_t M, int64_t kk, int64
   }
 }
 
+int scan_blocks(quake_index* idx, int batched) {
+  if (idx->cu_count == 0) {
+    int dev = 0;
+    QK_HIP(hipGetDevice(&dev));
+    QK_HIP(hipDeviceGetAttribute(&idx->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  const int per = idx->tune.blocks_per_cu > 0 ? idx->tune.blocks_per_cu : (batched ? 2 : 8);
+  return std::max(idx->cu_count, 8) * per;
+}
+
+namespace {
+
+void launch_rounds(quake_index* idx, const Store& st, const Job& job, const RoundArgs& a, int R, hipStream_t s) {
+  Workspace& w = idx->ws;
+  for (int r = 0; r < R; ++r) {
+    if (job.batched) {
+      {
+        ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
+        launch_group(w, st, a, s);
+      }
+      ProfileScope ps(idx->prof, QUAKE_PROF_SCAN, s);
+      launch_scan_mfma(w, st, a, job.dtype16, s);
+    } else {
+      {
+        ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
+        launch_emit(w, st, a, s);
+      }
+      ProfileScope ps(idx->prof, QUAKE_PROF_SCAN, s);
+      launch_scan_f32(w, st, a, s);
+    }
+    {
+      ProfileScope ps(idx->prof, QUAKE_PROF_COMMIT, s);
+      launch_commit(w, st, a, idx->cap_table, s);
+    }
+    ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
+    launch_demand(w, st, a, s);
+  }
+}
+
+std::vector<uint64_t> graph_key(const quake_index* idx, const Store& st, const Job& job, const RoundArgs& a, int R) {
+  const Workspace& w = idx->ws;
+  auto u = [](const void* p) { return (uint64_t)(uintptr_t)p; };
+  std::vector<uint64_t> k = {
+      (uint64_t)R, (uint64_t)job.batched, (uint64_t)job.dtype16, (uint64_t)a.nq, (uint64_t)a.M, (uint64_t)a.k,
+      (uint64_t)a.kk, (uint64_t)a.aps, (uint64_t)a.chunk_tiles, (uint64_t)a.wmax, (uint64_t)a.metric,
+      (uint64_t)a.items_cap, (uint64_t)a.blocks, (uint64_t)st.d, (uint64_t)st.dp, (uint64_t)st.nlist,
+      (uint64_t)st.dp16, u(idx->cap_table), u(st.centroids), u(st.d_off), u(st.d_size), u(st.d_cap), u(st.v32),
+      u(st.v16), u(st.v16n), u(st.rows32), u(st.ids), u(w.q), u(w.qn2), u(w.cand), u(w.mq), u(w.h), u(w.st_m),
+      u(w.st_w), u(w.st_weff), u(w.st_done), u(w.st_item), u(w.st_demand), u(w.st_rho), u(w.st_p0), u(w.st_V),
+      u(w.st_vsum), u(w.st_r), u(w.rk), u(w.ri), u(w.items), u(w.pk), u(w.pi), u(w.st_vecs), u(w.st_pair),
+      u(w.q16), u(w.qn2f), u(w.pair_q), u(w.pair_p), u(w.pair_pos), u(w.pair_base), u(w.sorted), u(w.pcount),
+      u(w.pstart), u(w.pitem), u(w.total)};
+  uint64_t tr, tro;
+  std::memcpy(&tr, &a.tau_r, 8);
+  std::memcpy(&tro, &a.tau_rho, 8);
+  k.push_back(tr);
+  k.push_back(tro);
+  return k;
+}
+
+}  // namespace
+
+void release_graphs(quake_index* idx) {
+  for (auto& g : idx->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  idx->graphs.clear();
+}
+
+// R rounds, replayed from a captured HIP graph when possible (profiling needs
+// events around each kernel class, so it launches directly).  A graph is
+// captured once per distinct set of kernel arguments; the captured rounds
+// contain kernel launches only.
+void run_rounds(quake_index* idx, const Store& st, const Job& job, const RoundArgs& a, int R, hipStream_t s) {
+  if (idx->prof.on || idx->tune.no_graph || idx->graphs_failed) {
+    launch_rounds(idx, st, job, a, R, s);
+    return;
+  }
+  std::vector<uint64_t> key = graph_key(idx, st, job, a, R);
+  hipGraphExec_t exec = nullptr;
+  for (auto& g : idx->graphs)
+    if (g.key == key) { exec = g.exec; break; }
+  if (!exec) {
+    if (!idx->capture_stream) QK_HIP(hipStreamCreateWithFlags(&idx->capture_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    bool ok = hipStreamBeginCapture(idx->capture_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (ok) {
+      launch_rounds(idx, st, job, a, R, idx->capture_stream);
+      ok = hipStreamEndCapture(idx->capture_stream, &graph) == hipSuccess && graph;
+    }
+    if (ok) ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess && exec;
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    if (!ok) {  // capture is an optimisation only: launch directly from now on
+      idx->graphs_failed = true;
+      launch_rounds(idx, st, job, a, R, s);
+      return;
+    }
+    if (idx->graphs.size() >= 16) {
+      (void)hipGraphExecDestroy(idx->graphs.front().exec);
+      idx->graphs.erase(idx->graphs.begin());
+    }
+    idx->graphs.push_back({std::move(key), exec});
+  }
+  QK_HIP(hipGraphLaunch(exec, s));
+}
+
 }  // namespace qk
 
 namespace {
@@ -627,49 +740,26 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
   // a smaller requested cap than the buffer already allocated still applies
   a.items_cap = std::min<int64_t>(w.items_cap, items);
   qk::launch_round_init(w, a, job.w0, s);
-  if (job.batched && idx->cu_count == 0) {
-    int dev = 0;
-    QK_HIP(hipGetDevice(&dev));
-    QK_HIP(hipDeviceGetAttribute(&idx->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+  a.blocks = qk::scan_blocks(idx, job.batched);
+  {
+    qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
+    qk::launch_demand(w, st, a, s);
   }
   // Every round commits at least one partition of the first unfinished
-  // query, so the loop ends within nq * M rounds.
+  // query, so the loop ends within nq * M rounds.  Rounds after the last one
+  // with work find nothing to do.
   const int64_t max_rounds = nq * (int64_t)job.M + 2;
-  for (int64_t round = 0;; ++round) {
-    QK_CHECK(round <= max_rounds, QUAKE_E_DEVICE, "search rounds did not converge");
-    {
-      qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
-      qk::launch_demand(w, st, a, s);
-    }
-    QK_HIP(hipMemcpyAsync(w.h_total, w.total, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  int64_t rounds = 0;
+  int chunk = 1;
+  for (;;) {
+    QK_HIP(hipMemcpyAsync(w.h_total, w.total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     QK_HIP(hipStreamSynchronize(s));
-    const int64_t total = w.h_total[0];
-    const int64_t nvec = w.h_total[1];
-    const int64_t npairs = w.h_total[2];
-    if (total == 0) break;
-    if (job.batched) {
-      {
-        qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
-        qk::launch_group(w, st, a, npairs, s);
-      }
-      qk::ProfileScope ps(idx->prof, QUAKE_PROF_SCAN, s);
-      qk::launch_scan_mfma(w, st, a, job.dtype16, std::max(idx->cu_count, 8) * 2, s);
-    } else {
-      {
-        qk::ProfileScope ps(idx->prof, QUAKE_PROF_PLAN, s);
-        qk::launch_emit(w, st, a, s);
-      }
-      {
-        qk::ProfileScope ps(idx->prof, QUAKE_PROF_SCAN, s);
-        qk::launch_scan_f32(w, st, a, total, s);
-      }
-      idx->prof.add(QUAKE_PROF_SCAN, (double)nvec * idx->d * sizeof(float),
-                    (double)nvec * idx->d * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
-    }
-    {
-      qk::ProfileScope ps(idx->prof, QUAKE_PROF_COMMIT, s);
-      qk::launch_commit(w, st, a, idx->cap_table, s);
-    }
+    if (w.h_total[0] == 0) break;
+    QK_CHECK(rounds <= max_rounds, QUAKE_E_DEVICE, "search rounds did not converge");
+    const int R = idx->tune.rounds_per_sync > 0 ? idx->tune.rounds_per_sync : chunk;
+    qk::run_rounds(idx, st, job, a, R, s);
+    rounds += R;
+    chunk = std::min(chunk * 2, 8);
   }
   if (job.batched) {
     {
@@ -683,11 +773,14 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
     qk::launch_finalize(w, a, out_ids, out_dist, out_nscanned, out_recall, s);
   }
   QK_HIP(hipGetLastError());
-  if (job.batched && idx->prof.on)
-    QK_HIP(hipMemcpyAsync(w.h_total + 4, w.total + 4, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  if (idx->prof.on)
+    QK_HIP(hipMemcpyAsync(w.h_total + 4, w.total + 4, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   QK_HIP(hipStreamSynchronize(s));
-  if (job.batched)
+  if (idx->prof.on && job.batched)
     idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[4] * idx->d * 2.0, (double)w.h_total[5] * idx->d * 2.0);
+  else if (idx->prof.on)
+    idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[6] * idx->d * sizeof(float),
+                  (double)w.h_total[6] * idx->d * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
   idx->prof.collect();
 }
 
@@ -854,7 +947,8 @@ int quake_set_tuning(quake_index* idx, const quake_tuning* t) {
   API_BEGIN
   check_index(idx);
   QK_CHECK(t, QUAKE_E_INVALID, "tuning is NULL");
-  QK_CHECK(t->chunk_tiles >= 0 && t->first_window >= 0 && t->max_window >= 0 && t->max_items >= 0,
+  QK_CHECK(t->chunk_tiles >= 0 && t->first_window >= 0 && t->max_window >= 0 && t->max_items >= 0 &&
+               t->blocks_per_cu >= 0 && t->rounds_per_sync >= 0 && t->no_graph >= 0,
            QUAKE_E_INVALID, "tuning values must be >= 0");
   idx->tune = *t;
   API_END
@@ -1122,6 +1216,8 @@ int quake_export_top(const quake_index* idx, float* top_centroids, int32_t* top_
 
 void quake_free(quake_index* idx) {
   if (!idx || idx->magic != 0x51554b45u) return;
+  qk::release_graphs(idx);
+  if (idx->capture_stream) (void)hipStreamDestroy(idx->capture_stream);
   if (idx->ws.h_total) (void)hipHostFree(idx->ws.h_total);
   idx->magic = 0;
   delete idx;

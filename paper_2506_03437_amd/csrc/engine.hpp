@@ -24,6 +24,15 @@ Job resolve(const quake_index* idx, const Store& st, const quake_search_params* 
 int64_t max_chunks(const Store& st, int chunk_tiles);
 // Per-query arrays of the workspace for nq queries (reallocates, dropping contents, when it grows).
 void ensure_queries(quake_index* idx, int64_t nq);
+// Grid of the persistent scan kernels.
+int scan_blocks(quake_index* idx, int batched);
+// R scan rounds on the stream without a host round trip: each round scans
+// the windows planned by the previous k_demand / k_prefix, commits, and
+// plans the next round (so the item count of the last one tells whether
+// work remains).
+void run_rounds(quake_index* idx, const Store& st, const Job& job, const RoundArgs& a, int R, hipStream_t s);
+// Destroys the captured round graphs of the index.
+void release_graphs(quake_index* idx);
 void ensure_workspace(quake_index* idx, int64_t nc, int64_t M, int64_t kk, int64_t items, int64_t pairs, int dp16,
                       bool scores = true);
 

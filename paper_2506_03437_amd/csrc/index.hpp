@@ -138,7 +138,8 @@ struct Workspace {
   int64_t* pitem = nullptr;     // [nlist + 1] first batched work item of each partition
   // device counters: [0] items, [1] vectors, [2] pairs of the round, [3] batched
   // items of the round, [4] batched vector reads and [5] batched query-vector
-  // products summed over the search
+  // products summed over the search, [6] plain-scan vectors summed over the
+  // search, [7] head of the round's item queue
   int64_t* total = nullptr;
   int64_t* h_total = nullptr;   // pinned host mirror
 };
@@ -186,6 +187,14 @@ struct quake_index {
   qk::Profiler prof;
   quake_tuning tune{};
   int cu_count = 0;
+  // captured scan rounds, keyed by every argument their kernels take
+  struct Graph {
+    std::vector<uint64_t> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<Graph> graphs;
+  hipStream_t capture_stream = nullptr;
+  bool graphs_failed = false;
 };
 
 namespace qk {
@@ -204,10 +213,12 @@ void launch_geometry(const float* q, const float* c, int64_t nq, int dp, int M, 
                      const int32_t* sel, int32_t* order, float* h, hipStream_t s);
 void launch_assign(const float* x, int64_t n, int dp, const float* c, int64_t nc, int metric, int32_t* assign,
                    hipStream_t s);
-void launch_kmeans_accumulate(const float* x, int64_t n, int dp, const int32_t* assign, float* sums,
+void launch_absmax(const float* x, int64_t n, uint32_t* out, hipStream_t s);
+void launch_kmeans_accumulate(const float* x, int64_t n, int dp, const int32_t* assign, int frac_bits, int64_t* sums,
                               int32_t* counts, hipStream_t s);
-void launch_kmeans_update(const float* sums, const int32_t* counts, int64_t nc, int dp, int normalise,
-                          float* c, hipStream_t s);
+void launch_kmeans_update(const int64_t* sums, const int32_t* counts, int64_t nc, int dp, int normalise,
+                          int frac_bits, float* c, hipStream_t s);
+void launch_normalise_rows(float* c, int64_t n, int dp, hipStream_t s);
 void launch_gather_rows(const float* x, int d, const int64_t* rows, int64_t nr, int dp, float* out,
                         hipStream_t s);
 
@@ -230,11 +241,12 @@ struct RoundArgs {
   int dim;           // d, for nothing but documentation of the table
   double tau_r, tau_rho;
   int64_t items_cap;
+  int blocks;        // grid of the persistent scan kernels (they read their item counts on the device)
 };
 void launch_round_init(Workspace& ws, const RoundArgs& a, int w0, hipStream_t s);
 void launch_demand(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
 void launch_emit(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
-void launch_scan_f32(Workspace& ws, const Store& st, const RoundArgs& a, int64_t nitems, hipStream_t s);
+void launch_scan_f32(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
 void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const double* table, hipStream_t s);
 void launch_finalize(Workspace& ws, const RoundArgs& a, int64_t* out_ids, float* out_dist,
                      int32_t* out_nscanned, double* out_recall, hipStream_t s);
@@ -242,8 +254,8 @@ void launch_finalize(Workspace& ws, const RoundArgs& a, int64_t* out_ids, float*
 // kernels: the batched scan (k_batched.hip)
 void launch_queries16(Workspace& ws, int64_t nq, int dp, int dp16, int dtype16, hipStream_t s,
                       const int32_t* slots = nullptr);
-void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, int64_t npairs, hipStream_t s);
-void launch_scan_mfma(Workspace& ws, const Store& st, const RoundArgs& a, int dtype16, int blocks, hipStream_t s);
+void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
+void launch_scan_mfma(Workspace& ws, const Store& st, const RoundArgs& a, int dtype16, hipStream_t s);
 void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s, const int32_t* slots = nullptr,
                    int64_t nslots = 0);
 void launch_norm16(const Store& st, int dtype16, hipStream_t s);

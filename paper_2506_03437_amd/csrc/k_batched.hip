@@ -149,24 +149,26 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
   }
 }
 
-__global__ __launch_bounds__(256) void k_pair_scatter(int64_t npairs, const int32_t* __restrict__ pair_p,
+__global__ __launch_bounds__(256) void k_pair_scatter(const int64_t* __restrict__ counters,
+                                                       const int32_t* __restrict__ pair_p,
                                                        const int32_t* __restrict__ pair_pos,
                                                        const int32_t* __restrict__ pstart,
                                                        int32_t* __restrict__ sorted) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= npairs) return;
-  sorted[pstart[pair_p[e]] + pair_pos[e]] = (int32_t)e;
+  const int64_t npairs = counters[2];
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < npairs; e += (int64_t)gridDim.x * 256)
+    sorted[pstart[pair_p[e]] + pair_pos[e]] = (int32_t)e;
 }
 
-void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, int64_t npairs, hipStream_t s) {
+void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_pairs, dim3((unsigned)((a.nq + 255) / 256)), dim3(256), 0, s, a.nq, a.M, a.chunk_tiles,
                      ws.cand, st.d_size, ws.st_m, ws.st_weff, ws.st_item, ws.st_pair, ws.pcount, ws.pair_q, ws.pair_p,
                      ws.pair_pos, ws.pair_base);
   hipLaunchKernelGGL(k_part_prefix, dim3(1), dim3(1024), 0, s, st.nlist, a.chunk_tiles, ws.pcount, st.d_size,
                      ws.pstart, ws.pitem, ws.total);
-  if (npairs > 0)
-    hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)((npairs + 255) / 256)), dim3(256), 0, s, npairs, ws.pair_p,
-                       ws.pair_pos, ws.pstart, ws.sorted);
+  // at most wmax pairs per query; the kernel reads this round's count
+  const int64_t bound = (a.nq * a.wmax + 255) / 256;
+  hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(bound, 2048))), dim3(256),
+                     0, s, ws.total, ws.pair_p, ws.pair_pos, ws.pstart, ws.sorted);
 }
 
 // ---------------------------------------------------------------- MFMA scan
@@ -423,7 +425,8 @@ static void scan_mfma_k(Workspace& ws, const Store& st, const RoundArgs& a, int 
 #undef QK_MFMA_LAUNCH
 }
 
-void launch_scan_mfma(Workspace& ws, const Store& st, const RoundArgs& a, int dtype16, int blocks, hipStream_t s) {
+void launch_scan_mfma(Workspace& ws, const Store& st, const RoundArgs& a, int dtype16, hipStream_t s) {
+  const int blocks = std::max(a.blocks, 1);
   const bool f16 = dtype16 == QUAKE_F16;
   const bool ip = a.metric == QUAKE_IP;
   if (f16) { if (ip) scan_mfma_k<1, 1>(ws, st, a, blocks, s); else scan_mfma_k<1, 0>(ws, st, a, blocks, s); }

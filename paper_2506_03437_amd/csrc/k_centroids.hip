@@ -318,49 +318,90 @@ void launch_geometry(const float* q, const float* c, int64_t nq, int dp, int M, 
 
 // ---------------------------------------------------------------- k-means
 
+// Cluster sums in fixed point: every coordinate becomes an integer multiple
+// of 2^-frac_bits and the sums are integer additions, which do not depend on
+// the order the atomics land in, so a build is reproducible run to run.
+// frac_bits is chosen on the host so that n * max|x| * 2^frac_bits < 2^62.
+__global__ __launch_bounds__(256) void k_absmax(const float* __restrict__ x, int64_t n, uint32_t* __restrict__ out) {
+  uint32_t m = 0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+    const uint32_t b = __float_as_uint(x[e]) & 0x7fffffffu;
+    if (b < 0x7f800000u && b > m) m = b;  // finite values only
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t v = __shfl_xor(m, o);
+    m = v > m ? v : m;
+  }
+  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+void launch_absmax(const float* x, int64_t n, uint32_t* out, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_absmax, dim3((unsigned)blocks), dim3(256), 0, s, x, n, out);
+}
+
 __global__ __launch_bounds__(256) void k_kmeans_accumulate(const float* __restrict__ x, int64_t n, int dp,
-                                                            const int32_t* __restrict__ assign,
-                                                            float* __restrict__ sums, int32_t* __restrict__ counts) {
+                                                            const int32_t* __restrict__ assign, double scale,
+                                                            int64_t* __restrict__ sums, int32_t* __restrict__ counts) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t row = e / dp;
   const int j = (int)(e - row * dp);
   if (row >= n) return;
   const int a = assign[row];
-  atomicAdd(&sums[(int64_t)a * dp + j], x[row * dp + j]);
+  const long long v = __double2ll_rn((double)x[row * dp + j] * scale);
+  atomicAdd((unsigned long long*)&sums[(int64_t)a * dp + j], (unsigned long long)v);
   if (j == 0) atomicAdd(&counts[a], 1);
 }
 
-void launch_kmeans_accumulate(const float* x, int64_t n, int dp, const int32_t* assign, float* sums,
+void launch_kmeans_accumulate(const float* x, int64_t n, int dp, const int32_t* assign, int frac_bits, int64_t* sums,
                               int32_t* counts, hipStream_t s) {
   const int64_t total = n * dp;
   if (total <= 0) return;
   hipLaunchKernelGGL(k_kmeans_accumulate, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, x, n, dp, assign,
-                     sums, counts);
+                     ldexp(1.0, frac_bits), sums, counts);
 }
 
-// c = sums / count for non-empty clusters (renormalised for spherical k-means).
-__global__ __launch_bounds__(64) void k_kmeans_update(const float* __restrict__ sums,
+// Centroid = sum / count (FP64 from the exact integer sums), unit length for
+// spherical k-means; empty clusters keep their centroid.
+__global__ __launch_bounds__(64) void k_kmeans_update(const int64_t* __restrict__ sums,
                                                        const int32_t* __restrict__ counts, int dp, int normalise,
-                                                       float* __restrict__ c) {
+                                                       double unscale, float* __restrict__ c) {
   const int64_t j = blockIdx.x;
   const int lane = threadIdx.x;
   const int cnt = counts[j];
   if (cnt == 0) return;
-  const float inv = 1.0f / (float)cnt;
-  float nrm = 0.f;
+  const double inv = unscale / (double)cnt;
+  double nrm = 0.0;
   for (int t = lane; t < dp; t += WAVE) {
-    const float v = sums[j * dp + t] * inv;
-    nrm = fmaf(v, v, nrm);
+    const double v = (double)sums[j * dp + t] * inv;
+    nrm += v * v;
   }
-  nrm = wave_sum_f(nrm);
-  const float scale = (normalise && nrm > 0.f) ? inv / sqrtf(nrm) : inv;
-  for (int t = lane; t < dp; t += WAVE) c[j * dp + t] = sums[j * dp + t] * scale;
+  nrm = wave_sum_d(nrm);
+  const double scale = (normalise && nrm > 0.0) ? inv / sqrt(nrm) : inv;
+  for (int t = lane; t < dp; t += WAVE) c[j * dp + t] = (float)((double)sums[j * dp + t] * scale);
 }
 
-void launch_kmeans_update(const float* sums, const int32_t* counts, int64_t nc, int dp, int normalise, float* c,
-                          hipStream_t s) {
+void launch_kmeans_update(const int64_t* sums, const int32_t* counts, int64_t nc, int dp, int normalise,
+                          int frac_bits, float* c, hipStream_t s) {
   if (nc <= 0) return;
-  hipLaunchKernelGGL(k_kmeans_update, dim3((unsigned)nc), dim3(64), 0, s, sums, counts, dp, normalise, c);
+  hipLaunchKernelGGL(k_kmeans_update, dim3((unsigned)nc), dim3(64), 0, s, sums, counts, dp, normalise,
+                     ldexp(1.0, -frac_bits), c);
+}
+
+// Rows scaled to unit length (rows of zeros stay zero).
+__global__ __launch_bounds__(64) void k_normalise_rows(float* __restrict__ c, int dp) {
+  const int64_t j = blockIdx.x;
+  double nrm = 0.0;
+  for (int t = threadIdx.x; t < dp; t += WAVE) nrm += (double)c[j * dp + t] * (double)c[j * dp + t];
+  nrm = wave_sum_d(nrm);
+  if (!(nrm > 0.0)) return;
+  const double inv = 1.0 / sqrt(nrm);
+  for (int t = threadIdx.x; t < dp; t += WAVE) c[j * dp + t] = (float)((double)c[j * dp + t] * inv);
+}
+
+void launch_normalise_rows(float* c, int64_t n, int dp, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_normalise_rows, dim3((unsigned)n), dim3(64), 0, s, c, dp);
 }
 
 __global__ __launch_bounds__(64) void k_gather_rows(const float* __restrict__ x, int d,

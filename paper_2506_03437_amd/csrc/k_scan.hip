@@ -147,6 +147,8 @@ __global__ __launch_bounds__(1024) void k_prefix(int64_t nq, int64_t cap, const 
     total[0] = items;
     total[1] = (int64_t)nvecs;
     total[2] = part[1023];
+    total[6] += (int64_t)nvecs;
+    total[7] = 0;  // head of the plain scan's item queue
   }
 }
 
@@ -190,18 +192,14 @@ void launch_emit(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t
 
 // ---------------------------------------------------------------- FP32 scan
 
+// One work item (query, partition, tiles [t0, t1)) of the plain scan: the
+// item's partial list, seeded with the query's committed k-th result.
 template <int METRIC, int KPL>
-__global__ __launch_bounds__(256) void k_scan_f32(const int4* __restrict__ items, int64_t nitems,
-                                                   const float* __restrict__ qpad, int dp,
-                                                   const float* __restrict__ v32, const int64_t* __restrict__ sid,
-                                                   const int64_t* __restrict__ poff,
-                                                   const int32_t* __restrict__ psize,
-                                                   const float* __restrict__ rk, const int64_t* __restrict__ ri,
-                                                   int kk, float* __restrict__ pk, int64_t* __restrict__ pi) {
-  const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (it >= nitems) return;
-  const int4 item = items[it];
+__device__ __forceinline__ void scan_item(const int4 item, int64_t it, int lane, const float* __restrict__ qpad,
+                                          int dp, const float* __restrict__ v32, const int64_t* __restrict__ sid,
+                                          const int64_t* __restrict__ poff, const int32_t* __restrict__ psize,
+                                          const float* __restrict__ rk, const int64_t* __restrict__ ri, int kk,
+                                          float* __restrict__ pk, int64_t* __restrict__ pi) {
   const int q = __builtin_amdgcn_readfirstlane(item.x);
   const int p = __builtin_amdgcn_readfirstlane(item.y);
   const int t0 = __builtin_amdgcn_readfirstlane(item.z);
@@ -237,18 +235,41 @@ __global__ __launch_bounds__(256) void k_scan_f32(const int4* __restrict__ items
   top.store(pk + it * kk, pi + it * kk);
 }
 
+template <int METRIC, int KPL>
+__global__ __launch_bounds__(256) void k_scan_f32(const int4* __restrict__ items, int64_t* __restrict__ counters,
+                                                   const float* __restrict__ qpad, int dp,
+                                                   const float* __restrict__ v32, const int64_t* __restrict__ sid,
+                                                   const int64_t* __restrict__ poff,
+                                                   const int32_t* __restrict__ psize,
+                                                   const float* __restrict__ rk, const int64_t* __restrict__ ri,
+                                                   int kk, float* __restrict__ pk, int64_t* __restrict__ pi) {
+  // Waves take items from the round's queue (head counters[7], reset by
+  // k_prefix) until it is empty: items differ in size, so the grid balances
+  // itself.
+  const int lane = threadIdx.x & 63;
+  const int64_t nitems = counters[0];
+  for (;;) {
+    int64_t it = 0;
+    if (lane == 0) it = (int64_t)atomicAdd((unsigned long long*)(counters + 7), 1ull);
+    it = readlane_i64(it, 0);
+    if (it >= nitems) break;
+    scan_item<METRIC, KPL>(items[it], it, lane, qpad, dp, v32, sid, poff, psize, rk, ri, kk, pk, pi);
+  }
+}
+
 template <int METRIC>
-static void scan_f32_k(Workspace& ws, const Store& st, const RoundArgs& a, int64_t nitems, hipStream_t s) {
-  const dim3 grid((unsigned)((nitems + 3) / 4));
+static void scan_f32_k(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
+  const int64_t need = (a.items_cap + 3) / 4;
+  const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(need, a.blocks)));
   if (a.kk <= 64)
-    hipLaunchKernelGGL((k_scan_f32<METRIC, 1>), grid, dim3(256), 0, s, ws.items, nitems, ws.q, st.dp, st.v32, st.ids,
-                       st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi);
+    hipLaunchKernelGGL((k_scan_f32<METRIC, 1>), grid, dim3(256), 0, s, ws.items, ws.total, ws.q, st.dp, st.v32,
+                       st.ids, st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi);
   else if (a.kk <= 128)
-    hipLaunchKernelGGL((k_scan_f32<METRIC, 2>), grid, dim3(256), 0, s, ws.items, nitems, ws.q, st.dp, st.v32, st.ids,
-                       st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi);
+    hipLaunchKernelGGL((k_scan_f32<METRIC, 2>), grid, dim3(256), 0, s, ws.items, ws.total, ws.q, st.dp, st.v32,
+                       st.ids, st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi);
   else
-    hipLaunchKernelGGL((k_scan_f32<METRIC, 4>), grid, dim3(256), 0, s, ws.items, nitems, ws.q, st.dp, st.v32, st.ids,
-                       st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi);
+    hipLaunchKernelGGL((k_scan_f32<METRIC, 4>), grid, dim3(256), 0, s, ws.items, ws.total, ws.q, st.dp, st.v32,
+                       st.ids, st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi);
 }
 
 // Items whose result lists are longer than a wave's sorted list holds (the
@@ -256,17 +277,12 @@ static void scan_f32_k(Workspace& ws, const Store& st, const RoundArgs& a, int64
 // one block scores all vectors of the item (at most 16 tiles), then sorts
 // them by (key, id) in LDS and keeps the first kk.
 template <int METRIC>
-__global__ __launch_bounds__(256) void k_scan_f32_sorted(const int4* __restrict__ items, int64_t nitems,
-                                                          const float* __restrict__ qpad, int dp,
-                                                          const float* __restrict__ v32, const int64_t* __restrict__ sid,
-                                                          const int64_t* __restrict__ poff,
-                                                          const int32_t* __restrict__ psize, int kk,
-                                                          float* __restrict__ pk, int64_t* __restrict__ pi) {
-  __shared__ float K[SORTED_ITEM_MAX];
-  __shared__ int64_t I[SORTED_ITEM_MAX];
-  const int64_t it = blockIdx.x;
+__device__ __forceinline__ void sorted_item(const int4 item, int64_t it, float* K, int64_t* I,
+                                            const float* __restrict__ qpad, int dp, const float* __restrict__ v32,
+                                            const int64_t* __restrict__ sid, const int64_t* __restrict__ poff,
+                                            const int32_t* __restrict__ psize, int kk, float* __restrict__ pk,
+                                            int64_t* __restrict__ pi) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int4 item = items[it];
   const int q = item.x, p = item.y, t0 = item.z, t1 = item.w;
   const int64_t tile0 = poff[p];
   const int size = psize[p];
@@ -306,19 +322,45 @@ __global__ __launch_bounds__(256) void k_scan_f32_sorted(const int4* __restrict_
   }
 }
 
-void launch_scan_f32(Workspace& ws, const Store& st, const RoundArgs& a, int64_t nitems, hipStream_t s) {
-  if (nitems <= 0) return;
+template <int METRIC>
+__global__ __launch_bounds__(256) void k_scan_f32_sorted(const int4* __restrict__ items,
+                                                          int64_t* __restrict__ counters,
+                                                          const float* __restrict__ qpad, int dp,
+                                                          const float* __restrict__ v32, const int64_t* __restrict__ sid,
+                                                          const int64_t* __restrict__ poff,
+                                                          const int32_t* __restrict__ psize, int kk,
+                                                          float* __restrict__ pk, int64_t* __restrict__ pi) {
+  __shared__ float K[SORTED_ITEM_MAX];
+  __shared__ int64_t I[SORTED_ITEM_MAX];
+  __shared__ int64_t next;
+  const int64_t nitems = counters[0];
+  for (;;) {
+    __syncthreads();  // the previous item's results are out of K / I, and `next` is free
+    if (threadIdx.x == 0) next = (int64_t)atomicAdd((unsigned long long*)(counters + 7), 1ull);
+    __syncthreads();
+    const int64_t it = next;
+    if (it >= nitems) break;
+    sorted_item<METRIC>(items[it], it, K, I, qpad, dp, v32, sid, poff, psize, kk, pk, pi);
+  }
+}
+
+// Persistent launch: the grid is fixed on the host and the kernels read
+// this round's item count (written by k_prefix) on the device, so a round
+// needs no host round trip.
+void launch_scan_f32(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
+  if (a.items_cap <= 0) return;
   if (a.kk > KMAX) {
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(a.items_cap, a.blocks)));
     if (a.metric == QUAKE_L2)
-      hipLaunchKernelGGL(k_scan_f32_sorted<QUAKE_L2>, dim3((unsigned)nitems), dim3(256), 0, s, ws.items, nitems, ws.q,
-                         st.dp, st.v32, st.ids, st.d_off, st.d_size, a.kk, ws.pk, ws.pi);
+      hipLaunchKernelGGL(k_scan_f32_sorted<QUAKE_L2>, grid, dim3(256), 0, s, ws.items, ws.total, ws.q, st.dp, st.v32,
+                         st.ids, st.d_off, st.d_size, a.kk, ws.pk, ws.pi);
     else
-      hipLaunchKernelGGL(k_scan_f32_sorted<QUAKE_IP>, dim3((unsigned)nitems), dim3(256), 0, s, ws.items, nitems, ws.q,
-                         st.dp, st.v32, st.ids, st.d_off, st.d_size, a.kk, ws.pk, ws.pi);
+      hipLaunchKernelGGL(k_scan_f32_sorted<QUAKE_IP>, grid, dim3(256), 0, s, ws.items, ws.total, ws.q, st.dp, st.v32,
+                         st.ids, st.d_off, st.d_size, a.kk, ws.pk, ws.pi);
     return;
   }
-  if (a.metric == QUAKE_L2) scan_f32_k<QUAKE_L2>(ws, st, a, nitems, s);
-  else scan_f32_k<QUAKE_IP>(ws, st, a, nitems, s);
+  if (a.metric == QUAKE_L2) scan_f32_k<QUAKE_L2>(ws, st, a, s);
+  else scan_f32_k<QUAKE_IP>(ws, st, a, s);
 }
 
 // ---------------------------------------------------------------- commit

@@ -67,6 +67,7 @@ struct quake_server {
   hipStream_t s = nullptr;
   int chunk_tiles = 16;
   int64_t items = 0;
+  int blocks = 0;
 
   std::thread worker;
   std::mutex mu;
@@ -123,6 +124,7 @@ struct quake_server {
     a.tau_r = job.tau_r;
     a.tau_rho = job.tau_rho;
     a.items_cap = std::min<int64_t>(idx->ws.items_cap, items);
+    a.blocks = blocks;
     return a;
   }
 
@@ -138,8 +140,7 @@ struct quake_server {
                          job.batched ? st().dp16 : 0, false);
     QK_HIP(hipMemsetAsync(idx->ws.total, 0, 8 * sizeof(int64_t), s));
     qk::launch_mark_free(idx->ws, cap, s);
-    if (job.batched && idx->cu_count == 0)
-      QK_HIP(hipDeviceGetAttribute(&idx->cu_count, hipDeviceAttributeMultiprocessorCount, device));
+    blocks = qk::scan_blocks(idx, job.batched);
     QK_HIP(hipStreamSynchronize(s));
   }
 
@@ -169,22 +170,13 @@ struct quake_server {
     qk::launch_init_slots(w, d_slots, n, job.kk, job.w0, s);
   }
 
+  // One scan round over all slots: plan, scan, commit.  No host round trip;
+  // the harvest that follows reads which slots finished.
   void round() {
     qk::Workspace& w = idx->ws;
     qk::RoundArgs a = args();
     qk::launch_demand(w, st(), a, s);
-    int64_t tot[3];
-    QK_HIP(hipMemcpyAsync(tot, w.total, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    QK_HIP(hipStreamSynchronize(s));
-    QK_CHECK(tot[0] > 0, QUAKE_E_DEVICE, "a round found no work for the searches in flight");
-    if (job.batched) {
-      qk::launch_group(w, st(), a, tot[2], s);
-      qk::launch_scan_mfma(w, st(), a, job.dtype16, std::max(idx->cu_count, 8) * 2, s);
-    } else {
-      qk::launch_emit(w, st(), a, s);
-      qk::launch_scan_f32(w, st(), a, tot[0], s);
-    }
-    qk::launch_commit(w, st(), a, idx->cap_table, s);
+    qk::run_rounds(idx, st(), job, a, 1, s);
     ++rounds;
   }
 

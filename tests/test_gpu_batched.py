@@ -67,7 +67,8 @@ def test_batched_schedules_agree(int_index):
     metric, dtype, X, Q, idx, ps = int_index
     kw = dict(k=10, recall_target=0.95, f_M=0.5, scan_mode="batched", scan_dtype=dtype)
     base = gu.search(idx, Q, **kw)
-    for sch in (dict(chunk_tiles=1), dict(max_items=1), dict(first_window=1, max_window=1), dict(first_window=16)):
+    for sch in (dict(chunk_tiles=1), dict(max_items=1), dict(first_window=1, max_window=1), dict(first_window=16),
+                dict(rounds_per_sync=1, blocks_per_cu=1), dict(rounds_per_sync=16, blocks_per_cu=8)):
         idx.set_tuning(**sch)
         got = gu.search(idx, Q, **kw)
         for a, b in zip(base, got):

@@ -62,6 +62,23 @@ def test_build_places_every_vector_in_its_nearest_partition(small_l2):
     assert n_live == X.shape[0] and nparts == w.nlist
 
 
+def test_build_is_reproducible():
+    """Cluster sums are exact integers in fixed point, so two builds with one
+    seed give bit-identical centroids and the same placement."""
+    spec = synth.MixtureSpec(key=23, n=30_000, d=96, n_components=50, zipf_s=1.1, unit_norm=True)
+    X = synth.database(spec)
+    out = []
+    for _ in range(2):
+        idx = gu.build(X, metric="ip", nlist=60, kmeans_iters=6, seed=11)
+        C, ids, part = idx.export()
+        out.append((C.cpu().numpy(), ids.cpu().numpy(), part.cpu().numpy()))
+        idx.free()
+    (C0, i0, p0), (C1, i1, p1) = out
+    assert (C0 == C1).all()
+    o0, o1 = np.argsort(i0), np.argsort(i1)
+    assert (i0[o0] == i1[o1]).all() and (p0[o0] == p1[o1]).all()
+
+
 @pytest.mark.parametrize("k", [10, 100, 256])
 def test_fixed_nprobe_matches_oracle(small_l2, k):
     w, X, Q, idx, ps = small_l2

@@ -29,7 +29,8 @@ def big_parts():
 
 
 SCHEDULES = [dict(chunk_tiles=1), dict(max_items=1), dict(first_window=1, max_window=1), dict(first_window=8),
-             dict(chunk_tiles=3, max_items=50), dict(chunk_tiles=200)]
+             dict(chunk_tiles=3, max_items=50), dict(chunk_tiles=200), dict(rounds_per_sync=1, blocks_per_cu=1),
+             dict(rounds_per_sync=16, blocks_per_cu=32), dict(no_graph=1, rounds_per_sync=3)]
 
 
 @pytest.mark.parametrize("mode", [dict(recall_target=0.9, f_M=0.5), dict(nprobe=5), dict(recall_target=0.99, f_M=1.0)])
