@@ -464,7 +464,7 @@ void ensure_queries(quake_index* idx, int64_t nq) {
   for (void* p : {(void*)w.q, (void*)w.qn2, (void*)w.st_m, (void*)w.st_w, (void*)w.st_weff, (void*)w.st_done,
                   (void*)w.st_item, (void*)w.st_demand, (void*)w.st_vecs, (void*)w.st_pair, (void*)w.st_rho,
                   (void*)w.st_p0, (void*)w.st_V, (void*)w.st_vsum, (void*)w.st_r, (void*)w.q16, (void*)w.qn2f,
-                  (void*)w.mq, (void*)w.mq0})
+                  (void*)w.mq, (void*)w.mq0, (void*)w.blk})
     mem.release(p);
   w.q = mem.alloc<float>((size_t)n * dp);
   w.qn2 = mem.alloc<double>(n);
@@ -474,6 +474,7 @@ void ensure_queries(quake_index* idx, int64_t nq) {
   w.st_done = mem.alloc<int32_t>(n);
   w.st_item = mem.alloc<int64_t>(n);
   w.st_demand = mem.alloc<int64_t>(n);
+  w.blk = mem.alloc<int64_t>((n / 256 + 1) * 4);
   w.st_vecs = mem.alloc<int64_t>(n);
   w.st_pair = mem.alloc<int64_t>(n);
   w.q16 = nullptr;
@@ -527,8 +528,8 @@ void ensure_workspace(quake_index* idx, int64_t nc, int64_t M, int64_t kk, int64
     w.pi = mem.alloc<int64_t>((size_t)w.items_cap * w.k_cap);
   }
   if (!w.total) {
-    w.total = mem.alloc<int64_t>(8);
-    QK_HIP(hipHostMalloc((void**)&w.h_total, 8 * sizeof(int64_t), hipHostMallocDefault));
+    w.total = mem.alloc<int64_t>(qk::COUNTERS);
+    QK_HIP(hipHostMalloc((void**)&w.h_total, qk::COUNTERS * sizeof(int64_t), hipHostMallocDefault));
   }
   if (dp16 > 0 && (!w.q16 || dp16 > w.q16_dim)) {
     mem.release(w.q16);
@@ -606,7 +607,7 @@ std::vector<uint64_t> graph_key(const quake_index* idx, const Store& st, const J
       u(w.st_w), u(w.st_weff), u(w.st_done), u(w.st_item), u(w.st_demand), u(w.st_rho), u(w.st_p0), u(w.st_V),
       u(w.st_vsum), u(w.st_r), u(w.rk), u(w.ri), u(w.items), u(w.pk), u(w.pi), u(w.st_vecs), u(w.st_pair),
       u(w.q16), u(w.qn2f), u(w.pair_q), u(w.pair_p), u(w.pair_pos), u(w.pair_base), u(w.sorted), u(w.pcount),
-      u(w.pstart), u(w.pitem), u(w.total)};
+      u(w.pstart), u(w.pitem), u(w.total), u(w.blk)};
   uint64_t tr, tro;
   std::memcpy(&tr, &a.tau_r, 8);
   std::memcpy(&tro, &a.tau_rho, 8);
@@ -703,7 +704,7 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
   ensure_workspace(idx, st.nlist, job.M, job.kk, items, job.batched ? nq * (int64_t)job.wmax : 0,
                    job.batched ? st.dp16 : 0, !job.given);
   qk::Workspace& w = idx->ws;
-  QK_HIP(hipMemsetAsync(w.total, 0, 8 * sizeof(int64_t), s));
+  QK_HIP(hipMemsetAsync(w.total, 0, qk::COUNTERS * sizeof(int64_t), s));
   if (job.given) {
     QK_HIP(hipMemcpyAsync(w.mq, w.mq0, nq * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     qk::ProfileScope ps(idx->prof, QUAKE_PROF_SELECT, s);
@@ -717,12 +718,7 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
     idx->prof.add(QUAKE_PROF_CENTROIDS, ((double)st.nlist + nq) * idx->dp * 4.0 + (double)nq * st.nlist * 4.0,
                   (double)nq * st.nlist * idx->dp * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
     qk::ProfileScope ps(idx->prof, QUAKE_PROF_SELECT, s);
-    if (job.aps) {
-      qk::launch_select(w.scores, nq, st.nlist, job.M, idx->metric, w.sel, s);
-      qk::launch_geometry(w.q, st.centroids, nq, idx->dp, job.M, w.mq, idx->metric, w.sel, w.cand, w.h, s);
-    } else {
-      qk::launch_select(w.scores, nq, st.nlist, job.M, idx->metric, w.cand, s);
-    }
+    qk::launch_candidates(st, w.q, w.scores, nq, idx->dp, job.M, job.aps, idx->metric, w.mq, w.sel, w.cand, w.h, s);
   }
   if (job.batched) qk::launch_queries16(w, nq, idx->dp, st.dp16, job.dtype16, s);
   qk::RoundArgs a{};
@@ -981,8 +977,7 @@ int quake_candidates(quake_index* idx, const float* q, int64_t nq, double f_M, i
   qk::launch_pad_rows(q, nq, idx->d, idx->dp, w.q, w.qn2, s);
   qk::launch_fill_i32(w.mq, nq, M, s);
   qk::launch_scores(w.q, nq, st.centroids, st.nlist, idx->dp, idx->metric, w.scores, s);
-  qk::launch_select(w.scores, nq, st.nlist, M, idx->metric, w.sel, s);
-  qk::launch_geometry(w.q, st.centroids, nq, idx->dp, M, w.mq, idx->metric, w.sel, w.cand, w.h, s);
+  qk::launch_candidates(st, w.q, w.scores, nq, idx->dp, M, 1, idx->metric, w.mq, w.sel, w.cand, w.h, s);
   QK_HIP(hipMemcpyAsync(order, w.cand, (size_t)nq * M * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   QK_HIP(hipMemcpyAsync(h, w.h, (size_t)nq * M * sizeof(float), hipMemcpyDeviceToDevice, s));
   QK_HIP(hipStreamSynchronize(s));

@@ -32,6 +32,18 @@ __device__ __forceinline__ int64_t shfl_up_i64(int64_t v, int delta) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+__device__ __forceinline__ int64_t shfl_i64(int64_t v, int src) {
+  int lo = __shfl((int)(uint32_t)(uint64_t)v, src);
+  int hi = __shfl((int)(uint32_t)((uint64_t)v >> 32), src);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__device__ __forceinline__ int64_t shfl_xor_i64(int64_t v, int mask) {
+  int lo = __shfl_xor((int)(uint32_t)(uint64_t)v, mask);
+  int hi = __shfl_xor((int)(uint32_t)((uint64_t)v >> 32), mask);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 __device__ __forceinline__ int64_t readlane_i64(int64_t v, int lane) {
   uint32_t lo = __builtin_amdgcn_readlane((uint32_t)(uint64_t)v, lane);
   uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)v >> 32), lane);
@@ -170,6 +182,66 @@ __device__ inline void wave_merge(const float* ak, const int64_t* ai, const floa
     const int pb = e + corank(ak, ai, n, bk[e], bi[e], false);
     if (pb < n) { ok[pb] = bk[e]; oi[pb] = bi[e]; }
   }
+}
+
+// Two ascending lists of up to 64 entries held one entry per lane (lanes past
+// a list's end hold empties): a := the 64 smallest of a and b, ascending.
+// Against b reversed, the lane-wise minimum is a bitonic sequence holding
+// the 64 smallest entries; six compare-exchange stages sort it.
+__device__ __forceinline__ void wave_merge64_kv(float& ak, int64_t& ai, float bk, int64_t bi) {
+  const int lane = lane_id();
+  const float rk = __shfl(bk, WAVE - 1 - lane);
+  const int64_t rv = shfl_i64(bi, WAVE - 1 - lane);
+  if (kv_less(rk, rv, ak, ai)) { ak = rk; ai = rv; }
+#pragma unroll
+  for (int stride = WAVE / 2; stride > 0; stride >>= 1) {
+    const float ok = __shfl_xor(ak, stride);
+    const int64_t oi = shfl_xor_i64(ai, stride);
+    const bool lower = (lane & stride) == 0;
+    if (lower ? kv_less(ok, oi, ak, ai) : kv_less(ak, ai, ok, oi)) { ak = ok; ai = oi; }
+  }
+}
+
+// (key, 32-bit tag) entries, one per lane: the same order with a 32-bit
+// tiebreak (a store slot or a list position).
+__device__ __forceinline__ bool ks_less(float ak, int32_t as, float bk, int32_t bs) {
+  return ak < bk || (ak == bk && as < bs);
+}
+
+__device__ __forceinline__ void swap_if(bool take, float& k, int32_t& s, float ok, int32_t os) {
+  if (take) { k = ok; s = os; }
+}
+
+// One compare-exchange stage of a bitonic network across the wave: lanes
+// `stride` apart swap so that the lower lane of each pair keeps the smaller
+// entry in ascending runs of length `size` (and the larger in descending ones).
+__device__ __forceinline__ void bitonic_step(float& k, int32_t& s, int size, int stride) {
+  const int lane = lane_id();
+  const float ok = __shfl_xor(k, stride);
+  const int32_t os = __shfl_xor(s, stride);
+  const bool up = (lane & size) == 0;
+  const bool lower = (lane & stride) == 0;
+  const bool other_first = ks_less(ok, os, k, s);
+  swap_if((lower == up) ? other_first : (!other_first && (ok != k || os != s)), k, s, ok, os);
+}
+
+// Sort one entry per lane ascending by (key, slot).
+__device__ __forceinline__ void wave_sort64(float& k, int32_t& s) {
+#pragma unroll
+  for (int size = 2; size <= WAVE; size <<= 1)
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) bitonic_step(k, s, size, stride);
+}
+
+// list (ascending, one entry per lane) := the 64 smallest of list and b
+// (b ascending): a bitonic split against b reversed, then a bitonic merge.
+__device__ __forceinline__ void wave_merge64(float& lk, int32_t& ls, float bk, int32_t bs) {
+  const int lane = lane_id();
+  const float rk = __shfl(bk, WAVE - 1 - lane);
+  const int32_t rs = __shfl(bs, WAVE - 1 - lane);
+  swap_if(ks_less(rk, rs, lk, ls), lk, ls, rk, rs);
+#pragma unroll
+  for (int stride = WAVE / 2; stride > 0; stride >>= 1) bitonic_step(lk, ls, WAVE, stride);
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));

@@ -41,6 +41,7 @@ inline int padded_dim16(int d) {
   return 32 * need;
 }
 constexpr int MAX_DIM = 4096;
+constexpr int COUNTERS = 16;      // device counters of a search (Workspace::total)
 constexpr int MAX_CANDIDATES = 4096;   // APS candidate set M (and nprobe) upper bound
 
 // Device allocations of one index, counted against an optional budget.
@@ -136,11 +137,13 @@ struct Workspace {
   int32_t* pcount = nullptr;    // [nlist] pairs per partition (kept zeroed between rounds)
   int32_t* pstart = nullptr;    // [nlist + 1]
   int64_t* pitem = nullptr;     // [nlist + 1] first batched work item of each partition
-  // device counters: [0] items, [1] vectors, [2] pairs of the round, [3] batched
-  // items of the round, [4] batched vector reads and [5] batched query-vector
-  // products summed over the search, [6] plain-scan vectors summed over the
-  // search, [7] head of the round's item queue
+  // device counters (COUNTERS of them): [0] items, [1] vectors, [2] pairs of
+  // the round, [3] batched items of the round, [4] batched vector reads and
+  // [5] batched query-vector products summed over the search, [6] plain-scan
+  // vectors summed over the search, [7] head of the round's item queue,
+  // [8] first query cut from the round
   int64_t* total = nullptr;
+  int64_t* blk = nullptr;       // [nq / 256 + 1][4] per-block planning sums, then offsets
   int64_t* h_total = nullptr;   // pinned host mirror
 };
 
@@ -211,6 +214,11 @@ void launch_select(const float* scores, int64_t nq, int64_t nc, int M, int metri
                    hipStream_t s);
 void launch_geometry(const float* q, const float* c, int64_t nq, int dp, int M, const int32_t* mq, int metric,
                      const int32_t* sel, int32_t* order, float* h, hipStream_t s);
+// The M best centroids per query and, in adaptive mode, their scan order and
+// bisector distances (one fused wave per query for M <= 64 and d <= 1024,
+// else k_select + k_geometry; mq must hold M for the latter).
+void launch_candidates(const Store& st, const float* q, const float* scores, int64_t nq, int dp, int M, int aps,
+                       int metric, const int32_t* mq, int32_t* sel, int32_t* cand, float* h, hipStream_t s);
 void launch_assign(const float* x, int64_t n, int dp, const float* c, int64_t nc, int metric, int32_t* assign,
                    hipStream_t s);
 void launch_absmax(const float* x, int64_t n, uint32_t* out, hipStream_t s);

@@ -183,46 +183,6 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
                                                     0, 0, 0);
 }
 
-__device__ __forceinline__ bool ks_less(float ak, int32_t as, float bk, int32_t bs) {
-  return ak < bk || (ak == bk && as < bs);
-}
-
-__device__ __forceinline__ void swap_if(bool take, float& k, int32_t& s, float ok, int32_t os) {
-  if (take) { k = ok; s = os; }
-}
-
-// One compare-exchange stage of a bitonic network across the wave: lanes
-// `stride` apart swap so that the lower lane of each pair keeps the smaller
-// entry in ascending runs of length `size` (and the larger in descending ones).
-__device__ __forceinline__ void bitonic_step(float& k, int32_t& s, int size, int stride) {
-  const int lane = lane_id();
-  const float ok = __shfl_xor(k, stride);
-  const int32_t os = __shfl_xor(s, stride);
-  const bool up = (lane & size) == 0;
-  const bool lower = (lane & stride) == 0;
-  const bool other_first = ks_less(ok, os, k, s);
-  swap_if((lower == up) ? other_first : (!other_first && (ok != k || os != s)), k, s, ok, os);
-}
-
-// Sort one entry per lane ascending by (key, slot).
-__device__ __forceinline__ void wave_sort64(float& k, int32_t& s) {
-#pragma unroll
-  for (int size = 2; size <= WAVE; size <<= 1)
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) bitonic_step(k, s, size, stride);
-}
-
-// list (ascending, one entry per lane) := the 64 smallest of list and b
-// (b ascending): a bitonic split against b reversed, then a bitonic merge.
-__device__ __forceinline__ void wave_merge64(float& lk, int32_t& ls, float bk, int32_t bs) {
-  const int lane = lane_id();
-  const float rk = __shfl(bk, WAVE - 1 - lane);
-  const int32_t rs = __shfl(bs, WAVE - 1 - lane);
-  swap_if(ks_less(rk, rs, lk, ls), lk, ls, rk, rs);
-#pragma unroll
-  for (int stride = WAVE / 2; stride > 0; stride >>= 1) bitonic_step(lk, ls, WAVE, stride);
-}
-
 template <int F16, int KS, int IP>
 __global__ __launch_bounds__(256, 2) void k_scan_mfma(
     const int64_t* __restrict__ counters, const int64_t* __restrict__ pitem, const int32_t* __restrict__ pstart,

@@ -316,6 +316,109 @@ void launch_geometry(const float* q, const float* c, int64_t nq, int dp, int M, 
                      sel, order, h);
 }
 
+// ---------------------------------------------------------------- fused selection (M <= 64)
+
+// One wave per query.  Selection: chunks of 64 scores are sorted and merged
+// into a running list of the 64 best (key, id), one entry per lane; chunks
+// with nothing better than the running M-th entry are skipped.  Geometry
+// (adaptive mode): the query and c_0 stay in registers (DPL dimensions per
+// lane) and each candidate row is read once for its bisector distance, in
+// the projection form and summation order of k_geometry; then the
+// candidates after c_0 are sorted by (h, selection order).
+template <int DPL>
+__global__ __launch_bounds__(256) void k_select64(const float* __restrict__ scores, int64_t nq, int64_t nc, int M,
+                                                   int ip, int geometry, const float* __restrict__ qpad,
+                                                   const float* __restrict__ c, int dp, int32_t* __restrict__ cand,
+                                                   float* __restrict__ hout) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (q >= nq) return;
+  const float* s = scores + q * nc;
+  float lk = KEY_EMPTY;
+  int32_t li = INT32_MAX;
+  for (int64_t base = 0; base < nc; base += WAVE) {
+    const int64_t e = base + lane;
+    float key = KEY_EMPTY;
+    int32_t id = INT32_MAX;
+    if (e < nc) {
+      const float raw = s[e];
+      key = ip ? -raw : raw;
+      id = (int32_t)e;
+    }
+    const float tk = readlane_f(lk, M - 1);
+    const int32_t ti = (int32_t)__builtin_amdgcn_readlane((uint32_t)li, M - 1);
+    if (!__ballot(ks_less(key, id, tk, ti))) continue;
+    wave_sort64(key, id);
+    wave_merge64(lk, li, key, id);
+  }
+  float h = 0.f;
+  int32_t tag = lane;
+  if (geometry) {
+    const int32_t c0 = (int32_t)__builtin_amdgcn_readlane((uint32_t)li, 0);
+    float qr[DPL], ar[DPL];
+#pragma unroll
+    for (int t = 0; t < DPL; ++t) {
+      const int j = t * WAVE + lane;
+      qr[t] = j < dp ? qpad[q * dp + j] : 0.f;
+      ar[t] = j < dp ? c[(int64_t)c0 * dp + j] : 0.f;
+    }
+    h = lane == 0 ? -__builtin_inff() : __builtin_inff();
+    for (int i = 1; i < M; ++i) {
+      const int32_t ci = (int32_t)__builtin_amdgcn_readlane((uint32_t)li, i);
+      const float* civ = c + (int64_t)ci * dp;
+      float num = 0.f, sep = 0.f;
+#pragma unroll
+      for (int t = 0; t < DPL; ++t) {
+        const int j = t * WAVE + lane;
+        if (j < dp) {
+          const float a = ar[t], b = civ[j], x = qr[t];
+          const float diff = a - b;
+          sep = fmaf(diff, diff, sep);
+          num = ip ? fmaf(x, diff, num) : fmaf(diff, (x - a) + (x - b), num);
+        }
+      }
+      num = wave_sum_f(num);
+      sep = wave_sum_f(sep);
+      float hi = 0.f;
+      if (sep > 0.f) hi = ip ? num / sqrtf(sep) : num / (2.0f * sqrtf(sep));
+      if (lane == i) h = fmaxf(hi, 0.f);
+    }
+    wave_sort64(h, tag);
+    if (lane == 0) h = 0.f;
+  }
+  const int32_t id = __shfl(li, tag);
+  if (lane < M) {
+    cand[q * M + lane] = id;
+    if (geometry) hout[q * M + lane] = h;
+  }
+}
+
+void launch_candidates(const Store& st, const float* q, const float* scores, int64_t nq, int dp, int M, int aps,
+                       int metric, const int32_t* mq, int32_t* sel, int32_t* cand, float* h, hipStream_t s) {
+  if (nq <= 0) return;
+  const int ip = metric == QUAKE_IP ? 1 : 0;
+  const int dpl = (dp + WAVE - 1) / WAVE;
+  if (M <= WAVE && dpl <= 16) {
+    const dim3 grid((unsigned)((nq + 3) / 4));
+#define QK_SEL(D)                                                                                             \
+  hipLaunchKernelGGL(k_select64<D>, grid, dim3(256), 0, s, scores, nq, st.nlist, M, ip, aps, q, st.centroids, dp, \
+                     cand, h)
+    if (dpl <= 2) QK_SEL(2);
+    else if (dpl <= 4) QK_SEL(4);
+    else if (dpl <= 8) QK_SEL(8);
+    else if (dpl <= 12) QK_SEL(12);
+    else QK_SEL(16);
+#undef QK_SEL
+    return;
+  }
+  if (aps) {
+    launch_select(scores, nq, st.nlist, M, metric, sel, s);
+    launch_geometry(q, st.centroids, nq, dp, M, mq, metric, sel, cand, h, s);
+  } else {
+    launch_select(scores, nq, st.nlist, M, metric, cand, s);
+  }
+}
+
 // ---------------------------------------------------------------- k-means
 
 // Cluster sums in fixed point: every coordinate becomes an integer multiple

@@ -58,19 +58,48 @@ void launch_round_init(Workspace& ws, const RoundArgs& a, int w0, hipStream_t s)
 
 // ---------------------------------------------------------------- planning
 
-// Work items each query needs for its window this round.  st_w is the
-// window the query asked for; st_weff is what it gets this round (0 when it
-// is finished or when the item buffer is full, see k_prefix).
-__global__ __launch_bounds__(256) void k_demand(int64_t nq, int M, int chunk_tiles, const int32_t* __restrict__ mq,
-                                                 const int32_t* __restrict__ cand, const int32_t* __restrict__ psize,
-                                                 const int32_t* __restrict__ st_m, const int32_t* __restrict__ st_w,
-                                                 int32_t* __restrict__ st_weff, const int32_t* __restrict__ st_done,
-                                                 int64_t* __restrict__ demand, int64_t* __restrict__ vecs) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (q >= nq) return;
+// Planning a round, in three steps that scale with the batch:
+//  k_demand  per query: the work items and vectors of its window this round
+//            (st_w is the window it asked for; st_weff what it gets) and, per
+//            block of 256 queries, exclusive prefix sums of items and window
+//            partitions (kept in st_item / st_pair) and the block's totals;
+//  k_prefix  one block: prefix sums over the block totals, and the cut -
+//            queries from the first one whose items would overflow the item
+//            buffer sit this round out (effective window 0, the requested
+//            window is kept for the next round); the buffer always holds the
+//            first unfinished query's window, so every round makes progress;
+//  k_place   per query: global item and pair offsets, windows past the cut
+//            cleared.
+constexpr int PLAN_BLOCK = 256;
+
+__device__ __forceinline__ int64_t wave_excl_scan_i64(int64_t v, int64_t& wave_total) {
+  const int lane = lane_id();
+  int64_t x = v;
+  for (int o = 1; o < WAVE; o <<= 1) {
+    const int64_t u = shfl_up_i64(x, o);
+    if (lane >= o) x += u;
+  }
+  wave_total = readlane_i64(x, WAVE - 1);
+  return x - v;
+}
+
+__global__ __launch_bounds__(PLAN_BLOCK) void k_demand(int64_t nq, int M, int chunk_tiles,
+                                                        const int32_t* __restrict__ mq,
+                                                        const int32_t* __restrict__ cand,
+                                                        const int32_t* __restrict__ psize,
+                                                        const int32_t* __restrict__ st_m,
+                                                        const int32_t* __restrict__ st_w,
+                                                        int32_t* __restrict__ st_weff,
+                                                        const int32_t* __restrict__ st_done,
+                                                        int64_t* __restrict__ demand, int64_t* __restrict__ vecs,
+                                                        int64_t* __restrict__ loc_item, int64_t* __restrict__ loc_pair,
+                                                        int64_t* __restrict__ blk) {
+  __shared__ int64_t wd[PLAN_BLOCK / WAVE], ww[PLAN_BLOCK / WAVE], wv[PLAN_BLOCK / WAVE];
+  const int64_t q = (int64_t)blockIdx.x * PLAN_BLOCK + threadIdx.x;
+  const int wave = threadIdx.x / WAVE;
   int64_t dmd = 0, nv = 0;
   int w = 0;
-  if (!st_done[q]) {
+  if (q < nq && !st_done[q]) {
     const int m = st_m[q];
     w = st_w[q];
     if (w > mq[q] - m) w = mq[q] - m;
@@ -80,83 +109,120 @@ __global__ __launch_bounds__(256) void k_demand(int64_t nq, int M, int chunk_til
       nv += sz;
     }
   }
-  st_weff[q] = w;
-  demand[q] = dmd;
-  vecs[q] = nv;
+  int64_t td, tw, tv;
+  const int64_t ed = wave_excl_scan_i64(dmd, td);
+  const int64_t ew = wave_excl_scan_i64((int64_t)w, tw);
+  wave_excl_scan_i64(nv, tv);
+  if (lane_id() == 0) { wd[wave] = td; ww[wave] = tw; wv[wave] = tv; }
+  __syncthreads();
+  int64_t bd = 0, bw = 0, bv = 0, od = 0, ow = 0;
+  for (int i = 0; i < PLAN_BLOCK / WAVE; ++i) {
+    if (i == wave) { od = bd; ow = bw; }
+    bd += wd[i]; bw += ww[i]; bv += wv[i];
+  }
+  if (q < nq) {
+    st_weff[q] = w;
+    demand[q] = dmd;
+    vecs[q] = nv;
+    loc_item[q] = od + ed;
+    loc_pair[q] = ow + ew;
+  }
+  if (threadIdx.x == 0) {
+    blk[blockIdx.x * 4 + 0] = bd;
+    blk[blockIdx.x * 4 + 1] = bv;
+    blk[blockIdx.x * 4 + 2] = bw;
+  }
 }
 
-// Exclusive prefix sum of the demands (one block).  Queries whose items would
-// not fit in the item buffer sit this round out (effective window 0, the
-// requested window is kept for the next round); the buffer always holds the
-// first unfinished query's window, so every round makes progress.
 __global__ __launch_bounds__(1024) void k_prefix(int64_t nq, int64_t cap, const int64_t* __restrict__ demand,
-                                                  const int64_t* __restrict__ vecs, int64_t* __restrict__ first,
-                                                  int32_t* __restrict__ st_weff, int64_t* __restrict__ first_pair,
+                                                  const int64_t* __restrict__ vecs,
+                                                  const int64_t* __restrict__ loc_item,
+                                                  const int64_t* __restrict__ loc_pair, int64_t* __restrict__ blk,
                                                   int64_t* __restrict__ total) {
-  __shared__ int64_t part[1024];
-  __shared__ int64_t overflow_at;
-  __shared__ unsigned long long nvecs;
+  __shared__ int64_t pd[1024], pw[1024], pv[1024];
+  __shared__ unsigned long long cut_blk, cut_q, nv_tail;
   const int t = threadIdx.x;
-  const int64_t per = (nq + 1023) / 1024;
+  const int64_t nb = (nq + PLAN_BLOCK - 1) / PLAN_BLOCK;
+  const int64_t per = (nb + 1023) / 1024;
   const int64_t lo = t * per;
-  const int64_t hi = (lo + per < nq) ? lo + per : nq;
-  int64_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += demand[i];
-  part[t] = s;
-  if (t == 0) { overflow_at = nq; nvecs = 0; }
+  const int64_t hi = (lo + per < nb) ? lo + per : nb;
+  int64_t sd = 0, sw = 0, sv = 0;
+  for (int64_t b = lo; b < hi; ++b) { sd += blk[b * 4]; sv += blk[b * 4 + 1]; sw += blk[b * 4 + 2]; }
+  pd[t] = sd; pw[t] = sw; pv[t] = sv;
+  if (t == 0) { cut_blk = (unsigned long long)nb; cut_q = (unsigned long long)nq; nv_tail = 0; }
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
-    const int64_t v = (t >= o) ? part[t - o] : 0;
+    const int64_t a = (t >= o) ? pd[t - o] : 0;
+    const int64_t c = (t >= o) ? pw[t - o] : 0;
+    const int64_t e = (t >= o) ? pv[t - o] : 0;
     __syncthreads();
-    part[t] += v;
+    pd[t] += a; pw[t] += c; pv[t] += e;
     __syncthreads();
   }
-  int64_t run = part[t] - s;
-  for (int64_t i = lo; i < hi; ++i) {
-    first[i] = run;
-    if (run + demand[i] > cap) atomicMin((unsigned long long*)&overflow_at, (unsigned long long)i);
-    run += demand[i];
+  // the block totals become block offsets: items before the block in column
+  // 0, vectors in 1, window partitions (pairs) in 2
+  int64_t rd = pd[t] - sd, rw = pw[t] - sw, rv = pv[t] - sv;
+  for (int64_t b = lo; b < hi; ++b) {
+    const int64_t d = blk[b * 4], v = blk[b * 4 + 1], w = blk[b * 4 + 2];
+    if (rd + d > cap) atomicMin(&cut_blk, (unsigned long long)b);
+    blk[b * 4] = rd; blk[b * 4 + 1] = rv; blk[b * 4 + 2] = rw;
+    rd += d; rv += v; rw += w;
   }
   __syncthreads();
-  const int64_t cut = overflow_at;
-  const int64_t items = (cut < nq) ? first[cut] : part[1023];
-  unsigned long long nv = 0;
-  int64_t w = 0;
-  for (int64_t i = lo; i < hi; ++i) {
-    if (i >= cut) st_weff[i] = 0;
-    else nv += (unsigned long long)vecs[i];
-    w += st_weff[i];
+  const int64_t cb = (int64_t)cut_blk;
+  if (cb < nb && t < PLAN_BLOCK) {
+    const int64_t q = cb * PLAN_BLOCK + t;
+    if (q < nq && blk[cb * 4] + loc_item[q] + demand[q] > cap) atomicMin(&cut_q, (unsigned long long)q);
   }
-  atomicAdd(&nvecs, nv);
   __syncthreads();
-  // second scan: (query, partition) pairs of the queries that run this round
-  part[t] = w;
+  const int64_t cut = (int64_t)cut_q;
+  if (cb < nb && t < PLAN_BLOCK) {
+    const int64_t q = cb * PLAN_BLOCK + t;
+    if (q < cut && q < nq) atomicAdd(&nv_tail, (unsigned long long)vecs[q]);
+  }
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int64_t v = (t >= o) ? part[t - o] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  run = part[t] - w;
-  for (int64_t i = lo; i < hi; ++i) {
-    first_pair[i] = run;
-    run += st_weff[i];
-  }
   if (t == 0) {
+    int64_t items, nvec, pairs;
+    if (cut < nq) {
+      items = blk[cb * 4] + loc_item[cut];
+      nvec = blk[cb * 4 + 1] + (int64_t)nv_tail;
+      pairs = blk[cb * 4 + 2] + loc_pair[cut];
+    } else {
+      items = pd[1023];
+      nvec = pv[1023];
+      pairs = pw[1023];
+    }
     total[0] = items;
-    total[1] = (int64_t)nvecs;
-    total[2] = part[1023];
-    total[6] += (int64_t)nvecs;
-    total[7] = 0;  // head of the plain scan's item queue
+    total[1] = nvec;
+    total[2] = pairs;
+    total[6] += nvec;
+    total[7] = 0;    // head of the plain scan's item queue
+    total[8] = cut;  // first query that sits this round out
   }
+}
+
+__global__ __launch_bounds__(PLAN_BLOCK) void k_place(int64_t nq, const int64_t* __restrict__ blk,
+                                                       const int64_t* __restrict__ total,
+                                                       int64_t* __restrict__ st_item, int64_t* __restrict__ st_pair,
+                                                       int32_t* __restrict__ st_weff) {
+  const int64_t q = (int64_t)blockIdx.x * PLAN_BLOCK + threadIdx.x;
+  if (q >= nq) return;
+  const int64_t b = blockIdx.x;
+  st_item[q] += blk[b * 4];
+  st_pair[q] += blk[b * 4 + 2];
+  if (q >= total[8]) st_weff[q] = 0;
 }
 
 void launch_demand(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_demand, dim3((unsigned)((a.nq + 255) / 256)), dim3(256), 0, s, a.nq, a.M, a.chunk_tiles, ws.mq,
-                     ws.cand, st.d_size, ws.st_m, ws.st_w, ws.st_weff, ws.st_done, ws.st_demand, ws.st_vecs);
+  if (a.nq <= 0) return;
+  const unsigned nb = (unsigned)((a.nq + PLAN_BLOCK - 1) / PLAN_BLOCK);
+  hipLaunchKernelGGL(k_demand, dim3(nb), dim3(PLAN_BLOCK), 0, s, a.nq, a.M, a.chunk_tiles, ws.mq, ws.cand, st.d_size,
+                     ws.st_m, ws.st_w, ws.st_weff, ws.st_done, ws.st_demand, ws.st_vecs, ws.st_item, ws.st_pair,
+                     ws.blk);
   hipLaunchKernelGGL(k_prefix, dim3(1), dim3(1024), 0, s, a.nq, a.items_cap, ws.st_demand, ws.st_vecs, ws.st_item,
-                     ws.st_weff, ws.st_pair, ws.total);
+                     ws.st_pair, ws.blk, ws.total);
+  hipLaunchKernelGGL(k_place, dim3(nb), dim3(PLAN_BLOCK), 0, s, a.nq, ws.blk, ws.total, ws.st_item, ws.st_pair,
+                     ws.st_weff);
 }
 
 // Write the work items of each query's window, in candidate order.
@@ -442,30 +508,88 @@ __device__ int predict_window(const Model& md, const float* __restrict__ hq, int
   return M - from;
 }
 
+// A query's committed list in LDS (one wave per query, lists up to LMAX).
 template <int LMAX>
-__global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, const int32_t* __restrict__ mq, int k, int kk,
-                                                int aps, int ip, int chunk_tiles,
-                                                int wmax, double tau_r, double tau_rho,
-                                                const int32_t* __restrict__ cand, const float* __restrict__ hcand,
-                                                const int32_t* __restrict__ psize, const double* __restrict__ qn2,
-                                                const float* __restrict__ pk, const int64_t* __restrict__ pi,
-                                                const double* __restrict__ table, int32_t* __restrict__ st_m,
-                                                int32_t* __restrict__ st_w, int32_t* __restrict__ st_done,
-                                                const int32_t* __restrict__ st_weff,
-                                                const int64_t* __restrict__ st_item, double* __restrict__ st_rho,
-                                                double* __restrict__ st_p0, double* __restrict__ st_V,
-                                                double* __restrict__ st_vsum, double* __restrict__ st_r,
-                                                float* __restrict__ rk, int64_t* __restrict__ ri) {
-  __shared__ float Ak[LMAX], Bk[LMAX], Ok[LMAX];
-  __shared__ int64_t Ai[LMAX], Bi[LMAX], Oi[LMAX];
-  const int64_t q = blockIdx.x;
-  const int lane = threadIdx.x;
+struct LdsList {
+  float *Ak, *Bk, *Ok;
+  int64_t *Ai, *Bi, *Oi;
+  int kk;
+  __device__ void load(const float* rk, const int64_t* ri) {
+    for (int e = lane_id(); e < kk; e += WAVE) { Ak[e] = rk[e]; Ai[e] = ri[e]; }
+  }
+  __device__ void prime(const float*, const int64_t*) {}
+  // merge partial list `cur`; `next` (or null) is the one after it
+  __device__ void merge(const float* ck, const int64_t* ci, const float*, const int64_t*) {
+    const int lane = lane_id();
+    for (int e = lane; e < kk; e += WAVE) { Bk[e] = ck[e]; Bi[e] = ci[e]; }
+    __syncthreads();
+    wave_merge(Ak, Ai, Bk, Bi, Ok, Oi, kk);
+    __syncthreads();
+    for (int e = lane; e < kk; e += WAVE) { Ak[e] = Ok[e]; Ai[e] = Oi[e]; }
+    __syncthreads();
+  }
+  __device__ float key(int j) const { return Ak[j]; }
+  __device__ int64_t id(int j) const { return Ai[j]; }
+  __device__ void store(float* rk, int64_t* ri) const {
+    for (int e = lane_id(); e < kk; e += WAVE) { rk[e] = Ak[e]; ri[e] = Ai[e]; }
+  }
+};
+
+// A query's committed list in registers, entry j in lane j (kk <= 64); the
+// next partial list is loaded while the current one merges.
+struct RegList {
+  float k, nk;
+  int64_t i, ni;
+  int kk;
+  __device__ void load(const float* rk, const int64_t* ri) {
+    const int lane = lane_id();
+    k = lane < kk ? rk[lane] : KEY_EMPTY;
+    i = lane < kk ? ri[lane] : -1;
+  }
+  __device__ void prime(const float* pk, const int64_t* pi) {
+    const int lane = lane_id();
+    nk = lane < kk ? pk[lane] : KEY_EMPTY;
+    ni = lane < kk ? pi[lane] : -1;
+  }
+  __device__ void merge(const float*, const int64_t*, const float* next_k, const int64_t* next_i) {
+    const float bk = nk;
+    const int64_t bi = ni;
+    if (next_k) prime(next_k, next_i);
+    wave_merge64_kv(k, i, bk, bi);
+  }
+  __device__ float key(int j) const { return readlane_f(k, j); }
+  __device__ int64_t id(int j) const { return readlane_i64(i, j); }
+  __device__ void store(float* rk, int64_t* ri) const {
+    const int lane = lane_id();
+    if (lane < kk) { rk[lane] = k; ri[lane] = i; }
+  }
+};
+
+// Commit one query's window in candidate order: merge each work item's
+// partial list into the committed list; after each partition, update the
+// recall model (recompute when rho moved by more than tau_rho * rho) and stop
+// once the estimate reaches the target.  Partitions of the window after the
+// stop point are discarded.  Then predict the next window.
+template <class List>
+__device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restrict__ mq, int k, int kk, int aps,
+                             int ip, int chunk_tiles, int wmax, double tau_r, double tau_rho,
+                             const int32_t* __restrict__ cand, const float* __restrict__ hcand,
+                             const int32_t* __restrict__ psize, const double* __restrict__ qn2,
+                             const float* __restrict__ pk, const int64_t* __restrict__ pi,
+                             const double* __restrict__ table, int32_t* __restrict__ st_m, int32_t* __restrict__ st_w,
+                             int32_t* __restrict__ st_done, const int32_t* __restrict__ st_weff,
+                             const int64_t* __restrict__ st_item, double* __restrict__ st_rho,
+                             double* __restrict__ st_p0, double* __restrict__ st_V, double* __restrict__ st_vsum,
+                             double* __restrict__ st_r, float* __restrict__ rk, int64_t* __restrict__ ri) {
+  const int lane = lane_id();
   const int w = st_weff[q];
-  if (st_done[q] || w == 0) return;
-  for (int e = lane; e < kk; e += WAVE) { Ak[e] = rk[q * kk + e]; Ai[e] = ri[q * kk + e]; }
+  L.load(rk + q * kk, ri + q * kk);
   const int m0 = st_m[q];
   const int Mq = mq[q];
   int64_t it = st_item[q];
+  int64_t it_end = it;
+  for (int j = 0; j < w; ++j) it_end += item_chunks(psize[cand[q * M + m0 + j]], chunk_tiles);
+  L.prime(pk + it * kk, pi + it * kk);
   Model md{st_rho[q], st_p0[q], st_V[q], st_vsum[q]};
   const double qn = ip ? qn2[q] : 0.0;
   const float* hq = hcand + q * M;
@@ -476,17 +600,14 @@ __global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, const int32_t*
     const int p = cand[q * M + m0 + j];
     const int nch = item_chunks(psize[p], chunk_tiles);
     for (int c = 0; c < nch; ++c, ++it) {
-      for (int e = lane; e < kk; e += WAVE) { Bk[e] = pk[it * kk + e]; Bi[e] = pi[it * kk + e]; }
-      __syncthreads();
-      wave_merge(Ak, Ai, Bk, Bi, Ok, Oi, kk);
-      __syncthreads();
-      for (int e = lane; e < kk; e += WAVE) { Ak[e] = Ok[e]; Ai[e] = Oi[e]; }
-      __syncthreads();
+      const bool more = it + 1 < it_end;
+      L.merge(pk + it * kk, pi + it * kk, more ? pk + (it + 1) * kk : nullptr, more ? pi + (it + 1) * kk : nullptr);
     }
     committed = m0 + j + 1;
     if (!aps) continue;
-    const bool full = Ai[k - 1] >= 0;
-    const double rho_new = full ? key_radius(Ak[k - 1], ip, qn) : __builtin_inf();
+    const int64_t kth_id = L.id(k - 1);
+    const bool full = kth_id >= 0;
+    const double rho_new = full ? key_radius(L.key(k - 1), ip, qn) : __builtin_inf();
     if (committed == 1) {
       recompute_model(md, rho_new, hq, Mq, committed, table);
     } else {
@@ -505,12 +626,12 @@ __global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, const int32_t*
   const bool done = stop || committed >= Mq;
   int wn = 0;
   if (!done) {
-    if (aps && Ai[k - 1] >= 0) wn = predict_window(md, hq, Mq, committed, tau_r, table);
+    if (aps && L.id(k - 1) >= 0) wn = predict_window(md, hq, Mq, committed, tau_r, table);
     else wn = 2 * w;
     if (wn < 1) wn = 1;
     if (wn > wmax) wn = wmax;
   }
-  for (int e = lane; e < kk; e += WAVE) { rk[q * kk + e] = Ak[e]; ri[q * kk + e] = Ai[e]; }
+  L.store(rk + q * kk, ri + q * kk);
   if (lane == 0) {
     st_m[q] = committed;
     st_w[q] = wn;
@@ -520,14 +641,50 @@ __global__ __launch_bounds__(64) void k_commit(int64_t nq, int M, const int32_t*
   }
 }
 
+#define QK_COMMIT_PARAMS                                                                                          \
+  int64_t nq, int M, const int32_t *__restrict__ mq, int k, int kk, int aps, int ip, int chunk_tiles, int wmax,  \
+      double tau_r, double tau_rho, const int32_t *__restrict__ cand, const float *__restrict__ hcand,            \
+      const int32_t *__restrict__ psize, const double *__restrict__ qn2, const float *__restrict__ pk,            \
+      const int64_t *__restrict__ pi, const double *__restrict__ table, int32_t *__restrict__ st_m,              \
+      int32_t *__restrict__ st_w, int32_t *__restrict__ st_done, const int32_t *__restrict__ st_weff,            \
+      const int64_t *__restrict__ st_item, double *__restrict__ st_rho, double *__restrict__ st_p0,              \
+      double *__restrict__ st_V, double *__restrict__ st_vsum, double *__restrict__ st_r, float *__restrict__ rk, \
+      int64_t *__restrict__ ri
+#define QK_COMMIT_ARGS                                                                                        \
+  M, mq, k, kk, aps, ip, chunk_tiles, wmax, tau_r, tau_rho, cand, hcand, psize, qn2, pk, pi, table, st_m, st_w, \
+      st_done, st_weff, st_item, st_rho, st_p0, st_V, st_vsum, st_r, rk, ri
+
+// Lists longer than a wave: one 64-thread block per query, lists in LDS.
+template <int LMAX>
+__global__ __launch_bounds__(64) void k_commit(QK_COMMIT_PARAMS) {
+  __shared__ float Ak[LMAX], Bk[LMAX], Ok[LMAX];
+  __shared__ int64_t Ai[LMAX], Bi[LMAX], Oi[LMAX];
+  const int64_t q = blockIdx.x;
+  if (st_done[q] || st_weff[q] == 0) return;
+  LdsList<LMAX> L{Ak, Bk, Ok, Ai, Bi, Oi, kk};
+  commit_query(q, L, QK_COMMIT_ARGS);
+}
+
+// Lists of at most 64 entries: one wave per query, four queries per block,
+// lists in registers.
+__global__ __launch_bounds__(256) void k_commit64(QK_COMMIT_PARAMS) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= nq || st_done[q] || st_weff[q] == 0) return;
+  RegList L;
+  L.kk = kk;
+  commit_query(q, L, QK_COMMIT_ARGS);
+}
+
 void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const double* table, hipStream_t s) {
-#define QK_COMMIT(L)                                                                                             \
-  hipLaunchKernelGGL((k_commit<L>), dim3((unsigned)a.nq), dim3(64), 0, s, a.nq, a.M, ws.mq, a.k, a.kk, a.aps,    \
-                     a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.tau_r, a.tau_rho, ws.cand, ws.h,     \
-                     st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_weff, ws.st_item, \
-                     ws.st_rho, ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri)
-  if (a.kk <= KMAX) QK_COMMIT(KMAX);
-  else QK_COMMIT(KMAX_LARGE);
+  if (a.nq <= 0) return;
+#define QK_COMMIT(KERNEL, GRID, BLOCK)                                                                        \
+  hipLaunchKernelGGL(KERNEL, dim3((unsigned)(GRID)), dim3(BLOCK), 0, s, a.nq, a.M, ws.mq, a.k, a.kk, a.aps,    \
+                     a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.tau_r, a.tau_rho, ws.cand, ws.h,  \
+                     st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_weff,        \
+                     ws.st_item, ws.st_rho, ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri)
+  if (a.kk <= WAVE) QK_COMMIT(k_commit64, (a.nq + 3) / 4, 256);
+  else if (a.kk <= KMAX) QK_COMMIT(k_commit<KMAX>, a.nq, 64);
+  else QK_COMMIT(k_commit<KMAX_LARGE>, a.nq, 64);
 #undef QK_COMMIT
 }
 

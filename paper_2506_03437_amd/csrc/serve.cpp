@@ -138,7 +138,7 @@ struct quake_server {
     qk::ensure_queries(idx, cap);
     qk::ensure_workspace(idx, st().nlist, job.M, job.kk, items, job.batched ? cap * (int64_t)job.wmax : 0,
                          job.batched ? st().dp16 : 0, false);
-    QK_HIP(hipMemsetAsync(idx->ws.total, 0, 8 * sizeof(int64_t), s));
+    QK_HIP(hipMemsetAsync(idx->ws.total, 0, qk::COUNTERS * sizeof(int64_t), s));
     qk::launch_mark_free(idx->ws, cap, s);
     blocks = qk::scan_blocks(idx, job.batched);
     QK_HIP(hipStreamSynchronize(s));
@@ -157,15 +157,9 @@ struct quake_server {
     qk::launch_rows_to_slots(d_x, n, d, dp, d_slots, w.q, w.qn2, s);
     qk::launch_pad_rows(d_x, n, d, dp, d_pad, d_n2, s);
     qk::launch_scores(d_pad, n, st().centroids, st().nlist, dp, idx->metric, d_scores, s);
-    if (job.aps) {
-      qk::launch_fill_i32(d_mq, n, job.M, s);
-      qk::launch_select(d_scores, n, st().nlist, job.M, idx->metric, d_sel, s);
-      qk::launch_geometry(d_pad, st().centroids, n, dp, job.M, d_mq, idx->metric, d_sel, d_cand, d_h, s);
-      qk::launch_candidates_to_slots(d_cand, d_h, n, job.M, d_slots, w.cand, w.h, w.mq, s);
-    } else {
-      qk::launch_select(d_scores, n, st().nlist, job.M, idx->metric, d_cand, s);
-      qk::launch_candidates_to_slots(d_cand, nullptr, n, job.M, d_slots, w.cand, w.h, w.mq, s);
-    }
+    qk::launch_fill_i32(d_mq, n, job.M, s);
+    qk::launch_candidates(st(), d_pad, d_scores, n, dp, job.M, job.aps, idx->metric, d_mq, d_sel, d_cand, d_h, s);
+    qk::launch_candidates_to_slots(d_cand, job.aps ? d_h : nullptr, n, job.M, d_slots, w.cand, w.h, w.mq, s);
     if (job.batched) qk::launch_queries16(w, n, dp, st().dp16, job.dtype16, s, d_slots);
     qk::launch_init_slots(w, d_slots, n, job.kk, job.w0, s);
   }
