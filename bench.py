@@ -17,9 +17,12 @@ region starts.
 
 `value` is the batched BF16 path's QPS over the timed steps; the plain FP32
 path is reported beside it.  Kernel durations come from a second pass over
-the same steps with the library's HIP-event profiler on.  The roofline object is the batched path's scan kernel
-(algorithmic bytes = distinct vector reads * d * 2, flops = 2 * d * query-
-vector products, over its HIP-event time on the search stream); the plain
+the same steps with the library's HIP-event profiler on.  Before timing, each
+path's scheduling knobs (work-item size, grid, rounds between host checks,
+windows; never the results) are autotuned on a separate seeded query batch.
+The roofline object is the batched path's scan kernel (algorithmic bytes =
+vectors read once per 64-query set * d * 2, flops = 2 * d * query-vector
+products, over its HIP-event time on the search stream); the plain
 FP32 scan's HBM roofline sits under `plain_fp32`.  The CPU oracle is timed on
 a bounded sample of the same queries.
 """
@@ -178,6 +181,7 @@ def main():
     ap.add_argument("--recall-sample", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recall-target", type=float, default=0.0, help="skip the sweep and use this target")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default scheduling knobs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy a BYTES-long device buffer 5 times (calibrates HBM byte counters) and exit")
     ap.add_argument("--serving-requests", type=int, default=40_000, help="0 skips the serving-loop leg")
@@ -219,6 +223,7 @@ def main():
     torch.cuda.synchronize()
     log(f"built {w.nlist} partitions in {time.perf_counter() - t0:.1f} s")
     Qd = torch.from_numpy(Q).to(dev)
+    Qtune = torch.from_numpy(synth.queries(w.spec, w.nq, noise_std=w.query_noise, stream_chunk=1)).to(dev)
     rng = np.random.default_rng(7)
     sample_rows = np.sort(rng.choice(w.nq, size=min(args.recall_sample, w.nq), replace=False))
 
@@ -252,6 +257,12 @@ def main():
                     f"{ns.float().mean().item():.2f}")
                 if rec >= 0.9:
                     break
+        knobs = None
+        if not args.no_autotune:
+            # scheduling knobs (never the results) tuned on a separate seeded batch
+            knobs, tuned_ms = idx.autotune(Qtune, reps=2 if path.startswith("batched") else 1, k=w.k,
+                                           recall_target=tau, f_M=w.f_M, **paths[path])
+            log(f"{path}: autotuned {knobs} ({tuned_ms:.2f} ms per search on the tuning batch)")
         for _ in range(args.warmup):
             run(path, tau)
         torch.cuda.synchronize()
@@ -289,6 +300,7 @@ def main():
             "scan_bytes_per_launch": nbytes / max(launches, 1),
             "scan_flops_per_launch": flops / max(launches, 1),
             "kernels_ms_per_step": {k: v[1] / args.steps for k, v in prof.items() if v[0]},
+            "tuning": knobs,
         }
         log(f"{path}: {res['qps']:.0f} QPS, {res['ms_per_step']:.2f} ms/step "
             f"({res['ms_per_step_profiled']:.2f} profiled), recall {rec}")

@@ -151,12 +151,24 @@ typedef struct {
   int32_t chunk_tiles;   /* store tiles (64 vectors each) per work item; default 16 */
   int32_t first_window;  /* APS: partitions per query in the first round; default 2 */
   int32_t max_window;    /* APS: most partitions per query in one round; default 32 */
-  int32_t blocks_per_cu; /* persistent scan grid, blocks of 4 waves per compute unit; default 2 (MFMA) / 8 (FP32) */
+  int32_t blocks_per_cu; /* persistent scan grid, blocks of 4 waves per compute unit; default 1 (MFMA) / 8 (FP32) */
   int64_t max_items;     /* work items per round (bounds the scratch memory); default from nq */
   int32_t rounds_per_sync; /* rounds enqueued between host checks for completion; default 1, 2, 4, then 8 */
   int32_t no_graph;      /* 1: launch every round's kernels; default 0 replays captured HIP graphs of rounds */
 } quake_tuning;
 int quake_set_tuning(quake_index* index, const quake_tuning* tuning);
+
+/* Autotuner: times searches of the sample queries q[nq][d] (device) with
+ * `params` under candidate settings of the knobs above (work-item size,
+ * rounds between host checks, persistent grid size, first and largest
+ * window), by coordinate descent from the current settings (median of
+ * `reps` timed searches per candidate, 0 -> 3; a change must be 1% faster),
+ * and leaves the fastest set on the index.  Writes the chosen knobs to *out
+ * and their median search time in milliseconds to *ms (both optional).
+ * Results never depend on these knobs, only the time does.  Errors as for
+ * quake_search; on error the previous knobs are restored. */
+int quake_autotune(quake_index* index, const float* q, int64_t nq, const quake_search_params* params, int32_t reps,
+                   quake_tuning* out, double* ms, void* stream);
 
 /* Kernel timing of searches, for roofline measurement.  With enable = 1 the
  * library records HIP events on the search stream around each kernel class

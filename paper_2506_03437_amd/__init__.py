@@ -9,6 +9,7 @@ from .quake import (  # noqa: F401
     QuakeError,
     Server,
     load_library,
+    quake_autotune,
     quake_build,
     quake_candidates,
     quake_cap_table,

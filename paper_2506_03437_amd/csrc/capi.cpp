@@ -519,11 +519,13 @@ void ensure_workspace(quake_index* idx, int64_t nc, int64_t M, int64_t kk, int64
     w.ri = mem.alloc<int64_t>(w.kk_cap);
   }
   if (items > w.items_cap || kk > w.k_cap || !w.items) {
-    mem.release(w.items); mem.release(w.pk); mem.release(w.pi);
-    w.items = nullptr; w.pk = nullptr; w.pi = nullptr;
+    mem.release(w.items); mem.release(w.pk); mem.release(w.pi); mem.release(w.bitems);
+    w.items = nullptr; w.pk = nullptr; w.pi = nullptr; w.bitems = nullptr;
     w.items_cap = std::max(items, w.items_cap);
     w.k_cap = std::max<int64_t>(kk, w.k_cap);
     w.items = mem.alloc<int4>(w.items_cap);
+    // batched items never outnumber the plain ones (one per query set, not per query)
+    w.bitems = mem.alloc<int4>(2 * w.items_cap);
     w.pk = mem.alloc<float>((size_t)w.items_cap * w.k_cap);
     w.pi = mem.alloc<int64_t>((size_t)w.items_cap * w.k_cap);
   }
@@ -537,7 +539,8 @@ void ensure_workspace(quake_index* idx, int64_t nc, int64_t M, int64_t kk, int64
     w.q16_dim = dp16;
   }
   if (pairs > w.pairs_cap || !w.pair_q) {
-    for (void* p : {(void*)w.pair_q, (void*)w.pair_p, (void*)w.pair_pos, (void*)w.pair_base, (void*)w.sorted})
+    for (void* p : {(void*)w.pair_q, (void*)w.pair_p, (void*)w.pair_pos, (void*)w.pair_base, (void*)w.sorted,
+                    (void*)w.sorted_q, (void*)w.sorted_base})
       mem.release(p);
     w.pairs_cap = std::max<int64_t>(pairs, 1);
     w.pair_q = mem.alloc<int32_t>(w.pairs_cap);
@@ -545,6 +548,8 @@ void ensure_workspace(quake_index* idx, int64_t nc, int64_t M, int64_t kk, int64
     w.pair_pos = mem.alloc<int32_t>(w.pairs_cap);
     w.pair_base = mem.alloc<int64_t>(w.pairs_cap);
     w.sorted = mem.alloc<int32_t>(w.pairs_cap);
+    w.sorted_q = mem.alloc<int32_t>(w.pairs_cap);
+    w.sorted_base = mem.alloc<int64_t>(w.pairs_cap);
   }
   if (nc + 1 > w.parts_cap || !w.pcount) {
     for (void* p : {(void*)w.pcount, (void*)w.pstart, (void*)w.pitem}) mem.release(p);
@@ -562,7 +567,7 @@ int scan_blocks(quake_index* idx, int batched) {
     QK_HIP(hipGetDevice(&dev));
     QK_HIP(hipDeviceGetAttribute(&idx->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
   }
-  const int per = idx->tune.blocks_per_cu > 0 ? idx->tune.blocks_per_cu : (batched ? 2 : 8);
+  const int per = idx->tune.blocks_per_cu > 0 ? idx->tune.blocks_per_cu : (batched ? 1 : 8);
   return std::max(idx->cu_count, 8) * per;
 }
 
@@ -606,7 +611,7 @@ std::vector<uint64_t> graph_key(const quake_index* idx, const Store& st, const J
       u(st.v16), u(st.v16n), u(st.rows32), u(st.ids), u(w.q), u(w.qn2), u(w.cand), u(w.mq), u(w.h), u(w.st_m),
       u(w.st_w), u(w.st_weff), u(w.st_done), u(w.st_item), u(w.st_demand), u(w.st_rho), u(w.st_p0), u(w.st_V),
       u(w.st_vsum), u(w.st_r), u(w.rk), u(w.ri), u(w.items), u(w.pk), u(w.pi), u(w.st_vecs), u(w.st_pair),
-      u(w.q16), u(w.qn2f), u(w.pair_q), u(w.pair_p), u(w.pair_pos), u(w.pair_base), u(w.sorted), u(w.pcount),
+      u(w.q16), u(w.qn2f), u(w.pair_q), u(w.pair_p), u(w.pair_pos), u(w.pair_base), u(w.sorted), u(w.sorted_q), u(w.sorted_base), u(w.bitems), u(w.pcount),
       u(w.pstart), u(w.pitem), u(w.total), u(w.blk)};
   uint64_t tr, tro;
   std::memcpy(&tr, &a.tau_r, 8);
@@ -947,6 +952,88 @@ int quake_set_tuning(quake_index* idx, const quake_tuning* t) {
                t->blocks_per_cu >= 0 && t->rounds_per_sync >= 0 && t->no_graph >= 0,
            QUAKE_E_INVALID, "tuning values must be >= 0");
   idx->tune = *t;
+  API_END
+}
+
+int quake_autotune(quake_index* idx, const float* q, int64_t nq, const quake_search_params* params, int32_t reps,
+                   quake_tuning* out, double* out_ms, void* stream) {
+  API_BEGIN
+  check_index(idx);
+  QK_CHECK(nq >= 1 && q, QUAKE_E_INVALID, "autotuning needs sample queries");
+  QK_CHECK(reps >= 0, QUAKE_E_INVALID, "reps must be >= 0");
+  const Job job = resolve(idx, idx->L0, params);
+  hipStream_t s = as_stream(stream);
+  const int R = reps > 0 ? reps : 3;
+  Tmp<int64_t> ids(idx->mem, (size_t)nq * job.k);
+  Tmp<float> dist(idx->mem, (size_t)nq * job.k);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  QK_HIP(hipEventCreate(&e0));
+  QK_HIP(hipEventCreate(&e1));
+  const quake_tuning saved = idx->tune;
+  const bool prof = idx->prof.on;
+  idx->prof.on = false;
+  auto search = [&]() {
+    const int rc = quake_search(idx, q, nq, params, ids.p, dist.p, nullptr, nullptr, stream);
+    if (rc != QUAKE_OK) throw qk::Error{rc, qk::g_error};
+  };
+  // median wall time of R searches under tuning t (after one warm-up search
+  // that grows buffers and captures graphs)
+  auto time_it = [&](const quake_tuning& t) {
+    idx->tune = t;
+    search();
+    std::vector<double> ms;
+    for (int r = 0; r < R; ++r) {
+      QK_HIP(hipEventRecord(e0, s));
+      search();
+      QK_HIP(hipEventRecord(e1, s));
+      QK_HIP(hipEventSynchronize(e1));
+      float v = 0.f;
+      QK_HIP(hipEventElapsedTime(&v, e0, e1));
+      ms.push_back(v);
+    }
+    std::sort(ms.begin(), ms.end());
+    return ms[ms.size() / 2];
+  };
+  try {
+    // coordinate descent over the knobs, twice; a change must win by 1%
+    quake_tuning best = saved;
+    double best_ms = time_it(best);
+    struct Knob {
+      int32_t quake_tuning::*field;
+      std::vector<int32_t> values;
+    };
+    std::vector<Knob> knobs = {{&quake_tuning::chunk_tiles, {8, 16, 32, 64, 128}},
+                               {&quake_tuning::rounds_per_sync, {0, 2, 4, 8}}};
+    if (job.batched)
+      knobs.push_back({&quake_tuning::blocks_per_cu, {1, 2}});
+    else
+      knobs.push_back({&quake_tuning::blocks_per_cu, {4, 8, 16}});
+    if (job.aps) {
+      knobs.push_back({&quake_tuning::first_window, {1, 2, 4, 8}});
+      knobs.push_back({&quake_tuning::max_window, {8, 16, 32, 64}});
+    }
+    for (int pass = 0; pass < 2; ++pass)
+      for (const Knob& kn : knobs)
+        for (int32_t v : kn.values) {
+          if (best.*kn.field == v) continue;
+          quake_tuning t = best;
+          t.*kn.field = v;
+          const double ms = time_it(t);
+          if (ms < 0.99 * best_ms) { best = t; best_ms = ms; }
+        }
+    idx->tune = best;
+    idx->prof.on = prof;
+    if (out) *out = best;
+    if (out_ms) *out_ms = best_ms;
+  } catch (...) {
+    idx->tune = saved;
+    idx->prof.on = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   API_END
 }
 

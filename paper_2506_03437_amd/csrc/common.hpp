@@ -26,6 +26,11 @@ __device__ __forceinline__ uint32_t float_order(float f) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
+// Inverse of float_order.
+__device__ __forceinline__ float float_from_order(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
 __device__ __forceinline__ int64_t shfl_up_i64(int64_t v, int delta) {
   int lo = __shfl_up((int)(uint32_t)(uint64_t)v, delta);
   int hi = __shfl_up((int)(uint32_t)((uint64_t)v >> 32), delta);
@@ -242,6 +247,56 @@ __device__ __forceinline__ void wave_merge64(float& lk, int32_t& ls, float bk, i
   swap_if(ks_less(rk, rs, lk, ls), lk, ls, rk, rs);
 #pragma unroll
   for (int stride = WAVE / 2; stride > 0; stride >>= 1) bitonic_step(lk, ls, WAVE, stride);
+}
+
+// N independent lists at once (one entry per lane in each): the shuffles of
+// the N lists are independent, so their latencies overlap.
+template <int N>
+__device__ __forceinline__ void bitonic_step_n(float (&k)[N], int32_t (&s)[N], int size, int stride) {
+  const int lane = lane_id();
+  float ok[N];
+  int32_t os[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    ok[q] = __shfl_xor(k[q], stride);
+    os[q] = __shfl_xor(s[q], stride);
+  }
+  const bool up = (lane & size) == 0;
+  const bool lower = (lane & stride) == 0;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    const bool other_first = ks_less(ok[q], os[q], k[q], s[q]);
+    swap_if((lower == up) ? other_first : (!other_first && (ok[q] != k[q] || os[q] != s[q])), k[q], s[q], ok[q],
+            os[q]);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void wave_sort64_n(float (&k)[N], int32_t (&s)[N]) {
+#pragma unroll
+  for (int size = 2; size <= WAVE; size <<= 1)
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) bitonic_step_n<N>(k, s, size, stride);
+}
+
+// lists[q] := the 64 smallest of lists[q] and b[q] (both ascending), for q < N.
+template <int N>
+__device__ __forceinline__ void wave_merge64_n(float* lk, int32_t* ls, float (&bk)[N], int32_t (&bs)[N]) {
+  const int lane = lane_id();
+  float mk[N];
+  int32_t ms[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    const float rk = __shfl(bk[q], WAVE - 1 - lane);
+    const int32_t rs = __shfl(bs[q], WAVE - 1 - lane);
+    mk[q] = lk[q];
+    ms[q] = ls[q];
+    swap_if(ks_less(rk, rs, mk[q], ms[q]), mk[q], ms[q], rk, rs);
+  }
+#pragma unroll
+  for (int stride = WAVE / 2; stride > 0; stride >>= 1) bitonic_step_n<N>(mk, ms, WAVE, stride);
+#pragma unroll
+  for (int q = 0; q < N; ++q) { lk[q] = mk[q]; ls[q] = ms[q]; }
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));

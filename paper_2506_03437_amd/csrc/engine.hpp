@@ -7,6 +7,7 @@ namespace qk {
 
 // Records the message quake_last_error returns on this thread; returns code.
 int set_error(int code, const std::string& msg);
+extern thread_local std::string g_error;
 
 // Number of candidate partitions for a fraction f of n (ceil, at least 1,
 // at most n; the product is taken with a 1e-9 allowance so that 0.05 * 1000

@@ -41,7 +41,7 @@ inline int padded_dim16(int d) {
   return 32 * need;
 }
 constexpr int MAX_DIM = 4096;
-constexpr int COUNTERS = 16;      // device counters of a search (Workspace::total)
+constexpr int COUNTERS = 32;      // device counters of a search (Workspace::total)
 constexpr int MAX_CANDIDATES = 4096;   // APS candidate set M (and nprobe) upper bound
 
 // Device allocations of one index, counted against an optional budget.
@@ -134,6 +134,10 @@ struct Workspace {
   int32_t* pair_pos = nullptr;  // [pairs] place among the partition's pairs
   int64_t* pair_base = nullptr; // [pairs] first partial-list slot of the pair
   int32_t* sorted = nullptr;    // [pairs] pairs in partition order
+  int32_t* sorted_q = nullptr;  // [pairs] their queries
+  int64_t* sorted_base = nullptr;  // [pairs] their first partial-list slots
+  int4* bitems = nullptr;       // [items][2] batched work items: (partition, index in it, pairs, first pair),
+                                //   (vectors, first tile low, first tile high, query sets)
   int32_t* pcount = nullptr;    // [nlist] pairs per partition (kept zeroed between rounds)
   int32_t* pstart = nullptr;    // [nlist + 1]
   int64_t* pitem = nullptr;     // [nlist + 1] first batched work item of each partition
@@ -141,7 +145,8 @@ struct Workspace {
   // the round, [3] batched items of the round, [4] batched vector reads and
   // [5] batched query-vector products summed over the search, [6] plain-scan
   // vectors summed over the search, [7] head of the round's item queue,
-  // [8] first query cut from the round
+  // [8] first query cut from the round, [16..23] per-XCD item queues of the
+  // batched scan
   int64_t* total = nullptr;
   int64_t* blk = nullptr;       // [nq / 256 + 1][4] per-block planning sums, then offsets
   int64_t* h_total = nullptr;   // pinned host mirror

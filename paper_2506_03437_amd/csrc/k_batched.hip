@@ -22,7 +22,12 @@
 
 namespace qk {
 
-constexpr int G = 16;  // queries per work item (one MFMA column block)
+constexpr int G = 16;           // queries per wave (one MFMA column block)
+constexpr int SET_GROUPS = 4;   // query groups per block, one per wave
+constexpr int SET = G * SET_GROUPS;  // queries that share one read of a tile
+constexpr int BUF = 3 * WAVE;   // per-query candidate pool (three entries per lane; holds kk, slack and a tile)
+constexpr int SLACK = 16;       // entries a mid-item cut may keep beyond kk
+constexpr int QUEUE_X = 16;     // counters[16 .. 23]: per-XCD item queues of the batched scan
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
@@ -110,9 +115,9 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
     const int c = pcount[p];
     np += c;
     if (c > 0) {
-      const int groups = (c + G - 1) / G;
-      ni += (int64_t)groups * chunks_of(psize[p], chunk_tiles);
-      rd += (unsigned long long)groups * (unsigned long long)psize[p];
+      const int sets = (c + SET - 1) / SET;
+      ni += (int64_t)sets * chunks_of(psize[p], chunk_tiles);
+      rd += (unsigned long long)sets * (unsigned long long)psize[p];
       pd += (unsigned long long)c * (unsigned long long)psize[p];
     }
   }
@@ -134,7 +139,7 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
     pstart[p] = (int32_t)rp;
     pitem[p] = ri;
     rp += c;
-    if (c > 0) ri += (int64_t)((c + G - 1) / G) * chunks_of(psize[p], chunk_tiles);
+    if (c > 0) ri += (int64_t)((c + SET - 1) / SET) * chunks_of(psize[p], chunk_tiles);
     pcount[p] = 0;
   }
   atomicAdd(&reads, rd);
@@ -146,17 +151,47 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
     counters[3] = si[1023];
     counters[4] += (int64_t)reads;
     counters[5] += (int64_t)products;
+    for (int x = 0; x < 8; ++x) counters[QUEUE_X + x] = 0;
   }
 }
 
 __global__ __launch_bounds__(256) void k_pair_scatter(const int64_t* __restrict__ counters,
                                                        const int32_t* __restrict__ pair_p,
                                                        const int32_t* __restrict__ pair_pos,
+                                                       const int32_t* __restrict__ pair_q,
+                                                       const int64_t* __restrict__ pair_base,
                                                        const int32_t* __restrict__ pstart,
-                                                       int32_t* __restrict__ sorted) {
+                                                       int32_t* __restrict__ sorted, int32_t* __restrict__ sorted_q,
+                                                       int64_t* __restrict__ sorted_base) {
   const int64_t npairs = counters[2];
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < npairs; e += (int64_t)gridDim.x * 256)
-    sorted[pstart[pair_p[e]] + pair_pos[e]] = (int32_t)e;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < npairs; e += (int64_t)gridDim.x * 256) {
+    const int32_t pos = pstart[pair_p[e]] + pair_pos[e];
+    sorted[pos] = (int32_t)e;
+    sorted_q[pos] = pair_q[e];
+    sorted_base[pos] = pair_base[e];
+  }
+}
+
+// The batched work items of the round, two int4 each: (partition, index of
+// the item within it, its pairs, its first pair) and (its vectors, first
+// tile low and high halves, query sets).  Item `local` of a partition is
+// chunk local / sets, query set local % sets.
+__global__ __launch_bounds__(256) void k_items(int64_t N, int chunk_tiles, const int32_t* __restrict__ pstart,
+                                                const int64_t* __restrict__ pitem,
+                                                const int32_t* __restrict__ psize,
+                                                const int64_t* __restrict__ poff, int4* __restrict__ bitems) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= N) return;
+  const int np = pstart[p + 1] - pstart[p];
+  if (np == 0) return;
+  const int sets = (np + SET - 1) / SET;
+  const int n = (int)(pitem[p + 1] - pitem[p]);
+  const int64_t tile0 = poff[p];
+  const int4 b = make_int4(psize[p], (int)(uint32_t)(uint64_t)tile0, (int)(uint32_t)((uint64_t)tile0 >> 32), sets);
+  for (int local = 0; local < n; ++local) {
+    bitems[2 * (pitem[p] + local)] = make_int4((int)p, local, np, pstart[p]);
+    bitems[2 * (pitem[p] + local) + 1] = b;
+  }
 }
 
 void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
@@ -168,7 +203,10 @@ void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_
   // at most wmax pairs per query; the kernel reads this round's count
   const int64_t bound = (a.nq * a.wmax + 255) / 256;
   hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(bound, 2048))), dim3(256),
-                     0, s, ws.total, ws.pair_p, ws.pair_pos, ws.pstart, ws.sorted);
+                     0, s, ws.total, ws.pair_p, ws.pair_pos, ws.pair_q, ws.pair_base, ws.pstart, ws.sorted,
+                     ws.sorted_q, ws.sorted_base);
+  hipLaunchKernelGGL(k_items, dim3((unsigned)((st.nlist + 255) / 256)), dim3(256), 0, s, st.nlist, a.chunk_tiles,
+                     ws.pstart, ws.pitem, st.d_size, st.d_off, ws.bitems);
 }
 
 // ---------------------------------------------------------------- MFMA scan
@@ -184,183 +222,338 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
 }
 
 template <int F16, int KS, int IP>
-__global__ __launch_bounds__(256, 2) void k_scan_mfma(
-    const int64_t* __restrict__ counters, const int64_t* __restrict__ pitem, const int32_t* __restrict__ pstart,
-    const int32_t* __restrict__ sorted, const int32_t* __restrict__ pair_q, const int64_t* __restrict__ pair_base,
-    int64_t N, int chunk_tiles, const uint16_t* __restrict__ q16, int dp16, const float* __restrict__ qn2f,
-    const uint16_t* __restrict__ v16, const float* __restrict__ v16n, const int64_t* __restrict__ sid,
-    const int64_t* __restrict__ poff, const int32_t* __restrict__ psize, const float* __restrict__ rk,
-    const int64_t* __restrict__ ri, int kk, float* __restrict__ pk, int64_t* __restrict__ pi) {
-  __shared__ float S[4][G][TILE + 1];
-  __shared__ float BK[4][G][WAVE];      // per query: candidates that beat the threshold, not yet merged
-  __shared__ int32_t BS[4][G][WAVE];
-  __shared__ float TK[4][G];            // per query: key and slot a candidate must beat
-  __shared__ int32_t TS[4][G];
-  __shared__ int32_t CN[4][G];          // per query: candidates waiting in BK / BS
+__global__ __launch_bounds__(256, 1) void k_scan_mfma(
+    int64_t* __restrict__ counters, const int4* __restrict__ bitems, const int32_t* __restrict__ sorted_q,
+    const int64_t* __restrict__ sorted_base, int chunk_tiles, const uint16_t* __restrict__ q16, int dp16,
+    const float* __restrict__ qn2f, const uint16_t* __restrict__ v16, const float* __restrict__ v16n,
+    const int64_t* __restrict__ sid, const float* __restrict__ rk, const int64_t* __restrict__ ri, int kk,
+    float* __restrict__ pk, int64_t* __restrict__ pi) {
+  // k-steps per stage: the largest of 4, 2, 1 that leaves an even number of
+  // stages per tile, so that a tile always starts in LDS buffer 0
+  constexpr int KST = (KS % 8 == 0) ? 4 : ((KS % 4 == 0) ? 2 : 1);
+  constexpr int NS = KS / KST;                  // stages per tile
+  constexpr int SU = KST * 4 * TILE;            // 16-byte units per stage
+  constexpr int UPT = SU / 256;                 // units each thread carries per stage
+  // loads run DEPTH stages (TA whole tiles) ahead of the MFMAs, so that each
+  // block keeps 32-128 KiB of the store in flight
+  constexpr int TA = NS >= 4 ? 1 : 2;
+  constexpr int DEPTH = NS * TA;
+  static_assert(KS % KST == 0 && NS % 2 == 0 && SU % 256 == 0, "stage shape");
+  __shared__ u32x4 RING[2][SU];                 // two stages of the current tile
+  __shared__ float BK[4][G][BUF];               // per query: candidates that beat the threshold, not yet merged
+  __shared__ int32_t BS[4][G][BUF];
+  __shared__ int64_t next_item;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // consecutive logical blocks on one XCD (blocks are dealt to the 8 XCDs in turn)
-  int lb = blockIdx.x;
-  if ((gridDim.x & 7) == 0) lb = (blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);
+  // Blocks take items in order from one queue: items differ widely in cost
+  // (power-law partition sizes and query counts), so a static split would
+  // leave some compute units idle; the query sets of one chunk are
+  // consecutive items, scored at about the same time.
+  const int nx = 1;
+  const int xcd = 0;
   const int64_t total = counters[3];
-  const int64_t stride = (int64_t)gridDim.x * 4;
-  static_assert(KS >= 2, "the load pipeline runs two k-steps ahead");
+  const int64_t range_lo = total * xcd / nx, range_hi = total * (xcd + 1) / nx;
   constexpr int nc8 = KS * 4;  // 8-element chunks per row of the 16-bit copy
-  float (*Sw)[TILE + 1] = S[wave];
-  float (*Bk)[WAVE] = BK[wave];
-  int32_t (*Bs)[WAVE] = BS[wave];
-  float* Tk = TK[wave];
-  int32_t* Ts = TS[wave];
-  int32_t* Cn = CN[wave];
-  for (int64_t it = (int64_t)lb * 4 + wave; it < total; it += stride) {
-    int64_t lo = 0, hi = N;
-    while (hi - lo > 1) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (pitem[mid] <= it) lo = mid; else hi = mid;
-    }
-    const int p = __builtin_amdgcn_readfirstlane((int)lo);
-    const int size = psize[p];
+  float (*Bk)[BUF] = BK[wave];
+  int32_t (*Bs)[BUF] = BS[wave];
+  for (;;) {
+    // every thread has read next_item before the block's next barrier, and
+    // thread 0 writes it again only after that barrier
+    if (threadIdx.x == 0)
+      next_item = range_lo + (int64_t)atomicAdd((unsigned long long*)(counters + QUEUE_X + xcd), 1ull);
+    __syncthreads();
+    const int64_t it = next_item;
+    if (it >= range_hi) break;
+    const int4 d0 = bitems[2 * it], d1 = bitems[2 * it + 1];
+    const int local = __builtin_amdgcn_readfirstlane(d0.y);
+    const int np = __builtin_amdgcn_readfirstlane(d0.z);
+    const int pfirst = __builtin_amdgcn_readfirstlane(d0.w);
+    const int size = __builtin_amdgcn_readfirstlane(d1.x);
+    const int64_t tile0 = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane(d1.z) << 32) |
+                                    (uint32_t)__builtin_amdgcn_readfirstlane(d1.y));
+    const int nsets = __builtin_amdgcn_readfirstlane(d1.w);
     const int tiles = (size + TILE - 1) / TILE;
-    const int nch = chunks_of(size, chunk_tiles);
-    const int local = (int)(it - pitem[p]);
-    const int np = pstart[p + 1] - pstart[p];
-    // the query group runs fastest, so that the waves of a block and the
-    // neighbouring blocks on the same XCD score the same tiles together and
-    // share them through L2
-    const int ngroups = (np + G - 1) / G;
-    const int c = local / ngroups, g = local - (local / ngroups) * ngroups;
-    const int gcount = min(G, np - g * G);
+    // the query set runs fastest, so that the sets of one chunk are scored
+    // at about the same time
+    const int c = local / nsets, gs = local - (local / nsets) * nsets;
+    const int g = gs * SET_GROUPS + wave;
+    const int gcount = max(0, min(G, np - g * G));
     const int t0 = c * chunk_tiles;
     const int t1 = min(tiles, t0 + chunk_tiles);
     const int j = lane & (G - 1);
     const bool has = j < gcount;
-    const int pair = has ? sorted[pstart[p] + g * G + j] : 0;
-    const int qj = has ? pair_q[pair] : 0;
+    const int pidx = has ? pfirst + g * G + j : pfirst;  // a valid pair in every lane
+    const int qj = sorted_q[pidx];
+    // Stage u of the item = k-steps [KST (u % NS), +KST) of tile t0 + u / NS:
+    // SU contiguous 16-byte units of the store.  The block carries two stages
+    // in registers (loads in flight) and one in LDS (being scored).
+    const int U = (t1 - t0) * NS;
+    // stages past the item's end reload its last stage, and an empty item
+    // reads the arena's first tile (never used either)
+    const u32x4* src = reinterpret_cast<const u32x4*>(v16) + (U > 0 ? (tile0 + t0) * (int64_t)nc8 * TILE : 0);
+    auto load = [&](int u, u32x4 (&r)[UPT]) {
+      u = max(0, min(u, U - 1));
+      const u32x4* sp = src + (int64_t)(u / NS) * nc8 * TILE + (int64_t)(u % NS) * SU;
+#pragma unroll
+      for (int e = 0; e < UPT; ++e) r[e] = sp[e * 256 + threadIdx.x];
+    };
+    auto put = [&](const u32x4 (&r)[UPT], int buf) {
+#pragma unroll
+      for (int e = 0; e < UPT; ++e) RING[buf][e * 256 + threadIdx.x] = r[e];
+    };
+    // registers: stage u (u >= 1) waits in slot (u - 1) % DEPTH until it is
+    // moved to LDS buffer u % 2 at the end of stage u - 1; the first stages
+    // are requested before the queries so that both arrive together
+    u32x4 rs[DEPTH][UPT];
+    u32x4 first[UPT];
+    load(0, first);
+#pragma unroll
+    for (int d = 1; d <= DEPTH; ++d) load(d, rs[d - 1]);
+    // Loads in this kernel are unconditional (clamped to valid addresses
+    // and the result discarded where unused): a load under a branch leaves
+    // the compiler unsure how many loads are in flight, and it then waits
+    // for all of them - which would drain the prefetch pipeline below.
     u32x4 breg[KS];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      u32x4 b = {0u, 0u, 0u, 0u};
-      if (has) b = *reinterpret_cast<const u32x4*>(q16 + (int64_t)qj * dp16 + 32 * s + 8 * (lane >> 4));
-      breg[s] = b;
+      // columns of absent queries score row 0 and are never read
+      breg[s] = *reinterpret_cast<const u32x4*>(q16 + (int64_t)qj * dp16 + 32 * s + 8 * (lane >> 4));
     }
-    const float my_qn2 = (IP || !has) ? 0.f : qn2f[qj];
-    // per query: a sorted list of its 64 best (one entry per lane), the
-    // threshold a candidate must beat (the kk-th entry, or the seed from the
-    // query's committed results) and the fill of its LDS buffer
-    float lk[G];
-    int32_t ls[G];
+    const float qn2_row = qn2f[qj];
+    const float my_qn2 = (IP || !has) ? 0.f : qn2_row;
+    // Per query j of the wave: an unsorted pool of candidates in LDS
+    // (Bk[j] / Bs[j], cn of them) and - held by the four lanes whose MFMA
+    // output column is j (lanes j, j + 16, j + 32, j + 48) - the key and slot
+    // a candidate must beat: the seed from the query's committed results,
+    // then the kk-th best of the pool whenever the pool is compacted.
+    float tk;
+    int32_t ts;
+    int cn = 0;
+    {
+      const float sk = rk[(int64_t)qj * kk + kk - 1];
+      const int32_t ss = (int32_t)ri[(int64_t)qj * kk + kk - 1];
+      tk = has ? sk : -KEY_EMPTY;  // absent queries take nothing
+      ts = has ? ss : -1;
+    }
+    // Cut query jj's pool.  Mid-item (exact = false): keep the entries up to
+    // a key T that at least kk and at most kk + SLACK entries reach - T is
+    // found by bisection on the keys' order-preserving bits with ballot
+    // counts, stopping once the count lands in that window - and make T the
+    // threshold (every kept entry, and the final kk, are at most T).  At the
+    // end (exact = true): keep exactly the kk best in (key, slot) order,
+    // bisecting on the slot among ties of the kk-th key when needed.
+    constexpr int EPL = BUF / WAVE;  // pool entries per lane
+    auto compact = [&](int jj, bool exact) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      const int n = __builtin_amdgcn_readlane(cn, jj);
+      if (n <= kk) return;
+      const int slack = exact ? 0 : min(SLACK, BUF - WAVE - kk);
+      float kv[EPL];
+      int32_t sv[EPL];
+      uint32_t uv[EPL];
 #pragma unroll
-    for (int jj = 0; jj < G; ++jj) { lk[jj] = KEY_EMPTY; ls[jj] = -1; }
-    if (lane < G) {
-      float sk = -KEY_EMPTY;
-      int32_t ss = -1;
-      if (lane < gcount) {
-        sk = rk[(int64_t)qj * kk + kk - 1];
-        ss = (int32_t)ri[(int64_t)qj * kk + kk - 1];
+      for (int e = 0; e < EPL; ++e) {
+        const bool v = e * WAVE + lane < n;
+        kv[e] = v ? Bk[jj][e * WAVE + lane] : KEY_EMPTY;
+        sv[e] = v ? Bs[jj][e * WAVE + lane] : INT32_MAX;
+        uv[e] = v ? float_order(kv[e]) : 0xffffffffu;
       }
-      Tk[lane] = sk;
-      Ts[lane] = ss;
-      Cn[lane] = 0;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    auto flush = [&](int jj) {
+      auto count_le = [&](uint32_t x) {
+        int c = 0;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) c += __popcll(__ballot(uv[e] <= x));
+        return c;
+      };
+      uint32_t lo = 0, hi = 0xffffffffu;
+      while (lo < hi) {
+        const uint32_t mid = lo + ((hi - lo) >> 1);
+        const int c = count_le(mid);
+        if (c >= kk) {
+          hi = mid;
+          if (c <= kk + slack) break;
+        } else {
+          lo = mid + 1;
+        }
+      }
+      const uint32_t T = hi;
+      int32_t slo = INT32_MAX;
+      // many ties at T can leave more than kk + slack entries: cut exactly then
+      if (exact || count_le(T) > kk + slack) {
+        int less = 0, eq = 0;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          less += __popcll(__ballot(uv[e] < T));
+          eq += __popcll(__ballot(uv[e] == T));
+        }
+        const int need = kk - less;
+        if (eq > need) {
+          int32_t a = 0, b = INT32_MAX;
+          while (a < b) {
+            const int32_t mid = a + ((b - a) >> 1);
+            int c = 0;
+#pragma unroll
+            for (int e = 0; e < EPL; ++e) c += __popcll(__ballot(uv[e] == T && sv[e] <= mid));
+            if (c >= need) b = mid; else a = mid + 1;
+          }
+          slo = a;
+        }
+      }
+      int base = 0;
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      const int n = Cn[jj];
-      float bk = KEY_EMPTY;
-      int32_t bs = -1;
-      if (lane < n) { bk = Bk[jj][lane]; bs = Bs[jj][lane]; }
-      wave_sort64(bk, bs);
-      wave_merge64(lk[jj], ls[jj], bk, bs);
-      const int32_t ns = __builtin_amdgcn_readlane(ls[jj], kk - 1);
-      const float nk = readlane_f(lk[jj], kk - 1);
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      if (lane == 0) {
-        Cn[jj] = 0;
-        if (ns >= 0) { Tk[jj] = nk; Ts[jj] = ns; }
+#pragma unroll
+      for (int e = 0; e < EPL; ++e) {
+        const bool keep = uv[e] < T || (uv[e] == T && sv[e] <= slo);
+        const uint64_t m = __ballot(keep);
+        const int p = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (keep) { Bk[jj][p] = kv[e]; Bs[jj][p] = sv[e]; }
+        base += __popcll(m);
+      }
+      if (j == jj) {
+        cn = base;
+        tk = float_from_order(T);
+        ts = slo;
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     };
-    const int64_t tile0 = poff[p];
-    // A fragments of one k-step: vectors 16b + (lane & 15) of the tile,
-    // elements 32s + 8 (lane >> 4) .. + 7, i.e. 16-byte chunk 4s + (lane >> 4)
+    put(first, 0);
+    __syncthreads();
+    // A fragments of one k-step: vectors 16b + (lane & 15), 16-byte chunk
+    // 4s + (lane >> 4) of the stage
     const int frag = (lane >> 4) * TILE + (lane & 15);
-    auto kstep = [&](const u32x4* tb, int s, u32x4 (&a)[4]) {
+    f32x4 acc[4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) a[b] = tb[(int64_t)(4 * s) * TILE + frag + 16 * b];
-    };
-    // Loads run two k-steps ahead of the MFMAs and continue into the next
-    // tile, so its first fragments are in flight during this tile's top-k.
-    const u32x4* tb_cur = reinterpret_cast<const u32x4*>(v16) + (tile0 + t0) * (int64_t)nc8 * TILE;
-    u32x4 pa[2][4];
-    if (t0 < t1) {
-      kstep(tb_cur, 0, pa[0]);
-      kstep(tb_cur, 1, pa[1]);
-    }
-    for (int t = t0; t < t1; ++t) {
-      const int64_t tile = tile0 + t;
-      const u32x4* tb_next = (t + 1 < t1) ? tb_cur + (int64_t)nc8 * TILE : tb_cur;
-      f32x4 acc[4];
+    for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tb = t0; tb < t1; tb += TA) {
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ta = 0; ta < TA; ++ta) {
+      const int t = tb + ta;
+      if (t >= t1) break;
+      int64_t tile_id = 0;
+      float tile_xn = 0.f;
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
+      for (int st = 0; st < NS; ++st) {
+        const int u = (t - t0) * NS + st;
+        const int slot = ta * NS + st;  // u % DEPTH
+        if (st == 0) {
+          // ids and norms of the tile, consumed after its last stage
+          tile_id = sid[(tile0 + t) * TILE + lane];
+          if (!IP) tile_xn = v16n[(tile0 + t) * TILE + lane];
+        }
+        if (gcount > 0) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[b] = mfma16<F16>(pa[s & 1][b], breg[s], acc[b]);
-        if (s + 2 < KS) kstep(tb_cur, s + 2, pa[s & 1]);
-        else kstep(tb_next, s + 2 - KS, pa[s & 1]);
+          for (int s = 0; s < KST; ++s) {
+            u32x4 a[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) a[b] = RING[st & 1][4 * s * TILE + frag + 16 * b];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[b] = mfma16<F16>(a[b], breg[st * KST + s], acc[b]);
+          }
+        }
+        // the other LDS buffer was last read in stage u - 1 (before the last
+        // barrier): it takes stage u + 1, whose registers then load stage
+        // u + 1 + DEPTH (after the last stage, the copy is never read)
+        put(rs[slot], (st + 1) & 1);
+        load(u + 1 + DEPTH, rs[slot]);
+        __syncthreads();
       }
-      tb_cur = tb_next;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      if (gcount == 0) continue;
+      {
+        // The tile's scores are complete.  acc[b][v] is the product of query
+        // j = lane & 15 with vector 16b + 4 (lane >> 4) + v of the tile, so
+        // every lane tests its 16 values against its query's threshold in
+        // registers; most tiles end here with nothing to keep.
+        const int64_t tile = tile0 + t;
+        const uint64_t live = __ballot(t * TILE + lane < size && tile_id >= 0);
+        const int32_t slot0 = (int32_t)(tile * TILE);
+        float key[16];
+        auto count = [&]() {
+          int n = 0;
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+          for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Sw[j][16 * b + (lane >> 4) * 4 + v] = acc[b][v];
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      const bool valid = t * TILE + lane < size;
-      const int32_t slot = (int32_t)(tile * TILE + lane);
-      const float xn = IP ? 0.f : v16n[slot];
-      const bool live = valid && sid[slot] >= 0;
+            for (int v = 0; v < 4; ++v) {
+              const int vi = 16 * b + 4 * (lane >> 4) + v;
+              n += ((live >> vi) & 1ull) && ks_less(key[4 * b + v], slot0 + vi, tk, ts);
+            }
+          return n;
+        };
 #pragma unroll
-      for (int jj = 0; jj < G; ++jj) {
-        if (jj >= gcount) break;
-        const float dot = Sw[jj][lane];
-        const float key = IP ? -dot : (__shfl(my_qn2, jj) + xn - 2.f * dot);
-        const float tkj = Tk[jj];
-        const int32_t tsj = Ts[jj];
-        bool pass = live && ks_less(key, slot, tkj, tsj);
-        uint64_t mask = __ballot(pass);
-        if (mask) {
-          int n = __popcll(mask);
-          int c0 = Cn[jj];
-          if (c0 + n > WAVE) {
-            flush(jj);
-            pass = live && ks_less(key, slot, Tk[jj], Ts[jj]);
-            mask = __ballot(pass);
-            n = __popcll(mask);
-            c0 = 0;
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int vi = 16 * b + 4 * (lane >> 4) + v;
+            const float dot = acc[b][v];
+            key[4 * b + v] = IP ? -dot : (my_qn2 + __shfl(tile_xn, vi) - 2.f * dot);
           }
-          const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-          if (pass) {
-            Bk[jj][c0 + rank] = key;
-            Bs[jj][c0 + rank] = slot;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        int np = count();
+        if (__ballot(np > 0)) {
+          // passes of the query over its four lanes, and this lane's offset
+          auto totals = [&](int n, int& tot, int& off) {
+            const int n0 = __shfl(n, j), n1 = __shfl(n, j + 16), n2 = __shfl(n, j + 32), n3 = __shfl(n, j + 48);
+            const int g4 = lane >> 4;
+            tot = n0 + n1 + n2 + n3;
+            off = (g4 > 0 ? n0 : 0) + (g4 > 1 ? n1 : 0) + (g4 > 2 ? n2 : 0);
+          };
+          int tot, off;
+          totals(np, tot, off);
+          // queries whose buffer would overflow merge it into their list first
+          const uint64_t over = __ballot(lane < G && cn + tot > BUF);
+          if (over) {
+#pragma unroll
+            for (int jj = 0; jj < G; ++jj)
+              if ((over >> jj) & 1ull) compact(jj, false);
+            np = count();
+            totals(np, tot, off);
           }
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-          if (lane == 0) Cn[jj] = c0 + n;
+          int pos = cn + off;
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int vi = 16 * b + 4 * (lane >> 4) + v;
+              if (((live >> vi) & 1ull) && ks_less(key[4 * b + v], slot0 + vi, tk, ts)) {
+                Bk[j][pos] = key[4 * b + v];
+                Bs[j][pos] = slot0 + vi;
+                ++pos;
+              }
+            }
+          cn += tot;
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
+    }
+    // The item's kk best per query, sorted: pools cut to kk, then sorted
+    // FB queries at a time (their shuffles overlap).
+    if (gcount > 0) {
 #pragma unroll
-    for (int jj = 0; jj < G; ++jj) {
-      if (jj >= gcount) break;
-      if (Cn[jj] > 0) flush(jj);
-      const int pr = __builtin_amdgcn_readlane(pair, jj);
-      const int64_t out = (pair_base[pr] + c) * kk;
-      if (lane < kk) {
-        pk[out + lane] = lk[jj];
-        pi[out + lane] = (int64_t)ls[jj];
+      for (int jj = 0; jj < G; ++jj)
+        if (jj < gcount) compact(jj, true);
+      constexpr int FB = 8;
+#pragma unroll
+      for (int q0 = 0; q0 < G; q0 += FB) {
+        if (q0 >= gcount) break;
+        float bk[FB];
+        int32_t bs[FB];
+#pragma unroll
+        for (int q = 0; q < FB; ++q) {
+          const int n = __builtin_amdgcn_readlane(cn, q0 + q);
+          bk[q] = lane < n ? Bk[q0 + q][lane] : KEY_EMPTY;
+          bs[q] = lane < n ? Bs[q0 + q][lane] : -1;
+        }
+        wave_sort64_n<FB>(bk, bs);
+#pragma unroll
+        for (int q = 0; q < FB; ++q) {
+          if (q0 + q >= gcount) break;
+          const int64_t out = (sorted_base[__builtin_amdgcn_readlane(pidx, q0 + q)] + c) * kk;
+          if (lane < kk) {
+            pk[out + lane] = bk[q];
+            pi[out + lane] = (int64_t)bs[q];
+          }
+        }
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     }
   }
 }
@@ -369,9 +562,9 @@ template <int F16, int IP>
 static void scan_mfma_k(Workspace& ws, const Store& st, const RoundArgs& a, int blocks, hipStream_t s) {
   const int ks = st.dp16 / 32;
 #define QK_MFMA_LAUNCH(KS)                                                                                      \
-  hipLaunchKernelGGL((k_scan_mfma<F16, KS, IP>), dim3(blocks), dim3(256), 0, s, ws.total, ws.pitem, ws.pstart, \
-                     ws.sorted, ws.pair_q, ws.pair_base, st.nlist, a.chunk_tiles, ws.q16, st.dp16, ws.qn2f,    \
-                     st.v16, st.v16n, st.ids, st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi)
+  hipLaunchKernelGGL((k_scan_mfma<F16, KS, IP>), dim3(blocks), dim3(256), 0, s, ws.total, ws.bitems,          \
+                     ws.sorted_q, ws.sorted_base, a.chunk_tiles, ws.q16, st.dp16, ws.qn2f, st.v16, st.v16n, st.ids, \
+                     ws.rk, ws.ri, a.kk, ws.pk, ws.pi)
   switch (ks) {
     case 2: QK_MFMA_LAUNCH(2); break;
     case 4: QK_MFMA_LAUNCH(4); break;

@@ -28,7 +28,7 @@ _MODE = {"plain": SCAN_PLAIN, "batched": SCAN_BATCHED}
 
 EXPORTED = ("quake_build", "quake_search", "quake_insert", "quake_delete", "quake_stats", "quake_export",
             "quake_export_top", "quake_candidates", "quake_cap_table", "quake_profile", "quake_set_tuning",
-            "quake_free", "quake_last_error", "quake_server_create", "quake_server_search", "quake_server_insert",
+            "quake_free", "quake_last_error", "quake_autotune", "quake_server_create", "quake_server_search", "quake_server_insert",
             "quake_server_delete", "quake_server_wait", "quake_server_stats", "quake_server_destroy")
 PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "unused6", "unused7")
 
@@ -99,6 +99,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.quake_cap_table.argtypes = [i32, ctypes.POINTER(f64)]
     lib.quake_profile.argtypes = [vp, i32, i32, vp]
     lib.quake_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    lib.quake_autotune.argtypes = [vp, vp, i64, ctypes.POINTER(SearchParams), i32, ctypes.POINTER(Tuning),
+                                   ctypes.POINTER(f64), vp]
     u64p = ctypes.POINTER(ctypes.c_uint64)
     lib.quake_server_create.argtypes = [vp, ctypes.POINTER(ServerParams), ctypes.POINTER(vp)]
     lib.quake_server_search.argtypes = [vp, vp, i64, u64p]
@@ -256,6 +258,18 @@ def quake_set_tuning(handle: int, chunk_tiles=0, first_window=0, max_window=0, m
     _check(load_library().quake_set_tuning(handle, ctypes.byref(t)))
 
 
+def quake_autotune(handle: int, q, reps: int = 3, **search_kw):
+    """Pick the fastest scheduling knobs for searches of q with search_kw; returns (knobs dict, median ms)."""
+    import torch
+    _dev(q, torch.float32)
+    p = _search_params(**search_kw)
+    t = Tuning()
+    ms = ctypes.c_double()
+    _check(load_library().quake_autotune(handle, _ptr(q), q.shape[0], ctypes.byref(p), reps, ctypes.byref(t),
+                                         ctypes.byref(ms), _stream()))
+    return {name: getattr(t, name) for name, _ in Tuning._fields_}, ms.value
+
+
 def quake_free(handle: int):
     if handle:
         load_library().quake_free(handle)
@@ -390,6 +404,9 @@ class Index:
 
     def set_tuning(self, **kw):
         quake_set_tuning(self.handle, **kw)
+
+    def autotune(self, q, reps=3, **search_kw):
+        return quake_autotune(self.handle, q, reps, **search_kw)
 
     def profile(self, enable=True, reset=False):
         return quake_profile(self.handle, enable, reset)

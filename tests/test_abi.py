@@ -72,3 +72,10 @@ def test_host_side_argument_errors():
     assert lib.quake_server_search(None, None, 1, None) == quake.E_INVALID
     assert lib.quake_server_wait(None, 1, 0.0, None, None, None, None) == quake.E_INVALID
     lib.quake_server_destroy(None)
+
+
+def test_autotune_argument_errors():
+    from paper_2506_03437_amd import quake
+    lib = quake.load_library()
+    sp = quake.SearchParams(10, 4, 0.0, 0, 0, 0, 0, 0, 0, 0, 0)
+    assert lib.quake_autotune(None, None, 1, ctypes.byref(sp), 3, None, None, None) == quake.E_STATE

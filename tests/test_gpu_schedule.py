@@ -71,3 +71,19 @@ def test_recall_monotone_in_target(big_parts):
             assert (rec >= prev_r - 1e-12).all()
         prev_m, prev_r = ns, rec
     assert (prev_r == 1.0).all()
+
+
+@pytest.mark.parametrize("mode", [dict(recall_target=0.9, f_M=0.5), dict(nprobe=5)])
+def test_autotune_picks_knobs_without_changing_results(big_parts, mode):
+    X, Q, idx, ps = big_parts
+    idx.set_tuning()
+    base = gu.search(idx, Q, k=20, **mode)
+    knobs, ms = idx.autotune(gu.to_dev(Q), reps=2, k=20, **mode)
+    assert ms > 0
+    assert knobs["chunk_tiles"] in (0, 8, 16, 32, 64, 128)
+    assert knobs["rounds_per_sync"] in (0, 2, 4, 8)
+    assert knobs["blocks_per_cu"] in (0, 4, 8, 16)
+    got = gu.search(idx, Q, k=20, **mode)
+    for a, b in zip(base, got):
+        assert (a == b).all(), f"tuning {knobs} changed the result"
+    idx.set_tuning()
