@@ -438,15 +438,15 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
           tile_id = sid[(tile0 + t) * TILE + lane];
           if (!IP) tile_xn = v16n[(tile0 + t) * TILE + lane];
         }
-        if (gcount > 0) {
+        // (waves without queries score too - their results are never read -
+        // so that the accumulators stay in the matrix registers throughout)
 #pragma unroll
-          for (int s = 0; s < KST; ++s) {
-            u32x4 a[4];
+        for (int s = 0; s < KST; ++s) {
+          u32x4 a[4];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) a[b] = RING[st & 1][4 * s * TILE + frag + 16 * b];
+          for (int b = 0; b < 4; ++b) a[b] = RING[st & 1][4 * s * TILE + frag + 16 * b];
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[b] = mfma16<F16>(a[b], breg[st * KST + s], acc[b]);
-          }
+          for (int b = 0; b < 4; ++b) acc[b] = mfma16<F16>(a[b], breg[st * KST + s], acc[b]);
         }
         // the other LDS buffer was last read in stage u - 1 (before the last
         // barrier): it takes stage u + 1, whose registers then load stage
@@ -465,15 +465,23 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
         const uint64_t live = __ballot(t * TILE + lane < size && tile_id >= 0);
         const int32_t slot0 = (int32_t)(tile * TILE);
         float key[16];
+        // live bits of this lane's 16 vectors (bit 4b + v: vector 16b + 4g + v)
+        const int g4 = lane >> 4;
+        uint32_t lm = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) lm |= (uint32_t)((live >> (16 * b + 4 * g4)) & 0xfull) << (4 * b);
+        // branch-free (key, slot) test against the threshold
+        auto passes = [&](int b, int v) {
+          const float kv = key[4 * b + v];
+          const int32_t sv = slot0 + 16 * b + 4 * g4 + v;
+          return (bool)(((lm >> (4 * b + v)) & 1u) & ((kv < tk) | ((kv == tk) & (sv < ts))));
+        };
         auto count = [&]() {
           int n = 0;
 #pragma unroll
           for (int b = 0; b < 4; ++b)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              const int vi = 16 * b + 4 * (lane >> 4) + v;
-              n += ((live >> vi) & 1ull) && ks_less(key[4 * b + v], slot0 + vi, tk, ts);
-            }
+            for (int v = 0; v < 4; ++v) n += passes(b, v) ? 1 : 0;
           return n;
         };
 #pragma unroll
@@ -491,7 +499,6 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
           // passes of the query over its four lanes, and this lane's offset
           auto totals = [&](int n, int& tot, int& off) {
             const int n0 = __shfl(n, j), n1 = __shfl(n, j + 16), n2 = __shfl(n, j + 32), n3 = __shfl(n, j + 48);
-            const int g4 = lane >> 4;
             tot = n0 + n1 + n2 + n3;
             off = (g4 > 0 ? n0 : 0) + (g4 > 1 ? n1 : 0) + (g4 > 2 ? n2 : 0);
           };
@@ -511,10 +518,9 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
           for (int b = 0; b < 4; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-              const int vi = 16 * b + 4 * (lane >> 4) + v;
-              if (((live >> vi) & 1ull) && ks_less(key[4 * b + v], slot0 + vi, tk, ts)) {
+              if (passes(b, v)) {
                 Bk[j][pos] = key[4 * b + v];
-                Bs[j][pos] = slot0 + vi;
+                Bs[j][pos] = slot0 + 16 * b + 4 * g4 + v;
                 ++pos;
               }
             }
