@@ -48,6 +48,28 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def profiled_traffic(workload, knobs):
+    """HBM bytes per launch of k_scan_mfma from the committed rocprofv3 counter
+    summary, when it was taken on this workload with these knobs and the
+    kernel's source has not changed since; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"k_scan_mfma_{workload}.md")
+    src = os.path.join(ROOT, "paper_2506_03437_amd", "csrc", "k_batched.hip")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if " = " in line and not line.startswith(" "):
+            k, v = line.strip().split(" = ", 1)
+            fields[k] = v
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    want = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in fields.get("knobs", "").split(",") if kv}
+    have = {k: v for k, v in (knobs or {}).items() if v}
+    if fields.get("kernel_source_sha256") != sha or want != have or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def cpu_baseline_leg(X, Q, sample_rows, idx, workload, seconds):
     """The CPU oracle on the host: exact ground truth for the recall sample
     and adaptive scanning over the device index's own partitioning, timed
@@ -182,6 +204,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--recall-target", type=float, default=0.0, help="skip the sweep and use this target")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default scheduling knobs")
+    ap.add_argument("--tuning", default="", help="knobs to set instead of autotuning, e.g. chunk_tiles=64,max_window=16")
+    ap.add_argument("--tuning-path", default="batched", help="path (plain/batched) the --tuning knobs apply to")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy a BYTES-long device buffer 5 times (calibrates HBM byte counters) and exit")
     ap.add_argument("--serving-requests", type=int, default=40_000, help="0 skips the serving-loop leg")
@@ -258,7 +282,14 @@ def main():
                 if rec >= 0.9:
                     break
         knobs = None
-        if not args.no_autotune:
+        if args.tuning and path.startswith(args.tuning_path):
+            # fixed knobs (to profile the configuration a tuned run chose)
+            knobs = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in args.tuning.split(",") if kv}
+            idx.set_tuning(**knobs)
+            log(f"{path}: knobs set to {knobs}")
+        elif args.tuning:
+            idx.set_tuning()
+        elif not args.no_autotune:
             # scheduling knobs (never the results) tuned on a separate seeded batch
             knobs, tuned_ms = idx.autotune(Qtune, reps=2 if path.startswith("batched") else 1, k=w.k,
                                            recall_target=tau, f_M=w.f_M, **paths[path])
@@ -321,7 +352,7 @@ def main():
     else:
         roof = {"bound": "hbm", "kernel": "k_scan_mfma", "achieved": batched["scan_gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": fb}
-    roof.update({"traffic": None, "hbm_gbs": batched["scan_gbs"], "hbm_frac": fb, "mfma_tflops":
+    roof.update({"traffic": profiled_traffic(w.name, batched["tuning"]), "hbm_gbs": batched["scan_gbs"], "hbm_frac": fb, "mfma_tflops":
                  batched["scan_tflops"], "mfma_frac": ff, "algorithmic_bytes_per_launch":
                  batched["scan_bytes_per_launch"], "flops_per_launch": batched["scan_flops_per_launch"],
                  "ms_per_launch": batched["scan_ms_per_launch"]})
