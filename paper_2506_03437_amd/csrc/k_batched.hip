@@ -334,19 +334,19 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
       tk = has ? sk : -KEY_EMPTY;  // absent queries take nothing
       ts = has ? ss : -1;
     }
-    // Cut query jj's pool.  Mid-item (exact = false): keep the entries up to
-    // a key T that at least kk and at most kk + SLACK entries reach - T is
-    // found by bisection on the keys' order-preserving bits with ballot
-    // counts, stopping once the count lands in that window - and make T the
-    // threshold (every kept entry, and the final kk, are at most T).  At the
-    // end (exact = true): keep exactly the kk best in (key, slot) order,
-    // bisecting on the slot among ties of the kk-th key when needed.
+    // Cut query jj's pool to at most `limit` entries (limit >= kk): keep the
+    // entries up to a key T that at least kk and at most `limit` entries
+    // reach - T is found by bisection on the keys' order-preserving bits with
+    // ballot counts, stopping once the count lands in that window - and make
+    // T the threshold (every kept entry, and the final kk, are at most T).
+    // When ties at T leave too many, keep exactly the kk best in (key, slot)
+    // order, bisecting on the slot among the ties.
     constexpr int EPL = BUF / WAVE;  // pool entries per lane
-    auto compact = [&](int jj, bool exact) {
+    auto compact = [&](int jj, int limit) {
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       const int n = __builtin_amdgcn_readlane(cn, jj);
-      if (n <= kk) return;
-      const int slack = exact ? 0 : min(SLACK, BUF - WAVE - kk);
+      if (n <= limit) return;
+      const int slack = limit - kk;
       float kv[EPL];
       int32_t sv[EPL];
       uint32_t uv[EPL];
@@ -376,8 +376,8 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
       }
       const uint32_t T = hi;
       int32_t slo = INT32_MAX;
-      // many ties at T can leave more than kk + slack entries: cut exactly then
-      if (exact || count_le(T) > kk + slack) {
+      // many ties at T can leave more than `limit` entries: cut exactly then
+      if (count_le(T) > limit) {
         int less = 0, eq = 0;
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
@@ -494,7 +494,12 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
           }
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
-        int np = count();
+        // nothing below the threshold in the whole wave: the usual case
+        float kmin = key[0];
+#pragma unroll
+        for (int e = 1; e < 16; ++e) kmin = fminf(kmin, key[e]);
+        int np = 0;
+        if (__ballot(kmin <= tk)) np = count();
         if (__ballot(np > 0)) {
           // passes of the query over its four lanes, and this lane's offset
           auto totals = [&](int n, int& tot, int& off) {
@@ -509,7 +514,7 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
           if (over) {
 #pragma unroll
             for (int jj = 0; jj < G; ++jj)
-              if ((over >> jj) & 1ull) compact(jj, false);
+              if ((over >> jj) & 1ull) compact(jj, kk + min(SLACK, BUF - WAVE - kk));
             np = count();
             totals(np, tot, off);
           }
@@ -530,12 +535,13 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
       }
     }
     }
-    // The item's kk best per query, sorted: pools cut to kk, then sorted
-    // FB queries at a time (their shuffles overlap).
+    // The item's kk best per query, sorted: pools cut to at most 64 entries
+    // (still holding the kk best), then sorted FB queries at a time (their
+    // shuffles overlap).
     if (gcount > 0) {
 #pragma unroll
       for (int jj = 0; jj < G; ++jj)
-        if (jj < gcount) compact(jj, true);
+        if (jj < gcount) compact(jj, WAVE);
       constexpr int FB = 8;
 #pragma unroll
       for (int q0 = 0; q0 < G; q0 += FB) {
