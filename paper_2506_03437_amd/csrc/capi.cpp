@@ -256,6 +256,12 @@ void upload_table(Store& st, hipStream_t s) {
   QK_HIP(hipMemcpyAsync(st.d_off, st.off.data(), N * sizeof(int64_t), hipMemcpyHostToDevice, s));
   QK_HIP(hipMemcpyAsync(st.d_size, st.size.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, s));
   QK_HIP(hipMemcpyAsync(st.d_cap, st.cap.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  // batched scans hand out work in this order: the largest partitions first,
+  // so that the last items of a launch are short ones
+  st.order.resize(N);
+  for (int64_t p = 0; p < N; ++p) st.order[p] = (int32_t)p;
+  std::stable_sort(st.order.begin(), st.order.end(), [&](int32_t a, int32_t b) { return st.size[a] > st.size[b]; });
+  QK_HIP(hipMemcpyAsync(st.d_order, st.order.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, s));
 }
 
 // Place rows into a fresh store: partition p gets capacity for its rows plus
@@ -294,6 +300,7 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
   st.d_off = idx->mem.alloc<int64_t>(N);
   st.d_size = idx->mem.alloc<int32_t>(N);
   st.d_cap = idx->mem.alloc<int32_t>(N);
+  st.d_order = idx->mem.alloc<int32_t>(N);
   upload_table(st, s);
   {
     Tmp<int64_t> d_slot(idx->mem, n);
@@ -607,7 +614,7 @@ std::vector<uint64_t> graph_key(const quake_index* idx, const Store& st, const J
       (uint64_t)R, (uint64_t)job.batched, (uint64_t)job.dtype16, (uint64_t)a.nq, (uint64_t)a.M, (uint64_t)a.k,
       (uint64_t)a.kk, (uint64_t)a.aps, (uint64_t)a.chunk_tiles, (uint64_t)a.wmax, (uint64_t)a.metric,
       (uint64_t)a.items_cap, (uint64_t)a.blocks, (uint64_t)st.d, (uint64_t)st.dp, (uint64_t)st.nlist,
-      (uint64_t)st.dp16, u(idx->cap_table), u(st.centroids), u(st.d_off), u(st.d_size), u(st.d_cap), u(st.v32),
+      (uint64_t)st.dp16, u(idx->cap_table), u(st.centroids), u(st.d_off), u(st.d_size), u(st.d_cap), u(st.d_order), u(st.v32),
       u(st.v16), u(st.v16n), u(st.rows32), u(st.ids), u(w.q), u(w.qn2), u(w.cand), u(w.mq), u(w.h), u(w.st_m),
       u(w.st_w), u(w.st_weff), u(w.st_done), u(w.st_item), u(w.st_demand), u(w.st_rho), u(w.st_p0), u(w.st_V),
       u(w.st_vsum), u(w.st_r), u(w.rk), u(w.ri), u(w.items), u(w.pk), u(w.pi), u(w.st_vecs), u(w.st_pair),

@@ -80,8 +80,10 @@ struct Store {
   int64_t* d_off = nullptr;     // [nlist] first tile of each partition
   int32_t* d_size = nullptr;    // [nlist] filled slots (deleted slots hold id -1)
   int32_t* d_cap = nullptr;     // [nlist] slots (multiple of 64)
+  int32_t* d_order = nullptr;   // [nlist] partitions by decreasing size (ties by index)
   std::vector<int64_t> off;
   std::vector<int32_t> size, cap;
+  std::vector<int32_t> order;    // host copy of d_order
   int64_t tiles = 0;            // arena tiles allocated
   int64_t used_tiles = 0;       // arena tiles handed out
   int32_t dp16 = 0;             // row length of the 16-bit copy: d rounded up to 32
@@ -140,7 +142,7 @@ struct Workspace {
                                 //   (vectors, first tile low, first tile high, query sets)
   int32_t* pcount = nullptr;    // [nlist] pairs per partition (kept zeroed between rounds)
   int32_t* pstart = nullptr;    // [nlist + 1]
-  int64_t* pitem = nullptr;     // [nlist + 1] first batched work item of each partition
+  int64_t* pitem = nullptr;     // [nlist] first batched work item of each partition (numbered in Store::order)
   // device counters (COUNTERS of them): [0] items, [1] vectors, [2] pairs of
   // the round, [3] batched items of the round, [4] batched vector reads and
   // [5] batched query-vector products summed over the search, [6] plain-scan

@@ -97,11 +97,14 @@ __global__ __launch_bounds__(256) void k_pairs(int64_t nq, int M, int chunk_tile
   }
 }
 
-// Per-partition pair offsets and work-item offsets (one block); clears the
-// counts for the next round and adds the round's vector reads and
-// query-vector products to the running totals.
+// Per-partition pair offsets (partition order) and work-item offsets (in
+// `order`, largest partitions first: the scan takes items in index order, so
+// a launch ends on short items); clears the counts for the next round and
+// adds the round's vector reads and query-vector products to the running
+// totals.  One block.
 __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles, int32_t* __restrict__ pcount,
-                                                       const int32_t* __restrict__ psize, int32_t* __restrict__ pstart,
+                                                       const int32_t* __restrict__ psize,
+                                                       const int32_t* __restrict__ order, int32_t* __restrict__ pstart,
                                                        int64_t* __restrict__ pitem, int64_t* __restrict__ counters) {
   __shared__ int64_t sp[1024], si[1024];
   __shared__ unsigned long long reads, products;
@@ -109,6 +112,10 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
   const int64_t per = (N + 1023) / 1024;
   const int64_t lo = t * per;
   const int64_t hi = (lo + per < N) ? lo + per : N;
+  auto items_of = [&](int64_t p) -> int64_t {
+    const int c = pcount[p];
+    return c > 0 ? (int64_t)((c + SET - 1) / SET) * chunks_of(psize[p], chunk_tiles) : 0;
+  };
   int64_t np = 0, ni = 0;
   unsigned long long rd = 0, pd = 0;
   for (int64_t p = lo; p < hi; ++p) {
@@ -116,11 +123,11 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
     np += c;
     if (c > 0) {
       const int sets = (c + SET - 1) / SET;
-      ni += (int64_t)sets * chunks_of(psize[p], chunk_tiles);
       rd += (unsigned long long)sets * (unsigned long long)psize[p];
       pd += (unsigned long long)c * (unsigned long long)psize[p];
     }
   }
+  for (int64_t r = lo; r < hi; ++r) ni += items_of(order[r]);
   sp[t] = np;
   si[t] = ni;
   if (t == 0) { reads = 0; products = 0; }
@@ -133,13 +140,18 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
     si[t] += b;
     __syncthreads();
   }
-  int64_t rp = sp[t] - np, ri = si[t] - ni;
-  for (int64_t p = lo; p < hi; ++p) {
-    const int c = pcount[p];
-    pstart[p] = (int32_t)rp;
+  int64_t ri = si[t] - ni;
+  for (int64_t r = lo; r < hi; ++r) {
+    const int64_t p = order[r];
     pitem[p] = ri;
-    rp += c;
-    if (c > 0) ri += (int64_t)((c + SET - 1) / SET) * chunks_of(psize[p], chunk_tiles);
+    ri += items_of(p);
+  }
+  // every thread has read the counts it needs before any is cleared
+  __syncthreads();
+  int64_t rp = sp[t] - np;
+  for (int64_t p = lo; p < hi; ++p) {
+    pstart[p] = (int32_t)rp;
+    rp += pcount[p];
     pcount[p] = 0;
   }
   atomicAdd(&reads, rd);
@@ -147,7 +159,6 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
   __syncthreads();
   if (t == 0) {
     pstart[N] = (int32_t)sp[1023];
-    pitem[N] = si[1023];
     counters[3] = si[1023];
     counters[4] += (int64_t)reads;
     counters[5] += (int64_t)products;
@@ -185,7 +196,7 @@ __global__ __launch_bounds__(256) void k_items(int64_t N, int chunk_tiles, const
   const int np = pstart[p + 1] - pstart[p];
   if (np == 0) return;
   const int sets = (np + SET - 1) / SET;
-  const int n = (int)(pitem[p + 1] - pitem[p]);
+  const int n = sets * chunks_of(psize[p], chunk_tiles);
   const int64_t tile0 = poff[p];
   const int4 b = make_int4(psize[p], (int)(uint32_t)(uint64_t)tile0, (int)(uint32_t)((uint64_t)tile0 >> 32), sets);
   for (int local = 0; local < n; ++local) {
@@ -199,7 +210,7 @@ void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_
                      ws.cand, st.d_size, ws.st_m, ws.st_weff, ws.st_item, ws.st_pair, ws.pcount, ws.pair_q, ws.pair_p,
                      ws.pair_pos, ws.pair_base);
   hipLaunchKernelGGL(k_part_prefix, dim3(1), dim3(1024), 0, s, st.nlist, a.chunk_tiles, ws.pcount, st.d_size,
-                     ws.pstart, ws.pitem, ws.total);
+                     st.d_order, ws.pstart, ws.pitem, ws.total);
   // at most wmax pairs per query; the kernel reads this round's count
   const int64_t bound = (a.nq * a.wmax + 255) / 256;
   hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(bound, 2048))), dim3(256),
