@@ -59,6 +59,34 @@ __device__ __forceinline__ float readlane_f(float v, int lane) {
   return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), lane));
 }
 
+// Lane exchange inside rows of 16 lanes through DPP (no LDS round trip):
+// quad_perm [1,0,3,2] and [2,3,0,1] swap neighbours and pairs, row_half_mirror
+// reverses each group of 8 and row_mirror each row of 16.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xf, 0xf, false);
+}
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+
+// Minimum and maximum of v over the wave (uniform results): DPP steps reduce
+// each row of 16 lanes, then the four row results are combined in scalars.
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  v = min(v, dpp_u32<DPP_XOR1>(v));
+  v = min(v, dpp_u32<DPP_XOR2>(v));
+  v = min(v, dpp_u32<DPP_HALF_MIRROR>(v));
+  v = min(v, dpp_u32<DPP_MIRROR>(v));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, dpp_u32<DPP_XOR1>(v));
+  v = max(v, dpp_u32<DPP_XOR2>(v));
+  v = max(v, dpp_u32<DPP_HALF_MIRROR>(v));
+  v = max(v, dpp_u32<DPP_MIRROR>(v));
+  return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   uint64_t b = (uint64_t)__double_as_longlong(v);
   uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, lane);
@@ -277,6 +305,36 @@ __device__ __forceinline__ void wave_sort64_n(float (&k)[N], int32_t (&s)[N]) {
   for (int size = 2; size <= WAVE; size <<= 1)
 #pragma unroll
     for (int stride = size >> 1; stride > 0; stride >>= 1) bitonic_step_n<N>(k, s, size, stride);
+}
+
+// (key, slot) packed into one integer whose unsigned order is the result
+// order: the key's order-preserving bits above the slot's bits (slots are
+// >= 0; the empty entry (+inf, -1) sorts last).
+__device__ __forceinline__ uint64_t pack_key_slot(float k, int32_t s) {
+  return ((uint64_t)float_order(k) << 32) | (uint32_t)s;
+}
+__device__ __forceinline__ float packed_key(uint64_t v) { return float_from_order((uint32_t)(v >> 32)); }
+__device__ __forceinline__ int32_t packed_slot(uint64_t v) { return (int32_t)(uint32_t)v; }
+
+// Sort N independent lists of packed entries (one per lane in each)
+// ascending with a bitonic network; per compare-exchange one 64-bit compare
+// and a select, the N lists' shuffles overlapping.
+template <int N>
+__device__ __forceinline__ void wave_sort64_packed_n(uint64_t (&v)[N]) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int size = 2; size <= WAVE; size <<= 1)
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      uint64_t o[N];
+#pragma unroll
+      for (int q = 0; q < N; ++q) o[q] = (uint64_t)shfl_xor_i64((int64_t)v[q], stride);
+      // the lower lane of a pair keeps the smaller entry in ascending runs
+      // of length `size`, the larger one in descending runs
+      const bool take_min = ((lane & size) == 0) == ((lane & stride) == 0);
+#pragma unroll
+      for (int q = 0; q < N; ++q) v[q] = ((o[q] < v[q]) == take_min) ? o[q] : v[q];
+    }
 }
 
 // lists[q] := the 64 smallest of lists[q] and b[q] (both ascending), for q < N.

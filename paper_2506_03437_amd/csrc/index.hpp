@@ -147,8 +147,7 @@ struct Workspace {
   // the round, [3] batched items of the round, [4] batched vector reads and
   // [5] batched query-vector products summed over the search, [6] plain-scan
   // vectors summed over the search, [7] head of the round's item queue,
-  // [8] first query cut from the round, [16..23] per-XCD item queues of the
-  // batched scan
+  // [8] first query cut from the round, [16] item queue of the batched scan
   int64_t* total = nullptr;
   int64_t* blk = nullptr;       // [nq / 256 + 1][4] per-block planning sums, then offsets
   int64_t* h_total = nullptr;   // pinned host mirror

@@ -17,6 +17,8 @@
 // commit and the recall model are shared.  Candidates carry store slots; after
 // the last round each query's candidates are re-scored in FP32 from the FP32
 // store (the same arithmetic as the plain scan) and the best k are kept.
+#include <type_traits>
+
 #include "common.hpp"
 #include "index.hpp"
 
@@ -27,7 +29,7 @@ constexpr int SET_GROUPS = 4;   // query groups per block, one per wave
 constexpr int SET = G * SET_GROUPS;  // queries that share one read of a tile
 constexpr int BUF = 3 * WAVE;   // per-query candidate pool (three entries per lane; holds kk, slack and a tile)
 constexpr int SLACK = 16;       // entries a mid-item cut may keep beyond kk
-constexpr int QUEUE_X = 16;     // counters[16 .. 23]: per-XCD item queues of the batched scan
+constexpr int QUEUE_X = 16;     // counters[16]: item queue of the batched scan
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
     counters[3] = si[1023];
     counters[4] += (int64_t)reads;
     counters[5] += (int64_t)products;
-    for (int x = 0; x < 8; ++x) counters[QUEUE_X + x] = 0;
+    counters[QUEUE_X] = 0;
   }
 }
 
@@ -253,27 +255,26 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
   __shared__ u32x4 RING[2][SU];                 // two stages of the current tile
   __shared__ float BK[4][G][BUF];               // per query: candidates that beat the threshold, not yet merged
   __shared__ int32_t BS[4][G][BUF];
-  __shared__ int64_t next_item;
+  __shared__ int64_t next_item[2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // Blocks take items in order from one queue: items differ widely in cost
   // (power-law partition sizes and query counts), so a static split would
   // leave some compute units idle; the query sets of one chunk are
-  // consecutive items, scored at about the same time.
-  const int nx = 1;
-  const int xcd = 0;
+  // consecutive items, scored at about the same time.  (A block claims its
+  // next item only when it is free: claiming ahead keeps large items from
+  // idle blocks at the end of a launch.)
   const int64_t total = counters[3];
-  const int64_t range_lo = total * xcd / nx, range_hi = total * (xcd + 1) / nx;
+  unsigned long long* queue = (unsigned long long*)(counters + QUEUE_X);
   constexpr int nc8 = KS * 4;  // 8-element chunks per row of the 16-bit copy
   float (*Bk)[BUF] = BK[wave];
   int32_t (*Bs)[BUF] = BS[wave];
-  for (;;) {
-    // every thread has read next_item before the block's next barrier, and
-    // thread 0 writes it again only after that barrier
-    if (threadIdx.x == 0)
-      next_item = range_lo + (int64_t)atomicAdd((unsigned long long*)(counters + QUEUE_X + xcd), 1ull);
+  for (int k = 0;; k ^= 1) {
+    // every thread read next_item[k] two items ago, before the barrier that
+    // started the last item
+    if (threadIdx.x == 0) next_item[k] = (int64_t)atomicAdd(queue, 1ull);
     __syncthreads();
-    const int64_t it = next_item;
-    if (it >= range_hi) break;
+    const int64_t it = next_item[k];
+    if (it >= total) break;
     const int4 d0 = bitems[2 * it], d1 = bitems[2 * it + 1];
     const int local = __builtin_amdgcn_readfirstlane(d0.y);
     const int np = __builtin_amdgcn_readfirstlane(d0.z);
@@ -294,6 +295,9 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
     const bool has = j < gcount;
     const int pidx = has ? pfirst + g * G + j : pfirst;  // a valid pair in every lane
     const int qj = sorted_q[pidx];
+    // first output slot of this lane's pair, used only at the item's end
+    // (loaded now so that its latency hides behind the scan)
+    const int64_t my_base = sorted_base[pidx];
     // Stage u of the item = k-steps [KST (u % NS), +KST) of tile t0 + u / NS:
     // SU contiguous 16-byte units of the store.  The block carries two stages
     // in registers (loads in flight) and one in LDS (being scored).
@@ -333,95 +337,131 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
     const float my_qn2 = (IP || !has) ? 0.f : qn2_row;
     // Per query j of the wave: an unsorted pool of candidates in LDS
     // (Bk[j] / Bs[j], cn of them) and - held by the four lanes whose MFMA
-    // output column is j (lanes j, j + 16, j + 32, j + 48) - the key and slot
-    // a candidate must beat: the seed from the query's committed results,
-    // then the kk-th best of the pool whenever the pool is compacted.
+    // output column is j (lanes j, j + 16, j + 32, j + 48) - the key tk a
+    // candidate must not exceed: the seed from the query's committed
+    // results, then the cut key of the pool whenever the pool is cut.  A
+    // candidate that ties tk is taken whatever its slot; when it ranks after
+    // the kk best in (key, slot) order, the final selection (or the commit)
+    // drops it.
     float tk;
-    int32_t ts;
     int cn = 0;
-    {
-      const float sk = rk[(int64_t)qj * kk + kk - 1];
-      const int32_t ss = (int32_t)ri[(int64_t)qj * kk + kk - 1];
-      tk = has ? sk : -KEY_EMPTY;  // absent queries take nothing
-      ts = has ? ss : -1;
-    }
-    // Cut query jj's pool to at most `limit` entries (limit >= kk): keep the
-    // entries up to a key T that at least kk and at most `limit` entries
-    // reach - T is found by bisection on the keys' order-preserving bits with
-    // ballot counts, stopping once the count lands in that window - and make
-    // T the threshold (every kept entry, and the final kk, are at most T).
-    // When ties at T leave too many, keep exactly the kk best in (key, slot)
-    // order, bisecting on the slot among the ties.
+    tk = rk[(int64_t)qj * kk + kk - 1];
+    // Cut the pools of up to NB queries (jq[q] < 0: none) that hold more
+    // than `limit` entries (limit >= kk) down to at most `limit`, all of
+    // them at or below a key T that at least kk entries reach; T becomes the
+    // query's tk.  T is found by bisection on the keys' order-preserving
+    // bits between the pool's smallest and largest key, with ballot counts,
+    // stopping as soon as the count lands in [kk, limit]; the NB bisections
+    // run interleaved.  When ties at T leave more than `limit`, keep exactly
+    // the kk best in (key, slot) order, bisecting on the slot among the ties.
     constexpr int EPL = BUF / WAVE;  // pool entries per lane
-    auto compact = [&](int jj, int limit) {
+    auto cut = [&](auto nb_tag, const int* jq, int limit) {
+      constexpr int NB = decltype(nb_tag)::value;
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      const int n = __builtin_amdgcn_readlane(cn, jj);
-      if (n <= limit) return;
-      const int slack = limit - kk;
-      float kv[EPL];
-      int32_t sv[EPL];
-      uint32_t uv[EPL];
+      int n[NB];
+      bool act[NB], any = false;
 #pragma unroll
-      for (int e = 0; e < EPL; ++e) {
-        const bool v = e * WAVE + lane < n;
-        kv[e] = v ? Bk[jj][e * WAVE + lane] : KEY_EMPTY;
-        sv[e] = v ? Bs[jj][e * WAVE + lane] : INT32_MAX;
-        uv[e] = v ? float_order(kv[e]) : 0xffffffffu;
+      for (int q = 0; q < NB; ++q) {
+        n[q] = jq[q] >= 0 ? __builtin_amdgcn_readlane(cn, jq[q]) : 0;
+        act[q] = n[q] > limit;
+        any |= act[q];
       }
-      auto count_le = [&](uint32_t x) {
-        int c = 0;
+      if (!any) return;
+      float kv[NB][EPL];
+      int32_t sv[NB][EPL];
+      uint32_t uv[NB][EPL];
+      uint32_t lo[NB], hi[NB];
 #pragma unroll
-        for (int e = 0; e < EPL; ++e) c += __popcll(__ballot(uv[e] <= x));
-        return c;
-      };
-      uint32_t lo = 0, hi = 0xffffffffu;
-      while (lo < hi) {
-        const uint32_t mid = lo + ((hi - lo) >> 1);
-        const int c = count_le(mid);
-        if (c >= kk) {
-          hi = mid;
-          if (c <= kk + slack) break;
-        } else {
-          lo = mid + 1;
-        }
-      }
-      const uint32_t T = hi;
-      int32_t slo = INT32_MAX;
-      // many ties at T can leave more than `limit` entries: cut exactly then
-      if (count_le(T) > limit) {
-        int less = 0, eq = 0;
+      for (int q = 0; q < NB; ++q) {
+        uint32_t mn = 0xffffffffu, mx = 0u;
 #pragma unroll
         for (int e = 0; e < EPL; ++e) {
-          less += __popcll(__ballot(uv[e] < T));
-          eq += __popcll(__ballot(uv[e] == T));
+          const bool v = act[q] && e * WAVE + lane < n[q];
+          const int jj = act[q] ? jq[q] : 0;
+          kv[q][e] = v ? Bk[jj][e * WAVE + lane] : KEY_EMPTY;
+          sv[q][e] = v ? Bs[jj][e * WAVE + lane] : INT32_MAX;
+          uv[q][e] = v ? float_order(kv[q][e]) : 0xffffffffu;
+          mn = min(mn, uv[q][e]);
+          mx = max(mx, v ? uv[q][e] : 0u);
         }
-        const int need = kk - less;
-        if (eq > need) {
-          int32_t a = 0, b = INT32_MAX;
-          while (a < b) {
-            const int32_t mid = a + ((b - a) >> 1);
-            int c = 0;
+        lo[q] = wave_min_u32(mn);
+        hi[q] = wave_max_u32(mx);
+      }
+      auto count_le = [&](int q, uint32_t x) {
+        int c = 0;
 #pragma unroll
-            for (int e = 0; e < EPL; ++e) c += __popcll(__ballot(uv[e] == T && sv[e] <= mid));
-            if (c >= need) b = mid; else a = mid + 1;
+        for (int e = 0; e < EPL; ++e) c += __popcll(__ballot(uv[q][e] <= x));
+        return c;
+      };
+      // invariant: at least kk entries are <= hi[q], fewer than kk < lo[q]
+      bool done[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) done[q] = !act[q] || lo[q] >= hi[q];
+      for (;;) {
+        bool all = true;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) all &= done[q];
+        if (all) break;
+        int c[NB];
+        uint32_t mid[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          mid[q] = lo[q] + ((hi[q] - lo[q]) >> 1);
+          c[q] = count_le(q, mid[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          if (done[q]) continue;
+          if (c[q] >= kk) {
+            hi[q] = mid[q];
+            done[q] = c[q] <= limit;
+          } else {
+            lo[q] = mid[q] + 1;
           }
-          slo = a;
+          done[q] |= lo[q] >= hi[q];
         }
       }
-      int base = 0;
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 #pragma unroll
-      for (int e = 0; e < EPL; ++e) {
-        const bool keep = uv[e] < T || (uv[e] == T && sv[e] <= slo);
-        const uint64_t m = __ballot(keep);
-        const int p = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if (keep) { Bk[jj][p] = kv[e]; Bs[jj][p] = sv[e]; }
-        base += __popcll(m);
-      }
-      if (j == jj) {
-        cn = base;
-        tk = float_from_order(T);
-        ts = slo;
+      for (int q = 0; q < NB; ++q) {
+        if (!act[q]) continue;
+        const uint32_t T = hi[q];
+        int32_t slo = INT32_MAX;
+        // many ties at T can leave more than `limit` entries: cut exactly then
+        if (count_le(q, T) > limit) {
+          int less = 0, eq = 0;
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            less += __popcll(__ballot(uv[q][e] < T));
+            eq += __popcll(__ballot(uv[q][e] == T));
+          }
+          const int need = kk - less;
+          if (eq > need) {
+            int32_t a = 0, b = INT32_MAX;
+            while (a < b) {
+              const int32_t mid = a + ((b - a) >> 1);
+              int c = 0;
+#pragma unroll
+              for (int e = 0; e < EPL; ++e) c += __popcll(__ballot(uv[q][e] == T && sv[q][e] <= mid));
+              if (c >= need) b = mid; else a = mid + 1;
+            }
+            slo = a;
+          }
+        }
+        const int jj = jq[q];
+        int base = 0;
+#pragma unroll
+        for (int e = 0; e < EPL; ++e) {
+          const bool keep = uv[q][e] < T || (uv[q][e] == T && sv[q][e] <= slo);
+          const uint64_t m = __ballot(keep);
+          const int p = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          if (keep) { Bk[jj][p] = kv[q][e]; Bs[jj][p] = sv[q][e]; }
+          base += __popcll(m);
+        }
+        if (j == jj) {
+          cn = base;
+          tk = float_from_order(T);
+        }
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     };
@@ -476,25 +516,13 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
         const uint64_t live = __ballot(t * TILE + lane < size && tile_id >= 0);
         const int32_t slot0 = (int32_t)(tile * TILE);
         float key[16];
-        // live bits of this lane's 16 vectors (bit 4b + v: vector 16b + 4g + v)
+        // live bits of this lane's 16 vectors (bit 4b + v: vector 16b + 4g + v);
+        // absent queries take nothing
         const int g4 = lane >> 4;
         uint32_t lm = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) lm |= (uint32_t)((live >> (16 * b + 4 * g4)) & 0xfull) << (4 * b);
-        // branch-free (key, slot) test against the threshold
-        auto passes = [&](int b, int v) {
-          const float kv = key[4 * b + v];
-          const int32_t sv = slot0 + 16 * b + 4 * g4 + v;
-          return (bool)(((lm >> (4 * b + v)) & 1u) & ((kv < tk) | ((kv == tk) & (sv < ts))));
-        };
-        auto count = [&]() {
-          int n = 0;
-#pragma unroll
-          for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) n += passes(b, v) ? 1 : 0;
-          return n;
-        };
+        if (!has) lm = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -505,13 +533,21 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
           }
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
-        // nothing below the threshold in the whole wave: the usual case
-        float kmin = key[0];
+        // bit e: value e is live and at or below the query's threshold
+        auto pass_bits = [&]() {
+          uint32_t m = 0;
 #pragma unroll
-        for (int e = 1; e < 16; ++e) kmin = fminf(kmin, key[e]);
-        int np = 0;
-        if (__ballot(kmin <= tk)) np = count();
-        if (__ballot(np > 0)) {
+          for (int e = 0; e < 16; ++e) m |= (key[e] <= tk ? 1u : 0u) << e;
+          return m & lm;
+        };
+        // nothing at or below the threshold in the whole wave: the usual case
+        float kmin = fminf(fminf(fminf(key[0], key[1]), fminf(key[2], key[3])),
+                           fminf(fminf(key[4], key[5]), fminf(key[6], key[7])));
+        kmin = fminf(kmin, fminf(fminf(fminf(key[8], key[9]), fminf(key[10], key[11])),
+                                 fminf(fminf(key[12], key[13]), fminf(key[14], key[15]))));
+        uint32_t pm = 0;
+        if (__ballot(kmin <= tk && lm != 0)) pm = pass_bits();
+        if (__ballot(pm != 0)) {
           // passes of the query over its four lanes, and this lane's offset
           auto totals = [&](int n, int& tot, int& off) {
             const int n0 = __shfl(n, j), n1 = __shfl(n, j + 16), n2 = __shfl(n, j + 32), n3 = __shfl(n, j + 48);
@@ -519,27 +555,31 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
             off = (g4 > 0 ? n0 : 0) + (g4 > 1 ? n1 : 0) + (g4 > 2 ? n2 : 0);
           };
           int tot, off;
-          totals(np, tot, off);
-          // queries whose buffer would overflow merge it into their list first
-          const uint64_t over = __ballot(lane < G && cn + tot > BUF);
+          totals(__popc(pm), tot, off);
+          // queries whose pool would overflow are cut first, two at a time
+          uint64_t over = __ballot(lane < G && cn + tot > BUF);
           if (over) {
-#pragma unroll
-            for (int jj = 0; jj < G; ++jj)
-              if ((over >> jj) & 1ull) compact(jj, kk + min(SLACK, BUF - WAVE - kk));
-            np = count();
-            totals(np, tot, off);
+            const int keep = kk + min(SLACK, BUF - WAVE - kk);
+            while (over) {
+              int jq[2];
+              jq[0] = __builtin_ctzll(over);
+              over &= over - 1;
+              jq[1] = over ? __builtin_ctzll(over) : -1;
+              if (over) over &= over - 1;
+              cut(std::integral_constant<int, 2>{}, jq, keep);
+            }
+            pm = pass_bits();
+            totals(__popc(pm), tot, off);
           }
           int pos = cn + off;
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              if (passes(b, v)) {
-                Bk[j][pos] = key[4 * b + v];
-                Bs[j][pos] = slot0 + 16 * b + 4 * g4 + v;
-                ++pos;
-              }
+          for (int e = 0; e < 16; ++e) {
+            if ((pm >> e) & 1u) {
+              Bk[j][pos] = key[e];
+              Bs[j][pos] = slot0 + 16 * (e >> 2) + 4 * g4 + (e & 3);
+              ++pos;
             }
+          }
           cn += tot;
           __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         }
@@ -547,32 +587,35 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
     }
     }
     // The item's kk best per query, sorted: pools cut to at most 64 entries
-    // (still holding the kk best), then sorted FB queries at a time (their
-    // shuffles overlap).
+    // (still holding the kk best), four queries at a time, then sorted FB
+    // queries at a time (their shuffles overlap).
     if (gcount > 0) {
 #pragma unroll
-      for (int jj = 0; jj < G; ++jj)
-        if (jj < gcount) compact(jj, WAVE);
+      for (int q0 = 0; q0 < G; q0 += 4) {
+        if (q0 >= gcount) break;
+        int jq[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) jq[q] = q0 + q < gcount ? q0 + q : -1;
+        cut(std::integral_constant<int, 4>{}, jq, WAVE);
+      }
       constexpr int FB = 8;
 #pragma unroll
       for (int q0 = 0; q0 < G; q0 += FB) {
         if (q0 >= gcount) break;
-        float bk[FB];
-        int32_t bs[FB];
+        uint64_t bv[FB];
 #pragma unroll
         for (int q = 0; q < FB; ++q) {
           const int n = __builtin_amdgcn_readlane(cn, q0 + q);
-          bk[q] = lane < n ? Bk[q0 + q][lane] : KEY_EMPTY;
-          bs[q] = lane < n ? Bs[q0 + q][lane] : -1;
+          bv[q] = pack_key_slot(lane < n ? Bk[q0 + q][lane] : KEY_EMPTY, lane < n ? Bs[q0 + q][lane] : -1);
         }
-        wave_sort64_n<FB>(bk, bs);
+        wave_sort64_packed_n<FB>(bv);
 #pragma unroll
         for (int q = 0; q < FB; ++q) {
           if (q0 + q >= gcount) break;
-          const int64_t out = (sorted_base[__builtin_amdgcn_readlane(pidx, q0 + q)] + c) * kk;
+          const int64_t out = (readlane_i64(my_base, q0 + q) + c) * kk;
           if (lane < kk) {
-            pk[out + lane] = bk[q];
-            pi[out + lane] = (int64_t)bs[q];
+            pk[out + lane] = packed_key(bv[q]);
+            pi[out + lane] = (int64_t)packed_slot(bv[q]);
           }
         }
       }
