@@ -672,27 +672,41 @@ __global__ __launch_bounds__(64) void k_rerank(int64_t nq, int k, int kk, const 
   const int64_t myslot = lane < kk ? ri[q * kk + lane] : -1;
   float key = KEY_EMPTY;
   int64_t id = -1;
-  // lanes 8e .. 8e+7 hold the eight partial sums of candidate e (dimension j
-  // goes to partial j mod 8); candidates are handled eight at a time
-  const int part = lane & 7, grp = lane >> 3;
-  for (int e0 = 0; e0 < kk; e0 += 8) {
-    const int e = e0 + grp;
-    const int64_t slot = e < kk ? __shfl(myslot, e) : -1;
-    float acc = 0.f;
+  // lanes 2e and 2e + 1 score candidate e0 + e: lane 2e keeps the partial
+  // sums of dimensions 8i .. 8i + 3, lane 2e + 1 those of 8i + 4 .. 8i + 7
+  // (dimension j goes to partial j mod 8), i ascending, reading 16 bytes of
+  // the row per step; 32 candidates per pass (dp is a multiple of 8)
+  const int half = lane & 1, cand = lane >> 1;
+  const float4* qv4 = reinterpret_cast<const float4*>(qv) + half;
+  for (int e0 = 0; e0 < kk; e0 += 32) {
+    // every lane takes part in the shuffle (lanes >= kk hold slot -1): a
+    // shuffle from a lane switched off by a branch would not return its slot
+    const int64_t slot = __shfl(myslot, e0 + cand);
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
     if (slot >= 0) {
-      const float* xv = rows + slot * (int64_t)dp;
-      for (int jj = part; jj < dp; jj += 8) {
-        const float x = xv[jj], y = qv[jj];
-        acc = METRIC == QUAKE_L2 ? fmaf(x - y, x - y, acc) : fmaf(x, y, acc);
+      const float4* xv4 = reinterpret_cast<const float4*>(rows + slot * (int64_t)dp) + half;
+      for (int i = 0; i < dp / 8; ++i) {
+        const float4 x = xv4[2 * i], y = qv4[2 * i];
+        if (METRIC == QUAKE_L2) {
+          a0 = fmaf(x.x - y.x, x.x - y.x, a0);
+          a1 = fmaf(x.y - y.y, x.y - y.y, a1);
+          a2 = fmaf(x.z - y.z, x.z - y.z, a2);
+          a3 = fmaf(x.w - y.w, x.w - y.w, a3);
+        } else {
+          a0 = fmaf(x.x, y.x, a0);
+          a1 = fmaf(x.y, y.y, a1);
+          a2 = fmaf(x.z, y.z, a2);
+          a3 = fmaf(x.w, y.w, a3);
+        }
       }
     }
-    // pairwise: ((a0+a1)+(a2+a3))+((a4+a5)+(a6+a7))
+    // pairwise: ((p0+p1)+(p2+p3))+((p4+p5)+(p6+p7)), the two halves from the
+    // lane pair
+    float acc = (a0 + a1) + (a2 + a3);
     acc += __shfl_xor(acc, 1);
-    acc += __shfl_xor(acc, 2);
-    acc += __shfl_xor(acc, 4);
     const float d = METRIC == QUAKE_L2 ? acc : -acc;
-    const float dk = __shfl(d, (lane - e0) * 8);
-    if (lane >= e0 && lane < e0 + 8 && myslot >= 0) key = dk;
+    const float dk = __shfl(d, ((lane - e0) & 31) * 2);
+    if (lane >= e0 && lane < e0 + 32 && myslot >= 0) key = dk;
   }
   if (myslot >= 0) id = sid[myslot];
   // bitonic sort of the 64 (key, id) pairs across the wave, ascending
