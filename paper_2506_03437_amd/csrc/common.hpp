@@ -337,6 +337,19 @@ __device__ __forceinline__ void wave_sort64_packed_n(uint64_t (&v)[N]) {
     }
 }
 
+// list (ascending, one packed entry per lane) := the 64 smallest of list and
+// b (ascending): a bitonic split against b reversed, then a bitonic merge.
+__device__ __forceinline__ void wave_merge64_packed(uint64_t& l, uint64_t b) {
+  const int lane = lane_id();
+  const uint64_t r = (uint64_t)shfl_i64((int64_t)b, WAVE - 1 - lane);
+  l = r < l ? r : l;
+#pragma unroll
+  for (int stride = WAVE / 2; stride > 0; stride >>= 1) {
+    const uint64_t o = (uint64_t)shfl_xor_i64((int64_t)l, stride);
+    l = ((o < l) == ((lane & stride) == 0)) ? o : l;
+  }
+}
+
 // lists[q] := the 64 smallest of lists[q] and b[q] (both ascending), for q < N.
 template <int N>
 __device__ __forceinline__ void wave_merge64_n(float* lk, int32_t* ls, float (&bk)[N], int32_t (&bs)[N]) {

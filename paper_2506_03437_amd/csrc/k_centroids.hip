@@ -334,23 +334,24 @@ __global__ __launch_bounds__(256) void k_select64(const float* __restrict__ scor
   const int lane = threadIdx.x & 63;
   if (q >= nq) return;
   const float* s = scores + q * nc;
-  float lk = KEY_EMPTY;
-  int32_t li = INT32_MAX;
+  // (key, id) packed into integers in result order (the key's zero made
+  // positive, so that -0 and +0 tie as they do as floats)
+  const uint64_t empty = pack_key_slot(KEY_EMPTY, INT32_MAX);
+  uint64_t l = empty;
   for (int64_t base = 0; base < nc; base += WAVE) {
     const int64_t e = base + lane;
-    float key = KEY_EMPTY;
-    int32_t id = INT32_MAX;
+    uint64_t v = empty;
     if (e < nc) {
       const float raw = s[e];
-      key = ip ? -raw : raw;
-      id = (int32_t)e;
+      v = pack_key_slot((ip ? -raw : raw) + 0.f, (int32_t)e);
     }
-    const float tk = readlane_f(lk, M - 1);
-    const int32_t ti = (int32_t)__builtin_amdgcn_readlane((uint32_t)li, M - 1);
-    if (!__ballot(ks_less(key, id, tk, ti))) continue;
-    wave_sort64(key, id);
-    wave_merge64(lk, li, key, id);
+    const uint64_t t = (uint64_t)readlane_i64((int64_t)l, M - 1);
+    if (!__ballot(v < t)) continue;
+    uint64_t vs[1] = {v};
+    wave_sort64_packed_n<1>(vs);
+    wave_merge64_packed(l, vs[0]);
   }
+  const int32_t li = packed_slot(l);
   float h = 0.f;
   int32_t tag = lane;
   if (geometry) {
@@ -383,7 +384,10 @@ __global__ __launch_bounds__(256) void k_select64(const float* __restrict__ scor
       if (sep > 0.f) hi = ip ? num / sqrtf(sep) : num / (2.0f * sqrtf(sep));
       if (lane == i) h = fmaxf(hi, 0.f);
     }
-    wave_sort64(h, tag);
+    uint64_t hv[1] = {pack_key_slot(h + 0.f, tag)};
+    wave_sort64_packed_n<1>(hv);
+    h = packed_key(hv[0]);
+    tag = packed_slot(hv[0]);
     if (lane == 0) h = 0.f;
   }
   const int32_t id = __shfl(li, tag);
