@@ -473,22 +473,35 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
     f32x4 acc[4];
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // Ids (and norms) of a tile are loaded one tile ahead: the wait for them
+    // at the tile's end then covers only loads issued before them, not the
+    // stage prefetches issued since (an empty item reads the arena's first
+    // tile, never used).
+    int64_t next_id;
+    float next_xn = 0.f;
+    {
+      const int64_t tn = (U > 0 ? tile0 + t0 : 0) * TILE + lane;
+      next_id = sid[tn];
+      if (!IP) next_xn = v16n[tn];
+    }
     for (int tb = t0; tb < t1; tb += TA) {
 #pragma unroll
     for (int ta = 0; ta < TA; ++ta) {
       const int t = tb + ta;
       if (t >= t1) break;
-      int64_t tile_id = 0;
-      float tile_xn = 0.f;
+      // this tile's ids and norms (loaded during the previous tile); the
+      // next tile's are requested now (the last tile requests itself again)
+      const int64_t tile_id = next_id;
+      const float tile_xn = next_xn;
+      {
+        const int64_t tn = (tile0 + min(t + 1, t1 - 1)) * TILE + lane;
+        next_id = sid[tn];
+        if (!IP) next_xn = v16n[tn];
+      }
 #pragma unroll
       for (int st = 0; st < NS; ++st) {
         const int u = (t - t0) * NS + st;
         const int slot = ta * NS + st;  // u % DEPTH
-        if (st == 0) {
-          // ids and norms of the tile, consumed after its last stage
-          tile_id = sid[(tile0 + t) * TILE + lane];
-          if (!IP) tile_xn = v16n[(tile0 + t) * TILE + lane];
-        }
         // (waves without queries score too - their results are never read -
         // so that the accumulators stay in the matrix registers throughout)
 #pragma unroll
