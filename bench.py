@@ -63,8 +63,12 @@ def profiled_traffic(workload, knobs):
             k, v = line.strip().split(" = ", 1)
             fields[k] = v
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    # how many rounds are enqueued per host sync, and graph replay, leave the
+    # scan launches themselves unchanged
+    same = ("rounds_per_sync", "no_graph")
     want = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in fields.get("knobs", "").split(",") if kv}
-    have = {k: v for k, v in (knobs or {}).items() if v}
+    want = {k: v for k, v in want.items() if k not in same}
+    have = {k: v for k, v in (knobs or {}).items() if v and k not in same}
     if fields.get("kernel_source_sha256") != sha or want != have or "traffic_bytes_per_launch" not in fields:
         return None
     return float(fields["traffic_bytes_per_launch"])

@@ -3,20 +3,21 @@
 // access and scan each partition once per batch, Sec. 7.5).
 //
 // Per round, every query's window of (query, partition) pairs is bucketed by
-// partition.  A work item is (partition, group of up to 16 queries, chunk of
-// tiles).  One wave scores a 64-vector tile against its 16 queries with
-// v_mfma_f32_16x16x32 on the 16-bit store copy (BF16 or FP16 products, FP32
-// accumulation): the queries sit in registers as B operands for the whole
-// item, the tile is read straight from the store into A operands (the store's
-// [chunk][64 vectors][8 elements] tile layout is the A fragment order, so a
-// wave's load of one k-step covers four contiguous 256-byte runs).  The
-// 16 x 64 score block goes through LDS so that each query's 64 scores sit one
-// per lane, where a wave-wide top-k list (one entry per lane) keeps the
-// query's best rerank_factor * k candidates.  Partial lists land in the same
-// per-(query, partition, chunk) slots as the plain scan, so the in-order
-// commit and the recall model are shared.  Candidates carry store slots; after
-// the last round each query's candidates are re-scored in FP32 from the FP32
-// store (the same arithmetic as the plain scan) and the best k are kept.
+// partition.  A work item is (partition chunk of up to chunk_tiles tiles,
+// set of up to 64 of the partition's queries); items are numbered largest
+// partition first.  A block of four waves takes items from a queue; each
+// tile of the chunk is staged once through LDS and scored by the four waves,
+// 16 queries each, with v_mfma_f32_16x16x32 on the 16-bit store copy (BF16
+// or FP16 products, FP32 accumulation): the queries sit in registers as B
+// operands for the whole item and the store's [chunk][64 vectors][8
+// elements] tile layout is the A fragment order.  After each tile every lane
+// holds 16 scores of one query and tests them against the query's threshold;
+// candidates go to a per-query pool in LDS that is cut by ballot-count
+// bisection, and at the item's end each query's best rerank_factor * k
+// (key, slot) are written, sorted, to the same per-(query, partition, chunk)
+// partial-list slots as the plain scan uses, so the in-order commit and the
+// recall model are shared.  Candidates carry store slots; after the last
+// round they are re-scored in FP32 (k_rerank.hip).
 #include <type_traits>
 
 #include "common.hpp"
@@ -663,91 +664,6 @@ void launch_scan_mfma(Workspace& ws, const Store& st, const RoundArgs& a, int dt
   const bool ip = a.metric == QUAKE_IP;
   if (f16) { if (ip) scan_mfma_k<1, 1>(ws, st, a, blocks, s); else scan_mfma_k<1, 0>(ws, st, a, blocks, s); }
   else { if (ip) scan_mfma_k<0, 1>(ws, st, a, blocks, s); else scan_mfma_k<0, 0>(ws, st, a, blocks, s); }
-}
-
-// ---------------------------------------------------------------- rerank
-
-// Re-score each query's candidates (store slots) in FP32 and keep the best k
-// by (distance, id).  The vectors come from the row-major FP32 copy kept for
-// this purpose (one contiguous row per candidate; the tile-interleaved store
-// would fetch a whole cache line per 16 bytes used); the sum runs in the same
-// order as the plain scan's: eight partial sums over the dimensions modulo 8,
-// added pairwise.  One wave per query, one lane per candidate for the sort;
-// the distance of each candidate is computed by the whole wave.
-template <int METRIC>
-__global__ __launch_bounds__(64) void k_rerank(int64_t nq, int k, int kk, const float* __restrict__ qpad, int dp,
-                                                const float* __restrict__ rows, const int64_t* __restrict__ sid,
-                                                float* __restrict__ rk, int64_t* __restrict__ ri,
-                                                const int32_t* __restrict__ slots) {
-  const int64_t q = slots ? slots[blockIdx.x] : blockIdx.x;
-  const int lane = threadIdx.x;
-  const float* qv = qpad + q * dp;
-  const int64_t myslot = lane < kk ? ri[q * kk + lane] : -1;
-  float key = KEY_EMPTY;
-  int64_t id = -1;
-  // lanes 2e and 2e + 1 score candidate e0 + e: lane 2e keeps the partial
-  // sums of dimensions 8i .. 8i + 3, lane 2e + 1 those of 8i + 4 .. 8i + 7
-  // (dimension j goes to partial j mod 8), i ascending, reading 16 bytes of
-  // the row per step; 32 candidates per pass (dp is a multiple of 8)
-  const int half = lane & 1, cand = lane >> 1;
-  const float4* qv4 = reinterpret_cast<const float4*>(qv) + half;
-  for (int e0 = 0; e0 < kk; e0 += 32) {
-    // every lane takes part in the shuffle (lanes >= kk hold slot -1): a
-    // shuffle from a lane switched off by a branch would not return its slot
-    const int64_t slot = __shfl(myslot, e0 + cand);
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-    if (slot >= 0) {
-      const float4* xv4 = reinterpret_cast<const float4*>(rows + slot * (int64_t)dp) + half;
-      for (int i = 0; i < dp / 8; ++i) {
-        const float4 x = xv4[2 * i], y = qv4[2 * i];
-        if (METRIC == QUAKE_L2) {
-          a0 = fmaf(x.x - y.x, x.x - y.x, a0);
-          a1 = fmaf(x.y - y.y, x.y - y.y, a1);
-          a2 = fmaf(x.z - y.z, x.z - y.z, a2);
-          a3 = fmaf(x.w - y.w, x.w - y.w, a3);
-        } else {
-          a0 = fmaf(x.x, y.x, a0);
-          a1 = fmaf(x.y, y.y, a1);
-          a2 = fmaf(x.z, y.z, a2);
-          a3 = fmaf(x.w, y.w, a3);
-        }
-      }
-    }
-    // pairwise: ((p0+p1)+(p2+p3))+((p4+p5)+(p6+p7)), the two halves from the
-    // lane pair
-    float acc = (a0 + a1) + (a2 + a3);
-    acc += __shfl_xor(acc, 1);
-    const float d = METRIC == QUAKE_L2 ? acc : -acc;
-    const float dk = __shfl(d, ((lane - e0) & 31) * 2);
-    if (lane >= e0 && lane < e0 + 32 && myslot >= 0) key = dk;
-  }
-  if (myslot >= 0) id = sid[myslot];
-  // bitonic sort of the 64 (key, id) pairs across the wave, ascending
-  for (int size = 2; size <= WAVE; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      const float ok = __shfl_xor(key, stride);
-      const int64_t oi = (int64_t)(((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)((uint64_t)id >> 32), stride) << 32) |
-                                   (uint32_t)__shfl_xor((int)(uint32_t)(uint64_t)id, stride));
-      const bool up = (lane & size) == 0;
-      const bool lower = (lane & stride) == 0;
-      const bool other_first = kv_less(ok, oi, key, id);
-      const bool take = (lower == up) ? other_first : !other_first;
-      if (take) { key = ok; id = oi; }
-    }
-  }
-  if (lane < k) { rk[q * kk + lane] = key; ri[q * kk + lane] = id; }
-}
-
-void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s, const int32_t* slots,
-                   int64_t nslots) {
-  const int64_t n = slots ? nslots : a.nq;
-  if (n <= 0) return;
-  if (a.metric == QUAKE_L2)
-    hipLaunchKernelGGL(k_rerank<QUAKE_L2>, dim3((unsigned)n), dim3(64), 0, s, a.nq, a.k, a.kk, ws.q, st.dp,
-                       st.rows32, st.ids, ws.rk, ws.ri, slots);
-  else
-    hipLaunchKernelGGL(k_rerank<QUAKE_IP>, dim3((unsigned)n), dim3(64), 0, s, a.nq, a.k, a.kk, ws.q, st.dp,
-                       st.rows32, st.ids, ws.rk, ws.ri, slots);
 }
 
 // ---------------------------------------------------------------- store norms

@@ -129,3 +129,27 @@ def test_batched_rejects_bad_modes(float_ip):
         args.update(kw)
         with pytest.raises(QuakeError):
             idx.search(gu.to_dev(Q[:4]), **args)
+
+
+@pytest.mark.parametrize("metric", ["l2", "ip"])
+def test_batched_heavy_ties(metric):
+    """Every vector stored 20 times: pools fill with equal keys, so cuts land
+    inside runs of ties (the slot bisection) and later candidates tie the
+    threshold.  Ids are exact on this integer data; ties go to the lower id
+    (the 20 copies of a vector all fit in the rerank_factor * k candidates)."""
+    rng = np.random.default_rng(21)
+    base = rng.integers(-4, 5, (60, 32)).astype(np.float32)
+    X = np.repeat(base, 20, axis=0)
+    ids = rng.permutation(100_000)[: X.shape[0]].astype(np.int64)
+    print(f"[build] heavy ties {metric}", flush=True)
+    idx = gu.build(X, ids, metric=metric, nlist=4, storage="bf16", kmeans_iters=3, seed=2)
+    try:
+        Q = np.clip(base[:16] + rng.integers(-1, 2, (16, 32)), -4, 4).astype(np.float32)
+        for k in (10, 16):
+            gi, gv, _, _ = gu.search(idx, Q, k=k, nprobe=4, scan_mode="batched", scan_dtype="bf16",
+                                     rerank_factor=4)
+            ei, ev = oknn.knn_exact(X, ids, Q, k, metric)
+            assert (gi == ei).all()
+            parity.check_all(Q, X, ids, gi, gv, ei, ev, metric, k)
+    finally:
+        idx.free()
