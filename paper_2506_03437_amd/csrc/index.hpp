@@ -256,6 +256,7 @@ struct RoundArgs {
   double tau_r, tau_rho;
   int64_t items_cap;
   int blocks;        // grid of the persistent scan kernels (they read their item counts on the device)
+  int slot_ids;      // 1: the lists carry store slots below 2^31 (batched path), not ids
 };
 void launch_round_init(Workspace& ws, const RoundArgs& a, int w0, hipStream_t s);
 void launch_demand(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);

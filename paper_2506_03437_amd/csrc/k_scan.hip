@@ -565,6 +565,35 @@ struct RegList {
   }
 };
 
+// The committed list of a batched search, whose entries carry store slots
+// (below 2^31): (key, slot) packed into integers in result order, so that a
+// merge step is one 64-bit compare.  A zero key is stored as +0 (a -0 key
+// compares equal to it as a float).  Empty entries are (+inf, -1).
+struct PackedList {
+  uint64_t v, nv;
+  int kk;
+  __device__ static uint64_t empty() { return pack_key_slot(KEY_EMPTY, -1); }
+  __device__ void load(const float* rk, const int64_t* ri) {
+    const int lane = lane_id();
+    v = lane < kk ? pack_key_slot(rk[lane] + 0.f, (int32_t)ri[lane]) : empty();
+  }
+  __device__ void prime(const float* pk, const int64_t* pi) {
+    const int lane = lane_id();
+    nv = lane < kk ? pack_key_slot(pk[lane] + 0.f, (int32_t)pi[lane]) : empty();
+  }
+  __device__ void merge(const float*, const int64_t*, const float* next_k, const int64_t* next_i) {
+    const uint64_t b = nv;
+    if (next_k) prime(next_k, next_i);
+    wave_merge64_packed(v, b);
+  }
+  __device__ float key(int j) const { return packed_key((uint64_t)readlane_i64((int64_t)v, j)); }
+  __device__ int64_t id(int j) const { return (int64_t)packed_slot((uint64_t)readlane_i64((int64_t)v, j)); }
+  __device__ void store(float* rk, int64_t* ri) const {
+    const int lane = lane_id();
+    if (lane < kk) { rk[lane] = packed_key(v); ri[lane] = (int64_t)packed_slot(v); }
+  }
+};
+
 // Commit one query's window in candidate order: merge each work item's
 // partial list into the committed list; after each partition, update the
 // recall model (recompute when rho moved by more than tau_rho * rho) and stop
@@ -667,10 +696,11 @@ __global__ __launch_bounds__(64) void k_commit(QK_COMMIT_PARAMS) {
 
 // Lists of at most 64 entries: one wave per query, four queries per block,
 // lists in registers.
+template <class List>
 __global__ __launch_bounds__(256) void k_commit64(QK_COMMIT_PARAMS) {
   const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (q >= nq || st_done[q] || st_weff[q] == 0) return;
-  RegList L;
+  List L;
   L.kk = kk;
   commit_query(q, L, QK_COMMIT_ARGS);
 }
@@ -682,7 +712,8 @@ void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const dou
                      a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.tau_r, a.tau_rho, ws.cand, ws.h,  \
                      st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_weff,        \
                      ws.st_item, ws.st_rho, ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri)
-  if (a.kk <= WAVE) QK_COMMIT(k_commit64, (a.nq + 3) / 4, 256);
+  if (a.kk <= WAVE && a.slot_ids) QK_COMMIT(k_commit64<PackedList>, (a.nq + 3) / 4, 256);
+  else if (a.kk <= WAVE) QK_COMMIT(k_commit64<RegList>, (a.nq + 3) / 4, 256);
   else if (a.kk <= KMAX) QK_COMMIT(k_commit<KMAX>, a.nq, 64);
   else QK_COMMIT(k_commit<KMAX_LARGE>, a.nq, 64);
 #undef QK_COMMIT
