@@ -92,26 +92,63 @@ __device__ __forceinline__ void tile_stage(const float (*qs)[SLD], const float (
     for (int j = 0; j < 4; ++j) acc[i][j] += part[i][j];
 }
 
-// S[q][c] = |q - c|^2 (L2) or q . c (IP) for a 64 x 64 tile per block.
+// S[q][c] = |q - c|^2 (L2) or q . c (IP) for a 64 x 64 tile per block.  The
+// slabs are double-buffered: the next slab's share of every thread is read
+// into registers while the current one is scored from LDS, so one barrier
+// per slab remains and the global loads' latency hides behind the products.
 template <int METRIC>
 __global__ __launch_bounds__(256) void k_scores(const float* __restrict__ q, int64_t nq,
                                                  const float* __restrict__ c, int64_t nc, int dp,
                                                  float* __restrict__ out) {
-  __shared__ float qs[ST][SLD];
-  __shared__ float cs[ST][SLD];
+  __shared__ float qs[2][ST][SLD];
+  __shared__ float cs[2][ST][SLD];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int64_t c0 = (int64_t)blockIdx.x * ST, q0 = (int64_t)blockIdx.y * ST;
+  // this thread's two 16-byte pieces of each 64 x 32 slab (pieces e and
+  // e + 256 of the slab's 512: row e >> 3, dimensions (e & 7) * 4 ..)
+  auto fetch = [&](const float* __restrict__ src, int64_t row0, int64_t rows, int k0, float4 (&v)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      const int r = e >> 3, k4 = (e & 7) * 4;
+      const int64_t g = row0 + r;
+      v[h] = (g < rows && k0 + k4 < dp) ? *reinterpret_cast<const float4*>(src + g * dp + k0 + k4)
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto put = [&](float (*dst)[SLD], const float4 (&v)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      *reinterpret_cast<float4*>(&dst[e >> 3][(e & 7) * 4]) = v[h];
+    }
+  };
   float acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+  float4 vq[2], vc[2];
+  fetch(q, q0, nq, 0, vq);
+  fetch(c, c0, nc, 0, vc);
+  put(qs[0], vq);
+  put(cs[0], vc);
+  __syncthreads();
+  int buf = 0;
   for (int k0 = 0; k0 < dp; k0 += SK) {
-    stage_slab(qs, q, q0, nq, dp, k0);
-    stage_slab(cs, c, c0, nc, dp, k0);
+    const bool more = k0 + SK < dp;
+    if (more) {
+      fetch(q, q0, nq, k0 + SK, vq);
+      fetch(c, c0, nc, k0 + SK, vc);
+    }
+    tile_stage<METRIC>(qs[buf], cs[buf], tx, ty, acc);
+    // the other buffer was last read before the previous barrier
+    if (more) {
+      put(qs[buf ^ 1], vq);
+      put(cs[buf ^ 1], vc);
+    }
     __syncthreads();
-    tile_stage<METRIC>(qs, cs, tx, ty, acc);
-    __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
