@@ -1,6 +1,7 @@
 // Device-side building blocks shared by the kernels: the (key, id) total
-// order of results, a wave-wide sorted top-k list, an LDS bitonic sort and a
-// co-rank merge of two sorted lists.
+// order of results, a wave-wide sorted top-k list, an LDS bitonic sort, a
+// co-rank merge of two sorted lists, wave bitonic sorts and merges of
+// (key, slot) packed into ordered integers, and DPP wave reductions.
 //
 // Result order: a result is a pair (key, id) with key = squared L2 distance,
 // or the negated inner product, so that smaller is better for both metrics;
@@ -235,78 +236,6 @@ __device__ __forceinline__ void wave_merge64_kv(float& ak, int64_t& ai, float bk
   }
 }
 
-// (key, 32-bit tag) entries, one per lane: the same order with a 32-bit
-// tiebreak (a store slot or a list position).
-__device__ __forceinline__ bool ks_less(float ak, int32_t as, float bk, int32_t bs) {
-  return ak < bk || (ak == bk && as < bs);
-}
-
-__device__ __forceinline__ void swap_if(bool take, float& k, int32_t& s, float ok, int32_t os) {
-  if (take) { k = ok; s = os; }
-}
-
-// One compare-exchange stage of a bitonic network across the wave: lanes
-// `stride` apart swap so that the lower lane of each pair keeps the smaller
-// entry in ascending runs of length `size` (and the larger in descending ones).
-__device__ __forceinline__ void bitonic_step(float& k, int32_t& s, int size, int stride) {
-  const int lane = lane_id();
-  const float ok = __shfl_xor(k, stride);
-  const int32_t os = __shfl_xor(s, stride);
-  const bool up = (lane & size) == 0;
-  const bool lower = (lane & stride) == 0;
-  const bool other_first = ks_less(ok, os, k, s);
-  swap_if((lower == up) ? other_first : (!other_first && (ok != k || os != s)), k, s, ok, os);
-}
-
-// Sort one entry per lane ascending by (key, slot).
-__device__ __forceinline__ void wave_sort64(float& k, int32_t& s) {
-#pragma unroll
-  for (int size = 2; size <= WAVE; size <<= 1)
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) bitonic_step(k, s, size, stride);
-}
-
-// list (ascending, one entry per lane) := the 64 smallest of list and b
-// (b ascending): a bitonic split against b reversed, then a bitonic merge.
-__device__ __forceinline__ void wave_merge64(float& lk, int32_t& ls, float bk, int32_t bs) {
-  const int lane = lane_id();
-  const float rk = __shfl(bk, WAVE - 1 - lane);
-  const int32_t rs = __shfl(bs, WAVE - 1 - lane);
-  swap_if(ks_less(rk, rs, lk, ls), lk, ls, rk, rs);
-#pragma unroll
-  for (int stride = WAVE / 2; stride > 0; stride >>= 1) bitonic_step(lk, ls, WAVE, stride);
-}
-
-// N independent lists at once (one entry per lane in each): the shuffles of
-// the N lists are independent, so their latencies overlap.
-template <int N>
-__device__ __forceinline__ void bitonic_step_n(float (&k)[N], int32_t (&s)[N], int size, int stride) {
-  const int lane = lane_id();
-  float ok[N];
-  int32_t os[N];
-#pragma unroll
-  for (int q = 0; q < N; ++q) {
-    ok[q] = __shfl_xor(k[q], stride);
-    os[q] = __shfl_xor(s[q], stride);
-  }
-  const bool up = (lane & size) == 0;
-  const bool lower = (lane & stride) == 0;
-#pragma unroll
-  for (int q = 0; q < N; ++q) {
-    const bool other_first = ks_less(ok[q], os[q], k[q], s[q]);
-    swap_if((lower == up) ? other_first : (!other_first && (ok[q] != k[q] || os[q] != s[q])), k[q], s[q], ok[q],
-            os[q]);
-  }
-}
-
-template <int N>
-__device__ __forceinline__ void wave_sort64_n(float (&k)[N], int32_t (&s)[N]) {
-#pragma unroll
-  for (int size = 2; size <= WAVE; size <<= 1)
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) bitonic_step_n<N>(k, s, size, stride);
-}
-
 // (key, slot) packed into one integer whose unsigned order is the result
 // order: the key's order-preserving bits above the slot's bits (slots are
 // >= 0; the empty entry (+inf, -1) sorts last).
@@ -348,26 +277,6 @@ __device__ __forceinline__ void wave_merge64_packed(uint64_t& l, uint64_t b) {
     const uint64_t o = (uint64_t)shfl_xor_i64((int64_t)l, stride);
     l = ((o < l) == ((lane & stride) == 0)) ? o : l;
   }
-}
-
-// lists[q] := the 64 smallest of lists[q] and b[q] (both ascending), for q < N.
-template <int N>
-__device__ __forceinline__ void wave_merge64_n(float* lk, int32_t* ls, float (&bk)[N], int32_t (&bs)[N]) {
-  const int lane = lane_id();
-  float mk[N];
-  int32_t ms[N];
-#pragma unroll
-  for (int q = 0; q < N; ++q) {
-    const float rk = __shfl(bk[q], WAVE - 1 - lane);
-    const int32_t rs = __shfl(bs[q], WAVE - 1 - lane);
-    mk[q] = lk[q];
-    ms[q] = ls[q];
-    swap_if(ks_less(rk, rs, mk[q], ms[q]), mk[q], ms[q], rk, rs);
-  }
-#pragma unroll
-  for (int stride = WAVE / 2; stride > 0; stride >>= 1) bitonic_step_n<N>(mk, ms, WAVE, stride);
-#pragma unroll
-  for (int q = 0; q < N; ++q) { lk[q] = mk[q]; ls[q] = ms[q]; }
 }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
