@@ -38,8 +38,7 @@ __global__ __launch_bounds__(256) void k_rerank_dist(int64_t nrows, int kk, cons
   if (slot >= 0) {
     const float4* xv4 = reinterpret_cast<const float4*>(rows + slot * (int64_t)dp) + half;
     const float4* qv4 = reinterpret_cast<const float4*>(qpad + (e / kk) * (int64_t)dp) + half;
-    for (int i = 0; i < dp / 8; ++i) {
-      const float4 x = xv4[2 * i], y = qv4[2 * i];
+    auto step = [&](const float4 x, const float4 y) {
       if (METRIC == QUAKE_L2) {
         a0 = fmaf(x.x - y.x, x.x - y.x, a0);
         a1 = fmaf(x.y - y.y, x.y - y.y, a1);
@@ -51,7 +50,21 @@ __global__ __launch_bounds__(256) void k_rerank_dist(int64_t nrows, int kk, cons
         a2 = fmaf(x.z, y.z, a2);
         a3 = fmaf(x.w, y.w, a3);
       }
+    };
+    // eight steps' loads are issued before their products (the sums still
+    // run in order, step by step)
+    const int steps = dp / 8, whole = steps & ~7;
+    for (int i0 = 0; i0 < whole; i0 += 8) {
+      float4 xs[8], ys[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        xs[u] = xv4[2 * (i0 + u)];
+        ys[u] = qv4[2 * (i0 + u)];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) step(xs[u], ys[u]);
     }
+    for (int i = whole; i < steps; ++i) step(xv4[2 * i], qv4[2 * i]);
   }
   // pairwise: ((p0+p1)+(p2+p3))+((p4+p5)+(p6+p7)), the two halves from the
   // lane pair (every lane takes part in the shuffle)
