@@ -404,16 +404,21 @@ __global__ __launch_bounds__(256) void k_select64(const float* __restrict__ scor
     for (int i = 1; i < M; ++i) {
       const int32_t ci = (int32_t)__builtin_amdgcn_readlane((uint32_t)li, i);
       const float* civ = c + (int64_t)ci * dp;
+      // the row's loads are unconditional (clamped; lanes past dp add
+      // nothing), so they are all in flight before the first product
+      float bv[DPL];
+#pragma unroll
+      for (int t = 0; t < DPL; ++t) bv[t] = civ[min(t * WAVE + lane, dp - 1)];
       float num = 0.f, sep = 0.f;
 #pragma unroll
       for (int t = 0; t < DPL; ++t) {
         const int j = t * WAVE + lane;
-        if (j < dp) {
-          const float a = ar[t], b = civ[j], x = qr[t];
-          const float diff = a - b;
-          sep = fmaf(diff, diff, sep);
-          num = ip ? fmaf(x, diff, num) : fmaf(diff, (x - a) + (x - b), num);
-        }
+        const float a = ar[t], b = bv[t], x = qr[t];
+        const float diff = a - b;
+        const float s2 = fmaf(diff, diff, sep);
+        const float n2 = ip ? fmaf(x, diff, num) : fmaf(diff, (x - a) + (x - b), num);
+        sep = j < dp ? s2 : sep;
+        num = j < dp ? n2 : num;
       }
       num = wave_sum_f(num);
       sep = wave_sum_f(sep);
