@@ -616,18 +616,31 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
   const int m0 = st_m[q];
   const int Mq = mq[q];
   int64_t it = st_item[q];
+  const float* hq = hcand + q * M;
+  // chunk counts and bisector distances of the window's first 64 slots, slot
+  // j in lane j: loaded together rather than one slot after another
+  int my_nch = 0;
+  float my_h = 0.f;
+  if (lane < w) {
+    my_nch = item_chunks(psize[cand[q * M + m0 + lane]], chunk_tiles);
+    if (aps) my_h = hq[m0 + lane];
+  }
   int64_t it_end = it;
-  for (int j = 0; j < w; ++j) it_end += item_chunks(psize[cand[q * M + m0 + j]], chunk_tiles);
+  {
+    int sum = my_nch;
+    for (int o = WAVE / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    it_end += sum;
+  }
+  for (int j = WAVE; j < w; ++j) it_end += item_chunks(psize[cand[q * M + m0 + j]], chunk_tiles);
   L.prime(pk + it * kk, pi + it * kk);
   Model md{st_rho[q], st_p0[q], st_V[q], st_vsum[q]};
   const double qn = ip ? qn2[q] : 0.0;
-  const float* hq = hcand + q * M;
   double r = st_r[q];
   int committed = m0;
   bool stop = false;
   for (int j = 0; j < w && !stop; ++j) {
-    const int p = cand[q * M + m0 + j];
-    const int nch = item_chunks(psize[p], chunk_tiles);
+    const int nch = j < WAVE ? __builtin_amdgcn_readlane(my_nch, j)
+                             : item_chunks(psize[cand[q * M + m0 + j]], chunk_tiles);
     for (int c = 0; c < nch; ++c, ++it) {
       const bool more = it + 1 < it_end;
       L.merge(pk + it * kk, pi + it * kk, more ? pk + (it + 1) * kk : nullptr, more ? pi + (it + 1) * kk : nullptr);
@@ -645,7 +658,8 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
       if (redo) {
         recompute_model(md, rho_new, hq, Mq, committed, table);
       } else if (md.V > 0.0) {
-        const double t = __builtin_isinf(md.rho) ? 0.0 : (double)hq[committed - 1] / md.rho;
+        const float hc = j < WAVE ? readlane_f(my_h, j) : hq[committed - 1];  // committed - 1 = m0 + j
+        const double t = __builtin_isinf(md.rho) ? 0.0 : (double)hc / md.rho;
         md.vsum += cap_share(table, t);
       }
     }
