@@ -103,10 +103,20 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_demand(int64_t nq, int M, int ch
     const int m = st_m[q];
     w = st_w[q];
     if (w > mq[q] - m) w = mq[q] - m;
-    for (int j = 0; j < w; ++j) {
-      const int32_t sz = psize[cand[q * M + m + j]];
-      dmd += item_chunks(sz, chunk_tiles);
-      nv += sz;
+    // eight slots at a time: their candidate loads, then their size loads,
+    // are in flight together
+    for (int j0 = 0; j0 < w; j0 += 8) {
+      int32_t c8[8], s8[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) c8[u] = cand[q * M + m + min(j0 + u, w - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s8[u] = psize[c8[u]];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (j0 + u < w) {
+          dmd += item_chunks(s8[u], chunk_tiles);
+          nv += s8[u];
+        }
     }
   }
   int64_t td, tw, tv;
