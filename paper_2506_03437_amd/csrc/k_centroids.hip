@@ -375,13 +375,14 @@ __global__ __launch_bounds__(256) void k_select64(const float* __restrict__ scor
   // positive, so that -0 and +0 tie as they do as floats)
   const uint64_t empty = pack_key_slot(KEY_EMPTY, INT32_MAX);
   uint64_t l = empty;
+  // each chunk's scores are requested one chunk ahead (clamped reads)
+  float raw_next = s[min<int64_t>(lane, nc - 1)];
   for (int64_t base = 0; base < nc; base += WAVE) {
     const int64_t e = base + lane;
+    const float raw = raw_next;
+    raw_next = s[min<int64_t>(base + WAVE + lane, nc - 1)];
     uint64_t v = empty;
-    if (e < nc) {
-      const float raw = s[e];
-      v = pack_key_slot((ip ? -raw : raw) + 0.f, (int32_t)e);
-    }
+    if (e < nc) v = pack_key_slot((ip ? -raw : raw) + 0.f, (int32_t)e);
     const uint64_t t = (uint64_t)readlane_i64((int64_t)l, M - 1);
     if (!__ballot(v < t)) continue;
     uint64_t vs[1] = {v};
