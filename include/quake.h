@@ -51,6 +51,23 @@ enum { QUAKE_L2 = 0, QUAKE_IP = 1 };
 enum { QUAKE_F32 = 0, QUAKE_BF16 = 1, QUAKE_F16 = 2 };
 enum { QUAKE_SCAN_PLAIN = 0, QUAKE_SCAN_BATCHED = 1 };
 
+/* Device memory provider for everything an index allocates: its partition
+ * store, id map, search workspace and temporary build / update buffers.
+ * alloc(bytes, ctx) returns device memory of at least `bytes` bytes on the
+ * current device, aligned to at least 256 bytes, or NULL when it cannot
+ * (the call then fails with QUAKE_E_NOMEM); free(p, ctx) takes back a
+ * pointer alloc returned.  ctx is passed through unchanged.  The library
+ * waits for the device to be idle before it frees a block, as hipFree does.
+ * The index keeps a copy of the struct, so both functions and ctx must stay
+ * valid until quake_free returns; they may be called from the serving
+ * loop's worker thread.  The Python binding passes torch's caching
+ * allocator.  A NULL allocator (or a NULL alloc) means hipMalloc / hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* p, void* ctx);
+  void* ctx;
+} quake_allocator;
+
 /* Build parameters (Sec. 3 index structure; k-means partitioning, Sec. 1). */
 typedef struct {
   int32_t metric;          /* QUAKE_L2 (squared Euclidean) or QUAKE_IP (inner product; rows
@@ -63,6 +80,12 @@ typedef struct {
   int64_t nlist_top;       /* level-1 partitions when n_levels == 2 */
   uint64_t seed;           /* k-means initialisation */
   const float* centroids;  /* optional device [nlist][d]: use these centroids (no k-means) */
+  const int32_t* assign;   /* optional device [n]: partition of every row, in [0, nlist).  Given,
+                              the rows are placed as it says (no nearest-centroid placement: the
+                              recall model's pruning assumes every row sits in its nearest
+                              partition, Sec. 5 "Geometric Model", which is then the caller's to keep); without
+                              centroids, each centroid is the mean of its rows (unit length for
+                              QUAKE_IP) and every partition must receive a row */
   size_t hbm_budget_bytes; /* 0 = unlimited; else every device allocation of the index counts */
   double capacity_slack;   /* extra partition capacity for inserts, fraction of size (>= 0) */
 } quake_build_params;
@@ -78,21 +101,28 @@ typedef struct {
   double upper_recall_target; /* two-level: level-1 target (paper fixes 99%); 0 -> 0.99 */
   double upper_f_M;        /* two-level: level-1 candidate fraction; 0 -> 0.25 */
   int32_t scan_mode;       /* QUAKE_SCAN_PLAIN: per-(query, partition) scans;
-                              QUAKE_SCAN_BATCHED: queries grouped per partition (Sec. 7.5) */
+                              QUAKE_SCAN_BATCHED: queries grouped per partition (Sec. 7.4, "Multi-Query Processing") */
   int32_t scan_dtype;      /* QUAKE_F32, or the index's reduced-precision copy */
   int32_t rerank_factor;   /* reduced precision: keep rerank_factor*k candidates, rerank in FP32;
-                              0 -> 4 */
+                              0 -> 4; -1: no rerank, the k best by the 16-bit path's own values
+                              (IP: the MFMA dot of the rounded query and row, FP32 accumulation;
+                              L2: |q|^2 + |x~|^2 - 2 q~.x~ with x~, q~ the rounded vectors) */
   int32_t window;          /* first-round speculation window (partitions per query); 0 -> auto */
 } quake_search_params;
 
 /* Build an index over x[n][d] (device, float32) with ids[n] (device int64,
  * unique, >= 0; NULL -> 0..n-1).  Runs k-means on the device unless
- * params->centroids is given; every vector is then placed in its nearest
- * centroid's partition.  *out receives the new handle.
- * Errors: INVALID (n < 1, d < 1 or > 4096, nlist out of range, bad enums),
+ * params->centroids or params->assign is given; without params->assign
+ * every vector is then placed in its nearest centroid's partition.  Device
+ * memory comes from `allocator` (NULL: hipMalloc).  *out receives the new
+ * handle.
+ * Errors: INVALID (n < 1, d < 1 or > 4096, nlist out of range, bad enums,
+ * a non-finite value in x or the given centroids, an assign entry outside
+ * [0, nlist), an empty partition under assign without centroids),
  * DUPLICATE (repeated ids), NOMEM, DEVICE. */
 int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d,
-                const quake_build_params* params, void* stream, quake_index** out);
+                const quake_build_params* params, const quake_allocator* allocator, void* stream,
+                quake_index** out);
 
 /* Search nq queries q[nq][d] (device float32).  Writes out_ids[nq][k]
  * (device int64) and out_dist[nq][k] (device float32): squared L2 distances
@@ -101,7 +131,8 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d,
  * skip): out_nscanned[nq] (device int32, partitions scanned at level 0) and
  * out_recall[nq] (device float64, the recall estimate at stop; 1 in nprobe mode).
  * Errors: INVALID (nq < 0, k, both/neither of nprobe / recall_target,
- * scan_dtype without a matching copy), NOMEM, DEVICE. */
+ * scan_dtype without a matching copy, a non-finite value in q; checked
+ * before any search work), NOMEM, DEVICE. */
 int quake_search(quake_index* index, const float* q, int64_t nq, const quake_search_params* params,
                  int64_t* out_ids, float* out_dist, int32_t* out_nscanned, double* out_recall,
                  void* stream);
@@ -110,7 +141,8 @@ int quake_search(quake_index* index, const float* q, int64_t nq, const quake_sea
  * batch (Sec. 2.1 updates; Sec. 3: each vector goes top-down to its nearest
  * leaf partition and is appended there).  Centroids do not move.
  * Errors: DUPLICATE (repeated id or id already present; nothing applied),
- * INVALID, NOMEM, DEVICE. */
+ * INVALID (negative id, a non-finite value in x; nothing applied), NOMEM,
+ * DEVICE. */
 int quake_insert(quake_index* index, const float* x, const int64_t* ids, int64_t n, void* stream);
 
 /* Delete the vectors with ids[n] (device int64) as one batch (Sec. 3: found
@@ -132,15 +164,20 @@ int quake_export(const quake_index* index, float* centroids, int64_t* ids, int32
 int quake_export_top(const quake_index* index, float* top_centroids, int32_t* top_of, void* stream);
 
 /* Candidate order of Adaptive Partition Scanning for nq queries, without
- * scanning: order[nq][M] (device int32, c_0 first, then ascending bisector
- * distance) and h[nq][M] (device float32, h[.][0] = 0).  M = ceil(f_M * nlist)
- * clamped to [1, nlist]; *out_M receives it.  Single-level indexes only. */
-int quake_candidates(quake_index* index, const float* q, int64_t nq, double f_M,
+ * scanning level 0: order[nq][M] (device int32, c_0 first, then ascending
+ * bisector distance) and h[nq][M] (device float32, h[.][0] = 0), with
+ * M = ceil(params->f_M * nlist) clamped to [1, nlist] (f_M 0 -> 0.05);
+ * *out_M receives M.  Of params only f_M, tau_rho and the upper-level
+ * settings are read.  On a two-level index the candidates are the ones the
+ * level-1 search returns, as in quake_search (Sec. 3; Sec. 5.1: APS at
+ * every level); a query given fewer than M has order -1 and h 0 after them.
+ * q = NULL with nq = 0 only reports M. */
+int quake_candidates(quake_index* index, const float* q, int64_t nq, const quake_search_params* params,
                      int32_t* order, float* h, int32_t* out_M, void* stream);
 
 /* The recall model's cap-volume table for dimension d (host memory): the
  * volume share of a d-ball beyond a hyperplane at distance t, at the 1,024
- * points t_j = j / 1023 (Sec. 5.3).  Host-only, no device needed. */
+ * points t_j = j / 1023 (Sec. 5.1, "Performance Optimizations").  Host-only, no device needed. */
 int quake_cap_table(int32_t d, double* out_1024);
 
 /* Scheduling knobs of the search; 0 keeps the built-in default.  They change

@@ -11,7 +11,7 @@ It is a plain, slow, FP64 NumPy restatement of what the search computes:
               Scanning (Sec. 5, Eqs. aps-pi / aps-p0 / aps-pi-final,
               Algorithm "Adaptive Partition Scanning")
 * ``twolevel`` search through a two-level index (Sec. 3 and Sec. 5; the
-              upper level's recall target is fixed, Sec. 5.2 / Table
+              upper level's recall target is fixed, Sec. 5.1 / Table
               two_level_results)
 * ``updates`` batched insert / delete replay (Sec. 2.1 and Sec. 3)
 * ``kmeans``  Lloyd iterations used only to check the device build's

@@ -2,7 +2,7 @@
 
 Test infrastructure only (see the package docstring).
 
-Geometric model (Sec. 5.1, Eq. aps-pi): with rho the distance from the query
+Geometric model (Sec. 5, "Geometric Model", Eq. aps-pi): with rho the distance from the query
 to its k-th nearest neighbour found so far, the chance that partition P_i
 holds a neighbour is the share of the ball B(q, rho) inside P_i.  Each
 neighbouring partition is approximated by the half-space beyond the
@@ -25,7 +25,7 @@ reason in the design notes):
       on the number of candidates only.)
 * R2  the 1,024-point precomputed table is indexed by t = h / rho on an
       even grid t_j = j / 1023, j = 0..1023, with linear interpolation
-      (Sec. 5.3).
+      (Sec. 5.1, "Performance Optimizations").
 * R3  until k results exist rho = +inf, every t = 0, and the estimated
       recall is held at 0.
 * R4  the recompute test compares against the rho of the last recompute;

@@ -5,7 +5,7 @@ Test infrastructure only (see the package docstring).
 Level 0 partitions the vectors; level 1 partitions the level-0 centroids;
 the top is one partition (Sec. 3).  APS runs at each level independently
 (Sec. 5), with the upper level's recall target fixed high (99% in the
-paper, Sec. 5.2 and Table two_level_results) and its own candidate
+paper, Sec. 5.1 and Table two_level_results) and its own candidate
 fraction (25% at level 1, 1.5% at level 0 in the paper's Sift10M runs).
 
 Reading (the paper does not spell out the hand-over between levels): the

@@ -3,9 +3,9 @@
 // The share of a ball of radius rho beyond a hyperplane at distance h from
 // its centre is a hyperspherical cap; with t = h / rho in [0, 1) its share of
 // the ball is 1/2 * I_{1 - t^2}((d + 1) / 2, 1/2), I being the regularised
-// incomplete beta function (Sec. 5.1 cites this closed form).  The search
+// incomplete beta function (Sec. 5, "Geometric Model", cites this closed form).  The search
 // looks the share up in a table of 1,024 evenly spaced t in [0, 1] with
-// linear interpolation (Sec. 5.3); this file fills that table.
+// linear interpolation (Sec. 5.1, "Performance Optimizations"); this file fills that table.
 //
 // I_x(a, b) is evaluated from its continued fraction
 //   I_x(a, b) = x^a (1 - x)^b / (a B(a, b)) * 1 / (1 + e_1 / (1 + e_2 / (1 + ...)))

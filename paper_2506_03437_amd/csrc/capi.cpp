@@ -63,7 +63,14 @@ void* DeviceMemory::raw_alloc(size_t bytes) {
     throw Error{QUAKE_E_NOMEM, "HBM budget exceeded: " + std::to_string(used + bytes) + " > " +
                                    std::to_string(budget) + " bytes"};
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+  if (user.alloc) {
+    p = user.alloc(bytes, user.ctx);
+    if (!p) throw Error{QUAKE_E_NOMEM, "the allocator returned no memory for " + std::to_string(bytes) + " bytes"};
+    if (reinterpret_cast<uintptr_t>(p) % 256 != 0) {
+      if (user.free) user.free(p, user.ctx);
+      throw Error{QUAKE_E_NOMEM, "the allocator returned a block not aligned to 256 bytes"};
+    }
+  } else if (hipMalloc(&p, bytes) != hipSuccess || !p) {
     (void)hipGetLastError();
     throw Error{QUAKE_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
   }
@@ -76,7 +83,14 @@ void DeviceMemory::release(void* p) {
   if (!p) return;
   for (size_t i = 0; i < blocks_.size(); ++i)
     if (blocks_[i].p == p) {
-      (void)hipFree(p);
+      if (user.alloc) {
+        // work queued on any stream may still use the block; hipFree waits
+        // for the device, and so does a release through the allocator
+        (void)hipDeviceSynchronize();
+        if (user.free) user.free(p, user.ctx);
+      } else {
+        (void)hipFree(p);
+      }
       used -= blocks_[i].bytes;
       blocks_[i] = blocks_.back();
       blocks_.pop_back();
@@ -85,7 +99,13 @@ void DeviceMemory::release(void* p) {
 }
 
 DeviceMemory::~DeviceMemory() {
-  for (auto& b : blocks_) (void)hipFree(b.p);
+  if (user.alloc) {
+    (void)hipDeviceSynchronize();
+    if (user.free)
+      for (auto& b : blocks_) user.free(b.p, user.ctx);
+  } else {
+    for (auto& b : blocks_) (void)hipFree(b.p);
+  }
 }
 
 hipEvent_t Profiler::event() {
@@ -156,6 +176,35 @@ void grow(qk::DeviceMemory& mem, T*& p, int64_t& cap, int64_t need) {
   p = mem.alloc<T>((size_t)cap);
 }
 
+// Fraction bits of the fixed-point cluster sums over rows [n][dp]: n *
+// max|x| * 2^bits stays below 2^62 (inputs are checked finite beforehand).
+int fixed_point_bits(qk::DeviceMemory& mem, const float* x, int64_t n, int dp, hipStream_t s) {
+  Tmp<uint32_t> amax(mem, 1);
+  QK_HIP(hipMemsetAsync(amax.p, 0, sizeof(uint32_t), s));
+  qk::launch_absmax(x, n * dp, amax.p, s);
+  uint32_t bits = 0;
+  QK_HIP(hipMemcpyAsync(&bits, amax.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  float m;
+  std::memcpy(&m, &bits, sizeof(m));
+  int frac_bits = 40;
+  if (m > 0.f) frac_bits = (int)std::floor(62.0 - std::log2((double)n * (double)m)) - 1;
+  return std::max(-60, std::min(frac_bits, 60));
+}
+
+// Centroid j = mean of the rows assigned to j (unit length when normalise),
+// from exact fixed-point sums; counts[j] receives the row count.  A centroid
+// with no rows is left as it was.
+void centroids_from(qk::DeviceMemory& mem, const float* x, int64_t n, int dp, const int32_t* assign, int64_t nc,
+                    int normalise, int frac_bits, float* centroids, int32_t* counts, hipStream_t s) {
+  Tmp<int64_t> sums(mem, (size_t)nc * dp);
+  QK_HIP(hipMemsetAsync(sums.p, 0, (size_t)nc * dp * sizeof(int64_t), s));
+  QK_HIP(hipMemsetAsync(counts, 0, (size_t)nc * sizeof(int32_t), s));
+  qk::launch_kmeans_accumulate(x, n, dp, assign, frac_bits, sums.p, counts, s);
+  qk::launch_kmeans_update(sums.p, counts, nc, dp, normalise, frac_bits, centroids, s);
+  QK_HIP(hipStreamSynchronize(s));
+}
+
 // Lloyd's k-means on the device over (a seeded sample of) the rows.  Rows
 // and centroids are [.][dp] FP32.  Initial centroids are distinct random
 // rows; an empty cluster is re-seeded with a random row.  Spherical k-means
@@ -192,32 +241,15 @@ void kmeans(qk::DeviceMemory& mem, const float* xpad, int64_t n, int dp, int64_t
     nt = max_train;
   }
   gather(train, pick_distinct(nt, nc), centroids);
-  Tmp<int64_t> sums(mem, (size_t)nc * dp);
   Tmp<int32_t> counts(mem, (size_t)nc);
   Tmp<int32_t> assign(mem, (size_t)nt);
   std::vector<int32_t> h_counts(nc);
   const int normalise = metric == QUAKE_IP ? 1 : 0;
   if (normalise) qk::launch_normalise_rows(centroids, nc, dp, s);
-  // fixed-point scale of the cluster sums: n * max|x| * 2^bits stays below 2^62
-  int frac_bits = 40;
-  {
-    Tmp<uint32_t> amax(mem, 1);
-    QK_HIP(hipMemsetAsync(amax.p, 0, sizeof(uint32_t), s));
-    qk::launch_absmax(train, nt * dp, amax.p, s);
-    uint32_t bits = 0;
-    QK_HIP(hipMemcpyAsync(&bits, amax.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    QK_HIP(hipStreamSynchronize(s));
-    float m;
-    std::memcpy(&m, &bits, sizeof(m));
-    if (m > 0.f) frac_bits = (int)std::floor(62.0 - std::log2((double)nt * (double)m)) - 1;
-    frac_bits = std::max(-60, std::min(frac_bits, 60));
-  }
+  const int frac_bits = fixed_point_bits(mem, train, nt, dp, s);
   for (int it = 0; it < iters; ++it) {
     qk::launch_assign(train, nt, dp, centroids, nc, metric, assign.p, s);
-    QK_HIP(hipMemsetAsync(sums.p, 0, (size_t)nc * dp * sizeof(int64_t), s));
-    QK_HIP(hipMemsetAsync(counts.p, 0, (size_t)nc * sizeof(int32_t), s));
-    qk::launch_kmeans_accumulate(train, nt, dp, assign.p, frac_bits, sums.p, counts.p, s);
-    qk::launch_kmeans_update(sums.p, counts.p, nc, dp, normalise, frac_bits, centroids, s);
+    centroids_from(mem, train, nt, dp, assign.p, nc, normalise, frac_bits, centroids, counts.p, s);
     QK_HIP(hipMemcpyAsync(h_counts.data(), counts.p, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     QK_HIP(hipStreamSynchronize(s));
     for (int64_t j = 0; j < nc; ++j) {
@@ -400,6 +432,26 @@ int64_t count_missing(quake_index* idx, const int64_t* ids, int64_t n, int64_t* 
   return h;
 }
 
+// ---------------------------------------------------------------- input checks
+
+// The index's check flag is cleared, a check kernel sets it, and the host
+// reads it back before any work that depends on the input.
+void clear_flag(quake_index* idx, hipStream_t s) {
+  QK_HIP(hipMemsetAsync(idx->d_flag, 0, sizeof(uint32_t), s));
+}
+
+bool flag_set(quake_index* idx, hipStream_t s) {
+  QK_HIP(hipMemcpyAsync(idx->h_flag, idx->d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  return *idx->h_flag != 0;
+}
+
+void require_finite(quake_index* idx, const float* x, int64_t count, const char* what, hipStream_t s) {
+  clear_flag(idx, s);
+  qk::launch_nonfinite(x, count, idx->d_flag, s);
+  QK_CHECK(!flag_set(idx, s), QUAKE_E_INVALID, std::string(what) + " holds a non-finite value");
+}
+
 // ---------------------------------------------------------------- searches
 
 }  // namespace
@@ -435,8 +487,10 @@ Job resolve(const quake_index* idx, const Store& st, const quake_search_params* 
   r.dtype16 = p->scan_dtype;
   QK_CHECK(r.batched == (p->scan_dtype != QUAKE_F32 ? 1 : 0), QUAKE_E_INVALID,
            "the batched scan runs on the 16-bit copy (scan_dtype BF16/F16) and the plain scan on FP32");
-  QK_CHECK(p->rerank_factor >= 0, QUAKE_E_INVALID, "rerank_factor must be >= 0");
-  r.kk = r.batched ? std::max(p->rerank_factor > 0 ? p->rerank_factor : 4, 1) * r.k : r.k;
+  QK_CHECK(p->rerank_factor >= -1, QUAKE_E_INVALID, "rerank_factor must be >= -1");
+  QK_CHECK(p->rerank_factor >= 0 || r.batched, QUAKE_E_INVALID, "rerank_factor -1 is for the batched scan");
+  r.rerank = p->rerank_factor >= 0 ? 1 : 0;
+  r.kk = r.batched ? (r.rerank ? std::max(p->rerank_factor > 0 ? p->rerank_factor : 4, 1) * r.k : r.k) : r.k;
   QK_CHECK(!r.batched || r.kk <= 64, QUAKE_E_INVALID, "the batched scan keeps at most 64 candidates per query");
   QK_CHECK(!r.batched || st.dp16 <= 1024, QUAKE_E_INVALID, "the batched scan supports d <= 1024");
   r.aps = has_rt ? 1 : 0;
@@ -676,6 +730,13 @@ void run_rounds(quake_index* idx, const Store& st, const Job& job, const RoundAr
 
 }  // namespace qk
 
+quake_index::~quake_index() {
+  qk::release_graphs(this);
+  if (capture_stream) (void)hipStreamDestroy(capture_stream);
+  if (ws.h_total) (void)hipHostFree(ws.h_total);
+  if (h_flag) (void)hipHostFree(h_flag);
+}
+
 namespace {
 
 using qk::candidate_count;
@@ -773,9 +834,11 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
   if (job.batched) {
     {
       qk::ProfileScope ps(idx->prof, QUAKE_PROF_RERANK, s);
-      qk::launch_rerank(w, st, a, s);
+      qk::launch_rerank(w, st, a, s, job.rerank != 0);
     }
-    idx->prof.add(QUAKE_PROF_RERANK, (double)nq * job.kk * idx->d * sizeof(float), (double)nq * job.kk * idx->d * 2.0);
+    if (job.rerank)
+      idx->prof.add(QUAKE_PROF_RERANK, (double)nq * job.kk * idx->d * sizeof(float),
+                    (double)nq * job.kk * idx->d * 2.0);
   }
   if (out_ids) {
     qk::ProfileScope ps(idx->prof, QUAKE_PROF_COMMIT, s);
@@ -842,7 +905,7 @@ int quake_cap_table(int32_t d, double* out) {
 }
 
 int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const quake_build_params* params,
-                void* stream, quake_index** out) {
+                const quake_allocator* allocator, void* stream, quake_index** out) {
   API_BEGIN
   QK_CHECK(out, QUAKE_E_INVALID, "out is NULL");
   *out = nullptr;
@@ -861,6 +924,7 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const 
              "nlist_top must be in [1, nlist]");
   hipStream_t s = as_stream(stream);
   std::unique_ptr<quake_index> idx(new quake_index());
+  if (allocator && allocator->alloc) idx->mem.user = *allocator;
   idx->mem.budget = params->hbm_budget_bytes;
   idx->metric = params->metric;
   idx->storage = params->storage_dtype;
@@ -868,6 +932,15 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const 
   idx->d = d;
   idx->dp = (int)round_up(d, 8);
   const int dp = idx->dp;
+  idx->d_flag = idx->mem.alloc<uint32_t>(1);
+  QK_HIP(hipHostMalloc((void**)&idx->h_flag, sizeof(uint32_t), hipHostMallocDefault));
+  require_finite(idx.get(), x, n * (int64_t)d, "x", s);
+  if (params->centroids) require_finite(idx.get(), params->centroids, params->nlist * (int64_t)d, "centroids", s);
+  if (params->assign) {
+    clear_flag(idx.get(), s);
+    qk::launch_check_range(params->assign, n, params->nlist, idx->d_flag, s);
+    QK_CHECK(!flag_set(idx.get(), s), QUAKE_E_INVALID, "assign holds a partition outside [0, nlist)");
+  }
 
   if (ids) {
     std::vector<int64_t> h(n);
@@ -895,10 +968,25 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const 
   L0.centroids = idx->mem.alloc<float>((size_t)L0.nlist * dp);
   if (params->centroids) {
     qk::launch_pad_rows(params->centroids, L0.nlist, d, dp, L0.centroids, nullptr, s);
+  } else if (params->assign) {
+    // each centroid is the mean of the rows the caller put in its partition
+    QK_HIP(hipMemsetAsync(L0.centroids, 0, (size_t)L0.nlist * dp * sizeof(float), s));
+    Tmp<int32_t> counts(idx->mem, (size_t)L0.nlist);
+    const int bits = fixed_point_bits(idx->mem, xpad, n, dp, s);
+    centroids_from(idx->mem, xpad, n, dp, params->assign, L0.nlist, idx->metric == QUAKE_IP ? 1 : 0, bits,
+                   L0.centroids, counts.p, s);
+    std::vector<int32_t> h_counts(L0.nlist);
+    QK_HIP(hipMemcpyAsync(h_counts.data(), counts.p, L0.nlist * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+    for (int64_t j = 0; j < L0.nlist; ++j)
+      QK_CHECK(h_counts[j] > 0, QUAKE_E_INVALID,
+               "assign leaves partition " + std::to_string(j) + " empty and no centroids are given");
   } else {
     kmeans(idx->mem, xpad, n, dp, L0.nlist, params->kmeans_iters, params->seed, idx->metric, L0.centroids, s);
   }
-  {
+  if (params->assign) {
+    build_store(idx.get(), L0, x, d, ids, n, params->assign, params->capacity_slack, params->storage_dtype, s);
+  } else {
     Tmp<int32_t> assign(idx->mem, n);
     qk::launch_assign(xpad, n, dp, L0.centroids, L0.nlist, idx->metric, assign.p, s);
     build_store(idx.get(), L0, x, d, ids, n, assign.p, params->capacity_slack, params->storage_dtype, s);
@@ -939,7 +1027,9 @@ int quake_search(quake_index* idx, const float* q, int64_t nq, const quake_searc
   QK_CHECK(q && out_ids && out_dist, QUAKE_E_INVALID, "q, out_ids and out_dist are required");
   hipStream_t s = as_stream(stream);
   ensure_queries(idx, nq);
-  qk::launch_pad_rows(q, nq, idx->d, idx->dp, idx->ws.q, idx->ws.qn2, s);
+  clear_flag(idx, s);
+  qk::launch_pad_rows(q, nq, idx->d, idx->dp, idx->ws.q, idx->ws.qn2, s, idx->d_flag);
+  QK_CHECK(!flag_set(idx, s), QUAKE_E_INVALID, "q holds a non-finite value");
   if (idx->n_levels == 2) {
     // level 1 picks the level-0 candidates: M0 = ceil(f_M * N0) nearest leaf
     // centroids it finds; nprobe mode takes the nprobe nearest it finds
@@ -1055,25 +1145,39 @@ int quake_profile(quake_index* idx, int32_t enable, int32_t reset, quake_kernel_
   API_END
 }
 
-int quake_candidates(quake_index* idx, const float* q, int64_t nq, double f_M, int32_t* order, float* h,
-                     int32_t* out_M, void* stream) {
+int quake_candidates(quake_index* idx, const float* q, int64_t nq, const quake_search_params* params,
+                     int32_t* order, float* h, int32_t* out_M, void* stream) {
   API_BEGIN
   check_index(idx);
-  QK_CHECK(idx->n_levels == 1, QUAKE_E_STATE, "candidate export is for single-level indexes");
+  QK_CHECK(params, QUAKE_E_INVALID, "params is NULL");
   QK_CHECK(nq >= 0 && (nq == 0 || (q && order && h)), QUAKE_E_INVALID, "bad arguments");
+  QK_CHECK(params->f_M >= 0 && params->upper_f_M >= 0 && params->upper_recall_target >= 0 &&
+               params->upper_recall_target <= 1.0 && params->tau_rho >= 0,
+           QUAKE_E_INVALID, "negative or out-of-range search parameter");
   const Store& st = idx->L0;
-  const int M = candidate_count(f_M > 0 ? f_M : 0.05, st.nlist);
+  const int M = candidate_count(params->f_M > 0 ? params->f_M : 0.05, st.nlist);
   QK_CHECK(M <= (st.nlist > 4096 ? 2048 : qk::MAX_CANDIDATES), QUAKE_E_INVALID, "too many candidates");
+  QK_CHECK(idx->n_levels == 1 || M <= qk::KMAX_LARGE, QUAKE_E_INVALID,
+           "the upper level returns at most 1024 candidates");
   if (out_M) *out_M = M;
   if (nq == 0) return QUAKE_OK;
   hipStream_t s = as_stream(stream);
   ensure_queries(idx, nq);
-  ensure_workspace(idx, st.nlist, M, 1, 1, 0, 0);
   qk::Workspace& w = idx->ws;
-  qk::launch_pad_rows(q, nq, idx->d, idx->dp, w.q, w.qn2, s);
-  qk::launch_fill_i32(w.mq, nq, M, s);
-  qk::launch_scores(w.q, nq, st.centroids, st.nlist, idx->dp, idx->metric, w.scores, s);
-  qk::launch_candidates(st, w.q, w.scores, nq, idx->dp, M, 1, idx->metric, w.mq, w.sel, w.cand, w.h, s);
+  clear_flag(idx, s);
+  qk::launch_pad_rows(q, nq, idx->d, idx->dp, w.q, w.qn2, s, idx->d_flag);
+  QK_CHECK(!flag_set(idx, s), QUAKE_E_INVALID, "q holds a non-finite value");
+  if (idx->n_levels == 2) {
+    upper_level(idx, nq, M, params, s);
+    ensure_workspace(idx, st.nlist, M, 1, 1, 0, 0, false);
+    QK_HIP(hipMemcpyAsync(w.mq, w.mq0, nq * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    qk::launch_geometry(w.q, st.centroids, nq, idx->dp, M, w.mq, idx->metric, w.cand0, w.cand, w.h, s);
+  } else {
+    ensure_workspace(idx, st.nlist, M, 1, 1, 0, 0);
+    qk::launch_fill_i32(w.mq, nq, M, s);
+    qk::launch_scores(w.q, nq, st.centroids, st.nlist, idx->dp, idx->metric, w.scores, s);
+    qk::launch_candidates(st, w.q, w.scores, nq, idx->dp, M, 1, idx->metric, w.mq, w.sel, w.cand, w.h, s);
+  }
   QK_HIP(hipMemcpyAsync(order, w.cand, (size_t)nq * M * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   QK_HIP(hipMemcpyAsync(h, w.h, (size_t)nq * M * sizeof(float), hipMemcpyDeviceToDevice, s));
   QK_HIP(hipStreamSynchronize(s));
@@ -1100,6 +1204,7 @@ int quake_insert(quake_index* idx, const float* x, const int64_t* ids, int64_t n
     QK_CHECK(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(), QUAKE_E_DUPLICATE,
              "the batch repeats an id");
   }
+  require_finite(idx, x, n * (int64_t)idx->d, "x", s);
   QK_CHECK(count_missing(idx, ids, n, nullptr, s) == n, QUAKE_E_DUPLICATE, "the batch names an id already present");
   const int dp = idx->dp;
   std::unique_ptr<Tmp<float>> xpad_buf;
@@ -1307,9 +1412,6 @@ int quake_export_top(const quake_index* idx, float* top_centroids, int32_t* top_
 
 void quake_free(quake_index* idx) {
   if (!idx || idx->magic != 0x51554b45u) return;
-  qk::release_graphs(idx);
-  if (idx->capture_stream) (void)hipStreamDestroy(idx->capture_stream);
-  if (idx->ws.h_total) (void)hipHostFree(idx->ws.h_total);
   idx->magic = 0;
   delete idx;
 }

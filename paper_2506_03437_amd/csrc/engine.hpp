@@ -17,6 +17,7 @@ int candidate_count(double f, int64_t n);
 // One search over one store, resolved from quake_search_params.
 struct Job {
   int k = 0, kk = 0, aps = 0, M = 0, w0 = 0, wmax = 0, batched = 0, dtype16 = QUAKE_F32;
+  int rerank = 1;      // batched path: re-score the kk candidates in FP32 (0: keep the 16-bit values)
   double tau_r = 0, f_M = 0, tau_rho = 0.01;
   bool given = false;  // candidate rows already in ws.cand0 / ws.mq0 (level 0 of two levels)
 };

@@ -45,10 +45,13 @@ constexpr int COUNTERS = 32;      // device counters of a search (Workspace::tot
 constexpr int MAX_CANDIDATES = 4096;   // APS candidate set M (and nprobe) upper bound
 
 // Device allocations of one index, counted against an optional budget.
+// Blocks come from the caller's allocator when one is set (torch's caching
+// allocator from the Python binding), else from hipMalloc.
 class DeviceMemory {
  public:
   size_t used = 0;
   size_t budget = 0;  // 0 = unlimited
+  quake_allocator user{};  // user.alloc == nullptr: hipMalloc / hipFree
   template <class T>
   T* alloc(size_t count) { return static_cast<T*>(raw_alloc(count * sizeof(T))); }
   void* raw_alloc(size_t bytes);
@@ -191,6 +194,8 @@ struct quake_index {
   qk::IdMap idmap;              // level-0 ids
   int32_t* top_of = nullptr;    // [L0.nlist] level-1 partition of each level-0 centroid
   double* cap_table = nullptr;  // [1024] device copy of the recall model table
+  uint32_t* d_flag = nullptr;   // input checks: set by kernels that find a bad value
+  uint32_t* h_flag = nullptr;   // pinned host mirror
   std::vector<double> h_cap_table;
   qk::Workspace ws;
   qk::Profiler prof;
@@ -204,6 +209,7 @@ struct quake_index {
   std::vector<Graph> graphs;
   hipStream_t capture_stream = nullptr;
   bool graphs_failed = false;
+  ~quake_index();  // graphs, streams and pinned buffers; device memory goes with `mem`
 };
 
 namespace qk {
@@ -213,7 +219,14 @@ void cap_fraction_table(int d, double* out /*[CAP_TABLE_POINTS]*/);
 double cap_fraction(double t, int d);
 
 // kernels: centroids and candidates (k_centroids.hip)
-void launch_pad_rows(const float* x, int64_t n, int d, int dp, float* out, double* norm2, hipStream_t s);
+// Rows [n][d] to [n][dp] (zero padded), optionally |row|^2 in FP64; `bad`
+// (when given) is set non-zero if any value read is not finite.
+void launch_pad_rows(const float* x, int64_t n, int d, int dp, float* out, double* norm2, hipStream_t s,
+                     uint32_t* bad = nullptr);
+// Sets *bad non-zero if any of x[0, n) is not finite (caller clears it).
+void launch_nonfinite(const float* x, int64_t n, uint32_t* bad, hipStream_t s);
+// Sets *bad non-zero if any of a[0, n) lies outside [0, nlist) (caller clears it).
+void launch_check_range(const int32_t* a, int64_t n, int64_t nlist, uint32_t* bad, hipStream_t s);
 void launch_scores(const float* q, int64_t nq, const float* c, int64_t nc, int dp, int metric, float* out,
                    hipStream_t s);
 void launch_select(const float* scores, int64_t nq, int64_t nc, int M, int metric, int32_t* cand,
@@ -271,7 +284,9 @@ void launch_queries16(Workspace& ws, int64_t nq, int dp, int dp16, int dtype16, 
                       const int32_t* slots = nullptr);
 void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
 void launch_scan_mfma(Workspace& ws, const Store& st, const RoundArgs& a, int dtype16, hipStream_t s);
-void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s, const int32_t* slots = nullptr,
+// exact = false: no FP32 re-scoring, only the slot -> id mapping and the best k by the 16-bit values.
+void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s, bool exact,
+                   const int32_t* slots = nullptr,
                    int64_t nslots = 0);
 void launch_norm16(const Store& st, int dtype16, hipStream_t s);
 

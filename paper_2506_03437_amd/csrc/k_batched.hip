@@ -1,6 +1,6 @@
 // Batched scan: queries that need the same partition in a round share one
 // read of it (multi-query execution: group queries by the partitions they
-// access and scan each partition once per batch, Sec. 7.5).
+// access and scan each partition once per batch, Sec. 7.4, "Multi-Query Processing").
 //
 // Per round, every query's window of (query, partition) pairs is bucketed by
 // partition.  A work item is (partition chunk of up to chunk_tiles tiles,

@@ -15,23 +15,65 @@ namespace qk {
 // ---------------------------------------------------------------- padding
 
 __global__ __launch_bounds__(256) void k_pad_rows(const float* __restrict__ x, int64_t n, int d, int dp,
-                                                   float* __restrict__ out, double* __restrict__ norm2) {
+                                                   float* __restrict__ out, double* __restrict__ norm2,
+                                                   uint32_t* __restrict__ bad) {
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   double acc = 0.0;
+  bool finite = true;
   for (int j = lane; j < dp; j += WAVE) {
     const float v = (j < d) ? x[row * d + j] : 0.0f;
     out[row * dp + j] = v;
+    finite &= __builtin_isfinite(v);
     acc += (double)v * (double)v;
   }
   acc = wave_sum_d(acc);
   if (norm2 && lane == 0) norm2[row] = acc;
+  if (bad && __ballot(!finite) && lane == 0) atomicOr(bad, 1u);
 }
 
-void launch_pad_rows(const float* x, int64_t n, int d, int dp, float* out, double* norm2, hipStream_t s) {
+void launch_pad_rows(const float* x, int64_t n, int d, int dp, float* out, double* norm2, hipStream_t s,
+                     uint32_t* bad) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, x, n, d, dp, out, norm2);
+  hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, x, n, d, dp, out, norm2, bad);
+}
+
+// ---------------------------------------------------------------- input checks
+
+__global__ __launch_bounds__(256) void k_nonfinite(const float4* __restrict__ x4, const float* __restrict__ x,
+                                                    int64_t n, uint32_t* __restrict__ bad) {
+  bool finite = true;
+  const int64_t n4 = ((uintptr_t)x & 15) == 0 ? n / 4 : 0;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n4; e += (int64_t)gridDim.x * 256) {
+    const float4 v = x4[e];
+    finite &= __builtin_isfinite(v.x) && __builtin_isfinite(v.y) && __builtin_isfinite(v.z) &&
+              __builtin_isfinite(v.w);
+  }
+  for (int64_t e = n4 * 4 + (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    finite &= __builtin_isfinite(x[e]);
+  if (__ballot(!finite) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+}
+
+void launch_nonfinite(const float* x, int64_t n, uint32_t* bad, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n / 4 + 255) / 256, 8192));
+  hipLaunchKernelGGL(k_nonfinite, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<const float4*>(x), x,
+                     n, bad);
+}
+
+__global__ __launch_bounds__(256) void k_check_range(const int32_t* __restrict__ a, int64_t n, int64_t nlist,
+                                                      uint32_t* __restrict__ bad) {
+  bool ok = true;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256)
+    ok &= a[e] >= 0 && (int64_t)a[e] < nlist;
+  if (__ballot(!ok) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+}
+
+void launch_check_range(const int32_t* a, int64_t n, int64_t nlist, uint32_t* bad, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_check_range, dim3((unsigned)blocks), dim3(256), 0, s, a, n, nlist, bad);
 }
 
 // ---------------------------------------------------------------- scoring

@@ -1,4 +1,4 @@
-// FP32 rerank of the batched path's candidates (Sec. 7.5 scans a reduced-
+// FP32 rerank of the batched path's candidates (Sec. 7.4, "Multi-Query Processing" scans a reduced-
 // precision copy; the candidates it keeps are re-scored exactly here).
 //
 // After the last round each query holds rerank_factor * k candidates (store
@@ -103,16 +103,17 @@ __global__ __launch_bounds__(256) void k_rerank_select(int64_t nrows, int k, int
   if (lane < k) { rk[q * kk + lane] = key; ri[q * kk + lane] = id; }
 }
 
-void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s, const int32_t* slots,
-                   int64_t nslots) {
+void launch_rerank(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s, bool exact,
+                   const int32_t* slots, int64_t nslots) {
   const int64_t n = slots ? nslots : a.nq;
   if (n <= 0) return;
   const int64_t pairs = n * a.kk;
   const dim3 g1((unsigned)((pairs + 127) / 128)), g2((unsigned)((n + 3) / 4));
-  if (a.metric == QUAKE_L2)
+  // without the FP32 re-scoring the 16-bit path's keys stay and are ranked as they are
+  if (exact && a.metric == QUAKE_L2)
     hipLaunchKernelGGL(k_rerank_dist<QUAKE_L2>, g1, dim3(256), 0, s, n, a.kk, ws.q, st.dp, st.rows32, ws.rk, ws.ri,
                        slots);
-  else
+  else if (exact)
     hipLaunchKernelGGL(k_rerank_dist<QUAKE_IP>, g1, dim3(256), 0, s, n, a.kk, ws.q, st.dp, st.rows32, ws.rk, ws.ri,
                        slots);
   hipLaunchKernelGGL(k_rerank_select, g2, dim3(256), 0, s, n, a.k, a.kk, st.ids, ws.rk, ws.ri, slots);

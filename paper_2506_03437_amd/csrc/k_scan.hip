@@ -5,7 +5,7 @@
 // items of at most `chunk_tiles` store tiles; one wave scans one item and
 // keeps the item's best results; then one wave per query commits the items
 // in candidate order.  Committing follows Algorithm "Adaptive Partition
-// Scanning" (Sec. 5.2) one partition at a time: merge that partition's
+// Scanning" (Sec. 5.1) one partition at a time: merge that partition's
 // results into the query's top-k, take rho from the k-th result, recompute
 // the recall model when rho moved by more than tau_rho, and stop once the
 // estimated recall reaches the target.  Partitions scanned past the stop
@@ -13,9 +13,9 @@
 // scanning ahead only trades extra reads for fewer rounds.  With a fixed
 // nprobe the window is the whole candidate list and one round suffices.
 //
-// Recall model (Sec. 5.1, Eqs. aps-pi, aps-p0, aps-pi-final): with t_i =
+// Recall model (Sec. 5, Eqs. aps-pi, aps-p0, aps-pi-final): with t_i =
 // h_i / rho, v_i is the volume share of the ball B(q, rho) beyond the
-// bisector of c_0 and c_i (looked up in the 1,024-point table of Sec. 5.3
+// bisector of c_0 and c_i (looked up in the 1,024-point table of Sec. 5.1, "Performance Optimizations"
 // with linear interpolation, 0 for t >= 1); p_0 = prod (1 - v_i) uses the raw
 // shares and the remaining 1 - p_0 is split in proportion to v_i, so the
 // estimate after scanning c_0 and the next m - 1 candidates is

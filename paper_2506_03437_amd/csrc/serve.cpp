@@ -14,6 +14,7 @@
 // queue stops admission until the slots drain, then runs as one batch.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -187,7 +188,7 @@ struct quake_server {
     std::memcpy(h_slots, fin.data(), n * sizeof(int32_t));
     QK_HIP(hipMemcpyAsync(d_slots, h_slots, n * sizeof(int32_t), hipMemcpyHostToDevice, s));
     qk::RoundArgs a = args();
-    if (job.batched) qk::launch_rerank(w, st(), a, s, d_slots, n);
+    if (job.batched) qk::launch_rerank(w, st(), a, s, job.rerank != 0, d_slots, n);
     qk::launch_gather_results(w, d_slots, n, job.k, job.kk, idx->metric, d_ids, d_dist, d_ns, d_rec, s);
     const int k = job.k;
     QK_HIP(hipMemcpyAsync(h_ids, d_ids, n * k * sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -338,6 +339,12 @@ namespace {
 
 int fail_rc(int code, const std::string& msg) { return qk::set_error(code, msg); }
 
+bool all_finite(const float* v, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
 #define SRV_BEGIN try {
 #define SRV_END                                                                            \
   }                                                                                        \
@@ -421,6 +428,7 @@ int quake_server_search(quake_server* srv, const float* q, int64_t n, uint64_t* 
   SRV_BEGIN
   QK_CHECK(srv && (n == 0 || q) && n >= 0, QUAKE_E_INVALID, "bad arguments");
   const int d = srv->idx->d;
+  QK_CHECK(all_finite(q, n * d), QUAKE_E_INVALID, "q holds a non-finite value");
   std::vector<Request> reqs(n);
   for (int64_t i = 0; i < n; ++i) {
     reqs[i].kind = 0;
@@ -434,6 +442,7 @@ int quake_server_search(quake_server* srv, const float* q, int64_t n, uint64_t* 
 int quake_server_insert(quake_server* srv, const float* x, const int64_t* ids, int64_t n, uint64_t* ticket) {
   SRV_BEGIN
   QK_CHECK(srv && n >= 0 && (n == 0 || (x && ids)), QUAKE_E_INVALID, "bad arguments");
+  QK_CHECK(all_finite(x, n * srv->idx->d), QUAKE_E_INVALID, "x holds a non-finite value");
   std::vector<Request> r(1);
   r[0].kind = 1;
   r[0].x.assign(x, x + n * srv->idx->d);

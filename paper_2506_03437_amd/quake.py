@@ -42,8 +42,44 @@ class QuakeError(RuntimeError):
 class BuildParams(ctypes.Structure):
     _fields_ = [("metric", ctypes.c_int32), ("storage_dtype", ctypes.c_int32), ("n_levels", ctypes.c_int32),
                 ("kmeans_iters", ctypes.c_int32), ("nlist", ctypes.c_int64), ("nlist_top", ctypes.c_int64),
-                ("seed", ctypes.c_uint64), ("centroids", ctypes.c_void_p), ("hbm_budget_bytes", ctypes.c_size_t),
-                ("capacity_slack", ctypes.c_double)]
+                ("seed", ctypes.c_uint64), ("centroids", ctypes.c_void_p), ("assign", ctypes.c_void_p),
+                ("hbm_budget_bytes", ctypes.c_size_t), ("capacity_slack", ctypes.c_double)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", ctypes.c_void_p)]
+
+
+def _torch_alloc(nbytes, ctx):
+    # ctx carries the device index; memory comes from torch's caching
+    # allocator on that device's current stream
+    try:
+        import torch
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=int(ctx or 0))
+    except Exception:
+        return None
+
+
+def _torch_free(ptr, ctx):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+# the callbacks live as long as the module (an index may call them until it is freed)
+_TORCH_ALLOC = ALLOC_FN(_torch_alloc)
+_TORCH_FREE = FREE_FN(_torch_free)
+
+
+def torch_allocator(device: int) -> Allocator:
+    """quake_allocator backed by torch's caching allocator on `device`."""
+    return Allocator(_TORCH_ALLOC, _TORCH_FREE, ctypes.c_void_p(device))
 
 
 class SearchParams(ctypes.Structure):
@@ -88,14 +124,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2506_03437_amd.build_lib`")
     lib = ctypes.CDLL(path)
     vp, i64, i32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
-    lib.quake_build.argtypes = [vp, vp, i64, i32, ctypes.POINTER(BuildParams), vp, ctypes.POINTER(vp)]
+    lib.quake_build.argtypes = [vp, vp, i64, i32, ctypes.POINTER(BuildParams), ctypes.POINTER(Allocator), vp,
+                                ctypes.POINTER(vp)]
     lib.quake_search.argtypes = [vp, vp, i64, ctypes.POINTER(SearchParams), vp, vp, vp, vp, vp]
     lib.quake_insert.argtypes = [vp, vp, vp, i64, vp]
     lib.quake_delete.argtypes = [vp, vp, i64, vp]
     lib.quake_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)]
     lib.quake_export.argtypes = [vp, vp, vp, vp, vp]
     lib.quake_export_top.argtypes = [vp, vp, vp, vp]
-    lib.quake_candidates.argtypes = [vp, vp, i64, f64, vp, vp, ctypes.POINTER(i32), vp]
+    lib.quake_candidates.argtypes = [vp, vp, i64, ctypes.POINTER(SearchParams), vp, vp, ctypes.POINTER(i32), vp]
     lib.quake_cap_table.argtypes = [i32, ctypes.POINTER(f64)]
     lib.quake_profile.argtypes = [vp, i32, i32, vp]
     lib.quake_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
@@ -148,18 +185,25 @@ def quake_cap_table(d: int) -> np.ndarray:
 
 
 def quake_build(x, ids=None, *, metric="l2", nlist=256, storage="f32", n_levels=1, nlist_top=0, kmeans_iters=10,
-                seed=0, centroids=None, hbm_budget_bytes=0, capacity_slack=0.0) -> int:
+                seed=0, centroids=None, assign=None, hbm_budget_bytes=0, capacity_slack=0.0,
+                allocator="torch") -> int:
+    """allocator: "torch" (the caching allocator of x's device, the default) or "hip" (hipMalloc)."""
     import torch
     _dev(x, torch.float32)
     if ids is not None:
         _dev(ids, torch.int64)
     if centroids is not None:
         _dev(centroids, torch.float32)
+    if assign is not None:
+        _dev(assign, torch.int32)
     p = BuildParams(_METRIC[metric], _DTYPE[storage], n_levels, kmeans_iters, nlist, nlist_top, seed,
-                    _ptr(centroids), hbm_budget_bytes, capacity_slack)
+                    _ptr(centroids), _ptr(assign), hbm_budget_bytes, capacity_slack)
+    if allocator not in ("torch", "hip"):
+        raise ValueError(f"allocator must be 'torch' or 'hip', not {allocator!r}")
+    alloc = ctypes.byref(torch_allocator(x.device.index or 0)) if allocator == "torch" else None
     h = ctypes.c_void_p()
-    _check(load_library().quake_build(_ptr(x), _ptr(ids), x.shape[0], x.shape[1], ctypes.byref(p), _stream(),
-                                      ctypes.byref(h)))
+    _check(load_library().quake_build(_ptr(x), _ptr(ids), x.shape[0], x.shape[1], ctypes.byref(p), alloc,
+                                      _stream(), ctypes.byref(h)))
     return h.value
 
 
@@ -231,17 +275,20 @@ def quake_export_top(handle: int, d: int, nlist_top: int):
     return C1, top_of
 
 
-def quake_candidates(handle: int, q, f_M: float):
-    """(order int32 [nq, M], h f32 [nq, M]) of adaptive scanning, without scanning."""
+def quake_candidates(handle: int, q, f_M: float, upper_recall_target=0.0, upper_f_M=0.0, tau_rho=0.0):
+    """(order int32 [nq, M], h f32 [nq, M]) of adaptive scanning, without scanning level 0."""
     import torch
     _dev(q, torch.float32)
-    _, nlist, _ = quake_stats(handle)
+    p = _search_params(k=1, f_M=f_M, tau_rho=tau_rho, upper_recall_target=upper_recall_target,
+                       upper_f_M=upper_f_M)
     M = ctypes.c_int32()
-    _check(load_library().quake_candidates(handle, None, 0, f_M, None, None, ctypes.byref(M), _stream()))
+    _check(load_library().quake_candidates(handle, None, 0, ctypes.byref(p), None, None, ctypes.byref(M),
+                                           _stream()))
     nq = q.shape[0]
     order = torch.empty((nq, M.value), dtype=torch.int32, device=q.device)
     h = torch.empty((nq, M.value), dtype=torch.float32, device=q.device)
-    _check(load_library().quake_candidates(handle, _ptr(q), nq, f_M, _ptr(order), _ptr(h), None, _stream()))
+    _check(load_library().quake_candidates(handle, _ptr(q), nq, ctypes.byref(p), _ptr(order), _ptr(h), None,
+                                           _stream()))
     return order, h
 
 
@@ -399,8 +446,8 @@ class Index:
     def export(self):
         return quake_export(self.handle, self.d)
 
-    def candidates(self, q, f_M=0.05):
-        return quake_candidates(self.handle, q, f_M)
+    def candidates(self, q, f_M=0.05, **upper_kw):
+        return quake_candidates(self.handle, q, f_M, **upper_kw)
 
     def set_tuning(self, **kw):
         quake_set_tuning(self.handle, **kw)

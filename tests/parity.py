@@ -82,16 +82,21 @@ def check_all(Q, X, ids, gpu_ids, gpu_vals, ref_ids, ref_vals, metric, k):
     assert not bad, f"{len(bad)} of {Q.shape[0]} queries differ; first: {bad[:3]}"
 
 
-def check_candidate_order(q, C, f_M, metric, order, h_gpu):
-    """The device order is a valid APS order for the oracle, up to near-ties."""
+def check_candidate_order(q, C, f_M, metric, order, h_gpu, cands=None):
+    """The device order is a valid APS order for the oracle, up to near-ties.
+
+    With ``cands`` (the candidate set a level above handed over) the set is
+    taken as given and only c_0, the order and h are checked."""
     from oracle import aps as oaps
-    o_ref, h_ref = oaps.aps_order(q, C, f_M, metric)
+    o_ref, h_ref = oaps.aps_order(q, C, f_M, metric, cands=cands)
     vals = knn.distances(q[None], C, metric)[0]
     key = knn.sort_key(vals, metric)
     scale = abs(key[o_ref[0]]) if metric == "l2" else float(np.linalg.norm(q)) * float(np.linalg.norm(C, axis=1).max())
     tol = 1e-5 * max(scale, 1e-30) + 1e-6
     # same candidate set except near-ties at the M-th place
-    if set(order.tolist()) != set(o_ref.tolist()):
+    if cands is not None:
+        assert set(order.tolist()) == set(o_ref.tolist()), "candidate set differs from the one handed over"
+    elif set(order.tolist()) != set(o_ref.tolist()):
         ks = np.sort(key)
         M = o_ref.shape[0]
         assert M < key.shape[0] and abs(ks[M] - ks[M - 1]) <= tol, "candidate set differs"

@@ -48,17 +48,17 @@ def test_cap_table_matches_oracle_table(d):
 def test_host_side_argument_errors():
     from paper_2506_03437_amd import quake
     lib = quake.load_library()
-    p = quake.BuildParams(0, 0, 1, 1, 4, 0, 0, None, 0, 0.0)
+    p = quake.BuildParams(0, 0, 1, 1, 4, 0, 0, None, None, 0, 0.0)
     h = ctypes.c_void_p()
-    assert lib.quake_build(None, None, 10, 8, ctypes.byref(p), None, ctypes.byref(h)) == quake.E_INVALID
+    assert lib.quake_build(None, None, 10, 8, ctypes.byref(p), None, None, ctypes.byref(h)) == quake.E_INVALID
     assert b"x" in lib.quake_last_error()
     fake = ctypes.c_void_p(1234)  # pointer value only, never dereferenced by the check below
-    assert lib.quake_build(fake, None, 10, 0, ctypes.byref(p), None, ctypes.byref(h)) == quake.E_INVALID
+    assert lib.quake_build(fake, None, 10, 0, ctypes.byref(p), None, None, ctypes.byref(h)) == quake.E_INVALID
     p.metric = 7
-    assert lib.quake_build(fake, None, 10, 8, ctypes.byref(p), None, ctypes.byref(h)) == quake.E_INVALID
+    assert lib.quake_build(fake, None, 10, 8, ctypes.byref(p), None, None, ctypes.byref(h)) == quake.E_INVALID
     p.metric = 0
     p.nlist = 11
-    assert lib.quake_build(fake, None, 10, 8, ctypes.byref(p), None, ctypes.byref(h)) == quake.E_INVALID
+    assert lib.quake_build(fake, None, 10, 8, ctypes.byref(p), None, None, ctypes.byref(h)) == quake.E_INVALID
     sp = quake.SearchParams(10, 4, 0.0, 0, 0, 0, 0, 0, 0, 0, 0)
     assert lib.quake_search(None, None, 1, ctypes.byref(sp), None, None, None, None, None) == quake.E_STATE
     assert lib.quake_insert(None, None, None, 1, None) == quake.E_STATE

@@ -28,7 +28,7 @@ def _int_data(n, d, seed, metric):
     centres = rng.integers(-3, 4, (12, d))
     X = centres[rng.integers(0, 12, n)] + rng.integers(-1, 2, (n, d))
     X = np.clip(X, -4, 4).astype(np.float32)
-    Q = (centres[rng.integers(0, 12, 64)] + rng.integers(-1, 2, (64, d))).astype(np.float32)
+    Q = (centres[rng.integers(0, 12, 256)] + rng.integers(-1, 2, (256, d))).astype(np.float32)
     return X, Q
 
 
@@ -52,15 +52,20 @@ def test_batched_exact_on_integer_data_nprobe(int_index):
         parity.check_all(Q, X, ps.ids, gi, gv, ri, rv, metric, k)
 
 
-def test_batched_exact_on_integer_data_aps(int_index):
+@pytest.mark.parametrize("tau", [0.8, 0.9, 0.97])
+def test_batched_exact_on_integer_data_aps(int_index, tau):
+    """Scores are exact here, so the batched path's adaptive decisions must
+    replay the oracle's Algorithm "Adaptive Partition Scanning" query by
+    query: the same stop count and recall estimate (up to decisions within
+    the floating-point margin of the device's FP32 bisector distances), and
+    exactly the top-k over the partitions scanned."""
     metric, dtype, X, Q, idx, ps = int_index
-    gi, gv, ns, _ = gu.search(idx, Q, k=10, recall_target=0.9, f_M=0.3, scan_mode="batched", scan_dtype=dtype)
-    order, _ = idx.candidates(gu.to_dev(Q), 0.3)
-    order = order.cpu().numpy()
-    id_to_row = {int(i): r for r, i in enumerate(ps.ids.tolist())}
-    for i in range(Q.shape[0]):
-        ri, rv = oivf.scan_partitions(ps, Q[i], order[i, :ns[i]], 10, metric)
-        parity.check_topk(Q[i], X, id_to_row, gi[i], gv[i], ri, rv, metric, 10, f"query {i}")
+    gi, gv, ns, rec = gu.search(idx, Q, k=10, recall_target=tau, f_M=0.3, scan_mode="batched", scan_dtype=dtype)
+    order, h = idx.candidates(gu.to_dev(Q), 0.3)
+    parity.check_aps(X, Q, ps, gi, gv, ns, rec, order.cpu().numpy(), h.cpu().numpy(), metric, 0.3, tau, 10)
+    # the plain FP32 path takes the same decisions on this data
+    fi, fv, fns, frec = gu.search(idx, Q, k=10, recall_target=tau, f_M=0.3)
+    assert (fns == ns).all() and (fi == gi).all()
 
 
 def test_batched_schedules_agree(int_index):
@@ -118,6 +123,44 @@ def test_bf16_nprobe_matches_fp32_candidates_closely(float_ip):
         for i, v in zip(b_i.tolist(), b_v.tolist()):
             if i in da:
                 assert da[i] == v
+
+
+def _bf16(a):
+    """Round to BF16 (nearest, ties to even), returned as float32 values."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+def test_mfma_scores_within_the_accumulation_bound(float_ip):
+    """Without the FP32 rerank the batched path returns its own BF16 MFMA
+    scores.  BF16 x BF16 products are exact in FP32, so only the FP32
+    accumulation rounds: each score lies within gamma_d * sum |q~_i x~_i|
+    (gamma_d = d u / (1 - d u), u = 2^-24) of the FP64 dot product of the
+    rounded query and row; and the ids are the top-k of the probed
+    partitions by that exact dot, up to values within twice the bound."""
+    X, Q, idx, ps, truth = float_ip
+    Qs = Q[:120]
+    bi, bv, _, _ = gu.search(idx, Qs, k=10, nprobe=8, scan_mode="batched", scan_dtype="bf16", rerank_factor=-1)
+    d = X.shape[1]
+    u = 2.0 ** -24
+    gamma = d * u / (1 - d * u)
+    Q16 = _bf16(Qs).astype(np.float64)
+    X16 = _bf16(X).astype(np.float64)
+    for i in range(Qs.shape[0]):
+        _, probes = oivf.centroid_ranking(Qs[i], ps.C, "ip")
+        rows = np.concatenate([ps.members[p] for p in probes[:8]])
+        exact = X16[rows] @ Q16[i]
+        bound = gamma * (np.abs(X16[rows]) @ np.abs(Q16[i]))
+        pos = {int(ps.ids[r]): j for j, r in enumerate(rows)}
+        got = [pos[int(g)] for g in bi[i]]
+        err = np.abs(bv[i].astype(np.float64) - exact[got])
+        assert (err <= bound[got]).all(), (i, float((err - bound[got]).max()))
+        kth = np.sort(exact)[::-1][9]
+        tol = 2 * float(bound.max())
+        assert (exact[got] >= kth - tol).all()
+        clear = set(np.nonzero(exact > kth + tol)[0].tolist())
+        assert clear <= set(got), f"query {i}: a clear top-10 row is missing"
 
 
 def test_batched_rejects_bad_modes(float_ip):

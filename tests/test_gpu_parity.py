@@ -62,6 +62,14 @@ def test_build_places_every_vector_in_its_nearest_partition(small_l2):
     assert n_live == X.shape[0] and nparts == w.nlist
 
 
+def test_ip_build_places_every_vector_in_its_best_partition(small_ip):
+    X, Q, idx, ps = small_ip
+    bad = oivf.assignment_violations(X, ps.assign, ps.C, "ip", rtol=1e-5)
+    assert bad.size == 0, f"{bad.size} vectors not in their highest-scoring partition"
+    # spherical k-means: unit-length centroids
+    np.testing.assert_allclose(np.linalg.norm(ps.C.astype(np.float64), axis=1), 1.0, atol=1e-5)
+
+
 def test_build_is_reproducible():
     """Cluster sums are exact integers in fixed point, so two builds with one
     seed give bit-identical centroids and the same placement."""
