@@ -210,10 +210,15 @@ int quake_autotune(quake_index* index, const float* q, int64_t nq, const quake_s
 /* Kernel timing of searches, for roofline measurement.  With enable = 1 the
  * library records HIP events on the search stream around each kernel class
  * and, after the search completes, adds the elapsed times to per-class
- * totals; it also adds the algorithmic bytes and flops of each launch (bytes:
- * vectors scanned * d * element size for scans, centroid rows for scoring).
- * reset = 1 zeroes the totals.  out (host, QUAKE_PROF_KINDS entries) receives
- * the totals when not NULL. */
+ * totals; it also adds the algorithmic bytes and flops of each launch.
+ * Bytes: for the plain scan every (query, vector) read, d * 4 each (no
+ * reuse between queries by design); for the batched scan every vector of
+ * every partition a round touches, once per round, d * 2 each (the bytes a
+ * launch has to read); centroid rows for scoring.  QUAKE_PROF_SCAN_SETS
+ * holds (bytes only) the batched scan's reads counted once per query set of
+ * up to 64 queries, the bytes its blocks request.  reset = 1 zeroes the
+ * totals.  out (host, QUAKE_PROF_KINDS entries) receives the totals when
+ * not NULL. */
 enum {
   QUAKE_PROF_CENTROIDS = 0, /* centroid scoring */
   QUAKE_PROF_SELECT = 1,    /* candidate selection and bisector geometry */
@@ -221,6 +226,7 @@ enum {
   QUAKE_PROF_SCAN = 3,      /* partition scans */
   QUAKE_PROF_COMMIT = 4,    /* in-order commit and recall model */
   QUAKE_PROF_RERANK = 5,    /* FP32 rerank of reduced-precision candidates */
+  QUAKE_PROF_SCAN_SETS = 6, /* batched scan reads per query set (bytes only, no launches) */
   QUAKE_PROF_KINDS = 8
 };
 typedef struct {

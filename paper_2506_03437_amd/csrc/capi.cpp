@@ -846,10 +846,12 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
   }
   QK_HIP(hipGetLastError());
   if (idx->prof.on)
-    QK_HIP(hipMemcpyAsync(w.h_total + 4, w.total + 4, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipMemcpyAsync(w.h_total + 4, w.total + 4, 6 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   QK_HIP(hipStreamSynchronize(s));
-  if (idx->prof.on && job.batched)
+  if (idx->prof.on && job.batched) {
     idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[4] * idx->d * 2.0, (double)w.h_total[5] * idx->d * 2.0);
+    idx->prof.add(QUAKE_PROF_SCAN_SETS, (double)w.h_total[9] * idx->d * 2.0, 0.0);
+  }
   else if (idx->prof.on)
     idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[6] * idx->d * sizeof(float),
                   (double)w.h_total[6] * idx->d * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
@@ -1108,8 +1110,23 @@ int quake_autotune(quake_index* idx, const float* q, int64_t nq, const quake_sea
     else
       knobs.push_back({&quake_tuning::blocks_per_cu, {4, 8, 16}});
     if (job.aps) {
-      knobs.push_back({&quake_tuning::first_window, {1, 2, 4, 8}});
-      knobs.push_back({&quake_tuning::max_window, {8, 16, 32, 64}});
+      knobs.push_back({&quake_tuning::first_window, {1, 2, 4, 8, 16, 32, 64}});
+      knobs.push_back({&quake_tuning::max_window, {8, 16, 32, 64, 128, 256}});
+    }
+    // wide windows trade speculative scans for fewer rounds (and so for
+    // fewer reads of partitions that several rounds touch); the two window
+    // sizes interact, so pairs of them are tried together first
+    if (job.aps) {
+      const int32_t pairs[][2] = {{2, 32}, {4, 32}, {8, 32}, {8, 64}, {16, 64}, {16, 128}, {32, 64},
+                                  {32, 128}, {64, 128}, {64, 256}};
+      for (const auto& pr : pairs) {
+        quake_tuning t = best;
+        t.first_window = pr[0];
+        t.max_window = pr[1];
+        if (t.first_window == best.first_window && t.max_window == best.max_window) continue;
+        const double ms = time_it(t);
+        if (ms < 0.97 * best_ms) { best = t; best_ms = ms; }
+      }
     }
     for (int pass = 0; pass < 2; ++pass)
       for (const Knob& kn : knobs)

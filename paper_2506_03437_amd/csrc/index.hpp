@@ -147,10 +147,12 @@ struct Workspace {
   int32_t* pstart = nullptr;    // [nlist + 1]
   int64_t* pitem = nullptr;     // [nlist] first batched work item of each partition (numbered in Store::order)
   // device counters (COUNTERS of them): [0] items, [1] vectors, [2] pairs of
-  // the round, [3] batched items of the round, [4] batched vector reads and
-  // [5] batched query-vector products summed over the search, [6] plain-scan
-  // vectors summed over the search, [7] head of the round's item queue,
-  // [8] first query cut from the round, [16] item queue of the batched scan
+  // the round, [3] batched items of the round, [4] batched distinct vector
+  // reads (each touched partition once per round) and [5] batched
+  // query-vector products summed over the search, [6] plain-scan vectors
+  // summed over the search, [7] head of the round's item queue, [8] first
+  // query cut from the round, [9] batched vector reads counted once per
+  // query set, [16] item queue of the batched scan
   int64_t* total = nullptr;
   int64_t* blk = nullptr;       // [nq / 256 + 1][4] per-block planning sums, then offsets
   int64_t* h_total = nullptr;   // pinned host mirror

@@ -103,14 +103,15 @@ __global__ __launch_bounds__(256) void k_pairs(int64_t nq, int M, int chunk_tile
 // Per-partition pair offsets (partition order) and work-item offsets (in
 // `order`, largest partitions first: the scan takes items in index order, so
 // a launch ends on short items); clears the counts for the next round and
-// adds the round's vector reads and query-vector products to the running
-// totals.  One block.
+// adds to the running totals the round's distinct vector reads (each
+// partition a round touches, once), its reads counted once per query set,
+// and its query-vector products.  One block.
 __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles, int32_t* __restrict__ pcount,
                                                        const int32_t* __restrict__ psize,
                                                        const int32_t* __restrict__ order, int32_t* __restrict__ pstart,
                                                        int64_t* __restrict__ pitem, int64_t* __restrict__ counters) {
   __shared__ int64_t sp[1024], si[1024];
-  __shared__ unsigned long long reads, products;
+  __shared__ unsigned long long reads, set_reads, products;
   const int t = threadIdx.x;
   const int64_t per = (N + 1023) / 1024;
   const int64_t lo = t * per;
@@ -120,20 +121,21 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
     return c > 0 ? (int64_t)((c + SET - 1) / SET) * chunks_of(psize[p], chunk_tiles) : 0;
   };
   int64_t np = 0, ni = 0;
-  unsigned long long rd = 0, pd = 0;
+  unsigned long long rd = 0, srd = 0, pd = 0;
   for (int64_t p = lo; p < hi; ++p) {
     const int c = pcount[p];
     np += c;
     if (c > 0) {
       const int sets = (c + SET - 1) / SET;
-      rd += (unsigned long long)sets * (unsigned long long)psize[p];
+      rd += (unsigned long long)psize[p];
+      srd += (unsigned long long)sets * (unsigned long long)psize[p];
       pd += (unsigned long long)c * (unsigned long long)psize[p];
     }
   }
   for (int64_t r = lo; r < hi; ++r) ni += items_of(order[r]);
   sp[t] = np;
   si[t] = ni;
-  if (t == 0) { reads = 0; products = 0; }
+  if (t == 0) { reads = 0; set_reads = 0; products = 0; }
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
     const int64_t a = (t >= o) ? sp[t - o] : 0;
@@ -158,6 +160,7 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
     pcount[p] = 0;
   }
   atomicAdd(&reads, rd);
+  atomicAdd(&set_reads, srd);
   atomicAdd(&products, pd);
   __syncthreads();
   if (t == 0) {
@@ -165,6 +168,7 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
     counters[3] = si[1023];
     counters[4] += (int64_t)reads;
     counters[5] += (int64_t)products;
+    counters[9] += (int64_t)set_reads;
     counters[QUEUE_X] = 0;
   }
 }

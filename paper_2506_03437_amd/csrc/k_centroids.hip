@@ -395,6 +395,184 @@ void launch_geometry(const float* q, const float* c, int64_t nq, int dp, int M, 
                      sel, order, h);
 }
 
+// ---------------------------------------------------------------- block selection (64 < M <= 256)
+
+// One block per query for candidate sets past one wave.  Selection is a
+// radix select on the order-preserving bits of the keys (value for L2,
+// negated score for IP; ties by centroid id): four 8-bit digit passes with
+// an LDS histogram find the M-th key T, then every key below T and the
+// lowest-id keys equal to T are gathered and sorted by (key, id).
+// Geometry (adaptive mode) as in k_geometry - the projection form, since a
+// difference of two scores would cancel most of the significand for close
+// centroids - with the query and c_0 held in registers (D4 float4 per
+// lane) and each wave taking every fourth candidate row; then the
+// candidates after c_0 are sorted by (h, selection rank).
+template <int KPT, int D4>
+__global__ __launch_bounds__(256) void k_select_large(const float* __restrict__ scores, int64_t nc, int M, int ip,
+                                                       int aps, const float* __restrict__ q,
+                                                       const float* __restrict__ c, int dp,
+                                                       int32_t* __restrict__ cand, float* __restrict__ hout) {
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t buf[256];
+  __shared__ int32_t ids[256];
+  __shared__ uint32_t s_digit, s_below, s_count;
+  const int tid = threadIdx.x;
+  const int64_t qi = blockIdx.x;
+  const float* sq = scores + qi * nc;
+  uint32_t key[KPT];
+#pragma unroll
+  for (int t = 0; t < KPT; ++t) {
+    const int64_t j = (int64_t)t * 256 + tid;
+    key[t] = j < nc ? float_order(ip ? -sq[j] : sq[j]) : 0xffffffffu;
+  }
+  // radix select: T = the M-th smallest key; `need` keys equal to T are taken
+  uint32_t prefix = 0, mask = 0;
+  int need = M;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    hist[tid] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < KPT; ++t)
+      if ((key[t] & mask) == prefix && (int64_t)t * 256 + tid < nc) atomicAdd(&hist[(key[t] >> shift) & 255u], 1u);
+    __syncthreads();
+    if (tid < WAVE) {
+      // inclusive scan of the 256 bins, four per lane
+      const uint32_t a0 = hist[4 * tid], a1 = hist[4 * tid + 1], a2 = hist[4 * tid + 2], a3 = hist[4 * tid + 3];
+      const uint32_t mine = a0 + a1 + a2 + a3;
+      uint32_t run = mine;
+      for (int o = 1; o < WAVE; o <<= 1) {
+        const uint32_t u = __shfl_up(run, o);
+        if (tid >= o) run += u;
+      }
+      const uint32_t before = run - mine;
+      const uint32_t c1 = before + a0, c2 = c1 + a1, c3 = c2 + a2, c4 = c3 + a3;
+      const uint32_t n = (uint32_t)need;
+      if (before < n && c4 >= n) {
+        int d;
+        uint32_t below;
+        if (c1 >= n) { d = 0; below = before; }
+        else if (c2 >= n) { d = 1; below = c1; }
+        else if (c3 >= n) { d = 2; below = c2; }
+        else { d = 3; below = c3; }
+        s_digit = (uint32_t)(4 * tid + d);
+        s_below = below;
+      }
+    }
+    __syncthreads();
+    prefix |= s_digit << shift;
+    mask |= 0xffu << shift;
+    need -= (int)s_below;
+    __syncthreads();
+  }
+  const uint32_t T = prefix;
+  // gather: keys below T, then `need` keys equal to T, the lowest ids first
+  if (tid == 0) s_count = 0;
+  buf[tid] = ~0ull;
+  int eqs = 0;
+#pragma unroll
+  for (int t = 0; t < KPT; ++t) eqs += ((int64_t)t * 256 + tid < nc && key[t] == T) ? 1 : 0;
+  hist[tid] = (uint32_t)eqs;
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < KPT; ++t) {
+    const int64_t j = (int64_t)t * 256 + tid;
+    if (j < nc && key[t] < T) buf[atomicAdd(&s_count, 1u)] = ((uint64_t)key[t] << 32) | (uint32_t)j;
+  }
+  if (tid == 0) {
+    uint32_t tot = 0;
+    for (int u = 0; u < 256; ++u) tot += hist[u];
+    s_digit = tot;
+  }
+  __syncthreads();
+  if ((int)s_digit == need) {  // the usual case: every key equal to T is taken
+#pragma unroll
+    for (int t = 0; t < KPT; ++t) {
+      const int64_t j = (int64_t)t * 256 + tid;
+      if (j < nc && key[t] == T) buf[atomicAdd(&s_count, 1u)] = ((uint64_t)T << 32) | (uint32_t)j;
+    }
+  } else {
+    // more ties than places: ids run t * 256 + tid, so chunk by chunk in id order
+    int taken = 0;
+    for (int t = 0; t < KPT && taken < need; ++t) {
+      const int64_t j = (int64_t)t * 256 + tid;
+      const bool eq = j < nc && key[t] == T;
+      __syncthreads();
+      hist[tid] = eq ? 1u : 0u;
+      __syncthreads();
+      uint32_t rank = 0, total = 0;
+      for (int u = 0; u < 256; ++u) {
+        const uint32_t v = hist[u];
+        rank += (u < tid) ? v : 0u;
+        total += v;
+      }
+      if (eq && taken + (int)rank < need) buf[atomicAdd(&s_count, 1u)] = ((uint64_t)T << 32) | (uint32_t)j;
+      taken += (int)total;
+    }
+  }
+  bitonic_sort_u64(buf, 256);
+  // buf[0..M) holds the M best in (key, id) order
+  if (!aps) {
+    if (tid < M) cand[qi * M + tid] = (int32_t)(uint32_t)(buf[tid] & 0xffffffffu);
+    return;
+  }
+  const int32_t c0 = (int32_t)(uint32_t)(buf[0] & 0xffffffffu);
+  ids[tid] = tid < M ? (int32_t)(uint32_t)(buf[tid] & 0xffffffffu) : -1;
+  __syncthreads();
+  {
+    const int w = tid >> 6, lane = tid & 63;
+    const float4* qv = reinterpret_cast<const float4*>(q + qi * dp);
+    const float4* c0v = reinterpret_cast<const float4*>(c + (int64_t)c0 * dp);
+    const int n4 = dp >> 2;
+    float4 qr[D4], ar[D4];
+#pragma unroll
+    for (int t = 0; t < D4; ++t) {
+      const int j = t * WAVE + lane;
+      qr[t] = j < n4 ? qv[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      ar[t] = j < n4 ? c0v[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    for (int i = 1 + w; i < M; i += 4) {
+      const float4* cjv = reinterpret_cast<const float4*>(c + (int64_t)ids[i] * dp);
+      // the row's loads are unconditional (clamped; lanes past dp add
+      // nothing), so they are all in flight before the first product
+      float4 bv[D4];
+#pragma unroll
+      for (int t = 0; t < D4; ++t) bv[t] = cjv[min(t * WAVE + lane, n4 - 1)];
+      float num = 0.f, sep = 0.f;
+#pragma unroll
+      for (int t = 0; t < D4; ++t) {
+        const bool in = t * WAVE + lane < n4;
+        const float4 a = ar[t], b = bv[t], x = qr[t];
+        const float e0 = a.x - b.x, e1 = a.y - b.y, e2 = a.z - b.z, e3 = a.w - b.w;
+        float s2 = fmaf(e0, e0, fmaf(e1, e1, fmaf(e2, e2, fmaf(e3, e3, sep))));
+        float n2 = ip ? fmaf(x.x, e0, fmaf(x.y, e1, fmaf(x.z, e2, fmaf(x.w, e3, num))))
+                      : fmaf(e0, (x.x - a.x) + (x.x - b.x),
+                             fmaf(e1, (x.y - a.y) + (x.y - b.y),
+                                  fmaf(e2, (x.z - a.z) + (x.z - b.z), fmaf(e3, (x.w - a.w) + (x.w - b.w), num))));
+        sep = in ? s2 : sep;
+        num = in ? n2 : num;
+      }
+      num = wave_sum_f(num);
+      sep = wave_sum_f(sep);
+      float hi = 0.f;
+      if (sep > 0.f) hi = ip ? num / sqrtf(sep) : num / (2.0f * sqrtf(sep));
+      if (lane == 0) hist[i] = __float_as_uint(fmaxf(hi, 0.f));
+    }
+  }
+  __syncthreads();
+  // order the candidates after c_0 by (h, selection rank)
+  const float h = (tid >= 1 && tid < M) ? __uint_as_float(hist[tid]) : 0.f;
+  buf[tid] = (tid >= 1 && tid < M) ? (((uint64_t)float_order(h) << 32) | (uint32_t)tid) : ~0ull;
+  bitonic_sort_u64(buf, 256);
+  if (tid == 0) {
+    cand[qi * M] = c0;
+    hout[qi * M] = 0.f;
+  } else if (tid < M) {
+    const uint64_t e = buf[tid - 1];
+    cand[qi * M + tid] = ids[(uint32_t)(e & 0xffffffffu)];
+    hout[qi * M + tid] = float_unorder((uint32_t)(e >> 32));
+  }
+}
+
 // ---------------------------------------------------------------- fused selection (M <= 64)
 
 // One wave per query.  Selection: chunks of 64 scores are sorted and merged
@@ -498,6 +676,22 @@ void launch_candidates(const Store& st, const float* q, const float* scores, int
     else if (dpl <= 12) QK_SEL(12);
     else QK_SEL(16);
 #undef QK_SEL
+    return;
+  }
+  if (M <= 256 && st.nlist <= 256 * 64 && dp <= 1024) {
+    const dim3 grid((unsigned)nq);
+    const int d4 = (dp / 4 + WAVE - 1) / WAVE;
+#define QK_SELL(K, D)                                                                                            \
+  hipLaunchKernelGGL((k_select_large<K, D>), grid, dim3(256), 0, s, scores, st.nlist, M, ip, aps, q, st.centroids, \
+                     dp, cand, h)
+#define QK_SELL_D(K) \
+  if (d4 <= 1) QK_SELL(K, 1); else if (d4 <= 2) QK_SELL(K, 2); else if (d4 <= 3) QK_SELL(K, 3); else QK_SELL(K, 4)
+    if (st.nlist <= 256 * 8) { QK_SELL_D(8); }
+    else if (st.nlist <= 256 * 16) { QK_SELL_D(16); }
+    else if (st.nlist <= 256 * 32) { QK_SELL_D(32); }
+    else { QK_SELL_D(64); }
+#undef QK_SELL_D
+#undef QK_SELL
     return;
   }
   if (aps) {

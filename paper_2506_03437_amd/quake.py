@@ -30,7 +30,7 @@ EXPORTED = ("quake_build", "quake_search", "quake_insert", "quake_delete", "quak
             "quake_export_top", "quake_candidates", "quake_cap_table", "quake_profile", "quake_set_tuning",
             "quake_free", "quake_last_error", "quake_autotune", "quake_server_create", "quake_server_search", "quake_server_insert",
             "quake_server_delete", "quake_server_wait", "quake_server_stats", "quake_server_destroy")
-PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "unused6", "unused7")
+PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "scan_sets", "unused7")
 
 
 class QuakeError(RuntimeError):
