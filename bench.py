@@ -81,13 +81,13 @@ def profiled_traffic(kernel, workload, source, knobs):
     fields = {}
     for line in open(path):
         if " = " in line and not line.startswith(" "):
-            k, v = line.strip().split(" = ", 1)
-            fields[k] = v
+            k, v = line.rstrip("\n").split(" = ", 1)
+            fields[k.strip()] = v.strip()
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     # how many rounds are enqueued per host sync, and graph replay, leave the
     # scan launches themselves unchanged
     same = ("rounds_per_sync", "no_graph")
-    want = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in fields.get("knobs", "").split(",") if kv}
+    want = {kv.split("=")[0]: int(kv.split("=")[1]) for kv in fields.get("knobs", "").split(",") if "=" in kv}
     want = {k: v for k, v in want.items() if k not in same and v}
     have = {k: v for k, v in (knobs or {}).items() if v and k not in same}
     if fields.get("kernel_source_sha256") != sha or want != have or "traffic_bytes_per_launch" not in fields:
