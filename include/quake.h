@@ -216,7 +216,7 @@ int quake_autotune(quake_index* index, const float* q, int64_t nq, const quake_s
  * every partition a round touches, once per round, d * 2 each (the bytes a
  * launch has to read); centroid rows for scoring.  QUAKE_PROF_SCAN_SETS
  * holds (bytes only) the batched scan's reads counted once per query set of
- * up to 64 queries, the bytes its blocks request.  reset = 1 zeroes the
+ * up to 128 queries, the bytes its blocks request.  reset = 1 zeroes the
  * totals.  out (host, QUAKE_PROF_KINDS entries) receives the totals when
  * not NULL. */
 enum {

@@ -4,9 +4,9 @@
 //
 // Per round, every query's window of (query, partition) pairs is bucketed by
 // partition.  A work item is (partition chunk of up to chunk_tiles tiles,
-// set of up to 64 of the partition's queries); items are numbered largest
-// partition first.  A block of four waves takes items from a queue; each
-// tile of the chunk is staged once through LDS and scored by the four waves,
+// set of up to 128 of the partition's queries); items are numbered largest
+// partition first.  A block of eight waves takes items from a queue; each
+// tile of the chunk is staged once through LDS and scored by the eight waves,
 // 16 queries each, with v_mfma_f32_16x16x32 on the 16-bit store copy (BF16
 // or FP16 products, FP32 accumulation): the queries sit in registers as B
 // operands for the whole item and the store's [chunk][64 vectors][8
@@ -26,10 +26,12 @@
 namespace qk {
 
 constexpr int G = 16;           // queries per wave (one MFMA column block)
-constexpr int SET_GROUPS = 4;   // query groups per block, one per wave
+constexpr int SET_GROUPS = 8;   // query groups per block, one per wave
 constexpr int SET = G * SET_GROUPS;  // queries that share one read of a tile
-constexpr int BUF = 3 * WAVE;   // per-query candidate pool (three entries per lane; holds kk, slack and a tile)
-constexpr int SLACK = 16;       // entries a mid-item cut may keep beyond kk
+constexpr int NT = WAVE * SET_GROUPS;  // threads per scan block
+constexpr int BUF = 2 * WAVE;   // per-query candidate pool (two entries per lane): a cut keeps at most
+                                // max(kk, 64) <= 64 entries, so a whole tile's 64 always fit after one
+constexpr int SLACK = 16;       // entries a mid-item cut may keep beyond kk (room permitting)
 constexpr int QUEUE_X = 16;     // counters[16]: item queue of the batched scan
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
@@ -240,26 +242,27 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
 }
 
 template <int F16, int KS, int IP>
-__global__ __launch_bounds__(256, 1) void k_scan_mfma(
+__global__ __launch_bounds__(NT, 1) void k_scan_mfma(
     int64_t* __restrict__ counters, const int4* __restrict__ bitems, const int32_t* __restrict__ sorted_q,
     const int64_t* __restrict__ sorted_base, int chunk_tiles, const uint16_t* __restrict__ q16, int dp16,
     const float* __restrict__ qn2f, const uint16_t* __restrict__ v16, const float* __restrict__ v16n,
     const int64_t* __restrict__ sid, const float* __restrict__ rk, const int64_t* __restrict__ ri, int kk,
     float* __restrict__ pk, int64_t* __restrict__ pi) {
-  // k-steps per stage: the largest of 4, 2, 1 that leaves an even number of
-  // stages per tile, so that a tile always starts in LDS buffer 0
-  constexpr int KST = (KS % 8 == 0) ? 4 : ((KS % 4 == 0) ? 2 : 1);
+  // k-steps per stage: 2, or 1 where that leaves an odd number of stages per
+  // tile (a tile always starts in LDS buffer 0); two 8 KiB stages leave LDS
+  // room for the 128 queries' candidate pools
+  constexpr int KST = (KS % 4 == 0) ? 2 : 1;
   constexpr int NS = KS / KST;                  // stages per tile
   constexpr int SU = KST * 4 * TILE;            // 16-byte units per stage
-  constexpr int UPT = SU / 256;                 // units each thread carries per stage
+  constexpr int UPT = SU >= NT ? SU / NT : 1;   // units each thread carries per stage
   // loads run DEPTH stages (TA whole tiles) ahead of the MFMAs, so that each
   // block keeps 32-128 KiB of the store in flight
   constexpr int TA = NS >= 4 ? 1 : 2;
   constexpr int DEPTH = NS * TA;
-  static_assert(KS % KST == 0 && NS % 2 == 0 && SU % 256 == 0, "stage shape");
+  static_assert(KS % KST == 0 && NS % 2 == 0 && (SU % NT == 0 || SU < NT), "stage shape");
   __shared__ u32x4 RING[2][SU];                 // two stages of the current tile
-  __shared__ float BK[4][G][BUF];               // per query: candidates that beat the threshold, not yet merged
-  __shared__ int32_t BS[4][G][BUF];
+  __shared__ float BK[SET_GROUPS][G][BUF];      // per query: candidates that beat the threshold, not yet merged
+  __shared__ int32_t BS[SET_GROUPS][G][BUF];
   __shared__ int64_t next_item[2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // Blocks take items in order from one queue: items differ widely in cost
@@ -310,15 +313,18 @@ __global__ __launch_bounds__(256, 1) void k_scan_mfma(
     // stages past the item's end reload its last stage, and an empty item
     // reads the arena's first tile (never used either)
     const u32x4* src = reinterpret_cast<const u32x4*>(v16) + (U > 0 ? (tile0 + t0) * (int64_t)nc8 * TILE : 0);
+    // (with fewer units per stage than threads, the surplus threads load a
+    // copy of the last unit and store nothing)
     auto load = [&](int u, u32x4 (&r)[UPT]) {
       u = max(0, min(u, U - 1));
       const u32x4* sp = src + (int64_t)(u / NS) * nc8 * TILE + (int64_t)(u % NS) * SU;
 #pragma unroll
-      for (int e = 0; e < UPT; ++e) r[e] = sp[e * 256 + threadIdx.x];
+      for (int e = 0; e < UPT; ++e) r[e] = sp[min(e * NT + (int)threadIdx.x, SU - 1)];
     };
     auto put = [&](const u32x4 (&r)[UPT], int buf) {
 #pragma unroll
-      for (int e = 0; e < UPT; ++e) RING[buf][e * 256 + threadIdx.x] = r[e];
+      for (int e = 0; e < UPT; ++e)
+        if (SU >= NT || (int)threadIdx.x < SU) RING[buf][e * NT + threadIdx.x] = r[e];
     };
     // registers: stage u (u >= 1) waits in slot (u - 1) % DEPTH until it is
     // moved to LDS buffer u % 2 at the end of stage u - 1; the first stages
@@ -646,7 +652,7 @@ template <int F16, int IP>
 static void scan_mfma_k(Workspace& ws, const Store& st, const RoundArgs& a, int blocks, hipStream_t s) {
   const int ks = st.dp16 / 32;
 #define QK_MFMA_LAUNCH(KS)                                                                                      \
-  hipLaunchKernelGGL((k_scan_mfma<F16, KS, IP>), dim3(blocks), dim3(256), 0, s, ws.total, ws.bitems,          \
+  hipLaunchKernelGGL((k_scan_mfma<F16, KS, IP>), dim3(blocks), dim3(NT), 0, s, ws.total, ws.bitems,           \
                      ws.sorted_q, ws.sorted_base, a.chunk_tiles, ws.q16, st.dp16, ws.qn2f, st.v16, st.v16n, st.ids, \
                      ws.rk, ws.ri, a.kk, ws.pk, ws.pi)
   switch (ks) {
