@@ -185,7 +185,7 @@ int quake_cap_table(int32_t d, double* out_1024);
  * are committed in candidate order whatever the cut.  Errors: INVALID for
  * negative values, STATE for a bad handle. */
 typedef struct {
-  int32_t chunk_tiles;   /* store tiles (64 vectors each) per work item; default 16 */
+  int32_t chunk_tiles;   /* store tiles (64 vectors each) per work item, <= 1024; default 16 */
   int32_t first_window;  /* APS: partitions per query in the first round; default 2 */
   int32_t max_window;    /* APS: most partitions per query in one round; default 32 */
   int32_t blocks_per_cu; /* persistent scan grid, blocks of 4 waves per compute unit; default 1 (MFMA) / 8 (FP32) */

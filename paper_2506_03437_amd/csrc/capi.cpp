@@ -1051,6 +1051,7 @@ int quake_set_tuning(quake_index* idx, const quake_tuning* t) {
   QK_CHECK(t->chunk_tiles >= 0 && t->first_window >= 0 && t->max_window >= 0 && t->max_items >= 0 &&
                t->blocks_per_cu >= 0 && t->rounds_per_sync >= 0 && t->no_graph >= 0,
            QUAKE_E_INVALID, "tuning values must be >= 0");
+  QK_CHECK(t->chunk_tiles <= 1024, QUAKE_E_INVALID, "chunk_tiles must be <= 1024");
   idx->tune = *t;
   API_END
 }

@@ -6,11 +6,15 @@
 // partition.  A work item is (partition chunk of up to chunk_tiles tiles,
 // set of up to 128 of the partition's queries); items are numbered largest
 // partition first.  A block of eight waves takes items from a queue; each
-// tile of the chunk is staged once through LDS and scored by the eight waves,
-// 16 queries each, with v_mfma_f32_16x16x32 on the 16-bit store copy (BF16
+// tile of the chunk is staged once through LDS and scored by the eight waves
+// for 128 queries with v_mfma_f32_16x16x32 on the 16-bit store copy (BF16
 // or FP16 products, FP32 accumulation): the queries sit in registers as B
 // operands for the whole item and the store's [chunk][64 vectors][8
-// elements] tile layout is the A fragment order.  After each tile every lane
+// elements] tile layout is the A fragment order.  The waves work in pairs
+// on two 16-query groups, one taking the even k-steps and the other the odd
+// ones, so every A fragment read from LDS feeds two MFMAs (LDS reads, not
+// the matrix cores, bound a tile shared by this many queries); at the end of
+// a tile the two halves of each group's sums meet in LDS.  After each tile every lane
 // holds 16 scores of one query and tests them against the query's threshold;
 // candidates go to a per-query pool in LDS that is cut by ballot-count
 // bisection, and at the item's end each query's best rerank_factor * k
@@ -31,6 +35,7 @@ constexpr int SET = G * SET_GROUPS;  // queries that share one read of a tile
 constexpr int NT = WAVE * SET_GROUPS;  // threads per scan block
 constexpr int BUF = 2 * WAVE;   // per-query candidate pool (two entries per lane): a cut keeps at most
                                 // max(kk, 64) <= 64 entries, so a whole tile's 64 always fit after one
+constexpr int MAX_ITEM_TILES = 1024;  // pool slots are 16-bit offsets from the item's first slot
 constexpr int SLACK = 16;       // entries a mid-item cut may keep beyond kk (room permitting)
 constexpr int QUEUE_X = 16;     // counters[16]: item queue of the batched scan
 
@@ -248,9 +253,10 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
     const float* __restrict__ qn2f, const uint16_t* __restrict__ v16, const float* __restrict__ v16n,
     const int64_t* __restrict__ sid, const float* __restrict__ rk, const int64_t* __restrict__ ri, int kk,
     float* __restrict__ pk, int64_t* __restrict__ pi) {
-  // k-steps per stage: 2, or 1 where that leaves an odd number of stages per
-  // tile (a tile always starts in LDS buffer 0); two 8 KiB stages leave LDS
-  // room for the 128 queries' candidate pools
+  // k-steps per stage: 2 (one for each wave of a pair), or 1 where that
+  // leaves an odd number of stages per tile (a tile always starts in LDS
+  // buffer 0; the pair then takes alternate stages); two 8 KiB stages leave
+  // LDS room for the 128 queries' candidate pools
   constexpr int KST = (KS % 4 == 0) ? 2 : 1;
   constexpr int NS = KS / KST;                  // stages per tile
   constexpr int SU = KST * 4 * TILE;            // 16-byte units per stage
@@ -262,7 +268,8 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
   static_assert(KS % KST == 0 && NS % 2 == 0 && (SU % NT == 0 || SU < NT), "stage shape");
   __shared__ u32x4 RING[2][SU];                 // two stages of the current tile
   __shared__ float BK[SET_GROUPS][G][BUF];      // per query: candidates that beat the threshold, not yet merged
-  __shared__ int32_t BS[SET_GROUPS][G][BUF];
+  __shared__ uint16_t BS[SET_GROUPS][G][BUF];   // their slots, as offsets from the item's first slot
+  __shared__ f32x4 XCH[SET_GROUPS][4][WAVE];    // each wave's half sums of its partner's group, per tile
   __shared__ int64_t next_item[2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // Blocks take items in order from one queue: items differ widely in cost
@@ -275,7 +282,12 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
   unsigned long long* queue = (unsigned long long*)(counters + QUEUE_X);
   constexpr int nc8 = KS * 4;  // 8-element chunks per row of the 16-bit copy
   float (*Bk)[BUF] = BK[wave];
-  int32_t (*Bs)[BUF] = BS[wave];
+  uint16_t (*Bs)[BUF] = BS[wave];
+  // wave pair (2p, 2p + 1): query groups 2p and 2p + 1 of the set; the wave
+  // of parity h takes the k-steps of parity h for both groups, and at the
+  // end of a tile keeps its own group (group `wave`) and hands the partner
+  // group's half sums over
+  const int h = wave & 1;
   for (int k = 0;; k ^= 1) {
     // every thread read next_item[k] two items ago, before the barrier that
     // started the last item
@@ -303,6 +315,11 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
     const bool has = j < gcount;
     const int pidx = has ? pfirst + g * G + j : pfirst;  // a valid pair in every lane
     const int qj = sorted_q[pidx];
+    // the partner wave's query in this lane's column (row 0 when absent)
+    const int gp = g ^ 1;
+    const int qp = sorted_q[j < max(0, min(G, np - gp * G)) ? pfirst + gp * G + j : pfirst];
+    // slot offsets in the pools are relative to the item's first slot
+    const int32_t item_slot0 = (int32_t)((tile0 + t0) * TILE);
     // first output slot of this lane's pair, used only at the item's end
     // (loaded now so that its latency hides behind the scan)
     const int64_t my_base = sorted_base[pidx];
@@ -338,11 +355,15 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
     // and the result discarded where unused): a load under a branch leaves
     // the compiler unsure how many loads are in flight, and it then waits
     // for all of them - which would drain the prefetch pipeline below.
-    u32x4 breg[KS];
+    // B fragments of the k-steps of this wave's parity, for its own group
+    // (breg[0]) and its partner's (breg[1]); columns of absent queries score
+    // row 0 and are never read
+    u32x4 breg[2][KS / 2];
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      // columns of absent queries score row 0 and are never read
-      breg[s] = *reinterpret_cast<const u32x4*>(q16 + (int64_t)qj * dp16 + 32 * s + 8 * (lane >> 4));
+    for (int i = 0; i < KS / 2; ++i) {
+      const int s = 2 * i + h;
+      breg[0][i] = *reinterpret_cast<const u32x4*>(q16 + (int64_t)qj * dp16 + 32 * s + 8 * (lane >> 4));
+      breg[1][i] = *reinterpret_cast<const u32x4*>(q16 + (int64_t)qp * dp16 + 32 * s + 8 * (lane >> 4));
     }
     const float qn2_row = qn2f[qj];
     const float my_qn2 = (IP || !has) ? 0.f : qn2_row;
@@ -390,7 +411,7 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
           const bool v = act[q] && e * WAVE + lane < n[q];
           const int jj = act[q] ? jq[q] : 0;
           kv[q][e] = v ? Bk[jj][e * WAVE + lane] : KEY_EMPTY;
-          sv[q][e] = v ? Bs[jj][e * WAVE + lane] : INT32_MAX;
+          sv[q][e] = v ? (int32_t)Bs[jj][e * WAVE + lane] : INT32_MAX;
           uv[q][e] = v ? float_order(kv[q][e]) : 0xffffffffu;
           mn = min(mn, uv[q][e]);
           mx = max(mx, v ? uv[q][e] : 0u);
@@ -466,7 +487,7 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
           const bool keep = uv[q][e] < T || (uv[q][e] == T && sv[q][e] <= slo);
           const uint64_t m = __ballot(keep);
           const int p = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          if (keep) { Bk[jj][p] = kv[q][e]; Bs[jj][p] = sv[q][e]; }
+          if (keep) { Bk[jj][p] = kv[q][e]; Bs[jj][p] = (uint16_t)sv[q][e]; }
           base += __popcll(m);
         }
         if (j == jj) {
@@ -481,9 +502,11 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
     // A fragments of one k-step: vectors 16b + (lane & 15), 16-byte chunk
     // 4s + (lane >> 4) of the stage
     const int frag = (lane >> 4) * TILE + (lane & 15);
-    f32x4 acc[4];
+    f32x4 acc[2][4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int gi = 0; gi < 2; ++gi)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[gi][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     // Ids (and norms) of a tile are loaded one tile ahead: the wait for them
     // at the tile's end then covers only loads issued before them, not the
     // stage prefetches issued since (an empty item reads the arena's first
@@ -513,15 +536,27 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
       for (int st = 0; st < NS; ++st) {
         const int u = (t - t0) * NS + st;
         const int slot = ta * NS + st;  // u % DEPTH
-        // (waves without queries score too - their results are never read -
+        // (groups without queries score too - their results are never read -
         // so that the accumulators stay in the matrix registers throughout)
-#pragma unroll
-        for (int s = 0; s < KST; ++s) {
+        auto kstep = [&](int s, int i) {
           u32x4 a[4];
 #pragma unroll
           for (int b = 0; b < 4; ++b) a[b] = RING[st & 1][4 * s * TILE + frag + 16 * b];
 #pragma unroll
-          for (int b = 0; b < 4; ++b) acc[b] = mfma16<F16>(a[b], breg[st * KST + s], acc[b]);
+          for (int b = 0; b < 4; ++b) acc[0][b] = mfma16<F16>(a[b], breg[0][i], acc[0][b]);
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[1][b] = mfma16<F16>(a[b], breg[1][i], acc[1][b]);
+        };
+        if constexpr (KST == 2) {
+          kstep(h, st);            // k-step 2 st + h of the tile
+        } else if ((st & 1) == h) {
+          kstep(0, st >> 1);       // k-step st, of this wave's parity
+        }
+        if (st == NS - 1) {
+          // the partner group's half sums go to the partner (read after the
+          // barrier below)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) XCH[wave][b][lane] = acc[1][b];
         }
         // the other LDS buffer was last read in stage u - 1 (before the last
         // barrier): it takes stage u + 1, whose registers then load stage
@@ -530,15 +565,26 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
         load(u + 1 + DEPTH, rs[slot]);
         __syncthreads();
       }
-      if (gcount == 0) continue;
+      // the own group's sums: even k-steps plus odd k-steps (in that order
+      // on both waves of the pair, so the two halves add up identically)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const f32x4 other = XCH[wave ^ 1][b][lane];
+        acc[0][b] = h == 0 ? acc[0][b] + other : other + acc[0][b];
+        acc[1][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      if (gcount == 0) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[0][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        continue;
+      }
       {
-        // The tile's scores are complete.  acc[b][v] is the product of query
-        // j = lane & 15 with vector 16b + 4 (lane >> 4) + v of the tile, so
-        // every lane tests its 16 values against its query's threshold in
-        // registers; most tiles end here with nothing to keep.
-        const int64_t tile = tile0 + t;
+        // The tile's scores are complete.  acc[0][b][v] is the product of
+        // query j = lane & 15 with vector 16b + 4 (lane >> 4) + v of the
+        // tile, so every lane tests its 16 values against its query's
+        // threshold in registers; most tiles end here with nothing to keep.
         const uint64_t live = __ballot(t * TILE + lane < size && tile_id >= 0);
-        const int32_t slot0 = (int32_t)(tile * TILE);
+        const int32_t slot0 = (int32_t)((t - t0) * TILE);  // relative to the item's first slot
         float key[16];
         // live bits of this lane's 16 vectors (bit 4b + v: vector 16b + 4g + v);
         // absent queries take nothing
@@ -552,11 +598,11 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int vi = 16 * b + 4 * (lane >> 4) + v;
-            const float dot = acc[b][v];
+            const float dot = acc[0][b][v];
             key[4 * b + v] = IP ? -dot : (my_qn2 + __shfl(tile_xn, vi) - 2.f * dot);
           }
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < 4; ++b) acc[0][b] = f32x4{0.f, 0.f, 0.f, 0.f};
         // bit e: value e is live and at or below the query's threshold
         auto pass_bits = [&]() {
           uint32_t m = 0;
@@ -600,7 +646,7 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
           for (int e = 0; e < 16; ++e) {
             if ((pm >> e) & 1u) {
               Bk[j][pos] = key[e];
-              Bs[j][pos] = slot0 + 16 * (e >> 2) + 4 * g4 + (e & 3);
+              Bs[j][pos] = (uint16_t)(slot0 + 16 * (e >> 2) + 4 * g4 + (e & 3));
               ++pos;
             }
           }
@@ -630,7 +676,8 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
 #pragma unroll
         for (int q = 0; q < FB; ++q) {
           const int n = __builtin_amdgcn_readlane(cn, q0 + q);
-          bv[q] = pack_key_slot(lane < n ? Bk[q0 + q][lane] : KEY_EMPTY, lane < n ? Bs[q0 + q][lane] : -1);
+          bv[q] = pack_key_slot(lane < n ? Bk[q0 + q][lane] : KEY_EMPTY,
+                                lane < n ? item_slot0 + (int32_t)Bs[q0 + q][lane] : -1);
         }
         wave_sort64_packed_n<FB>(bv);
 #pragma unroll
