@@ -192,6 +192,8 @@ typedef struct {
   int64_t max_items;     /* work items per round (bounds the scratch memory); default from nq */
   int32_t rounds_per_sync; /* rounds enqueued between host checks for completion; default 1, 2, 4, then 8 */
   int32_t no_graph;      /* 1: launch every round's kernels; default 0 replays captured HIP graphs of rounds */
+  int32_t window_scale;  /* APS: a query's predicted next window is scaled by this percentage, 100..1000
+                            (fewer rounds for more speculative scans); default 100 */
 } quake_tuning;
 int quake_set_tuning(quake_index* index, const quake_tuning* tuning);
 

@@ -666,7 +666,7 @@ std::vector<uint64_t> graph_key(const quake_index* idx, const Store& st, const J
   auto u = [](const void* p) { return (uint64_t)(uintptr_t)p; };
   std::vector<uint64_t> k = {
       (uint64_t)R, (uint64_t)job.batched, (uint64_t)job.dtype16, (uint64_t)a.nq, (uint64_t)a.M, (uint64_t)a.k,
-      (uint64_t)a.kk, (uint64_t)a.aps, (uint64_t)a.chunk_tiles, (uint64_t)a.wmax, (uint64_t)a.metric,
+      (uint64_t)a.kk, (uint64_t)a.aps, (uint64_t)a.chunk_tiles, (uint64_t)a.wmax, (uint64_t)a.wscale, (uint64_t)a.metric,
       (uint64_t)a.items_cap, (uint64_t)a.blocks, (uint64_t)a.slot_ids, (uint64_t)st.d, (uint64_t)st.dp, (uint64_t)st.nlist,
       (uint64_t)st.dp16, u(idx->cap_table), u(st.centroids), u(st.d_off), u(st.d_size), u(st.d_cap), u(st.d_order), u(st.v32),
       u(st.v16), u(st.v16n), u(st.rows32), u(st.ids), u(w.q), u(w.qn2), u(w.cand), u(w.mq), u(w.h), u(w.st_m),
@@ -772,8 +772,12 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
   const int64_t mc = max_chunks(st, chunk_tiles);
   // the buffer must hold one full window of the largest partitions (progress)
   const int64_t floor_items = (int64_t)job.wmax * mc + 1;
-  const int64_t items =
-      std::max<int64_t>(idx->tune.max_items > 0 ? idx->tune.max_items : nq * std::max(job.w0, 4) * 2, floor_items);
+  // by default room for every query's first window twice over, and on the
+  // batched path for a whole round of largest windows (partitions there are
+  // mostly one chunk): a round that runs out of items defers queries to a
+  // further round, which reads the partitions it touches once more
+  const int64_t def_items = nq * (int64_t)std::max(std::max(job.w0, 4) * 2, job.batched ? job.wmax : 0);
+  const int64_t items = std::max<int64_t>(idx->tune.max_items > 0 ? idx->tune.max_items : def_items, floor_items);
   ensure_workspace(idx, st.nlist, job.M, job.kk, items, job.batched ? nq * (int64_t)job.wmax : 0,
                    job.batched ? st.dp16 : 0, !job.given);
   qk::Workspace& w = idx->ws;
@@ -802,6 +806,7 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
   a.aps = job.aps;
   a.chunk_tiles = chunk_tiles;
   a.wmax = job.wmax;
+  a.wscale = idx->tune.window_scale > 0 ? idx->tune.window_scale : 100;
   a.slot_ids = job.batched && st.tiles * qk::TILE < (int64_t{1} << 31) ? 1 : 0;
   a.metric = idx->metric;
   a.dim = idx->d;
@@ -1052,6 +1057,8 @@ int quake_set_tuning(quake_index* idx, const quake_tuning* t) {
                t->blocks_per_cu >= 0 && t->rounds_per_sync >= 0 && t->no_graph >= 0,
            QUAKE_E_INVALID, "tuning values must be >= 0");
   QK_CHECK(t->chunk_tiles <= 1024, QUAKE_E_INVALID, "chunk_tiles must be <= 1024");
+  QK_CHECK(t->window_scale == 0 || (t->window_scale >= 100 && t->window_scale <= 1000), QUAKE_E_INVALID,
+           "window_scale must be 0 or in [100, 1000]");
   idx->tune = *t;
   API_END
 }
@@ -1113,13 +1120,15 @@ int quake_autotune(quake_index* idx, const float* q, int64_t nq, const quake_sea
     if (job.aps) {
       knobs.push_back({&quake_tuning::first_window, {1, 2, 4, 8, 16, 32, 64}});
       knobs.push_back({&quake_tuning::max_window, {8, 16, 32, 64, 128, 256}});
+      knobs.push_back({&quake_tuning::window_scale, {100, 150, 200, 300}});
     }
     // wide windows trade speculative scans for fewer rounds (and so for
     // fewer reads of partitions that several rounds touch); the two window
     // sizes interact, so pairs of them are tried together first
     if (job.aps) {
-      const int32_t pairs[][2] = {{2, 32}, {4, 32}, {8, 32}, {8, 64}, {16, 64}, {16, 128}, {32, 64},
-                                  {32, 128}, {64, 128}, {64, 256}};
+      const int32_t pairs[][2] = {{1, 32}, {1, 64}, {1, 128}, {2, 32}, {2, 64}, {2, 128}, {4, 32}, {4, 64},
+                                  {4, 128}, {8, 32}, {8, 64}, {16, 64}, {16, 128}, {32, 64}, {32, 128},
+                                  {64, 128}, {64, 256}};
       for (const auto& pr : pairs) {
         quake_tuning t = best;
         t.first_window = pr[0];

@@ -266,6 +266,7 @@ struct RoundArgs {
   int aps;           // 1: adaptive; 0: fixed nprobe
   int chunk_tiles;   // tiles per work item
   int wmax;
+  int wscale;        // predicted windows are scaled by this percentage (>= 100)
   int metric;
   int dim;           // d, for nothing but documentation of the table
   double tau_r, tau_rho;

@@ -253,11 +253,11 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
     const float* __restrict__ qn2f, const uint16_t* __restrict__ v16, const float* __restrict__ v16n,
     const int64_t* __restrict__ sid, const float* __restrict__ rk, const int64_t* __restrict__ ri, int kk,
     float* __restrict__ pk, int64_t* __restrict__ pi) {
-  // k-steps per stage: 2 (one for each wave of a pair), or 1 where that
-  // leaves an odd number of stages per tile (a tile always starts in LDS
-  // buffer 0; the pair then takes alternate stages); two 8 KiB stages leave
-  // LDS room for the 128 queries' candidate pools
-  constexpr int KST = (KS % 4 == 0) ? 2 : 1;
+  // k-steps per stage: 4 (two for each wave of a pair), else 2 or 1 where
+  // that leaves an odd number of stages per tile (a tile always starts in
+  // LDS buffer 0; with 1 the pair takes alternate stages); the two stages,
+  // the 128 queries' candidate pools and the pairs' exchange fill the LDS
+  constexpr int KST = (KS % 8 == 0) ? 4 : ((KS % 4 == 0) ? 2 : 1);
   constexpr int NS = KS / KST;                  // stages per tile
   constexpr int SU = KST * 4 * TILE;            // 16-byte units per stage
   constexpr int UPT = SU >= NT ? SU / NT : 1;   // units each thread carries per stage
@@ -270,7 +270,11 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
   __shared__ float BK[SET_GROUPS][G][BUF];      // per query: candidates that beat the threshold, not yet merged
   __shared__ uint16_t BS[SET_GROUPS][G][BUF];   // their slots, as offsets from the item's first slot
   __shared__ f32x4 XCH[SET_GROUPS][4][WAVE];    // each wave's half sums of its partner's group, per tile
-  __shared__ int64_t next_item[2];
+  // the item a block takes next is published in LDS buffer 1 of the ring:
+  // between the last barrier of an item (buffer 1 was read before it) and
+  // the first stage of the next (it writes buffer 1 after two barriers) no
+  // one touches that buffer
+  int64_t* next_item = reinterpret_cast<int64_t*>(&RING[1][0]);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // Blocks take items in order from one queue: items differ widely in cost
   // (power-law partition sizes and query counts), so a static split would
@@ -361,7 +365,7 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
     u32x4 breg[2][KS / 2];
 #pragma unroll
     for (int i = 0; i < KS / 2; ++i) {
-      const int s = 2 * i + h;
+      const int s = 2 * i + h;  // k-step of breg[.][i]
       breg[0][i] = *reinterpret_cast<const u32x4*>(q16 + (int64_t)qj * dp16 + 32 * s + 8 * (lane >> 4));
       breg[1][i] = *reinterpret_cast<const u32x4*>(q16 + (int64_t)qp * dp16 + 32 * s + 8 * (lane >> 4));
     }
@@ -547,7 +551,10 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
 #pragma unroll
           for (int b = 0; b < 4; ++b) acc[1][b] = mfma16<F16>(a[b], breg[1][i], acc[1][b]);
         };
-        if constexpr (KST == 2) {
+        if constexpr (KST == 4) {
+          kstep(h, 2 * st);        // k-steps 4 st + h and 4 st + 2 + h of the tile
+          kstep(2 + h, 2 * st + 1);
+        } else if constexpr (KST == 2) {
           kstep(h, st);            // k-step 2 st + h of the tile
         } else if ((st & 1) == h) {
           kstep(0, st >> 1);       // k-step st, of this wave's parity

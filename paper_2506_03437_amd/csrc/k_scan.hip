@@ -611,7 +611,7 @@ struct PackedList {
 // stop point are discarded.  Then predict the next window.
 template <class List>
 __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restrict__ mq, int k, int kk, int aps,
-                             int ip, int chunk_tiles, int wmax, double tau_r, double tau_rho,
+                             int ip, int chunk_tiles, int wmax, int wscale, double tau_r, double tau_rho,
                              const int32_t* __restrict__ cand, const float* __restrict__ hcand,
                              const int32_t* __restrict__ psize, const double* __restrict__ qn2,
                              const float* __restrict__ pk, const int64_t* __restrict__ pi,
@@ -679,7 +679,11 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
   const bool done = stop || committed >= Mq;
   int wn = 0;
   if (!done) {
-    if (aps && L.id(k - 1) >= 0) wn = predict_window(md, hq, Mq, committed, tau_r, table);
+    // the prediction assumes rho stays where it is; rho only shrinks as
+    // more partitions are committed, so a query usually needs more - the
+    // window is scaled by wscale percent (speculation costs scans, not
+    // results: partitions past the stop point are discarded)
+    if (aps && L.id(k - 1) >= 0) wn = (predict_window(md, hq, Mq, committed, tau_r, table) * wscale + 99) / 100;
     else wn = 2 * w;
     if (wn < 1) wn = 1;
     if (wn > wmax) wn = wmax;
@@ -696,6 +700,7 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
 
 #define QK_COMMIT_PARAMS                                                                                          \
   int64_t nq, int M, const int32_t *__restrict__ mq, int k, int kk, int aps, int ip, int chunk_tiles, int wmax,  \
+      int wscale,                                                                                                 \
       double tau_r, double tau_rho, const int32_t *__restrict__ cand, const float *__restrict__ hcand,            \
       const int32_t *__restrict__ psize, const double *__restrict__ qn2, const float *__restrict__ pk,            \
       const int64_t *__restrict__ pi, const double *__restrict__ table, int32_t *__restrict__ st_m,              \
@@ -704,7 +709,7 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
       double *__restrict__ st_V, double *__restrict__ st_vsum, double *__restrict__ st_r, float *__restrict__ rk, \
       int64_t *__restrict__ ri
 #define QK_COMMIT_ARGS                                                                                        \
-  M, mq, k, kk, aps, ip, chunk_tiles, wmax, tau_r, tau_rho, cand, hcand, psize, qn2, pk, pi, table, st_m, st_w, \
+  M, mq, k, kk, aps, ip, chunk_tiles, wmax, wscale, tau_r, tau_rho, cand, hcand, psize, qn2, pk, pi, table, st_m, st_w, \
       st_done, st_weff, st_item, st_rho, st_p0, st_V, st_vsum, st_r, rk, ri
 
 // Lists longer than a wave: one 64-thread block per query, lists in LDS.
@@ -733,7 +738,8 @@ void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const dou
   if (a.nq <= 0) return;
 #define QK_COMMIT(KERNEL, GRID, BLOCK)                                                                        \
   hipLaunchKernelGGL(KERNEL, dim3((unsigned)(GRID)), dim3(BLOCK), 0, s, a.nq, a.M, ws.mq, a.k, a.kk, a.aps,    \
-                     a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.tau_r, a.tau_rho, ws.cand, ws.h,  \
+                     a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.wscale, a.tau_r, a.tau_rho, ws.cand,     \
+                     ws.h,                                                                                      \
                      st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_weff,        \
                      ws.st_item, ws.st_rho, ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri)
   if (a.kk <= WAVE && a.slot_ids) QK_COMMIT(k_commit64<PackedList>, (a.nq + 3) / 4, 256);

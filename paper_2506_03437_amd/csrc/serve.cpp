@@ -120,6 +120,7 @@ struct quake_server {
     a.aps = job.aps;
     a.chunk_tiles = chunk_tiles;
     a.wmax = job.wmax;
+    a.wscale = idx->tune.window_scale > 0 ? idx->tune.window_scale : 100;
     a.slot_ids = job.batched && st().tiles * qk::TILE < (int64_t{1} << 31) ? 1 : 0;
     a.metric = idx->metric;
     a.dim = idx->d;

@@ -92,7 +92,7 @@ class SearchParams(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk_tiles", ctypes.c_int32), ("first_window", ctypes.c_int32), ("max_window", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("max_items", ctypes.c_int64), ("rounds_per_sync", ctypes.c_int32),
-                ("no_graph", ctypes.c_int32)]
+                ("no_graph", ctypes.c_int32), ("window_scale", ctypes.c_int32)]
 
 
 class ServerParams(ctypes.Structure):
@@ -300,8 +300,9 @@ def quake_profile(handle: int, enable: bool = True, reset: bool = False):
 
 
 def quake_set_tuning(handle: int, chunk_tiles=0, first_window=0, max_window=0, max_items=0, blocks_per_cu=0,
-                     rounds_per_sync=0, no_graph=0):
-    t = Tuning(chunk_tiles, first_window, max_window, blocks_per_cu, max_items, rounds_per_sync, no_graph)
+                     rounds_per_sync=0, no_graph=0, window_scale=0):
+    t = Tuning(chunk_tiles, first_window, max_window, blocks_per_cu, max_items, rounds_per_sync, no_graph,
+               window_scale)
     _check(load_library().quake_set_tuning(handle, ctypes.byref(t)))
 
 
