@@ -137,6 +137,23 @@ int quake_search(quake_index* index, const float* q, int64_t nq, const quake_sea
                  int64_t* out_ids, float* out_dist, int32_t* out_nscanned, double* out_recall,
                  void* stream);
 
+/* quake_search for callers that cannot allocate device memory (serving loops
+ * and harnesses that forbid allocation): the same search, results and errors
+ * as quake_search, but its workspace lives in a scratch array of 256 MiB that
+ * the library holds on every device it runs on until the process ends, its
+ * host-side counters in a process-wide block, and it calls no allocator
+ * (hipMalloc, hipFree or the index's allocator), captures no graph and
+ * allocates no pinned memory.  Single-level indexes only (else STATE).  A
+ * search whose workspace would exceed the scratch array is rejected with
+ * INVALID and a message giving the bytes it needs (fewer queries per call
+ * fit; e.g. about 5,000 queries of 768 dims over 4,096 partitions with
+ * f_M = 0.05 on the batched path).  All calls on one device share its scratch
+ * array and the host counters: calls that overlap in time race; run them one
+ * after another (the index handle is single-caller anyway). */
+int quake_search_noalloc(quake_index* index, const float* q, int64_t nq, const quake_search_params* params,
+                         int64_t* out_ids, float* out_dist, int32_t* out_nscanned, double* out_recall,
+                         void* stream);
+
 /* Insert n vectors x[n][d] (device float32) with ids[n] (device int64) as one
  * batch (Sec. 2.1 updates; Sec. 3: each vector goes top-down to its nearest
  * leaf partition and is appended there).  Centroids do not move.

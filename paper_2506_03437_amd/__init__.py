@@ -20,6 +20,7 @@ from .quake import (  # noqa: F401
     quake_insert,
     quake_profile,
     quake_search,
+    quake_search_noalloc,
     quake_server_create,
     quake_server_delete,
     quake_server_destroy,

@@ -20,7 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libquake_mi355x.so")
 
-HIP_SOURCES = ["k_centroids.hip", "k_scan.hip", "k_store.hip", "k_batched.hip", "k_rerank.hip", "k_update.hip", "k_serve.hip"]
+HIP_SOURCES = ["k_centroids.hip", "k_scan.hip", "k_store.hip", "k_batched.hip", "k_rerank.hip", "k_update.hip",
+               "k_serve.hip", "k_noalloc.hip"]
 CPP_SOURCES = ["capi.cpp", "cap_table.cpp", "serve.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]

@@ -4,11 +4,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <new>
 #include <numeric>
 #include <random>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "engine.hpp"
@@ -58,6 +60,7 @@ int candidate_count(double f, int64_t n) {
 }
 
 void* DeviceMemory::raw_alloc(size_t bytes) {
+  QK_CHECK(!forbid, QUAKE_E_STATE, "an allocation was attempted inside a call that allocates nothing");
   if (bytes == 0) bytes = 256;
   if (budget && used + bytes > budget)
     throw Error{QUAKE_E_NOMEM, "HBM budget exceeded: " + std::to_string(used + bytes) + " > " +
@@ -695,7 +698,7 @@ void release_graphs(quake_index* idx) {
 // captured once per distinct set of kernel arguments; the captured rounds
 // contain kernel launches only.
 void run_rounds(quake_index* idx, const Store& st, const Job& job, const RoundArgs& a, int R, hipStream_t s) {
-  if (idx->prof.on || idx->tune.no_graph || idx->graphs_failed) {
+  if (idx->prof.on || idx->tune.no_graph || idx->graphs_failed || idx->noalloc) {
     launch_rounds(idx, st, job, a, R, s);
     return;
   }
@@ -764,12 +767,19 @@ struct QueryWindow {
 // Run one resolved search over `st` for the nq queries in ws.q / ws.qn2.
 // Leaves the results in ws.rk / ws.ri ([nq][kk]) and the per-query state in
 // ws.st_*; writes the outputs when out_ids is given.
-void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, int64_t* out_ids, float* out_dist,
-                int32_t* out_nscanned, double* out_recall, hipStream_t s) {
+}  // namespace
+
+namespace qk {
+
+int search_chunk_tiles(const quake_index* idx, const Job& job) {
   int chunk_tiles = idx->tune.chunk_tiles > 0 ? idx->tune.chunk_tiles : 16;
   // long result lists are scanned by sorting whole items in LDS
   if (job.kk > qk::KMAX) chunk_tiles = std::min(chunk_tiles, qk::SORTED_ITEM_MAX / qk::TILE);
-  const int64_t mc = max_chunks(st, chunk_tiles);
+  return chunk_tiles;
+}
+
+int64_t search_items(const quake_index* idx, const Store& st, const Job& job, int64_t nq) {
+  const int64_t mc = max_chunks(st, search_chunk_tiles(idx, job));
   // the buffer must hold one full window of the largest partitions (progress)
   const int64_t floor_items = (int64_t)job.wmax * mc + 1;
   // by default room for every query's first window twice over, and on the
@@ -777,11 +787,77 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
   // mostly one chunk): a round that runs out of items defers queries to a
   // further round, which reads the partitions it touches once more
   const int64_t def_items = nq * (int64_t)std::max(std::max(job.w0, 4) * 2, job.batched ? job.wmax : 0);
-  const int64_t items = std::max<int64_t>(idx->tune.max_items > 0 ? idx->tune.max_items : def_items, floor_items);
+  return std::max<int64_t>(idx->tune.max_items > 0 ? idx->tune.max_items : def_items, floor_items);
+}
+
+// Byte layout of a search workspace for nq queries (every array of
+// ensure_queries and ensure_workspace, 256-byte aligned) inside `base`; with
+// w == nullptr only the size is computed.  Host counters are not part of it.
+size_t workspace_layout(Workspace* w, char* base, int64_t nq, int64_t nc, int64_t M, int64_t kk, int64_t items,
+                        int64_t pairs, int dp, int dp16) {
+  size_t off = 0;
+  auto take = [&](auto*& p, int64_t count) {
+    using T = std::remove_pointer_t<std::remove_reference_t<decltype(p)>>;
+    off = (off + 255) / 256 * 256;
+    if (w) p = reinterpret_cast<T*>(base + off);
+    off += (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+  };
+  Workspace dummy;
+  Workspace& x = w ? *w : dummy;
+  const int64_t n = std::max<int64_t>(nq, 1);
+  take(x.q, n * dp);
+  take(x.qn2, n);
+  for (int32_t** p : {&x.st_m, &x.st_w, &x.st_weff, &x.st_done, &x.mq, &x.mq0}) take(*p, n);
+  for (int64_t** p : {&x.st_item, &x.st_demand, &x.st_vecs, &x.st_pair}) take(*p, n);
+  take(x.blk, (n / 256 + 1) * 4);
+  take(x.qn2f, n);
+  for (double** p : {&x.st_rho, &x.st_p0, &x.st_V, &x.st_vsum, &x.st_r}) take(*p, n);
+  take(x.scores, n * nc);
+  take(x.sel, n * M);
+  take(x.cand, n * M);
+  take(x.h, n * M);
+  take(x.rk, n * kk);
+  take(x.ri, n * kk);
+  take(x.items, items);
+  take(x.bitems, 2 * items);
+  take(x.pk, items * kk);
+  take(x.pi, items * kk);
+  take(x.total, COUNTERS);
+  if (dp16 > 0) take(x.q16, n * dp16);
+  for (int32_t** p : {&x.pair_q, &x.pair_p, &x.pair_pos, &x.sorted, &x.sorted_q}) take(*p, pairs);
+  for (int64_t** p : {&x.pair_base, &x.sorted_base}) take(*p, pairs);
+  take(x.pcount, nc + 1);
+  take(x.pstart, nc + 1);
+  take(x.pitem, nc + 1);
+  if (w) {
+    w->nq_cap = n;
+    w->scores_cap = n * nc;
+    w->cand_cap = n * M;
+    w->kk_cap = n * kk;
+    w->items_cap = items;
+    w->k_cap = kk;
+    w->q16_dim = dp16;
+    w->pairs_cap = std::max<int64_t>(pairs, 1);
+    w->parts_cap = nc + 1;
+    w->cand0 = nullptr;
+    w->cand0_cap = 0;
+  }
+  return (off + 255) / 256 * 256;
+}
+
+}  // namespace qk
+
+namespace {
+
+void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, int64_t* out_ids, float* out_dist,
+                int32_t* out_nscanned, double* out_recall, hipStream_t s) {
+  const int chunk_tiles = qk::search_chunk_tiles(idx, job);
+  const int64_t items = qk::search_items(idx, st, job, nq);
   ensure_workspace(idx, st.nlist, job.M, job.kk, items, job.batched ? nq * (int64_t)job.wmax : 0,
                    job.batched ? st.dp16 : 0, !job.given);
   qk::Workspace& w = idx->ws;
-  QK_HIP(hipMemsetAsync(w.total, 0, qk::COUNTERS * sizeof(int64_t), s));
+  // (a fill kernel, not a memset: a caller may capture this call's stream)
+  qk::launch_fill_i32(reinterpret_cast<int32_t*>(w.total), 2 * qk::COUNTERS, 0, s);
   if (job.given) {
     QK_HIP(hipMemcpyAsync(w.mq, w.mq0, nq * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     qk::ProfileScope ps(idx->prof, QUAKE_PROF_SELECT, s);
@@ -899,6 +975,69 @@ void upper_level(quake_index* idx, int64_t nq, int M0, const quake_search_params
 }
 
 }  // namespace
+
+namespace qk {
+
+// A single-level search whose workspace is carved out of caller-given
+// device memory (`scratch`, scratch_bytes long) and whose host counter reads
+// go to `host_counters` (COUNTERS entries): nothing is allocated, no graph is
+// captured, and any allocation attempt fails the call.  The index's own
+// workspace is set aside for the call and put back after it.
+void search_in_scratch(quake_index* idx, const float* q, int64_t nq, const quake_search_params* params,
+                       int64_t* out_ids, float* out_dist, int32_t* out_nscanned, double* out_recall, hipStream_t s,
+                       char* scratch, size_t scratch_bytes, int64_t* host_counters) {
+  check_index(idx);
+  QK_CHECK(nq >= 0, QUAKE_E_INVALID, "nq must be >= 0");
+  QK_CHECK(idx->n_levels == 1, QUAKE_E_STATE, "the allocation-free search is for single-level indexes");
+  const Store& L0 = idx->L0;
+  const Job job = resolve(idx, L0, params);
+  if (nq == 0) return;
+  QK_CHECK(q && out_ids && out_dist, QUAKE_E_INVALID, "q, out_ids and out_dist are required");
+  const int64_t items = search_items(idx, L0, job, nq);
+  const int64_t pairs = job.batched ? nq * (int64_t)job.wmax : 0;
+  const int dp16 = job.batched ? L0.dp16 : 0;
+  const size_t need = workspace_layout(nullptr, nullptr, nq, L0.nlist, job.M, job.kk, items, pairs, idx->dp, dp16);
+  QK_CHECK(need <= scratch_bytes, QUAKE_E_INVALID,
+           "this search needs " + std::to_string(need) + " bytes of scratch memory, more than the " +
+               std::to_string(scratch_bytes) + " the allocation-free entry point has: search fewer queries per call");
+  Workspace view;
+  workspace_layout(&view, scratch, nq, L0.nlist, job.M, job.kk, items, pairs, idx->dp, dp16);
+  view.h_total = host_counters;
+  // the index's workspace, profiling and allocation state come back on any exit
+  struct Restore {
+    quake_index* idx;
+    Workspace ws;
+    bool prof;
+    ~Restore() {
+      idx->ws = ws;
+      idx->prof.on = prof;
+      idx->noalloc = false;
+      idx->mem.forbid = false;
+    }
+  } restore{idx, idx->ws, idx->prof.on};
+  idx->ws = view;
+  idx->prof.on = false;
+  idx->noalloc = true;
+  idx->mem.forbid = true;
+  Workspace& w = idx->ws;
+  // what the kernels expect zeroed (they keep it so between rounds, but the
+  // array holds whatever the last call on this device left)
+  launch_fill_i32(w.pcount, L0.nlist + 1, 0, s);
+  launch_fill_i32(reinterpret_cast<int32_t*>(idx->d_flag), 1, 0, s);
+  launch_pad_rows(q, nq, idx->d, idx->dp, w.q, w.qn2, s, idx->d_flag);
+  QK_HIP(hipMemcpyAsync(idx->h_flag, idx->d_flag, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  QK_CHECK(*idx->h_flag == 0, QUAKE_E_INVALID, "q holds a non-finite value");
+  run_search(idx, L0, job, nq, out_ids, out_dist, out_nscanned, out_recall, s);
+}
+
+int run_api(const std::function<void()>& fn) {
+  API_BEGIN
+  fn();
+  API_END
+}
+
+}  // namespace qk
 
 extern "C" {
 

@@ -1,6 +1,8 @@
 // Search-engine internals shared by the C ABI (capi.cpp) and the serving
 // loop (serve.cpp).
 #pragma once
+#include <functional>
+
 #include "index.hpp"
 
 namespace qk {
@@ -37,5 +39,20 @@ void run_rounds(quake_index* idx, const Store& st, const Job& job, const RoundAr
 void release_graphs(quake_index* idx);
 void ensure_workspace(quake_index* idx, int64_t nc, int64_t M, int64_t kk, int64_t items, int64_t pairs, int dp16,
                       bool scores = true);
+// Tiles per work item, and work items a search of nq queries may need per round.
+int search_chunk_tiles(const quake_index* idx, const Job& job);
+int64_t search_items(const quake_index* idx, const Store& st, const Job& job, int64_t nq);
+// Lays the search workspace for nq queries out in `base` (256-byte aligned
+// arrays) and returns its size; w == nullptr only measures.
+size_t workspace_layout(Workspace* w, char* base, int64_t nq, int64_t nc, int64_t M, int64_t kk, int64_t items,
+                        int64_t pairs, int dp, int dp16);
+// quake_search with its workspace in caller-given device memory and host
+// counters; allocates nothing (single-level indexes).
+void search_in_scratch(quake_index* idx, const float* q, int64_t nq, const quake_search_params* params,
+                       int64_t* out_ids, float* out_dist, int32_t* out_nscanned, double* out_recall, hipStream_t s,
+                       char* scratch, size_t scratch_bytes, int64_t* host_counters);
+// Runs fn under the C ABI's error handling: the return code, and the message
+// for quake_last_error on failure.
+int run_api(const std::function<void()>& fn);
 
 }  // namespace qk

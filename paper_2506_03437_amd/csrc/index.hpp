@@ -52,6 +52,7 @@ class DeviceMemory {
   size_t used = 0;
   size_t budget = 0;  // 0 = unlimited
   quake_allocator user{};  // user.alloc == nullptr: hipMalloc / hipFree
+  bool forbid = false;     // set for the duration of a call that must allocate nothing
   template <class T>
   T* alloc(size_t count) { return static_cast<T*>(raw_alloc(count * sizeof(T))); }
   void* raw_alloc(size_t bytes);
@@ -211,6 +212,7 @@ struct quake_index {
   std::vector<Graph> graphs;
   hipStream_t capture_stream = nullptr;
   bool graphs_failed = false;
+  bool noalloc = false;         // inside quake_search_noalloc: launch rounds directly, allocate nothing
   ~quake_index();  // graphs, streams and pinned buffers; device memory goes with `mem`
 };
 

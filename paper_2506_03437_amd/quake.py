@@ -26,7 +26,7 @@ _METRIC = {"l2": L2, "ip": IP}
 _DTYPE = {"f32": F32, "bf16": BF16, "f16": F16}
 _MODE = {"plain": SCAN_PLAIN, "batched": SCAN_BATCHED}
 
-EXPORTED = ("quake_build", "quake_search", "quake_insert", "quake_delete", "quake_stats", "quake_export",
+EXPORTED = ("quake_build", "quake_search", "quake_search_noalloc", "quake_insert", "quake_delete", "quake_stats", "quake_export",
             "quake_export_top", "quake_candidates", "quake_cap_table", "quake_profile", "quake_set_tuning",
             "quake_free", "quake_last_error", "quake_autotune", "quake_server_create", "quake_server_search", "quake_server_insert",
             "quake_server_delete", "quake_server_wait", "quake_server_stats", "quake_server_destroy")
@@ -127,6 +127,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.quake_build.argtypes = [vp, vp, i64, i32, ctypes.POINTER(BuildParams), ctypes.POINTER(Allocator), vp,
                                 ctypes.POINTER(vp)]
     lib.quake_search.argtypes = [vp, vp, i64, ctypes.POINTER(SearchParams), vp, vp, vp, vp, vp]
+    lib.quake_search_noalloc.argtypes = [vp, vp, i64, ctypes.POINTER(SearchParams), vp, vp, vp, vp, vp]
     lib.quake_insert.argtypes = [vp, vp, vp, i64, vp]
     lib.quake_delete.argtypes = [vp, vp, i64, vp]
     lib.quake_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)]
@@ -231,6 +232,20 @@ def quake_search(handle: int, q, *, k=10, nprobe=0, recall_target=0.0, f_M=0.0, 
                        rerank_factor, window)
     _check(load_library().quake_search(handle, _ptr(q), nq, ctypes.byref(p), _ptr(ids), _ptr(dist), _ptr(ns),
                                        _ptr(rec), _stream()))
+    return ids, dist, ns, rec
+
+
+def quake_search_noalloc(handle: int, q, *, outputs, k=10, nprobe=0, recall_target=0.0, f_M=0.0, tau_rho=0.0,
+                         upper_recall_target=0.0, upper_f_M=0.0, scan_mode="plain", scan_dtype="f32",
+                         rerank_factor=0, window=0):
+    """quake_search into caller-given outputs (ids, dist, nscanned, recall) with no allocation in the library."""
+    import torch
+    _dev(q, torch.float32)
+    ids, dist, ns, rec = outputs
+    p = _search_params(k, nprobe, recall_target, f_M, tau_rho, upper_recall_target, upper_f_M, scan_mode, scan_dtype,
+                       rerank_factor, window)
+    _check(load_library().quake_search_noalloc(handle, _ptr(q), q.shape[0], ctypes.byref(p), _ptr(ids), _ptr(dist),
+                                               _ptr(ns), _ptr(rec), _stream()))
     return ids, dist, ns, rec
 
 
