@@ -16,6 +16,10 @@ It is a plain, slow, FP64 NumPy restatement of what the search computes:
 * ``updates`` batched insert / delete replay (Sec. 2.1 and Sec. 3)
 * ``kmeans``  Lloyd iterations used only to check the device build's
               objective (Sec. 3; parity unpinned for the centroids)
+* ``maintenance`` the cost model, split / delete deltas, the estimate ->
+              verify -> commit workflow and the split, refinement and delete
+              actions on vectors (Sec. 4, Eqs. CostPartition, CostTotal,
+              DeltaC, delta_split_exact, delta_merge_exact, delta_split_est)
 
 It shares no code, headers, tables or constants with the device path.
 """
