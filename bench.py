@@ -10,6 +10,14 @@ plus N(0, 0.1^2) noise, renormalised), k = 10, adaptive partition scanning
 with f_M = 0.05.  The paper's datasets are not available; this seeded
 mixture stands in for them.
 
+`--workload two-level-50m-d128-f16`: 50M x 128 rows drawn around 50,000
+generator-defined leaves (Zipf(1.1) leaf sizes), the leaves' centres as the
+level-0 centroids (each row stored in its nearest), 64 top partitions over
+them, L2, FP16 copy, 65,536 queries per step, f_M = 0.015 (750 level-0
+candidates from the level-1 search at recall target 0.99 over 25% of the
+top partitions).  The per-level split times the level-1 search with the
+level-0 candidate geometry (quake_candidates) on its own.
+
 Recall is measured against FP64 exact ground truth (the CPU oracle) on a
 seeded 1,000-query subsample.  Both paths are run at recall targets 0.8,
 0.9 and 0.95 (recall and the BF16 - FP32 gap reported per target); the
@@ -130,24 +138,40 @@ def cpu_baseline_leg(X, Q, sample_rows, idx, workload, tau, seconds, gt_seconds,
     from oracle import aps as oaps
     from oracle import ivf as oivf
 
+    from oracle import twolevel as otl
+
     C, eids, epart = idx.export()
     C = C.cpu().numpy()
     assign = np.empty(X.shape[0], dtype=np.int64)
     assign[eids.cpu().numpy()] = epart.cpu().numpy()
     ps = oivf.PartitionedSet(X, np.arange(X.shape[0]), assign, C)
     table = oaps.CapTable(X.shape[1])
-    params = oaps.APSParams(k=10, recall_target=tau, f_M=workload.f_M, metric=workload.metric)
+    if workload.leaves is not None:
+        from paper_2506_03437_amd import quake_export_top
+        C1, top_of = quake_export_top(idx.handle, X.shape[1], workload.nlist_top)
+        tl = otl.TwoLevelSet(ps, top_of.cpu().numpy().astype(np.int64), C1.cpu().numpy())
+        tparams = otl.TwoLevelParams(k=10, recall_target=tau, f_M=workload.f_M, metric=workload.metric)
+
+        def one(q):
+            otl.two_level_search_one(tl, q, tparams, table)
+        what = "two-level adaptive partition scanning (level 1: target 0.99, f_M 0.25)"
+    else:
+        params = oaps.APSParams(k=10, recall_target=tau, f_M=workload.f_M, metric=workload.metric)
+
+        def one(q):
+            oaps.aps_search_one(ps, q, params, table)
+        what = "adaptive partition scanning"
     Qs = Q[sample_rows]
     cores = len(os.sched_getaffinity(0))
     done = 0
     t0 = time.perf_counter()
     while done < Qs.shape[0] and time.perf_counter() - t0 < seconds:
-        oaps.aps_search_one(ps, Qs[done], params, table)
+        one(Qs[done])
         done += 1
     t_aps = time.perf_counter() - t0
     base = {
         "value": done / t_aps, "unit": "queries/s", "cores": cores, "kind": "oracle",
-        "sample": (f"{done} of the workload's queries, FP64 NumPy adaptive partition scanning "
+        "sample": (f"{done} of the workload's queries, FP64 NumPy {what} "
                    f"(recall target {tau}, the batched GPU leg's) over the device index's partitioning, "
                    f"{t_aps:.1f} s"),
     }
@@ -295,24 +319,39 @@ def main():
     from paper_2506_03437_amd import Index
 
     w = synth.get_workload(args.workload)
+    two_level = w.leaves is not None
     threads = host_threads()
     t0 = time.perf_counter()
-    X = synth.database(w.spec, threads=threads)
-    Q = synth.queries(w.spec, w.nq, noise_std=w.query_noise, threads=threads)
+    if two_level:
+        centres, _, X = synth.leaf_spec_database(w.leaves, threads=threads)
+        Q = synth.leaf_spec_queries(w.leaves, X, w.nq, w.query_noise)
+        Qtune_h = synth.leaf_spec_queries(w.leaves, X, w.nq, w.query_noise, stream_chunk=1)
+    else:
+        X = synth.database(w.spec, threads=threads)
+        Q = synth.queries(w.spec, w.nq, noise_std=w.query_noise, threads=threads)
+        Qtune_h = synth.queries(w.spec, w.nq, noise_std=w.query_noise, stream_chunk=1, threads=threads)
     log(f"generated {X.shape} database and {Q.shape} queries in {time.perf_counter() - t0:.1f} s "
         f"({threads} threads)")
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
     Xd = torch.from_numpy(X).to(dev)
-    idx = Index(Xd, metric=w.metric, nlist=w.nlist, storage=w.storage, kmeans_iters=10, seed=1)
+    if two_level:
+        # level 0: the generator's leaf centres (each row goes to its nearest);
+        # level 1: k-means of those centres into nlist_top partitions
+        idx = Index(Xd, metric=w.metric, nlist=w.nlist, storage=w.storage, n_levels=2, nlist_top=w.nlist_top,
+                    centroids=torch.from_numpy(centres).to(dev), kmeans_iters=10, seed=1)
+    else:
+        idx = Index(Xd, metric=w.metric, nlist=w.nlist, storage=w.storage, kmeans_iters=10, seed=1)
     del Xd
     torch.cuda.synchronize()
-    log(f"built {w.nlist} partitions in {time.perf_counter() - t0:.1f} s "
-        f"({idx.stats()[2] / 1e9:.1f} GB of index memory)")
+    log(f"built {w.nlist} partitions{f' under {w.nlist_top}' if two_level else ''} in "
+        f"{time.perf_counter() - t0:.1f} s ({idx.stats()[2] / 1e9:.1f} GB of index memory)")
     Qd = torch.from_numpy(Q).to(dev)
-    Qtune = torch.from_numpy(synth.queries(w.spec, w.nq, noise_std=w.query_noise, stream_chunk=1,
-                                           threads=threads)).to(dev)
+    Qtune = torch.from_numpy(Qtune_h).to(dev)
+    del Qtune_h
+    # the upper level of a two-level index: recall target 0.99 over 25% of its partitions
+    upper = dict(upper_recall_target=0.99, upper_f_M=0.25) if two_level else {}
     rng = np.random.default_rng(7)
     sample_rows = np.sort(rng.choice(w.nq, size=min(args.recall_sample, w.nq), replace=False))
 
@@ -324,14 +363,16 @@ def main():
         gt_seconds = time.perf_counter() - t0
         log(f"oracle exact k-NN for {sample_rows.size} queries: {gt_seconds:.1f} s")
 
+    bkey = f"batched_{w.storage}"
     all_paths = {
         "plain_fp32": dict(scan_mode="plain", scan_dtype="f32"),
-        "batched_bf16": dict(scan_mode="batched", scan_dtype=w.storage, rerank_factor=args.rerank_factor),
+        bkey: dict(scan_mode="batched", scan_dtype=w.storage, rerank_factor=args.rerank_factor),
     }
-    paths = {p: all_paths[p] for p in args.paths.split(",") if p}
+    paths = {(bkey if p.startswith("batched") else p): None for p in args.paths.split(",") if p}
+    paths = {p: all_paths[p] for p in paths}
 
     def run(path, tau):
-        return idx.search(Qd, k=w.k, recall_target=tau, f_M=w.f_M, **paths[path])
+        return idx.search(Qd, k=w.k, recall_target=tau, f_M=w.f_M, **upper, **paths[path])
 
     def recall_of(ids):
         found = ids.cpu().numpy()[sample_rows]
@@ -374,7 +415,8 @@ def main():
             idx.set_tuning()
         else:
             # scheduling knobs (never the results) tuned on a separate seeded batch
-            knobs, tuned_ms = idx.autotune(Qtune, reps=2, k=w.k, recall_target=tau, f_M=w.f_M, **paths[path])
+            knobs, tuned_ms = idx.autotune(Qtune, reps=2, k=w.k, recall_target=tau, f_M=w.f_M, **upper,
+                                           **paths[path])
             log(f"{path}: autotuned {knobs} ({tuned_ms:.2f} ms per search on the tuning batch)")
         for _ in range(min(args.warmup, 1) if path.startswith("plain") else args.warmup):
             run(path, tau)
@@ -395,6 +437,20 @@ def main():
         torch.cuda.synchronize()
         elapsed_prof = time.perf_counter() - t0
         prof = idx.profile(enable=False, reset=True)
+        level_split = None
+        if two_level:
+            # the level-1 search and the level-0 candidate geometry alone (what
+            # quake_candidates runs), timed over the same steps; level 0's
+            # scan rounds and rerank are the rest of a step
+            for _ in range(steps):
+                idx.candidates(Qd, w.f_M, **upper)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                idx.candidates(Qd, w.f_M, **upper)
+            torch.cuda.synchronize()
+            up_ms = (time.perf_counter() - t0) * 1e3 / steps
+            level_split = {"level1_and_candidates_ms": up_ms, "level0_ms": elapsed * 1e3 / steps - up_ms}
         ids, _, ns, _ = out
         rec = recall_of(ids) if truth is not None else None
         launches, ms, nbytes, flops = prof["scan"]
@@ -415,6 +471,8 @@ def main():
             "kernels_ms_per_step": {k: v[1] / steps for k, v in prof.items() if v[0]},
             "tuning": knobs,
         }
+        if level_split:
+            res["per_level_ms_per_step"] = level_split
         if path.startswith("batched"):
             res["scan_set_bytes_per_launch"] = prof["scan_sets"][2] / max(launches, 1)
             res["scan_bytes_per_step"] = nbytes / steps
@@ -428,12 +486,12 @@ def main():
     results = {}
     for p in paths:
         results[p] = measure(p, min(args.plain_steps, args.steps) if p.startswith("plain") else args.steps)
-    batched = results.get("batched_bf16")
+    batched = results.get(bkey)
     plain = results.get("plain_fp32")
 
     cpu = None
     if not args.no_cpu_baseline and truth is not None:
-        cpu = cpu_baseline_leg(X, Q, sample_rows, idx, w, chosen.get("batched_bf16", chosen[next(iter(paths))]),
+        cpu = cpu_baseline_leg(X, Q, sample_rows, idx, w, chosen.get(bkey, chosen[next(iter(paths))]),
                                args.cpu_seconds, gt_seconds, threads)
     serving = None
     if args.serving_requests > 0 and batched is not None:
@@ -469,9 +527,10 @@ def main():
     if len(ladder) == 2:
         for tau in REPORT_TARGETS:
             a = [e for e in ladder["plain_fp32"] if e["recall_target"] == tau]
-            b = [e for e in ladder["batched_bf16"] if e["recall_target"] == tau]
+            b = [e for e in ladder[bkey] if e["recall_target"] == tau]
             if a and b:
-                gap.append({"recall_target": tau, "fp32": a[0]["recall_at_10"], "bf16_rerank": b[0]["recall_at_10"],
+                gap.append({"recall_target": tau, "fp32": a[0]["recall_at_10"],
+                            f"{w.storage}_rerank": b[0]["recall_at_10"],
                             "gap": b[0]["recall_at_10"] - a[0]["recall_at_10"]})
     head = batched or plain
     line = {
@@ -485,18 +544,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if batched else "f32",
+        "dtype": w.storage if batched else "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.spec.n, "d": w.spec.d, "nlist": w.nlist, "metric": w.metric,
                    "queries_per_step": w.nq, "k": w.k, "recall_target": head["recall_target"], "f_M": w.f_M,
-                   "path": f"batched BF16 MFMA scan + FP32 rerank of {args.rerank_factor}k candidates, "
-                           "adaptive partition scanning"},
+                   "path": f"batched {w.storage.upper()} MFMA scan + FP32 rerank of {args.rerank_factor}k "
+                           "candidates, adaptive partition scanning"
+                           + (f"; two levels ({w.nlist_top} top partitions, level-1 target 0.99 over 25%)"
+                              if two_level else "")},
         "recall_at_10": head["recall_at_10"],
         "speedup_vs_plain_fp32": batched["qps"] / plain["qps"] if batched and plain else None,
         "roofline": roof,
         "recall_by_target": ladder,
-        "recall_gap_bf16_minus_fp32": gap,
-        "batched_bf16": batched,
+        f"recall_gap_{w.storage}_minus_fp32": gap,
+        bkey: batched,
         "plain_fp32": plain,
         "serving": serving,
         "cpu_baseline": cpu,

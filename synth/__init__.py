@@ -15,6 +15,7 @@ from .mixture import (  # noqa: F401
     query_rows,
     queries,
     leaf_spec_database,
+    leaf_spec_queries,
 )
 from .trace import TraceSpec, serving_trace  # noqa: F401
 from .workloads import WORKLOADS, Workload, get_workload  # noqa: F401

@@ -58,7 +58,7 @@ WORKLOADS: Dict[str, Workload] = {
         spec=MixtureSpec(key=4, n=50_000_000, d=128, n_components=1000, zipf_s=1.1),
         nlist=50_000, metric="l2", nq=65_536, k=10, recall_target=0.9, f_M=0.015,
         storage="f16", leaves=LeafSpec(MixtureSpec(key=4, n=50_000_000, d=128, n_components=1000, zipf_s=1.1), 50_000),
-        nlist_top=64),
+        nlist_top=64, query_noise=0.05),
     # Serving: 10M x 768 BF16 start, skewed drifting queries, 1% updates per step.
     "serving-10m-d768-bf16": Workload(
         name="serving-10m-d768-bf16",

@@ -155,3 +155,17 @@ def check_aps(X, Q, ps, gi, gv, ns, rec, order, h, metric, f_M, tau_r, k=10, row
             assert abs(rec[i] - res.steps[-1].recall) < 1e-4, f"query {i}: recall estimate {rec[i]} vs {res.steps[-1].recall}"
     assert ordered >= 0.98 * rows.size
     assert margin <= 0.01 * rows.size, f"{margin} queries decided within the margin"
+
+
+def level1_set_explained(q, C0, dev_set, r1, tau1, metric="l2"):
+    """A device level-0 candidate set that differs from the oracle's level-1
+    result must differ only in centroids tied (within 1e-5) with the M0-th
+    one, or the oracle's level-1 search must have decided within the margin."""
+    ref = r1.ids[r1.ids >= 0]
+    D = knn.distances(q[None], C0, metric)[0]
+    key = -D if metric == "ip" else D
+    kth = float(key[ref].max())
+    diff = set(dev_set) ^ set(ref.tolist())
+    if all(abs(float(key[j]) - kth) <= 1e-5 * max(abs(kth), 1e-30) for j in diff):
+        return True
+    return replay_margin(r1, tau1, 0.01, r1.m)

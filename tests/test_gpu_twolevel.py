@@ -57,19 +57,6 @@ def test_exact_upper_level_equals_single_level(two_level):
         parity.check_topk(Q[i], X, id_to_row, gi[i], gv[i], ri, rv, "l2", 10, f"query {i}")
 
 
-def _level1_set_explained(q, C0, dev_set, r1, tau1):
-    """A device level-0 candidate set that differs from the oracle's level-1
-    result must differ only in centroids tied (within 1e-5) with the M0-th
-    one, or the oracle's level-1 search must have decided within the margin."""
-    ref = r1.ids[r1.ids >= 0]
-    D = oknn.distances(q[None], C0, "l2")[0]
-    kth = float(D[ref].max())
-    diff = set(dev_set) ^ set(ref.tolist())
-    if all(abs(float(D[j]) - kth) <= 1e-5 * max(kth, 1e-30) for j in diff):
-        return True
-    return parity.replay_margin(r1, tau1, 0.01, r1.m)
-
-
 def test_paper_settings_follow_the_oracle(two_level):
     """Query by query, over the device's own candidate list (exported by
     quake_candidates from the device's level-1 search): the results are
@@ -99,7 +86,7 @@ def test_paper_settings_follow_the_oracle(two_level):
         parity.check_topk(Q[i], X, id_to_row, gi[i], gv[i], ri, rv, "l2", 10, f"query {i}")
         r1 = oaps.aps_search_one(tl.top, Q[i], upper, table)
         if set(dev.tolist()) != set(r1.ids[r1.ids >= 0].tolist()):
-            assert _level1_set_explained(Q[i], tl.leaves.C, dev.tolist(), r1, 0.99), f"query {i}: level-1 set"
+            assert parity.level1_set_explained(Q[i], tl.leaves.C, dev.tolist(), r1, 0.99), f"query {i}: level-1 set"
             set_margin += 1
         if not parity.check_candidate_order(Q[i], tl.leaves.C, 0.05, "l2", dev, hdev, cands=dev):
             set_margin += 1
