@@ -180,6 +180,88 @@ int quake_export(const quake_index* index, float* centroids, int64_t* ids, int32
  * centroid, top_of[nlist] (device int32). */
 int quake_export_top(const quake_index* index, float* top_centroids, int32_t* top_of, void* stream);
 
+/* ------------------------------------------------------------ maintenance
+ *
+ * Adaptive incremental maintenance (Sec. 4).  Stage 0 of the decision
+ * workflow (Sec. 4.2): every search, the serving loop included, adds one to
+ * the access count of each partition a query committed (a partition scanned
+ * speculatively past the stop point is not counted) and the number of
+ * queries to the window; insert routing and the autotuner's searches are not
+ * counted.  A_j = hits_j / window is the cost model's access frequency. */
+
+/* Access statistics of level `level` (0, or 1 on a two-level index):
+ * hits[nlist] (host int64, may be NULL) and *window (host, may be NULL);
+ * reset != 0 clears both afterwards. */
+int quake_access_stats(quake_index* index, int32_t level, int64_t* hits, int64_t* window, int32_t reset,
+                       void* stream);
+
+/* One decision of a maintenance pass: the estimate (Eq. delta_split_est, or
+ * the uniform-redistribution delete estimate), the verified delta with the
+ * actual sizes (Eqs. delta_split_exact / delta_merge_exact), and whether it
+ * was committed (verified < -tau). */
+typedef struct {
+  int32_t partition;   /* id before the pass */
+  int32_t action;      /* 0 split, 1 delete */
+  int32_t committed;
+  int32_t new_partition; /* split: the right child's id before deletes renumber; delete: -1 */
+  double estimate;
+  double verified;
+} quake_decision;
+
+typedef struct {
+  double tau;            /* commit threshold (>= 0), in the unit of lambda_cost */
+  double alpha;          /* access fraction each split child inherits, in (0, 1] */
+  int32_t refine_radius; /* r_f: partitions nearest to each split child refined with it (>= 0) */
+  int32_t refine_iters;  /* k-means passes of a refinement (0: no refinement) */
+  int32_t split_iters;   /* Lloyd steps of the 2-means split (>= 1) */
+  int32_t min_split_size;/* partitions with fewer live vectors are not split (>= 2) */
+  int64_t merge_below;   /* partitions with fewer live vectors are delete candidates (0: no deletes) */
+  int32_t lambda_points; /* >= 2 */
+  int32_t max_decisions; /* capacity of `decisions` */
+  const double* lambda_size; /* host [lambda_points], strictly ascending: scan sizes */
+  const double* lambda_cost; /* host [lambda_points]: profiled latency of scanning that many vectors */
+  const int64_t* hits;   /* host [nlist] access counts to use, or NULL: the index's own */
+  int64_t window;        /* queries behind `hits` (>= 1 with hits; ignored without) */
+  quake_decision* decisions; /* host [max_decisions] or NULL: the decisions, in the order taken */
+} quake_maintain_params;
+
+typedef struct {
+  int32_t decisions;     /* decisions taken (may exceed max_decisions; the rest are not written) */
+  int32_t splits;        /* committed splits */
+  int32_t deletes;       /* committed deletes */
+  int32_t pad;
+  int64_t nlist_before, nlist_after;
+  int64_t vectors_moved; /* vectors that changed partition (splits, refinement, deletes) */
+} quake_maintain_report;
+
+/* One maintenance pass over level 0 of a one-level index (Sec. 4.2, Stages
+ * 1-3), with lambda interpolated linearly between the profiled sizes
+ * (extended linearly past the ends) and the centroid overhead
+ * dO+/- = lambda(N +/- 1) - lambda(N):
+ *   1. estimate every partition's split; for each one below -tau, split it
+ *      by 2-means on the device (start: the vector farthest from the
+ *      centroid and the one farthest from that; inner product: spherical),
+ *      verify with the children's actual sizes and the same frequency
+ *      assumption (alpha A each), commit below -tau, otherwise keep the
+ *      partition as it was;
+ *   2. refine around each committed split: k-means passes seeded by the
+ *      current centroids over the two children and the refine_radius
+ *      partitions nearest to each child (Sec. 4.2, "Partition Refinement");
+ *   3. for every other partition below merge_below: estimate the delete with
+ *      its vectors and accesses spread evenly over its refine_radius nearest
+ *      partitions; below -tau, send each vector to its nearest remaining
+ *      centroid, verify with the actual receivers (frequency following the
+ *      vectors) and commit below -tau;
+ *   4. renumber the surviving partitions in their old order, and clear the
+ *      access statistics.
+ * Vectors that change partition move with all their copies; ids are kept.
+ * Decisions are taken in partition order, every estimate against the index
+ * as the earlier steps of the pass left it, with the centroid overhead taken
+ * at the partition count before the pass.  Errors: INVALID for bad
+ * parameters, STATE on a two-level index (not supported). */
+int quake_maintain(quake_index* index, const quake_maintain_params* params, quake_maintain_report* report,
+                   void* stream);
+
 /* Candidate order of Adaptive Partition Scanning for nq queries, without
  * scanning level 0: order[nq][M] (device int32, c_0 first, then ascending
  * bisector distance) and h[nq][M] (device float32, h[.][0] = 0), with

@@ -286,7 +286,10 @@ def maintain(X: np.ndarray, part: np.ndarray, C: np.ndarray, hits: np.ndarray, w
 
     X: rows (live vectors), part: their partitions, C: centroids [N, d],
     hits[j]: queries of the window that scanned j.  Returns (part', C',
-    decisions) with partitions renumbered after deletions.
+    decisions) with partitions renumbered after deletions.  The centroid
+    overhead terms are taken at the partition count before the pass; every
+    other quantity is read from the index as the earlier steps of the pass
+    left it (split estimates need only the partition's own statistics).
     """
     X = np.asarray(X, dtype=np.float64)
     part = np.asarray(part, dtype=np.int64).copy()
@@ -343,17 +346,17 @@ def maintain(X: np.ndarray, part: np.ndarray, C: np.ndarray, hits: np.ndarray, w
     deleted = []
     if prm.merge_below > 0:
         for j in range(N0):
-            if j in split_parts or not s0[j] < prm.merge_below:
+            rows = np.nonzero(part == j)[0]
+            sj = float(rows.size)
+            if j in split_parts or not sj < prm.merge_below:
                 continue
             alive = [p for p in range(C.shape[0]) if p != j and p not in deleted]
             if not alive:
                 continue
             rec = nearest_centroids(C, C[j], prm.refine_radius, exclude=[j] + deleted, metric=metric)
-            est = delta_merge_estimate(dO_minus, A0[j], s0[j], [(A[m], float((part == m).sum())) for m in rec], lam)
+            est = delta_merge_estimate(dO_minus, A0[j], sj, [(A[m], float((part == m).sum())) for m in rec], lam)
             if not est < -prm.tau:
                 continue
-            rows = np.nonzero(part == j)[0]
-            sj = float(rows.size)
             dest = nearest_among(X[rows], C, alive, metric) if rows.size else np.zeros(0, dtype=np.int64)
             recv = []
             for m in np.unique(dest):

@@ -9,6 +9,7 @@ from .quake import (  # noqa: F401
     QuakeError,
     Server,
     load_library,
+    quake_access_stats,
     quake_autotune,
     quake_build,
     quake_candidates,
@@ -18,6 +19,7 @@ from .quake import (  # noqa: F401
     quake_export_top,
     quake_free,
     quake_insert,
+    quake_maintain,
     quake_profile,
     quake_search,
     quake_search_noalloc,

@@ -336,6 +336,9 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
   st.d_size = idx->mem.alloc<int32_t>(N);
   st.d_cap = idx->mem.alloc<int32_t>(N);
   st.d_order = idx->mem.alloc<int32_t>(N);
+  st.d_hits = idx->mem.alloc<uint32_t>(std::max<int64_t>(N, 1));
+  QK_HIP(hipMemsetAsync(st.d_hits, 0, std::max<int64_t>(N, 1) * sizeof(uint32_t), s));
+  st.window = 0;
   upload_table(st, s);
   {
     Tmp<int64_t> d_slot(idx->mem, n);
@@ -401,6 +404,45 @@ void relocate(Store& st, int64_t p, int32_t cap, hipStream_t s) {
   st.used_tiles += cap / qk::TILE;
 }
 
+// Fill the holes (deleted slots, id -1) below the live count of every
+// partition p with which[p] set from the partition's live tail, so that its
+// first size - tomb slots hold its vectors; moved vectors keep their ids.
+void compact(quake_index* idx, Store& st, const std::vector<char>& which, hipStream_t s) {
+  std::vector<int64_t> src, dst, moved_ids;
+  for (int64_t p = 0; p < st.nlist; ++p) {
+    if (!which[p] || st.tomb[p] == 0) continue;
+    const int64_t base = st.off[p] * qk::TILE;
+    const int64_t size = st.size[p];
+    std::vector<int64_t> pid(size);
+    QK_HIP(hipMemcpyAsync(pid.data(), st.ids + base, size * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+    const int64_t keep = size - st.tomb[p];
+    int64_t hole = 0, tail = keep;
+    while (true) {
+      while (hole < keep && pid[hole] >= 0) ++hole;
+      while (tail < size && pid[tail] < 0) ++tail;
+      if (hole >= keep || tail >= size) break;
+      src.push_back(base + tail);
+      dst.push_back(base + hole);
+      moved_ids.push_back(pid[tail]);
+      ++hole;
+      ++tail;
+    }
+    st.size[p] = (int32_t)keep;
+    st.tomb[p] = 0;
+  }
+  if (!src.empty()) {
+    const int64_t m = (int64_t)src.size();
+    Tmp<int64_t> d_src(idx->mem, m), d_dst(idx->mem, m), d_ids(idx->mem, m);
+    QK_HIP(hipMemcpyAsync(d_src.p, src.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    QK_HIP(hipMemcpyAsync(d_dst.p, dst.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    QK_HIP(hipMemcpyAsync(d_ids.p, moved_ids.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    qk::launch_move_slots(st, d_src.p, d_dst.p, m, s);
+    qk::launch_map_update(idx->idmap, d_ids.p, d_dst.p, m, s);
+    QK_HIP(hipStreamSynchronize(s));
+  }
+}
+
 // ---------------------------------------------------------------- id map
 
 void map_rebuild(quake_index* idx, int64_t expect, hipStream_t s) {
@@ -460,6 +502,16 @@ void require_finite(quake_index* idx, const float* x, int64_t count, const char*
 }  // namespace
 
 namespace qk {
+
+void store_grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s) { grow_arena(idx, st, need, s); }
+void store_relocate(Store& st, int64_t p, int32_t cap, hipStream_t s) { relocate(st, p, cap, s); }
+void store_upload_table(Store& st, hipStream_t s) { upload_table(st, s); }
+void store_compact(quake_index* idx, Store& st, const std::vector<char>& which, hipStream_t s) {
+  compact(idx, st, which, s);
+}
+int store_fixed_point_bits(DeviceMemory& mem, const float* x, int64_t n, int dp, hipStream_t s) {
+  return fixed_point_bits(mem, x, n, dp, s);
+}
 
 int64_t max_chunks(const Store& st, int chunk_tiles) {
   int64_t mx = 1;
@@ -670,7 +722,7 @@ std::vector<uint64_t> graph_key(const quake_index* idx, const Store& st, const J
   std::vector<uint64_t> k = {
       (uint64_t)R, (uint64_t)job.batched, (uint64_t)job.dtype16, (uint64_t)a.nq, (uint64_t)a.M, (uint64_t)a.k,
       (uint64_t)a.kk, (uint64_t)a.aps, (uint64_t)a.chunk_tiles, (uint64_t)a.wmax, (uint64_t)a.wscale, (uint64_t)a.metric,
-      (uint64_t)a.items_cap, (uint64_t)a.blocks, (uint64_t)a.slot_ids, (uint64_t)st.d, (uint64_t)st.dp, (uint64_t)st.nlist,
+      (uint64_t)a.items_cap, (uint64_t)a.blocks, (uint64_t)a.slot_ids, u(a.hits), (uint64_t)st.d, (uint64_t)st.dp, (uint64_t)st.nlist,
       (uint64_t)st.dp16, u(idx->cap_table), u(st.centroids), u(st.d_off), u(st.d_size), u(st.d_cap), u(st.d_order), u(st.v32),
       u(st.v16), u(st.v16n), u(st.rows32), u(st.ids), u(w.q), u(w.qn2), u(w.cand), u(w.mq), u(w.h), u(w.st_m),
       u(w.st_w), u(w.st_weff), u(w.st_done), u(w.st_item), u(w.st_demand), u(w.st_rho), u(w.st_p0), u(w.st_V),
@@ -888,6 +940,9 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
   a.dim = idx->d;
   a.tau_r = job.tau_r;
   a.tau_rho = job.tau_rho;
+  const bool count = job.count && idx->count_access;
+  a.hits = count ? st.d_hits : nullptr;
+  if (count) st.window += nq;
   // a smaller requested cap than the buffer already allocated still applies
   a.items_cap = std::min<int64_t>(w.items_cap, items);
   qk::launch_round_init(w, a, job.w0, s);
@@ -1219,6 +1274,7 @@ int quake_autotune(quake_index* idx, const float* q, int64_t nq, const quake_sea
   const quake_tuning saved = idx->tune;
   const bool prof = idx->prof.on;
   idx->prof.on = false;
+  idx->count_access = false;  // tuning searches are not workload: keep them out of the access statistics
   auto search = [&]() {
     const int rc = quake_search(idx, q, nq, params, ids.p, dist.p, nullptr, nullptr, stream);
     if (rc != QUAKE_OK) throw qk::Error{rc, qk::g_error};
@@ -1288,11 +1344,13 @@ int quake_autotune(quake_index* idx, const float* q, int64_t nq, const quake_sea
         }
     idx->tune = best;
     idx->prof.on = prof;
+    idx->count_access = true;
     if (out) *out = best;
     if (out_ms) *out_ms = best_ms;
   } catch (...) {
     idx->tune = saved;
     idx->prof.on = prof;
+    idx->count_access = true;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     throw;
@@ -1391,6 +1449,7 @@ int quake_insert(quake_index* idx, const float* x, const int64_t* ids, int64_t n
     ensure_queries(idx, n);
     qk::launch_pad_rows(xpad, n, dp, dp, idx->ws.q, idx->ws.qn2, s);
     Job route;
+    route.count = false;
     route.k = route.kk = 1;
     route.M = route.w0 = route.wmax = 1;  // the nearest top partition, its nearest leaf
     run_search(idx, idx->L1, route, n, nullptr, nullptr, nullptr, nullptr, s);
@@ -1475,39 +1534,9 @@ int quake_delete(quake_index* idx, const int64_t* ids, int64_t n, void* stream) 
   }
   // compaction: a partition with a quarter of its slots deleted has its
   // holes below the new size filled from its live tail
-  std::vector<int64_t> src, dst, moved_ids;
-  for (int64_t p = 0; p < st.nlist; ++p) {
-    if (!touched[p] || st.tomb[p] * 4 < st.size[p]) continue;
-    const int64_t base = st.off[p] * qk::TILE;
-    const int64_t size = st.size[p];
-    std::vector<int64_t> pid(size);
-    QK_HIP(hipMemcpyAsync(pid.data(), st.ids + base, size * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    QK_HIP(hipStreamSynchronize(s));
-    const int64_t keep = size - st.tomb[p];
-    int64_t hole = 0, tail = keep;
-    while (true) {
-      while (hole < keep && pid[hole] >= 0) ++hole;
-      while (tail < size && pid[tail] < 0) ++tail;
-      if (hole >= keep || tail >= size) break;
-      src.push_back(base + tail);
-      dst.push_back(base + hole);
-      moved_ids.push_back(pid[tail]);
-      ++hole;
-      ++tail;
-    }
-    st.size[p] = (int32_t)keep;
-    st.tomb[p] = 0;
-  }
-  if (!src.empty()) {
-    const int64_t m = (int64_t)src.size();
-    Tmp<int64_t> d_src(idx->mem, m), d_dst(idx->mem, m), d_ids(idx->mem, m);
-    QK_HIP(hipMemcpyAsync(d_src.p, src.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    QK_HIP(hipMemcpyAsync(d_dst.p, dst.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    QK_HIP(hipMemcpyAsync(d_ids.p, moved_ids.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    qk::launch_move_slots(st, d_src.p, d_dst.p, m, s);
-    qk::launch_map_update(idx->idmap, d_ids.p, d_dst.p, m, s);
-    QK_HIP(hipStreamSynchronize(s));
-  }
+  for (int64_t p = 0; p < st.nlist; ++p)
+    if (touched[p] && st.tomb[p] * 4 < st.size[p]) touched[p] = 0;
+  compact(idx, st, touched, s);
   upload_table(st, s);
   QK_HIP(hipStreamSynchronize(s));
   API_END

@@ -22,6 +22,7 @@ struct Job {
   int rerank = 1;      // batched path: re-score the kk candidates in FP32 (0: keep the 16-bit values)
   double tau_r = 0, f_M = 0, tau_rho = 0.01;
   bool given = false;  // candidate rows already in ws.cand0 / ws.mq0 (level 0 of two levels)
+  bool count = true;   // add the queries to the store's access statistics (not for insert routing)
 };
 
 Job resolve(const quake_index* idx, const Store& st, const quake_search_params* p);
@@ -54,5 +55,19 @@ void search_in_scratch(quake_index* idx, const float* q, int64_t nq, const quake
 // Runs fn under the C ABI's error handling: the return code, and the message
 // for quake_last_error on failure.
 int run_api(const std::function<void()>& fn);
+
+// Store upkeep shared by updates and maintenance (capi.cpp).
+// The arena holds at least `need` tiles (grown by copying; old tiles keep their contents).
+void store_grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s);
+// Partition p moves to fresh tiles at the arena's end (which must have room) with capacity cap.
+void store_relocate(Store& st, int64_t p, int32_t cap, hipStream_t s);
+// Device copies of off / size / cap and the size order.
+void store_upload_table(Store& st, hipStream_t s);
+// Deleted slots of the partitions with which[p] set are filled from their live tails.
+void store_compact(quake_index* idx, Store& st, const std::vector<char>& which, hipStream_t s);
+// Fraction bits of exact fixed-point sums over rows [n][dp].
+int store_fixed_point_bits(DeviceMemory& mem, const float* x, int64_t n, int dp, hipStream_t s);
+// The maintenance pass behind quake_maintain (maintain.cpp).
+void maintain(quake_index* idx, const quake_maintain_params& p, quake_maintain_report* report, hipStream_t s);
 
 }  // namespace qk

@@ -99,6 +99,8 @@ struct Store {
   int64_t live = 0;
   std::vector<int32_t> tomb;     // deleted slots still inside size[p]
   std::vector<int32_t> tile_part;  // partition owning each arena tile (-1 = unused)
+  uint32_t* d_hits = nullptr;   // [nlist] queries that scanned each partition since the counters were cleared
+  mutable int64_t window = 0;   // queries searched since then (searches take the store const)
 };
 
 struct Workspace {
@@ -213,6 +215,7 @@ struct quake_index {
   hipStream_t capture_stream = nullptr;
   bool graphs_failed = false;
   bool noalloc = false;         // inside quake_search_noalloc: launch rounds directly, allocate nothing
+  bool count_access = true;     // searches add to the access statistics (off while the autotuner runs)
   ~quake_index();  // graphs, streams and pinned buffers; device memory goes with `mem`
 };
 
@@ -275,6 +278,7 @@ struct RoundArgs {
   int64_t items_cap;
   int blocks;        // grid of the persistent scan kernels (they read their item counts on the device)
   int slot_ids;      // 1: the lists carry store slots below 2^31 (batched path), not ids
+  uint32_t* hits;    // per-partition access counts the commit adds to, or null
 };
 void launch_round_init(Workspace& ws, const RoundArgs& a, int w0, hipStream_t s);
 void launch_demand(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
@@ -307,6 +311,22 @@ void launch_norm16_slots(Store& st, const int64_t* slots, int64_t n, int dtype16
 void launch_level1_to_candidates(int64_t nq, int M0, int kk, const int64_t* ri, int32_t* cand0, int32_t* mq,
                                  hipStream_t s);
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+
+// kernels: maintenance (k_maintain.hip)
+// out[i] = the FP32 vector in store slot slots[i], row-major [n][dp].
+void launch_gather_slots(const Store& st, const int64_t* slots, int64_t n, float* out, hipStream_t s);
+// far[s] = the row of [lo[s], lo[s+1]) farthest from ref[s] (largest squared
+// distance, or smallest inner product; ties to the lower row).
+void launch_seg_farthest(const float* x, const int64_t* lo, int64_t nseg, const float* ref, int dp, int metric,
+                         int64_t* far, hipStream_t s);
+// lab[i] = 2 seg[i] + (1 if row i is strictly nearer to c[2 seg + 1] than to c[2 seg]).
+void launch_seg_assign2(const float* x, int64_t n, const int32_t* seg, const float* c, int dp, int metric,
+                        int32_t* lab, hipStream_t s);
+// lab[i] = the nearest of the G centroids c[G][dp] (ties to the lower index).
+void launch_nearest_of(const float* x, int64_t n, const float* c, int G, int dp, int metric, int32_t* lab,
+                       hipStream_t s);
+// c[rows[g]] = src[g] for g < G.
+void launch_put_rows(const float* src, const int32_t* rows, int64_t G, int dp, float* c, hipStream_t s);
 
 // kernels: serving (k_serve.hip)
 void launch_rows_to_slots(const float* x, int64_t n, int d, int dp, const int32_t* slots, float* out, double* norm2,

@@ -619,7 +619,8 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
                              int32_t* __restrict__ st_done, const int32_t* __restrict__ st_weff,
                              const int64_t* __restrict__ st_item, double* __restrict__ st_rho,
                              double* __restrict__ st_p0, double* __restrict__ st_V, double* __restrict__ st_vsum,
-                             double* __restrict__ st_r, float* __restrict__ rk, int64_t* __restrict__ ri) {
+                             double* __restrict__ st_r, float* __restrict__ rk, int64_t* __restrict__ ri,
+                             uint32_t* __restrict__ hits) {
   const int lane = lane_id();
   const int w = st_weff[q];
   L.load(rk + q * kk, ri + q * kk);
@@ -689,6 +690,9 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
     if (wn > wmax) wn = wmax;
   }
   L.store(rk + q * kk, ri + q * kk);
+  // access statistics: every partition committed here was scanned by this query
+  if (hits)
+    for (int j = m0 + lane; j < committed; j += WAVE) atomicAdd(&hits[cand[q * M + j]], 1u);
   if (lane == 0) {
     st_m[q] = committed;
     st_w[q] = wn;
@@ -707,10 +711,10 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
       int32_t *__restrict__ st_w, int32_t *__restrict__ st_done, const int32_t *__restrict__ st_weff,            \
       const int64_t *__restrict__ st_item, double *__restrict__ st_rho, double *__restrict__ st_p0,              \
       double *__restrict__ st_V, double *__restrict__ st_vsum, double *__restrict__ st_r, float *__restrict__ rk, \
-      int64_t *__restrict__ ri
+      int64_t *__restrict__ ri, uint32_t *__restrict__ hits
 #define QK_COMMIT_ARGS                                                                                        \
   M, mq, k, kk, aps, ip, chunk_tiles, wmax, wscale, tau_r, tau_rho, cand, hcand, psize, qn2, pk, pi, table, st_m, st_w, \
-      st_done, st_weff, st_item, st_rho, st_p0, st_V, st_vsum, st_r, rk, ri
+      st_done, st_weff, st_item, st_rho, st_p0, st_V, st_vsum, st_r, rk, ri, hits
 
 // Lists longer than a wave: one 64-thread block per query, lists in LDS.
 template <int LMAX>
@@ -741,7 +745,7 @@ void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const dou
                      a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.wscale, a.tau_r, a.tau_rho, ws.cand,     \
                      ws.h,                                                                                      \
                      st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_weff,        \
-                     ws.st_item, ws.st_rho, ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri)
+                     ws.st_item, ws.st_rho, ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri, a.hits)
   if (a.kk <= WAVE && a.slot_ids) QK_COMMIT(k_commit64<PackedList>, (a.nq + 3) / 4, 256);
   else if (a.kk <= WAVE) QK_COMMIT(k_commit64<RegList>, (a.nq + 3) / 4, 256);
   else if (a.kk <= KMAX) QK_COMMIT(k_commit<KMAX>, a.nq, 64);

@@ -128,6 +128,7 @@ struct quake_server {
     a.tau_rho = job.tau_rho;
     a.items_cap = std::min<int64_t>(idx->ws.items_cap, items);
     a.blocks = blocks;
+    a.hits = st().d_hits;
     return a;
   }
 
@@ -165,6 +166,7 @@ struct quake_server {
     qk::launch_candidates_to_slots(d_cand, job.aps ? d_h : nullptr, n, job.M, d_slots, w.cand, w.h, w.mq, s);
     if (job.batched) qk::launch_queries16(w, n, dp, st().dp16, job.dtype16, s, d_slots);
     qk::launch_init_slots(w, d_slots, n, job.kk, job.w0, s);
+    st().window += n;
   }
 
   // One scan round over all slots: plan, scan, commit.  No host round trip;

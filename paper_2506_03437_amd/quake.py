@@ -29,7 +29,8 @@ _MODE = {"plain": SCAN_PLAIN, "batched": SCAN_BATCHED}
 EXPORTED = ("quake_build", "quake_search", "quake_search_noalloc", "quake_insert", "quake_delete", "quake_stats", "quake_export",
             "quake_export_top", "quake_candidates", "quake_cap_table", "quake_profile", "quake_set_tuning",
             "quake_free", "quake_last_error", "quake_autotune", "quake_server_create", "quake_server_search", "quake_server_insert",
-            "quake_server_delete", "quake_server_wait", "quake_server_stats", "quake_server_destroy")
+            "quake_server_delete", "quake_server_wait", "quake_server_stats", "quake_server_destroy",
+            "quake_access_stats", "quake_maintain")
 PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "scan_sets", "unused7")
 
 
@@ -112,6 +113,25 @@ class KernelProfile(ctypes.Structure):
                 ("flops", ctypes.c_double)]
 
 
+class Decision(ctypes.Structure):
+    _fields_ = [("partition", ctypes.c_int32), ("action", ctypes.c_int32), ("committed", ctypes.c_int32),
+                ("new_partition", ctypes.c_int32), ("estimate", ctypes.c_double), ("verified", ctypes.c_double)]
+
+
+class MaintainParams(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("alpha", ctypes.c_double), ("refine_radius", ctypes.c_int32),
+                ("refine_iters", ctypes.c_int32), ("split_iters", ctypes.c_int32), ("min_split_size", ctypes.c_int32),
+                ("merge_below", ctypes.c_int64), ("lambda_points", ctypes.c_int32), ("max_decisions", ctypes.c_int32),
+                ("lambda_size", ctypes.c_void_p), ("lambda_cost", ctypes.c_void_p), ("hits", ctypes.c_void_p),
+                ("window", ctypes.c_int64), ("decisions", ctypes.c_void_p)]
+
+
+class MaintainReport(ctypes.Structure):
+    _fields_ = [("decisions", ctypes.c_int32), ("splits", ctypes.c_int32), ("deletes", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("nlist_before", ctypes.c_int64), ("nlist_after", ctypes.c_int64),
+                ("vectors_moved", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -133,6 +153,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.quake_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)]
     lib.quake_export.argtypes = [vp, vp, vp, vp, vp]
     lib.quake_export_top.argtypes = [vp, vp, vp, vp]
+    lib.quake_access_stats.argtypes = [vp, i32, vp, ctypes.POINTER(i64), i32, vp]
+    lib.quake_maintain.argtypes = [vp, ctypes.POINTER(MaintainParams), ctypes.POINTER(MaintainReport), vp]
     lib.quake_candidates.argtypes = [vp, vp, i64, ctypes.POINTER(SearchParams), vp, vp, ctypes.POINTER(i32), vp]
     lib.quake_cap_table.argtypes = [i32, ctypes.POINTER(f64)]
     lib.quake_profile.argtypes = [vp, i32, i32, vp]
@@ -288,6 +310,38 @@ def quake_export_top(handle: int, d: int, nlist_top: int):
     top_of = torch.empty((nlist,), dtype=torch.int32, device=dev)
     _check(load_library().quake_export_top(handle, _ptr(C1), _ptr(top_of), _stream()))
     return C1, top_of
+
+
+def quake_access_stats(handle: int, level: int = 0, reset: bool = False):
+    """(hits int64 [nlist] numpy, window) of the level's access statistics."""
+    nlist = quake_stats(handle)[1] if level == 0 else None
+    if nlist is None:
+        raise ValueError("level 1 statistics: pass level=0 or read them through the C ABI")
+    hits = np.zeros(nlist, dtype=np.int64)
+    window = ctypes.c_int64()
+    _check(load_library().quake_access_stats(handle, level, hits.ctypes.data, ctypes.byref(window), int(reset),
+                                             _stream()))
+    return hits, window.value
+
+
+def quake_maintain(handle: int, lambda_size, lambda_cost, *, tau=0.25, alpha=0.9, refine_radius=50, refine_iters=1,
+                   split_iters=8, min_split_size=2, merge_below=0, hits=None, window=0, max_decisions=4096):
+    """One maintenance pass; returns (report dict, decisions list of dicts)."""
+    ls = np.ascontiguousarray(lambda_size, dtype=np.float64)
+    lc = np.ascontiguousarray(lambda_cost, dtype=np.float64)
+    if ls.shape != lc.shape or ls.ndim != 1:
+        raise ValueError("lambda_size and lambda_cost must be 1-D arrays of the same length")
+    h = None if hits is None else np.ascontiguousarray(hits, dtype=np.int64)
+    dec = (Decision * max(max_decisions, 1))()
+    p = MaintainParams(tau, alpha, refine_radius, refine_iters, split_iters, min_split_size, merge_below, ls.size,
+                       max_decisions, ls.ctypes.data, lc.ctypes.data, None if h is None else h.ctypes.data,
+                       window, ctypes.cast(dec, ctypes.c_void_p))
+    r = MaintainReport()
+    _check(load_library().quake_maintain(handle, ctypes.byref(p), ctypes.byref(r), _stream()))
+    rep = {name: getattr(r, name) for name, _ in MaintainReport._fields_ if name != "pad"}
+    out = [{name: getattr(dec[i], name) for name, _ in Decision._fields_}
+           for i in range(min(r.decisions, max_decisions))]
+    return rep, out
 
 
 def quake_candidates(handle: int, q, f_M: float, upper_recall_target=0.0, upper_f_M=0.0, tau_rho=0.0):
@@ -473,6 +527,12 @@ class Index:
 
     def profile(self, enable=True, reset=False):
         return quake_profile(self.handle, enable, reset)
+
+    def access_stats(self, reset=False):
+        return quake_access_stats(self.handle, 0, reset)
+
+    def maintain(self, lambda_size, lambda_cost, **kw):
+        return quake_maintain(self.handle, lambda_size, lambda_cost, **kw)
 
     def free(self):
         quake_free(self.handle)

@@ -53,12 +53,17 @@ WORKLOADS: Dict[str, Workload] = {
         spec=MixtureSpec(key=3, n=10_000_000, d=768, n_components=1000, zipf_s=1.1, unit_norm=True),
         nlist=4096, metric="ip", nq=16_384, k=10, recall_target=0.9, f_M=0.05, storage="bf16"),
     # 50M x 128 FP16 store, 50k generator-defined leaves under 64 top partitions, L2.
+    # Leaf sizes Zipf(0.3) over a random ranking (mean 1,000, largest about
+    # 43k); rows spread 0.2 per dimension around their leaf centre, twice the
+    # spread of the centres around their component, so that a query's ten
+    # nearest neighbours lie in about six leaves (half in its nearest one).
     "two-level-50m-d128-f16": Workload(
         name="two-level-50m-d128-f16",
         spec=MixtureSpec(key=4, n=50_000_000, d=128, n_components=1000, zipf_s=1.1),
         nlist=50_000, metric="l2", nq=65_536, k=10, recall_target=0.9, f_M=0.015,
-        storage="f16", leaves=LeafSpec(MixtureSpec(key=4, n=50_000_000, d=128, n_components=1000, zipf_s=1.1), 50_000),
-        nlist_top=64, query_noise=0.05),
+        storage="f16", leaves=LeafSpec(MixtureSpec(key=4, n=50_000_000, d=128, n_components=1000, zipf_s=1.1), 50_000,
+                                       leaf_zipf_s=0.3, leaf_std=0.2),
+        nlist_top=64, query_noise=0.1),
     # Serving: 10M x 768 BF16 start, skewed drifting queries, 1% updates per step.
     "serving-10m-d768-bf16": Workload(
         name="serving-10m-d768-bf16",

@@ -79,3 +79,12 @@ def test_autotune_argument_errors():
     lib = quake.load_library()
     sp = quake.SearchParams(10, 4, 0.0, 0, 0, 0, 0, 0, 0, 0, 0)
     assert lib.quake_autotune(None, None, 1, ctypes.byref(sp), 3, None, None, None) == quake.E_STATE
+
+
+def test_maintenance_argument_errors():
+    from paper_2506_03437_amd import quake
+    lib = quake.load_library()
+    p = quake.MaintainParams()
+    assert lib.quake_maintain(None, ctypes.byref(p), None, None) == quake.E_STATE
+    assert lib.quake_access_stats(None, 0, None, None, 0, None) == quake.E_STATE
+    assert b"handle" in lib.quake_last_error()
