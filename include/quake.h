@@ -195,6 +195,17 @@ int quake_export_top(const quake_index* index, float* top_centroids, int32_t* to
 int quake_access_stats(quake_index* index, int32_t level, int64_t* hits, int64_t* window, int32_t reset,
                        void* stream);
 
+/* lambda(s) on this GPU (Sec. 4.1 measures it by offline profiling; Sec. 8
+ * asks for a per-device profile on heterogeneous hardware): for each
+ * sizes[i], a one-partition index of that many of this index's vectors (same
+ * metric and copies) is searched by nq of them with params' path and k
+ * (nprobe 1), reps times after one warm-up; out_us[i] (host) = microseconds
+ * per query, i.e. the cost one query adds to a batch of nq that scans one
+ * partition of sizes[i] vectors.  sizes[i] and nq may not exceed the index's
+ * live vectors.  Allocates its temporaries like the index does. */
+int quake_profile_latency(quake_index* index, const int32_t* sizes, int32_t points, int32_t nq,
+                          const quake_search_params* params, int32_t reps, double* out_us, void* stream);
+
 /* One decision of a maintenance pass: the estimate (Eq. delta_split_est, or
  * the uniform-redistribution delete estimate), the verified delta with the
  * actual sizes (Eqs. delta_split_exact / delta_merge_exact), and whether it
@@ -348,18 +359,27 @@ int quake_profile(quake_index* index, int32_t enable, int32_t reset, quake_kerne
  * The slot count is max_slots, or what hbm_budget_bytes of search
  * workspace holds (each slot needs the query row, its candidates, its result
  * lists and its share of the work items).  Updates keep submission order:
+ * every search answers as if it ran alone on the index state of its epoch
+ * (the state after the updates submitted before it; the paper's system
+ * runs searches and updates serially, Sec. 8).  Without overlap_updates,
  * admission pauses at an update, the queries already admitted finish, the
- * batch is applied (an epoch), and admission resumes - so every search
- * answers as if it ran alone on the index state of its epoch (the
- * paper's system runs searches and updates serially, Sec. 8).
- * While a server runs, its index must not be used through other entry
- * points.  Single-level indexes only.
+ * batch is applied, and admission resumes.  With overlap_updates (Sec. 8,
+ * "Concurrency", names copy-on-write views as the way to run updates beside
+ * queries) the server holds a second copy of the level-0 store (twice the
+ * store's device memory): the update is applied to the copy no search
+ * reads, the copies swap, later searches run on the new version while the
+ * earlier ones finish on the old one, and the old copy replays the update
+ * once its searches are done - an update waits only for the searches of the
+ * version before the current one.  While a server runs, its index must not
+ * be used through other entry points; afterwards the index holds the newest
+ * version.  Single-level indexes only.
  * ---------------------------------------------------------------------- */
 typedef struct quake_server quake_server;
 
 typedef struct {
   int32_t max_slots;        /* queries in flight at once; 0 -> from hbm_budget_bytes, else 4096 */
-  int32_t reserved;
+  int32_t overlap_updates;  /* 1: keep a second copy of the level-0 store and apply each update
+                               beside the searches admitted before it (see below); 0: drain */
   size_t hbm_budget_bytes;  /* device bytes the in-flight searches may use; 0 -> unlimited */
   quake_search_params search;
 } quake_server_params;
@@ -372,6 +392,7 @@ typedef struct {
   int64_t max_in_flight;    /* most slots held at once */
   int64_t epochs;           /* update batches applied */
   int64_t rounds;           /* scan rounds run */
+  int64_t overlapped_updates; /* updates applied while searches of the previous version ran */
   double p50_latency_s;     /* arrival -> answer ready, over completed searches */
   double p99_latency_s;
   double mean_latency_s;

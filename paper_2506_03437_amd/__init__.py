@@ -21,6 +21,7 @@ from .quake import (  # noqa: F401
     quake_insert,
     quake_maintain,
     quake_profile,
+    quake_profile_latency,
     quake_search,
     quake_search_noalloc,
     quake_server_create,

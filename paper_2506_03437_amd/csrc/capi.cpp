@@ -722,7 +722,7 @@ std::vector<uint64_t> graph_key(const quake_index* idx, const Store& st, const J
   std::vector<uint64_t> k = {
       (uint64_t)R, (uint64_t)job.batched, (uint64_t)job.dtype16, (uint64_t)a.nq, (uint64_t)a.M, (uint64_t)a.k,
       (uint64_t)a.kk, (uint64_t)a.aps, (uint64_t)a.chunk_tiles, (uint64_t)a.wmax, (uint64_t)a.wscale, (uint64_t)a.metric,
-      (uint64_t)a.items_cap, (uint64_t)a.blocks, (uint64_t)a.slot_ids, u(a.hits), (uint64_t)st.d, (uint64_t)st.dp, (uint64_t)st.nlist,
+      (uint64_t)a.items_cap, (uint64_t)a.blocks, (uint64_t)a.slot_ids, u(a.hits), u(a.slot_tag), (uint64_t)a.tag, (uint64_t)st.d, (uint64_t)st.dp, (uint64_t)st.nlist,
       (uint64_t)st.dp16, u(idx->cap_table), u(st.centroids), u(st.d_off), u(st.d_size), u(st.d_cap), u(st.d_order), u(st.v32),
       u(st.v16), u(st.v16n), u(st.rows32), u(st.ids), u(w.q), u(w.qn2), u(w.cand), u(w.mq), u(w.h), u(w.st_m),
       u(w.st_w), u(w.st_weff), u(w.st_done), u(w.st_item), u(w.st_demand), u(w.st_rho), u(w.st_p0), u(w.st_V),

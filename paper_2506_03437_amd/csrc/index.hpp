@@ -279,6 +279,8 @@ struct RoundArgs {
   int blocks;        // grid of the persistent scan kernels (they read their item counts on the device)
   int slot_ids;      // 1: the lists carry store slots below 2^31 (batched path), not ids
   uint32_t* hits;    // per-partition access counts the commit adds to, or null
+  const uint8_t* slot_tag;  // serving: store tag of every query slot, or null (all queries take part)
+  int tag;           // with slot_tag: the tag of the store this round scans
 };
 void launch_round_init(Workspace& ws, const RoundArgs& a, int w0, hipStream_t s);
 void launch_demand(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);

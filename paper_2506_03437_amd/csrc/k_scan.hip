@@ -91,6 +91,7 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_demand(int64_t nq, int M, int ch
                                                         const int32_t* __restrict__ st_w,
                                                         int32_t* __restrict__ st_weff,
                                                         const int32_t* __restrict__ st_done,
+                                                        const uint8_t* __restrict__ slot_tag, int tag,
                                                         int64_t* __restrict__ demand, int64_t* __restrict__ vecs,
                                                         int64_t* __restrict__ loc_item, int64_t* __restrict__ loc_pair,
                                                         int64_t* __restrict__ blk) {
@@ -99,7 +100,8 @@ __global__ __launch_bounds__(PLAN_BLOCK) void k_demand(int64_t nq, int M, int ch
   const int wave = threadIdx.x / WAVE;
   int64_t dmd = 0, nv = 0;
   int w = 0;
-  if (q < nq && !st_done[q]) {
+  // with slot tags, only the queries of this round's store get a window
+  if (q < nq && !st_done[q] && (slot_tag == nullptr || slot_tag[q] == tag)) {
     const int m = st_m[q];
     w = st_w[q];
     if (w > mq[q] - m) w = mq[q] - m;
@@ -227,8 +229,8 @@ void launch_demand(Workspace& ws, const Store& st, const RoundArgs& a, hipStream
   if (a.nq <= 0) return;
   const unsigned nb = (unsigned)((a.nq + PLAN_BLOCK - 1) / PLAN_BLOCK);
   hipLaunchKernelGGL(k_demand, dim3(nb), dim3(PLAN_BLOCK), 0, s, a.nq, a.M, a.chunk_tiles, ws.mq, ws.cand, st.d_size,
-                     ws.st_m, ws.st_w, ws.st_weff, ws.st_done, ws.st_demand, ws.st_vecs, ws.st_item, ws.st_pair,
-                     ws.blk);
+                     ws.st_m, ws.st_w, ws.st_weff, ws.st_done, a.slot_tag, a.tag, ws.st_demand, ws.st_vecs,
+                     ws.st_item, ws.st_pair, ws.blk);
   hipLaunchKernelGGL(k_prefix, dim3(1), dim3(1024), 0, s, a.nq, a.items_cap, ws.st_demand, ws.st_vecs, ws.st_item,
                      ws.st_pair, ws.blk, ws.total);
   hipLaunchKernelGGL(k_place, dim3(nb), dim3(PLAN_BLOCK), 0, s, a.nq, ws.blk, ws.total, ws.st_item, ws.st_pair,

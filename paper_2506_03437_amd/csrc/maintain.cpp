@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -617,6 +618,79 @@ int quake_maintain(quake_index* index, const quake_maintain_params* params, quak
     QK_CHECK(index && index->magic == 0x51554b45u, QUAKE_E_STATE, "invalid or freed index handle");
     QK_CHECK(params, QUAKE_E_INVALID, "params is NULL");
     qk::maintain(index, *params, report, reinterpret_cast<hipStream_t>(stream));
+  });
+}
+
+int quake_profile_latency(quake_index* index, const int32_t* sizes, int32_t points, int32_t nq,
+                          const quake_search_params* params, int32_t reps, double* out_us, void* stream) {
+  return qk::run_api([&] {
+    QK_CHECK(index && index->magic == 0x51554b45u, QUAKE_E_STATE, "invalid or freed index handle");
+    QK_CHECK(sizes && out_us && points >= 1, QUAKE_E_INVALID, "need sizes, out_us and points >= 1");
+    QK_CHECK(nq >= 1 && reps >= 1 && params, QUAKE_E_INVALID, "need nq >= 1, reps >= 1 and params");
+    qk::Store& st = index->L0;
+    int64_t want = nq;
+    for (int32_t i = 0; i < points; ++i) {
+      QK_CHECK(sizes[i] >= 1, QUAKE_E_INVALID, "sizes must be >= 1");
+      want = std::max<int64_t>(want, sizes[i]);
+    }
+    QK_CHECK(want <= st.live, QUAKE_E_INVALID, "the index holds fewer vectors than the largest size (or nq)");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int d = index->d, dp = index->dp;
+    // the first `want` live vectors of the store, partition by partition
+    std::vector<int64_t> slots, ids, lo;
+    std::vector<int32_t> parts;
+    int64_t have = 0;
+    for (int64_t p = 0; p < st.nlist && have < want; ++p) {
+      parts.push_back((int32_t)p);
+      have += qk::live_size(st, p);
+    }
+    qk::live_rows(st, parts, slots, ids, lo, s);
+    slots.resize(want);
+    qk::Buf<int64_t> d_slots(index->mem, want);
+    qk::Buf<float> xp(index->mem, (size_t)want * dp), x(index->mem, (size_t)want * d);
+    qk::upload(d_slots.p, slots, s);
+    qk::launch_gather_slots(st, d_slots.p, want, xp.p, s);
+    QK_HIP(hipMemcpy2DAsync(x.p, d * sizeof(float), xp.p, dp * sizeof(float), d * sizeof(float), want,
+                            hipMemcpyDeviceToDevice, s));
+    QK_HIP(hipStreamSynchronize(s));
+    quake_search_params sp = *params;
+    sp.nprobe = 1;
+    sp.recall_target = 0.0;
+    qk::Buf<int64_t> oi(index->mem, (size_t)nq * std::max(sp.k, 1));
+    qk::Buf<float> od(index->mem, (size_t)nq * std::max(sp.k, 1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    QK_HIP(hipEventCreate(&e0));
+    QK_HIP(hipEventCreate(&e1));
+    struct Events {
+      hipEvent_t a, b;
+      ~Events() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+    } ev{e0, e1};
+    for (int32_t i = 0; i < points; ++i) {
+      // a one-partition index of sizes[i] of those vectors, same metric and copies
+      quake_build_params bp{};
+      bp.metric = index->metric;
+      bp.storage_dtype = index->storage;
+      bp.n_levels = 1;
+      bp.nlist = 1;
+      bp.kmeans_iters = 0;
+      quake_index* tmp = nullptr;
+      const quake_allocator* alloc = index->mem.user.alloc ? &index->mem.user : nullptr;
+      int rc = quake_build(x.p, nullptr, sizes[i], d, &bp, alloc, stream, &tmp);
+      QK_CHECK(rc == QUAKE_OK, rc, "profile build: " + qk::g_error);
+      std::unique_ptr<quake_index, void (*)(quake_index*)> hold(tmp, quake_free);
+      auto run = [&] {
+        const int r = quake_search(tmp, x.p, nq, &sp, oi.p, od.p, nullptr, nullptr, stream);
+        QK_CHECK(r == QUAKE_OK, r, "profile search: " + qk::g_error);
+      };
+      run();  // grows the workspace and captures the round graphs
+      QK_HIP(hipEventRecord(e0, s));
+      for (int32_t r = 0; r < reps; ++r) run();
+      QK_HIP(hipEventRecord(e1, s));
+      QK_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      QK_HIP(hipEventElapsedTime(&ms, e0, e1));
+      out_us[i] = (double)ms * 1e3 / reps / nq;
+    }
   });
 }
 

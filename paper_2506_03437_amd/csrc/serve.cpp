@@ -10,8 +10,18 @@
 // already in progress and its work items share rounds (and, on the batched
 // path, partition reads) with searches admitted earlier.  Per-query results
 // do not depend on the company a query keeps: every step of a query's search
-// reads only that query's own state.  An update request at the head of the
-// queue stops admission until the slots drain, then runs as one batch.
+// reads only that query's own state.
+//
+// Updates.  By default an update request at the head of the queue stops
+// admission until the slots drain, then runs as one batch.  With
+// overlap_updates the server keeps a second copy of the level-0 store (a
+// copy-on-write view made coarse: HBM holds two versions of the index): an
+// update is applied to the copy that no search is reading, the two swap, and
+// new searches run on the new version while the searches admitted before the
+// update finish on the old one - every round scans each version for its own
+// query slots (slot tags).  The old version catches up by replaying the
+// update once its last search has finished; an update only waits for the
+// version before the current one to drain.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -51,6 +61,53 @@ struct Answer {
 };
 
 template <class T>
+T* dup(qk::DeviceMemory& mem, std::vector<void*>& got, const T* src, size_t n, hipStream_t s) {
+  if (!src) return nullptr;
+  T* p = mem.alloc<T>(std::max<size_t>(n, 1));
+  got.push_back(p);
+  if (n) QK_HIP(hipMemcpyAsync(p, src, n * sizeof(T), hipMemcpyDeviceToDevice, s));
+  return p;
+}
+
+// Second copy of a level-0 store and its id map (the access counters are shared).
+void clone_store(qk::DeviceMemory& mem, const qk::Store& a, const qk::IdMap& am, qk::Store& b, qk::IdMap& bm,
+                 hipStream_t s) {
+  std::vector<void*> got;
+  try {
+    qk::Store t = a;
+    const size_t slots = (size_t)a.tiles * qk::TILE, N = (size_t)a.nlist;
+    t.centroids = dup(mem, got, a.centroids, N * a.dp, s);
+    t.d_off = dup(mem, got, a.d_off, N, s);
+    t.d_size = dup(mem, got, a.d_size, N, s);
+    t.d_cap = dup(mem, got, a.d_cap, N, s);
+    t.d_order = dup(mem, got, a.d_order, N, s);
+    t.v32 = dup(mem, got, a.v32, slots * a.dp, s);
+    t.v16 = dup(mem, got, a.v16, slots * a.dp16, s);
+    t.v16n = dup(mem, got, a.v16n, slots, s);
+    t.rows32 = dup(mem, got, a.rows32, slots * a.dp, s);
+    t.ids = dup(mem, got, a.ids, slots, s);
+    qk::IdMap tm = am;
+    tm.keys = dup(mem, got, am.keys, (size_t)am.mask + 1, s);
+    tm.vals = dup(mem, got, am.vals, (size_t)am.mask + 1, s);
+    QK_HIP(hipStreamSynchronize(s));
+    b = std::move(t);
+    bm = tm;
+  } catch (...) {
+    for (void* p : got) mem.release(p);
+    throw;
+  }
+}
+
+void free_store(qk::DeviceMemory& mem, qk::Store& b, qk::IdMap& bm) {
+  for (void* p : {(void*)b.centroids, (void*)b.d_off, (void*)b.d_size, (void*)b.d_cap, (void*)b.d_order,
+                  (void*)b.v32, (void*)b.v16, (void*)b.v16n, (void*)b.rows32, (void*)b.ids, (void*)bm.keys,
+                  (void*)bm.vals})
+    mem.release(p);
+  b = qk::Store();
+  bm = qk::IdMap();
+}
+
+template <class T>
 T* pinned(size_t n) {
   void* p = nullptr;
   QK_HIP(hipHostMalloc(&p, std::max<size_t>(n, 1) * sizeof(T), hipHostMallocDefault));
@@ -83,6 +140,20 @@ struct quake_server {
   std::vector<double> slot_arrive;
   std::vector<int32_t> free_slots;
   int64_t active = 0, max_active = 0, epochs = 0, rounds = 0, completed = 0;
+
+  // overlapped updates: idx->L0 is the newest version (tag front), `other`
+  // the previous one while its searches finish, then a copy that has
+  // replayed every update
+  bool overlap = false;
+  bool have_twin = false;
+  qk::Store other;
+  qk::IdMap other_map;
+  int front = 0;                        // tag of idx->L0; `other` has 1 - front
+  std::vector<uint8_t> slot_tag;        // host mirror of d_tag
+  uint8_t* d_tag = nullptr;             // [cap] store tag of every slot
+  int64_t active_tag[2] = {0, 0};
+  std::deque<Request> replay;           // updates `other` has yet to apply
+  int64_t overlapped = 0;               // updates applied while the previous version had searches
   std::vector<double> lat;
   double first_arrive = -1, last_done = 0;
 
@@ -110,8 +181,10 @@ struct quake_server {
   double* h_rec = nullptr;
 
   const qk::Store& st() const { return idx->L0; }
+  const qk::Store& store_of(int tag) const { return tag == front ? idx->L0 : other; }
 
-  qk::RoundArgs args() const {
+  qk::RoundArgs args(int tag) const {
+    const qk::Store& st = store_of(tag);
     qk::RoundArgs a{};
     a.nq = cap;
     a.M = job.M;
@@ -121,27 +194,38 @@ struct quake_server {
     a.chunk_tiles = chunk_tiles;
     a.wmax = job.wmax;
     a.wscale = idx->tune.window_scale > 0 ? idx->tune.window_scale : 100;
-    a.slot_ids = job.batched && st().tiles * qk::TILE < (int64_t{1} << 31) ? 1 : 0;
+    a.slot_ids = job.batched && st.tiles * qk::TILE < (int64_t{1} << 31) ? 1 : 0;
     a.metric = idx->metric;
     a.dim = idx->d;
     a.tau_r = job.tau_r;
     a.tau_rho = job.tau_rho;
     a.items_cap = std::min<int64_t>(idx->ws.items_cap, items);
     a.blocks = blocks;
-    a.hits = st().d_hits;
+    a.hits = st.d_hits;
+    if (overlap) {
+      a.slot_tag = d_tag;
+      a.tag = tag;
+    }
     return a;
   }
 
-  // Size the search workspace for cap slots and mark every slot free.
-  void setup() {
+  // Work-item bound of a round and the workspace for it: the larger of the
+  // two versions' needs (partition sizes differ between them).
+  void size_items() {
     chunk_tiles = idx->tune.chunk_tiles > 0 ? idx->tune.chunk_tiles : 16;
     // long result lists are scanned by sorting whole items in LDS
     if (job.kk > qk::KMAX) chunk_tiles = std::min(chunk_tiles, qk::SORTED_ITEM_MAX / qk::TILE);
-    const int64_t mc = qk::max_chunks(st(), chunk_tiles);
+    int64_t mc = qk::max_chunks(st(), chunk_tiles);
+    if (have_twin) mc = std::max(mc, qk::max_chunks(other, chunk_tiles));
     items = std::max<int64_t>(cap * std::max(job.w0, 4) * 2, (int64_t)job.wmax * mc + 1);
     qk::ensure_queries(idx, cap);
     qk::ensure_workspace(idx, st().nlist, job.M, job.kk, items, job.batched ? cap * (int64_t)job.wmax : 0,
                          job.batched ? st().dp16 : 0, false);
+  }
+
+  // Size the search workspace for cap slots and mark every slot free.
+  void setup() {
+    size_items();
     QK_HIP(hipMemsetAsync(idx->ws.total, 0, qk::COUNTERS * sizeof(int64_t), s));
     qk::launch_mark_free(idx->ws, cap, s);
     blocks = qk::scan_blocks(idx, job.batched);
@@ -167,15 +251,23 @@ struct quake_server {
     if (job.batched) qk::launch_queries16(w, n, dp, st().dp16, job.dtype16, s, d_slots);
     qk::launch_init_slots(w, d_slots, n, job.kk, job.w0, s);
     st().window += n;
+    if (overlap) {
+      for (int64_t i = 0; i < n; ++i) slot_tag[slots[i]] = (uint8_t)front;
+      QK_HIP(hipMemcpyAsync(d_tag, slot_tag.data(), cap, hipMemcpyHostToDevice, s));
+      active_tag[front] += n;
+    }
   }
 
   // One scan round over all slots: plan, scan, commit.  No host round trip;
   // the harvest that follows reads which slots finished.
   void round() {
     qk::Workspace& w = idx->ws;
-    qk::RoundArgs a = args();
-    qk::launch_demand(w, st(), a, s);
-    qk::run_rounds(idx, st(), job, a, 1, s);
+    for (int tag : {front, 1 - front}) {
+      if (overlap ? active_tag[tag] == 0 : tag != front) continue;
+      qk::RoundArgs a = args(tag);
+      qk::launch_demand(w, store_of(tag), a, s);
+      qk::run_rounds(idx, store_of(tag), job, a, 1, s);
+    }
     ++rounds;
   }
 
@@ -184,14 +276,28 @@ struct quake_server {
     QK_HIP(hipMemcpyAsync(h_done, w.st_done, cap * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     QK_HIP(hipStreamSynchronize(s));
     std::vector<int32_t> fin;
-    for (int64_t q = 0; q < cap; ++q)
-      if (slot_ticket[q] != 0 && h_done[q]) fin.push_back((int32_t)q);
+    // finished slots grouped by store (the rerank reads the rows of the version the query scanned)
+    for (int tag : {front, 1 - front}) {
+      if (!overlap && tag != front) continue;  // one pass over the slots without tags
+      for (int64_t q = 0; q < cap; ++q)
+        if (slot_ticket[q] != 0 && h_done[q] && (!overlap || slot_tag[q] == tag)) fin.push_back((int32_t)q);
+    }
     if (fin.empty()) return;
     const int64_t n = (int64_t)fin.size();
+    QK_CHECK(n <= cap, QUAKE_E_DEVICE, "more finished slots than slots");  // the staging buffers hold cap
     std::memcpy(h_slots, fin.data(), n * sizeof(int32_t));
     QK_HIP(hipMemcpyAsync(d_slots, h_slots, n * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    qk::RoundArgs a = args();
-    if (job.batched) qk::launch_rerank(w, st(), a, s, job.rerank != 0, d_slots, n);
+    if (job.batched) {
+      int64_t at = 0;
+      for (int tag : {front, 1 - front}) {
+        int64_t cnt = 0;
+        while (at + cnt < n && (!overlap || slot_tag[fin[at + cnt]] == tag)) ++cnt;
+        if (cnt == 0) continue;
+        qk::RoundArgs a = args(tag);
+        qk::launch_rerank(w, store_of(tag), a, s, job.rerank != 0, d_slots + at, cnt);
+        at += cnt;
+      }
+    }
     qk::launch_gather_results(w, d_slots, n, job.k, job.kk, idx->metric, d_ids, d_dist, d_ns, d_rec, s);
     const int k = job.k;
     QK_HIP(hipMemcpyAsync(h_ids, d_ids, n * k * sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -213,6 +319,7 @@ struct quake_server {
         slot_ticket[q] = 0;
         free_slots.push_back(q);
         --active;
+        if (overlap) --active_tag[slot_tag[q]];
         ++completed;
       }
       last_done = t;
@@ -220,7 +327,8 @@ struct quake_server {
     cv_done.notify_all();
   }
 
-  void apply_update(Request& r) {
+  // Applies an update batch to idx->L0 / idx->idmap; returns its status.
+  int run_update(const Request& r) {
     const int64_t n = (int64_t)r.ids.size();
     int rc = QUAKE_OK;
     int64_t* d_i = idx->mem.alloc<int64_t>(std::max<int64_t>(n, 1));
@@ -241,7 +349,27 @@ struct quake_server {
     }
     idx->mem.release(d_i);
     idx->mem.release(d_v);
-    setup();  // partition sizes changed: work-item bounds and buffers follow
+    return rc;
+  }
+
+  // Runs an update batch on `other` (no search reads it) in place of idx->L0.
+  int run_update_on_other(const Request& r) {
+    std::swap(idx->L0, other);
+    std::swap(idx->idmap, other_map);
+    int rc;
+    try {
+      rc = run_update(r);
+    } catch (...) {
+      std::swap(idx->L0, other);
+      std::swap(idx->idmap, other_map);
+      throw;
+    }
+    std::swap(idx->L0, other);
+    std::swap(idx->idmap, other_map);
+    return rc;
+  }
+
+  void answer_update(const Request& r, int rc) {
     {
       std::lock_guard<std::mutex> lk(mu);
       Answer& an = answers[r.ticket];
@@ -251,6 +379,41 @@ struct quake_server {
     }
     cv_done.notify_all();
   }
+
+  // Drain mode: every slot is free when this runs.
+  void apply_update(Request& r) {
+    const int rc = run_update(r);
+    setup();  // partition sizes changed: work-item bounds and buffers follow
+    answer_update(r, rc);
+  }
+
+  // Overlap mode: the previous version has no searches left.  It replays what
+  // it missed, takes the new batch, and becomes the version new searches see.
+  void apply_update_overlapped(Request& r) {
+    if (!have_twin) {
+      clone_store(idx->mem, idx->L0, idx->idmap, other, other_map, s);
+      other.d_hits = idx->L0.d_hits;
+      have_twin = true;
+    }
+    for (const Request& p : replay) run_update_on_other(p);
+    replay.clear();
+    const int rc = run_update_on_other(r);
+    if (rc == QUAKE_OK) {
+      if (active_tag[front] > 0) ++overlapped;
+      std::swap(idx->L0, other);
+      std::swap(idx->idmap, other_map);
+      std::swap(idx->L0.window, other.window);  // the access window stays with the index
+      front = 1 - front;
+      replay.push_back(r);
+    }
+    release_graphs_of_old();
+    size_items();  // partition sizes changed: work-item bounds and buffers follow
+    answer_update(r, rc);
+  }
+
+  // Captured rounds key on the stores' arrays, which an update may
+  // reallocate: the cache is dropped so that no replay reads a freed buffer.
+  void release_graphs_of_old() { qk::release_graphs(idx); }
 
   void run() {
     try {
@@ -276,14 +439,18 @@ struct quake_server {
           }
           active += (int64_t)adm.size();
           max_active = std::max(max_active, active);
-          if (adm.empty() && active == 0 && !fifo.empty() && fifo.front().kind != 0) {
+          // an update runs once nothing reads the version it will change:
+          // the only version (drain mode) or the previous one (overlap mode)
+          const bool ready = overlap ? active_tag[1 - front] == 0 : active == 0;
+          if (adm.empty() && ready && !fifo.empty() && fifo.front().kind != 0) {
             upd = std::move(fifo.front());
             fifo.pop_front();
             has_upd = true;
           }
         }
         if (has_upd) {
-          apply_update(upd);
+          if (overlap) apply_update_overlapped(upd);
+          else apply_update(upd);
           continue;
         }
         if (!adm.empty()) admit(adm, slots);
@@ -329,8 +496,16 @@ struct quake_server {
 
   void release_buffers() {
     for (void* p : {(void*)d_x, (void*)d_pad, (void*)d_n2, (void*)d_scores, (void*)d_sel, (void*)d_cand, (void*)d_h,
-                    (void*)d_mq, (void*)d_slots, (void*)d_ids, (void*)d_dist, (void*)d_ns, (void*)d_rec})
+                    (void*)d_mq, (void*)d_slots, (void*)d_ids, (void*)d_dist, (void*)d_ns, (void*)d_rec,
+                    (void*)d_tag})
       idx->mem.release(p);
+    if (have_twin) {
+      // idx->L0 is the newest version; the older copy goes
+      qk::release_graphs(idx);
+      other.d_hits = nullptr;
+      free_store(idx->mem, other, other_map);
+      have_twin = false;
+    }
     for (void* p : {(void*)h_x, (void*)h_slots, (void*)h_done, (void*)h_ids, (void*)h_dist, (void*)h_ns,
                     (void*)h_rec})
       if (p) (void)hipHostFree(p);
@@ -378,8 +553,11 @@ int quake_server_create(quake_index* idx, const quake_server_params* params, qua
   QK_CHECK(idx && idx->magic == 0x51554b45u, QUAKE_E_STATE, "invalid index handle");
   QK_CHECK(idx->n_levels == 1, QUAKE_E_INVALID, "the serving loop runs on single-level indexes");
   QK_CHECK(params->max_slots >= 0, QUAKE_E_INVALID, "max_slots must be >= 0");
+  QK_CHECK(params->overlap_updates == 0 || params->overlap_updates == 1, QUAKE_E_INVALID,
+           "overlap_updates must be 0 or 1");
   std::unique_ptr<quake_server> srv(new quake_server());
   srv->idx = idx;
+  srv->overlap = params->overlap_updates != 0;
   srv->sp = params->search;
   srv->job = qk::resolve(idx, idx->L0, &srv->sp);
   int64_t cap = params->max_slots > 0 ? params->max_slots : 4096;
@@ -407,6 +585,11 @@ int quake_server_create(quake_index* idx, const quake_server_params* params, qua
     srv->d_dist = mem.alloc<float>(cap * k);
     srv->d_ns = mem.alloc<int32_t>(cap);
     srv->d_rec = mem.alloc<double>(cap);
+    if (srv->overlap) {
+      srv->d_tag = mem.alloc<uint8_t>(cap);
+      srv->slot_tag.assign(cap, 0);
+      QK_HIP(hipMemcpy(srv->d_tag, srv->slot_tag.data(), cap, hipMemcpyHostToDevice));
+    }
     srv->h_x = pinned<float>(cap * idx->d);
     srv->h_slots = pinned<int32_t>(cap);
     srv->h_done = pinned<int32_t>(cap);
@@ -501,6 +684,7 @@ int quake_server_stats(quake_server* srv, quake_server_report* out, int32_t rese
   out->max_in_flight = srv->max_active;
   out->epochs = srv->epochs;
   out->rounds = srv->rounds;
+  out->overlapped_updates = srv->overlapped;
   if (!srv->lat.empty()) {
     std::vector<double> l(srv->lat);
     std::sort(l.begin(), l.end());

@@ -30,7 +30,7 @@ EXPORTED = ("quake_build", "quake_search", "quake_search_noalloc", "quake_insert
             "quake_export_top", "quake_candidates", "quake_cap_table", "quake_profile", "quake_set_tuning",
             "quake_free", "quake_last_error", "quake_autotune", "quake_server_create", "quake_server_search", "quake_server_insert",
             "quake_server_delete", "quake_server_wait", "quake_server_stats", "quake_server_destroy",
-            "quake_access_stats", "quake_maintain")
+            "quake_access_stats", "quake_maintain", "quake_profile_latency")
 PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "scan_sets", "unused7")
 
 
@@ -97,14 +97,15 @@ class Tuning(ctypes.Structure):
 
 
 class ServerParams(ctypes.Structure):
-    _fields_ = [("max_slots", ctypes.c_int32), ("reserved", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t),
-                ("search", SearchParams)]
+    _fields_ = [("max_slots", ctypes.c_int32), ("overlap_updates", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_size_t), ("search", SearchParams)]
 
 
 class ServerReport(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_int64), ("queued", ctypes.c_int64), ("in_flight", ctypes.c_int64),
                 ("slots", ctypes.c_int64), ("max_in_flight", ctypes.c_int64), ("epochs", ctypes.c_int64),
-                ("rounds", ctypes.c_int64), ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
+                ("rounds", ctypes.c_int64), ("overlapped_updates", ctypes.c_int64),
+                ("p50_latency_s", ctypes.c_double), ("p99_latency_s", ctypes.c_double),
                 ("mean_latency_s", ctypes.c_double), ("qps", ctypes.c_double)]
 
 
@@ -155,6 +156,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.quake_export_top.argtypes = [vp, vp, vp, vp]
     lib.quake_access_stats.argtypes = [vp, i32, vp, ctypes.POINTER(i64), i32, vp]
     lib.quake_maintain.argtypes = [vp, ctypes.POINTER(MaintainParams), ctypes.POINTER(MaintainReport), vp]
+    lib.quake_profile_latency.argtypes = [vp, vp, i32, i32, ctypes.POINTER(SearchParams), i32, vp, vp]
     lib.quake_candidates.argtypes = [vp, vp, i64, ctypes.POINTER(SearchParams), vp, vp, ctypes.POINTER(i32), vp]
     lib.quake_cap_table.argtypes = [i32, ctypes.POINTER(f64)]
     lib.quake_profile.argtypes = [vp, i32, i32, vp]
@@ -324,6 +326,18 @@ def quake_access_stats(handle: int, level: int = 0, reset: bool = False):
     return hits, window.value
 
 
+def quake_profile_latency(handle: int, sizes, nq: int = 1024, reps: int = 3, **search_kw) -> np.ndarray:
+    """Microseconds per query of scanning one partition of each size (numpy float64)."""
+    sz = np.ascontiguousarray(sizes, dtype=np.int32)
+    out = np.zeros(sz.size, dtype=np.float64)
+    kw = dict(search_kw)
+    kw.setdefault("nprobe", 1)
+    p = _search_params(**kw)
+    _check(load_library().quake_profile_latency(handle, sz.ctypes.data, sz.size, nq, ctypes.byref(p), reps,
+                                                out.ctypes.data, _stream()))
+    return out
+
+
 def quake_maintain(handle: int, lambda_size, lambda_cost, *, tau=0.25, alpha=0.9, refine_radius=50, refine_iters=1,
                    split_iters=8, min_split_size=2, merge_below=0, hits=None, window=0, max_decisions=4096):
     """One maintenance pass; returns (report dict, decisions list of dicts)."""
@@ -398,9 +412,9 @@ def _host(a, dtype, ndim):
     return a
 
 
-def quake_server_create(handle: int, *, max_slots=0, hbm_budget_bytes=0, **search_kw) -> int:
+def quake_server_create(handle: int, *, max_slots=0, hbm_budget_bytes=0, overlap_updates=False, **search_kw) -> int:
     """Start a serving loop on an index; search_kw as for quake_search."""
-    p = ServerParams(max_slots, 0, hbm_budget_bytes, _search_params(**search_kw))
+    p = ServerParams(max_slots, int(bool(overlap_updates)), hbm_budget_bytes, _search_params(**search_kw))
     h = ctypes.c_void_p()
     _check(load_library().quake_server_create(handle, ctypes.byref(p), ctypes.byref(h)))
     return h.value
@@ -530,6 +544,9 @@ class Index:
 
     def access_stats(self, reset=False):
         return quake_access_stats(self.handle, 0, reset)
+
+    def profile_latency(self, sizes, nq=1024, reps=3, **search_kw):
+        return quake_profile_latency(self.handle, sizes, nq, reps, **search_kw)
 
     def maintain(self, lambda_size, lambda_cost, **kw):
         return quake_maintain(self.handle, lambda_size, lambda_cost, **kw)

@@ -178,3 +178,55 @@ def test_hbm_budget_limits_slots():
         _same(got, ref)
     finally:
         idx.free()
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_overlapped_updates_keep_submission_order(batched):
+    """With overlap_updates the server applies an update beside the searches
+    admitted before it (on a second copy of the store); every search still
+    answers, bit for bit, as on the index state of its epoch."""
+    from paper_2506_03437_amd import Server
+    X, Q, rng, mu = _data(10_000, 32, 19, nq=120)
+    kw = dict(k=10, recall_target=0.99, f_M=0.3)
+    storage = "bf16" if batched else "f32"
+    if batched:
+        kw.update(scan_mode="batched", scan_dtype="bf16", rerank_factor=4)
+    build = dict(nlist=40, storage=storage, kmeans_iters=4, seed=2)
+    B = (mu[rng.integers(0, 24, 3000)] + rng.standard_normal((3000, 32))).astype(np.float32)
+    bid = np.arange(60_000, 63_000, dtype=np.int64)
+    idx = gu.build(X, **build)
+    ref = gu.build(X, **build)  # builds are bit-reproducible
+    try:
+        r0 = gu.search(idx, Q, **kw)[:3]
+        ref.insert(gu.to_dev(B), gu.to_dev(bid))
+        r1 = gu.search(ref, Q, **kw)[:3]
+        with Server(idx, max_slots=64, overlap_updates=True, **kw) as srv:
+            ta = srv.search(Q)
+            ti = srv.insert(B, bid)
+            tc = srv.search(Q)
+            td = srv.delete(bid)
+            te = srv.search(Q)
+            tdup = srv.insert(B[:2], np.array([7, 7], dtype=np.int64))  # rejected: the versions stay equal
+            tf = srv.search(Q)
+            res = {}
+            for name, ts in (("a", ta), ("c", tc), ("e", te), ("f", tf)):
+                out = [srv.wait(t, timeout_s=60.0) for t in ts]
+                assert all(o[3] == 0 for o in out)
+                res[name] = (np.stack([o[0] for o in out]), np.stack([o[1] for o in out]),
+                             np.array([o[2] for o in out]))
+            assert srv.wait(ti, timeout_s=60.0)[3] == 0
+            assert srv.wait(td, timeout_s=60.0)[3] == 0
+            assert srv.wait(tdup, timeout_s=60.0)[3] == -4
+            st = srv.stats()
+        print(f"[serving] {st}", flush=True)
+        assert st["epochs"] == 3 and st["overlapped_updates"] >= 1
+        assert idx.stats()[0] == X.shape[0]
+        r2 = gu.search(idx, Q, **kw)[:3]  # the index now holds the newest version
+        _same(res["a"], r0)
+        _same(res["c"], r1)
+        _same(res["e"], r2)
+        _same(res["f"], r2)
+        assert not all((x == y).all() for x, y in zip(r0, r1))
+    finally:
+        idx.free()
+        ref.free()
