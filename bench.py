@@ -183,14 +183,20 @@ def cpu_baseline_leg(X, Q, sample_rows, idx, workload, tau, seconds, gt_seconds,
     return base
 
 
-def serving_leg(idx, w, X, tau, rates, n_requests, hbm_budget):
+def serving_leg(make_index, w, X, tau, rates, n_requests, hbm_budget, rerank_factor, overlap, compare):
     """Continuous batching through the serving loop on the same index: a
     trace of single-query requests (Zipf(1.2) over the mixture components,
     popular set re-drawn every 10,000 requests) with a 1% insert batch and a
     1% delete batch after every 10,000 queries.  Each offered rate replays the
     trace open-loop with Poisson arrivals; the closed-loop run submits it all
     at once (the sustained rate).  Latency = arrival (enqueue) to answer ready.
-    Updates are undone between runs so every run starts from the same index."""
+    By default an update waits for the running searches to finish; with
+    `overlap` it is applied beside the searches admitted before it (on a
+    second copy of the store); `compare` adds a closed-loop run in the other
+    mode.  Every run
+    starts from a fresh build of the same index (make_index); the submitter
+    sleeps between arrivals so that the library's allocator callbacks, which
+    take the interpreter lock, are not held up by it."""
     import numpy as np
     import synth
     from paper_2506_03437_amd import Server
@@ -199,12 +205,13 @@ def serving_leg(idx, w, X, tau, rates, n_requests, hbm_budget):
     ts = synth.TraceSpec(n_requests=n_requests, drift_every=10_000, update_every=10_000, update_frac=0.01,
                          new_components=10)
     events = synth.serving_trace(w.spec, np.arange(n_live, dtype=np.int64), ts)
-    kw = dict(k=w.k, recall_target=tau, f_M=w.f_M, scan_mode="batched", scan_dtype=w.storage, rerank_factor=4)
+    kw = dict(k=w.k, recall_target=tau, f_M=w.f_M, scan_mode="batched", scan_dtype=w.storage,
+              rerank_factor=rerank_factor)
 
-    def replay(rate):
+    def replay(rate, overlapped=overlap):
         rng = np.random.default_rng(11)
-        inserted, deleted = [], []
-        with Server(idx, hbm_budget_bytes=hbm_budget, **kw) as srv:
+        idx = make_index()
+        with Server(idx, hbm_budget_bytes=hbm_budget, overlap_updates=overlapped, **kw) as srv:
             slots = srv.stats()["slots"]
             tickets, upd = [], []
             t0 = time.perf_counter()
@@ -224,43 +231,38 @@ def serving_leg(idx, w, X, tau, rates, n_requests, hbm_budget):
                         if j > i:
                             tickets += srv.search(Qb[i:j])
                             i = j
+                        else:
+                            time.sleep(max(0.0, min(float(arr[i]) - now, 1e-3)))
                 elif ev[0] == "insert":
                     upd.append(srv.insert(ev[1], ev[2]))
-                    inserted.append(ev[2])
                 else:
                     upd.append(srv.delete(ev[1]))
-                    deleted.append(ev[1])
             for t in tickets:
                 srv.wait(t, 300.0)
             statuses = [srv.wait(t, 300.0)[3] for t in upd]
             st = srv.stats()
+        idx.free()
         assert all(x == 0 for x in statuses), f"update batches failed: {statuses}"
-        # undo the updates: remove what was inserted and is still live, restore what was deleted
-        import torch
-        dev = torch.device("cuda", 0)
-        ins = np.concatenate(inserted) if inserted else np.zeros(0, np.int64)
-        dels = np.concatenate(deleted) if deleted else np.zeros(0, np.int64)
-        still = np.setdiff1d(ins, dels)
-        if still.size:
-            idx.delete(torch.from_numpy(still).to(dev))
-        back = dels[dels < n_live]
-        if back.size:
-            Xb = np.ascontiguousarray(X[back])
-            idx.insert(torch.from_numpy(Xb).to(dev), torch.from_numpy(back).to(dev))
-        torch.cuda.synchronize()
-        assert idx.stats()[0] == n_live
         return {"offered_qps": rate, "achieved_qps": st["qps"], "p50_ms": st["p50_latency_s"] * 1e3,
                 "p99_ms": st["p99_latency_s"] * 1e3, "mean_ms": st["mean_latency_s"] * 1e3,
                 "completed": st["completed"], "slots": slots, "max_in_flight": st["max_in_flight"],
-                "rounds": st["rounds"], "update_batches": len(statuses)}
+                "rounds": st["rounds"], "update_batches": len(statuses),
+                "overlapped_updates": st["overlapped_updates"], "updates_beside_searches": overlapped}
 
     out = {"trace": f"{n_requests} single-query requests, Zipf(1.2) components drifting every 10,000, "
                     f"1% insert + 1% delete batch every 10,000 queries", "hbm_budget_bytes": hbm_budget,
-           "recall_target": tau, "start": f"{n_live} rows of {w.name}", "runs": []}
+           "recall_target": tau, "start": f"{n_live} rows of {w.name}", "updates_beside_searches": overlap,
+           "runs": []}
     closed = replay(None)
     out["sustained"] = closed
     log(f"serving closed-loop: {closed['achieved_qps']:.0f} QPS, p50 {closed['p50_ms']:.2f} ms, "
-        f"p99 {closed['p99_ms']:.2f} ms, slots {closed['slots']}")
+        f"p99 {closed['p99_ms']:.2f} ms, slots {closed['slots']}, "
+        f"{closed['overlapped_updates']} of {closed['update_batches']} updates beside running searches")
+    if compare:
+        other = replay(None, overlapped=not overlap)
+        out["sustained_other_update_mode"] = other
+        log(f"serving closed-loop, {'draining at' if overlap else 'beside'} updates: {other['achieved_qps']:.0f} QPS, "
+            f"p50 {other['p50_ms']:.2f} ms, p99 {other['p99_ms']:.2f} ms")
     for r in rates:
         res = replay(r)
         out["runs"].append(res)
@@ -296,6 +298,11 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=0, help="> 0 runs the serving-loop leg")
     ap.add_argument("--serving-rates", default="20000,100000,400000")
     ap.add_argument("--serving-hbm-budget", type=int, default=256 << 20)
+    ap.add_argument("--serving-overlap", action="store_true",
+                    help="serving: apply each update beside the searches admitted before it (second store copy) "
+                         "instead of draining them first")
+    ap.add_argument("--serving-compare", action="store_true",
+                    help="serving: add a closed-loop run in the other update mode")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
@@ -342,7 +349,11 @@ def main():
         idx = Index(Xd, metric=w.metric, nlist=w.nlist, storage=w.storage, n_levels=2, nlist_top=w.nlist_top,
                     centroids=torch.from_numpy(centres).to(dev), kmeans_iters=10, seed=1)
     else:
-        idx = Index(Xd, metric=w.metric, nlist=w.nlist, storage=w.storage, kmeans_iters=10, seed=1)
+        # serving inserts: 5% spare capacity per partition and in the arena;
+        # without the plain FP32 path the index keeps no FP32 tile copy
+        idx = Index(Xd, metric=w.metric, nlist=w.nlist, storage=w.storage, kmeans_iters=10, seed=1,
+                    capacity_slack=0.05 if args.serving_requests > 0 else 0.0,
+                    f32_tiles="plain_fp32" in args.paths.split(","))
     del Xd
     torch.cuda.synchronize()
     log(f"built {w.nlist} partitions{f' under {w.nlist_top}' if two_level else ''} in "
@@ -496,8 +507,22 @@ def main():
     serving = None
     if args.serving_requests > 0 and batched is not None:
         rates = [float(r) for r in args.serving_rates.split(",") if r]
-        serving = serving_leg(idx, w, X, batched["recall_target"], rates, args.serving_requests,
-                              args.serving_hbm_budget)
+        idx.free()
+        idx = None
+
+        def make_index():
+            Xd = torch.from_numpy(X).to(dev)
+            out = Index(Xd, metric=w.metric, nlist=w.nlist, storage=w.storage, kmeans_iters=10, seed=1,
+                        capacity_slack=0.05, f32_tiles=False)
+            del Xd
+            if batched.get("tuning"):
+                out.set_tuning(**batched["tuning"])  # the knobs the batched leg was timed with
+            torch.cuda.synchronize()
+            return out
+
+        serving = serving_leg(make_index, w, X, batched["recall_target"], rates, args.serving_requests,
+                              args.serving_hbm_budget, args.rerank_factor, args.serving_overlap,
+                              args.serving_compare)
 
     roof = None
     if batched is not None:
@@ -563,7 +588,8 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
-    idx.free()
+    if idx is not None:
+        idx.free()
 
 
 if __name__ == "__main__":

@@ -87,7 +87,11 @@ typedef struct {
                               centroids, each centroid is the mean of its rows (unit length for
                               QUAKE_IP) and every partition must receive a row */
   size_t hbm_budget_bytes; /* 0 = unlimited; else every device allocation of the index counts */
-  double capacity_slack;   /* extra partition capacity for inserts, fraction of size (>= 0) */
+  double capacity_slack;   /* extra partition capacity for inserts, fraction of size (>= 0); the
+                              arena also keeps that fraction of spare tiles for partitions that outgrow theirs */
+  int32_t drop_f32_tiles;  /* 1 (with a 16-bit copy): keep no FP32 tile copy of level 0 - only the
+                              16-bit tiles the batched scan reads and the row-major FP32 copy the
+                              rerank reads (a third less memory); plain FP32 searches are then INVALID */
 } quake_build_params;
 
 /* Search parameters.  Exactly one of nprobe > 0 (fixed number of partitions)

@@ -60,6 +60,7 @@ int candidate_count(double f, int64_t n) {
 }
 
 void* DeviceMemory::raw_alloc(size_t bytes) {
+  std::lock_guard<std::mutex> lk(mu_);
   QK_CHECK(!forbid, QUAKE_E_STATE, "an allocation was attempted inside a call that allocates nothing");
   if (bytes == 0) bytes = 256;
   if (budget && used + bytes > budget)
@@ -84,6 +85,7 @@ void* DeviceMemory::raw_alloc(size_t bytes) {
 
 void DeviceMemory::release(void* p) {
   if (!p) return;
+  std::lock_guard<std::mutex> lk(mu_);
   for (size_t i = 0; i < blocks_.size(); ++i)
     if (blocks_[i].p == p) {
       if (user.alloc) {
@@ -266,11 +268,13 @@ void kmeans(qk::DeviceMemory& mem, const float* xpad, int64_t n, int dp, int64_t
 
 // ---------------------------------------------------------------- the store
 
-void alloc_store_arrays(quake_index* idx, Store& st, int64_t tiles, int dtype16, hipStream_t s) {
+void alloc_store_arrays(quake_index* idx, Store& st, int64_t tiles, int dtype16, bool f32_tiles, hipStream_t s) {
   auto& mem = idx->mem;
   const size_t slots = (size_t)tiles * qk::TILE;
-  st.v32 = mem.alloc<float>(slots * st.dp);
-  QK_HIP(hipMemsetAsync(st.v32, 0, slots * st.dp * sizeof(float), s));
+  if (f32_tiles) {
+    st.v32 = mem.alloc<float>(slots * st.dp);
+    QK_HIP(hipMemsetAsync(st.v32, 0, slots * st.dp * sizeof(float), s));
+  }
   if (dtype16 != QUAKE_F32) {
     st.v16 = mem.alloc<uint16_t>(slots * st.dp16);
     QK_HIP(hipMemsetAsync(st.v16, 0, slots * st.dp16 * sizeof(uint16_t), s));
@@ -303,7 +307,7 @@ void upload_table(Store& st, hipStream_t s) {
 // slack, rounded up to whole tiles; rows keep their input order within a
 // partition.
 void build_store(quake_index* idx, Store& st, const float* xin, int d, const int64_t* ids, int64_t n,
-                 const int32_t* d_assign, double slack, int dtype16, hipStream_t s) {
+                 const int32_t* d_assign, double slack, int dtype16, bool f32_tiles, hipStream_t s) {
   std::vector<int32_t> a(n);
   QK_HIP(hipMemcpyAsync(a.data(), d_assign, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   QK_HIP(hipStreamSynchronize(s));
@@ -330,7 +334,12 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
     slot[i] = st.off[p] * qk::TILE + fill[p]++;
   }
   st.dp16 = qk::padded_dim16(st.d);
-  alloc_store_arrays(idx, st, std::max<int64_t>(tiles, 1), dtype16, s);
+  // with slack, the arena also keeps that fraction of spare tiles for
+  // partitions that outgrow their capacity (so that the first overflowing
+  // inserts do not have to grow, and copy, the whole arena)
+  const int64_t spare = slack > 0 ? (int64_t)std::ceil(tiles * slack) : 0;
+  alloc_store_arrays(idx, st, std::max<int64_t>(tiles + spare, 1), dtype16, f32_tiles, s);
+  st.tile_part.resize(std::max<int64_t>(tiles + spare, 1), -1);
   st.used_tiles = tiles;
   st.d_off = idx->mem.alloc<int64_t>(N);
   st.d_size = idx->mem.alloc<int32_t>(N);
@@ -350,18 +359,77 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
   st.live = n;
 }
 
-// Enlarge the arena to at least `need` tiles (allocates before touching the
-// old arrays, so a failure leaves the store as it was).
-void grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s) {
-  if (need <= st.tiles) return;
-  const int64_t tiles = std::max<int64_t>(need, st.tiles + st.tiles / 2);
+// Copy every partition's filled tiles back to back into a fresh arena of
+// `tiles` tiles (relocations leave their old tiles behind; this drops them).
+// Store slots change: the caller rebuilds the id map.
+void repack_arena(quake_index* idx, Store& st, int64_t tiles, hipStream_t s) {
   Store fresh;
   fresh.d = st.d;
   fresh.dp = st.dp;
   fresh.dp16 = st.dp16;
-  alloc_store_arrays(idx, fresh, tiles, st.v16 ? idx->storage : QUAKE_F32, s);
+  alloc_store_arrays(idx, fresh, tiles, st.v16 ? idx->storage : QUAKE_F32, st.v32 != nullptr, s);
+  std::vector<int64_t> off(st.nlist);
+  std::vector<int32_t> tile_part(tiles, -1);
+  int64_t next = 0;
+  for (int64_t p = 0; p < st.nlist; ++p) {
+    off[p] = next;
+    for (int64_t t = 0; t < st.cap[p] / qk::TILE; ++t) tile_part[next + t] = (int32_t)p;
+    const size_t n = (size_t)((st.size[p] + qk::TILE - 1) / qk::TILE) * qk::TILE;
+    const size_t a = (size_t)st.off[p] * qk::TILE, b = (size_t)next * qk::TILE;
+    if (n > 0) {
+      if (st.v32)
+        QK_HIP(hipMemcpyAsync(fresh.v32 + b * st.dp, st.v32 + a * st.dp, n * st.dp * sizeof(float),
+                              hipMemcpyDeviceToDevice, s));
+      if (st.v16)
+        QK_HIP(hipMemcpyAsync(fresh.v16 + b * st.dp16, st.v16 + a * st.dp16, n * st.dp16 * sizeof(uint16_t),
+                              hipMemcpyDeviceToDevice, s));
+      if (st.v16n) QK_HIP(hipMemcpyAsync(fresh.v16n + b, st.v16n + a, n * sizeof(float), hipMemcpyDeviceToDevice, s));
+      if (st.rows32)
+        QK_HIP(hipMemcpyAsync(fresh.rows32 + b * st.dp, st.rows32 + a * st.dp, n * st.dp * sizeof(float),
+                              hipMemcpyDeviceToDevice, s));
+      QK_HIP(hipMemcpyAsync(fresh.ids + b, st.ids + a, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    }
+    next += st.cap[p] / qk::TILE;
+  }
+  QK_HIP(hipStreamSynchronize(s));
+  for (void* p : {(void*)st.v32, (void*)st.v16, (void*)st.v16n, (void*)st.rows32, (void*)st.ids}) idx->mem.release(p);
+  st.v32 = fresh.v32;
+  st.v16 = fresh.v16;
+  st.v16n = fresh.v16n;
+  st.rows32 = fresh.rows32;
+  st.ids = fresh.ids;
+  st.tiles = tiles;
+  st.used_tiles = next;
+  st.off.swap(off);
+  st.tile_part.swap(tile_part);
+}
+
+// Enlarge the arena to at least `need` tiles (allocates before touching the
+// old arrays, so a failure leaves the store as it was).  With `repack`, when
+// tiles left behind by relocations make up a quarter of the used arena the
+// partitions are packed into a fresh arena instead (slots change: the caller
+// rebuilds the id map; returns true then).
+bool grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s, bool repack = false) {
+  if (need <= st.tiles) return false;
+  if (repack) {
+    int64_t held = 0;
+    for (int64_t p = 0; p < st.nlist; ++p) held += st.cap[p] / qk::TILE;
+    if ((st.used_tiles - held) * 4 >= st.used_tiles) {
+      const int64_t extra = need - st.used_tiles;
+      repack_arena(idx, st, held + extra + (held + extra) / 8, s);
+      return true;
+    }
+  }
+  // an eighth more at a time: growing copies the arena, and the old and new
+  // arrays coexist while it does (an index of tens of GB must fit twice)
+  const int64_t tiles = std::max<int64_t>(need, st.tiles + st.tiles / 8);
+  Store fresh;
+  fresh.d = st.d;
+  fresh.dp = st.dp;
+  fresh.dp16 = st.dp16;
+  alloc_store_arrays(idx, fresh, tiles, st.v16 ? idx->storage : QUAKE_F32, st.v32 != nullptr, s);
   const size_t used = (size_t)st.used_tiles * qk::TILE;
-  QK_HIP(hipMemcpyAsync(fresh.v32, st.v32, used * st.dp * sizeof(float), hipMemcpyDeviceToDevice, s));
+  if (st.v32) QK_HIP(hipMemcpyAsync(fresh.v32, st.v32, used * st.dp * sizeof(float), hipMemcpyDeviceToDevice, s));
   if (st.v16) QK_HIP(hipMemcpyAsync(fresh.v16, st.v16, used * st.dp16 * sizeof(uint16_t), hipMemcpyDeviceToDevice, s));
   if (st.v16n) QK_HIP(hipMemcpyAsync(fresh.v16n, st.v16n, used * sizeof(float), hipMemcpyDeviceToDevice, s));
   if (st.rows32) QK_HIP(hipMemcpyAsync(fresh.rows32, st.rows32, used * st.dp * sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -375,6 +443,7 @@ void grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s) {
   st.ids = fresh.ids;
   st.tiles = tiles;
   st.tile_part.resize(tiles, -1);
+  return false;
 }
 
 // Copy partition p's filled tiles to `tiles` fresh tiles at the end of the
@@ -385,7 +454,9 @@ void relocate(Store& st, int64_t p, int32_t cap, hipStream_t s) {
   const size_t n = (size_t)ntiles * qk::TILE;
   const size_t a = (size_t)from * qk::TILE, b = (size_t)to * qk::TILE;
   if (n > 0) {
-    QK_HIP(hipMemcpyAsync(st.v32 + b * st.dp, st.v32 + a * st.dp, n * st.dp * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (st.v32)
+      QK_HIP(hipMemcpyAsync(st.v32 + b * st.dp, st.v32 + a * st.dp, n * st.dp * sizeof(float),
+                            hipMemcpyDeviceToDevice, s));
     if (st.v16)
       QK_HIP(hipMemcpyAsync(st.v16 + b * st.dp16, st.v16 + a * st.dp16, n * st.dp16 * sizeof(uint16_t),
                             hipMemcpyDeviceToDevice, s));
@@ -407,7 +478,7 @@ void relocate(Store& st, int64_t p, int32_t cap, hipStream_t s) {
 // Fill the holes (deleted slots, id -1) below the live count of every
 // partition p with which[p] set from the partition's live tail, so that its
 // first size - tomb slots hold its vectors; moved vectors keep their ids.
-void compact(quake_index* idx, Store& st, const std::vector<char>& which, hipStream_t s) {
+void compact(quake_index* idx, Store& st, qk::IdMap& map, const std::vector<char>& which, hipStream_t s) {
   std::vector<int64_t> src, dst, moved_ids;
   for (int64_t p = 0; p < st.nlist; ++p) {
     if (!which[p] || st.tomb[p] == 0) continue;
@@ -438,15 +509,14 @@ void compact(quake_index* idx, Store& st, const std::vector<char>& which, hipStr
     QK_HIP(hipMemcpyAsync(d_dst.p, dst.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
     QK_HIP(hipMemcpyAsync(d_ids.p, moved_ids.data(), m * sizeof(int64_t), hipMemcpyHostToDevice, s));
     qk::launch_move_slots(st, d_src.p, d_dst.p, m, s);
-    qk::launch_map_update(idx->idmap, d_ids.p, d_dst.p, m, s);
+    qk::launch_map_update(map, d_ids.p, d_dst.p, m, s);
     QK_HIP(hipStreamSynchronize(s));
   }
 }
 
 // ---------------------------------------------------------------- id map
 
-void map_rebuild(quake_index* idx, int64_t expect, hipStream_t s) {
-  qk::IdMap& m = idx->idmap;
+void map_rebuild(quake_index* idx, qk::IdMap& m, const Store& st, int64_t expect, hipStream_t s) {
   uint64_t cap = 1024;
   while (cap < (uint64_t)std::max<int64_t>(expect, 1) * 4) cap <<= 1;
   int64_t* keys = idx->mem.alloc<int64_t>(cap);
@@ -463,14 +533,15 @@ void map_rebuild(quake_index* idx, int64_t expect, hipStream_t s) {
   m.vals = vals;
   m.mask = cap - 1;
   QK_HIP(hipMemsetAsync(m.keys, 0xff, cap * sizeof(int64_t), s));
-  qk::launch_map_insert_store(m, idx->L0.ids, idx->L0.used_tiles * qk::TILE, s);
-  m.used = idx->L0.live;
+  qk::launch_map_insert_store(m, st.ids, st.used_tiles * qk::TILE, s);
+  m.used = st.live;
 }
 
-int64_t count_missing(quake_index* idx, const int64_t* ids, int64_t n, int64_t* slots, hipStream_t s) {
+int64_t count_missing(quake_index* idx, const qk::IdMap& m, const int64_t* ids, int64_t n, int64_t* slots,
+                      hipStream_t s) {
   Tmp<int64_t> miss(idx->mem, 1);
   QK_HIP(hipMemsetAsync(miss.p, 0, sizeof(int64_t), s));
-  qk::launch_map_find(idx->idmap, ids, n, slots, miss.p, s);
+  qk::launch_map_find(m, ids, n, slots, miss.p, s);
   int64_t h = 0;
   QK_HIP(hipMemcpyAsync(&h, miss.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   QK_HIP(hipStreamSynchronize(s));
@@ -503,14 +574,122 @@ void require_finite(quake_index* idx, const float* x, int64_t count, const char*
 
 namespace qk {
 
-void store_grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s) { grow_arena(idx, st, need, s); }
+void store_grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s) { grow_arena(idx, st, need, s, false); }
 void store_relocate(Store& st, int64_t p, int32_t cap, hipStream_t s) { relocate(st, p, cap, s); }
 void store_upload_table(Store& st, hipStream_t s) { upload_table(st, s); }
 void store_compact(quake_index* idx, Store& st, const std::vector<char>& which, hipStream_t s) {
-  compact(idx, st, which, s);
+  compact(idx, st, idx->idmap, which, s);
 }
 int store_fixed_point_bits(DeviceMemory& mem, const float* x, int64_t n, int dp, hipStream_t s) {
   return fixed_point_bits(mem, x, n, dp, s);
+}
+
+// Insert n rows x[n][d] with ids into the level-0 store `st` and its id map
+// (routed: the partition of every row, else each goes to its nearest
+// centroid).  The batch is checked whole before anything changes: ids >= 0,
+// no id twice, none already present.  Partitions that overflow move to fresh
+// tiles with 1.5x their need.
+void insert_rows(quake_index* idx, Store& st, IdMap& map, const float* x, const int64_t* ids, int64_t n,
+                 const std::vector<int32_t>* routed, hipStream_t s) {
+  std::vector<int64_t> h_ids(n);
+  QK_HIP(hipMemcpyAsync(h_ids.data(), ids, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  QK_CHECK(std::all_of(h_ids.begin(), h_ids.end(), [](int64_t v) { return v >= 0; }), QUAKE_E_INVALID,
+           "ids must be >= 0");
+  {
+    std::vector<int64_t> sorted(h_ids);
+    std::sort(sorted.begin(), sorted.end());
+    QK_CHECK(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(), QUAKE_E_DUPLICATE,
+             "the batch repeats an id");
+  }
+  QK_CHECK(count_missing(idx, map, ids, n, nullptr, s) == n, QUAKE_E_DUPLICATE,
+           "the batch names an id already present");
+  const int dp = idx->dp;
+  std::vector<int32_t> part(n);
+  if (routed) {
+    part = *routed;
+  } else {
+    std::unique_ptr<Tmp<float>> xpad_buf;
+    const float* xpad = x;
+    if (dp != idx->d) {
+      xpad_buf.reset(new Tmp<float>(idx->mem, (size_t)n * dp));
+      launch_pad_rows(x, n, idx->d, dp, xpad_buf->p, nullptr, s);
+      xpad = xpad_buf->p;
+    }
+    Tmp<int32_t> assign(idx->mem, n);
+    launch_assign(xpad, n, dp, st.centroids, st.nlist, idx->metric, assign.p, s);
+    QK_HIP(hipMemcpyAsync(part.data(), assign.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+  }
+  std::vector<int64_t> cnt(st.nlist, 0);
+  for (int64_t i = 0; i < n; ++i) cnt[part[i]]++;
+  std::vector<std::pair<int64_t, int32_t>> moves;
+  int64_t extra = 0;
+  for (int64_t p = 0; p < st.nlist; ++p) {
+    if (cnt[p] == 0 || st.size[p] + cnt[p] <= st.cap[p]) continue;
+    const int64_t want = round_up((int64_t)std::ceil((st.size[p] + cnt[p]) * 1.5), TILE);
+    QK_CHECK(want <= INT32_MAX, QUAKE_E_INVALID, "partition too large");
+    moves.push_back({p, (int32_t)want});
+    extra += want / TILE;
+  }
+  const bool repacked = grow_arena(idx, st, st.used_tiles + extra, s, true);
+  for (auto& mv : moves) relocate(st, mv.first, mv.second, s);
+  std::vector<int64_t> slot(n);
+  std::vector<int64_t> fill(st.nlist, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t p = part[i];
+    slot[i] = st.off[p] * TILE + st.size[p] + fill[p]++;
+  }
+  Tmp<int64_t> d_slot(idx->mem, n);
+  QK_HIP(hipMemcpyAsync(d_slot.p, slot.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  launch_scatter(x, n, idx->d, dp, st.dp16, ids, d_slot.p, st.v32, st.v16, st.v16 ? idx->storage : QUAKE_F32,
+                 st.rows32, st.ids, s);
+  launch_norm16_slots(st, d_slot.p, n, idx->storage, s);
+  for (int64_t p = 0; p < st.nlist; ++p) st.size[p] += (int32_t)cnt[p];
+  upload_table(st, s);
+  st.live += n;
+  if (repacked || !moves.empty() || (map.used + n) * 2 > (int64_t)map.mask + 1) {
+    map_rebuild(idx, map, st, st.live, s);
+  } else {
+    launch_map_insert(map, ids, d_slot.p, n, s);
+    map.used += n;
+  }
+  QK_HIP(hipStreamSynchronize(s));
+}
+
+// Delete the rows with the n given ids from `st` and its id map (the batch is
+// rejected whole, NOTFOUND, when an id repeats or is absent).  Deleted slots
+// hold id -1; a partition with a quarter of its slots deleted is compacted.
+void delete_rows(quake_index* idx, Store& st, IdMap& map, const int64_t* ids, int64_t n, hipStream_t s) {
+  std::vector<int64_t> h_ids(n);
+  QK_HIP(hipMemcpyAsync(h_ids.data(), ids, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  {
+    std::vector<int64_t> sorted(h_ids);
+    std::sort(sorted.begin(), sorted.end());
+    QK_CHECK(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(), QUAKE_E_NOTFOUND,
+             "the batch repeats an id");
+  }
+  Tmp<int64_t> slots(idx->mem, n);
+  QK_CHECK(count_missing(idx, map, ids, n, slots.p, s) == 0, QUAKE_E_NOTFOUND,
+           "the batch names an id that is absent");
+  launch_mark_deleted(st, slots.p, n, s);
+  launch_map_erase(map, ids, n, s);
+  std::vector<int64_t> h_slots(n);
+  QK_HIP(hipMemcpyAsync(h_slots.data(), slots.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  st.live -= n;
+  std::vector<char> touched(st.nlist, 0);
+  for (int64_t sl : h_slots) {
+    const int32_t p = st.tile_part[sl / TILE];
+    st.tomb[p]++;
+    touched[p] = 1;
+  }
+  for (int64_t p = 0; p < st.nlist; ++p)
+    if (touched[p] && st.tomb[p] * 4 < st.size[p]) touched[p] = 0;
+  compact(idx, st, map, touched, s);
+  upload_table(st, s);
+  QK_HIP(hipStreamSynchronize(s));
 }
 
 int64_t max_chunks(const Store& st, int chunk_tiles) {
@@ -542,6 +721,8 @@ Job resolve(const quake_index* idx, const Store& st, const quake_search_params* 
   r.dtype16 = p->scan_dtype;
   QK_CHECK(r.batched == (p->scan_dtype != QUAKE_F32 ? 1 : 0), QUAKE_E_INVALID,
            "the batched scan runs on the 16-bit copy (scan_dtype BF16/F16) and the plain scan on FP32");
+  QK_CHECK(r.batched || st.v32, QUAKE_E_INVALID,
+           "the index keeps no FP32 tile copy (drop_f32_tiles): search with the batched scan");
   QK_CHECK(p->rerank_factor >= -1, QUAKE_E_INVALID, "rerank_factor must be >= -1");
   QK_CHECK(p->rerank_factor >= 0 || r.batched, QUAKE_E_INVALID, "rerank_factor -1 is for the batched scan");
   r.rerank = p->rerank_factor >= 0 ? 1 : 0;
@@ -1123,6 +1304,9 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const 
   if (params->n_levels == 2)
     QK_CHECK(params->nlist_top >= 1 && params->nlist_top <= params->nlist, QUAKE_E_INVALID,
              "nlist_top must be in [1, nlist]");
+  QK_CHECK(params->drop_f32_tiles == 0 || (params->drop_f32_tiles == 1 && params->storage_dtype != QUAKE_F32),
+           QUAKE_E_INVALID, "drop_f32_tiles needs a 16-bit copy (storage_dtype BF16 or F16)");
+  const bool f32_tiles = params->drop_f32_tiles == 0;
   hipStream_t s = as_stream(stream);
   std::unique_ptr<quake_index> idx(new quake_index());
   if (allocator && allocator->alloc) idx->mem.user = *allocator;
@@ -1186,13 +1370,15 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const 
     kmeans(idx->mem, xpad, n, dp, L0.nlist, params->kmeans_iters, params->seed, idx->metric, L0.centroids, s);
   }
   if (params->assign) {
-    build_store(idx.get(), L0, x, d, ids, n, params->assign, params->capacity_slack, params->storage_dtype, s);
+    build_store(idx.get(), L0, x, d, ids, n, params->assign, params->capacity_slack, params->storage_dtype,
+                f32_tiles, s);
   } else {
     Tmp<int32_t> assign(idx->mem, n);
     qk::launch_assign(xpad, n, dp, L0.centroids, L0.nlist, idx->metric, assign.p, s);
-    build_store(idx.get(), L0, x, d, ids, n, assign.p, params->capacity_slack, params->storage_dtype, s);
+    build_store(idx.get(), L0, x, d, ids, n, assign.p, params->capacity_slack, params->storage_dtype, f32_tiles,
+                s);
   }
-  map_rebuild(idx.get(), n, s);
+  map_rebuild(idx.get(), idx->idmap, idx->L0, n, s);
 
   if (idx->n_levels == 2) {
     Store& L1 = idx->L1;
@@ -1204,7 +1390,7 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const 
            params->seed ^ 0x9e3779b97f4a7c15ull, idx->metric, L1.centroids, s);
     idx->top_of = idx->mem.alloc<int32_t>(L0.nlist);
     qk::launch_assign(L0.centroids, L0.nlist, dp, L1.centroids, L1.nlist, idx->metric, idx->top_of, s);
-    build_store(idx.get(), L1, L0.centroids, dp, nullptr, L0.nlist, idx->top_of, 0.0, QUAKE_F32, s);
+    build_store(idx.get(), L1, L0.centroids, dp, nullptr, L0.nlist, idx->top_of, 0.0, QUAKE_F32, true, s);
   }
 
   idx->h_cap_table.resize(qk::CAP_TABLE_POINTS);
@@ -1415,89 +1601,35 @@ int quake_insert(quake_index* idx, const float* x, const int64_t* ids, int64_t n
   if (n == 0) return QUAKE_OK;
   QK_CHECK(x && ids, QUAKE_E_INVALID, "x and ids are required");
   hipStream_t s = as_stream(stream);
-  Store& st = idx->L0;
-  // the batch is checked whole before anything changes
-  std::vector<int64_t> h_ids(n);
-  QK_HIP(hipMemcpyAsync(h_ids.data(), ids, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  QK_HIP(hipStreamSynchronize(s));
-  QK_CHECK(std::all_of(h_ids.begin(), h_ids.end(), [](int64_t v) { return v >= 0; }), QUAKE_E_INVALID,
-           "ids must be >= 0");
-  {
-    std::vector<int64_t> sorted(h_ids);
-    std::sort(sorted.begin(), sorted.end());
-    QK_CHECK(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(), QUAKE_E_DUPLICATE,
-             "the batch repeats an id");
-  }
   require_finite(idx, x, n * (int64_t)idx->d, "x", s);
-  QK_CHECK(count_missing(idx, ids, n, nullptr, s) == n, QUAKE_E_DUPLICATE, "the batch names an id already present");
-  const int dp = idx->dp;
-  std::unique_ptr<Tmp<float>> xpad_buf;
-  const float* xpad = x;
-  if (dp != idx->d) {
-    xpad_buf.reset(new Tmp<float>(idx->mem, (size_t)n * dp));
-    qk::launch_pad_rows(x, n, idx->d, dp, xpad_buf->p, nullptr, s);
-    xpad = xpad_buf->p;
-  }
-  // route: nearest leaf, top-down through the upper level when there is one
-  std::vector<int32_t> part(n);
-  if (idx->n_levels == 1) {
-    Tmp<int32_t> assign(idx->mem, n);
-    qk::launch_assign(xpad, n, dp, st.centroids, st.nlist, idx->metric, assign.p, s);
-    QK_HIP(hipMemcpyAsync(part.data(), assign.p, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    QK_HIP(hipStreamSynchronize(s));
-  } else {
+  std::vector<int32_t> routed;
+  if (idx->n_levels == 2) {
+    // top-down: the nearest top partition, then its nearest leaf (a level-1
+    // search with one candidate and one result)
+    std::unique_ptr<Tmp<float>> xpad_buf;
+    const float* xpad = x;
+    if (idx->dp != idx->d) {
+      xpad_buf.reset(new Tmp<float>(idx->mem, (size_t)n * idx->dp));
+      qk::launch_pad_rows(x, n, idx->d, idx->dp, xpad_buf->p, nullptr, s);
+      xpad = xpad_buf->p;
+    }
     ensure_queries(idx, n);
-    qk::launch_pad_rows(xpad, n, dp, dp, idx->ws.q, idx->ws.qn2, s);
+    qk::launch_pad_rows(xpad, n, idx->dp, idx->dp, idx->ws.q, idx->ws.qn2, s);
     Job route;
     route.count = false;
     route.k = route.kk = 1;
-    route.M = route.w0 = route.wmax = 1;  // the nearest top partition, its nearest leaf
+    route.M = route.w0 = route.wmax = 1;
     run_search(idx, idx->L1, route, n, nullptr, nullptr, nullptr, nullptr, s);
     std::vector<int64_t> leaf(n);
     QK_HIP(hipMemcpyAsync(leaf.data(), idx->ws.ri, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     QK_HIP(hipStreamSynchronize(s));
+    routed.resize(n);
     for (int64_t i = 0; i < n; ++i) {
       QK_CHECK(leaf[i] >= 0, QUAKE_E_DEVICE, "top-down routing found no leaf");
-      part[i] = (int32_t)leaf[i];
+      routed[i] = (int32_t)leaf[i];
     }
   }
-  // room: partitions that overflow move to fresh tiles with 1.5x the need
-  std::vector<int64_t> cnt(st.nlist, 0);
-  for (int64_t i = 0; i < n; ++i) cnt[part[i]]++;
-  std::vector<std::pair<int64_t, int32_t>> moves;
-  int64_t extra = 0;
-  for (int64_t p = 0; p < st.nlist; ++p) {
-    if (cnt[p] == 0 || st.size[p] + cnt[p] <= st.cap[p]) continue;
-    const int64_t want = round_up((int64_t)std::ceil((st.size[p] + cnt[p]) * 1.5), qk::TILE);
-    QK_CHECK(want <= INT32_MAX, QUAKE_E_INVALID, "partition too large");
-    moves.push_back({p, (int32_t)want});
-    extra += want / qk::TILE;
-  }
-  grow_arena(idx, st, st.used_tiles + extra, s);
-  for (auto& mv : moves) relocate(st, mv.first, mv.second, s);
-  std::vector<int64_t> slot(n);
-  std::vector<int64_t> fill(st.nlist, 0);
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t p = part[i];
-    slot[i] = st.off[p] * qk::TILE + st.size[p] + fill[p]++;
-  }
-  {
-    Tmp<int64_t> d_slot(idx->mem, n);
-    QK_HIP(hipMemcpyAsync(d_slot.p, slot.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    qk::launch_scatter(x, n, idx->d, dp, st.dp16, ids, d_slot.p, st.v32, st.v16, st.v16 ? idx->storage : QUAKE_F32,
-                       st.rows32, st.ids, s);
-    qk::launch_norm16_slots(st, d_slot.p, n, idx->storage, s);
-    for (int64_t p = 0; p < st.nlist; ++p) st.size[p] += (int32_t)cnt[p];
-    upload_table(st, s);
-    st.live += n;
-    if (!moves.empty() || (idx->idmap.used + n) * 2 > (int64_t)idx->idmap.mask + 1) {
-      map_rebuild(idx, st.live, s);
-    } else {
-      qk::launch_map_insert(idx->idmap, ids, d_slot.p, n, s);
-      idx->idmap.used += n;
-    }
-    QK_HIP(hipStreamSynchronize(s));
-  }
+  qk::insert_rows(idx, idx->L0, idx->idmap, x, ids, n, routed.empty() ? nullptr : &routed, s);
   API_END
 }
 
@@ -1507,38 +1639,7 @@ int quake_delete(quake_index* idx, const int64_t* ids, int64_t n, void* stream) 
   QK_CHECK(n >= 0, QUAKE_E_INVALID, "n must be >= 0");
   if (n == 0) return QUAKE_OK;
   QK_CHECK(ids, QUAKE_E_INVALID, "ids are required");
-  hipStream_t s = as_stream(stream);
-  Store& st = idx->L0;
-  std::vector<int64_t> h_ids(n);
-  QK_HIP(hipMemcpyAsync(h_ids.data(), ids, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  QK_HIP(hipStreamSynchronize(s));
-  {
-    std::vector<int64_t> sorted(h_ids);
-    std::sort(sorted.begin(), sorted.end());
-    QK_CHECK(std::adjacent_find(sorted.begin(), sorted.end()) == sorted.end(), QUAKE_E_NOTFOUND,
-             "the batch repeats an id");
-  }
-  Tmp<int64_t> slots(idx->mem, n);
-  QK_CHECK(count_missing(idx, ids, n, slots.p, s) == 0, QUAKE_E_NOTFOUND, "the batch names an id that is absent");
-  qk::launch_mark_deleted(st, slots.p, n, s);
-  qk::launch_map_erase(idx->idmap, ids, n, s);
-  std::vector<int64_t> h_slots(n);
-  QK_HIP(hipMemcpyAsync(h_slots.data(), slots.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  QK_HIP(hipStreamSynchronize(s));
-  st.live -= n;
-  std::vector<char> touched(st.nlist, 0);
-  for (int64_t sl : h_slots) {
-    const int32_t p = st.tile_part[sl / qk::TILE];
-    st.tomb[p]++;
-    touched[p] = 1;
-  }
-  // compaction: a partition with a quarter of its slots deleted has its
-  // holes below the new size filled from its live tail
-  for (int64_t p = 0; p < st.nlist; ++p)
-    if (touched[p] && st.tomb[p] * 4 < st.size[p]) touched[p] = 0;
-  compact(idx, st, touched, s);
-  upload_table(st, s);
-  QK_HIP(hipStreamSynchronize(s));
+  qk::delete_rows(idx, idx->L0, idx->idmap, ids, n, as_stream(stream));
   API_END
 }
 

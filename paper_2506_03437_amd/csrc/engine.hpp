@@ -67,6 +67,13 @@ void store_upload_table(Store& st, hipStream_t s);
 void store_compact(quake_index* idx, Store& st, const std::vector<char>& which, hipStream_t s);
 // Fraction bits of exact fixed-point sums over rows [n][dp].
 int store_fixed_point_bits(DeviceMemory& mem, const float* x, int64_t n, int dp, hipStream_t s);
+// Batched insert / delete on a level-0 store and its id map (quake_insert and
+// quake_delete run them on the index's own; the serving loop also on its
+// second copy, from its update thread).  routed: partition of every row,
+// else the nearest centroid's.  Errors as quake_insert / quake_delete.
+void insert_rows(quake_index* idx, Store& st, IdMap& map, const float* x, const int64_t* ids, int64_t n,
+                 const std::vector<int32_t>* routed, hipStream_t s);
+void delete_rows(quake_index* idx, Store& st, IdMap& map, const int64_t* ids, int64_t n, hipStream_t s);
 // The maintenance pass behind quake_maintain (maintain.cpp).
 void maintain(quake_index* idx, const quake_maintain_params& p, quake_maintain_report* report, hipStream_t s);
 

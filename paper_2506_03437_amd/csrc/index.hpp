@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -46,7 +47,7 @@ constexpr int MAX_CANDIDATES = 4096;   // APS candidate set M (and nprobe) upper
 
 // Device allocations of one index, counted against an optional budget.
 // Blocks come from the caller's allocator when one is set (torch's caching
-// allocator from the Python binding), else from hipMalloc.
+// allocator from the Python binding), else from hipMalloc.  Thread-safe.
 class DeviceMemory {
  public:
   size_t used = 0;
@@ -62,6 +63,7 @@ class DeviceMemory {
  private:
   struct Block { void* p; size_t bytes; };
   std::vector<Block> blocks_;
+  std::mutex mu_;  // the serving loop's update thread allocates beside its search thread
 };
 
 // One level's partitions.  Vectors of partition p occupy tiles
@@ -91,7 +93,7 @@ struct Store {
   int64_t tiles = 0;            // arena tiles allocated
   int64_t used_tiles = 0;       // arena tiles handed out
   int32_t dp16 = 0;             // row length of the 16-bit copy: d rounded up to 32
-  float* v32 = nullptr;
+  float* v32 = nullptr;         // FP32 tiles [dp/4][64][4] (null when the index keeps only the 16-bit tiles)
   uint16_t* v16 = nullptr;      // BF16 or FP16 copy, or null; tiles [dp16/8][64][8]
   float* v16n = nullptr;        // [tiles * 64] |x|^2 of the 16-bit copy (L2 only)
   float* rows32 = nullptr;      // [tiles * 64][dp] row-major FP32 rows by slot (with a 16-bit copy: rerank)

@@ -46,6 +46,11 @@ __global__ __launch_bounds__(256) void k_gather_slots(const float* __restrict__ 
 }
 
 void launch_gather_slots(const Store& st, const int64_t* slots, int64_t n, float* out, hipStream_t s) {
+  // without FP32 tiles the row-major FP32 copy holds the same values by slot
+  if (!st.v32) {
+    launch_gather_rows(st.rows32, st.dp, slots, n, st.dp, out, s);
+    return;
+  }
   const int64_t total = n * (st.dp >> 2);
   if (total > 0) hipLaunchKernelGGL(k_gather_slots, grid_of(total), dim3(256), 0, s, st.v32, slots, n, st.dp, out);
 }

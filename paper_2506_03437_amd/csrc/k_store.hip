@@ -38,8 +38,7 @@ __global__ __launch_bounds__(256) void k_scatter(const float* __restrict__ x, in
     const int j = c4 * 4 + u;
     v[u] = (j < d) ? x[row * d + j] : 0.f;
   }
-  float4* dst = reinterpret_cast<float4*>(v32) + (tile * nch4 + c4) * TILE + lane;
-  *dst = make_float4(v[0], v[1], v[2], v[3]);
+  if (v32) reinterpret_cast<float4*>(v32)[(tile * nch4 + c4) * TILE + lane] = make_float4(v[0], v[1], v[2], v[3]);
   if (v16) {
     const int c8 = c4 >> 1, half = c4 & 1;
     uint16_t* d16 = v16 + ((tile * (dp16 >> 3) + c8) * TILE + lane) * 8 + half * 4;

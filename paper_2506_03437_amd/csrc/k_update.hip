@@ -149,8 +149,10 @@ __global__ __launch_bounds__(256) void k_move_slots(const int64_t* __restrict__ 
   const int64_t a = src[i], b = dst[i];
   const int64_t ta = a / TILE, tb = b / TILE;
   const int la = (int)(a - ta * TILE), lb = (int)(b - tb * TILE);
-  float4* f = reinterpret_cast<float4*>(v32);
-  f[(tb * nch4 + c4) * TILE + lb] = f[(ta * nch4 + c4) * TILE + la];
+  if (v32) {
+    float4* f = reinterpret_cast<float4*>(v32);
+    f[(tb * nch4 + c4) * TILE + lb] = f[(ta * nch4 + c4) * TILE + la];
+  }
   if (v16) {
     const int nc8 = dp16 >> 3;
     const int c8 = c4 >> 1, half = c4 & 1;

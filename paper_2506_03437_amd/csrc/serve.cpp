@@ -153,7 +153,16 @@ struct quake_server {
   uint8_t* d_tag = nullptr;             // [cap] store tag of every slot
   int64_t active_tag[2] = {0, 0};
   std::deque<Request> replay;           // updates `other` has yet to apply
-  int64_t overlapped = 0;               // updates applied while the previous version had searches
+  int64_t overlapped = 0;               // updates applied while searches ran
+  // the update thread (overlap mode): it owns `other` while up_busy
+  std::thread updater;
+  hipStream_t s_up = nullptr;
+  std::condition_variable cv_up;
+  bool up_busy = false, up_ready = false, up_stop = false, up_fatal = false;
+  bool up_replay_only = false;          // the job only brings `other` up to date (admission goes on)
+  std::deque<Request> up_jobs;          // replays, then the new batch
+  int up_rc = QUAKE_OK;
+  std::string up_err;
   std::vector<double> lat;
   double first_arrive = -1, last_done = 0;
 
@@ -327,45 +336,31 @@ struct quake_server {
     cv_done.notify_all();
   }
 
-  // Applies an update batch to idx->L0 / idx->idmap; returns its status.
-  int run_update(const Request& r) {
+  // Applies an update batch to a store and its id map on stream `us`;
+  // returns its status (the batch is rejected whole on error).
+  int apply_to(qk::Store& st, qk::IdMap& map, const Request& r, hipStream_t us, std::string* err = nullptr) {
     const int64_t n = (int64_t)r.ids.size();
-    int rc = QUAKE_OK;
-    int64_t* d_i = idx->mem.alloc<int64_t>(std::max<int64_t>(n, 1));
+    if (n == 0) return QUAKE_OK;
+    int64_t* d_i = nullptr;
     float* d_v = nullptr;
+    int rc = QUAKE_OK;
     try {
-      QK_HIP(hipMemcpyAsync(d_i, r.ids.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
+      d_i = idx->mem.alloc<int64_t>(n);
+      QK_HIP(hipMemcpyAsync(d_i, r.ids.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, us));
       if (r.kind == 1) {
-        d_v = idx->mem.alloc<float>(std::max<int64_t>(n, 1) * idx->d);
-        QK_HIP(hipMemcpyAsync(d_v, r.x.data(), (size_t)n * idx->d * sizeof(float), hipMemcpyHostToDevice, s));
-        rc = quake_insert(idx, d_v, d_i, n, s);
+        d_v = idx->mem.alloc<float>((size_t)n * idx->d);
+        QK_HIP(hipMemcpyAsync(d_v, r.x.data(), (size_t)n * idx->d * sizeof(float), hipMemcpyHostToDevice, us));
+        qk::insert_rows(idx, st, map, d_v, d_i, n, nullptr, us);
       } else {
-        rc = quake_delete(idx, d_i, n, s);
+        qk::delete_rows(idx, st, map, d_i, n, us);
       }
-    } catch (...) {
-      idx->mem.release(d_i);
-      idx->mem.release(d_v);
-      throw;
+    } catch (const qk::Error& e) {
+      rc = e.code;
+      if (err) *err = e.msg;
     }
+    QK_HIP(hipStreamSynchronize(us));
     idx->mem.release(d_i);
     idx->mem.release(d_v);
-    return rc;
-  }
-
-  // Runs an update batch on `other` (no search reads it) in place of idx->L0.
-  int run_update_on_other(const Request& r) {
-    std::swap(idx->L0, other);
-    std::swap(idx->idmap, other_map);
-    int rc;
-    try {
-      rc = run_update(r);
-    } catch (...) {
-      std::swap(idx->L0, other);
-      std::swap(idx->idmap, other_map);
-      throw;
-    }
-    std::swap(idx->L0, other);
-    std::swap(idx->idmap, other_map);
     return rc;
   }
 
@@ -382,38 +377,101 @@ struct quake_server {
 
   // Drain mode: every slot is free when this runs.
   void apply_update(Request& r) {
-    const int rc = run_update(r);
+    const int rc = apply_to(idx->L0, idx->idmap, r, s);
     setup();  // partition sizes changed: work-item bounds and buffers follow
     answer_update(r, rc);
   }
 
-  // Overlap mode: the previous version has no searches left.  It replays what
-  // it missed, takes the new batch, and becomes the version new searches see.
-  void apply_update_overlapped(Request& r) {
-    if (!have_twin) {
-      clone_store(idx->mem, idx->L0, idx->idmap, other, other_map, s);
-      other.d_hits = idx->L0.d_hits;
-      have_twin = true;
+  // Overlap mode, on the update thread: `other` (no search reads it) takes
+  // the batches the newer version took since, then the new one.  The first
+  // time, `other` is made as a copy of the index's store (reading it while
+  // searches read it too).
+  void update_loop() {
+    try {
+      QK_HIP(hipSetDevice(device));
+    } catch (...) {
     }
-    for (const Request& p : replay) run_update_on_other(p);
+    while (true) {
+      std::deque<Request> jobs;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_up.wait(lk, [&] { return up_stop || (up_busy && !up_ready); });
+        if (!(up_busy && !up_ready)) break;
+        jobs = up_jobs;
+      }
+      int rc = QUAKE_OK;
+      std::string err;
+      bool fatal_err = false;
+      try {
+        if (!have_twin) {
+          clone_store(idx->mem, idx->L0, idx->idmap, other, other_map, s_up);
+          other.d_hits = idx->L0.d_hits;
+          have_twin = true;
+        }
+        const size_t replays = up_replay_only ? jobs.size() : jobs.size() - 1;
+        for (size_t i = 0; i < replays; ++i) {
+          const int prc = apply_to(other, other_map, jobs[i], s_up, &err);
+          // a replay that fails (memory) would leave the versions different
+          QK_CHECK(prc == QUAKE_OK, QUAKE_E_NOMEM, "the second store copy could not replay an update: " + err);
+        }
+        if (!up_replay_only) rc = apply_to(other, other_map, jobs.back(), s_up, &err);
+      } catch (const qk::Error& e) {
+        rc = e.code;
+        err = e.msg;
+        fatal_err = true;
+      } catch (const std::exception& e) {
+        rc = QUAKE_E_DEVICE;
+        err = e.what();
+        fatal_err = true;
+      }
+      {
+        std::lock_guard<std::mutex> lk(mu);
+        up_rc = rc;
+        up_err = err;
+        up_fatal = fatal_err;
+        up_ready = true;
+      }
+      cv_work.notify_all();
+    }
+  }
+
+  // Overlap mode, on the search thread, once the update thread is done: on
+  // success the two versions swap and new searches see the update.
+  void finish_update() {
+    Request r;
+    int rc;
+    bool only_replay;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      QK_CHECK(!up_fatal, QUAKE_E_NOMEM, up_err);
+      only_replay = up_replay_only;
+      if (!only_replay) r = std::move(up_jobs.back());
+      rc = up_rc;
+      up_jobs.clear();
+      up_busy = false;
+      up_ready = false;
+      up_replay_only = false;
+    }
     replay.clear();
-    const int rc = run_update_on_other(r);
+    if (only_replay) {  // `other` has caught up; nothing becomes visible
+      qk::release_graphs(idx);
+      size_items();
+      return;
+    }
     if (rc == QUAKE_OK) {
-      if (active_tag[front] > 0) ++overlapped;
       std::swap(idx->L0, other);
       std::swap(idx->idmap, other_map);
       std::swap(idx->L0.window, other.window);  // the access window stays with the index
       front = 1 - front;
-      replay.push_back(r);
+      replay.push_back(std::move(r));
     }
-    release_graphs_of_old();
+    // captured rounds key on the stores' arrays, which an update may
+    // reallocate: the cache is dropped so that no replay reads a freed buffer
+    qk::release_graphs(idx);
     size_items();  // partition sizes changed: work-item bounds and buffers follow
-    answer_update(r, rc);
+    if (rc == QUAKE_OK) answer_update(replay.back(), rc);
+    else answer_update(r, rc);
   }
-
-  // Captured rounds key on the stores' arrays, which an update may
-  // reallocate: the cache is dropped so that no replay reads a freed buffer.
-  void release_graphs_of_old() { qk::release_graphs(idx); }
 
   void run() {
     try {
@@ -424,11 +482,15 @@ struct quake_server {
         std::vector<int32_t> slots;
         Request upd;
         bool has_upd = false;
+        bool up_done = false;
         {
           std::unique_lock<std::mutex> lk(mu);
-          cv_work.wait(lk, [&] { return stop || !fifo.empty() || active > 0; });
-          if (stop && fifo.empty() && active == 0) break;
-          while (!fifo.empty() && fifo.front().kind == 0 && !free_slots.empty()) {
+          cv_work.wait(lk, [&] { return stop || !fifo.empty() || active > 0 || up_ready; });
+          if (stop && fifo.empty() && active == 0 && !up_busy) break;
+          up_done = up_ready;
+          // while an update is being applied, later searches wait: they must see it
+          const bool blocked = up_busy && !up_replay_only;
+          while (!blocked && !fifo.empty() && fifo.front().kind == 0 && !free_slots.empty()) {
             const int32_t q = free_slots.back();
             free_slots.pop_back();
             slot_ticket[q] = fifo.front().ticket;
@@ -440,17 +502,35 @@ struct quake_server {
           active += (int64_t)adm.size();
           max_active = std::max(max_active, active);
           // an update runs once nothing reads the version it will change:
-          // the only version (drain mode) or the previous one (overlap mode)
-          const bool ready = overlap ? active_tag[1 - front] == 0 : active == 0;
+          // the only version (drain mode) or the previous one (overlap mode,
+          // where the update thread applies it beside the running searches)
+          const bool ready = overlap ? (!up_busy && active_tag[1 - front] == 0) : active == 0;
           if (adm.empty() && ready && !fifo.empty() && fifo.front().kind != 0) {
-            upd = std::move(fifo.front());
-            fifo.pop_front();
-            has_upd = true;
+            if (overlap) {
+              up_jobs.assign(replay.begin(), replay.end());
+              up_jobs.push_back(std::move(fifo.front()));
+              fifo.pop_front();
+              up_busy = true;
+              if (active > 0) ++overlapped;
+              cv_up.notify_one();
+            } else {
+              upd = std::move(fifo.front());
+              fifo.pop_front();
+              has_upd = true;
+            }
+          } else if (overlap && !up_busy && !replay.empty() && active_tag[1 - front] == 0) {
+            // the previous version's searches are done: bring it up to date
+            // now, beside the searches, so that the next update only waits
+            // for its own batch
+            up_jobs.assign(replay.begin(), replay.end());
+            up_busy = true;
+            up_replay_only = true;
+            cv_up.notify_one();
           }
         }
+        if (up_done) finish_update();
         if (has_upd) {
-          if (overlap) apply_update_overlapped(upd);
-          else apply_update(upd);
+          apply_update(upd);
           continue;
         }
         if (!adm.empty()) admit(adm, slots);
@@ -510,6 +590,7 @@ struct quake_server {
                     (void*)h_rec})
       if (p) (void)hipHostFree(p);
     if (s) (void)hipStreamDestroy(s);
+    if (s_up) (void)hipStreamDestroy(s_up);
   }
 };
 
@@ -604,8 +685,10 @@ int quake_server_create(quake_index* idx, const quake_server_params* params, qua
   srv->slot_ticket.assign(cap, 0);
   srv->slot_arrive.assign(cap, 0.0);
   for (int64_t q = cap - 1; q >= 0; --q) srv->free_slots.push_back((int32_t)q);
+  if (srv->overlap) QK_HIP(hipStreamCreateWithFlags(&srv->s_up, hipStreamNonBlocking));
   quake_server* raw = srv.get();
   srv->worker = std::thread([raw] { raw->run(); });
+  if (srv->overlap) srv->updater = std::thread([raw] { raw->update_loop(); });
   *out = srv.release();
   SRV_END
 }
@@ -714,6 +797,12 @@ void quake_server_destroy(quake_server* srv) {
   }
   srv->cv_work.notify_all();
   if (srv->worker.joinable()) srv->worker.join();
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->up_stop = true;
+  }
+  srv->cv_up.notify_all();
+  if (srv->updater.joinable()) srv->updater.join();
   srv->release_buffers();
   delete srv;
 }

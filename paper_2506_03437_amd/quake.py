@@ -44,7 +44,8 @@ class BuildParams(ctypes.Structure):
     _fields_ = [("metric", ctypes.c_int32), ("storage_dtype", ctypes.c_int32), ("n_levels", ctypes.c_int32),
                 ("kmeans_iters", ctypes.c_int32), ("nlist", ctypes.c_int64), ("nlist_top", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("centroids", ctypes.c_void_p), ("assign", ctypes.c_void_p),
-                ("hbm_budget_bytes", ctypes.c_size_t), ("capacity_slack", ctypes.c_double)]
+                ("hbm_budget_bytes", ctypes.c_size_t), ("capacity_slack", ctypes.c_double),
+                ("drop_f32_tiles", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -211,8 +212,9 @@ def quake_cap_table(d: int) -> np.ndarray:
 
 def quake_build(x, ids=None, *, metric="l2", nlist=256, storage="f32", n_levels=1, nlist_top=0, kmeans_iters=10,
                 seed=0, centroids=None, assign=None, hbm_budget_bytes=0, capacity_slack=0.0,
-                allocator="torch") -> int:
-    """allocator: "torch" (the caching allocator of x's device, the default) or "hip" (hipMalloc)."""
+                allocator="torch", f32_tiles=True) -> int:
+    """allocator: "torch" (the caching allocator of x's device, the default) or "hip" (hipMalloc).
+    f32_tiles=False (with a 16-bit storage copy): no FP32 tile copy, batched searches only."""
     import torch
     _dev(x, torch.float32)
     if ids is not None:
@@ -222,7 +224,7 @@ def quake_build(x, ids=None, *, metric="l2", nlist=256, storage="f32", n_levels=
     if assign is not None:
         _dev(assign, torch.int32)
     p = BuildParams(_METRIC[metric], _DTYPE[storage], n_levels, kmeans_iters, nlist, nlist_top, seed,
-                    _ptr(centroids), _ptr(assign), hbm_budget_bytes, capacity_slack)
+                    _ptr(centroids), _ptr(assign), hbm_budget_bytes, capacity_slack, 0 if f32_tiles else 1)
     if allocator not in ("torch", "hip"):
         raise ValueError(f"allocator must be 'torch' or 'hip', not {allocator!r}")
     alloc = ctypes.byref(torch_allocator(x.device.index or 0)) if allocator == "torch" else None

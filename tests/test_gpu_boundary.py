@@ -160,3 +160,40 @@ def test_index_memory_comes_from_the_torch_allocator(data):
             assert (a == b).all()
     finally:
         idx.free()
+
+
+def test_index_without_fp32_tiles(data):
+    """drop_f32_tiles: the batched path (16-bit tiles, rerank from the
+    row-major FP32 copy) answers bit for bit as with the FP32 tiles, updates
+    and maintenance keep working, plain FP32 searches are refused, and the
+    index holds a third less memory."""
+    X, Q = data
+    kw = dict(k=10, recall_target=0.9, scan_mode="batched", scan_dtype="bf16", rerank_factor=4)
+    full = gu.build(X, metric="l2", nlist=32, storage="bf16", kmeans_iters=3, seed=2)
+    lean = gu.build(X, metric="l2", nlist=32, storage="bf16", kmeans_iters=3, seed=2, f32_tiles=False)
+    try:
+        assert lean.stats()[2] < 0.75 * full.stats()[2]
+        for a, b in zip(gu.search(full, Q, **kw), gu.search(lean, Q, **kw)):
+            assert (a == b).all()
+        msg = _invalid(lambda: gu.search(lean, Q, k=10, recall_target=0.9))
+        assert "FP32 tile" in msg
+        rng = np.random.default_rng(8)
+        B = (X[rng.choice(X.shape[0], 3000)] + 0.1).astype(np.float32)
+        bid = np.arange(10**6, 10**6 + 3000, dtype=np.int64)
+        for idx in (full, lean):
+            idx.insert(gu.to_dev(B), gu.to_dev(bid))
+            idx.delete(gu.to_dev(bid[::2]))
+        for a, b in zip(gu.search(full, Q, **kw), gu.search(lean, Q, **kw)):
+            assert (a == b).all()
+        lam = ([1, 100, 1000, 10000], [1.0, 3.0, 25.0, 300.0])
+        hits = np.full(32, 50, dtype=np.int64)
+        hits[:4] = 1000
+        ra, da = full.maintain(*lam, tau=0.5, hits=hits, window=1000)
+        rb, db = lean.maintain(*lam, tau=0.5, hits=hits, window=1000)
+        assert ra == rb and da == db and ra["splits"] >= 1
+        for a, b in zip(gu.search(full, Q, **kw), gu.search(lean, Q, **kw)):
+            assert (a == b).all()
+        _invalid(lambda: gu.build(X, metric="l2", nlist=32, storage="f32", f32_tiles=False))
+    finally:
+        full.free()
+        lean.free()

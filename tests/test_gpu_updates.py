@@ -180,3 +180,27 @@ def test_updates_keep_the_16bit_copy_in_step():
         ri, rv, _ = oivf.ivf_search(ps, Q, 10, 6, metric)
         parity.check_all(Q, ps.X, ps.ids, gi, gv, ri, rv, metric, 10)
         idx.free()
+
+
+def test_repeated_overflow_repacks_the_arena(base):
+    """Growing partitions move to fresh tiles and leave their old ones behind;
+    once those make up a quarter of the arena an insert packs the partitions
+    into a fresh arena instead of growing it.  The state and the searches
+    still follow the replay, and device memory stays bounded."""
+    idx, r, Q, rng, mu = base
+    C = r.C
+    # one partition keeps growing: each move leaves its previous tiles behind,
+    # a third of the arena after a few batches
+    for step in range(12):
+        B = (C[3] + 0.01 * rng.standard_normal((1500, 24))).astype(np.float32)
+        bid = np.arange(800_000 + step * 2000, 800_000 + step * 2000 + 1500, dtype=np.int64)
+        idx.insert(gu.to_dev(B), gu.to_dev(bid))
+        assert r.insert(B, bid) == oupd.OK
+        if step % 3 == 2:
+            _check_same_state(idx, r, "l2")
+            _search_matches(idx, r, np.concatenate([Q, B[:10]]), "l2")
+    dels = np.arange(800_000, 800_000 + 1500, dtype=np.int64)
+    idx.delete(gu.to_dev(dels))
+    assert r.delete(dels) == oupd.OK
+    _check_same_state(idx, r, "l2")
+    _search_matches(idx, r, Q, "l2")
