@@ -204,6 +204,105 @@ __global__ __launch_bounds__(256) void k_scores(const float* __restrict__ q, int
   }
 }
 
+// Inner-product scores on the FP32 matrix cores: the same 64 x 64 tiles
+// and double-buffered 32-dimension slabs as k_scores, each wave computing a
+// 32 x 32 quarter as 2 x 2 blocks of v_mfma_f32_16x16x4_f32 (FP32 products
+// and sums: a dot product has no cancellation to guard against, unlike the
+// L2 difference form, which stays on the vector units).
+typedef __attribute__((ext_vector_type(4))) float f32x4v;
+
+__global__ __launch_bounds__(256) void k_scores_ip_mfma(const float* __restrict__ q, int64_t nq,
+                                                        const float* __restrict__ c, int64_t nc, int dp,
+                                                        float* __restrict__ out) {
+  __shared__ float qs[2][ST][SLD];
+  __shared__ float cs[2][ST][SLD];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wm = wave >> 1, wn = wave & 1;  // the wave's 32 x 32 quarter of the tile
+  const int64_t c0 = (int64_t)blockIdx.x * ST, q0 = (int64_t)blockIdx.y * ST;
+  auto fetch = [&](const float* __restrict__ src, int64_t row0, int64_t rows, int k0, float4 (&v)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      const int r = e >> 3, k4 = (e & 7) * 4;
+      const int64_t g = row0 + r;
+      v[h] = (g < rows && k0 + k4 < dp) ? *reinterpret_cast<const float4*>(src + g * dp + k0 + k4)
+                                         : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  };
+  auto put = [&](float (*dst)[SLD], const float4 (&v)[2]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = threadIdx.x + 256 * h;
+      *reinterpret_cast<float4*>(&dst[e >> 3][(e & 7) * 4]) = v[h];
+    }
+  };
+  f32x4v acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4v{0.f, 0.f, 0.f, 0.f};
+  // operand lanes: row (query or centroid) lane & 15 of a 16-block, dimension lane >> 4 of a 4-step
+  const int r16 = lane & 15, k4 = lane >> 4;
+  float4 vq[2], vc[2];
+  fetch(q, q0, nq, 0, vq);
+  fetch(c, c0, nc, 0, vc);
+  put(qs[0], vq);
+  put(cs[0], vc);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = 0; k0 < dp; k0 += SK) {
+    const bool more = k0 + SK < dp;
+    if (more) {
+      fetch(q, q0, nq, k0 + SK, vq);
+      fetch(c, c0, nc, k0 + SK, vc);
+    }
+    // each slab's 32 dimensions are summed on their own and then added in
+    // (the blocked partial sums of k_scores: a short chain per slab instead
+    // of one chain over all dimensions keeps the rounding error small)
+    f32x4v part[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) part[i][j] = f32x4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < SK; kk += 4) {
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = qs[buf][wm * 32 + i * 16 + r16][kk + k4];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = cs[buf][wn * 32 + j * 16 + r16][kk + k4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          part[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], part[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] += part[i][j];
+    if (more) {
+      put(qs[buf ^ 1], vq);
+      put(cs[buf ^ 1], vc);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+  // D[4 (lane >> 4) + r][lane & 15] of each 16 x 16 block
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t qi = q0 + wm * 32 + i * 16 + 4 * k4 + r;
+      if (qi >= nq) continue;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int64_t ci = c0 + wn * 32 + j * 16 + r16;
+        if (ci < nc) out[qi * nc + ci] = acc[i][j][r];
+      }
+    }
+}
+
 void launch_scores(const float* q, int64_t nq, const float* c, int64_t nc, int dp, int metric, float* out,
                    hipStream_t s) {
   if (nq <= 0 || nc <= 0) return;
@@ -211,7 +310,7 @@ void launch_scores(const float* q, int64_t nq, const float* c, int64_t nc, int d
   if (metric == QUAKE_L2)
     hipLaunchKernelGGL(k_scores<QUAKE_L2>, grid, dim3(256), 0, s, q, nq, c, nc, dp, out);
   else
-    hipLaunchKernelGGL(k_scores<QUAKE_IP>, grid, dim3(256), 0, s, q, nq, c, nc, dp, out);
+    hipLaunchKernelGGL(k_scores_ip_mfma, grid, dim3(256), 0, s, q, nq, c, nc, dp, out);
 }
 
 // Nearest centroid of every row (k-means assignment and the build's final
