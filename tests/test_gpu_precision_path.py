@@ -40,7 +40,7 @@ def precision_path():
     idx = gu.build(X, metric="ip", nlist=base.nlist, storage="bf16", kmeans_iters=4, seed=9)
     ps = gu.oracle_view(idx, X)
     rng = np.random.default_rng(5)
-    sample = np.sort(rng.choice(NQ, 96, replace=False))
+    sample = np.sort(rng.choice(NQ, 128, replace=False))
     yield X, Q, idx, ps, sample
     idx.free()
 
