@@ -343,6 +343,8 @@ enum {
   QUAKE_PROF_COMMIT = 4,    /* in-order commit and recall model */
   QUAKE_PROF_RERANK = 5,    /* FP32 rerank of reduced-precision candidates */
   QUAKE_PROF_SCAN_SETS = 6, /* batched scan reads per query set (bytes only, no launches) */
+  QUAKE_PROF_UPPER = 7,     /* everything the level-1 search of a two-level index runs (the other
+                               kinds then cover level 0 alone) */
   QUAKE_PROF_KINDS = 8
 };
 typedef struct {

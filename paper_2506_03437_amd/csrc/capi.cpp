@@ -126,6 +126,7 @@ hipEvent_t Profiler::event() {
 
 void Profiler::begin(int kind, hipStream_t s) {
   if (!on) return;
+  if (only >= 0) kind = only;
   Span sp{kind, event(), event()};
   QK_HIP(hipEventRecord(sp.a, s));
   pending.push_back(sp);
@@ -1202,6 +1203,11 @@ void upper_level(quake_index* idx, int64_t nq, int M0, const quake_search_params
                                    qk::SORTED_ITEM_MAX / qk::TILE);
   const int64_t per_query = (int64_t)up.M * max_chunks(L1, chunk_tiles);
   const int64_t slice = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(1 << 17) / std::max<int64_t>(per_query, 1)));
+  struct Only {  // the level-1 work is timed as one kind of its own
+    qk::Profiler& p;
+    explicit Only(qk::Profiler& p_) : p(p_) { p.only = QUAKE_PROF_UPPER; }
+    ~Only() { p.only = -1; }
+  } only(idx->prof);
   for (int64_t q0 = 0; q0 < nq; q0 += slice) {
     const int64_t n = std::min(slice, nq - q0);
     QueryWindow win(w, q0, idx->dp);

@@ -173,7 +173,9 @@ struct Profiler {
   hipEvent_t event();
   void begin(int kind, hipStream_t s);
   void end(hipStream_t s);
+  int only = -1;  // >= 0: every span and count goes to this kind (the level-1 search)
   void add(int kind, double bytes, double flops) {
+    if (only >= 0) kind = only;
     if (on) { acc[kind].bytes += bytes; acc[kind].flops += flops; }
   }
   void collect();  // after the stream is synchronised

@@ -31,7 +31,7 @@ EXPORTED = ("quake_build", "quake_search", "quake_search_noalloc", "quake_insert
             "quake_free", "quake_last_error", "quake_autotune", "quake_server_create", "quake_server_search", "quake_server_insert",
             "quake_server_delete", "quake_server_wait", "quake_server_stats", "quake_server_destroy",
             "quake_access_stats", "quake_maintain", "quake_profile_latency")
-PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "scan_sets", "unused7")
+PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "scan_sets", "upper")
 
 
 class QuakeError(RuntimeError):

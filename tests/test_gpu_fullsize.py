@@ -87,3 +87,15 @@ def test_batched_bf16_full_size(full, tau):
     print(f"[batched] tau {tau}: recall@10 plain {rp:.4f} batched {rb:.4f}, partitions plain {pns.mean():.2f} "
           f"batched {ns.mean():.2f}", flush=True)
     assert rb >= rp - 0.005
+
+
+def test_plain_fp32_k100_full_size(full):
+    """k = 100 on the full-size workload (the batched scan keeps at most 64
+    candidates per query, so k = 100 runs on the plain path)."""
+    w, X, Q, idx, ps, rows, truth_rows, truth = full
+    gi, gv, ns, rec = gu.search(idx, Q, k=100, recall_target=0.9, f_M=w.f_M)
+    order, h = idx.candidates(gu.to_dev(Q[rows]), w.f_M)
+    parity.check_aps(X, Q, ps, gi, gv, ns, rec, order.cpu().numpy(), h.cpu().numpy(), w.metric, w.f_M, 0.9,
+                     100, rows=rows)
+    assert (gi[rows] >= 0).all()
+    print(f"[plain] k=100: partitions {ns.mean():.2f}", flush=True)
