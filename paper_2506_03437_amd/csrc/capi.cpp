@@ -817,13 +817,14 @@ void ensure_workspace(quake_index* idx, int64_t nc, int64_t M, int64_t kk, int64
     w.ri = mem.alloc<int64_t>(w.kk_cap);
   }
   if (items > w.items_cap || kk > w.k_cap || !w.items) {
-    mem.release(w.items); mem.release(w.pk); mem.release(w.pi); mem.release(w.bitems);
-    w.items = nullptr; w.pk = nullptr; w.pi = nullptr; w.bitems = nullptr;
+    mem.release(w.items); mem.release(w.pk); mem.release(w.pi); mem.release(w.bitems); mem.release(w.xitem);
+    w.items = nullptr; w.pk = nullptr; w.pi = nullptr; w.bitems = nullptr; w.xitem = nullptr;
     w.items_cap = std::max(items, w.items_cap);
     w.k_cap = std::max<int64_t>(kk, w.k_cap);
     w.items = mem.alloc<int4>(w.items_cap);
     // batched items never outnumber the plain ones (one per query set, not per query)
     w.bitems = mem.alloc<int4>(2 * w.items_cap);
+    w.xitem = mem.alloc<int64_t>(w.items_cap);
     w.pk = mem.alloc<float>((size_t)w.items_cap * w.k_cap);
     w.pi = mem.alloc<int64_t>((size_t)w.items_cap * w.k_cap);
   }
@@ -850,11 +851,13 @@ void ensure_workspace(quake_index* idx, int64_t nc, int64_t M, int64_t kk, int64
     w.sorted_base = mem.alloc<int64_t>(w.pairs_cap);
   }
   if (nc + 1 > w.parts_cap || !w.pcount) {
-    for (void* p : {(void*)w.pcount, (void*)w.pstart, (void*)w.pitem}) mem.release(p);
+    for (void* p : {(void*)w.pcount, (void*)w.pstart, (void*)w.pitem, (void*)w.pxoff, (void*)w.pxcd}) mem.release(p);
     w.parts_cap = nc + 1;
     w.pcount = mem.alloc<int32_t>(w.parts_cap);
     w.pstart = mem.alloc<int32_t>(w.parts_cap);
     w.pitem = mem.alloc<int64_t>(w.parts_cap);
+    w.pxoff = mem.alloc<int64_t>(w.parts_cap);
+    w.pxcd = mem.alloc<int32_t>(w.parts_cap);
     QK_HIP(hipMemset(w.pcount, 0, w.parts_cap * sizeof(int32_t)));
   }
 }
@@ -910,7 +913,7 @@ std::vector<uint64_t> graph_key(const quake_index* idx, const Store& st, const J
       u(w.st_w), u(w.st_weff), u(w.st_done), u(w.st_item), u(w.st_demand), u(w.st_rho), u(w.st_p0), u(w.st_V),
       u(w.st_vsum), u(w.st_r), u(w.rk), u(w.ri), u(w.items), u(w.pk), u(w.pi), u(w.st_vecs), u(w.st_pair),
       u(w.q16), u(w.qn2f), u(w.pair_q), u(w.pair_p), u(w.pair_pos), u(w.pair_base), u(w.sorted), u(w.sorted_q), u(w.sorted_base), u(w.bitems), u(w.pcount),
-      u(w.pstart), u(w.pitem), u(w.total), u(w.blk)};
+      u(w.pstart), u(w.pitem), u(w.pxoff), u(w.pxcd), u(w.xitem), u(w.total), u(w.blk)};
   uint64_t tr, tro;
   std::memcpy(&tr, &a.tau_r, 8);
   std::memcpy(&tro, &a.tau_rho, 8);
@@ -1054,6 +1057,7 @@ size_t workspace_layout(Workspace* w, char* base, int64_t nq, int64_t nc, int64_
   take(x.ri, n * kk);
   take(x.items, items);
   take(x.bitems, 2 * items);
+  take(x.xitem, items);
   take(x.pk, items * kk);
   take(x.pi, items * kk);
   take(x.total, COUNTERS);
@@ -1063,6 +1067,8 @@ size_t workspace_layout(Workspace* w, char* base, int64_t nq, int64_t nc, int64_
   take(x.pcount, nc + 1);
   take(x.pstart, nc + 1);
   take(x.pitem, nc + 1);
+  take(x.pxoff, nc + 1);
+  take(x.pxcd, nc + 1);
   if (w) {
     w->nq_cap = n;
     w->scores_cap = n * nc;

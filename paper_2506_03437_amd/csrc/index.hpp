@@ -151,13 +151,17 @@ struct Workspace {
   int32_t* pcount = nullptr;    // [nlist] pairs per partition (kept zeroed between rounds)
   int32_t* pstart = nullptr;    // [nlist + 1]
   int64_t* pitem = nullptr;     // [nlist] first batched work item of each partition (numbered in Store::order)
+  int64_t* pxoff = nullptr;     // [nlist] first place of each partition's items in its compute die's queue
+  int32_t* pxcd = nullptr;      // [nlist] that queue (partitions of size rank r: queue r % 8)
+  int64_t* xitem = nullptr;     // [items] batched items in the order the eight queues hand them out
   // device counters (COUNTERS of them): [0] items, [1] vectors, [2] pairs of
   // the round, [3] batched items of the round, [4] batched distinct vector
   // reads (each touched partition once per round) and [5] batched
   // query-vector products summed over the search, [6] plain-scan vectors
   // summed over the search, [7] head of the round's item queue, [8] first
   // query cut from the round, [9] batched vector reads counted once per
-  // query set, [16] item queue of the batched scan
+  // query set, [16, 24) heads of the batched scan's eight item queues,
+  // [24, 32) their lengths
   int64_t* total = nullptr;
   int64_t* blk = nullptr;       // [nq / 256 + 1][4] per-block planning sums, then offsets
   int64_t* h_total = nullptr;   // pinned host mirror

@@ -37,7 +37,8 @@ constexpr int BUF = 2 * WAVE;   // per-query candidate pool (two entries per lan
                                 // max(kk, 64) <= 64 entries, so a whole tile's 64 always fit after one
 constexpr int MAX_ITEM_TILES = 1024;  // pool slots are 16-bit offsets from the item's first slot
 constexpr int SLACK = 16;       // entries a mid-item cut may keep beyond kk (room permitting)
-constexpr int QUEUE_X = 16;     // counters[16]: item queue of the batched scan
+constexpr int QUEUE_X = 16;     // counters[16, 24): the batched scan's item queues, [24, 32): their lengths
+constexpr int XCDS = 8;         // compute dies (XCDs) of the GPU, each with its own L2
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(8))) _Float16 f16x8;
@@ -113,11 +114,18 @@ __global__ __launch_bounds__(256) void k_pairs(int64_t nq, int M, int chunk_tile
 // adds to the running totals the round's distinct vector reads (each
 // partition a round touches, once), its reads counted once per query set,
 // and its query-vector products.  One block.
+//
+// The items also go to eight queues, one per compute die (XCD): the
+// partition of size rank r to queue r % 8, each queue largest partition
+// first.  A scan block takes items from its die's queue (then from the
+// others), so the query sets of a chunk are scored on one die at about the
+// same time and its L2 serves their repeated reads of the chunk.
 __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles, int32_t* __restrict__ pcount,
                                                        const int32_t* __restrict__ psize,
                                                        const int32_t* __restrict__ order, int32_t* __restrict__ pstart,
-                                                       int64_t* __restrict__ pitem, int64_t* __restrict__ counters) {
-  __shared__ int64_t sp[1024], si[1024];
+                                                       int64_t* __restrict__ pitem, int64_t* __restrict__ pxoff,
+                                                       int32_t* __restrict__ pxcd, int64_t* __restrict__ counters) {
+  __shared__ int64_t sp[1024], si[1024], sx[1024];
   __shared__ unsigned long long reads, set_reads, products;
   const int t = threadIdx.x;
   const int64_t per = (N + 1023) / 1024;
@@ -158,6 +166,33 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
     pitem[p] = ri;
     ri += items_of(p);
   }
+  // the die queues: a prefix over the ranks of each residue
+  for (int x = 0; x < XCDS; ++x) {
+    int64_t mine = 0;
+    for (int64_t r = lo; r < hi; ++r)
+      if ((r & (XCDS - 1)) == x) mine += items_of(order[r]);
+    sx[t] = mine;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+      const int64_t a = (t >= o) ? sx[t - o] : 0;
+      __syncthreads();
+      sx[t] += a;
+      __syncthreads();
+    }
+    int64_t run = sx[t] - mine;
+    for (int64_t r = lo; r < hi; ++r)
+      if ((r & (XCDS - 1)) == x) {
+        const int64_t p = order[r];
+        pxoff[p] = run;
+        pxcd[p] = x;
+        run += items_of(p);
+      }
+    if (t == 0) {
+      counters[QUEUE_X + x] = 0;
+      counters[QUEUE_X + XCDS + x] = sx[1023];
+    }
+    __syncthreads();
+  }
   // every thread has read the counts it needs before any is cleared
   __syncthreads();
   int64_t rp = sp[t] - np;
@@ -176,7 +211,6 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
     counters[4] += (int64_t)reads;
     counters[5] += (int64_t)products;
     counters[9] += (int64_t)set_reads;
-    counters[QUEUE_X] = 0;
   }
 }
 
@@ -204,7 +238,10 @@ __global__ __launch_bounds__(256) void k_pair_scatter(const int64_t* __restrict_
 __global__ __launch_bounds__(256) void k_items(int64_t N, int chunk_tiles, const int32_t* __restrict__ pstart,
                                                 const int64_t* __restrict__ pitem,
                                                 const int32_t* __restrict__ psize,
-                                                const int64_t* __restrict__ poff, int4* __restrict__ bitems) {
+                                                const int64_t* __restrict__ poff, const int64_t* __restrict__ pxoff,
+                                                const int32_t* __restrict__ pxcd,
+                                                const int64_t* __restrict__ counters, int4* __restrict__ bitems,
+                                                int64_t* __restrict__ xitem) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (p >= N) return;
   const int np = pstart[p + 1] - pstart[p];
@@ -213,9 +250,13 @@ __global__ __launch_bounds__(256) void k_items(int64_t N, int chunk_tiles, const
   const int n = sets * chunks_of(psize[p], chunk_tiles);
   const int64_t tile0 = poff[p];
   const int4 b = make_int4(psize[p], (int)(uint32_t)(uint64_t)tile0, (int)(uint32_t)((uint64_t)tile0 >> 32), sets);
+  const int x = pxcd[p];
+  int64_t xbase = pxoff[p];
+  for (int y = 0; y < x; ++y) xbase += counters[QUEUE_X + XCDS + y];
   for (int local = 0; local < n; ++local) {
     bitems[2 * (pitem[p] + local)] = make_int4((int)p, local, np, pstart[p]);
     bitems[2 * (pitem[p] + local) + 1] = b;
+    xitem[xbase + local] = pitem[p] + local;
   }
 }
 
@@ -224,14 +265,14 @@ void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_
                      ws.cand, st.d_size, ws.st_m, ws.st_weff, ws.st_item, ws.st_pair, ws.pcount, ws.pair_q, ws.pair_p,
                      ws.pair_pos, ws.pair_base);
   hipLaunchKernelGGL(k_part_prefix, dim3(1), dim3(1024), 0, s, st.nlist, a.chunk_tiles, ws.pcount, st.d_size,
-                     st.d_order, ws.pstart, ws.pitem, ws.total);
+                     st.d_order, ws.pstart, ws.pitem, ws.pxoff, ws.pxcd, ws.total);
   // at most wmax pairs per query; the kernel reads this round's count
   const int64_t bound = (a.nq * a.wmax + 255) / 256;
   hipLaunchKernelGGL(k_pair_scatter, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(bound, 2048))), dim3(256),
                      0, s, ws.total, ws.pair_p, ws.pair_pos, ws.pair_q, ws.pair_base, ws.pstart, ws.sorted,
                      ws.sorted_q, ws.sorted_base);
   hipLaunchKernelGGL(k_items, dim3((unsigned)((st.nlist + 255) / 256)), dim3(256), 0, s, st.nlist, a.chunk_tiles,
-                     ws.pstart, ws.pitem, st.d_size, st.d_off, ws.bitems);
+                     ws.pstart, ws.pitem, st.d_size, st.d_off, ws.pxoff, ws.pxcd, ws.total, ws.bitems, ws.xitem);
 }
 
 // ---------------------------------------------------------------- MFMA scan
@@ -252,7 +293,7 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
     const int64_t* __restrict__ sorted_base, int chunk_tiles, const uint16_t* __restrict__ q16, int dp16,
     const float* __restrict__ qn2f, const uint16_t* __restrict__ v16, const float* __restrict__ v16n,
     const int64_t* __restrict__ sid, const float* __restrict__ rk, const int64_t* __restrict__ ri, int kk,
-    float* __restrict__ pk, int64_t* __restrict__ pi) {
+    float* __restrict__ pk, int64_t* __restrict__ pi, const int64_t* __restrict__ xitem) {
   // k-steps per stage: 4 (two for each wave of a pair), else 2 or 1 where
   // that leaves an odd number of stages per tile (a tile always starts in
   // LDS buffer 0; with 1 the pair takes alternate stages); the two stages,
@@ -276,14 +317,18 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
   // one touches that buffer
   int64_t* next_item = reinterpret_cast<int64_t*>(&RING[1][0]);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // Blocks take items in order from one queue: items differ widely in cost
+  // Blocks take items in order from queues: items differ widely in cost
   // (power-law partition sizes and query counts), so a static split would
   // leave some compute units idle; the query sets of one chunk are
-  // consecutive items, scored at about the same time.  (A block claims its
-  // next item only when it is free: claiming ahead keeps large items from
-  // idle blocks at the end of a launch.)
+  // consecutive items of one queue, scored at about the same time.  A block
+  // takes from the queue of its compute die first (workgroups are dealt to
+  // the dies in turn, so block b runs on die b % 8), then from the others.
+  // (A block claims its next item only when it is free: claiming ahead
+  // keeps large items from idle blocks at the end of a launch.)
   const int64_t total = counters[3];
   unsigned long long* queue = (unsigned long long*)(counters + QUEUE_X);
+  int xq = 0;  // queues found empty so far (thread 0's)
+  const int x0 = (int)(blockIdx.x & (XCDS - 1));
   constexpr int nc8 = KS * 4;  // 8-element chunks per row of the 16-bit copy
   float (*Bk)[BUF] = BK[wave];
   uint16_t (*Bs)[BUF] = BS[wave];
@@ -295,7 +340,21 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
   for (int k = 0;; k ^= 1) {
     // every thread read next_item[k] two items ago, before the barrier that
     // started the last item
-    if (threadIdx.x == 0) next_item[k] = (int64_t)atomicAdd(queue, 1ull);
+    if (threadIdx.x == 0) {
+      int64_t got = total;  // none left
+      while (xq < XCDS) {
+        const int x = (x0 + xq) & (XCDS - 1);
+        const int64_t j = (int64_t)atomicAdd(queue + x, 1ull);
+        if (j < counters[QUEUE_X + XCDS + x]) {
+          int64_t base = 0;
+          for (int y = 0; y < x; ++y) base += counters[QUEUE_X + XCDS + y];
+          got = xitem[base + j];
+          break;
+        }
+        ++xq;
+      }
+      next_item[k] = got;
+    }
     __syncthreads();
     const int64_t it = next_item[k];
     if (it >= total) break;
@@ -708,7 +767,7 @@ static void scan_mfma_k(Workspace& ws, const Store& st, const RoundArgs& a, int 
 #define QK_MFMA_LAUNCH(KS)                                                                                      \
   hipLaunchKernelGGL((k_scan_mfma<F16, KS, IP>), dim3(blocks), dim3(NT), 0, s, ws.total, ws.bitems,           \
                      ws.sorted_q, ws.sorted_base, a.chunk_tiles, ws.q16, st.dp16, ws.qn2f, st.v16, st.v16n, st.ids, \
-                     ws.rk, ws.ri, a.kk, ws.pk, ws.pi)
+                     ws.rk, ws.ri, a.kk, ws.pk, ws.pi, ws.xitem)
   switch (ks) {
     case 2: QK_MFMA_LAUNCH(2); break;
     case 4: QK_MFMA_LAUNCH(4); break;
