@@ -201,12 +201,14 @@ int quake_access_stats(quake_index* index, int32_t level, int64_t* hits, int64_t
 
 /* lambda(s) on this GPU (Sec. 4.1 measures it by offline profiling; Sec. 8
  * asks for a per-device profile on heterogeneous hardware): for each
- * sizes[i], a one-partition index of that many of this index's vectors (same
- * metric and copies) is searched by nq of them with params' path and k
- * (nprobe 1), reps times after one warm-up; out_us[i] (host) = microseconds
- * per query, i.e. the cost one query adds to a batch of nq that scans one
- * partition of sizes[i] vectors.  sizes[i] and nq may not exceed the index's
- * live vectors.  Allocates its temporaries like the index does. */
+ * sizes[i], an index of eight partitions of that many of this index's
+ * vectors (same metric and copies) is searched by nq of them with params'
+ * path and k, once with nprobe 1 and once with nprobe 8, reps times each
+ * after a warm-up; out_us[i] (host) = (time with 8 - time with 1) / 7 in
+ * microseconds per query: what one more partition of sizes[i] vectors costs
+ * a query in a batch of nq, without the work every search does once.  8 x
+ * sizes[i] and nq may not exceed the index's live vectors.  Allocates its
+ * temporaries like the index does. */
 int quake_profile_latency(quake_index* index, const int32_t* sizes, int32_t points, int32_t nq,
                           const quake_search_params* params, int32_t reps, double* out_us, void* stream);
 

@@ -628,12 +628,13 @@ int quake_profile_latency(quake_index* index, const int32_t* sizes, int32_t poin
     QK_CHECK(sizes && out_us && points >= 1, QUAKE_E_INVALID, "need sizes, out_us and points >= 1");
     QK_CHECK(nq >= 1 && reps >= 1 && params, QUAKE_E_INVALID, "need nq >= 1, reps >= 1 and params");
     qk::Store& st = index->L0;
+    constexpr int PARTS = 8;  // partitions of each profiling index
     int64_t want = nq;
     for (int32_t i = 0; i < points; ++i) {
       QK_CHECK(sizes[i] >= 1, QUAKE_E_INVALID, "sizes must be >= 1");
-      want = std::max<int64_t>(want, sizes[i]);
+      want = std::max<int64_t>(want, (int64_t)PARTS * sizes[i]);
     }
-    QK_CHECK(want <= st.live, QUAKE_E_INVALID, "the index holds fewer vectors than the largest size (or nq)");
+    QK_CHECK(want <= st.live, QUAKE_E_INVALID, "the index holds fewer than 8 x the largest size (or nq) vectors");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int d = index->d, dp = index->dp;
     // the first `want` live vectors of the store, partition by partition
@@ -654,10 +655,10 @@ int quake_profile_latency(quake_index* index, const int32_t* sizes, int32_t poin
                             hipMemcpyDeviceToDevice, s));
     QK_HIP(hipStreamSynchronize(s));
     quake_search_params sp = *params;
-    sp.nprobe = 1;
     sp.recall_target = 0.0;
     qk::Buf<int64_t> oi(index->mem, (size_t)nq * std::max(sp.k, 1));
     qk::Buf<float> od(index->mem, (size_t)nq * std::max(sp.k, 1));
+    qk::Buf<int32_t> assign(index->mem, (size_t)want);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     QK_HIP(hipEventCreate(&e0));
     QK_HIP(hipEventCreate(&e1));
@@ -666,30 +667,44 @@ int quake_profile_latency(quake_index* index, const int32_t* sizes, int32_t poin
       ~Events() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
     } ev{e0, e1};
     for (int32_t i = 0; i < points; ++i) {
-      // a one-partition index of sizes[i] of those vectors, same metric and copies
+      // an index of eight partitions of sizes[i] of those vectors each (same
+      // metric and copies); a partition scanned beyond the first costs
+      // (time with all eight - time with one) / 7 per query: what the
+      // cost model's lambda is, without the per-query work (centroid
+      // scoring, selection, rerank) every search does once
+      const int64_t n = (int64_t)PARTS * sizes[i];
+      std::vector<int32_t> a(n);
+      for (int64_t r = 0; r < n; ++r) a[r] = (int32_t)(r / sizes[i]);
+      qk::upload(assign.p, a, s);
+      QK_HIP(hipStreamSynchronize(s));
       quake_build_params bp{};
       bp.metric = index->metric;
       bp.storage_dtype = index->storage;
       bp.n_levels = 1;
-      bp.nlist = 1;
-      bp.kmeans_iters = 0;
+      bp.nlist = PARTS;
+      bp.assign = assign.p;
       quake_index* tmp = nullptr;
       const quake_allocator* alloc = index->mem.user.alloc ? &index->mem.user : nullptr;
-      int rc = quake_build(x.p, nullptr, sizes[i], d, &bp, alloc, stream, &tmp);
+      int rc = quake_build(x.p, nullptr, n, d, &bp, alloc, stream, &tmp);
       QK_CHECK(rc == QUAKE_OK, rc, "profile build: " + qk::g_error);
       std::unique_ptr<quake_index, void (*)(quake_index*)> hold(tmp, quake_free);
-      auto run = [&] {
-        const int r = quake_search(tmp, x.p, nq, &sp, oi.p, od.p, nullptr, nullptr, stream);
-        QK_CHECK(r == QUAKE_OK, r, "profile search: " + qk::g_error);
-      };
-      run();  // grows the workspace and captures the round graphs
-      QK_HIP(hipEventRecord(e0, s));
-      for (int32_t r = 0; r < reps; ++r) run();
-      QK_HIP(hipEventRecord(e1, s));
-      QK_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      QK_HIP(hipEventElapsedTime(&ms, e0, e1));
-      out_us[i] = (double)ms * 1e3 / reps / nq;
+      double us[2];
+      for (int v = 0; v < 2; ++v) {
+        sp.nprobe = v == 0 ? 1 : PARTS;
+        auto run = [&] {
+          const int r = quake_search(tmp, x.p, nq, &sp, oi.p, od.p, nullptr, nullptr, stream);
+          QK_CHECK(r == QUAKE_OK, r, "profile search: " + qk::g_error);
+        };
+        run();  // grows the workspace and captures the round graphs
+        QK_HIP(hipEventRecord(e0, s));
+        for (int32_t r = 0; r < reps; ++r) run();
+        QK_HIP(hipEventRecord(e1, s));
+        QK_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        QK_HIP(hipEventElapsedTime(&ms, e0, e1));
+        us[v] = (double)ms * 1e3 / reps / nq;
+      }
+      out_us[i] = std::max(0.0, (us[1] - us[0]) / (PARTS - 1));
     }
   });
 }

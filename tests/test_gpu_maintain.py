@@ -234,16 +234,17 @@ def test_two_level_maintenance_is_refused():
 
 
 def test_latency_profile_on_this_gpu(counted):
-    """lambda(s) measured on the device (one-partition indexes of s of the
-    index's vectors, nq queries, nprobe 1) is positive and grows with s, for
-    both scan paths, and the index it was taken from is left as it was."""
+    """lambda(s) measured on the device (the cost of one more partition of s
+    of the index's vectors per query: eight-partition indexes searched with
+    nprobe 8 and 1) is not negative and grows with s, for both scan paths,
+    and the index it was taken from is left as it was."""
     X, Q, idx, ps = counted
     before = idx.stats()
-    sizes = [64, 1024, 16384]
+    sizes = [64, 512, 2048]
     plain = idx.profile_latency(sizes, nq=1024, reps=2, k=10)
     batched = idx.profile_latency(sizes, nq=1024, reps=2, k=10, scan_mode="batched", scan_dtype="bf16",
                                   rerank_factor=4)
     print(f"[lambda] plain {plain} us, batched {batched} us per query", flush=True)
-    assert (plain > 0).all() and (batched > 0).all()
+    assert (plain >= 0).all() and (batched >= 0).all()
     assert plain[-1] > plain[0] and batched[-1] > batched[0]
     assert idx.stats() == before
