@@ -39,6 +39,12 @@ reason in the design notes):
 * R7  beta parameters a = (d + 1) / 2, b = 1/2.
 * Candidate order: "largest p_i first" equals ascending h (all caps share
   one rho and v is decreasing in t); ties by centroid value, then id.
+
+Estimator variants (Sec. 5.1, Table tab:recall_overhead): APS recomputes
+p_0 and p_i only when rho moved by more than tau_rho and reads the cap
+share from the table; APS-R recomputes after every partition, still from
+the table; APS-RP recomputes after every partition and evaluates the cap
+share directly (``ExactCap``).
 """
 
 from __future__ import annotations
@@ -73,6 +79,19 @@ def cap_fraction(t, d: int):
     return out
 
 
+class ExactCap:
+    """cap_fraction evaluated directly at every call, with no table: the
+    estimator of the variant that recomputes without precomputation
+    (APS-RP, Sec. 5.1 and Table tab:recall_overhead).  Negative t is taken
+    as 0, as the table does."""
+
+    def __init__(self, d: int):
+        self.d = d
+
+    def __call__(self, t: np.ndarray) -> np.ndarray:
+        return cap_fraction(np.maximum(np.asarray(t, dtype=np.float64), 0.0), self.d)
+
+
 class CapTable:
     """cap_fraction sampled at TABLE_POINTS even points of t in [0, 1] (R2)."""
 
@@ -100,6 +119,10 @@ class APSParams:
     f_M: float = 0.05
     tau_rho: float = 0.01
     metric: str = "l2"
+    # recompute p_0 and p_i after every partition scanned, whatever rho did
+    # (the APS-R and APS-RP variants of Table tab:recall_overhead); otherwise
+    # only when rho moved by more than tau_rho * rho
+    recompute_every: bool = False
 
 
 @dataclass
@@ -109,7 +132,7 @@ class APSStep:
     rho_new: float    # k-th distance after this step
     recomputed: bool
     recall: float     # estimate r after this step
-    recompute_gap: float  # |rho' - rho| - tau_rho * rho (inf when rho was inf)
+    recompute_gap: float  # |rho' - rho| - tau_rho * rho (inf when rho was inf or every step recomputes)
 
 
 @dataclass
@@ -239,7 +262,10 @@ def aps_search_one(ps: PartitionedSet, q: np.ndarray, params: APSParams, table: 
         res_i, res_v = merge_topk(res_i, res_v, ti, tv, k, metric)
         m += 1
         rho_new = kth_radius(res_i, res_v)
-        if math.isinf(rho):
+        if params.recompute_every:
+            gap = math.inf
+            do = True
+        elif math.isinf(rho):
             gap = math.inf
             do = not math.isinf(rho_new)
         else:
