@@ -50,6 +50,12 @@ enum {
 enum { QUAKE_L2 = 0, QUAKE_IP = 1 };
 enum { QUAKE_F32 = 0, QUAKE_BF16 = 1, QUAKE_F16 = 2 };
 enum { QUAKE_SCAN_PLAIN = 0, QUAKE_SCAN_BATCHED = 1 };
+/* Recall estimator of an adaptive search (Sec. 5.1, Table tab:recall_overhead):
+ * APS recomputes the partition probabilities when rho moved by more than
+ * tau_rho and reads the cap share from the 1,024-point table; APS_R
+ * recomputes after every partition, from the table; APS_RP recomputes after
+ * every partition and evaluates the share from the incomplete beta function. */
+enum { QUAKE_EST_APS = 0, QUAKE_EST_APS_R = 1, QUAKE_EST_APS_RP = 2 };
 
 /* Device memory provider for everything an index allocates: its partition
  * store, id map, search workspace and temporary build / update buffers.
@@ -112,6 +118,7 @@ typedef struct {
                               (IP: the MFMA dot of the rounded query and row, FP32 accumulation;
                               L2: |q|^2 + |x~|^2 - 2 q~.x~ with x~, q~ the rounded vectors) */
   int32_t window;          /* first-round speculation window (partitions per query); 0 -> auto */
+  int32_t estimator;       /* QUAKE_EST_APS (default), QUAKE_EST_APS_R or QUAKE_EST_APS_RP; every level */
 } quake_search_params;
 
 /* Build an index over x[n][d] (device, float32) with ids[n] (device int64,
@@ -134,7 +141,7 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d,
  * results are id -1 with +inf (L2) / -inf (IP).  Optional outputs (NULL to
  * skip): out_nscanned[nq] (device int32, partitions scanned at level 0) and
  * out_recall[nq] (device float64, the recall estimate at stop; 1 in nprobe mode).
- * Errors: INVALID (nq < 0, k, both/neither of nprobe / recall_target,
+ * Errors: INVALID (nq < 0, k, both/neither of nprobe / recall_target, an unknown estimator,
  * scan_dtype without a matching copy, a non-finite value in q; checked
  * before any search work), NOMEM, DEVICE. */
 int quake_search(quake_index* index, const float* q, int64_t nq, const quake_search_params* params,

@@ -72,4 +72,11 @@ void cap_fraction_table(int d, double* out) {
   for (int j = 0; j < CAP_TABLE_POINTS; ++j) out[j] = cap_fraction((double)j / (CAP_TABLE_POINTS - 1), d);
 }
 
+void cap_model_table(int d, double* out) {
+  cap_fraction_table(d, out);
+  const double a = 0.5 * (d + 1);
+  out[CAP_TABLE_POINTS] = a;
+  out[CAP_TABLE_POINTS + 1] = log_beta(a, 0.5);
+}
+
 }  // namespace qk

@@ -716,6 +716,7 @@ Job resolve(const quake_index* idx, const Store& st, const quake_search_params* 
   QK_CHECK(p->f_M >= 0 && p->tau_rho >= 0 && p->upper_f_M >= 0 && p->upper_recall_target >= 0 &&
                p->upper_recall_target <= 1.0 && p->window >= 0,
            QUAKE_E_INVALID, "negative or out-of-range search parameter");
+  QK_CHECK(p->estimator >= QUAKE_EST_APS && p->estimator <= QUAKE_EST_APS_RP, QUAKE_E_INVALID, "unknown estimator");
   Job r;
   r.k = p->k;
   r.batched = p->scan_mode == QUAKE_SCAN_BATCHED ? 1 : 0;
@@ -734,6 +735,7 @@ Job resolve(const quake_index* idx, const Store& st, const quake_search_params* 
   r.tau_r = p->recall_target;
   r.f_M = p->f_M > 0 ? p->f_M : 0.05;
   r.tau_rho = p->tau_rho > 0 ? p->tau_rho : 0.01;
+  r.est = p->estimator;
   const int64_t N = st.nlist;
   const int64_t cap_m = N > 4096 ? 2048 : qk::MAX_CANDIDATES;
   const quake_tuning& tu = idx->tune;
@@ -919,6 +921,7 @@ std::vector<uint64_t> graph_key(const quake_index* idx, const Store& st, const J
   std::memcpy(&tro, &a.tau_rho, 8);
   k.push_back(tr);
   k.push_back(tro);
+  k.push_back((uint64_t)a.est);
   return k;
 }
 
@@ -1128,6 +1131,7 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
   a.dim = idx->d;
   a.tau_r = job.tau_r;
   a.tau_rho = job.tau_rho;
+  a.est = job.est;
   const bool count = job.count && idx->count_access;
   a.hits = count ? st.d_hits : nullptr;
   if (count) st.window += nq;
@@ -1193,6 +1197,7 @@ void upper_level(quake_index* idx, int64_t nq, int M0, const quake_search_params
   up.tau_r = p->upper_recall_target > 0 ? p->upper_recall_target : 0.99;
   up.f_M = p->upper_f_M > 0 ? p->upper_f_M : 0.25;
   up.tau_rho = p->tau_rho > 0 ? p->tau_rho : 0.01;
+  up.est = p->estimator;
   up.M = candidate_count(up.f_M, L1.nlist);
   up.w0 = up.M;  // the upper level is small: scan its candidates in one round
   up.wmax = up.M;
@@ -1405,10 +1410,10 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const 
     build_store(idx.get(), L1, L0.centroids, dp, nullptr, L0.nlist, idx->top_of, 0.0, QUAKE_F32, true, s);
   }
 
-  idx->h_cap_table.resize(qk::CAP_TABLE_POINTS);
-  qk::cap_fraction_table(d, idx->h_cap_table.data());
-  idx->cap_table = idx->mem.alloc<double>(qk::CAP_TABLE_POINTS);
-  QK_HIP(hipMemcpyAsync(idx->cap_table, idx->h_cap_table.data(), qk::CAP_TABLE_POINTS * sizeof(double),
+  idx->h_cap_table.resize(qk::CAP_TABLE_SIZE);
+  qk::cap_model_table(d, idx->h_cap_table.data());
+  idx->cap_table = idx->mem.alloc<double>(qk::CAP_TABLE_SIZE);
+  QK_HIP(hipMemcpyAsync(idx->cap_table, idx->h_cap_table.data(), qk::CAP_TABLE_SIZE * sizeof(double),
                         hipMemcpyHostToDevice, s));
   QK_HIP(hipStreamSynchronize(s));
   *out = idx.release();
@@ -1576,6 +1581,8 @@ int quake_candidates(quake_index* idx, const float* q, int64_t nq, const quake_s
   QK_CHECK(params->f_M >= 0 && params->upper_f_M >= 0 && params->upper_recall_target >= 0 &&
                params->upper_recall_target <= 1.0 && params->tau_rho >= 0,
            QUAKE_E_INVALID, "negative or out-of-range search parameter");
+  QK_CHECK(params->estimator >= QUAKE_EST_APS && params->estimator <= QUAKE_EST_APS_RP, QUAKE_E_INVALID,
+           "unknown estimator");
   const Store& st = idx->L0;
   const int M = candidate_count(params->f_M > 0 ? params->f_M : 0.05, st.nlist);
   QK_CHECK(M <= (st.nlist > 4096 ? 2048 : qk::MAX_CANDIDATES), QUAKE_E_INVALID, "too many candidates");

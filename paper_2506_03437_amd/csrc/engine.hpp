@@ -21,6 +21,7 @@ struct Job {
   int k = 0, kk = 0, aps = 0, M = 0, w0 = 0, wmax = 0, batched = 0, dtype16 = QUAKE_F32;
   int rerank = 1;      // batched path: re-score the kk candidates in FP32 (0: keep the 16-bit values)
   double tau_r = 0, f_M = 0, tau_rho = 0.01;
+  int est = QUAKE_EST_APS;  // recall estimator variant
   bool given = false;  // candidate rows already in ws.cand0 / ws.mq0 (level 0 of two levels)
   bool count = true;   // add the queries to the store's access statistics (not for insert routing)
 };

@@ -32,6 +32,9 @@ constexpr int KMAX = 256;         // largest result list of the wave-list scans
 constexpr int KMAX_LARGE = 1024;  // largest result list at all (upper level of two levels)
 constexpr int SORTED_ITEM_MAX = 1024;  // vectors per item of the sort-based scan (16 tiles)
 constexpr int CAP_TABLE_POINTS = 1024;
+// the device table holds the points, then a = (d + 1) / 2 and log B(a, 1/2)
+// for the direct evaluation of the cap share
+constexpr int CAP_TABLE_SIZE = CAP_TABLE_POINTS + 2;
 
 // Row length of the 16-bit store copy: d rounded up to 32 * KS for a k-step
 // count KS the MFMA scan is compiled for (2, 4, 8, 12, 16, 24 or 32).
@@ -231,6 +234,8 @@ namespace qk {
 
 // cap_table.cpp
 void cap_fraction_table(int d, double* out /*[CAP_TABLE_POINTS]*/);
+// the table, then a = (d + 1) / 2 and log B(a, 1/2): the device copy
+void cap_model_table(int d, double* out /*[CAP_TABLE_SIZE]*/);
 double cap_fraction(double t, int d);
 
 // kernels: centroids and candidates (k_centroids.hip)
@@ -283,6 +288,7 @@ struct RoundArgs {
   int metric;
   int dim;           // d, for nothing but documentation of the table
   double tau_r, tau_rho;
+  int est;           // recall estimator variant (QUAKE_EST_*)
   int64_t items_cap;
   int blocks;        // grid of the persistent scan kernels (they read their item counts on the device)
   int slot_ids;      // 1: the lists carry store slots below 2^31 (batched path), not ids

@@ -22,6 +22,12 @@
 //   r = p_0 + (1 - p_0) * (v_1 + ... + v_{m-1}) / (v_1 + ... + v_{M-1}).
 // Until k results exist rho = +inf (all t = 0) and r is held at 0.  The
 // model is evaluated in FP64; it is the only FP64 on the device.
+//
+// Estimator variants (Sec. 5.1, Table tab:recall_overhead): APS recomputes
+// when rho moved by more than tau_rho, from the table; APS-R recomputes after
+// every partition, from the table; APS-RP recomputes after every partition
+// and evaluates each share directly from the incomplete beta function.  The
+// window prediction (speculation, not a decision) always reads the table.
 #include "common.hpp"
 #include "index.hpp"
 
@@ -454,6 +460,50 @@ __device__ __forceinline__ double cap_share(const double* __restrict__ table, do
   return a + f * (b - a);
 }
 
+// 1 / (1 + e_1 / (1 + e_2 / (1 + ...))), the continued fraction of I_x(a, b)
+// with e_{2m+1} = -(a + m)(a + b + m) x / ((a + 2m)(a + 2m + 1)) and
+// e_{2m} = m (b - m) x / ((a + 2m - 1)(a + 2m)) (NIST DLMF 8.17.22), summed by
+// the modified Lentz method (Thompson and Barnett, J. Comput. Phys. 64, 1986)
+// until a factor is within 1e-16 of 1 (at most 4,096 terms).
+__device__ double beta_fraction(double a, double b, double x) {
+  const double tiny = 1e-300;
+  double f = 1.0, C = 1.0, D = 0.0;
+  for (int j = 1; j <= 4096; ++j) {
+    const double m = (double)(j >> 1);
+    const double e = (j & 1) ? -(a + m) * (a + b + m) * x / ((a + 2.0 * m) * (a + 2.0 * m + 1.0))
+                             : m * (b - m) * x / ((a + 2.0 * m - 1.0) * (a + 2.0 * m));
+    D = 1.0 + e * D;
+    if (fabs(D) < tiny) D = tiny;
+    C = 1.0 + e / C;
+    if (fabs(C) < tiny) C = tiny;
+    D = 1.0 / D;
+    const double delta = C * D;
+    f *= delta;
+    if (fabs(delta - 1.0) < 1e-16) break;
+  }
+  return 1.0 / f;
+}
+
+// The share of the ball beyond the bisector evaluated directly:
+// 1/2 I_{1 - t^2}(a, 1/2) with a = (d + 1) / 2 and lb = log B(a, 1/2), both
+// stored after the table's points.  The fraction is summed for x = 1 - t^2
+// below (a + 1) / (a + 5/2), else for I_{t^2}(1/2, a) = 1 - I_{1-t^2}(a, 1/2),
+// with t^2 passed in exactly.
+__device__ double cap_direct(const double* __restrict__ table, double t) {
+  if (!(t < 1.0)) return 0.0;
+  if (t < 0.0) t = 0.0;
+  const double a = table[CAP_TABLE_POINTS], lb = table[CAP_TABLE_POINTS + 1], b = 0.5;
+  const double y = t * t, x = 1.0 - y;
+  if (y <= 0.0) return 0.5;
+  const double pre = exp(a * log(x) + b * log(y) - lb);
+  if (x < (a + 1.0) / (a + b + 2.0)) return 0.5 * (pre / a) * beta_fraction(a, b, x);
+  return 0.5 * (1.0 - (pre / b) * beta_fraction(b, a, y));
+}
+
+__device__ __forceinline__ double cap_value(const double* __restrict__ table, double t, bool direct) {
+  return direct ? cap_direct(table, t) : cap_share(table, t);
+}
+
 // Euclidean distance to a result key: sqrt of the squared L2 distance, or for
 // inner product on unit-norm data sqrt(|q|^2 + 1 - 2 s) with s = -key.
 __device__ __forceinline__ double key_radius(float key, int ip, double qn2) {
@@ -471,13 +521,13 @@ struct Model {
 // p_0, V = sum v_i and the committed mass v_1 + ... + v_{m-1} for radius rho
 // (candidates 1 .. M - 1 of the query).
 __device__ void recompute_model(Model& md, double rho, const float* __restrict__ hq, int M, int committed,
-                                const double* __restrict__ table) {
+                                const double* __restrict__ table, bool direct) {
   const int lane = lane_id();
   double vs = 0.0, pr = 1.0, vc = 0.0;
   const bool inf = __builtin_isinf(rho);
   for (int i = 1 + lane; i < M; i += WAVE) {
     const double t = inf ? 0.0 : (double)hq[i] / rho;
-    const double v = cap_share(table, t);
+    const double v = cap_value(table, t, direct);
     vs += v;
     pr *= (1.0 - v);
     if (i < committed) vc += v;
@@ -613,7 +663,7 @@ struct PackedList {
 // stop point are discarded.  Then predict the next window.
 template <class List>
 __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restrict__ mq, int k, int kk, int aps,
-                             int ip, int chunk_tiles, int wmax, int wscale, double tau_r, double tau_rho,
+                             int ip, int chunk_tiles, int wmax, int wscale, double tau_r, double tau_rho, int est,
                              const int32_t* __restrict__ cand, const float* __restrict__ hcand,
                              const int32_t* __restrict__ psize, const double* __restrict__ qn2,
                              const float* __restrict__ pk, const int64_t* __restrict__ pi,
@@ -664,12 +714,12 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
     const bool full = kth_id >= 0;
     const double rho_new = full ? key_radius(L.key(k - 1), ip, qn) : __builtin_inf();
     if (committed == 1) {
-      recompute_model(md, rho_new, hq, Mq, committed, table);
+      recompute_model(md, rho_new, hq, Mq, committed, table, est == QUAKE_EST_APS_RP);
     } else {
-      const bool redo = __builtin_isinf(md.rho) ? !__builtin_isinf(rho_new)
-                                                 : fabs(rho_new - md.rho) > tau_rho * md.rho;
+      const bool redo = est != QUAKE_EST_APS || (__builtin_isinf(md.rho) ? !__builtin_isinf(rho_new)
+                                                                          : fabs(rho_new - md.rho) > tau_rho * md.rho);
       if (redo) {
-        recompute_model(md, rho_new, hq, Mq, committed, table);
+        recompute_model(md, rho_new, hq, Mq, committed, table, est == QUAKE_EST_APS_RP);
       } else if (md.V > 0.0) {
         const float hc = j < WAVE ? readlane_f(my_h, j) : hq[committed - 1];  // committed - 1 = m0 + j
         const double t = __builtin_isinf(md.rho) ? 0.0 : (double)hc / md.rho;
@@ -707,7 +757,7 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
 #define QK_COMMIT_PARAMS                                                                                          \
   int64_t nq, int M, const int32_t *__restrict__ mq, int k, int kk, int aps, int ip, int chunk_tiles, int wmax,  \
       int wscale,                                                                                                 \
-      double tau_r, double tau_rho, const int32_t *__restrict__ cand, const float *__restrict__ hcand,            \
+      double tau_r, double tau_rho, int est, const int32_t *__restrict__ cand, const float *__restrict__ hcand,   \
       const int32_t *__restrict__ psize, const double *__restrict__ qn2, const float *__restrict__ pk,            \
       const int64_t *__restrict__ pi, const double *__restrict__ table, int32_t *__restrict__ st_m,              \
       int32_t *__restrict__ st_w, int32_t *__restrict__ st_done, const int32_t *__restrict__ st_weff,            \
@@ -715,7 +765,7 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
       double *__restrict__ st_V, double *__restrict__ st_vsum, double *__restrict__ st_r, float *__restrict__ rk, \
       int64_t *__restrict__ ri, uint32_t *__restrict__ hits
 #define QK_COMMIT_ARGS                                                                                        \
-  M, mq, k, kk, aps, ip, chunk_tiles, wmax, wscale, tau_r, tau_rho, cand, hcand, psize, qn2, pk, pi, table, st_m, st_w, \
+  M, mq, k, kk, aps, ip, chunk_tiles, wmax, wscale, tau_r, tau_rho, est, cand, hcand, psize, qn2, pk, pi, table, st_m, st_w, \
       st_done, st_weff, st_item, st_rho, st_p0, st_V, st_vsum, st_r, rk, ri, hits
 
 // Lists longer than a wave: one 64-thread block per query, lists in LDS.
@@ -744,7 +794,8 @@ void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const dou
   if (a.nq <= 0) return;
 #define QK_COMMIT(KERNEL, GRID, BLOCK)                                                                        \
   hipLaunchKernelGGL(KERNEL, dim3((unsigned)(GRID)), dim3(BLOCK), 0, s, a.nq, a.M, ws.mq, a.k, a.kk, a.aps,    \
-                     a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.wscale, a.tau_r, a.tau_rho, ws.cand,     \
+                     a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.wscale, a.tau_r, a.tau_rho, a.est,      \
+                     ws.cand,                                                                                   \
                      ws.h,                                                                                      \
                      st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_weff,        \
                      ws.st_item, ws.st_rho, ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri, a.hits)

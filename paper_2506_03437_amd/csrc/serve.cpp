@@ -208,6 +208,7 @@ struct quake_server {
     a.dim = idx->d;
     a.tau_r = job.tau_r;
     a.tau_rho = job.tau_rho;
+    a.est = job.est;
     a.items_cap = std::min<int64_t>(idx->ws.items_cap, items);
     a.blocks = blocks;
     a.hits = st.d_hits;

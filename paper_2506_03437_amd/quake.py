@@ -88,7 +88,7 @@ class SearchParams(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("nprobe", ctypes.c_int32), ("recall_target", ctypes.c_double),
                 ("f_M", ctypes.c_double), ("tau_rho", ctypes.c_double), ("upper_recall_target", ctypes.c_double),
                 ("upper_f_M", ctypes.c_double), ("scan_mode", ctypes.c_int32), ("scan_dtype", ctypes.c_int32),
-                ("rerank_factor", ctypes.c_int32), ("window", ctypes.c_int32)]
+                ("rerank_factor", ctypes.c_int32), ("window", ctypes.c_int32), ("estimator", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):
@@ -234,15 +234,23 @@ def quake_build(x, ids=None, *, metric="l2", nlist=256, storage="f32", n_levels=
     return h.value
 
 
+# recall estimator variants (QUAKE_EST_*): the threshold recompute from the
+# table, every-partition recompute from the table, and every-partition
+# recompute with the cap share evaluated directly
+ESTIMATORS = {"aps": 0, "aps-r": 1, "aps-rp": 2}
+
+
 def _search_params(k=10, nprobe=0, recall_target=0.0, f_M=0.0, tau_rho=0.0, upper_recall_target=0.0,
-                   upper_f_M=0.0, scan_mode="plain", scan_dtype="f32", rerank_factor=0, window=0) -> SearchParams:
+                   upper_f_M=0.0, scan_mode="plain", scan_dtype="f32", rerank_factor=0, window=0,
+                   estimator="aps") -> SearchParams:
+    est = ESTIMATORS[estimator] if isinstance(estimator, str) else int(estimator)
     return SearchParams(k, nprobe, recall_target, f_M, tau_rho, upper_recall_target, upper_f_M, _MODE[scan_mode],
-                        _DTYPE[scan_dtype], rerank_factor, window)
+                        _DTYPE[scan_dtype], rerank_factor, window, est)
 
 
 def quake_search(handle: int, q, *, k=10, nprobe=0, recall_target=0.0, f_M=0.0, tau_rho=0.0,
                  upper_recall_target=0.0, upper_f_M=0.0, scan_mode="plain", scan_dtype="f32", rerank_factor=0,
-                 window=0, outputs=None):
+                 window=0, estimator="aps", outputs=None):
     """Returns (ids int64 [nq,k], dist f32 [nq,k], nscanned int32 [nq], recall f64 [nq])."""
     import torch
     _dev(q, torch.float32)
@@ -255,7 +263,7 @@ def quake_search(handle: int, q, *, k=10, nprobe=0, recall_target=0.0, f_M=0.0, 
                    torch.empty((nq,), dtype=torch.float64, device=dev))
     ids, dist, ns, rec = outputs
     p = _search_params(k, nprobe, recall_target, f_M, tau_rho, upper_recall_target, upper_f_M, scan_mode, scan_dtype,
-                       rerank_factor, window)
+                       rerank_factor, window, estimator)
     _check(load_library().quake_search(handle, _ptr(q), nq, ctypes.byref(p), _ptr(ids), _ptr(dist), _ptr(ns),
                                        _ptr(rec), _stream()))
     return ids, dist, ns, rec
@@ -263,13 +271,13 @@ def quake_search(handle: int, q, *, k=10, nprobe=0, recall_target=0.0, f_M=0.0, 
 
 def quake_search_noalloc(handle: int, q, *, outputs, k=10, nprobe=0, recall_target=0.0, f_M=0.0, tau_rho=0.0,
                          upper_recall_target=0.0, upper_f_M=0.0, scan_mode="plain", scan_dtype="f32",
-                         rerank_factor=0, window=0):
+                         rerank_factor=0, window=0, estimator="aps"):
     """quake_search into caller-given outputs (ids, dist, nscanned, recall) with no allocation in the library."""
     import torch
     _dev(q, torch.float32)
     ids, dist, ns, rec = outputs
     p = _search_params(k, nprobe, recall_target, f_M, tau_rho, upper_recall_target, upper_f_M, scan_mode, scan_dtype,
-                       rerank_factor, window)
+                       rerank_factor, window, estimator)
     _check(load_library().quake_search_noalloc(handle, _ptr(q), q.shape[0], ctypes.byref(p), _ptr(ids), _ptr(dist),
                                                _ptr(ns), _ptr(rec), _stream()))
     return ids, dist, ns, rec

@@ -122,17 +122,20 @@ def replay_margin(res, tau_r, tau_rho, upto):
     return False
 
 
-def check_aps(X, Q, ps, gi, gv, ns, rec, order, h, metric, f_M, tau_r, k=10, rows=None):
+def check_aps(X, Q, ps, gi, gv, ns, rec, order, h, metric, f_M, tau_r, k=10, rows=None, estimator="aps"):
     """Adaptive-scan parity for the queries `rows` (default all) of a device
     search: the results are the top-k over the partitions the device
     scanned, the candidate order is a valid APS order, and the stop count
     and recall estimate replay the oracle's, except decisions within the
-    margins (at most 1% of the queries)."""
+    margins (at most 1% of the queries).  `estimator` names the variant the
+    device ran: "aps" (threshold recompute, table), "aps-r" (every
+    partition, table) or "aps-rp" (every partition, direct evaluation)."""
     from oracle import aps as oaps
     from oracle import ivf as oivf
     rows = np.arange(Q.shape[0]) if rows is None else np.asarray(rows)
-    table = oaps.CapTable(X.shape[1])
-    params = oaps.APSParams(k=k, recall_target=tau_r, f_M=f_M, metric=metric)
+    table = oaps.ExactCap(X.shape[1]) if estimator == "aps-rp" else oaps.CapTable(X.shape[1])
+    params = oaps.APSParams(k=k, recall_target=tau_r, f_M=f_M, metric=metric,
+                            recompute_every=estimator in ("aps-r", "aps-rp"))
     id_to_row = {int(i): r for r, i in enumerate(ps.ids.tolist())}
     margin = 0
     ordered = 0

@@ -88,3 +88,39 @@ def test_maintenance_argument_errors():
     assert lib.quake_maintain(None, ctypes.byref(p), None, None) == quake.E_STATE
     assert lib.quake_access_stats(None, 0, None, None, 0, None) == quake.E_STATE
     assert b"handle" in lib.quake_last_error()
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every ctypes mirror of a header struct has the C compiler's size and
+    field offsets (a field added on one side only fails here)."""
+    import shutil
+    import subprocess
+    from paper_2506_03437_amd import quake
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    pairs = {
+        "quake_allocator": quake.Allocator, "quake_build_params": quake.BuildParams,
+        "quake_search_params": quake.SearchParams, "quake_tuning": quake.Tuning,
+        "quake_server_params": quake.ServerParams, "quake_server_report": quake.ServerReport,
+        "quake_kernel_profile": quake.KernelProfile, "quake_decision": quake.Decision,
+        "quake_maintain_params": quake.MaintainParams, "quake_maintain_report": quake.MaintainReport,
+    }
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "quake.h"', 'int main(void) {']
+    for cname, cls in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, *_ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, what, val = line.split()
+        got[(cname, what)] = int(val)
+    for cname, cls in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for fname, *_ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
