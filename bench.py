@@ -356,6 +356,161 @@ def maintenance_leg(idx, w, X, tau_r, rerank_factor, threads):
             "after": after, "decisions_committed": int(sum(1 for d in dec if d["committed"]))}
 
 
+def min_nprobe_per_query(key, part_of, truth, need):
+    """For each query (row of `key`, its centroid keys, smaller is nearer;
+    ties by partition number), the fewest nearest partitions that together
+    hold `need` of its true neighbours (`truth` rows, `part_of` maps a row to
+    its partition)."""
+    import numpy as np
+    rank = np.empty(key.shape, dtype=np.int64)
+    rank[np.arange(key.shape[0])[:, None], np.argsort(key, axis=1, kind="stable")] = np.arange(key.shape[1])[None, :]
+    nb_rank = np.sort(np.take_along_axis(rank, part_of[truth], axis=1), axis=1)
+    return nb_rank[:, need - 1] + 1
+
+
+def ablation_leg(idx, w, Q, Qd, truth, sample_rows, recall_of, paths, upper):
+    """Estimator and early-termination ablations on synthetic data.
+
+    * Estimators (Sec. 5.1, Table tab:recall_overhead): APS (recompute when
+      rho moved by more than 1%, table), APS-R (recompute after every
+      partition, table) and APS-RP (every partition, incomplete beta on the
+      device) at recall target 0.9 on each path: recall@10, partitions
+      scanned, time per search and the commit kernel's time (where the
+      estimator runs).
+    * Early termination (Sec. 7, Table tab:early_term) at targets 0.8, 0.9
+      and 0.99 on the first path: APS; a fixed nprobe tuned by binary search
+      over the ground-truth sample (the tuning time is reported); and the
+      per-query oracle, the fewest nearest partitions that hold ceil(target k)
+      of the query's true neighbours (a lower bound on partitions; its time
+      groups the sample queries by their nprobe, one search per group).
+    * f_M (Sec. 8, "Setting System Parameters"): 0.01 to 0.1 at target 0.9.
+    """
+    import math
+    import numpy as np
+    import torch
+
+    def sync():
+        torch.cuda.synchronize()
+
+    def timed(Qx, steps=5, **kw):
+        idx.search(Qx, k=w.k, **upper, **kw)
+        sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = idx.search(Qx, k=w.k, **upper, **kw)
+        sync()
+        return out, (time.perf_counter() - t0) * 1e3 / steps
+
+    def commit_ms(**kw):
+        idx.profile(enable=True, reset=True)
+        sync()
+        idx.search(Qd, k=w.k, **upper, **kw)
+        sync()
+        prof = idx.profile(enable=False, reset=True)
+        return prof["commit"][1], sum(v[1] for k, v in prof.items() if k != "scan_sets")
+
+    res = {"estimators": {}, "early_termination": {}, "f_M": {}}
+    for p, pkw in paths.items():
+        rows = []
+        base_ns = None
+        for est in ("aps", "aps-r", "aps-rp"):
+            (ids, _, ns, rec), ms = timed(Qd, recall_target=0.9, f_M=w.f_M, estimator=est, **pkw)
+            cms, kms = commit_ms(recall_target=0.9, f_M=w.f_M, estimator=est, **pkw)
+            nsn = ns.cpu().numpy()
+            base_ns = nsn if base_ns is None else base_ns
+            rows.append({"estimator": est, "recall_at_10": recall_of(ids), "ms_per_search": ms,
+                         "commit_ms_per_search": cms, "kernel_ms_per_search": kms,
+                         "mean_partitions_scanned": float(nsn.mean()),
+                         "mean_recall_estimate": float(rec.double().mean().item()),
+                         "same_stop_as_aps": float((nsn == base_ns).mean())})
+            log(f"ablation {p} {est}: recall {rows[-1]['recall_at_10']:.4f}, {ms:.2f} ms per search, "
+                f"commit {cms:.3f} ms, partitions {rows[-1]['mean_partitions_scanned']:.2f}")
+        res["estimators"][p] = rows
+
+    p0 = next(iter(paths))
+    pkw = paths[p0]
+    Qs = Qd[torch.from_numpy(sample_rows).to(Qd.device)]
+    # the per-query oracle: partition ranks of each query's true neighbours
+    C, eids, epart = idx.export()
+    C = C.cpu().numpy().astype(np.float64)
+    part_of = np.empty(int(eids.max().item()) + 1, dtype=np.int64)
+    part_of[eids.cpu().numpy()] = epart.cpu().numpy()
+    Qh = Q[sample_rows].astype(np.float64)
+    if w.metric == "ip":
+        key = -(Qh @ C.T)
+    else:
+        key = (Qh * Qh).sum(1)[:, None] - 2.0 * Qh @ C.T + (C * C).sum(1)[None, :]
+    nlist = C.shape[0]
+    limit = min(nlist, 4096)
+    for tau in (0.8, 0.9, 0.99):
+        need = int(math.ceil(tau * w.k - 1e-9))
+        row = {}
+        (ids, _, ns, _), ms = timed(Qd, recall_target=tau, f_M=w.f_M, **pkw)
+        (sids, _, sns, _), sms = timed(Qs, recall_target=tau, f_M=w.f_M, **pkw)
+        row["aps"] = {"recall_at_10": recall_of(ids), "ms_per_search": ms,
+                      "mean_partitions_scanned": float(ns.float().mean().item()),
+                      "sample_mean_partitions_scanned": float(sns.float().mean().item()),
+                      "sample_ms_per_search": sms}
+        # fixed nprobe: the smallest whose mean recall over the sample reaches tau
+        t0 = time.perf_counter()
+        lo, hi, probes = 1, limit, 0
+        while lo < hi:
+            mid = (lo + hi) // 2
+            fids, _, _, _ = idx.search(Qs, k=w.k, nprobe=mid, **upper, **pkw)
+            found = fids.cpu().numpy()
+            probes += 1
+            r = float(np.mean([len(set(found[i].tolist()) & set(truth[i].tolist())) for i in range(found.shape[0])]))
+            if r / w.k >= tau:
+                hi = mid
+            else:
+                lo = mid + 1
+        tune_s = time.perf_counter() - t0
+        (fids, _, _, _), fms = timed(Qd, nprobe=lo, **pkw)
+        (_, _, _, _), fsms = timed(Qs, nprobe=lo, **pkw)
+        row["fixed"] = {"nprobe": lo, "tuning_seconds": tune_s, "tuning_searches": probes,
+                        "recall_at_10": recall_of(fids), "ms_per_search": fms, "sample_ms_per_search": fsms}
+        # APS at the smallest target of the ladder whose measured recall reaches tau
+        for t in LADDER:
+            (mids, _, mns, _), mms = timed(Qd, recall_target=t, f_M=w.f_M, **pkw)
+            if recall_of(mids) >= tau or t == LADDER[-1]:
+                break
+        row["aps_matched"] = {"recall_target": t, "recall_at_10": recall_of(mids), "ms_per_search": mms,
+                              "mean_partitions_scanned": float(mns.float().mean().item())}
+        # the per-query oracle
+        onp = min_nprobe_per_query(key, part_of, truth, need)
+        t_or = 0.0
+        found = np.empty((sample_rows.size, w.k), dtype=np.int64)
+        groups = np.unique(onp)
+        for v in groups.tolist():
+            sel = np.nonzero(onp == v)[0]
+            Qg = Qs[torch.from_numpy(sel).to(Qd.device)]
+            idx.search(Qg, k=w.k, nprobe=int(v), **upper, **pkw)
+            sync()
+            t0 = time.perf_counter()
+            gids, _, _, _ = idx.search(Qg, k=w.k, nprobe=int(v), **upper, **pkw)
+            sync()
+            t_or += time.perf_counter() - t0
+            found[sel] = gids.cpu().numpy()
+        orec = float(np.mean([len(set(found[i].tolist()) & set(truth[i].tolist())) for i in range(found.shape[0])]))
+        row["oracle"] = {"mean_partitions_scanned": float(onp.mean()), "recall_at_10": orec / w.k,
+                         "sample_ms_grouped": t_or * 1e3, "groups": int(groups.size)}
+        log(f"ablation {p0} target {tau}: APS recall {row['aps']['recall_at_10']:.4f} over "
+            f"{row['aps']['mean_partitions_scanned']:.1f} partitions; fixed nprobe {lo} ({tune_s:.1f} s tuning) recall "
+            f"{row['fixed']['recall_at_10']:.4f}; oracle {row['oracle']['mean_partitions_scanned']:.1f} partitions")
+        res["early_termination"][str(tau)] = row
+
+    for p, pkw in paths.items():
+        rows = []
+        for f in (0.01, 0.02, 0.05, 0.1):
+            (ids, _, ns, _), ms = timed(Qd, recall_target=0.9, f_M=f, **pkw)
+            rows.append({"f_M": f, "candidates": int(math.ceil(f * nlist - 1e-9)), "recall_at_10": recall_of(ids),
+                         "ms_per_search": ms, "mean_partitions_scanned": float(ns.float().mean().item())})
+            log(f"ablation {p} f_M {f}: recall {rows[-1]['recall_at_10']:.4f}, {ms:.2f} ms, "
+                f"partitions {rows[-1]['mean_partitions_scanned']:.2f}")
+        res["f_M"][p] = rows
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -381,6 +536,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy a BYTES-long device buffer 5 times (calibrates HBM byte counters) and exit")
     ap.add_argument("--serving-requests", type=int, default=0, help="> 0 runs the serving-loop leg")
+    ap.add_argument("--ablation", action="store_true",
+                    help="estimator, early-termination and f_M ablations on the workload (after the timed legs)")
     ap.add_argument("--maintenance", action="store_true",
                     help="run a maintenance pass under skewed queries and time them before and after")
     ap.add_argument("--serving-rates", default="20000,100000,400000")
@@ -591,6 +748,9 @@ def main():
     if not args.no_cpu_baseline and truth is not None:
         cpu = cpu_baseline_leg(X, Q, sample_rows, idx, w, chosen.get(bkey, chosen[next(iter(paths))]),
                                args.cpu_seconds, gt_seconds, threads)
+    ablation = None
+    if args.ablation and truth is not None:
+        ablation = ablation_leg(idx, w, Q, Qd, truth, sample_rows, recall_of, paths, upper)
     maint = None
     if args.maintenance and batched is not None and not two_level:
         maint = maintenance_leg(idx, w, X, batched["recall_target"], args.rerank_factor, threads)
@@ -676,6 +836,7 @@ def main():
         "plain_fp32": plain,
         "serving": serving,
         "maintenance": maint,
+        "ablation": ablation,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -64,6 +64,13 @@ WORKLOADS: Dict[str, Workload] = {
         storage="f16", leaves=LeafSpec(MixtureSpec(key=4, n=50_000_000, d=128, n_components=1000, zipf_s=1.1), 50_000,
                                        leaf_zipf_s=0.3, leaf_std=0.2),
         nlist_top=64, query_noise=0.1),
+    # Estimator and early-termination ablations: 1M x 128 (the size of the
+    # paper's ablation dataset), 1,000 Zipf(1.1) components, 1,000
+    # partitions, L2, 10,000 queries, FP16 copy for the batched path.
+    "ablation-1m-d128-l2": Workload(
+        name="ablation-1m-d128-l2",
+        spec=MixtureSpec(key=6, n=1_000_000, d=128, n_components=1000, zipf_s=1.1),
+        nlist=1000, metric="l2", nq=10_000, k=10, recall_target=0.9, f_M=0.05, storage="f16"),
     # Serving: 10M x 768 BF16 start, skewed drifting queries, 1% updates per step.
     "serving-10m-d768-bf16": Workload(
         name="serving-10m-d768-bf16",
