@@ -44,7 +44,8 @@ enum {
   QUAKE_E_NOTFOUND = -3,  /* a delete batch names an id that is absent; nothing applied */
   QUAKE_E_DUPLICATE = -4, /* an insert batch repeats an id or names a present one; nothing applied */
   QUAKE_E_DEVICE = -5,    /* a HIP call failed */
-  QUAKE_E_STATE = -6      /* the handle is not usable (NULL, freed, wrong level count) */
+  QUAKE_E_STATE = -6,     /* the handle is not usable (NULL, freed, wrong level count) */
+  QUAKE_E_IO = -7         /* a file could not be opened, written or renamed */
 };
 
 enum { QUAKE_L2 = 0, QUAKE_IP = 1 };
@@ -181,10 +182,35 @@ int quake_delete(quake_index* index, const int64_t* ids, int64_t n, void* stream
 /* Host-side counters: live vectors, level-0 partitions, device bytes held. */
 int quake_stats(const quake_index* index, int64_t* n_live, int64_t* n_partitions, size_t* device_bytes);
 
+/* Host-side shape of the index: dimension, metric, 16-bit storage dtype
+ * (QUAKE_F32 = none) and level count.  Any pointer may be NULL. */
+int quake_describe(const quake_index* index, int32_t* d, int32_t* metric, int32_t* storage_dtype, int32_t* n_levels);
+
 /* Export the level-0 partitioning for checking: centroids[nlist][d] (device
  * float32), and for every live vector its id and partition (device int64
  * ids[n_live], int32 part[n_live], in store order).  Any pointer may be NULL. */
 int quake_export(const quake_index* index, float* centroids, int64_t* ids, int32_t* part, void* stream);
+
+/* Save the index to a file: the level-0 centroids, every live vector with
+ * its id and partition (partition by partition, in store order), the
+ * access statistics, the scheduling knobs, and for two levels the level-1
+ * centroids and the top partition of every level-0 centroid, followed by a
+ * 64-bit FNV-1a checksum.  Written to "<path>.tmp", then renamed to path.
+ * No search, update or server may run on the index meanwhile.
+ * Errors: INVALID (empty path, an index with no live vector), IO, NOMEM,
+ * DEVICE, STATE. */
+int quake_save(quake_index* index, const char* path, void* stream);
+
+/* Load a saved index into a new handle: the store is built afresh from the
+ * saved centroids and assignment (each partition keeps its saved row order;
+ * no k-means, no re-placement), so searches see the same partitions,
+ * centroids and rows as on the saved index.  Device memory comes from
+ * `allocator` (NULL: hipMalloc), within hbm_budget_bytes (0: unlimited).
+ * Errors: IO (cannot open), INVALID (not a saved index, another version, a
+ * truncated or corrupt file: checked before anything is built), NOMEM,
+ * DEVICE. */
+int quake_load(const char* path, const quake_allocator* allocator, size_t hbm_budget_bytes, void* stream,
+               quake_index** out);
 
 /* Export the level-1 partitioning of a two-level index: top centroids
  * [nlist_top][d] (device float32) and the top partition of every level-0

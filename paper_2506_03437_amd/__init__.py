@@ -15,13 +15,16 @@ from .quake import (  # noqa: F401
     quake_candidates,
     quake_cap_table,
     quake_delete,
+    quake_describe,
     quake_export,
     quake_export_top,
     quake_free,
     quake_insert,
+    quake_load,
     quake_maintain,
     quake_profile,
     quake_profile_latency,
+    quake_save,
     quake_search,
     quake_search_noalloc,
     quake_server_create,

@@ -22,7 +22,7 @@ LIB = os.path.join(PKG, "libquake_mi355x.so")
 
 HIP_SOURCES = ["k_centroids.hip", "k_scan.hip", "k_store.hip", "k_batched.hip", "k_rerank.hip", "k_update.hip",
                "k_serve.hip", "k_noalloc.hip", "k_maintain.hip"]
-CPP_SOURCES = ["capi.cpp", "cap_table.cpp", "serve.cpp", "maintain.cpp"]
+CPP_SOURCES = ["capi.cpp", "cap_table.cpp", "serve.cpp", "maintain.cpp", "persist.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
 HIP_FLAGS = ["-x", "hip", "--offload-arch=gfx950", "-munsafe-fp-atomics",

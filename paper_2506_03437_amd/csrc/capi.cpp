@@ -1303,11 +1303,11 @@ int quake_cap_table(int32_t d, double* out) {
   API_END
 }
 
-int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const quake_build_params* params,
-                const quake_allocator* allocator, void* stream, quake_index** out) {
-  API_BEGIN
-  QK_CHECK(out, QUAKE_E_INVALID, "out is NULL");
-  *out = nullptr;
+}  // extern "C"
+
+quake_index* qk::build_index(const float* x, const int64_t* ids, int64_t n, int32_t d,
+                             const quake_build_params* params, const float* top_centroids, const int32_t* top_of,
+                             const quake_allocator* allocator, hipStream_t s) {
   QK_CHECK(params, QUAKE_E_INVALID, "params is NULL");
   QK_CHECK(x && n >= 1, QUAKE_E_INVALID, "need x and n >= 1");
   QK_CHECK(d >= 1 && d <= qk::MAX_DIM, QUAKE_E_INVALID, "d must be in [1, 4096]");
@@ -1315,7 +1315,9 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const 
   QK_CHECK(params->storage_dtype >= QUAKE_F32 && params->storage_dtype <= QUAKE_F16, QUAKE_E_INVALID,
            "unknown storage dtype");
   QK_CHECK(params->n_levels == 1 || params->n_levels == 2, QUAKE_E_INVALID, "n_levels must be 1 or 2");
-  QK_CHECK(params->nlist >= 1 && params->nlist <= n, QUAKE_E_INVALID, "nlist must be in [1, n]");
+  // (given centroids and assignment may leave partitions empty, as deletes do)
+  QK_CHECK(params->nlist >= 1 && (params->nlist <= n || (params->centroids && params->assign)), QUAKE_E_INVALID,
+           "nlist must be in [1, n]");
   QK_CHECK(params->nlist <= INT32_MAX, QUAKE_E_INVALID, "nlist too large");
   QK_CHECK(params->kmeans_iters >= 0 && params->capacity_slack >= 0, QUAKE_E_INVALID, "bad k-means settings");
   if (params->n_levels == 2)
@@ -1324,10 +1326,10 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const 
   QK_CHECK(params->drop_f32_tiles == 0 || (params->drop_f32_tiles == 1 && params->storage_dtype != QUAKE_F32),
            QUAKE_E_INVALID, "drop_f32_tiles needs a 16-bit copy (storage_dtype BF16 or F16)");
   const bool f32_tiles = params->drop_f32_tiles == 0;
-  hipStream_t s = as_stream(stream);
   std::unique_ptr<quake_index> idx(new quake_index());
   if (allocator && allocator->alloc) idx->mem.user = *allocator;
   idx->mem.budget = params->hbm_budget_bytes;
+  idx->slack = params->capacity_slack;
   idx->metric = params->metric;
   idx->storage = params->storage_dtype;
   idx->n_levels = params->n_levels;
@@ -1403,10 +1405,20 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const 
     L1.dp = dp;
     L1.nlist = params->nlist_top;
     L1.centroids = idx->mem.alloc<float>((size_t)L1.nlist * dp);
-    kmeans(idx->mem, L0.centroids, L0.nlist, dp, L1.nlist, std::max(params->kmeans_iters, 1),
-           params->seed ^ 0x9e3779b97f4a7c15ull, idx->metric, L1.centroids, s);
     idx->top_of = idx->mem.alloc<int32_t>(L0.nlist);
-    qk::launch_assign(L0.centroids, L0.nlist, dp, L1.centroids, L1.nlist, idx->metric, idx->top_of, s);
+    if (top_centroids && top_of) {
+      // a given level 1 (a saved index): its centroids and the top partition of every level-0 centroid
+      require_finite(idx.get(), top_centroids, L1.nlist * (int64_t)d, "top centroids", s);
+      clear_flag(idx.get(), s);
+      qk::launch_check_range(top_of, L0.nlist, L1.nlist, idx->d_flag, s);
+      QK_CHECK(!flag_set(idx.get(), s), QUAKE_E_INVALID, "top_of holds a partition outside [0, nlist_top)");
+      qk::launch_pad_rows(top_centroids, L1.nlist, d, dp, L1.centroids, nullptr, s);
+      QK_HIP(hipMemcpyAsync(idx->top_of, top_of, L0.nlist * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    } else {
+      kmeans(idx->mem, L0.centroids, L0.nlist, dp, L1.nlist, std::max(params->kmeans_iters, 1),
+             params->seed ^ 0x9e3779b97f4a7c15ull, idx->metric, L1.centroids, s);
+      qk::launch_assign(L0.centroids, L0.nlist, dp, L1.centroids, L1.nlist, idx->metric, idx->top_of, s);
+    }
     build_store(idx.get(), L1, L0.centroids, dp, nullptr, L0.nlist, idx->top_of, 0.0, QUAKE_F32, true, s);
   }
 
@@ -1416,7 +1428,17 @@ int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const 
   QK_HIP(hipMemcpyAsync(idx->cap_table, idx->h_cap_table.data(), qk::CAP_TABLE_SIZE * sizeof(double),
                         hipMemcpyHostToDevice, s));
   QK_HIP(hipStreamSynchronize(s));
-  *out = idx.release();
+  return idx.release();
+}
+
+extern "C" {
+
+int quake_build(const float* x, const int64_t* ids, int64_t n, int32_t d, const quake_build_params* params,
+                const quake_allocator* allocator, void* stream, quake_index** out) {
+  API_BEGIN
+  QK_CHECK(out, QUAKE_E_INVALID, "out is NULL");
+  *out = nullptr;
+  *out = qk::build_index(x, ids, n, d, params, nullptr, nullptr, allocator, as_stream(stream));
   API_END
 }
 
@@ -1668,6 +1690,16 @@ int quake_stats(const quake_index* idx, int64_t* n_live, int64_t* n_partitions, 
   if (n_live) *n_live = idx->L0.live;
   if (n_partitions) *n_partitions = idx->L0.nlist;
   if (device_bytes) *device_bytes = idx->mem.used;
+  API_END
+}
+
+int quake_describe(const quake_index* idx, int32_t* d, int32_t* metric, int32_t* storage_dtype, int32_t* n_levels) {
+  API_BEGIN
+  check_index(idx);
+  if (d) *d = idx->d;
+  if (metric) *metric = idx->metric;
+  if (storage_dtype) *storage_dtype = idx->storage;
+  if (n_levels) *n_levels = idx->n_levels;
   API_END
 }
 

@@ -75,6 +75,12 @@ int store_fixed_point_bits(DeviceMemory& mem, const float* x, int64_t n, int dp,
 void insert_rows(quake_index* idx, Store& st, IdMap& map, const float* x, const int64_t* ids, int64_t n,
                  const std::vector<int32_t>* routed, hipStream_t s);
 void delete_rows(quake_index* idx, Store& st, IdMap& map, const int64_t* ids, int64_t n, hipStream_t s);
+// quake_build's work; with top_centroids (device [nlist_top][d]) and top_of
+// (device [nlist]) a two-level index takes that level 1 instead of k-means.
+// Returns the new index; throws on error.
+quake_index* build_index(const float* x, const int64_t* ids, int64_t n, int32_t d, const quake_build_params* params,
+                         const float* top_centroids, const int32_t* top_of, const quake_allocator* allocator,
+                         hipStream_t s);
 // The maintenance pass behind quake_maintain (maintain.cpp).
 void maintain(quake_index* idx, const quake_maintain_params& p, quake_maintain_report* report, hipStream_t s);
 

@@ -216,6 +216,7 @@ struct quake_index {
   qk::Workspace ws;
   qk::Profiler prof;
   quake_tuning tune{};
+  double slack = 0.0;           // capacity_slack of the build (kept for save / load)
   int cu_count = 0;
   // captured scan rounds, keyed by every argument their kernels take
   struct Graph {

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libquake_mi355x.so")
 
-OK, E_INVALID, E_NOMEM, E_NOTFOUND, E_DUPLICATE, E_DEVICE, E_STATE = 0, -1, -2, -3, -4, -5, -6
+OK, E_INVALID, E_NOMEM, E_NOTFOUND, E_DUPLICATE, E_DEVICE, E_STATE, E_IO = 0, -1, -2, -3, -4, -5, -6, -7
 L2, IP = 0, 1
 F32, BF16, F16 = 0, 1, 2
 SCAN_PLAIN, SCAN_BATCHED = 0, 1
@@ -30,7 +30,8 @@ EXPORTED = ("quake_build", "quake_search", "quake_search_noalloc", "quake_insert
             "quake_export_top", "quake_candidates", "quake_cap_table", "quake_profile", "quake_set_tuning",
             "quake_free", "quake_last_error", "quake_autotune", "quake_server_create", "quake_server_search", "quake_server_insert",
             "quake_server_delete", "quake_server_wait", "quake_server_stats", "quake_server_destroy",
-            "quake_access_stats", "quake_maintain", "quake_profile_latency")
+            "quake_access_stats", "quake_maintain", "quake_profile_latency", "quake_describe", "quake_save",
+            "quake_load")
 PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "scan_sets", "upper")
 
 
@@ -155,6 +156,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.quake_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)]
     lib.quake_export.argtypes = [vp, vp, vp, vp, vp]
     lib.quake_export_top.argtypes = [vp, vp, vp, vp]
+    lib.quake_describe.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32)]
+    lib.quake_save.argtypes = [vp, ctypes.c_char_p, vp]
+    lib.quake_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(Allocator), ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     lib.quake_access_stats.argtypes = [vp, i32, vp, ctypes.POINTER(i64), i32, vp]
     lib.quake_maintain.argtypes = [vp, ctypes.POINTER(MaintainParams), ctypes.POINTER(MaintainReport), vp]
     lib.quake_profile_latency.argtypes = [vp, vp, i32, i32, ctypes.POINTER(SearchParams), i32, vp, vp]
@@ -322,6 +327,29 @@ def quake_export_top(handle: int, d: int, nlist_top: int):
     top_of = torch.empty((nlist,), dtype=torch.int32, device=dev)
     _check(load_library().quake_export_top(handle, _ptr(C1), _ptr(top_of), _stream()))
     return C1, top_of
+
+
+def quake_describe(handle: int) -> dict:
+    d, metric, storage, levels = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().quake_describe(handle, ctypes.byref(d), ctypes.byref(metric), ctypes.byref(storage),
+                                         ctypes.byref(levels)))
+    inv_m = {v: k for k, v in _METRIC.items()}
+    inv_d = {v: k for k, v in _DTYPE.items()}
+    return {"d": d.value, "metric": inv_m[metric.value], "storage": inv_d[storage.value], "n_levels": levels.value}
+
+
+def quake_save(handle: int, path: str):
+    _check(load_library().quake_save(handle, os.fsencode(path), _stream()))
+
+
+def quake_load(path: str, *, device: int = 0, hbm_budget_bytes: int = 0, allocator="torch") -> int:
+    """A saved index in a new handle on `device` (allocator as quake_build)."""
+    if allocator not in ("torch", "hip"):
+        raise ValueError(f"allocator must be 'torch' or 'hip', not {allocator!r}")
+    alloc = ctypes.byref(torch_allocator(device)) if allocator == "torch" else None
+    h = ctypes.c_void_p()
+    _check(load_library().quake_load(os.fsencode(path), alloc, hbm_budget_bytes, _stream(), ctypes.byref(h)))
+    return h.value
 
 
 def quake_access_stats(handle: int, level: int = 0, reset: bool = False):
@@ -524,6 +552,21 @@ class Index:
         self.d = x.shape[1]
         self.metric = build_kw.get("metric", "l2")
         self.handle = quake_build(x, ids, **build_kw)
+
+    @classmethod
+    def load(cls, path, **load_kw) -> "Index":
+        """The index saved at `path` (quake_load)."""
+        self = cls.__new__(cls)
+        self.handle = quake_load(path, **load_kw)
+        info = quake_describe(self.handle)
+        self.d, self.metric = info["d"], info["metric"]
+        return self
+
+    def save(self, path):
+        quake_save(self.handle, path)
+
+    def describe(self):
+        return quake_describe(self.handle)
 
     def search(self, q, **kw):
         return quake_search(self.handle, q, **kw)

@@ -124,3 +124,21 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for fname, *_ in cls._fields_:
             assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_save_and_load_argument_errors(tmp_path):
+    """Errors found before any device work: a missing file, a file that is
+    not a saved index or is cut short inside the header, a NULL handle."""
+    from paper_2506_03437_amd import quake
+    lib = quake.load_library()
+    h = ctypes.c_void_p()
+    assert lib.quake_load(str(tmp_path / "absent.qk").encode(), None, 0, None, ctypes.byref(h)) == quake.E_IO
+    assert h.value is None
+    (tmp_path / "junk.qk").write_bytes(b"not an index" * 20)
+    assert lib.quake_load(str(tmp_path / "junk.qk").encode(), None, 0, None, ctypes.byref(h)) == quake.E_INVALID
+    assert b"magic" in lib.quake_last_error()
+    (tmp_path / "short.qk").write_bytes(b"QUAKEIX1" + b"\0" * 20)
+    assert lib.quake_load(str(tmp_path / "short.qk").encode(), None, 0, None, ctypes.byref(h)) == quake.E_INVALID
+    assert lib.quake_load(None, None, 0, None, ctypes.byref(h)) == quake.E_INVALID
+    assert lib.quake_save(None, str(tmp_path / "x.qk").encode(), None) == quake.E_STATE
+    assert lib.quake_describe(None, None, None, None, None) == quake.E_STATE
