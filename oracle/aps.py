@@ -40,6 +40,15 @@ reason in the design notes):
 * Candidate order: "largest p_i first" equals ascending h (all caps share
   one rho and v is decreasing in t); ties by centroid value, then id.
 
+Filters (Sec. 8, "Filters": the paper names the idea only):
+* F1  a candidate's cap share v_i becomes the share of passing rows beyond
+      its bisector, u_i = v_i f_i / (v_i f_i + (1 - v_i) f_0), with f_i the
+      estimated pass fraction of P_i and f_0 that of P_0; p_0 and p_i then
+      follow Eqs. aps-p0 and aps-pi-final with u in place of v.
+* F2  a row passes when its 32 label bits share a bit with the query's
+      mask; f_i sums the per-bit counts of the mask's bits (exact for one
+      label per row), capped at the partition's live rows.
+
 Estimator variants (Sec. 5.1, Table tab:recall_overhead): APS recomputes
 p_0 and p_i only when rho moved by more than tau_rho and reads the cap
 share from the table; APS-R recomputes after every partition, still from
@@ -197,18 +206,53 @@ def aps_order(q: np.ndarray, C: np.ndarray, f_M: float, metric: str, cands: Opti
     return np.concatenate([[c0], others[o]]).astype(np.int64), h[o]
 
 
-class _Estimator:
-    """p_0 and p_i for the current rho (Eqs. aps-p0 and aps-pi-final, reading R1)."""
+def pass_fractions(ps: PartitionedSet, attr: np.ndarray, mask: int) -> np.ndarray:
+    """Estimated share of each partition's rows that pass a filter (Sec. 8,
+    "Filters"): a row passes when its label bits share a bit with `mask`; the
+    estimate counts the rows carrying each bit of the mask and sums the
+    counts (exact when every row carries one bit, an upper bound otherwise),
+    capped at the partition's size.  Empty partitions get 0."""
+    attr = np.asarray(attr, dtype=np.uint64)
+    bits = [b for b in range(32) if (int(mask) >> b) & 1]
+    f = np.zeros(ps.nlist)
+    for p in range(ps.nlist):
+        rows = ps.members[p]
+        if rows.shape[0] == 0:
+            continue
+        a = attr[rows]
+        est = sum(int(((a >> np.uint64(b)) & np.uint64(1)).sum()) for b in bits)
+        f[p] = min(rows.shape[0], est) / rows.shape[0]
+    return f
 
-    def __init__(self, h: np.ndarray, table: CapTable):
+
+def filtered_share(v: np.ndarray, f: np.ndarray, f0: float) -> np.ndarray:
+    """Cap shares scaled for a filter (reading F1): of the passing rows in the
+    ball, the share beyond the bisector of c_0 and c_i when the rows beyond it
+    pass with fraction f_i and those on c_0's side with f_0,
+        u_i = v_i f_i / (v_i f_i + (1 - v_i) f_0),
+    and 0 where v_i f_i = 0.  With equal fractions u_i = v_i."""
+    num = v * f
+    den = num + (1.0 - v) * f0
+    return np.where(num > 0.0, num / np.where(den > 0.0, den, 1.0), 0.0)
+
+
+class _Estimator:
+    """p_0 and p_i for the current rho (Eqs. aps-p0 and aps-pi-final, reading R1),
+    with the cap shares scaled by pass fractions under a filter (reading F1)."""
+
+    def __init__(self, h: np.ndarray, table: CapTable, f: Optional[np.ndarray] = None, f0: float = 1.0):
         self.h = h
         self.table = table
+        self.f = f
+        self.f0 = f0
         self.p0 = 1.0
         self.p = np.zeros(h.shape[0])
 
     def recompute(self, rho: float):
         t = np.zeros_like(self.h) if math.isinf(rho) else self.h / rho
         v = self.table(t)
+        if self.f is not None:
+            v = filtered_share(v, self.f, self.f0)
         V = float(v.sum())
         self.p0 = float(np.prod(1.0 - v))
         if V > 0.0:
@@ -222,11 +266,15 @@ class _Estimator:
 
 
 def aps_search_one(ps: PartitionedSet, q: np.ndarray, params: APSParams, table: CapTable,
-                   order: Optional[np.ndarray] = None, h: Optional[np.ndarray] = None) -> APSResult:
+                   order: Optional[np.ndarray] = None, h: Optional[np.ndarray] = None,
+                   attr: Optional[np.ndarray] = None, mask: Optional[int] = None) -> APSResult:
     """Algorithm "Adaptive Partition Scanning" for one query.
 
     ``order``/``h`` may be given to replay a specific candidate order; by
-    default they come from :func:`aps_order`.
+    default they come from :func:`aps_order`.  With ``attr`` (label bits of
+    every row) and ``mask``, only rows sharing a bit with the mask are
+    results, and the recall model scales its cap shares by each candidate's
+    pass fraction (Sec. 8, "Filters"; readings F1, F2).
     """
     metric = params.metric
     k = params.k
@@ -235,8 +283,14 @@ def aps_search_one(ps: PartitionedSet, q: np.ndarray, params: APSParams, table: 
     q64 = np.asarray(q, dtype=np.float64)
     qn2 = float(q64 @ q64)
 
+    filt = attr is not None and mask is not None
+    if filt:
+        attr64 = np.asarray(attr, dtype=np.uint64)
+
     def scan(p):
         rows = ps.members[int(p)]
+        if filt:
+            rows = rows[(attr64[rows] & np.uint64(int(mask))) != 0]
         if rows.shape[0] == 0:
             return select_topk(np.zeros(0), np.zeros(0, dtype=np.int64), k, metric)
         vals = distances(q[None, :], ps.X[rows], metric)[0]
@@ -251,7 +305,12 @@ def aps_search_one(ps: PartitionedSet, q: np.ndarray, params: APSParams, table: 
     res_i, res_v = scan(order[0])
     m = 1
     rho = kth_radius(res_i, res_v)
-    est = _Estimator(np.asarray(h, dtype=np.float64), table)
+    if filt:
+        frac = pass_fractions(ps, attr, mask)
+        est = _Estimator(np.asarray(h, dtype=np.float64), table, frac[np.asarray(order[1:], dtype=np.int64)],
+                         float(frac[int(order[0])]))
+    else:
+        est = _Estimator(np.asarray(h, dtype=np.float64), table)
     est.recompute(rho)
     full = res_i[k - 1] >= 0
     r = est.recall(0) if full else 0.0
@@ -281,8 +340,9 @@ def aps_search_one(ps: PartitionedSet, q: np.ndarray, params: APSParams, table: 
 
 
 def aps_search(ps: PartitionedSet, Q: np.ndarray, params: APSParams, table: Optional[CapTable] = None,
-               orders=None):
-    """APS for every query: (ids [nq,k], values [nq,k], m [nq], per-query results)."""
+               orders=None, attr: Optional[np.ndarray] = None, masks: Optional[np.ndarray] = None):
+    """APS for every query: (ids [nq,k], values [nq,k], m [nq], per-query results).
+    With ``attr`` and ``masks`` (one per query) the searches are filtered."""
     table = table or CapTable(ps.X.shape[1])
     nq = Q.shape[0]
     out_i = np.empty((nq, params.k), dtype=np.int64)
@@ -291,7 +351,7 @@ def aps_search(ps: PartitionedSet, Q: np.ndarray, params: APSParams, table: Opti
     results = []
     for i in range(nq):
         o, h = (None, None) if orders is None else orders[i]
-        res = aps_search_one(ps, Q[i], params, table, o, h)
+        res = aps_search_one(ps, Q[i], params, table, o, h, attr, None if masks is None else int(masks[i]))
         out_i[i], out_v[i], ms[i] = res.ids, res.vals, res.m
         results.append(res)
     return out_i, out_v, ms, results
