@@ -99,6 +99,9 @@ typedef struct {
   int32_t drop_f32_tiles;  /* 1 (with a 16-bit copy): keep no FP32 tile copy of level 0 - only the
                               16-bit tiles the batched scan reads and the row-major FP32 copy the
                               rerank reads (a third less memory); plain FP32 searches are then INVALID */
+  const uint32_t* attrs;   /* optional device [n]: 32 label bits of every row, for filtered searches
+                              (Sec. 8, "Filters"); a labelled index takes its inserts through
+                              quake_insert_attrs */
 } quake_build_params;
 
 /* Search parameters.  Exactly one of nprobe > 0 (fixed number of partitions)
@@ -120,6 +123,11 @@ typedef struct {
                               L2: |q|^2 + |x~|^2 - 2 q~.x~ with x~, q~ the rounded vectors) */
   int32_t window;          /* first-round speculation window (partitions per query); 0 -> auto */
   int32_t estimator;       /* QUAKE_EST_APS (default), QUAKE_EST_APS_R or QUAKE_EST_APS_RP; every level */
+  const uint32_t* filter;  /* optional device [nq]: label mask of every query (Sec. 8, "Filters"): only
+                              rows whose label bits share a bit with it are results, and the recall
+                              model scales each candidate's cap share by the partition's estimated
+                              pass fraction (per-bit counts of the mask's bits, capped at its live
+                              rows).  Needs a labelled one-level index and the plain FP32 scan. */
 } quake_search_params;
 
 /* Build an index over x[n][d] (device, float32) with ids[n] (device int64,
@@ -173,6 +181,12 @@ int quake_search_noalloc(quake_index* index, const float* q, int64_t nq, const q
  * INVALID (negative id, a non-finite value in x; nothing applied), NOMEM,
  * DEVICE. */
 int quake_insert(quake_index* index, const float* x, const int64_t* ids, int64_t n, void* stream);
+
+/* quake_insert for a labelled index: attrs[n] (device uint32) are the rows'
+ * label bits.  Errors as quake_insert; INVALID when the index is not
+ * labelled (and quake_insert is INVALID on a labelled one). */
+int quake_insert_attrs(quake_index* index, const float* x, const int64_t* ids, const uint32_t* attrs, int64_t n,
+                       void* stream);
 
 /* Delete the vectors with ids[n] (device int64) as one batch (Sec. 3: found
  * through the id map and removed).  Errors: NOTFOUND (an id is absent or

@@ -20,6 +20,7 @@ from .quake import (  # noqa: F401
     quake_export_top,
     quake_free,
     quake_insert,
+    quake_insert_attrs,
     quake_load,
     quake_maintain,
     quake_profile,

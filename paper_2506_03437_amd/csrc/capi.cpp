@@ -288,6 +288,10 @@ void alloc_store_arrays(quake_index* idx, Store& st, int64_t tiles, int dtype16,
   }
   st.ids = mem.alloc<int64_t>(slots);
   QK_HIP(hipMemsetAsync(st.ids, 0xff, slots * sizeof(int64_t), s));
+  if (idx->labelled && &st != &idx->L1) {
+    st.attr = mem.alloc<uint32_t>(slots);
+    QK_HIP(hipMemsetAsync(st.attr, 0, slots * sizeof(uint32_t), s));
+  }
   st.tiles = tiles;
 }
 
@@ -308,7 +312,8 @@ void upload_table(Store& st, hipStream_t s) {
 // slack, rounded up to whole tiles; rows keep their input order within a
 // partition.
 void build_store(quake_index* idx, Store& st, const float* xin, int d, const int64_t* ids, int64_t n,
-                 const int32_t* d_assign, double slack, int dtype16, bool f32_tiles, hipStream_t s) {
+                 const int32_t* d_assign, double slack, int dtype16, bool f32_tiles, hipStream_t s,
+                 const uint32_t* attrs = nullptr) {
   std::vector<int32_t> a(n);
   QK_HIP(hipMemcpyAsync(a.data(), d_assign, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   QK_HIP(hipStreamSynchronize(s));
@@ -350,11 +355,16 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
   QK_HIP(hipMemsetAsync(st.d_hits, 0, std::max<int64_t>(N, 1) * sizeof(uint32_t), s));
   st.window = 0;
   upload_table(st, s);
+  if (st.attr) {
+    st.d_attr_cnt = idx->mem.alloc<uint32_t>((size_t)std::max<int64_t>(N, 1) * 33);
+    st.attr_dirty = true;
+  }
   {
     Tmp<int64_t> d_slot(idx->mem, n);
     QK_HIP(hipMemcpyAsync(d_slot.p, slot.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s));
     qk::launch_scatter(xin, n, d, st.dp, st.dp16, ids, d_slot.p, st.v32, st.v16, dtype16, st.rows32, st.ids, s);
     qk::launch_norm16(st, dtype16, s);
+    if (st.attr && attrs) qk::launch_put_u32(attrs, d_slot.p, n, st.attr, s);
     QK_HIP(hipStreamSynchronize(s));
   }
   st.live = n;
@@ -389,16 +399,19 @@ void repack_arena(quake_index* idx, Store& st, int64_t tiles, hipStream_t s) {
         QK_HIP(hipMemcpyAsync(fresh.rows32 + b * st.dp, st.rows32 + a * st.dp, n * st.dp * sizeof(float),
                               hipMemcpyDeviceToDevice, s));
       QK_HIP(hipMemcpyAsync(fresh.ids + b, st.ids + a, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+      if (st.attr) QK_HIP(hipMemcpyAsync(fresh.attr + b, st.attr + a, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     }
     next += st.cap[p] / qk::TILE;
   }
   QK_HIP(hipStreamSynchronize(s));
-  for (void* p : {(void*)st.v32, (void*)st.v16, (void*)st.v16n, (void*)st.rows32, (void*)st.ids}) idx->mem.release(p);
+  for (void* p : {(void*)st.v32, (void*)st.v16, (void*)st.v16n, (void*)st.rows32, (void*)st.ids, (void*)st.attr})
+    idx->mem.release(p);
   st.v32 = fresh.v32;
   st.v16 = fresh.v16;
   st.v16n = fresh.v16n;
   st.rows32 = fresh.rows32;
   st.ids = fresh.ids;
+  st.attr = fresh.attr;
   st.tiles = tiles;
   st.used_tiles = next;
   st.off.swap(off);
@@ -435,13 +448,16 @@ bool grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s, bool r
   if (st.v16n) QK_HIP(hipMemcpyAsync(fresh.v16n, st.v16n, used * sizeof(float), hipMemcpyDeviceToDevice, s));
   if (st.rows32) QK_HIP(hipMemcpyAsync(fresh.rows32, st.rows32, used * st.dp * sizeof(float), hipMemcpyDeviceToDevice, s));
   QK_HIP(hipMemcpyAsync(fresh.ids, st.ids, used * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  if (st.attr) QK_HIP(hipMemcpyAsync(fresh.attr, st.attr, used * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   QK_HIP(hipStreamSynchronize(s));
-  for (void* p : {(void*)st.v32, (void*)st.v16, (void*)st.v16n, (void*)st.rows32, (void*)st.ids}) idx->mem.release(p);
+  for (void* p : {(void*)st.v32, (void*)st.v16, (void*)st.v16n, (void*)st.rows32, (void*)st.ids, (void*)st.attr})
+    idx->mem.release(p);
   st.v32 = fresh.v32;
   st.v16 = fresh.v16;
   st.v16n = fresh.v16n;
   st.rows32 = fresh.rows32;
   st.ids = fresh.ids;
+  st.attr = fresh.attr;
   st.tiles = tiles;
   st.tile_part.resize(tiles, -1);
   return false;
@@ -466,6 +482,7 @@ void relocate(Store& st, int64_t p, int32_t cap, hipStream_t s) {
       QK_HIP(hipMemcpyAsync(st.rows32 + b * st.dp, st.rows32 + a * st.dp, n * st.dp * sizeof(float),
                             hipMemcpyDeviceToDevice, s));
     QK_HIP(hipMemcpyAsync(st.ids + b, st.ids + a, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    if (st.attr) QK_HIP(hipMemcpyAsync(st.attr + b, st.attr + a, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     // the old slots no longer hold the partition's vectors
     QK_HIP(hipMemsetAsync(st.ids + a, 0xff, (size_t)st.cap[p] * sizeof(int64_t), s));
   }
@@ -591,7 +608,9 @@ int store_fixed_point_bits(DeviceMemory& mem, const float* x, int64_t n, int dp,
 // no id twice, none already present.  Partitions that overflow move to fresh
 // tiles with 1.5x their need.
 void insert_rows(quake_index* idx, Store& st, IdMap& map, const float* x, const int64_t* ids, int64_t n,
-                 const std::vector<int32_t>* routed, hipStream_t s) {
+                 const std::vector<int32_t>* routed, hipStream_t s, const uint32_t* attrs) {
+  QK_CHECK(!st.attr || attrs, QUAKE_E_INVALID, "the index labels its rows: insert them with their label bits");
+  QK_CHECK(st.attr || !attrs, QUAKE_E_INVALID, "the index was built without row labels");
   std::vector<int64_t> h_ids(n);
   QK_HIP(hipMemcpyAsync(h_ids.data(), ids, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   QK_HIP(hipStreamSynchronize(s));
@@ -646,6 +665,10 @@ void insert_rows(quake_index* idx, Store& st, IdMap& map, const float* x, const 
   launch_scatter(x, n, idx->d, dp, st.dp16, ids, d_slot.p, st.v32, st.v16, st.v16 ? idx->storage : QUAKE_F32,
                  st.rows32, st.ids, s);
   launch_norm16_slots(st, d_slot.p, n, idx->storage, s);
+  if (st.attr) {
+    launch_put_u32(attrs, d_slot.p, n, st.attr, s);
+    st.attr_dirty = true;
+  }
   for (int64_t p = 0; p < st.nlist; ++p) st.size[p] += (int32_t)cnt[p];
   upload_table(st, s);
   st.live += n;
@@ -676,6 +699,7 @@ void delete_rows(quake_index* idx, Store& st, IdMap& map, const int64_t* ids, in
            "the batch names an id that is absent");
   launch_mark_deleted(st, slots.p, n, s);
   launch_map_erase(map, ids, n, s);
+  st.attr_dirty = true;
   std::vector<int64_t> h_slots(n);
   QK_HIP(hipMemcpyAsync(h_slots.data(), slots.p, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   QK_HIP(hipStreamSynchronize(s));
@@ -736,6 +760,9 @@ Job resolve(const quake_index* idx, const Store& st, const quake_search_params* 
   r.f_M = p->f_M > 0 ? p->f_M : 0.05;
   r.tau_rho = p->tau_rho > 0 ? p->tau_rho : 0.01;
   r.est = p->estimator;
+  QK_CHECK(!p->filter || (st.attr && idx->n_levels == 1 && !r.batched && r.kk <= qk::KMAX), QUAKE_E_INVALID,
+           "a filtered search needs a labelled one-level index and the plain FP32 scan");
+  r.filter = p->filter;
   const int64_t N = st.nlist;
   const int64_t cap_m = N > 4096 ? 2048 : qk::MAX_CANDIDATES;
   const quake_tuning& tu = idx->tune;
@@ -922,6 +949,9 @@ std::vector<uint64_t> graph_key(const quake_index* idx, const Store& st, const J
   k.push_back(tr);
   k.push_back(tro);
   k.push_back((uint64_t)a.est);
+  k.push_back(u(a.qmask));
+  k.push_back(u(a.attr));
+  k.push_back(u(a.attr_cnt));
   return k;
 }
 
@@ -1132,6 +1162,16 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
   a.tau_r = job.tau_r;
   a.tau_rho = job.tau_rho;
   a.est = job.est;
+  if (job.filter) {
+    // per-partition label counts, recounted after any change to the rows
+    if (st.attr_dirty) {
+      qk::launch_attr_counts(st, s);
+      st.attr_dirty = false;
+    }
+    a.qmask = job.filter;
+    a.attr = st.attr;
+    a.attr_cnt = st.d_attr_cnt;
+  }
   const bool count = job.count && idx->count_access;
   a.hits = count ? st.d_hits : nullptr;
   if (count) st.window += nq;
@@ -1330,6 +1370,7 @@ quake_index* qk::build_index(const float* x, const int64_t* ids, int64_t n, int3
   if (allocator && allocator->alloc) idx->mem.user = *allocator;
   idx->mem.budget = params->hbm_budget_bytes;
   idx->slack = params->capacity_slack;
+  idx->labelled = params->attrs != nullptr;
   idx->metric = params->metric;
   idx->storage = params->storage_dtype;
   idx->n_levels = params->n_levels;
@@ -1390,12 +1431,12 @@ quake_index* qk::build_index(const float* x, const int64_t* ids, int64_t n, int3
   }
   if (params->assign) {
     build_store(idx.get(), L0, x, d, ids, n, params->assign, params->capacity_slack, params->storage_dtype,
-                f32_tiles, s);
+                f32_tiles, s, params->attrs);
   } else {
     Tmp<int32_t> assign(idx->mem, n);
     qk::launch_assign(xpad, n, dp, L0.centroids, L0.nlist, idx->metric, assign.p, s);
     build_store(idx.get(), L0, x, d, ids, n, assign.p, params->capacity_slack, params->storage_dtype, f32_tiles,
-                s);
+                s, params->attrs);
   }
   map_rebuild(idx.get(), idx->idmap, idx->L0, n, s);
 
@@ -1635,11 +1676,11 @@ int quake_candidates(quake_index* idx, const float* q, int64_t nq, const quake_s
   API_END
 }
 
-int quake_insert(quake_index* idx, const float* x, const int64_t* ids, int64_t n, void* stream) {
-  API_BEGIN
+static void insert_api(quake_index* idx, const float* x, const int64_t* ids, const uint32_t* attrs, int64_t n,
+                       void* stream) {
   check_index(idx);
   QK_CHECK(n >= 0, QUAKE_E_INVALID, "n must be >= 0");
-  if (n == 0) return QUAKE_OK;
+  if (n == 0) return;
   QK_CHECK(x && ids, QUAKE_E_INVALID, "x and ids are required");
   hipStream_t s = as_stream(stream);
   require_finite(idx, x, n * (int64_t)idx->d, "x", s);
@@ -1670,7 +1711,20 @@ int quake_insert(quake_index* idx, const float* x, const int64_t* ids, int64_t n
       routed[i] = (int32_t)leaf[i];
     }
   }
-  qk::insert_rows(idx, idx->L0, idx->idmap, x, ids, n, routed.empty() ? nullptr : &routed, s);
+  qk::insert_rows(idx, idx->L0, idx->idmap, x, ids, n, routed.empty() ? nullptr : &routed, s, attrs);
+}
+
+int quake_insert(quake_index* idx, const float* x, const int64_t* ids, int64_t n, void* stream) {
+  API_BEGIN
+  insert_api(idx, x, ids, nullptr, n, stream);
+  API_END
+}
+
+int quake_insert_attrs(quake_index* idx, const float* x, const int64_t* ids, const uint32_t* attrs, int64_t n,
+                       void* stream) {
+  API_BEGIN
+  QK_CHECK(n <= 0 || attrs, QUAKE_E_INVALID, "attrs are required");
+  insert_api(idx, x, ids, attrs, n, stream);
   API_END
 }
 

@@ -22,6 +22,7 @@ struct Job {
   int rerank = 1;      // batched path: re-score the kk candidates in FP32 (0: keep the 16-bit values)
   double tau_r = 0, f_M = 0, tau_rho = 0.01;
   int est = QUAKE_EST_APS;  // recall estimator variant
+  const uint32_t* filter = nullptr;  // label mask of every query (device [nq]), or null
   bool given = false;  // candidate rows already in ws.cand0 / ws.mq0 (level 0 of two levels)
   bool count = true;   // add the queries to the store's access statistics (not for insert routing)
 };
@@ -73,7 +74,7 @@ int store_fixed_point_bits(DeviceMemory& mem, const float* x, int64_t n, int dp,
 // second copy, from its update thread).  routed: partition of every row,
 // else the nearest centroid's.  Errors as quake_insert / quake_delete.
 void insert_rows(quake_index* idx, Store& st, IdMap& map, const float* x, const int64_t* ids, int64_t n,
-                 const std::vector<int32_t>* routed, hipStream_t s);
+                 const std::vector<int32_t>* routed, hipStream_t s, const uint32_t* attrs = nullptr);
 void delete_rows(quake_index* idx, Store& st, IdMap& map, const int64_t* ids, int64_t n, hipStream_t s);
 // quake_build's work; with top_centroids (device [nlist_top][d]) and top_of
 // (device [nlist]) a two-level index takes that level 1 instead of k-means.

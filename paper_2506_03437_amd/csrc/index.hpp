@@ -101,6 +101,9 @@ struct Store {
   float* v16n = nullptr;        // [tiles * 64] |x|^2 of the 16-bit copy (L2 only)
   float* rows32 = nullptr;      // [tiles * 64][dp] row-major FP32 rows by slot (with a 16-bit copy: rerank)
   int64_t* ids = nullptr;       // [tiles * 64], -1 = empty or deleted
+  uint32_t* attr = nullptr;     // [tiles * 64] label bits of every slot (level 0 of a labelled index), or null
+  uint32_t* d_attr_cnt = nullptr;  // [nlist][33]: live rows carrying each label bit, then live rows
+  mutable bool attr_dirty = true;  // d_attr_cnt must be recounted before the next filtered search
   int64_t live = 0;
   std::vector<int32_t> tomb;     // deleted slots still inside size[p]
   std::vector<int32_t> tile_part;  // partition owning each arena tile (-1 = unused)
@@ -217,6 +220,7 @@ struct quake_index {
   qk::Profiler prof;
   quake_tuning tune{};
   double slack = 0.0;           // capacity_slack of the build (kept for save / load)
+  bool labelled = false;        // level-0 rows carry label bits (filtered searches)
   int cu_count = 0;
   // captured scan rounds, keyed by every argument their kernels take
   struct Graph {
@@ -290,6 +294,9 @@ struct RoundArgs {
   int dim;           // d, for nothing but documentation of the table
   double tau_r, tau_rho;
   int est;           // recall estimator variant (QUAKE_EST_*)
+  const uint32_t* qmask;     // filtered search: label mask of every query (device [nq]), or null
+  const uint32_t* attr;      // with qmask: label bits of every slot
+  const uint32_t* attr_cnt;  // with qmask: [nlist][33] per-bit and live counts
   int64_t items_cap;
   int blocks;        // grid of the persistent scan kernels (they read their item counts on the device)
   int slot_ids;      // 1: the lists carry store slots below 2^31 (batched path), not ids
@@ -324,6 +331,10 @@ void launch_map_erase(IdMap& m, const int64_t* ids, int64_t n, hipStream_t s);
 void launch_map_update(IdMap& m, const int64_t* ids, const int64_t* slots, int64_t n, hipStream_t s);
 void launch_mark_deleted(Store& st, const int64_t* slots, int64_t n, hipStream_t s);
 void launch_move_slots(Store& st, const int64_t* src, const int64_t* dst, int64_t n, hipStream_t s);
+// dst[slot[i]] = src[i] for i < n (label bits of placed rows)
+void launch_put_u32(const uint32_t* src, const int64_t* slot, int64_t n, uint32_t* dst, hipStream_t s);
+// d_attr_cnt from the label bits of every live slot
+void launch_attr_counts(const Store& st, hipStream_t s);
 void launch_norm16_slots(Store& st, const int64_t* slots, int64_t n, int dtype16, hipStream_t s);
 void launch_level1_to_candidates(int64_t nq, int M0, int kk, const int64_t* ri, int32_t* cand0, int32_t* mq,
                                  hipStream_t s);

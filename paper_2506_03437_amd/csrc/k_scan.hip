@@ -277,19 +277,23 @@ void launch_emit(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t
 // ---------------------------------------------------------------- FP32 scan
 
 // One work item (query, partition, tiles [t0, t1)) of the plain scan: the
-// item's partial list, seeded with the query's committed k-th result.
+// item's partial list, seeded with the query's committed k-th result.  With
+// qmask (a filtered search) a row is a result only when its label bits share
+// a bit with the query's mask.
 template <int METRIC, int KPL>
 __device__ __forceinline__ void scan_item(const int4 item, int64_t it, int lane, const float* __restrict__ qpad,
                                           int dp, const float* __restrict__ v32, const int64_t* __restrict__ sid,
                                           const int64_t* __restrict__ poff, const int32_t* __restrict__ psize,
                                           const float* __restrict__ rk, const int64_t* __restrict__ ri, int kk,
-                                          float* __restrict__ pk, int64_t* __restrict__ pi) {
+                                          float* __restrict__ pk, int64_t* __restrict__ pi,
+                                          const uint32_t* __restrict__ attr, const uint32_t* __restrict__ qmask) {
   const int q = __builtin_amdgcn_readfirstlane(item.x);
   const int p = __builtin_amdgcn_readfirstlane(item.y);
   const int t0 = __builtin_amdgcn_readfirstlane(item.z);
   const int t1 = __builtin_amdgcn_readfirstlane(item.w);
   const float seed_k = rk[(int64_t)q * kk + kk - 1];
   const int64_t seed_i = ri[(int64_t)q * kk + kk - 1];
+  const uint32_t qm = qmask ? qmask[q] : 0u;
   WaveTopK<KPL> top;
   top.init(kk, seed_k, seed_i);
   const int64_t tile0 = poff[p];
@@ -305,7 +309,7 @@ __device__ __forceinline__ void scan_item(const int4 item, int64_t it, int lane,
     int64_t myid = -1;
     if (valid && !(key > top.tk)) {
       myid = sid[slot];
-      pass = myid >= 0 && kv_less(key, myid, top.tk, top.ti);
+      pass = myid >= 0 && (!qmask || (attr[slot] & qm) != 0u) && kv_less(key, myid, top.tk, top.ti);
     }
     uint64_t mask = __ballot(pass);
     while (mask) {
@@ -326,7 +330,9 @@ __global__ __launch_bounds__(256) void k_scan_f32(const int4* __restrict__ items
                                                    const int64_t* __restrict__ poff,
                                                    const int32_t* __restrict__ psize,
                                                    const float* __restrict__ rk, const int64_t* __restrict__ ri,
-                                                   int kk, float* __restrict__ pk, int64_t* __restrict__ pi) {
+                                                   int kk, float* __restrict__ pk, int64_t* __restrict__ pi,
+                                                   const uint32_t* __restrict__ attr,
+                                                   const uint32_t* __restrict__ qmask) {
   // Waves take items from the round's queue (head counters[7], reset by
   // k_prefix) until it is empty: items differ in size, so the grid balances
   // itself.
@@ -337,7 +343,7 @@ __global__ __launch_bounds__(256) void k_scan_f32(const int4* __restrict__ items
     if (lane == 0) it = (int64_t)atomicAdd((unsigned long long*)(counters + 7), 1ull);
     it = readlane_i64(it, 0);
     if (it >= nitems) break;
-    scan_item<METRIC, KPL>(items[it], it, lane, qpad, dp, v32, sid, poff, psize, rk, ri, kk, pk, pi);
+    scan_item<METRIC, KPL>(items[it], it, lane, qpad, dp, v32, sid, poff, psize, rk, ri, kk, pk, pi, attr, qmask);
   }
 }
 
@@ -347,13 +353,13 @@ static void scan_f32_k(Workspace& ws, const Store& st, const RoundArgs& a, hipSt
   const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>(need, a.blocks)));
   if (a.kk <= 64)
     hipLaunchKernelGGL((k_scan_f32<METRIC, 1>), grid, dim3(256), 0, s, ws.items, ws.total, ws.q, st.dp, st.v32,
-                       st.ids, st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi);
+                       st.ids, st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi, a.attr, a.qmask);
   else if (a.kk <= 128)
     hipLaunchKernelGGL((k_scan_f32<METRIC, 2>), grid, dim3(256), 0, s, ws.items, ws.total, ws.q, st.dp, st.v32,
-                       st.ids, st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi);
+                       st.ids, st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi, a.attr, a.qmask);
   else
     hipLaunchKernelGGL((k_scan_f32<METRIC, 4>), grid, dim3(256), 0, s, ws.items, ws.total, ws.q, st.dp, st.v32,
-                       st.ids, st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi);
+                       st.ids, st.d_off, st.d_size, ws.rk, ws.ri, a.kk, ws.pk, ws.pi, a.attr, a.qmask);
 }
 
 // Items whose result lists are longer than a wave's sorted list holds (the
@@ -518,16 +524,44 @@ struct Model {
   double rho, p0, V, vsum;
 };
 
+// A filtered search (Sec. 8, "Filters"): each candidate's cap share v
+// becomes the share of passing rows beyond its bisector,
+// u = v f / (v f + (1 - v) f_0), with f the candidate partition's estimated
+// pass fraction and f_0 that of the first partition.  A partition's
+// estimate sums the live rows carrying each bit of the query's mask (exact
+// for one label per row), capped at its live rows.
+struct Filter {
+  const int32_t* cand = nullptr;   // the query's candidate row
+  const uint32_t* cnt = nullptr;   // [nlist][33]; null: no filter
+  uint32_t mask = 0;
+  double f0 = 1.0;
+  __device__ double fraction(int p) const {
+    const uint32_t* c = cnt + (int64_t)p * 33;
+    const uint32_t live = c[32];
+    if (live == 0) return 0.0;
+    uint64_t est = 0;
+    for (uint32_t m = mask; m; m &= m - 1) est += c[__builtin_ctz(m)];
+    return (double)(est < live ? est : live) / (double)live;
+  }
+  // the share of candidate position i (>= 1) for cap share v
+  __device__ double share(double v, int i) const {
+    if (!cnt) return v;
+    const double num = v * fraction(cand[i]);
+    if (!(num > 0.0)) return 0.0;
+    return num / (num + (1.0 - v) * f0);
+  }
+};
+
 // p_0, V = sum v_i and the committed mass v_1 + ... + v_{m-1} for radius rho
 // (candidates 1 .. M - 1 of the query).
 __device__ void recompute_model(Model& md, double rho, const float* __restrict__ hq, int M, int committed,
-                                const double* __restrict__ table, bool direct) {
+                                const double* __restrict__ table, bool direct, const Filter& fl) {
   const int lane = lane_id();
   double vs = 0.0, pr = 1.0, vc = 0.0;
   const bool inf = __builtin_isinf(rho);
   for (int i = 1 + lane; i < M; i += WAVE) {
     const double t = inf ? 0.0 : (double)hq[i] / rho;
-    const double v = cap_value(table, t, direct);
+    const double v = fl.share(cap_value(table, t, direct), i);
     vs += v;
     pr *= (1.0 - v);
     if (i < committed) vc += v;
@@ -547,7 +581,7 @@ __device__ __forceinline__ double model_recall(const Model& md) {
 // Smallest number of further candidates, from position `from`, after which
 // the current model reaches the target; M - from if it never does.
 __device__ int predict_window(const Model& md, const float* __restrict__ hq, int M, int from, double target,
-                              const double* __restrict__ table) {
+                              const double* __restrict__ table, const Filter& fl) {
   if (!(md.V > 0.0)) return 1;
   const double need = (target - md.p0) * md.V / (1.0 - md.p0) - md.vsum;
   if (need <= 0.0) return 1;
@@ -557,7 +591,7 @@ __device__ int predict_window(const Model& md, const float* __restrict__ hq, int
   for (int base = from; base < M; base += WAVE) {
     const int i = base + lane;
     double v = 0.0;
-    if (i < M) v = cap_share(table, inf ? 0.0 : (double)hq[i] / md.rho);
+    if (i < M) v = fl.share(cap_share(table, inf ? 0.0 : (double)hq[i] / md.rho), i);
     // inclusive scan over the wave
     for (int o = 1; o < WAVE; o <<= 1) {
       const double u = __shfl_up(v, o);
@@ -672,7 +706,8 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
                              const int64_t* __restrict__ st_item, double* __restrict__ st_rho,
                              double* __restrict__ st_p0, double* __restrict__ st_V, double* __restrict__ st_vsum,
                              double* __restrict__ st_r, float* __restrict__ rk, int64_t* __restrict__ ri,
-                             uint32_t* __restrict__ hits) {
+                             uint32_t* __restrict__ hits, const uint32_t* __restrict__ qmask,
+                             const uint32_t* __restrict__ attr_cnt) {
   const int lane = lane_id();
   const int w = st_weff[q];
   L.load(rk + q * kk, ri + q * kk);
@@ -697,6 +732,13 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
   for (int j = WAVE; j < w; ++j) it_end += item_chunks(psize[cand[q * M + m0 + j]], chunk_tiles);
   L.prime(pk + it * kk, pi + it * kk);
   Model md{st_rho[q], st_p0[q], st_V[q], st_vsum[q]};
+  Filter fl;
+  if (aps && qmask) {
+    fl.cand = cand + q * M;
+    fl.cnt = attr_cnt;
+    fl.mask = qmask[q];
+    fl.f0 = fl.fraction(fl.cand[0]);
+  }
   const double qn = ip ? qn2[q] : 0.0;
   double r = st_r[q];
   int committed = m0;
@@ -714,16 +756,16 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
     const bool full = kth_id >= 0;
     const double rho_new = full ? key_radius(L.key(k - 1), ip, qn) : __builtin_inf();
     if (committed == 1) {
-      recompute_model(md, rho_new, hq, Mq, committed, table, est == QUAKE_EST_APS_RP);
+      recompute_model(md, rho_new, hq, Mq, committed, table, est == QUAKE_EST_APS_RP, fl);
     } else {
       const bool redo = est != QUAKE_EST_APS || (__builtin_isinf(md.rho) ? !__builtin_isinf(rho_new)
                                                                           : fabs(rho_new - md.rho) > tau_rho * md.rho);
       if (redo) {
-        recompute_model(md, rho_new, hq, Mq, committed, table, est == QUAKE_EST_APS_RP);
+        recompute_model(md, rho_new, hq, Mq, committed, table, est == QUAKE_EST_APS_RP, fl);
       } else if (md.V > 0.0) {
         const float hc = j < WAVE ? readlane_f(my_h, j) : hq[committed - 1];  // committed - 1 = m0 + j
         const double t = __builtin_isinf(md.rho) ? 0.0 : (double)hc / md.rho;
-        md.vsum += cap_share(table, t);
+        md.vsum += fl.share(cap_share(table, t), committed - 1);
       }
     }
     r = full ? model_recall(md) : 0.0;
@@ -736,7 +778,7 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
     // more partitions are committed, so a query usually needs more - the
     // window is scaled by wscale percent (speculation costs scans, not
     // results: partitions past the stop point are discarded)
-    if (aps && L.id(k - 1) >= 0) wn = (predict_window(md, hq, Mq, committed, tau_r, table) * wscale + 99) / 100;
+    if (aps && L.id(k - 1) >= 0) wn = (predict_window(md, hq, Mq, committed, tau_r, table, fl) * wscale + 99) / 100;
     else wn = 2 * w;
     if (wn < 1) wn = 1;
     if (wn > wmax) wn = wmax;
@@ -763,10 +805,11 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
       int32_t *__restrict__ st_w, int32_t *__restrict__ st_done, const int32_t *__restrict__ st_weff,            \
       const int64_t *__restrict__ st_item, double *__restrict__ st_rho, double *__restrict__ st_p0,              \
       double *__restrict__ st_V, double *__restrict__ st_vsum, double *__restrict__ st_r, float *__restrict__ rk, \
-      int64_t *__restrict__ ri, uint32_t *__restrict__ hits
+      int64_t *__restrict__ ri, uint32_t *__restrict__ hits, const uint32_t *__restrict__ qmask,                  \
+      const uint32_t *__restrict__ attr_cnt
 #define QK_COMMIT_ARGS                                                                                        \
   M, mq, k, kk, aps, ip, chunk_tiles, wmax, wscale, tau_r, tau_rho, est, cand, hcand, psize, qn2, pk, pi, table, st_m, st_w, \
-      st_done, st_weff, st_item, st_rho, st_p0, st_V, st_vsum, st_r, rk, ri, hits
+      st_done, st_weff, st_item, st_rho, st_p0, st_V, st_vsum, st_r, rk, ri, hits, qmask, attr_cnt
 
 // Lists longer than a wave: one 64-thread block per query, lists in LDS.
 template <int LMAX>
@@ -798,7 +841,8 @@ void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const dou
                      ws.cand,                                                                                   \
                      ws.h,                                                                                      \
                      st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_weff,        \
-                     ws.st_item, ws.st_rho, ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri, a.hits)
+                     ws.st_item, ws.st_rho, ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri, a.hits, a.qmask,   \
+                     a.attr_cnt)
   if (a.kk <= WAVE && a.slot_ids) QK_COMMIT(k_commit64<PackedList>, (a.nq + 3) / 4, 256);
   else if (a.kk <= WAVE) QK_COMMIT(k_commit64<RegList>, (a.nq + 3) / 4, 256);
   else if (a.kk <= KMAX) QK_COMMIT(k_commit<KMAX>, a.nq, 64);

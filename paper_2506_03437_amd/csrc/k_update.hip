@@ -140,7 +140,8 @@ void launch_mark_deleted(Store& st, const int64_t* slots, int64_t n, hipStream_t
 __global__ __launch_bounds__(256) void k_move_slots(const int64_t* __restrict__ src, const int64_t* __restrict__ dst,
                                                      int64_t n, int dp, int dp16, float* __restrict__ v32,
                                                      uint16_t* __restrict__ v16, float* __restrict__ v16n,
-                                                     float* __restrict__ rows32, int64_t* __restrict__ sid) {
+                                                     float* __restrict__ rows32, int64_t* __restrict__ sid,
+                                                     uint32_t* __restrict__ attr) {
   const int nch4 = dp >> 2;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t i = e / nch4;
@@ -165,6 +166,7 @@ __global__ __launch_bounds__(256) void k_move_slots(const int64_t* __restrict__ 
     *reinterpret_cast<float4*>(rows32 + b * dp + c4 * 4) = *reinterpret_cast<const float4*>(rows32 + a * dp + c4 * 4);
   if (c4 == 0) {
     if (v16n) v16n[b] = v16n[a];
+    if (attr) attr[b] = attr[a];
     sid[b] = sid[a];
     sid[a] = -1;
   }
@@ -174,7 +176,47 @@ void launch_move_slots(Store& st, const int64_t* src, const int64_t* dst, int64_
   const int64_t total = n * (st.dp >> 2);
   if (total <= 0) return;
   hipLaunchKernelGGL(k_move_slots, grid_of(total), dim3(256), 0, s, src, dst, n, st.dp, st.dp16, st.v32, st.v16,
-                     st.v16n, st.rows32, st.ids);
+                     st.v16n, st.rows32, st.ids, st.attr);
+}
+
+__global__ __launch_bounds__(256) void k_put_u32(const uint32_t* __restrict__ src, const int64_t* __restrict__ slot,
+                                                  int64_t n, uint32_t* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[slot[i]] = src[i];
+}
+
+void launch_put_u32(const uint32_t* src, const int64_t* slot, int64_t n, uint32_t* dst, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_put_u32, grid_of(n), dim3(256), 0, s, src, slot, n, dst);
+}
+
+// Per partition (one block each): live rows carrying each of the 32 label
+// bits, and live rows, into cnt[p][0..32].
+__global__ __launch_bounds__(256) void k_attr_counts(const uint32_t* __restrict__ attr,
+                                                      const int64_t* __restrict__ sid,
+                                                      const int64_t* __restrict__ poff,
+                                                      const int32_t* __restrict__ psize, uint32_t* __restrict__ cnt) {
+  __shared__ uint32_t c[33];
+  const int p = blockIdx.x;
+  if (threadIdx.x < 33) c[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = poff[p] * TILE;
+  for (int j = threadIdx.x; j < psize[p]; j += 256) {
+    if (sid[base + j] < 0) continue;
+    uint32_t a = attr[base + j];
+    atomicAdd(&c[32], 1u);
+    while (a) {
+      atomicAdd(&c[__builtin_ctz(a)], 1u);
+      a &= a - 1;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 33) cnt[(int64_t)p * 33 + threadIdx.x] = c[threadIdx.x];
+}
+
+void launch_attr_counts(const Store& st, hipStream_t s) {
+  if (st.nlist > 0 && st.attr)
+    hipLaunchKernelGGL(k_attr_counts, dim3((unsigned)st.nlist), dim3(256), 0, s, st.attr, st.ids, st.d_off, st.d_size,
+                       st.d_attr_cnt);
 }
 
 // |x|^2 of the 16-bit copy for the listed slots.

@@ -132,6 +132,12 @@ void realloc_tables(quake_index* idx, Store& st, hipStream_t s) {
   st.d_order = mem.alloc<int32_t>(N);
   st.d_hits = mem.alloc<uint32_t>(N);
   launch_fill_i32(reinterpret_cast<int32_t*>(st.d_hits), N, 0, s);
+  if (st.attr) {
+    // label counts per partition: recounted before the next filtered search
+    mem.release(st.d_attr_cnt);
+    st.d_attr_cnt = mem.alloc<uint32_t>((size_t)N * 33);
+    st.attr_dirty = true;
+  }
 }
 
 // Appends `extra` empty partitions (no tiles yet); their centroids are left
@@ -593,6 +599,7 @@ void maintain(quake_index* idx, const quake_maintain_params& p, quake_maintain_r
   store_upload_table(st, s);
   launch_fill_i32(reinterpret_cast<int32_t*>(st.d_hits), std::max<int64_t>(st.nlist, 1), 0, s);
   st.window = 0;
+  st.attr_dirty = true;
   QK_HIP(hipStreamSynchronize(s));
   release_graphs(idx);
   if (p.decisions)

@@ -3,8 +3,8 @@
 // The file holds the index's logical content, not its device layout: the
 // level-0 centroids, the access statistics, a two-level index's level 1
 // (its centroids and the top partition of every level-0 centroid), and every
-// live vector with its id and partition, partition by partition in store
-// order.  Loading builds a fresh store from that content with the given
+// live vector with its id, partition and (for a labelled index) label bits,
+// partition by partition in store order.  Loading builds a fresh store from that content with the given
 // centroids and assignment, so each partition keeps its rows in the saved
 // order (deleted slots and relocation gaps are gone) and every search on the
 // loaded index sees the same partitions, centroids and rows.
@@ -34,7 +34,7 @@ struct FileHeader {
   char magic[8];
   uint32_t version;
   uint32_t header_bytes;
-  int32_t d, metric, storage, n_levels, drop_f32_tiles, reserved0;
+  int32_t d, metric, storage, n_levels, drop_f32_tiles, labelled;
   int64_t nlist, nlist_top, n_live, window;
   double capacity_slack;
   quake_tuning tune;
@@ -108,8 +108,15 @@ void save(quake_index* idx, const char* path, hipStream_t s) {
   if (!sid.empty())
     QK_HIP(hipMemcpyAsync(sid.data(), st.ids, sid.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   QK_HIP(hipStreamSynchronize(s));
+  std::vector<uint32_t> all_attr;
+  if (st.attr) {
+    all_attr.resize(sid.size());
+    QK_HIP(hipMemcpyAsync(all_attr.data(), st.attr, all_attr.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+  }
   std::vector<int64_t> slots, ids;
   std::vector<int32_t> part;
+  std::vector<uint32_t> attr;
   slots.reserve(st.live);
   ids.reserve(st.live);
   part.reserve(st.live);
@@ -121,6 +128,7 @@ void save(quake_index* idx, const char* path, hipStream_t s) {
       slots.push_back(base + j);
       ids.push_back(id);
       part.push_back((int32_t)p);
+      if (st.attr) attr.push_back(all_attr[base + j]);
     }
   }
   QK_CHECK((int64_t)ids.size() == st.live, QUAKE_E_DEVICE, "live count and store disagree");
@@ -136,6 +144,7 @@ void save(quake_index* idx, const char* path, hipStream_t s) {
   hd.storage = idx->storage;
   hd.n_levels = idx->n_levels;
   hd.drop_f32_tiles = st.v32 ? 0 : 1;
+  hd.labelled = st.attr ? 1 : 0;
   hd.nlist = st.nlist;
   hd.nlist_top = idx->n_levels == 2 ? idx->L1.nlist : 0;
   hd.n_live = n;
@@ -165,6 +174,7 @@ void save(quake_index* idx, const char* path, hipStream_t s) {
   }
   w.put(ids.data(), ids.size() * sizeof(int64_t));
   w.put(part.data(), part.size() * sizeof(int32_t));
+  w.put(attr.data(), attr.size() * sizeof(uint32_t));
   {
     const int64_t chunk = std::min<int64_t>(kChunkRows, n);
     Buf<int64_t> d_slots(idx->mem, chunk);
@@ -198,7 +208,7 @@ quake_index* load(const char* path, const quake_allocator* allocator, size_t hbm
            "unsupported file version");
   QK_CHECK(hd.d >= 1 && hd.d <= MAX_DIM && hd.nlist >= 1 && hd.nlist <= INT32_MAX && hd.n_live >= 1 &&
                (hd.n_levels == 1 || (hd.n_levels == 2 && hd.nlist_top >= 1 && hd.nlist_top <= hd.nlist)) &&
-               hd.capacity_slack >= 0 && hd.window >= 0,
+               hd.capacity_slack >= 0 && hd.window >= 0 && (hd.labelled == 0 || hd.labelled == 1),
            QUAKE_E_INVALID, "corrupt header");
   const int d = hd.d;
   const int64_t n = hd.n_live, N = hd.nlist;
@@ -231,6 +241,11 @@ quake_index* load(const char* path, const quake_allocator* allocator, size_t hbm
   to_device(ids.p, n * sizeof(int64_t));
   Buf<int32_t> part(tmp, n);
   to_device(part.p, n * sizeof(int32_t));
+  std::unique_ptr<Buf<uint32_t>> attr;
+  if (hd.labelled) {
+    attr.reset(new Buf<uint32_t>(tmp, n));
+    to_device(attr->p, n * sizeof(uint32_t));
+  }
   Buf<float> x(tmp, (size_t)n * d);
   to_device(x.p, (size_t)n * d * sizeof(float));
   const uint64_t expect = r.hash.h;
@@ -250,6 +265,7 @@ quake_index* load(const char* path, const quake_allocator* allocator, size_t hbm
   bp.hbm_budget_bytes = hbm_budget_bytes;
   bp.capacity_slack = hd.capacity_slack;
   bp.drop_f32_tiles = hd.drop_f32_tiles;
+  bp.attrs = attr ? attr->p : nullptr;
   std::unique_ptr<quake_index> idx(
       build_index(x.p, ids.p, n, d, &bp, C1 ? C1->p : nullptr, top ? top->p : nullptr, allocator, s));
   QK_HIP(hipMemcpyAsync(idx->L0.d_hits, hits.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice, s));

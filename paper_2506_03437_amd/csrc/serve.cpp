@@ -86,6 +86,8 @@ void clone_store(qk::DeviceMemory& mem, const qk::Store& a, const qk::IdMap& am,
     t.v16n = dup(mem, got, a.v16n, slots, s);
     t.rows32 = dup(mem, got, a.rows32, slots * a.dp, s);
     t.ids = dup(mem, got, a.ids, slots, s);
+    t.attr = dup(mem, got, a.attr, slots, s);
+    t.d_attr_cnt = dup(mem, got, a.d_attr_cnt, N * 33, s);
     qk::IdMap tm = am;
     tm.keys = dup(mem, got, am.keys, (size_t)am.mask + 1, s);
     tm.vals = dup(mem, got, am.vals, (size_t)am.mask + 1, s);
@@ -100,8 +102,8 @@ void clone_store(qk::DeviceMemory& mem, const qk::Store& a, const qk::IdMap& am,
 
 void free_store(qk::DeviceMemory& mem, qk::Store& b, qk::IdMap& bm) {
   for (void* p : {(void*)b.centroids, (void*)b.d_off, (void*)b.d_size, (void*)b.d_cap, (void*)b.d_order,
-                  (void*)b.v32, (void*)b.v16, (void*)b.v16n, (void*)b.rows32, (void*)b.ids, (void*)bm.keys,
-                  (void*)bm.vals})
+                  (void*)b.v32, (void*)b.v16, (void*)b.v16n, (void*)b.rows32, (void*)b.ids, (void*)b.attr,
+                  (void*)b.d_attr_cnt, (void*)bm.keys, (void*)bm.vals})
     mem.release(p);
   b = qk::Store();
   bm = qk::IdMap();

@@ -31,7 +31,7 @@ EXPORTED = ("quake_build", "quake_search", "quake_search_noalloc", "quake_insert
             "quake_free", "quake_last_error", "quake_autotune", "quake_server_create", "quake_server_search", "quake_server_insert",
             "quake_server_delete", "quake_server_wait", "quake_server_stats", "quake_server_destroy",
             "quake_access_stats", "quake_maintain", "quake_profile_latency", "quake_describe", "quake_save",
-            "quake_load")
+            "quake_load", "quake_insert_attrs")
 PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "scan_sets", "upper")
 
 
@@ -46,7 +46,7 @@ class BuildParams(ctypes.Structure):
                 ("kmeans_iters", ctypes.c_int32), ("nlist", ctypes.c_int64), ("nlist_top", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("centroids", ctypes.c_void_p), ("assign", ctypes.c_void_p),
                 ("hbm_budget_bytes", ctypes.c_size_t), ("capacity_slack", ctypes.c_double),
-                ("drop_f32_tiles", ctypes.c_int32)]
+                ("drop_f32_tiles", ctypes.c_int32), ("attrs", ctypes.c_void_p)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -89,7 +89,8 @@ class SearchParams(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("nprobe", ctypes.c_int32), ("recall_target", ctypes.c_double),
                 ("f_M", ctypes.c_double), ("tau_rho", ctypes.c_double), ("upper_recall_target", ctypes.c_double),
                 ("upper_f_M", ctypes.c_double), ("scan_mode", ctypes.c_int32), ("scan_dtype", ctypes.c_int32),
-                ("rerank_factor", ctypes.c_int32), ("window", ctypes.c_int32), ("estimator", ctypes.c_int32)]
+                ("rerank_factor", ctypes.c_int32), ("window", ctypes.c_int32), ("estimator", ctypes.c_int32),
+                ("filter", ctypes.c_void_p)]
 
 
 class Tuning(ctypes.Structure):
@@ -152,6 +153,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.quake_search.argtypes = [vp, vp, i64, ctypes.POINTER(SearchParams), vp, vp, vp, vp, vp]
     lib.quake_search_noalloc.argtypes = [vp, vp, i64, ctypes.POINTER(SearchParams), vp, vp, vp, vp, vp]
     lib.quake_insert.argtypes = [vp, vp, vp, i64, vp]
+    lib.quake_insert_attrs.argtypes = [vp, vp, vp, vp, i64, vp]
     lib.quake_delete.argtypes = [vp, vp, i64, vp]
     lib.quake_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)]
     lib.quake_export.argtypes = [vp, vp, vp, vp, vp]
@@ -209,6 +211,15 @@ def _dev(t, dtype):
     return t
 
 
+def _labels(t):
+    """Label bits (32 per row or query): a contiguous CUDA int32 or uint32
+    tensor, passed as its bit pattern."""
+    import torch
+    assert t.is_cuda and t.dtype in (torch.int32, torch.uint32) and t.is_contiguous(), \
+        "need a contiguous CUDA int32 / uint32 tensor of label bits"
+    return t
+
+
 def quake_cap_table(d: int) -> np.ndarray:
     out = np.zeros(1024, dtype=np.float64)
     _check(load_library().quake_cap_table(d, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
@@ -217,7 +228,7 @@ def quake_cap_table(d: int) -> np.ndarray:
 
 def quake_build(x, ids=None, *, metric="l2", nlist=256, storage="f32", n_levels=1, nlist_top=0, kmeans_iters=10,
                 seed=0, centroids=None, assign=None, hbm_budget_bytes=0, capacity_slack=0.0,
-                allocator="torch", f32_tiles=True) -> int:
+                allocator="torch", f32_tiles=True, attrs=None) -> int:
     """allocator: "torch" (the caching allocator of x's device, the default) or "hip" (hipMalloc).
     f32_tiles=False (with a 16-bit storage copy): no FP32 tile copy, batched searches only."""
     import torch
@@ -228,8 +239,11 @@ def quake_build(x, ids=None, *, metric="l2", nlist=256, storage="f32", n_levels=
         _dev(centroids, torch.float32)
     if assign is not None:
         _dev(assign, torch.int32)
+    if attrs is not None:
+        _labels(attrs)
     p = BuildParams(_METRIC[metric], _DTYPE[storage], n_levels, kmeans_iters, nlist, nlist_top, seed,
-                    _ptr(centroids), _ptr(assign), hbm_budget_bytes, capacity_slack, 0 if f32_tiles else 1)
+                    _ptr(centroids), _ptr(assign), hbm_budget_bytes, capacity_slack, 0 if f32_tiles else 1,
+                    _ptr(attrs))
     if allocator not in ("torch", "hip"):
         raise ValueError(f"allocator must be 'torch' or 'hip', not {allocator!r}")
     alloc = ctypes.byref(torch_allocator(x.device.index or 0)) if allocator == "torch" else None
@@ -247,15 +261,16 @@ ESTIMATORS = {"aps": 0, "aps-r": 1, "aps-rp": 2}
 
 def _search_params(k=10, nprobe=0, recall_target=0.0, f_M=0.0, tau_rho=0.0, upper_recall_target=0.0,
                    upper_f_M=0.0, scan_mode="plain", scan_dtype="f32", rerank_factor=0, window=0,
-                   estimator="aps") -> SearchParams:
+                   estimator="aps", filter=None) -> SearchParams:
     est = ESTIMATORS[estimator] if isinstance(estimator, str) else int(estimator)
     return SearchParams(k, nprobe, recall_target, f_M, tau_rho, upper_recall_target, upper_f_M, _MODE[scan_mode],
-                        _DTYPE[scan_dtype], rerank_factor, window, est)
+                        _DTYPE[scan_dtype], rerank_factor, window, est,
+                        None if filter is None else _labels(filter).data_ptr())
 
 
 def quake_search(handle: int, q, *, k=10, nprobe=0, recall_target=0.0, f_M=0.0, tau_rho=0.0,
                  upper_recall_target=0.0, upper_f_M=0.0, scan_mode="plain", scan_dtype="f32", rerank_factor=0,
-                 window=0, estimator="aps", outputs=None):
+                 window=0, estimator="aps", filter=None, outputs=None):
     """Returns (ids int64 [nq,k], dist f32 [nq,k], nscanned int32 [nq], recall f64 [nq])."""
     import torch
     _dev(q, torch.float32)
@@ -268,7 +283,7 @@ def quake_search(handle: int, q, *, k=10, nprobe=0, recall_target=0.0, f_M=0.0, 
                    torch.empty((nq,), dtype=torch.float64, device=dev))
     ids, dist, ns, rec = outputs
     p = _search_params(k, nprobe, recall_target, f_M, tau_rho, upper_recall_target, upper_f_M, scan_mode, scan_dtype,
-                       rerank_factor, window, estimator)
+                       rerank_factor, window, estimator, filter)
     _check(load_library().quake_search(handle, _ptr(q), nq, ctypes.byref(p), _ptr(ids), _ptr(dist), _ptr(ns),
                                        _ptr(rec), _stream()))
     return ids, dist, ns, rec
@@ -276,13 +291,13 @@ def quake_search(handle: int, q, *, k=10, nprobe=0, recall_target=0.0, f_M=0.0, 
 
 def quake_search_noalloc(handle: int, q, *, outputs, k=10, nprobe=0, recall_target=0.0, f_M=0.0, tau_rho=0.0,
                          upper_recall_target=0.0, upper_f_M=0.0, scan_mode="plain", scan_dtype="f32",
-                         rerank_factor=0, window=0, estimator="aps"):
+                         rerank_factor=0, window=0, estimator="aps", filter=None):
     """quake_search into caller-given outputs (ids, dist, nscanned, recall) with no allocation in the library."""
     import torch
     _dev(q, torch.float32)
     ids, dist, ns, rec = outputs
     p = _search_params(k, nprobe, recall_target, f_M, tau_rho, upper_recall_target, upper_f_M, scan_mode, scan_dtype,
-                       rerank_factor, window, estimator)
+                       rerank_factor, window, estimator, filter)
     _check(load_library().quake_search_noalloc(handle, _ptr(q), q.shape[0], ctypes.byref(p), _ptr(ids), _ptr(dist),
                                                _ptr(ns), _ptr(rec), _stream()))
     return ids, dist, ns, rec
@@ -293,6 +308,14 @@ def quake_insert(handle: int, x, ids):
     _dev(x, torch.float32)
     _dev(ids, torch.int64)
     _check(load_library().quake_insert(handle, _ptr(x), _ptr(ids), x.shape[0], _stream()))
+
+
+def quake_insert_attrs(handle: int, x, ids, attrs):
+    import torch
+    _dev(x, torch.float32)
+    _dev(ids, torch.int64)
+    _labels(attrs)
+    _check(load_library().quake_insert_attrs(handle, _ptr(x), _ptr(ids), _ptr(attrs), x.shape[0], _stream()))
 
 
 def quake_delete(handle: int, ids):
@@ -571,8 +594,11 @@ class Index:
     def search(self, q, **kw):
         return quake_search(self.handle, q, **kw)
 
-    def insert(self, x, ids):
-        quake_insert(self.handle, x, ids)
+    def insert(self, x, ids, attrs=None):
+        if attrs is None:
+            quake_insert(self.handle, x, ids)
+        else:
+            quake_insert_attrs(self.handle, x, ids, attrs)
 
     def delete(self, ids):
         quake_delete(self.handle, ids)

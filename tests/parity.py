@@ -122,14 +122,27 @@ def replay_margin(res, tau_r, tau_rho, upto):
     return False
 
 
-def check_aps(X, Q, ps, gi, gv, ns, rec, order, h, metric, f_M, tau_r, k=10, rows=None, estimator="aps"):
+def scan_filtered(ps, q, parts, k, metric, attr, mask):
+    """Exact top-k over the rows of the given partitions whose label bits
+    share a bit with `mask`."""
+    from oracle import ivf as oivf
+    rows = np.concatenate([ps.members[int(p)] for p in parts]) if len(parts) else np.zeros(0, dtype=np.int64)
+    rows = rows[(np.asarray(attr, dtype=np.uint64)[rows] & np.uint64(int(mask))) != 0]
+    sub = oivf.PartitionedSet(ps.X[rows], ps.ids[rows], np.zeros(rows.shape[0], dtype=np.int64), ps.C[:1])
+    return oivf.scan_partitions(sub, q, [0], k, metric)
+
+
+def check_aps(X, Q, ps, gi, gv, ns, rec, order, h, metric, f_M, tau_r, k=10, rows=None, estimator="aps",
+              attr=None, masks=None):
     """Adaptive-scan parity for the queries `rows` (default all) of a device
     search: the results are the top-k over the partitions the device
     scanned, the candidate order is a valid APS order, and the stop count
     and recall estimate replay the oracle's, except decisions within the
     margins (at most 1% of the queries).  `estimator` names the variant the
     device ran: "aps" (threshold recompute, table), "aps-r" (every
-    partition, table) or "aps-rp" (every partition, direct evaluation)."""
+    partition, table) or "aps-rp" (every partition, direct evaluation).
+    With `attr` (label bits of every row of ps) and `masks` (one per query)
+    the search was filtered."""
     from oracle import aps as oaps
     from oracle import ivf as oivf
     rows = np.arange(Q.shape[0]) if rows is None else np.asarray(rows)
@@ -143,14 +156,18 @@ def check_aps(X, Q, ps, gi, gv, ns, rec, order, h, metric, f_M, tau_r, k=10, row
         m = int(ns[i])
         assert 1 <= m <= order.shape[1]
         # results: exactly the top-k over the partitions the device scanned
-        ri, rv = oivf.scan_partitions(ps, Q[i], order[j, :m], k, metric)
+        if attr is None:
+            ri, rv = oivf.scan_partitions(ps, Q[i], order[j, :m], k, metric)
+        else:
+            ri, rv = scan_filtered(ps, Q[i], order[j, :m], k, metric, attr, masks[i])
         check_topk(Q[i], X, id_to_row, gi[i], gv[i], ri, rv, metric, k, f"query {i}")
         if not check_candidate_order(Q[i], ps.C, f_M, metric, order[j], h[j]):
             continue
         ordered += 1
         vals = knn.distances(Q[i][None], ps.C, metric)[0]
         h_ref = oaps.bisector_distances(Q[i], ps.C, vals, int(order[j, 0]), order[j, 1:].astype(np.int64), metric)
-        res = oaps.aps_search_one(ps, Q[i], params, table, order=order[j].astype(np.int64), h=h_ref)
+        res = oaps.aps_search_one(ps, Q[i], params, table, order=order[j].astype(np.int64), h=h_ref, attr=attr,
+                                  mask=None if masks is None else int(masks[i]))
         if res.m != m:
             assert replay_margin(res, tau_r, 0.01, max(res.m, m)), f"query {i}: device scanned {m}, oracle {res.m}"
             margin += 1

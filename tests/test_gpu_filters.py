@@ -1,0 +1,154 @@
+"""Filtered search on the device against the oracle (Sec. 8, "Filters").
+
+Rows carry 32 label bits; a query passes its mask, and only rows sharing a
+bit with it are results.  The adaptive search scales each candidate's cap
+share by the partition's estimated pass fraction; its results, stop counts
+and recall estimates replay the oracle's filtered search query by query
+(one label per row, where the estimate is exact, and several labels per
+row, where it is the per-bit upper bound), also after inserts and deletes
+and after a save and load.  A mask that every row passes gives the
+unfiltered search; a fixed nprobe gives the filtered top-k of those
+partitions.  Unsupported combinations are refused.
+"""
+
+import numpy as np
+import pytest
+
+import gpu_util as gu
+import parity
+import synth
+from oracle import knn as oknn
+from oracle import ivf as oivf
+
+pytestmark = pytest.mark.gpu
+
+
+def _labels(n, rng, multi):
+    if multi:
+        return rng.integers(1, 1 << 6, n).astype(np.uint32)     # several of 6 labels per row
+    # one of 8 labels, skewed: label j with weight 1 / (j + 1)
+    w = 1.0 / np.arange(1, 9)
+    return (np.uint32(1) << rng.choice(8, n, p=w / w.sum()).astype(np.uint32)).astype(np.uint32)
+
+
+def _i32(a):
+    return gu.to_dev(np.asarray(a, dtype=np.uint32).view(np.int32))
+
+
+@pytest.fixture(scope="module", params=["one-label", "multi-label"])
+def labelled(request):
+    multi = request.param == "multi-label"
+    spec = synth.MixtureSpec(key=51, n=40_000, d=64, n_components=50, zipf_s=1.1)
+    X = synth.database(spec)
+    Q = synth.queries(spec, 300)
+    rng = np.random.default_rng(5)
+    attr = _labels(X.shape[0], rng, multi)
+    masks = (rng.integers(1, 1 << 6, Q.shape[0]) if multi else
+             (np.uint32(1) << rng.integers(0, 8, Q.shape[0]).astype(np.uint32))).astype(np.uint32)
+    print(f"[build] labelled {request.param} n={X.shape[0]} d=64 nlist=100", flush=True)
+    idx = gu.build(X, metric="l2", nlist=100, kmeans_iters=5, seed=4, attrs=_i32(attr))
+    ps = gu.oracle_view(idx, X)
+    yield X, Q, attr, masks, idx, ps
+    idx.free()
+
+
+@pytest.mark.parametrize("tau", [0.8, 0.95])
+def test_filtered_aps_matches_oracle(labelled, tau):
+    X, Q, attr, masks, idx, ps = labelled
+    gi, gv, ns, rec = gu.search(idx, Q, k=10, recall_target=tau, f_M=0.2, filter=_i32(masks))
+    order, h = idx.candidates(gu.to_dev(Q), 0.2)
+    parity.check_aps(X, Q, ps, gi, gv, ns, rec, order.cpu().numpy(), h.cpu().numpy(), "l2", 0.2, tau, 10,
+                     attr=attr, masks=masks)
+    ok = gi >= 0
+    assert ((attr[np.where(ok, gi, 0)] & masks[:, None]) != 0)[ok].all()
+
+
+def test_filtered_fixed_nprobe(labelled):
+    X, Q, attr, masks, idx, ps = labelled
+    gi, gv, ns, _ = gu.search(idx, Q, k=10, nprobe=6, filter=_i32(masks))
+    _, _, probes = oivf.ivf_search(ps, Q, 10, 6, "l2")
+    id_to_row = {int(i): r for r, i in enumerate(ps.ids.tolist())}
+    checked = 0
+    for i in range(Q.shape[0]):
+        key = np.sort(oknn.distances(Q[i][None], ps.C, "l2")[0])
+        if key[6] - key[5] <= 1e-5 * key[5]:
+            continue  # the sixth and seventh centroids tie in FP32: either may be scanned
+        ri, rv = parity.scan_filtered(ps, Q[i], probes[i], 10, "l2", attr, masks[i])
+        parity.check_topk(Q[i], X, id_to_row, gi[i], gv[i], ri, rv, "l2", 10, f"query {i}")
+        live = gi[i][gi[i] >= 0]
+        assert ((attr[live] & masks[i]) != 0).all()
+        checked += 1
+    assert checked >= 0.99 * Q.shape[0]
+
+
+def test_mask_every_row_passes_is_the_unfiltered_search(labelled):
+    X, Q, attr, masks, idx, ps = labelled
+    everything = np.full(Q.shape[0], 0xFFFFFFFF, dtype=np.uint32)
+    fi, fv, fns, frec = gu.search(idx, Q, k=10, recall_target=0.9, f_M=0.2, filter=_i32(everything))
+    ui, uv, uns, urec = gu.search(idx, Q, k=10, recall_target=0.9, f_M=0.2)
+    same = fns == uns
+    assert same.mean() >= 0.99
+    assert (fi[same] == ui[same]).all() and (fv[same] == uv[same]).all()
+    np.testing.assert_allclose(frec[same], urec[same], atol=1e-12)
+
+
+def test_updates_and_save_load_keep_labels(tmp_path):
+    from paper_2506_03437_amd import Index
+    spec = synth.MixtureSpec(key=52, n=20_000, d=32, n_components=30, zipf_s=1.1)
+    X = synth.database(spec)
+    Q = synth.queries(spec, 200)
+    rng = np.random.default_rng(9)
+    attr = _labels(X.shape[0], rng, False)
+    masks = (np.uint32(1) << rng.integers(0, 8, Q.shape[0]).astype(np.uint32)).astype(np.uint32)
+    print("[build] labelled updates", flush=True)
+    idx = gu.build(X, metric="l2", nlist=40, kmeans_iters=4, seed=6, attrs=_i32(attr))
+    # inserts that overflow partitions (relocations move the labels) and deletes
+    Xn = (X[rng.choice(X.shape[0], 3000, replace=False)] + 0.05 * rng.standard_normal((3000, 32))).astype(np.float32)
+    an = _labels(3000, rng, False)
+    ids_n = np.arange(10 ** 6, 10 ** 6 + 3000, dtype=np.int64)
+    idx.insert(gu.to_dev(Xn), gu.to_dev(ids_n), attrs=_i32(an))
+    dead = rng.choice(X.shape[0], 6000, replace=False).astype(np.int64)   # enough to compact partitions
+    idx.delete(gu.to_dev(dead))
+    keep = np.setdiff1d(np.arange(X.shape[0]), dead)
+    Xa = np.concatenate([X[keep], Xn])
+    ida = np.concatenate([keep.astype(np.int64), ids_n])
+    aa = np.concatenate([attr[keep], an])
+    ps = gu.oracle_view(idx, Xa, ida)
+    gi, gv, ns, rec = gu.search(idx, Q, k=10, recall_target=0.9, f_M=0.25, filter=_i32(masks))
+    order, h = idx.candidates(gu.to_dev(Q), 0.25)
+    parity.check_aps(Xa, Q, ps, gi, gv, ns, rec, order.cpu().numpy(), h.cpu().numpy(), "l2", 0.25, 0.9, 10,
+                     attr=aa, masks=masks)
+    path = str(tmp_path / "labelled.qk")
+    idx.save(path)
+    b = Index.load(path)
+    r2 = gu.search(b, Q, k=10, recall_target=0.9, f_M=0.25, filter=_i32(masks))
+    for x, y in zip((gi, gv, ns, rec), r2):
+        assert (x == y).all()
+    b.free()
+    idx.free()
+
+
+def test_unsupported_combinations_are_refused():
+    from paper_2506_03437_amd import quake
+    spec = synth.MixtureSpec(key=53, n=5_000, d=16, n_components=10)
+    X = synth.database(spec)
+    Q = synth.queries(spec, 8)
+    rng = np.random.default_rng(2)
+    attr = _labels(X.shape[0], rng, False)
+    m = _i32(np.ones(8, dtype=np.uint32))
+    print("[build] refusals", flush=True)
+    plain = gu.build(X, metric="l2", nlist=10, kmeans_iters=2, seed=1, storage="f16")
+    lab = gu.build(X, metric="l2", nlist=10, kmeans_iters=2, seed=1, storage="f16", attrs=_i32(attr))
+    x1 = gu.to_dev(X[:2])
+    i1 = gu.to_dev(np.array([10 ** 7, 10 ** 7 + 1], dtype=np.int64))
+    for call in (
+        lambda: gu.search(plain, Q, k=10, recall_target=0.9, filter=m),                 # no labels
+        lambda: gu.search(lab, Q, k=10, recall_target=0.9, filter=m, scan_mode="batched", scan_dtype="f16"),
+        lambda: lab.insert(x1, i1),                                                       # labels missing
+        lambda: plain.insert(x1, i1, attrs=_i32(np.ones(2, dtype=np.uint32))),            # index has none
+    ):
+        with pytest.raises(quake.QuakeError) as e:
+            call()
+        assert e.value.code == quake.E_INVALID
+    plain.free()
+    lab.free()
