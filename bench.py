@@ -511,6 +511,96 @@ def ablation_leg(idx, w, Q, Qd, truth, sample_rows, recall_of, paths, upper):
     return res
 
 
+def filter_leg(w, sample_rows, threads):
+    """Filtered search (Sec. 8, "Filters") on the workload's rows with
+    seeded labels: one of 8 labels per row, the row's mixture component's
+    home label with probability 0.7, else uniform; every query filters on
+    one uniformly drawn label (about 1 row in 8 passes).  A labelled index of
+    the same shape is built; recall@10 is against the exact filtered k-NN of
+    the sample queries.  Reported: the filtered adaptive search at targets
+    0.8 / 0.9 / 0.95 (plain FP32 path), a fixed nprobe tuned by binary search
+    to filtered recall 0.9, and post-filtering (an unfiltered adaptive search
+    for k / (pass rate) results, of which the first k passing are kept)."""
+    import numpy as np
+    import torch
+    import synth
+    from oracle import knn as oknn
+    from paper_2506_03437_amd import Index
+
+    dev = torch.device("cuda", 0)
+    X, comp = synth.database(w.spec, with_components=True, threads=threads)
+    Q = synth.queries(w.spec, w.nq, noise_std=w.query_noise, threads=threads)
+    attrs = synth.row_labels(w.spec, comp)
+    masks = synth.query_masks(w.spec, w.nq)
+    as_dev = lambda a: torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(dev)
+    Xd = torch.from_numpy(X).to(dev)
+    idx = Index(Xd, metric=w.metric, nlist=w.nlist, kmeans_iters=10, seed=1, attrs=as_dev(attrs))
+    del Xd
+    Qd = torch.from_numpy(Q).to(dev)
+    Md = as_dev(masks)
+    truth = np.empty((sample_rows.size, w.k), dtype=np.int64)
+    for lab in np.unique(masks[sample_rows]).tolist():
+        sel = np.nonzero(masks[sample_rows] == lab)[0]
+        rows = np.nonzero(attrs == lab)[0]
+        ti, _ = oknn.knn_exact(X[rows], rows.astype(np.int64), Q[sample_rows[sel]], w.k, w.metric)
+        truth[sel] = ti
+    pass_rate = float(np.mean([(attrs == m).mean() for m in np.unique(masks)]))
+
+    def recall(ids):
+        found = ids[sample_rows] if ids.shape[0] == w.nq else ids
+        return float(np.mean([len(set(found[i].tolist()) & set(truth[i].tolist())) for i in range(truth.shape[0])])) / w.k
+
+    def timed(**kw):
+        idx.search(Qd, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            out = idx.search(Qd, **kw)
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) * 1e3 / 3
+
+    res = {"setup": "8 labels, home label of the row's component with probability 0.7; one label per query; "
+                    f"mean pass rate {pass_rate:.3f}", "aps": []}
+    for tau in (0.8, 0.9, 0.95):
+        (ids, _, ns, _), ms = timed(k=w.k, recall_target=tau, f_M=w.f_M, filter=Md)
+        res["aps"].append({"recall_target": tau, "recall_at_10": recall(ids.cpu().numpy()), "ms_per_search": ms,
+                           "mean_partitions_scanned": float(ns.float().mean().item())})
+        log(f"filters: APS target {tau}: recall {res['aps'][-1]['recall_at_10']:.4f}, "
+            f"{res['aps'][-1]['mean_partitions_scanned']:.1f} partitions, {ms:.2f} ms")
+    for t in LADDER:
+        (ids, _, ns, _), ms = timed(k=w.k, recall_target=t, f_M=w.f_M, filter=Md)
+        r = recall(ids.cpu().numpy())
+        if r >= 0.9 or t == LADDER[-1]:
+            break
+    res["aps_matched"] = {"recall_target": t, "recall_at_10": r, "ms_per_search": ms,
+                          "mean_partitions_scanned": float(ns.float().mean().item())}
+    Qs = Qd[torch.from_numpy(sample_rows).to(dev)]
+    Ms = Md[torch.from_numpy(sample_rows).to(dev)]
+    lo, hi = 1, min(w.nlist, 4096)
+    while lo < hi:
+        mid = (lo + hi) // 2
+        fids, _, _, _ = idx.search(Qs, k=w.k, nprobe=mid, filter=Ms)
+        if recall(fids.cpu().numpy()) >= 0.9:
+            hi = mid
+        else:
+            lo = mid + 1
+    (fids, _, _, _), fms = timed(k=w.k, nprobe=lo, filter=Md)
+    res["fixed_nprobe"] = {"nprobe": lo, "recall_at_10": recall(fids.cpu().numpy()), "ms_per_search": fms}
+    kp = int(min(256, round(w.k / pass_rate)))
+    (pids, _, pns, _), pms = timed(k=kp, recall_target=0.9, f_M=w.f_M)
+    pids = pids.cpu().numpy()
+    kept = np.full((w.nq, w.k), -1, dtype=np.int64)
+    for i in sample_rows.tolist():
+        ok = [j for j in pids[i].tolist() if j >= 0 and attrs[j] & masks[i]][: w.k]
+        kept[i, : len(ok)] = ok
+    res["post_filter"] = {"k_searched": kp, "recall_target": 0.9, "recall_at_10": recall(kept),
+                          "ms_per_search": pms, "mean_partitions_scanned": float(pns.float().mean().item())}
+    log(f"filters: APS target {t}: recall {r:.4f}; fixed nprobe {lo} recall {res['fixed_nprobe']['recall_at_10']:.4f} {fms:.2f} ms; post-filter "
+        f"k={kp}: recall {res['post_filter']['recall_at_10']:.4f}, {pms:.2f} ms")
+    idx.free()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -751,6 +841,8 @@ def main():
     ablation = None
     if args.ablation and truth is not None:
         ablation = ablation_leg(idx, w, Q, Qd, truth, sample_rows, recall_of, paths, upper)
+        if not two_level:
+            ablation["filters"] = filter_leg(w, sample_rows, threads)
     maint = None
     if args.maintenance and batched is not None and not two_level:
         maint = maintenance_leg(idx, w, X, batched["recall_target"], args.rerank_factor, threads)

@@ -17,5 +17,6 @@ from .mixture import (  # noqa: F401
     leaf_spec_database,
     leaf_spec_queries,
 )
+from .labels import query_masks, row_labels  # noqa: F401
 from .trace import TraceSpec, serving_trace  # noqa: F401
 from .workloads import WORKLOADS, Workload, get_workload  # noqa: F401
