@@ -226,6 +226,27 @@ int quake_save(quake_index* index, const char* path, void* stream);
 int quake_load(const char* path, const quake_allocator* allocator, size_t hbm_budget_bytes, void* stream,
                quake_index** out);
 
+/* Add a level ("Add Level", Sec. 4.2): partition the level-0 centroids of a
+ * one-level index into nlist_top partitions by k-means (kmeans_iters Lloyd
+ * iterations, seeded), which become level 1: searches then run the level-1
+ * search first and inserts route top-down, as on an index built with two
+ * levels.  Errors: STATE (the index has two levels: at most two are
+ * supported), INVALID (nlist_top outside [1, nlist]), NOMEM, DEVICE. */
+int quake_add_level(quake_index* index, int64_t nlist_top, int32_t kmeans_iters, uint64_t seed, void* stream);
+
+/* Remove the top level ("Remove Level", Sec. 4.2): the level-0 centroids
+ * become the top again; level 0 is unchanged.  Errors: STATE (one level). */
+int quake_remove_level(quake_index* index, void* stream);
+
+/* The level thresholds of Sec. 4.2 ("Adding and Removing Levels"): a
+ * one-level index with more than add_above partitions (0: never) gets a
+ * level of nlist_top partitions (0: round(sqrt(nlist))); a two-level index
+ * whose top level has fewer than remove_below partitions loses it.
+ * *action (optional) receives 1 (added), -1 (removed) or 0.  Errors as
+ * quake_add_level / quake_remove_level; INVALID for a negative argument. */
+int quake_adjust_levels(quake_index* index, int64_t add_above, int64_t remove_below, int64_t nlist_top,
+                        int32_t kmeans_iters, uint64_t seed, void* stream, int32_t* action);
+
 /* Export the level-1 partitioning of a two-level index: top centroids
  * [nlist_top][d] (device float32) and the top partition of every level-0
  * centroid, top_of[nlist] (device int32). */

@@ -10,6 +10,8 @@ from .quake import (  # noqa: F401
     Server,
     load_library,
     quake_access_stats,
+    quake_add_level,
+    quake_adjust_levels,
     quake_autotune,
     quake_build,
     quake_candidates,
@@ -25,6 +27,7 @@ from .quake import (  # noqa: F401
     quake_maintain,
     quake_profile,
     quake_profile_latency,
+    quake_remove_level,
     quake_save,
     quake_search,
     quake_search_noalloc,

@@ -1345,6 +1345,49 @@ int quake_cap_table(int32_t d, double* out) {
 
 }  // extern "C"
 
+// Level 1 over the level-0 centroids (Sec. 3; "Add Level", Sec. 4.2): k-means
+// of the centroids into nlist_top partitions, or the given top centroids
+// (device [nlist_top][d]) and top_of (device [nlist]); then the store of
+// the level-0 centroids partitioned by it.
+void build_top_level(quake_index* idx, int64_t nlist_top, int32_t kmeans_iters, uint64_t seed,
+                     const float* top_centroids, const int32_t* top_of, hipStream_t s) {
+  const Store& L0 = idx->L0;
+  const int d = idx->d, dp = idx->dp;
+  Store& L1 = idx->L1;
+  L1 = Store();
+  L1.d = d;
+  L1.dp = dp;
+  L1.nlist = nlist_top;
+  L1.centroids = idx->mem.alloc<float>((size_t)L1.nlist * dp);
+  idx->top_of = idx->mem.alloc<int32_t>(L0.nlist);
+  if (top_centroids && top_of) {
+    // a given level 1 (a saved index): its centroids and the top partition of every level-0 centroid
+    require_finite(idx, top_centroids, L1.nlist * (int64_t)d, "top centroids", s);
+    clear_flag(idx, s);
+    qk::launch_check_range(top_of, L0.nlist, L1.nlist, idx->d_flag, s);
+    QK_CHECK(!flag_set(idx, s), QUAKE_E_INVALID, "top_of holds a partition outside [0, nlist_top)");
+    qk::launch_pad_rows(top_centroids, L1.nlist, d, dp, L1.centroids, nullptr, s);
+    QK_HIP(hipMemcpyAsync(idx->top_of, top_of, L0.nlist * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  } else {
+    kmeans(idx->mem, L0.centroids, L0.nlist, dp, L1.nlist, std::max(kmeans_iters, 1), seed ^ 0x9e3779b97f4a7c15ull,
+           idx->metric, L1.centroids, s);
+    qk::launch_assign(L0.centroids, L0.nlist, dp, L1.centroids, L1.nlist, idx->metric, idx->top_of, s);
+  }
+  build_store(idx, L1, L0.centroids, dp, nullptr, L0.nlist, idx->top_of, 0.0, QUAKE_F32, true, s);
+}
+
+// Drops level 1 ("Remove Level", Sec. 4.2): the level-0 centroids become the
+// top again.
+void drop_top_level(quake_index* idx) {
+  Store& L1 = idx->L1;
+  for (void* p : {(void*)L1.centroids, (void*)L1.d_off, (void*)L1.d_size, (void*)L1.d_cap, (void*)L1.d_order,
+                  (void*)L1.d_hits, (void*)L1.v32, (void*)L1.v16, (void*)L1.v16n, (void*)L1.rows32, (void*)L1.ids,
+                  (void*)idx->top_of})
+    idx->mem.release(p);
+  L1 = Store();
+  idx->top_of = nullptr;
+}
+
 quake_index* qk::build_index(const float* x, const int64_t* ids, int64_t n, int32_t d,
                              const quake_build_params* params, const float* top_centroids, const int32_t* top_of,
                              const quake_allocator* allocator, hipStream_t s) {
@@ -1440,28 +1483,8 @@ quake_index* qk::build_index(const float* x, const int64_t* ids, int64_t n, int3
   }
   map_rebuild(idx.get(), idx->idmap, idx->L0, n, s);
 
-  if (idx->n_levels == 2) {
-    Store& L1 = idx->L1;
-    L1.d = d;
-    L1.dp = dp;
-    L1.nlist = params->nlist_top;
-    L1.centroids = idx->mem.alloc<float>((size_t)L1.nlist * dp);
-    idx->top_of = idx->mem.alloc<int32_t>(L0.nlist);
-    if (top_centroids && top_of) {
-      // a given level 1 (a saved index): its centroids and the top partition of every level-0 centroid
-      require_finite(idx.get(), top_centroids, L1.nlist * (int64_t)d, "top centroids", s);
-      clear_flag(idx.get(), s);
-      qk::launch_check_range(top_of, L0.nlist, L1.nlist, idx->d_flag, s);
-      QK_CHECK(!flag_set(idx.get(), s), QUAKE_E_INVALID, "top_of holds a partition outside [0, nlist_top)");
-      qk::launch_pad_rows(top_centroids, L1.nlist, d, dp, L1.centroids, nullptr, s);
-      QK_HIP(hipMemcpyAsync(idx->top_of, top_of, L0.nlist * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    } else {
-      kmeans(idx->mem, L0.centroids, L0.nlist, dp, L1.nlist, std::max(params->kmeans_iters, 1),
-             params->seed ^ 0x9e3779b97f4a7c15ull, idx->metric, L1.centroids, s);
-      qk::launch_assign(L0.centroids, L0.nlist, dp, L1.centroids, L1.nlist, idx->metric, idx->top_of, s);
-    }
-    build_store(idx.get(), L1, L0.centroids, dp, nullptr, L0.nlist, idx->top_of, 0.0, QUAKE_F32, true, s);
-  }
+  if (idx->n_levels == 2)
+    build_top_level(idx.get(), params->nlist_top, params->kmeans_iters, params->seed, top_centroids, top_of, s);
 
   idx->h_cap_table.resize(qk::CAP_TABLE_SIZE);
   qk::cap_model_table(d, idx->h_cap_table.data());
@@ -1794,6 +1817,56 @@ int quake_export(const quake_index* cidx, float* centroids, int64_t* ids, int32_
       QK_HIP(hipMemcpyAsync(part, o_part.data(), o_part.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
   }
   QK_HIP(hipStreamSynchronize(s));
+  API_END
+}
+
+int quake_add_level(quake_index* idx, int64_t nlist_top, int32_t kmeans_iters, uint64_t seed, void* stream) {
+  API_BEGIN
+  check_index(idx);
+  QK_CHECK(idx->n_levels == 1, QUAKE_E_STATE, "the index has two levels already (at most two are supported)");
+  QK_CHECK(nlist_top >= 1 && nlist_top <= idx->L0.nlist && kmeans_iters >= 0, QUAKE_E_INVALID,
+           "nlist_top must be in [1, nlist] and kmeans_iters >= 0");
+  hipStream_t s = as_stream(stream);
+  QK_HIP(hipStreamSynchronize(s));
+  try {
+    build_top_level(idx, nlist_top, kmeans_iters, seed, nullptr, nullptr, s);
+  } catch (...) {
+    drop_top_level(idx);
+    throw;
+  }
+  qk::release_graphs(idx);
+  idx->n_levels = 2;
+  API_END
+}
+
+int quake_remove_level(quake_index* idx, void* stream) {
+  API_BEGIN
+  check_index(idx);
+  QK_CHECK(idx->n_levels == 2, QUAKE_E_STATE, "the index has one level");
+  QK_HIP(hipStreamSynchronize(as_stream(stream)));
+  qk::release_graphs(idx);
+  drop_top_level(idx);
+  idx->n_levels = 1;
+  API_END
+}
+
+int quake_adjust_levels(quake_index* idx, int64_t add_above, int64_t remove_below, int64_t nlist_top,
+                        int32_t kmeans_iters, uint64_t seed, void* stream, int32_t* action) {
+  API_BEGIN
+  check_index(idx);
+  QK_CHECK(add_above >= 0 && remove_below >= 0 && nlist_top >= 0, QUAKE_E_INVALID, "negative threshold");
+  if (action) *action = 0;
+  if (idx->n_levels == 1 && add_above > 0 && idx->L0.nlist > add_above) {
+    const int64_t top = nlist_top > 0 ? std::min<int64_t>(nlist_top, idx->L0.nlist)
+                                      : std::max<int64_t>(1, (int64_t)std::llround(std::sqrt((double)idx->L0.nlist)));
+    const int rc = quake_add_level(idx, top, kmeans_iters, seed, stream);
+    if (rc != QUAKE_OK) return rc;
+    if (action) *action = 1;
+  } else if (idx->n_levels == 2 && idx->L1.nlist < remove_below) {
+    const int rc = quake_remove_level(idx, stream);
+    if (rc != QUAKE_OK) return rc;
+    if (action) *action = -1;
+  }
   API_END
 }
 

@@ -31,7 +31,7 @@ EXPORTED = ("quake_build", "quake_search", "quake_search_noalloc", "quake_insert
             "quake_free", "quake_last_error", "quake_autotune", "quake_server_create", "quake_server_search", "quake_server_insert",
             "quake_server_delete", "quake_server_wait", "quake_server_stats", "quake_server_destroy",
             "quake_access_stats", "quake_maintain", "quake_profile_latency", "quake_describe", "quake_save",
-            "quake_load", "quake_insert_attrs")
+            "quake_load", "quake_insert_attrs", "quake_add_level", "quake_remove_level", "quake_adjust_levels")
 PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "scan_sets", "upper")
 
 
@@ -161,6 +161,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.quake_describe.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                                    ctypes.POINTER(i32)]
     lib.quake_save.argtypes = [vp, ctypes.c_char_p, vp]
+    lib.quake_add_level.argtypes = [vp, i64, i32, ctypes.c_uint64, vp]
+    lib.quake_remove_level.argtypes = [vp, vp]
+    lib.quake_adjust_levels.argtypes = [vp, i64, i64, i64, i32, ctypes.c_uint64, vp, ctypes.POINTER(i32)]
     lib.quake_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(Allocator), ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     lib.quake_access_stats.argtypes = [vp, i32, vp, ctypes.POINTER(i64), i32, vp]
     lib.quake_maintain.argtypes = [vp, ctypes.POINTER(MaintainParams), ctypes.POINTER(MaintainReport), vp]
@@ -359,6 +362,23 @@ def quake_describe(handle: int) -> dict:
     inv_m = {v: k for k, v in _METRIC.items()}
     inv_d = {v: k for k, v in _DTYPE.items()}
     return {"d": d.value, "metric": inv_m[metric.value], "storage": inv_d[storage.value], "n_levels": levels.value}
+
+
+def quake_add_level(handle: int, nlist_top: int, kmeans_iters: int = 10, seed: int = 0):
+    _check(load_library().quake_add_level(handle, nlist_top, kmeans_iters, seed, _stream()))
+
+
+def quake_remove_level(handle: int):
+    _check(load_library().quake_remove_level(handle, _stream()))
+
+
+def quake_adjust_levels(handle: int, add_above: int = 0, remove_below: int = 0, nlist_top: int = 0,
+                        kmeans_iters: int = 10, seed: int = 0) -> int:
+    """1 when a level was added, -1 when one was removed, else 0."""
+    action = ctypes.c_int32()
+    _check(load_library().quake_adjust_levels(handle, add_above, remove_below, nlist_top, kmeans_iters, seed,
+                                              _stream(), ctypes.byref(action)))
+    return action.value
 
 
 def quake_save(handle: int, path: str):
@@ -587,6 +607,15 @@ class Index:
 
     def save(self, path):
         quake_save(self.handle, path)
+
+    def add_level(self, nlist_top, kmeans_iters=10, seed=0):
+        quake_add_level(self.handle, nlist_top, kmeans_iters, seed)
+
+    def remove_level(self):
+        quake_remove_level(self.handle)
+
+    def adjust_levels(self, **kw):
+        return quake_adjust_levels(self.handle, **kw)
 
     def describe(self):
         return quake_describe(self.handle)
