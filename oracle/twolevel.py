@@ -1,4 +1,4 @@
-"""Search through a two-level partitioned index (Sec. 3 and Sec. 5).
+"""Search through a two-level (or deeper) partitioned index (Sec. 3 and Sec. 5).
 
 Test infrastructure only (see the package docstring).
 
@@ -68,3 +68,45 @@ def two_level_search(tl: TwoLevelSet, Q: np.ndarray, p: TwoLevelParams, table: C
         r0, r1 = two_level_search_one(tl, Q[i], p, table)
         ids[i], vals[i], m0[i], m1[i] = r0.ids, r0.vals, r0.m, r1.m
     return ids, vals, m0, m1
+
+
+class LevelStack:
+    """Level 0 partitions the vectors; every level l >= 1 partitions the
+    centroids of level l - 1 (Sec. 3).  ``uppers`` lists (assign, centroids)
+    of levels 1, 2, ... from the bottom up."""
+
+    def __init__(self, leaves: PartitionedSet, uppers):
+        self.levels = [leaves]
+        for assign, C in uppers:
+            below = self.levels[-1]
+            self.levels.append(PartitionedSet(below.C, np.arange(below.nlist, dtype=np.int64), assign, C))
+
+
+def multi_level_search_one(ls: LevelStack, q: np.ndarray, p: TwoLevelParams, table: CapTable):
+    """APS at every level from the top down (Sec. 3, Sec. 5), extending the
+    two-level hand-over: the search at level l >= 1 is a k-NN search over the
+    centroids of level l - 1 with k_l = M_{l-1} = ceil(f_M(l-1) N_{l-1})
+    (f_M(0) = p.f_M, the upper fraction above), at the upper recall target;
+    its results, nearest first, are the candidate set of the search below.
+    Only the top level takes its candidates from all of its centroids.
+    Returns the level-0 result and the upper results from the top down."""
+    uppers = []
+    cands = None
+    for l in range(len(ls.levels) - 1, 0, -1):
+        below = ls.levels[l - 1]
+        k_l = candidate_count(p.f_M if l == 1 else p.upper_f_M, below.nlist)
+        prm = APSParams(k=k_l, recall_target=p.upper_recall_target, f_M=p.upper_f_M, tau_rho=p.tau_rho,
+                        metric=p.metric)
+        if cands is None:
+            r = aps_search_one(ls.levels[l], q, prm, table)
+        else:
+            order, h = aps_order(q, ls.levels[l].C, p.upper_f_M, p.metric, cands=cands)
+            r = aps_search_one(ls.levels[l], q, prm, table, order=order, h=h)
+        uppers.append(r)
+        cands = r.ids[r.ids >= 0]
+    lower = APSParams(k=p.k, recall_target=p.recall_target, f_M=p.f_M, tau_rho=p.tau_rho, metric=p.metric)
+    if cands is None:
+        return aps_search_one(ls.levels[0], q, lower, table), uppers
+    order, h = aps_order(q, ls.levels[0].C, p.f_M, p.metric, cands=cands)
+    return aps_search_one(ls.levels[0], q, lower, table, order=order, h=h), uppers
+

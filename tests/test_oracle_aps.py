@@ -216,3 +216,42 @@ def test_two_level_full_upper_equals_single_level():
     gi, _, m0, _ = twolevel.two_level_search(tl, Q, p)
     si, _, sm, _ = aps.aps_search(ps, Q, aps.APSParams(k=10, recall_target=0.9, f_M=0.2))
     assert (gi == si).all() and (m0 == sm).all()
+
+
+def _three_levels():
+    ps, Q = _mixture_index("l2", n=8000, nlist=64)
+    rng = np.random.default_rng(2)
+    C1, _, _ = kmeans.lloyd(ps.C, ps.C[rng.choice(64, 12, replace=False)], 4)
+    a1 = kmeans.assign_nearest(ps.C, C1)
+    C2, _, _ = kmeans.lloyd(C1, C1[rng.choice(12, 3, replace=False)], 4)
+    a2 = kmeans.assign_nearest(C1, C2)
+    return ps, Q, (a1, C1.astype(np.float32)), (a2, C2.astype(np.float32))
+
+
+def test_multi_level_search_of_two_levels_is_the_two_level_search():
+    ps, Q, l1, _ = _three_levels()
+    tl = twolevel.TwoLevelSet(ps, l1[0], l1[1])
+    ls = twolevel.LevelStack(ps, [l1])
+    tab = aps.CapTable(ps.X.shape[1])
+    p = twolevel.TwoLevelParams(k=10, recall_target=0.9, f_M=0.2, upper_recall_target=0.99, upper_f_M=0.5)
+    for q in Q:
+        r0, r1 = twolevel.two_level_search_one(tl, q, p, tab)
+        m0, ups = twolevel.multi_level_search_one(ls, q, p, tab)
+        assert m0.ids.tolist() == r0.ids.tolist() and m0.m == r0.m
+        assert len(ups) == 1 and ups[0].ids.tolist() == r1.ids.tolist()
+
+
+def test_three_levels_with_exact_upper_levels_equal_one_level():
+    """Scanning every upper partition to recall 1 makes every upper search
+    exact, so the level-0 candidates are the M_0 nearest centroids and the
+    search is the one-level search."""
+    ps, Q, l1, l2 = _three_levels()
+    ls = twolevel.LevelStack(ps, [l1, l2])
+    assert [lv.nlist for lv in ls.levels] == [64, 12, 3]
+    tab = aps.CapTable(ps.X.shape[1])
+    p = twolevel.TwoLevelParams(k=10, recall_target=0.9, f_M=0.2, upper_recall_target=1.0, upper_f_M=1.0)
+    si, _, sm, _ = aps.aps_search(ps, Q, aps.APSParams(k=10, recall_target=0.9, f_M=0.2))
+    for i, q in enumerate(Q):
+        r0, ups = twolevel.multi_level_search_one(ls, q, p, tab)
+        assert len(ups) == 2
+        assert r0.ids.tolist() == si[i].tolist() and r0.m == sm[i]
