@@ -226,28 +226,44 @@ int quake_save(quake_index* index, const char* path, void* stream);
 int quake_load(const char* path, const quake_allocator* allocator, size_t hbm_budget_bytes, void* stream,
                quake_index** out);
 
-/* Add a level ("Add Level", Sec. 4.2): partition the level-0 centroids of a
- * one-level index into nlist_top partitions by k-means (kmeans_iters Lloyd
- * iterations, seeded), which become level 1: searches then run the level-1
- * search first and inserts route top-down, as on an index built with two
- * levels.  Errors: STATE (the index has two levels: at most two are
- * supported), INVALID (nlist_top outside [1, nlist]), NOMEM, DEVICE. */
+/* Add a level ("Add Level", Sec. 4.2): partition the centroids of the
+ * current top level into nlist_top partitions by k-means (kmeans_iters Lloyd
+ * iterations, seeded), which become the new top level.  Searches then run
+ * adaptive scanning at every level from the top down, each upper level
+ * returning the candidate set of the level below (M_l = ceil(f_M N_l) with
+ * upper_f_M for levels >= 1, f_M for level 0), and inserts route top-down.
+ * A one-level index becomes two-level as if built so; a two-level one
+ * becomes three-level.  Errors: STATE (three levels: at most three are
+ * supported), INVALID (nlist_top outside [1, top partitions]), NOMEM,
+ * DEVICE. */
 int quake_add_level(quake_index* index, int64_t nlist_top, int32_t kmeans_iters, uint64_t seed, void* stream);
 
-/* Remove the top level ("Remove Level", Sec. 4.2): the level-0 centroids
- * become the top again; level 0 is unchanged.  Errors: STATE (one level). */
+/* Remove the top level ("Remove Level", Sec. 4.2): the centroids of the
+ * level below become the top again; the levels below are unchanged.
+ * Errors: STATE (one level). */
 int quake_remove_level(quake_index* index, void* stream);
 
-/* The level thresholds of Sec. 4.2 ("Adding and Removing Levels"): a
- * one-level index with more than add_above partitions (0: never) gets a
- * level of nlist_top partitions (0: round(sqrt(nlist))); a two-level index
- * whose top level has fewer than remove_below partitions loses it.
+/* The level thresholds of Sec. 4.2 ("Adding and Removing Levels"): an index
+ * of fewer than three levels whose top level has more than add_above
+ * partitions (0: never) gets a new top level of nlist_top partitions (0:
+ * round(sqrt(top partitions))); an index of several levels whose top level
+ * has fewer than remove_below partitions loses it.
  * *action (optional) receives 1 (added), -1 (removed) or 0.  Errors as
  * quake_add_level / quake_remove_level; INVALID for a negative argument. */
 int quake_adjust_levels(quake_index* index, int64_t add_above, int64_t remove_below, int64_t nlist_top,
                         int32_t kmeans_iters, uint64_t seed, void* stream, int32_t* action);
 
-/* Export the level-1 partitioning of a two-level index: top centroids
+/* Export upper level `level` (1 or 2): its centroids [N_level][d] (device
+ * float32) and the partition of every centroid of the level below,
+ * parent[N_{level-1}] (device int32).  Any pointer may be NULL.
+ * Errors: INVALID (no such level). */
+int quake_export_level(const quake_index* index, int32_t level, float* centroids, int32_t* parent, void* stream);
+
+/* Partitions per level: out[0] = N_0, out[1] = N_1 (0 without level 1),
+ * out[2] = N_2 (0 without level 2). */
+int quake_level_sizes(const quake_index* index, int64_t* out);
+
+/* Export the level-1 partitioning of a two- or three-level index: top centroids
  * [nlist_top][d] (device float32) and the top partition of every level-0
  * centroid, top_of[nlist] (device int32). */
 int quake_export_top(const quake_index* index, float* top_centroids, int32_t* top_of, void* stream);

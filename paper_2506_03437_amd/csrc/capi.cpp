@@ -288,7 +288,7 @@ void alloc_store_arrays(quake_index* idx, Store& st, int64_t tiles, int dtype16,
   }
   st.ids = mem.alloc<int64_t>(slots);
   QK_HIP(hipMemsetAsync(st.ids, 0xff, slots * sizeof(int64_t), s));
-  if (idx->labelled && &st != &idx->L1) {
+  if (idx->labelled && &st != &idx->L1 && &st != &idx->L2) {
     st.attr = mem.alloc<uint32_t>(slots);
     QK_HIP(hipMemsetAsync(st.attr, 0, slots * sizeof(uint32_t), s));
   }
@@ -1226,44 +1226,87 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
   idx->prof.collect();
 }
 
-// Level-1 search of a two-level index for queries [0, nq) already in ws.q:
-// the M0 nearest leaf centroids it finds become each query's level-0
-// candidate row in ws.cand0 (count in ws.mq0).
+// int32 buffer of at least `need` entries
+void ensure_i32(quake_index* idx, int32_t*& buf, int64_t& cap, int64_t need) {
+  if (buf && need <= cap) return;
+  idx->mem.release(buf);
+  buf = nullptr;
+  cap = need;
+  buf = idx->mem.alloc<int32_t>(std::max<int64_t>(cap, 1));
+}
+
+// Searches of the upper levels for queries [0, nq) already in ws.q, from the
+// top down (Sec. 3, Sec. 5: APS at every level, the upper levels at a high
+// recall target): the search at level l >= 1 returns the M_{l-1} centroids
+// of level l - 1 that are the candidate set of the search below it, where
+// M_{l-1} = ceil(f_M(l-1) N_{l-1}).  Only the top level scores all of its
+// centroids.  The M0 level-0 candidates of every query end in ws.cand0
+// (count in ws.mq0).
 void upper_level(quake_index* idx, int64_t nq, int M0, const quake_search_params* p, hipStream_t s) {
   const Store& L1 = idx->L1;
-  Job up;
-  up.k = up.kk = M0;
-  up.aps = 1;
-  up.tau_r = p->upper_recall_target > 0 ? p->upper_recall_target : 0.99;
-  up.f_M = p->upper_f_M > 0 ? p->upper_f_M : 0.25;
-  up.tau_rho = p->tau_rho > 0 ? p->tau_rho : 0.01;
-  up.est = p->estimator;
-  up.M = candidate_count(up.f_M, L1.nlist);
-  up.w0 = up.M;  // the upper level is small: scan its candidates in one round
-  up.wmax = up.M;
+  const bool three = idx->n_levels == 3;
+  auto upper_job = [&](int k, const Store& st) {
+    Job up;
+    up.k = up.kk = k;
+    up.aps = 1;
+    up.tau_r = p->upper_recall_target > 0 ? p->upper_recall_target : 0.99;
+    up.f_M = p->upper_f_M > 0 ? p->upper_f_M : 0.25;
+    up.tau_rho = p->tau_rho > 0 ? p->tau_rho : 0.01;
+    up.est = p->estimator;
+    up.M = candidate_count(up.f_M, st.nlist);
+    up.w0 = up.M;  // the upper levels are small: scan their candidates in one round
+    up.wmax = up.M;
+    return up;
+  };
+  Job up1 = upper_job(M0, L1);
+  Job up2;
   qk::Workspace& w = idx->ws;
-  if ((int64_t)M0 * w.nq_cap > w.cand0_cap || !w.cand0) {
-    idx->mem.release(w.cand0);
-    w.cand0 = nullptr;
-    w.cand0_cap = (int64_t)M0 * w.nq_cap;
-    w.cand0 = idx->mem.alloc<int32_t>(w.cand0_cap);
+  if (three) {
+    // level 2 returns the M1 candidates of the level-1 search
+    up2 = upper_job(up1.M, idx->L2);
+    QK_CHECK(up1.M <= qk::KMAX_LARGE, QUAKE_E_INVALID, "the level-2 search returns at most 1024 candidates");
+    up1.given = true;
+    ensure_i32(idx, w.cand1, w.cand1_cap, (int64_t)up1.M * w.nq_cap);
+    ensure_i32(idx, w.mq1, w.mq1_cap, w.nq_cap);
   }
-  // bound the upper level's partial lists (M0 entries each) by running it on
-  // slices of the batch
+  ensure_i32(idx, w.cand0, w.cand0_cap, (int64_t)M0 * w.nq_cap);
+  // bound the upper levels' partial lists by running them on slices of the batch
   const int chunk_tiles = std::min(idx->tune.chunk_tiles > 0 ? idx->tune.chunk_tiles : 16,
                                    qk::SORTED_ITEM_MAX / qk::TILE);
-  const int64_t per_query = (int64_t)up.M * max_chunks(L1, chunk_tiles);
+  int64_t per_query = (int64_t)up1.M * max_chunks(L1, chunk_tiles);
+  if (three) per_query = std::max<int64_t>(per_query, (int64_t)up2.M * max_chunks(idx->L2, chunk_tiles));
   const int64_t slice = std::max<int64_t>(1, std::min<int64_t>(nq, (int64_t)(1 << 17) / std::max<int64_t>(per_query, 1)));
-  struct Only {  // the level-1 work is timed as one kind of its own
+  struct Only {  // the upper levels' work is timed as one kind of its own
     qk::Profiler& p;
     explicit Only(qk::Profiler& p_) : p(p_) { p.only = QUAKE_PROF_UPPER; }
     ~Only() { p.only = -1; }
   } only(idx->prof);
+  // the level-1 search of three levels reads its candidates where a given
+  // search reads them (ws.cand0 / ws.mq0): the two buffers swap for it
+  struct Swap {
+    qk::Workspace& w;
+    bool on = false;
+    void flip() {
+      std::swap(w.cand0, w.cand1);
+      std::swap(w.cand0_cap, w.cand1_cap);
+      std::swap(w.mq0, w.mq1);
+      on = !on;
+    }
+    ~Swap() { if (on) flip(); }
+  } sw{w};
   for (int64_t q0 = 0; q0 < nq; q0 += slice) {
     const int64_t n = std::min(slice, nq - q0);
     QueryWindow win(w, q0, idx->dp);
-    run_search(idx, L1, up, n, nullptr, nullptr, nullptr, nullptr, s);
-    qk::launch_level1_to_candidates(n, M0, up.kk, w.ri, w.cand0 + q0 * M0, w.mq0 + q0, s);
+    if (three) {
+      run_search(idx, idx->L2, up2, n, nullptr, nullptr, nullptr, nullptr, s);
+      qk::launch_level1_to_candidates(n, up1.M, up2.kk, w.ri, w.cand1, w.mq1, s);
+      sw.flip();
+      run_search(idx, L1, up1, n, nullptr, nullptr, nullptr, nullptr, s);
+      sw.flip();
+    } else {
+      run_search(idx, L1, up1, n, nullptr, nullptr, nullptr, nullptr, s);
+    }
+    qk::launch_level1_to_candidates(n, M0, up1.kk, w.ri, w.cand0 + q0 * M0, w.mq0 + q0, s);
   }
 }
 
@@ -1345,47 +1388,50 @@ int quake_cap_table(int32_t d, double* out) {
 
 }  // extern "C"
 
-// Level 1 over the level-0 centroids (Sec. 3; "Add Level", Sec. 4.2): k-means
-// of the centroids into nlist_top partitions, or the given top centroids
-// (device [nlist_top][d]) and top_of (device [nlist]); then the store of
-// the level-0 centroids partitioned by it.
-void build_top_level(quake_index* idx, int64_t nlist_top, int32_t kmeans_iters, uint64_t seed,
-                     const float* top_centroids, const int32_t* top_of, hipStream_t s) {
-  const Store& L0 = idx->L0;
+// Level `level` (1 or 2) over the centroids of the level below (Sec. 3;
+// "Add Level", Sec. 4.2): k-means of those centroids into nlist_top
+// partitions, or the given top centroids (device [nlist_top][d]) and parent
+// of every centroid below (device [N below]); then the store of the
+// centroids below partitioned by it.
+void qk::build_top_level(quake_index* idx, int level, int64_t nlist_top, int32_t kmeans_iters, uint64_t seed,
+                     const float* top_centroids, const int32_t* parent, hipStream_t s) {
+  const Store& below = level == 1 ? idx->L0 : idx->L1;
+  Store& up = level == 1 ? idx->L1 : idx->L2;
+  int32_t*& of = level == 1 ? idx->top_of : idx->top_of2;
   const int d = idx->d, dp = idx->dp;
-  Store& L1 = idx->L1;
-  L1 = Store();
-  L1.d = d;
-  L1.dp = dp;
-  L1.nlist = nlist_top;
-  L1.centroids = idx->mem.alloc<float>((size_t)L1.nlist * dp);
-  idx->top_of = idx->mem.alloc<int32_t>(L0.nlist);
-  if (top_centroids && top_of) {
-    // a given level 1 (a saved index): its centroids and the top partition of every level-0 centroid
-    require_finite(idx, top_centroids, L1.nlist * (int64_t)d, "top centroids", s);
+  up = Store();
+  up.d = d;
+  up.dp = dp;
+  up.nlist = nlist_top;
+  up.centroids = idx->mem.alloc<float>((size_t)up.nlist * dp);
+  of = idx->mem.alloc<int32_t>(below.nlist);
+  if (top_centroids && parent) {
+    // a given level (a saved index): its centroids and the parent of every centroid below
+    require_finite(idx, top_centroids, up.nlist * (int64_t)d, "top centroids", s);
     clear_flag(idx, s);
-    qk::launch_check_range(top_of, L0.nlist, L1.nlist, idx->d_flag, s);
-    QK_CHECK(!flag_set(idx, s), QUAKE_E_INVALID, "top_of holds a partition outside [0, nlist_top)");
-    qk::launch_pad_rows(top_centroids, L1.nlist, d, dp, L1.centroids, nullptr, s);
-    QK_HIP(hipMemcpyAsync(idx->top_of, top_of, L0.nlist * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    qk::launch_check_range(parent, below.nlist, up.nlist, idx->d_flag, s);
+    QK_CHECK(!flag_set(idx, s), QUAKE_E_INVALID, "a parent index lies outside the level above");
+    qk::launch_pad_rows(top_centroids, up.nlist, d, dp, up.centroids, nullptr, s);
+    QK_HIP(hipMemcpyAsync(of, parent, below.nlist * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   } else {
-    kmeans(idx->mem, L0.centroids, L0.nlist, dp, L1.nlist, std::max(kmeans_iters, 1), seed ^ 0x9e3779b97f4a7c15ull,
-           idx->metric, L1.centroids, s);
-    qk::launch_assign(L0.centroids, L0.nlist, dp, L1.centroids, L1.nlist, idx->metric, idx->top_of, s);
+    kmeans(idx->mem, below.centroids, below.nlist, dp, up.nlist, std::max(kmeans_iters, 1),
+           seed ^ 0x9e3779b97f4a7c15ull, idx->metric, up.centroids, s);
+    qk::launch_assign(below.centroids, below.nlist, dp, up.centroids, up.nlist, idx->metric, of, s);
   }
-  build_store(idx, L1, L0.centroids, dp, nullptr, L0.nlist, idx->top_of, 0.0, QUAKE_F32, true, s);
+  build_store(idx, up, below.centroids, dp, nullptr, below.nlist, of, 0.0, QUAKE_F32, true, s);
 }
 
-// Drops level 1 ("Remove Level", Sec. 4.2): the level-0 centroids become the
-// top again.
-void drop_top_level(quake_index* idx) {
-  Store& L1 = idx->L1;
-  for (void* p : {(void*)L1.centroids, (void*)L1.d_off, (void*)L1.d_size, (void*)L1.d_cap, (void*)L1.d_order,
-                  (void*)L1.d_hits, (void*)L1.v32, (void*)L1.v16, (void*)L1.v16n, (void*)L1.rows32, (void*)L1.ids,
-                  (void*)idx->top_of})
+// Drops the top level ("Remove Level", Sec. 4.2): the centroids of the
+// level below become the top again.
+void drop_top_level(quake_index* idx, int level) {
+  Store& up = level == 1 ? idx->L1 : idx->L2;
+  int32_t*& of = level == 1 ? idx->top_of : idx->top_of2;
+  for (void* p : {(void*)up.centroids, (void*)up.d_off, (void*)up.d_size, (void*)up.d_cap, (void*)up.d_order,
+                  (void*)up.d_hits, (void*)up.v32, (void*)up.v16, (void*)up.v16n, (void*)up.rows32, (void*)up.ids,
+                  (void*)of})
     idx->mem.release(p);
-  L1 = Store();
-  idx->top_of = nullptr;
+  up = Store();
+  of = nullptr;
 }
 
 quake_index* qk::build_index(const float* x, const int64_t* ids, int64_t n, int32_t d,
@@ -1484,7 +1530,7 @@ quake_index* qk::build_index(const float* x, const int64_t* ids, int64_t n, int3
   map_rebuild(idx.get(), idx->idmap, idx->L0, n, s);
 
   if (idx->n_levels == 2)
-    build_top_level(idx.get(), params->nlist_top, params->kmeans_iters, params->seed, top_centroids, top_of, s);
+    qk::build_top_level(idx.get(), 1, params->nlist_top, params->kmeans_iters, params->seed, top_centroids, top_of, s);
 
   idx->h_cap_table.resize(qk::CAP_TABLE_SIZE);
   qk::cap_model_table(d, idx->h_cap_table.data());
@@ -1520,8 +1566,8 @@ int quake_search(quake_index* idx, const float* q, int64_t nq, const quake_searc
   clear_flag(idx, s);
   qk::launch_pad_rows(q, nq, idx->d, idx->dp, idx->ws.q, idx->ws.qn2, s, idx->d_flag);
   QK_CHECK(!flag_set(idx, s), QUAKE_E_INVALID, "q holds a non-finite value");
-  if (idx->n_levels == 2) {
-    // level 1 picks the level-0 candidates: M0 = ceil(f_M * N0) nearest leaf
+  if (idx->n_levels >= 2) {
+    // the upper levels pick the level-0 candidates: M0 = ceil(f_M * N0) nearest leaf
     // centroids it finds; nprobe mode takes the nprobe nearest it finds
     const int M0 = job.M;
     QK_CHECK(M0 <= qk::KMAX_LARGE, QUAKE_E_INVALID, "the upper level returns at most 1024 candidates");
@@ -1682,7 +1728,7 @@ int quake_candidates(quake_index* idx, const float* q, int64_t nq, const quake_s
   clear_flag(idx, s);
   qk::launch_pad_rows(q, nq, idx->d, idx->dp, w.q, w.qn2, s, idx->d_flag);
   QK_CHECK(!flag_set(idx, s), QUAKE_E_INVALID, "q holds a non-finite value");
-  if (idx->n_levels == 2) {
+  if (idx->n_levels >= 2) {
     upper_level(idx, nq, M, params, s);
     ensure_workspace(idx, st.nlist, M, 1, 1, 0, 0, false);
     QK_HIP(hipMemcpyAsync(w.mq, w.mq0, nq * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
@@ -1708,9 +1754,9 @@ static void insert_api(quake_index* idx, const float* x, const int64_t* ids, con
   hipStream_t s = as_stream(stream);
   require_finite(idx, x, n * (int64_t)idx->d, "x", s);
   std::vector<int32_t> routed;
-  if (idx->n_levels == 2) {
-    // top-down: the nearest top partition, then its nearest leaf (a level-1
-    // search with one candidate and one result)
+  if (idx->n_levels >= 2) {
+    // top-down: the nearest top partition, then its nearest member at each
+    // level below (searches with one candidate and one result)
     std::unique_ptr<Tmp<float>> xpad_buf;
     const float* xpad = x;
     if (idx->dp != idx->d) {
@@ -1724,7 +1770,17 @@ static void insert_api(quake_index* idx, const float* x, const int64_t* ids, con
     route.count = false;
     route.k = route.kk = 1;
     route.M = route.w0 = route.wmax = 1;
-    run_search(idx, idx->L1, route, n, nullptr, nullptr, nullptr, nullptr, s);
+    if (idx->n_levels == 3) {
+      qk::Workspace& w = idx->ws;
+      run_search(idx, idx->L2, route, n, nullptr, nullptr, nullptr, nullptr, s);
+      ensure_i32(idx, w.cand0, w.cand0_cap, std::max<int64_t>(n, w.nq_cap));
+      qk::launch_level1_to_candidates(n, 1, 1, w.ri, w.cand0, w.mq0, s);
+      Job r1 = route;
+      r1.given = true;
+      run_search(idx, idx->L1, r1, n, nullptr, nullptr, nullptr, nullptr, s);
+    } else {
+      run_search(idx, idx->L1, route, n, nullptr, nullptr, nullptr, nullptr, s);
+    }
     std::vector<int64_t> leaf(n);
     QK_HIP(hipMemcpyAsync(leaf.data(), idx->ws.ri, n * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     QK_HIP(hipStreamSynchronize(s));
@@ -1823,30 +1879,32 @@ int quake_export(const quake_index* cidx, float* centroids, int64_t* ids, int32_
 int quake_add_level(quake_index* idx, int64_t nlist_top, int32_t kmeans_iters, uint64_t seed, void* stream) {
   API_BEGIN
   check_index(idx);
-  QK_CHECK(idx->n_levels == 1, QUAKE_E_STATE, "the index has two levels already (at most two are supported)");
-  QK_CHECK(nlist_top >= 1 && nlist_top <= idx->L0.nlist && kmeans_iters >= 0, QUAKE_E_INVALID,
-           "nlist_top must be in [1, nlist] and kmeans_iters >= 0");
+  QK_CHECK(idx->n_levels < 3, QUAKE_E_STATE, "the index has three levels already (at most three are supported)");
+  const Store& top = idx->n_levels == 1 ? idx->L0 : idx->L1;
+  QK_CHECK(nlist_top >= 1 && nlist_top <= top.nlist && kmeans_iters >= 0, QUAKE_E_INVALID,
+           "nlist_top must be in [1, partitions of the current top level] and kmeans_iters >= 0");
   hipStream_t s = as_stream(stream);
   QK_HIP(hipStreamSynchronize(s));
+  const int level = idx->n_levels;
   try {
-    build_top_level(idx, nlist_top, kmeans_iters, seed, nullptr, nullptr, s);
+    qk::build_top_level(idx, level, nlist_top, kmeans_iters, seed, nullptr, nullptr, s);
   } catch (...) {
-    drop_top_level(idx);
+    drop_top_level(idx, level);
     throw;
   }
   qk::release_graphs(idx);
-  idx->n_levels = 2;
+  idx->n_levels = level + 1;
   API_END
 }
 
 int quake_remove_level(quake_index* idx, void* stream) {
   API_BEGIN
   check_index(idx);
-  QK_CHECK(idx->n_levels == 2, QUAKE_E_STATE, "the index has one level");
+  QK_CHECK(idx->n_levels >= 2, QUAKE_E_STATE, "the index has one level");
   QK_HIP(hipStreamSynchronize(as_stream(stream)));
   qk::release_graphs(idx);
-  drop_top_level(idx);
-  idx->n_levels = 1;
+  drop_top_level(idx, idx->n_levels - 1);
+  idx->n_levels -= 1;
   API_END
 }
 
@@ -1856,13 +1914,14 @@ int quake_adjust_levels(quake_index* idx, int64_t add_above, int64_t remove_belo
   check_index(idx);
   QK_CHECK(add_above >= 0 && remove_below >= 0 && nlist_top >= 0, QUAKE_E_INVALID, "negative threshold");
   if (action) *action = 0;
-  if (idx->n_levels == 1 && add_above > 0 && idx->L0.nlist > add_above) {
-    const int64_t top = nlist_top > 0 ? std::min<int64_t>(nlist_top, idx->L0.nlist)
-                                      : std::max<int64_t>(1, (int64_t)std::llround(std::sqrt((double)idx->L0.nlist)));
-    const int rc = quake_add_level(idx, top, kmeans_iters, seed, stream);
+  const int64_t top = idx->n_levels == 1 ? idx->L0.nlist : idx->n_levels == 2 ? idx->L1.nlist : idx->L2.nlist;
+  if (idx->n_levels < 3 && add_above > 0 && top > add_above) {
+    const int64_t n = nlist_top > 0 ? std::min<int64_t>(nlist_top, top)
+                                    : std::max<int64_t>(1, (int64_t)std::llround(std::sqrt((double)top)));
+    const int rc = quake_add_level(idx, n, kmeans_iters, seed, stream);
     if (rc != QUAKE_OK) return rc;
     if (action) *action = 1;
-  } else if (idx->n_levels == 2 && idx->L1.nlist < remove_below) {
+  } else if (idx->n_levels >= 2 && top < remove_below) {
     const int rc = quake_remove_level(idx, stream);
     if (rc != QUAKE_OK) return rc;
     if (action) *action = -1;
@@ -1870,10 +1929,36 @@ int quake_adjust_levels(quake_index* idx, int64_t add_above, int64_t remove_belo
   API_END
 }
 
+int quake_export_level(const quake_index* idx, int32_t level, float* centroids, int32_t* parent, void* stream) {
+  API_BEGIN
+  check_index(idx);
+  QK_CHECK(level >= 1 && level < idx->n_levels, QUAKE_E_INVALID, "no such upper level");
+  hipStream_t s = as_stream(stream);
+  const Store& up = level == 1 ? idx->L1 : idx->L2;
+  const Store& below = level == 1 ? idx->L0 : idx->L1;
+  const int32_t* of = level == 1 ? idx->top_of : idx->top_of2;
+  if (centroids)
+    QK_HIP(hipMemcpy2DAsync(centroids, idx->d * sizeof(float), up.centroids, idx->dp * sizeof(float),
+                            idx->d * sizeof(float), up.nlist, hipMemcpyDeviceToDevice, s));
+  if (parent) QK_HIP(hipMemcpyAsync(parent, of, below.nlist * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  QK_HIP(hipStreamSynchronize(s));
+  API_END
+}
+
+int quake_level_sizes(const quake_index* idx, int64_t* nlist_per_level) {
+  API_BEGIN
+  check_index(idx);
+  QK_CHECK(nlist_per_level, QUAKE_E_INVALID, "output is NULL");
+  nlist_per_level[0] = idx->L0.nlist;
+  nlist_per_level[1] = idx->n_levels >= 2 ? idx->L1.nlist : 0;
+  nlist_per_level[2] = idx->n_levels >= 3 ? idx->L2.nlist : 0;
+  API_END
+}
+
 int quake_export_top(const quake_index* idx, float* top_centroids, int32_t* top_of, void* stream) {
   API_BEGIN
   check_index(idx);
-  QK_CHECK(idx->n_levels == 2, QUAKE_E_STATE, "index has one level");
+  QK_CHECK(idx->n_levels >= 2, QUAKE_E_STATE, "index has one level");
   hipStream_t s = as_stream(stream);
   if (top_centroids)
     QK_HIP(hipMemcpy2DAsync(top_centroids, idx->d * sizeof(float), idx->L1.centroids, idx->dp * sizeof(float),

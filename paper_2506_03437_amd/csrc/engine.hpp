@@ -82,6 +82,10 @@ void delete_rows(quake_index* idx, Store& st, IdMap& map, const int64_t* ids, in
 quake_index* build_index(const float* x, const int64_t* ids, int64_t n, int32_t d, const quake_build_params* params,
                          const float* top_centroids, const int32_t* top_of, const quake_allocator* allocator,
                          hipStream_t s);
+// Level `level` (1 or 2) over the centroids of the level below: k-means, or
+// the given top centroids and parent of every centroid below (capi.cpp).
+void build_top_level(quake_index* idx, int level, int64_t nlist_top, int32_t kmeans_iters, uint64_t seed,
+                     const float* top_centroids, const int32_t* parent, hipStream_t s);
 // The maintenance pass behind quake_maintain (maintain.cpp).
 void maintain(quake_index* idx, const quake_maintain_params& p, quake_maintain_report* report, hipStream_t s);
 

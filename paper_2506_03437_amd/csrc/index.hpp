@@ -122,6 +122,9 @@ struct Workspace {
   int32_t* cand0 = nullptr;     // [nq][M0] level-0 candidates found by the level-1 search
   int32_t* mq0 = nullptr;       // [nq] their number
   int64_t cand0_cap = 0;
+  int32_t* cand1 = nullptr;     // [nq][M1] level-1 candidates found by the level-2 search (three levels)
+  int32_t* mq1 = nullptr;       // [nq] their number
+  int64_t cand1_cap = 0, mq1_cap = 0;
   float* h = nullptr;           // [nq][M] bisector distances in scan order
   int32_t* st_m = nullptr;      // committed partitions
   int32_t* st_w = nullptr;      // window the query asks for in the next round
@@ -209,9 +212,11 @@ struct quake_index {
   int32_t d = 0, dp = 0;
   qk::DeviceMemory mem;
   qk::Store L0;                 // level 0: the vectors
-  qk::Store L1;                 // level 1 (two-level): the level-0 centroids
+  qk::Store L1;                 // level 1 (two or three levels): the level-0 centroids
+  qk::Store L2;                 // level 2 (three levels): the level-1 centroids
   qk::IdMap idmap;              // level-0 ids
   int32_t* top_of = nullptr;    // [L0.nlist] level-1 partition of each level-0 centroid
+  int32_t* top_of2 = nullptr;   // [L1.nlist] level-2 partition of each level-1 centroid
   double* cap_table = nullptr;  // [1024] device copy of the recall model table
   uint32_t* d_flag = nullptr;   // input checks: set by kernels that find a bad value
   uint32_t* h_flag = nullptr;   // pinned host mirror

@@ -720,8 +720,8 @@ int quake_access_stats(quake_index* index, int32_t level, int64_t* hits, int64_t
                        void* stream) {
   return qk::run_api([&] {
     QK_CHECK(index && index->magic == 0x51554b45u, QUAKE_E_STATE, "invalid or freed index handle");
-    QK_CHECK(level == 0 || (level == 1 && index->n_levels == 2), QUAKE_E_INVALID, "no such level");
-    qk::Store& st = level == 0 ? index->L0 : index->L1;
+    QK_CHECK(level >= 0 && level < index->n_levels, QUAKE_E_INVALID, "no such level");
+    qk::Store& st = level == 0 ? index->L0 : level == 1 ? index->L1 : index->L2;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     if (hits) {
       std::vector<uint32_t> h(st.nlist);

@@ -38,7 +38,7 @@ struct FileHeader {
   int64_t nlist, nlist_top, n_live, window;
   double capacity_slack;
   quake_tuning tune;
-  uint8_t pad[128 - 8 - 8 - 24 - 32 - 8 - sizeof(quake_tuning)];
+  int64_t nlist_top2;  // level-2 partitions of a three-level index, else 0
 };
 static_assert(sizeof(FileHeader) == 128, "file header is 128 bytes");
 
@@ -146,7 +146,8 @@ void save(quake_index* idx, const char* path, hipStream_t s) {
   hd.drop_f32_tiles = st.v32 ? 0 : 1;
   hd.labelled = st.attr ? 1 : 0;
   hd.nlist = st.nlist;
-  hd.nlist_top = idx->n_levels == 2 ? idx->L1.nlist : 0;
+  hd.nlist_top = idx->n_levels >= 2 ? idx->L1.nlist : 0;
+  hd.nlist_top2 = idx->n_levels >= 3 ? idx->L2.nlist : 0;
   hd.n_live = n;
   hd.window = st.window;
   hd.capacity_slack = idx->slack;
@@ -164,13 +165,16 @@ void save(quake_index* idx, const char* path, hipStream_t s) {
   QK_HIP(hipMemcpyAsync(hits.data(), st.d_hits, st.nlist * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   QK_HIP(hipStreamSynchronize(s));
   w.put(hits.data(), hits.size() * sizeof(uint32_t));
-  if (idx->n_levels == 2) {
-    const std::vector<float> C1 = strip_rows(idx->L1.centroids, idx->L1.nlist, d, dp, s);
-    w.put(C1.data(), C1.size() * sizeof(float));
-    std::vector<int32_t> top(st.nlist);
-    QK_HIP(hipMemcpyAsync(top.data(), idx->top_of, st.nlist * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  for (int level = 1; level < idx->n_levels; ++level) {
+    const Store& up = level == 1 ? idx->L1 : idx->L2;
+    const int64_t nbelow = level == 1 ? st.nlist : idx->L1.nlist;
+    const std::vector<float> C = strip_rows(up.centroids, up.nlist, d, dp, s);
+    w.put(C.data(), C.size() * sizeof(float));
+    std::vector<int32_t> parent(nbelow);
+    QK_HIP(hipMemcpyAsync(parent.data(), level == 1 ? idx->top_of : idx->top_of2, nbelow * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, s));
     QK_HIP(hipStreamSynchronize(s));
-    w.put(top.data(), top.size() * sizeof(int32_t));
+    w.put(parent.data(), parent.size() * sizeof(int32_t));
   }
   w.put(ids.data(), ids.size() * sizeof(int64_t));
   w.put(part.data(), part.size() * sizeof(int32_t));
@@ -207,7 +211,8 @@ quake_index* load(const char* path, const quake_allocator* allocator, size_t hbm
   QK_CHECK(hd.version == kVersion && hd.header_bytes == sizeof(FileHeader), QUAKE_E_INVALID,
            "unsupported file version");
   QK_CHECK(hd.d >= 1 && hd.d <= MAX_DIM && hd.nlist >= 1 && hd.nlist <= INT32_MAX && hd.n_live >= 1 &&
-               (hd.n_levels == 1 || (hd.n_levels == 2 && hd.nlist_top >= 1 && hd.nlist_top <= hd.nlist)) &&
+               (hd.n_levels == 1 || (hd.n_levels >= 2 && hd.n_levels <= 3 && hd.nlist_top >= 1 && hd.nlist_top <= hd.nlist)) &&
+               (hd.n_levels == 3 ? hd.nlist_top2 >= 1 && hd.nlist_top2 <= hd.nlist_top : hd.nlist_top2 == 0) &&
                hd.capacity_slack >= 0 && hd.window >= 0 && (hd.labelled == 0 || hd.labelled == 1),
            QUAKE_E_INVALID, "corrupt header");
   const int d = hd.d;
@@ -229,13 +234,19 @@ quake_index* load(const char* path, const quake_allocator* allocator, size_t hbm
   to_device(C0.p, (size_t)N * d * sizeof(float));
   std::vector<uint32_t> hits(N);
   r.get(hits.data(), N * sizeof(uint32_t));
-  std::unique_ptr<Buf<float>> C1;
-  std::unique_ptr<Buf<int32_t>> top;
-  if (hd.n_levels == 2) {
+  std::unique_ptr<Buf<float>> C1, C2;
+  std::unique_ptr<Buf<int32_t>> top, top2;
+  if (hd.n_levels >= 2) {
     C1.reset(new Buf<float>(tmp, (size_t)hd.nlist_top * d));
     to_device(C1->p, (size_t)hd.nlist_top * d * sizeof(float));
     top.reset(new Buf<int32_t>(tmp, N));
     to_device(top->p, N * sizeof(int32_t));
+  }
+  if (hd.n_levels == 3) {
+    C2.reset(new Buf<float>(tmp, (size_t)hd.nlist_top2 * d));
+    to_device(C2->p, (size_t)hd.nlist_top2 * d * sizeof(float));
+    top2.reset(new Buf<int32_t>(tmp, hd.nlist_top));
+    to_device(top2->p, hd.nlist_top * sizeof(int32_t));
   }
   Buf<int64_t> ids(tmp, n);
   to_device(ids.p, n * sizeof(int64_t));
@@ -257,7 +268,7 @@ quake_index* load(const char* path, const quake_allocator* allocator, size_t hbm
   quake_build_params bp{};
   bp.metric = hd.metric;
   bp.storage_dtype = hd.storage;
-  bp.n_levels = hd.n_levels;
+  bp.n_levels = hd.n_levels >= 2 ? 2 : 1;
   bp.nlist = N;
   bp.nlist_top = hd.nlist_top;
   bp.centroids = C0.p;
@@ -268,6 +279,10 @@ quake_index* load(const char* path, const quake_allocator* allocator, size_t hbm
   bp.attrs = attr ? attr->p : nullptr;
   std::unique_ptr<quake_index> idx(
       build_index(x.p, ids.p, n, d, &bp, C1 ? C1->p : nullptr, top ? top->p : nullptr, allocator, s));
+  if (hd.n_levels == 3) {
+    build_top_level(idx.get(), 2, hd.nlist_top2, 0, 0, C2->p, top2->p, s);
+    idx->n_levels = 3;
+  }
   QK_HIP(hipMemcpyAsync(idx->L0.d_hits, hits.data(), N * sizeof(uint32_t), hipMemcpyHostToDevice, s));
   QK_HIP(hipStreamSynchronize(s));
   idx->L0.window = hd.window;

@@ -31,7 +31,8 @@ EXPORTED = ("quake_build", "quake_search", "quake_search_noalloc", "quake_insert
             "quake_free", "quake_last_error", "quake_autotune", "quake_server_create", "quake_server_search", "quake_server_insert",
             "quake_server_delete", "quake_server_wait", "quake_server_stats", "quake_server_destroy",
             "quake_access_stats", "quake_maintain", "quake_profile_latency", "quake_describe", "quake_save",
-            "quake_load", "quake_insert_attrs", "quake_add_level", "quake_remove_level", "quake_adjust_levels")
+            "quake_load", "quake_insert_attrs", "quake_add_level", "quake_remove_level", "quake_adjust_levels",
+            "quake_export_level", "quake_level_sizes")
 PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "scan_sets", "upper")
 
 
@@ -162,6 +163,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                                    ctypes.POINTER(i32)]
     lib.quake_save.argtypes = [vp, ctypes.c_char_p, vp]
     lib.quake_add_level.argtypes = [vp, i64, i32, ctypes.c_uint64, vp]
+    lib.quake_export_level.argtypes = [vp, i32, vp, vp, vp]
+    lib.quake_level_sizes.argtypes = [vp, ctypes.POINTER(i64)]
     lib.quake_remove_level.argtypes = [vp, vp]
     lib.quake_adjust_levels.argtypes = [vp, i64, i64, i64, i32, ctypes.c_uint64, vp, ctypes.POINTER(i32)]
     lib.quake_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(Allocator), ctypes.c_size_t, vp, ctypes.POINTER(vp)]
@@ -366,6 +369,23 @@ def quake_describe(handle: int) -> dict:
 
 def quake_add_level(handle: int, nlist_top: int, kmeans_iters: int = 10, seed: int = 0):
     _check(load_library().quake_add_level(handle, nlist_top, kmeans_iters, seed, _stream()))
+
+
+def quake_level_sizes(handle: int) -> list:
+    out = (ctypes.c_int64 * 3)()
+    _check(load_library().quake_level_sizes(handle, out))
+    return [int(v) for v in out]
+
+
+def quake_export_level(handle: int, level: int, d: int):
+    """(centroids f32 [N_level, d], parent int32 [N_{level-1}]) of upper level `level`."""
+    import torch
+    sizes = quake_level_sizes(handle)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    C = torch.empty((max(sizes[level], 1), d), dtype=torch.float32, device=dev)
+    parent = torch.empty((max(sizes[level - 1], 1),), dtype=torch.int32, device=dev)
+    _check(load_library().quake_export_level(handle, level, _ptr(C), _ptr(parent), _stream()))
+    return C[: sizes[level]], parent[: sizes[level - 1]]
 
 
 def quake_remove_level(handle: int):
@@ -607,6 +627,12 @@ class Index:
 
     def save(self, path):
         quake_save(self.handle, path)
+
+    def level_sizes(self):
+        return quake_level_sizes(self.handle)
+
+    def export_level(self, level):
+        return quake_export_level(self.handle, level, self.d)
 
     def add_level(self, nlist_top, kmeans_iters=10, seed=0):
         quake_add_level(self.handle, nlist_top, kmeans_iters, seed)
