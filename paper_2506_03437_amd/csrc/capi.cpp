@@ -760,8 +760,8 @@ Job resolve(const quake_index* idx, const Store& st, const quake_search_params* 
   r.f_M = p->f_M > 0 ? p->f_M : 0.05;
   r.tau_rho = p->tau_rho > 0 ? p->tau_rho : 0.01;
   r.est = p->estimator;
-  QK_CHECK(!p->filter || (st.attr && idx->n_levels == 1 && !r.batched && r.kk <= qk::KMAX), QUAKE_E_INVALID,
-           "a filtered search needs a labelled one-level index and the plain FP32 scan");
+  QK_CHECK(!p->filter || (st.attr && idx->n_levels == 1 && r.kk <= qk::KMAX), QUAKE_E_INVALID,
+           "a filtered search needs a labelled one-level index");
   r.filter = p->filter;
   const int64_t N = st.nlist;
   const int64_t cap_m = N > 4096 ? 2048 : qk::MAX_CANDIDATES;

@@ -287,13 +287,16 @@ __device__ __forceinline__ f32x4 mfma16(u32x4 a, u32x4 b, f32x4 c) {
                                                     0, 0, 0);
 }
 
-template <int F16, int KS, int IP>
+// FILT: a filtered search - a row is a candidate only when its label bits
+// (attr, by slot) share a bit with its query's mask (qmask, by query).
+template <int F16, int KS, int IP, int FILT>
 __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
     int64_t* __restrict__ counters, const int4* __restrict__ bitems, const int32_t* __restrict__ sorted_q,
     const int64_t* __restrict__ sorted_base, int chunk_tiles, const uint16_t* __restrict__ q16, int dp16,
     const float* __restrict__ qn2f, const uint16_t* __restrict__ v16, const float* __restrict__ v16n,
     const int64_t* __restrict__ sid, const float* __restrict__ rk, const int64_t* __restrict__ ri, int kk,
-    float* __restrict__ pk, int64_t* __restrict__ pi, const int64_t* __restrict__ xitem) {
+    float* __restrict__ pk, int64_t* __restrict__ pi, const int64_t* __restrict__ xitem,
+    const uint32_t* __restrict__ attr, const uint32_t* __restrict__ qmask) {
   // k-steps per stage: 4 (two for each wave of a pair), else 2 or 1 where
   // that leaves an odd number of stages per tile (a tile always starts in
   // LDS buffer 0; with 1 the pair takes alternate stages); the two stages,
@@ -378,6 +381,8 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
     const bool has = j < gcount;
     const int pidx = has ? pfirst + g * G + j : pfirst;  // a valid pair in every lane
     const int qj = sorted_q[pidx];
+    uint32_t qm = 0;
+    if constexpr (FILT) qm = qmask[qj];
     // the partner wave's query in this lane's column (row 0 when absent)
     const int gp = g ^ 1;
     const int qp = sorted_q[j < max(0, min(G, np - gp * G)) ? pfirst + gp * G + j : pfirst];
@@ -576,10 +581,12 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
     // tile, never used).
     int64_t next_id;
     float next_xn = 0.f;
+    uint32_t next_attr = 0;
     {
       const int64_t tn = (U > 0 ? tile0 + t0 : 0) * TILE + lane;
       next_id = sid[tn];
       if (!IP) next_xn = v16n[tn];
+      if constexpr (FILT) next_attr = attr[tn];
     }
     for (int tb = t0; tb < t1; tb += TA) {
 #pragma unroll
@@ -590,10 +597,12 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
       // next tile's are requested now (the last tile requests itself again)
       const int64_t tile_id = next_id;
       const float tile_xn = next_xn;
+      const uint32_t tile_attr = next_attr;
       {
         const int64_t tn = (tile0 + min(t + 1, t1 - 1)) * TILE + lane;
         next_id = sid[tn];
         if (!IP) next_xn = v16n[tn];
+        if constexpr (FILT) next_attr = attr[tn];
       }
 #pragma unroll
       for (int st = 0; st < NS; ++st) {
@@ -658,6 +667,16 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
         uint32_t lm = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) lm |= (uint32_t)((live >> (16 * b + 4 * g4)) & 0xfull) << (4 * b);
+        if constexpr (FILT) {
+          // rows whose labels miss the query's mask are never candidates
+          uint32_t fm = 0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              fm |= ((__shfl(tile_attr, 16 * b + 4 * g4 + v) & qm) != 0u ? 1u : 0u) << (4 * b + v);
+          lm &= fm;
+        }
         if (!has) lm = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b)
@@ -761,13 +780,13 @@ __global__ __launch_bounds__(NT, 1) void k_scan_mfma(
   }
 }
 
-template <int F16, int IP>
+template <int F16, int IP, int FILT>
 static void scan_mfma_k(Workspace& ws, const Store& st, const RoundArgs& a, int blocks, hipStream_t s) {
   const int ks = st.dp16 / 32;
 #define QK_MFMA_LAUNCH(KS)                                                                                      \
-  hipLaunchKernelGGL((k_scan_mfma<F16, KS, IP>), dim3(blocks), dim3(NT), 0, s, ws.total, ws.bitems,           \
+  hipLaunchKernelGGL((k_scan_mfma<F16, KS, IP, FILT>), dim3(blocks), dim3(NT), 0, s, ws.total, ws.bitems,     \
                      ws.sorted_q, ws.sorted_base, a.chunk_tiles, ws.q16, st.dp16, ws.qn2f, st.v16, st.v16n, st.ids, \
-                     ws.rk, ws.ri, a.kk, ws.pk, ws.pi, ws.xitem)
+                     ws.rk, ws.ri, a.kk, ws.pk, ws.pi, ws.xitem, a.attr, a.qmask)
   switch (ks) {
     case 2: QK_MFMA_LAUNCH(2); break;
     case 4: QK_MFMA_LAUNCH(4); break;
@@ -785,8 +804,13 @@ void launch_scan_mfma(Workspace& ws, const Store& st, const RoundArgs& a, int dt
   const int blocks = std::max(a.blocks, 1);
   const bool f16 = dtype16 == QUAKE_F16;
   const bool ip = a.metric == QUAKE_IP;
-  if (f16) { if (ip) scan_mfma_k<1, 1>(ws, st, a, blocks, s); else scan_mfma_k<1, 0>(ws, st, a, blocks, s); }
-  else { if (ip) scan_mfma_k<0, 1>(ws, st, a, blocks, s); else scan_mfma_k<0, 0>(ws, st, a, blocks, s); }
+  if (a.qmask) {
+    if (f16) { if (ip) scan_mfma_k<1, 1, 1>(ws, st, a, blocks, s); else scan_mfma_k<1, 0, 1>(ws, st, a, blocks, s); }
+    else { if (ip) scan_mfma_k<0, 1, 1>(ws, st, a, blocks, s); else scan_mfma_k<0, 0, 1>(ws, st, a, blocks, s); }
+  } else {
+    if (f16) { if (ip) scan_mfma_k<1, 1, 0>(ws, st, a, blocks, s); else scan_mfma_k<1, 0, 0>(ws, st, a, blocks, s); }
+    else { if (ip) scan_mfma_k<0, 1, 0>(ws, st, a, blocks, s); else scan_mfma_k<0, 0, 0>(ws, st, a, blocks, s); }
+  }
 }
 
 // ---------------------------------------------------------------- store norms

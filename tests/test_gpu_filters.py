@@ -8,7 +8,8 @@ and recall estimates replay the oracle's filtered search query by query
 row, where it is the per-bit upper bound), also after inserts and deletes
 and after a save and load.  A mask that every row passes gives the
 unfiltered search; a fixed nprobe gives the filtered top-k of those
-partitions.  Unsupported combinations are refused.
+partitions; the batched scan filters as the plain one does.  Unsupported
+combinations are refused.
 """
 
 import numpy as np
@@ -128,6 +129,31 @@ def test_updates_and_save_load_keep_labels(tmp_path):
     idx.free()
 
 
+@pytest.mark.parametrize("metric", ["l2", "ip"])
+def test_batched_filtered_on_integer_data(metric):
+    """Small-integer rows: BF16 holds them exactly, so the batched scan's
+    filtered decisions replay the oracle's and equal the plain path's."""
+    rng = np.random.default_rng(34)
+    centres = rng.integers(-3, 4, (12, 64))
+    comp = rng.integers(0, 12, 20_000)
+    X = np.clip(centres[comp] + rng.integers(-1, 2, (20_000, 64)), -4, 4).astype(np.float32)
+    Q = (centres[rng.integers(0, 12, 256)] + rng.integers(-1, 2, (256, 64))).astype(np.float32)
+    attr = (np.uint32(1) << np.where(rng.random(20_000) < 0.7, comp % 8, rng.integers(0, 8, 20_000))
+            .astype(np.uint32)).astype(np.uint32)
+    masks = (np.uint32(1) << rng.integers(0, 8, 256).astype(np.uint32)).astype(np.uint32)
+    print(f"[build] labelled integer data {metric} bf16", flush=True)
+    idx = gu.build(X, metric=metric, nlist=40, storage="bf16", kmeans_iters=4, seed=2, attrs=_i32(attr))
+    ps = gu.oracle_view(idx, X)
+    kw = dict(k=10, recall_target=0.9, f_M=0.3, filter=_i32(masks))
+    gi, gv, ns, rec = gu.search(idx, Q, scan_mode="batched", scan_dtype="bf16", **kw)
+    order, h = idx.candidates(gu.to_dev(Q), 0.3)
+    parity.check_aps(X, Q, ps, gi, gv, ns, rec, order.cpu().numpy(), h.cpu().numpy(), metric, 0.3, 0.9, 10,
+                     attr=attr, masks=masks)
+    fi, fv, fns, frec = gu.search(idx, Q, **kw)
+    assert (fns == ns).all() and (fi == gi).all()
+    idx.free()
+
+
 def test_unsupported_combinations_are_refused():
     from paper_2506_03437_amd import quake
     spec = synth.MixtureSpec(key=53, n=5_000, d=16, n_components=10)
@@ -143,7 +169,6 @@ def test_unsupported_combinations_are_refused():
     i1 = gu.to_dev(np.array([10 ** 7, 10 ** 7 + 1], dtype=np.int64))
     for call in (
         lambda: gu.search(plain, Q, k=10, recall_target=0.9, filter=m),                 # no labels
-        lambda: gu.search(lab, Q, k=10, recall_target=0.9, filter=m, scan_mode="batched", scan_dtype="f16"),
         lambda: lab.insert(x1, i1),                                                       # labels missing
         lambda: plain.insert(x1, i1, attrs=_i32(np.ones(2, dtype=np.uint32))),            # index has none
     ):
