@@ -335,7 +335,7 @@ typedef struct {
   int64_t vectors_moved; /* vectors that changed partition (splits, refinement, deletes) */
 } quake_maintain_report;
 
-/* One maintenance pass over level 0 of a one-level index (Sec. 4.2, Stages
+/* One maintenance pass over level 0 (Sec. 4.2, Stages
  * 1-3), with lambda interpolated linearly between the profiled sizes
  * (extended linearly past the ends) and the centroid overhead
  * dO+/- = lambda(N +/- 1) - lambda(N):
@@ -354,12 +354,15 @@ typedef struct {
  *      centroid, verify with the actual receivers (frequency following the
  *      vectors) and commit below -tau;
  *   4. renumber the surviving partitions in their old order, and clear the
- *      access statistics.
+ *      access statistics;
+ *   5. with upper levels, rebuild level 1 over the new level-0 centroids,
+ *      each in its nearest level-1 partition (level-1 centroids do not move,
+ *      so higher levels are unchanged): the changes propagate upward.
  * Vectors that change partition move with all their copies; ids are kept.
  * Decisions are taken in partition order, every estimate against the index
  * as the earlier steps of the pass left it, with the centroid overhead taken
  * at the partition count before the pass.  Errors: INVALID for bad
- * parameters, STATE on a two-level index (not supported). */
+ * parameters. */
 int quake_maintain(quake_index* index, const quake_maintain_params* params, quake_maintain_report* report,
                    void* stream);
 

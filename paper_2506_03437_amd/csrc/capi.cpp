@@ -1434,6 +1434,32 @@ void drop_top_level(quake_index* idx, int level) {
   of = nullptr;
 }
 
+// After level 0's partitions change (maintenance), the level-1 store is
+// rebuilt over the new level-0 centroids, each in its nearest level-1
+// partition: a split's new centroid joins the level above and a deleted one
+// leaves it (Sec. 4.2, "Decision Workflow", changes propagate upward).
+// Level-1 centroids do not move, so the levels above are unchanged.
+void qk::rebuild_level1(quake_index* idx, hipStream_t s) {
+  const int d = idx->d, dp = idx->dp;
+  const int64_t n1 = idx->L1.nlist;
+  Tmp<float> C1(idx->mem, (size_t)n1 * d);
+  QK_HIP(hipMemcpy2DAsync(C1.p, d * sizeof(float), idx->L1.centroids, dp * sizeof(float), d * sizeof(float), n1,
+                          hipMemcpyDeviceToDevice, s));
+  Tmp<int32_t> top(idx->mem, idx->L0.nlist);
+  qk::launch_assign(idx->L0.centroids, idx->L0.nlist, dp, idx->L1.centroids, n1, idx->metric, top.p, s);
+  QK_HIP(hipStreamSynchronize(s));
+  drop_top_level(idx, 1);
+  try {
+    qk::build_top_level(idx, 1, n1, 0, 0, C1.p, top.p, s);
+  } catch (...) {
+    // the index falls back to level 0 alone rather than keep a stale level 1
+    drop_top_level(idx, 1);
+    if (idx->n_levels == 3) drop_top_level(idx, 2);
+    idx->n_levels = 1;
+    throw;
+  }
+}
+
 quake_index* qk::build_index(const float* x, const int64_t* ids, int64_t n, int32_t d,
                              const quake_build_params* params, const float* top_centroids, const int32_t* top_of,
                              const quake_allocator* allocator, hipStream_t s) {

@@ -86,6 +86,9 @@ quake_index* build_index(const float* x, const int64_t* ids, int64_t n, int32_t 
 // the given top centroids and parent of every centroid below (capi.cpp).
 void build_top_level(quake_index* idx, int level, int64_t nlist_top, int32_t kmeans_iters, uint64_t seed,
                      const float* top_centroids, const int32_t* parent, hipStream_t s);
+// Level 1 rebuilt over the current level-0 centroids (their nearest level-1
+// partitions; level-1 centroids unchanged) after level 0 changed (capi.cpp).
+void rebuild_level1(quake_index* idx, hipStream_t s);
 // The maintenance pass behind quake_maintain (maintain.cpp).
 void maintain(quake_index* idx, const quake_maintain_params& p, quake_maintain_report* report, hipStream_t s);
 

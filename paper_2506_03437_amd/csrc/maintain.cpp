@@ -419,7 +419,6 @@ void check_params(const quake_maintain_params& p) {
 }  // namespace
 
 void maintain(quake_index* idx, const quake_maintain_params& p, quake_maintain_report* report, hipStream_t s) {
-  QK_CHECK(idx->n_levels == 1, QUAKE_E_STATE, "maintenance of a two-level index is not supported");
   check_params(p);
   Store& st = idx->L0;
   const int dp = st.dp;
@@ -601,6 +600,7 @@ void maintain(quake_index* idx, const quake_maintain_params& p, quake_maintain_r
   st.window = 0;
   st.attr_dirty = true;
   QK_HIP(hipStreamSynchronize(s));
+  if (idx->n_levels >= 2) rebuild_level1(idx, s);
   release_graphs(idx);
   if (p.decisions)
     for (size_t i = 0; i < dec.size() && (int64_t)i < p.max_decisions; ++i) p.decisions[i] = dec[i];

@@ -220,17 +220,49 @@ def test_maintenance_with_the_index_counters(counted):
         idx.free()
 
 
-def test_two_level_maintenance_is_refused():
-    from paper_2506_03437_amd import QuakeError
-    spec = synth.MixtureSpec(key=62, n=4_000, d=16, n_components=8)
-    X = synth.database(spec)
-    idx = gu.build(X, metric="l2", nlist=32, n_levels=2, nlist_top=4, kmeans_iters=3)
+def test_two_level_maintenance_propagates_upward():
+    """Maintenance of a two-level index acts on level 0 exactly as on the
+    one-level index with the same level 0 (same decisions, partitions and
+    centroids), keeps the level-1 centroids, and places every new level-0
+    centroid in its nearest level-1 partition (Sec. 4.2: splits add, deletes
+    remove a centroid at the parent level).  Searches then run on both
+    levels and return the exact top-k over the partitions they scanned."""
+    X, assign, hits = _pairs_index("l2", seed=3)
+    print(f"[build] pairs index, one and two levels: {X.shape[0]} rows", flush=True)
+    one = gu.build(X, metric="l2", nlist=int(hits.size), storage="bf16", assign=gu.to_dev(assign))
+    C0, _, _ = one.export()
+    two = gu.build(X, metric="l2", nlist=int(hits.size), n_levels=2, nlist_top=5, kmeans_iters=4, seed=3,
+                   storage="bf16", centroids=C0, assign=gu.to_dev(assign))
     try:
-        with pytest.raises(QuakeError) as e:
-            idx.maintain(LAMBDA_SIZE, LAMBDA_COST)
-        assert e.value.code == -6
+        T_before, _ = two.export_level(1)
+        kw = dict(tau=0.2, alpha=1.0, refine_radius=1, refine_iters=1, split_iters=8, min_split_size=2,
+                  merge_below=20, hits=hits, window=1000)
+        r1, d1 = one.maintain(LAMBDA_SIZE, LAMBDA_COST, **kw)
+        r2, d2 = two.maintain(LAMBDA_SIZE, LAMBDA_COST, **kw)
+        assert r1 == r2 and d1 == d2 and r2["splits"] == 8 and r2["deletes"] == 4
+        a1, a2 = gu.oracle_view(one, X), gu.oracle_view(two, X)
+        assert (a1.assign == a2.assign).all() and (a1.C == a2.C).all()
+        T_after, top_of = two.export_level(1)
+        assert (T_after.cpu().numpy() == T_before.cpu().numpy()).all()
+        assert two.level_sizes() == [a2.nlist, 5, 0]
+        bad = oivf.assignment_violations(a2.C, top_of.cpu().numpy().astype(np.int64), T_after.cpu().numpy(), "l2",
+                                         rtol=1e-5)
+        assert bad.size == 0
+        rng = np.random.default_rng(5)
+        Q = (X[rng.choice(X.shape[0], 200, replace=False)] + 0.05 * rng.standard_normal((200, X.shape[1]))
+             ).astype(np.float32)
+        gi, gv, ns, _ = gu.search(two, Q, k=10, recall_target=0.9, f_M=0.25, upper_recall_target=0.99,
+                                  upper_f_M=0.5)
+        order, h = two.candidates(gu.to_dev(Q), 0.25, upper_recall_target=0.99, upper_f_M=0.5)
+        order = order.cpu().numpy()
+        id_to_row = {i: i for i in range(X.shape[0])}
+        for i in range(Q.shape[0]):
+            dev = order[i][order[i] >= 0].astype(np.int64)
+            ri, rv = oivf.scan_partitions(a2, Q[i], dev[: int(ns[i])], 10, "l2")
+            parity.check_topk(Q[i], X, id_to_row, gi[i], gv[i], ri, rv, "l2", 10, f"query {i}")
     finally:
-        idx.free()
+        one.free()
+        two.free()
 
 
 def test_latency_profile_on_this_gpu(counted):
