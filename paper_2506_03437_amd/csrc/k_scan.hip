@@ -506,8 +506,12 @@ __device__ double cap_direct(const double* __restrict__ table, double t) {
   return 0.5 * (1.0 - (pre / b) * beta_fraction(b, a, y));
 }
 
-__device__ __forceinline__ double cap_value(const double* __restrict__ table, double t, bool direct) {
-  return direct ? cap_direct(table, t) : cap_share(table, t);
+// The share of the ball beyond the bisector at t, from the table or (DIRECT)
+// evaluated directly.
+template <int DIRECT>
+__device__ __forceinline__ double cap_value(const double* __restrict__ table, double t) {
+  if constexpr (DIRECT) return cap_direct(table, t);
+  else return cap_share(table, t);
 }
 
 // Euclidean distance to a result key: sqrt of the squared L2 distance, or for
@@ -554,14 +558,16 @@ struct Filter {
 
 // p_0, V = sum v_i and the committed mass v_1 + ... + v_{m-1} for radius rho
 // (candidates 1 .. M - 1 of the query).
+template <int DIRECT, int FILT>
 __device__ void recompute_model(Model& md, double rho, const float* __restrict__ hq, int M, int committed,
-                                const double* __restrict__ table, bool direct, const Filter& fl) {
+                                const double* __restrict__ table, const Filter& fl) {
   const int lane = lane_id();
   double vs = 0.0, pr = 1.0, vc = 0.0;
   const bool inf = __builtin_isinf(rho);
   for (int i = 1 + lane; i < M; i += WAVE) {
     const double t = inf ? 0.0 : (double)hq[i] / rho;
-    const double v = fl.share(cap_value(table, t, direct), i);
+    double v = cap_value<DIRECT>(table, t);
+    if constexpr (FILT) v = fl.share(v, i);
     vs += v;
     pr *= (1.0 - v);
     if (i < committed) vc += v;
@@ -580,6 +586,7 @@ __device__ __forceinline__ double model_recall(const Model& md) {
 
 // Smallest number of further candidates, from position `from`, after which
 // the current model reaches the target; M - from if it never does.
+template <int FILT>
 __device__ int predict_window(const Model& md, const float* __restrict__ hq, int M, int from, double target,
                               const double* __restrict__ table, const Filter& fl) {
   if (!(md.V > 0.0)) return 1;
@@ -591,7 +598,10 @@ __device__ int predict_window(const Model& md, const float* __restrict__ hq, int
   for (int base = from; base < M; base += WAVE) {
     const int i = base + lane;
     double v = 0.0;
-    if (i < M) v = fl.share(cap_share(table, inf ? 0.0 : (double)hq[i] / md.rho), i);
+    if (i < M) {
+      v = cap_share(table, inf ? 0.0 : (double)hq[i] / md.rho);
+      if constexpr (FILT) v = fl.share(v, i);
+    }
     // inclusive scan over the wave
     for (int o = 1; o < WAVE; o <<= 1) {
       const double u = __shfl_up(v, o);
@@ -695,7 +705,7 @@ struct PackedList {
 // recall model (recompute when rho moved by more than tau_rho * rho) and stop
 // once the estimate reaches the target.  Partitions of the window after the
 // stop point are discarded.  Then predict the next window.
-template <class List>
+template <int DIRECT, int FILT, class List>
 __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restrict__ mq, int k, int kk, int aps,
                              int ip, int chunk_tiles, int wmax, int wscale, double tau_r, double tau_rho, int est,
                              const int32_t* __restrict__ cand, const float* __restrict__ hcand,
@@ -733,7 +743,7 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
   L.prime(pk + it * kk, pi + it * kk);
   Model md{st_rho[q], st_p0[q], st_V[q], st_vsum[q]};
   Filter fl;
-  if (aps && qmask) {
+  if (FILT && aps) {
     fl.cand = cand + q * M;
     fl.cnt = attr_cnt;
     fl.mask = qmask[q];
@@ -756,16 +766,18 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
     const bool full = kth_id >= 0;
     const double rho_new = full ? key_radius(L.key(k - 1), ip, qn) : __builtin_inf();
     if (committed == 1) {
-      recompute_model(md, rho_new, hq, Mq, committed, table, est == QUAKE_EST_APS_RP, fl);
+      recompute_model<DIRECT, FILT>(md, rho_new, hq, Mq, committed, table, fl);
     } else {
       const bool redo = est != QUAKE_EST_APS || (__builtin_isinf(md.rho) ? !__builtin_isinf(rho_new)
                                                                           : fabs(rho_new - md.rho) > tau_rho * md.rho);
       if (redo) {
-        recompute_model(md, rho_new, hq, Mq, committed, table, est == QUAKE_EST_APS_RP, fl);
+        recompute_model<DIRECT, FILT>(md, rho_new, hq, Mq, committed, table, fl);
       } else if (md.V > 0.0) {
         const float hc = j < WAVE ? readlane_f(my_h, j) : hq[committed - 1];  // committed - 1 = m0 + j
         const double t = __builtin_isinf(md.rho) ? 0.0 : (double)hc / md.rho;
-        md.vsum += fl.share(cap_share(table, t), committed - 1);
+        double v = cap_share(table, t);
+        if constexpr (FILT) v = fl.share(v, committed - 1);
+        md.vsum += v;
       }
     }
     r = full ? model_recall(md) : 0.0;
@@ -778,7 +790,7 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
     // more partitions are committed, so a query usually needs more - the
     // window is scaled by wscale percent (speculation costs scans, not
     // results: partitions past the stop point are discarded)
-    if (aps && L.id(k - 1) >= 0) wn = (predict_window(md, hq, Mq, committed, tau_r, table, fl) * wscale + 99) / 100;
+    if (aps && L.id(k - 1) >= 0) wn = (predict_window<FILT>(md, hq, Mq, committed, tau_r, table, fl) * wscale + 99) / 100;
     else wn = 2 * w;
     if (wn < 1) wn = 1;
     if (wn > wmax) wn = wmax;
@@ -812,29 +824,30 @@ __device__ void commit_query(int64_t q, List& L, int M, const int32_t* __restric
       st_done, st_weff, st_item, st_rho, st_p0, st_V, st_vsum, st_r, rk, ri, hits, qmask, attr_cnt
 
 // Lists longer than a wave: one 64-thread block per query, lists in LDS.
-template <int LMAX>
+// DIRECT: cap shares evaluated directly (APS-RP); FILT: a filtered search.
+template <int DIRECT, int FILT, int LMAX>
 __global__ __launch_bounds__(64) void k_commit(QK_COMMIT_PARAMS) {
   __shared__ float Ak[LMAX], Bk[LMAX], Ok[LMAX];
   __shared__ int64_t Ai[LMAX], Bi[LMAX], Oi[LMAX];
   const int64_t q = blockIdx.x;
   if (st_done[q] || st_weff[q] == 0) return;
   LdsList<LMAX> L{Ak, Bk, Ok, Ai, Bi, Oi, kk};
-  commit_query(q, L, QK_COMMIT_ARGS);
+  commit_query<DIRECT, FILT>(q, L, QK_COMMIT_ARGS);
 }
 
 // Lists of at most 64 entries: one wave per query, four queries per block,
 // lists in registers.
-template <class List>
+template <int DIRECT, int FILT, class List>
 __global__ __launch_bounds__(256) void k_commit64(QK_COMMIT_PARAMS) {
   const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (q >= nq || st_done[q] || st_weff[q] == 0) return;
   List L;
   L.kk = kk;
-  commit_query(q, L, QK_COMMIT_ARGS);
+  commit_query<DIRECT, FILT>(q, L, QK_COMMIT_ARGS);
 }
 
-void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const double* table, hipStream_t s) {
-  if (a.nq <= 0) return;
+template <int DIRECT, int FILT>
+static void launch_commit_k(Workspace& ws, const Store& st, const RoundArgs& a, const double* table, hipStream_t s) {
 #define QK_COMMIT(KERNEL, GRID, BLOCK)                                                                        \
   hipLaunchKernelGGL(KERNEL, dim3((unsigned)(GRID)), dim3(BLOCK), 0, s, a.nq, a.M, ws.mq, a.k, a.kk, a.aps,    \
                      a.metric == QUAKE_IP ? 1 : 0, a.chunk_tiles, a.wmax, a.wscale, a.tau_r, a.tau_rho, a.est,      \
@@ -843,11 +856,23 @@ void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const dou
                      st.d_size, ws.qn2, ws.pk, ws.pi, table, ws.st_m, ws.st_w, ws.st_done, ws.st_weff,        \
                      ws.st_item, ws.st_rho, ws.st_p0, ws.st_V, ws.st_vsum, ws.st_r, ws.rk, ws.ri, a.hits, a.qmask,   \
                      a.attr_cnt)
-  if (a.kk <= WAVE && a.slot_ids) QK_COMMIT(k_commit64<PackedList>, (a.nq + 3) / 4, 256);
-  else if (a.kk <= WAVE) QK_COMMIT(k_commit64<RegList>, (a.nq + 3) / 4, 256);
-  else if (a.kk <= KMAX) QK_COMMIT(k_commit<KMAX>, a.nq, 64);
-  else QK_COMMIT(k_commit<KMAX_LARGE>, a.nq, 64);
+  if (a.kk <= WAVE && a.slot_ids) QK_COMMIT((k_commit64<DIRECT, FILT, PackedList>), (a.nq + 3) / 4, 256);
+  else if (a.kk <= WAVE) QK_COMMIT((k_commit64<DIRECT, FILT, RegList>), (a.nq + 3) / 4, 256);
+  else if (a.kk <= KMAX) QK_COMMIT((k_commit<DIRECT, FILT, KMAX>), a.nq, 64);
+  else QK_COMMIT((k_commit<DIRECT, FILT, KMAX_LARGE>), a.nq, 64);
 #undef QK_COMMIT
+}
+
+void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const double* table, hipStream_t s) {
+  if (a.nq <= 0) return;
+  const bool direct = a.aps && a.est == QUAKE_EST_APS_RP, filt = a.aps && a.qmask;
+  if (direct) {
+    if (filt) launch_commit_k<1, 1>(ws, st, a, table, s);
+    else launch_commit_k<1, 0>(ws, st, a, table, s);
+  } else {
+    if (filt) launch_commit_k<0, 1>(ws, st, a, table, s);
+    else launch_commit_k<0, 0>(ws, st, a, table, s);
+  }
 }
 
 // ---------------------------------------------------------------- outputs
