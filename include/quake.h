@@ -494,7 +494,8 @@ typedef struct {
   double qps;               /* completed / (last answer - first arrival) */
 } quake_server_report;
 
-/* Errors: INVALID (bad params, two-level index), STATE, NOMEM, DEVICE. */
+/* Errors: INVALID (bad params, an index with upper levels, a filter in the search
+ * params), STATE, NOMEM, DEVICE. */
 int quake_server_create(quake_index* index, const quake_server_params* params, quake_server** out);
 /* Submit n single-query searches q[n][d] (host float32); tickets are
  * *first_ticket .. *first_ticket + n - 1. */

@@ -637,6 +637,7 @@ int quake_server_create(quake_index* idx, const quake_server_params* params, qua
   QK_CHECK(idx && idx->magic == 0x51554b45u, QUAKE_E_STATE, "invalid index handle");
   QK_CHECK(idx->n_levels == 1, QUAKE_E_INVALID, "the serving loop runs on single-level indexes");
   QK_CHECK(params->max_slots >= 0, QUAKE_E_INVALID, "max_slots must be >= 0");
+  QK_CHECK(!params->search.filter, QUAKE_E_INVALID, "the serving loop takes no filter (requests carry no masks)");
   QK_CHECK(params->overlap_updates == 0 || params->overlap_updates == 1, QUAKE_E_INVALID,
            "overlap_updates must be 0 or 1");
   std::unique_ptr<quake_server> srv(new quake_server());

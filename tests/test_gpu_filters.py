@@ -171,6 +171,7 @@ def test_unsupported_combinations_are_refused():
         lambda: gu.search(plain, Q, k=10, recall_target=0.9, filter=m),                 # no labels
         lambda: lab.insert(x1, i1),                                                       # labels missing
         lambda: plain.insert(x1, i1, attrs=_i32(np.ones(2, dtype=np.uint32))),            # index has none
+        lambda: quake.quake_server_create(lab.handle, k=10, recall_target=0.9, filter=m),  # requests carry no masks
     ):
         with pytest.raises(quake.QuakeError) as e:
             call()
