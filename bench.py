@@ -511,6 +511,50 @@ def ablation_leg(idx, w, Q, Qd, truth, sample_rows, recall_of, paths, upper):
     return res
 
 
+def levels_leg(idx, w, Qd, recall_of, path_kw):
+    """One, two and three levels over the same level 0 (Sec. 3; Sec. 4.2
+    "Add Level"; Sec. 7 "Multi-Level Recall Estimation", Table
+    tab:two_level_results): a level of round(sqrt(N)) partitions is added on
+    top of the current one twice, and each configuration is searched at
+    level-0 targets 0.8 / 0.9 / 0.95 with the upper levels at 0.99 over 25%
+    of their partitions.  The upper-level time is the candidate search
+    alone (quake_candidates, which runs the upper levels and the level-0
+    geometry); the levels are removed afterwards."""
+    import math
+    import torch
+
+    def timed(fn, steps=3):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = fn()
+        torch.cuda.synchronize()
+        return out, (time.perf_counter() - t0) * 1e3 / steps
+
+    res = []
+    added = 0
+    for levels in (1, 2, 3):
+        if levels > 1:
+            top = idx.level_sizes()[levels - 2]
+            idx.add_level(max(1, int(round(math.sqrt(top)))), kmeans_iters=10, seed=levels)
+            added += 1
+        up = dict(upper_recall_target=0.99, upper_f_M=0.25) if levels > 1 else {}
+        sizes = idx.level_sizes()
+        for tau in (0.8, 0.9, 0.95):
+            (ids, _, ns, _), ms = timed(lambda: idx.search(Qd, k=w.k, recall_target=tau, f_M=w.f_M, **up, **path_kw))
+            _, cms = timed(lambda: idx.candidates(Qd, w.f_M, **up))
+            row = {"levels": levels, "partitions_per_level": sizes[:levels], "recall_target": tau,
+                   "recall_at_10": recall_of(ids), "ms_per_search": ms, "candidates_ms": cms,
+                   "mean_partitions_scanned": float(ns.float().mean().item())}
+            res.append(row)
+            log(f"levels {levels} {sizes[:levels]} target {tau}: recall {row['recall_at_10']:.4f}, {ms:.2f} ms "
+                f"(candidates {cms:.2f} ms), {row['mean_partitions_scanned']:.1f} partitions")
+    for _ in range(added):
+        idx.remove_level()
+    return res
+
+
 def filter_leg(w, sample_rows, threads):
     """Filtered search (Sec. 8, "Filters") on the workload's rows with
     seeded labels: one of 8 labels per row, the row's mixture component's
@@ -626,6 +670,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy a BYTES-long device buffer 5 times (calibrates HBM byte counters) and exit")
     ap.add_argument("--serving-requests", type=int, default=0, help="> 0 runs the serving-loop leg")
+    ap.add_argument("--levels", action="store_true",
+                    help="one, two and three levels over the workload's index (after the timed legs)")
     ap.add_argument("--ablation", action="store_true",
                     help="estimator, early-termination and f_M ablations on the workload (after the timed legs)")
     ap.add_argument("--maintenance", action="store_true",
@@ -843,6 +889,9 @@ def main():
         ablation = ablation_leg(idx, w, Q, Qd, truth, sample_rows, recall_of, paths, upper)
         if not two_level:
             ablation["filters"] = filter_leg(w, sample_rows, threads)
+    levels = None
+    if args.levels and truth is not None and not two_level:
+        levels = levels_leg(idx, w, Qd, recall_of, paths[next(iter(paths))])
     maint = None
     if args.maintenance and batched is not None and not two_level:
         maint = maintenance_leg(idx, w, X, batched["recall_target"], args.rerank_factor, threads)
@@ -929,6 +978,7 @@ def main():
         "serving": serving,
         "maintenance": maint,
         "ablation": ablation,
+        "levels": levels,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -71,6 +71,13 @@ WORKLOADS: Dict[str, Workload] = {
         name="ablation-1m-d128-l2",
         spec=MixtureSpec(key=6, n=1_000_000, d=128, n_components=1000, zipf_s=1.1),
         nlist=1000, metric="l2", nq=10_000, k=10, recall_target=0.9, f_M=0.05, storage="f16"),
+    # Levels: 10M x 128, 1,000 Zipf(1.1) components, 40,000 partitions (the
+    # partition count of the paper's two-level table), L2, 10,000 queries,
+    # f_M 1.5% (600 level-0 candidates), FP16 copy.
+    "levels-10m-d128-l2": Workload(
+        name="levels-10m-d128-l2",
+        spec=MixtureSpec(key=7, n=10_000_000, d=128, n_components=1000, zipf_s=1.1),
+        nlist=40_000, metric="l2", nq=10_000, k=10, recall_target=0.9, f_M=0.015, storage="f16"),
     # Serving: 10M x 768 BF16 start, skewed drifting queries, 1% updates per step.
     "serving-10m-d768-bf16": Workload(
         name="serving-10m-d768-bf16",
