@@ -81,7 +81,8 @@ typedef struct {
                               should be unit-norm, centroids are renormalised: spherical k-means) */
   int32_t storage_dtype;   /* extra reduced-precision copy of the vectors: QUAKE_F32 = none,
                               QUAKE_BF16 or QUAKE_F16 (used by scan_dtype != QUAKE_F32) */
-  int32_t n_levels;        /* 1, or 2 (level 1 partitions the level-0 centroids) */
+  int32_t n_levels;        /* 1, or 2 (level 1 partitions the level-0 centroids); a third level is
+                              added to a live index with quake_add_level */
   int32_t kmeans_iters;    /* Lloyd iterations (>= 0) when centroids are not given */
   int64_t nlist;           /* level-0 partitions, 1 <= nlist <= n */
   int64_t nlist_top;       /* level-1 partitions when n_levels == 2 */
@@ -127,7 +128,7 @@ typedef struct {
                               rows whose label bits share a bit with it are results, and the recall
                               model scales each candidate's cap share by the partition's estimated
                               pass fraction (per-bit counts of the mask's bits, capped at its live
-                              rows).  Needs a labelled one-level index and the plain FP32 scan. */
+                              rows).  Needs a labelled one-level index (either scan path). */
 } quake_search_params;
 
 /* Build an index over x[n][d] (device, float32) with ids[n] (device int64,
