@@ -142,3 +142,17 @@ def test_save_and_load_argument_errors(tmp_path):
     assert lib.quake_load(None, None, 0, None, ctypes.byref(h)) == quake.E_INVALID
     assert lib.quake_save(None, str(tmp_path / "x.qk").encode(), None) == quake.E_STATE
     assert lib.quake_describe(None, None, None, None, None) == quake.E_STATE
+
+
+def test_level_and_label_entry_points_check_the_handle():
+    from paper_2506_03437_amd import quake
+    lib = quake.load_library()
+    out = (ctypes.c_int64 * 3)()
+    act = ctypes.c_int32(7)
+    assert lib.quake_add_level(None, 4, 2, 0, None) == quake.E_STATE
+    assert lib.quake_remove_level(None, None) == quake.E_STATE
+    assert lib.quake_adjust_levels(None, 10, 0, 0, 2, 0, None, ctypes.byref(act)) == quake.E_STATE
+    assert lib.quake_export_level(None, 1, None, None, None) == quake.E_STATE
+    assert lib.quake_level_sizes(None, out) == quake.E_STATE
+    assert lib.quake_insert_attrs(None, None, None, None, 1, None) == quake.E_INVALID  # attrs missing
+    assert lib.quake_insert_attrs(None, None, None, ctypes.c_void_p(8), 1, None) == quake.E_STATE
