@@ -57,3 +57,22 @@ def test_trace_skew_and_drift():
         w /= w.sum()
         assert abs(frac[0] - w[0]) < 0.03          # the hottest component takes its Zipf share
     assert comps[0].argmax() != comps[1].argmax()   # the popular set moved
+
+
+def test_row_labels_follow_location():
+    """One label bit per row; a row carries its component's home label
+    (component mod 8) with probability 0.7 + 0.3 / 8; masks are one bit,
+    uniform over the labels; both are reproducible."""
+    spec = synth.MixtureSpec(key=91, n=40_000, d=4, n_components=64, zipf_s=1.1)
+    _, comp = synth.database(spec, with_components=True)
+    lab = synth.row_labels(spec, comp)
+    assert lab.dtype == np.uint32 and (np.bitwise_and(lab, lab - 1) == 0).all() and (lab != 0).all()
+    home = (np.uint32(1) << (comp % 8).astype(np.uint32)).astype(np.uint32)
+    frac = (lab == home).mean()
+    want = 0.7 + 0.3 / 8
+    assert abs(frac - want) < 5 * np.sqrt(want * (1 - want) / lab.size)
+    assert (synth.row_labels(spec, comp) == lab).all()
+    m = synth.query_masks(spec, 16_000)
+    assert (np.bitwise_and(m, m - 1) == 0).all()
+    counts = np.bincount(np.log2(m).astype(int), minlength=8)
+    assert counts.size == 8 and (np.abs(counts - 2000) < 5 * np.sqrt(2000)).all()
