@@ -160,3 +160,29 @@ def test_calibration_band_inner_product_d768():
         assert rec >= tau - 0.02, (tau, rec)
         assert rec >= prev
         prev = rec
+
+
+def test_ip_multi_level_search_replays_l2_on_the_unit_sphere():
+    """The level hand-over keeps the metric: with unit vectors and unit
+    centroids at every level, the three-level search in inner product takes
+    the same candidates, stops and results as in L2."""
+    from oracle import twolevel
+    ps, Q = _unit_sphere_index(5, n=4000, nlist=60)
+    rng = np.random.default_rng(6)
+    C1 = _unit(ps.C[rng.choice(60, 10, replace=False)] + 0.05 * rng.standard_normal((10, ps.C.shape[1])))
+    a1 = np.argmax(ps.C @ C1.T, axis=1)
+    C2 = _unit(C1[rng.choice(10, 3, replace=False)] + 0.05 * rng.standard_normal((3, ps.C.shape[1])))
+    a2 = np.argmax(C1 @ C2.T, axis=1)
+    ls = twolevel.LevelStack(ps, [(a1, C1), (a2, C2)])
+    table = aps.CapTable(ps.X.shape[1])
+    pl = twolevel.TwoLevelParams(k=10, recall_target=0.9, f_M=0.2, upper_recall_target=0.99, upper_f_M=0.5,
+                                 metric="l2")
+    pi = twolevel.TwoLevelParams(k=10, recall_target=0.9, f_M=0.2, upper_recall_target=0.99, upper_f_M=0.5,
+                                 metric="ip")
+    for q in Q:
+        rl, ul = twolevel.multi_level_search_one(ls, q, pl, table)
+        ri, ui = twolevel.multi_level_search_one(ls, q, pi, table)
+        for a, b in zip(ul, ui):
+            assert a.ids.tolist() == b.ids.tolist() and a.m == b.m
+        assert rl.order.tolist() == ri.order.tolist() and rl.m == ri.m
+        assert rl.ids.tolist() == ri.ids.tolist()
