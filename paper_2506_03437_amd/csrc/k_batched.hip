@@ -83,7 +83,8 @@ void launch_queries16(Workspace& ws, int64_t nq, int dp, int dp16, int dtype16, 
 
 // Record every (query, window slot) pair of the round and count pairs per
 // partition.  pair_base is the first partial-list slot of the pair (the same
-// numbering as the plain scan's work items).
+// numbering as the plain scan's work items).  One wave per query, a lane per
+// window slot: the slots' item offsets are a prefix sum over the wave.
 __global__ __launch_bounds__(256) void k_pairs(int64_t nq, int M, int chunk_tiles, const int32_t* __restrict__ cand,
                                                 const int32_t* __restrict__ psize, const int32_t* __restrict__ st_m,
                                                 const int32_t* __restrict__ st_weff,
@@ -91,20 +92,31 @@ __global__ __launch_bounds__(256) void k_pairs(int64_t nq, int M, int chunk_tile
                                                 const int64_t* __restrict__ st_pair, int32_t* __restrict__ pcount,
                                                 int32_t* __restrict__ pair_q, int32_t* __restrict__ pair_p,
                                                 int32_t* __restrict__ pair_pos, int64_t* __restrict__ pair_base) {
-  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (q >= nq) return;
   const int w = st_weff[q];
   if (w == 0) return;
   const int m = st_m[q];
   int64_t it = st_item[q];
   const int64_t pr = st_pair[q];
-  for (int j = 0; j < w; ++j) {
-    const int p = cand[q * M + m + j];
-    pair_q[pr + j] = (int32_t)q;
-    pair_p[pr + j] = p;
-    pair_base[pr + j] = it;
-    pair_pos[pr + j] = atomicAdd(&pcount[p], 1);
-    it += chunks_of(psize[p], chunk_tiles);
+  for (int j0 = 0; j0 < w; j0 += WAVE) {
+    const int j = j0 + lane;
+    const bool on = j < w;
+    const int p = on ? cand[q * M + m + j] : 0;
+    const int c = on ? chunks_of(psize[p], chunk_tiles) : 0;
+    int incl = c;
+    for (int o = 1; o < WAVE; o <<= 1) {
+      const int u = __shfl_up(incl, o);
+      if (lane >= o) incl += u;
+    }
+    if (on) {
+      pair_q[pr + j] = (int32_t)q;
+      pair_p[pr + j] = p;
+      pair_base[pr + j] = it + (incl - c);
+      pair_pos[pr + j] = atomicAdd(&pcount[p], 1);
+    }
+    it += __shfl(incl, WAVE - 1);
   }
 }
 
@@ -125,7 +137,7 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
                                                        const int32_t* __restrict__ order, int32_t* __restrict__ pstart,
                                                        int64_t* __restrict__ pitem, int64_t* __restrict__ pxoff,
                                                        int32_t* __restrict__ pxcd, int64_t* __restrict__ counters) {
-  __shared__ int64_t sp[1024], si[1024], sx[1024];
+  __shared__ int64_t sp[1024], si[1024], sx[XCDS][1024];
   __shared__ unsigned long long reads, set_reads, products;
   const int t = threadIdx.x;
   const int64_t per = (N + 1023) / 1024;
@@ -166,32 +178,39 @@ __global__ __launch_bounds__(1024) void k_part_prefix(int64_t N, int chunk_tiles
     pitem[p] = ri;
     ri += items_of(p);
   }
-  // the die queues: a prefix over the ranks of each residue
-  for (int x = 0; x < XCDS; ++x) {
-    int64_t mine = 0;
-    for (int64_t r = lo; r < hi; ++r)
-      if ((r & (XCDS - 1)) == x) mine += items_of(order[r]);
-    sx[t] = mine;
+  // the die queues: a prefix over the ranks of each residue, the eight
+  // residues scanned together
+  int64_t mine[XCDS];
+#pragma unroll
+  for (int x = 0; x < XCDS; ++x) mine[x] = 0;
+  for (int64_t r = lo; r < hi; ++r) mine[r & (XCDS - 1)] += items_of(order[r]);
+#pragma unroll
+  for (int x = 0; x < XCDS; ++x) sx[x][t] = mine[x];
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int64_t a[XCDS];
+#pragma unroll
+    for (int x = 0; x < XCDS; ++x) a[x] = (t >= o) ? sx[x][t - o] : 0;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {
-      const int64_t a = (t >= o) ? sx[t - o] : 0;
-      __syncthreads();
-      sx[t] += a;
-      __syncthreads();
-    }
-    int64_t run = sx[t] - mine;
-    for (int64_t r = lo; r < hi; ++r)
-      if ((r & (XCDS - 1)) == x) {
-        const int64_t p = order[r];
-        pxoff[p] = run;
-        pxcd[p] = x;
-        run += items_of(p);
-      }
-    if (t == 0) {
-      counters[QUEUE_X + x] = 0;
-      counters[QUEUE_X + XCDS + x] = sx[1023];
-    }
+#pragma unroll
+    for (int x = 0; x < XCDS; ++x) sx[x][t] += a[x];
     __syncthreads();
+  }
+  {
+    int64_t run[XCDS];
+#pragma unroll
+    for (int x = 0; x < XCDS; ++x) run[x] = sx[x][t] - mine[x];
+    for (int64_t r = lo; r < hi; ++r) {
+      const int x = (int)(r & (XCDS - 1));
+      const int64_t p = order[r];
+      pxoff[p] = run[x];
+      pxcd[p] = x;
+      run[x] += items_of(p);
+    }
+  }
+  if (t < XCDS) {
+    counters[QUEUE_X + t] = 0;
+    counters[QUEUE_X + XCDS + t] = sx[t][1023];
   }
   // every thread has read the counts it needs before any is cleared
   __syncthreads();
@@ -261,7 +280,7 @@ __global__ __launch_bounds__(256) void k_items(int64_t N, int chunk_tiles, const
 }
 
 void launch_group(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_pairs, dim3((unsigned)((a.nq + 255) / 256)), dim3(256), 0, s, a.nq, a.M, a.chunk_tiles,
+  hipLaunchKernelGGL(k_pairs, dim3((unsigned)((a.nq + 3) / 4)), dim3(256), 0, s, a.nq, a.M, a.chunk_tiles,
                      ws.cand, st.d_size, ws.st_m, ws.st_weff, ws.st_item, ws.st_pair, ws.pcount, ws.pair_q, ws.pair_p,
                      ws.pair_pos, ws.pair_base);
   hipLaunchKernelGGL(k_part_prefix, dim3(1), dim3(1024), 0, s, st.nlist, a.chunk_tiles, ws.pcount, st.d_size,
