@@ -20,6 +20,8 @@ It is a plain, slow, FP64 NumPy restatement of what the search computes:
               verify -> commit workflow and the split, refinement and delete
               actions on vectors (Sec. 4, Eqs. CostPartition, CostTotal,
               DeltaC, delta_split_exact, delta_merge_exact, delta_split_est)
+* ``pq``      product-quantized rows and the scan over their codes with an
+              exact rerank (Sec. 8, "Vector Compression")
 
 It shares no code, headers, tables or constants with the device path.
 """

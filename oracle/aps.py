@@ -60,7 +60,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import Callable, List, Optional
 
 import numpy as np
 from scipy.special import betainc
@@ -267,7 +267,9 @@ class _Estimator:
 
 def aps_search_one(ps: PartitionedSet, q: np.ndarray, params: APSParams, table: CapTable,
                    order: Optional[np.ndarray] = None, h: Optional[np.ndarray] = None,
-                   attr: Optional[np.ndarray] = None, mask: Optional[int] = None) -> APSResult:
+                   attr: Optional[np.ndarray] = None, mask: Optional[int] = None,
+                   row_values: Optional[Callable[[np.ndarray], np.ndarray]] = None,
+                   keep: Optional[int] = None) -> APSResult:
     """Algorithm "Adaptive Partition Scanning" for one query.
 
     ``order``/``h`` may be given to replay a specific candidate order; by
@@ -275,9 +277,16 @@ def aps_search_one(ps: PartitionedSet, q: np.ndarray, params: APSParams, table: 
     every row) and ``mask``, only rows sharing a bit with the mask are
     results, and the recall model scales its cap shares by each candidate's
     pass fraction (Sec. 8, "Filters"; readings F1, F2).
+
+    ``row_values(rows)`` replaces the exact values of the scanned rows (a
+    compressed scan's scores, Sec. 8, "Vector Compression"), and the result
+    list keeps the best ``keep`` >= k rows by them; rho still comes from the
+    k-th value of that list.
     """
     metric = params.metric
     k = params.k
+    keep = k if keep is None else int(keep)
+    assert keep >= k
     if order is None:
         order, h = aps_order(q, ps.C, params.f_M, metric)
     q64 = np.asarray(q, dtype=np.float64)
@@ -292,9 +301,9 @@ def aps_search_one(ps: PartitionedSet, q: np.ndarray, params: APSParams, table: 
         if filt:
             rows = rows[(attr64[rows] & np.uint64(int(mask))) != 0]
         if rows.shape[0] == 0:
-            return select_topk(np.zeros(0), np.zeros(0, dtype=np.int64), k, metric)
-        vals = distances(q[None, :], ps.X[rows], metric)[0]
-        return select_topk(vals, ps.ids[rows], k, metric)
+            return select_topk(np.zeros(0), np.zeros(0, dtype=np.int64), keep, metric)
+        vals = distances(q[None, :], ps.X[rows], metric)[0] if row_values is None else row_values(rows)
+        return select_topk(vals, ps.ids[rows], keep, metric)
 
     def kth_radius(ids, vals):
         if ids[k - 1] < 0:
@@ -318,7 +327,7 @@ def aps_search_one(ps: PartitionedSet, q: np.ndarray, params: APSParams, table: 
     M = order.shape[0]
     while r < params.recall_target and m < M:
         ti, tv = scan(order[m])
-        res_i, res_v = merge_topk(res_i, res_v, ti, tv, k, metric)
+        res_i, res_v = merge_topk(res_i, res_v, ti, tv, keep, metric)
         m += 1
         rho_new = kth_radius(res_i, res_v)
         if params.recompute_every:
