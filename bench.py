@@ -663,7 +663,11 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default scheduling knobs")
     ap.add_argument("--tuning", default="", help="knobs to set instead of autotuning, e.g. chunk_tiles=64,max_window=16")
     ap.add_argument("--tuning-path", default="batched", help="path (plain/batched) the --tuning knobs apply to")
-    ap.add_argument("--paths", default="plain_fp32,batched_bf16")
+    ap.add_argument("--paths", default="plain_fp32,batched_bf16",
+                    help="comma list of plain_fp32, batched_<storage> and plain_pq8 (needs --pq-m)")
+    ap.add_argument("--pq-m", type=int, default=0,
+                    help="also keep product codes of this many subspaces (Sec. 8, vector compression): the "
+                         "plain_pq8 path scans them and reranks --rerank-factor x k candidates in FP32")
     ap.add_argument("--rerank-factor", type=int, default=6,
                     help="batched path: FP32 rerank of this many x k candidates (6: the BF16 - FP32 recall@10 gap "
                          "stays within 0.005 on this workload; 4 loses about 0.01)")
@@ -733,7 +737,7 @@ def main():
         # without the plain FP32 path the index keeps no FP32 tile copy
         idx = Index(Xd, metric=w.metric, nlist=w.nlist, storage=w.storage, kmeans_iters=10, seed=1,
                     capacity_slack=0.05 if args.serving_requests > 0 else 0.0,
-                    f32_tiles="plain_fp32" in args.paths.split(","))
+                    f32_tiles="plain_fp32" in args.paths.split(","), pq_m=args.pq_m)
     del Xd
     torch.cuda.synchronize()
     log(f"built {w.nlist} partitions{f' under {w.nlist_top}' if two_level else ''} in "
@@ -758,6 +762,7 @@ def main():
     all_paths = {
         "plain_fp32": dict(scan_mode="plain", scan_dtype="f32"),
         bkey: dict(scan_mode="batched", scan_dtype=w.storage, rerank_factor=args.rerank_factor),
+        "plain_pq8": dict(scan_mode="plain", scan_dtype="pq8", rerank_factor=args.rerank_factor),
     }
     paths = {(bkey if p.startswith("batched") else p): None for p in args.paths.split(",") if p}
     paths = {p: all_paths[p] for p in paths}

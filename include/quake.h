@@ -50,6 +50,9 @@ enum {
 
 enum { QUAKE_L2 = 0, QUAKE_IP = 1 };
 enum { QUAKE_F32 = 0, QUAKE_BF16 = 1, QUAKE_F16 = 2 };
+/* scan_dtype of a search over the index's product-quantization codes (Sec. 8,
+ * "Vector Compression"; built with pq_m > 0) */
+enum { QUAKE_PQ8 = 3 };
 enum { QUAKE_SCAN_PLAIN = 0, QUAKE_SCAN_BATCHED = 1 };
 /* Recall estimator of an adaptive search (Sec. 5.1, Table tab:recall_overhead):
  * APS recomputes the partition probabilities when rho moved by more than
@@ -103,6 +106,15 @@ typedef struct {
   const uint32_t* attrs;   /* optional device [n]: 32 label bits of every row, for filtered searches
                               (Sec. 8, "Filters"); a labelled index takes its inserts through
                               quake_insert_attrs */
+  int32_t pq_m;            /* 0, or keep a product-quantized copy of level 0 (Sec. 8, "Vector
+                              Compression"): pq_m subspaces of d / pq_m consecutive dimensions (pq_m a
+                              multiple of 4 dividing d, d / pq_m <= 32), 256 codewords each, one byte
+                              per subspace and row; searched with scan_dtype QUAKE_PQ8.  The index also
+                              keeps the row-major FP32 copy the rerank reads, and drop_f32_tiles may be
+                              set without a 16-bit copy */
+  const float* pq_codebook; /* optional device [pq_m][256][d / pq_m]: use this codebook; else it is
+                              trained by kmeans_iters Lloyd iterations per subspace (squared L2, from
+                              256 distinct rows of a seeded sample of at most 65,536; needs n >= 256) */
 } quake_build_params;
 
 /* Search parameters.  Exactly one of nprobe > 0 (fixed number of partitions)
@@ -117,7 +129,11 @@ typedef struct {
   double upper_f_M;        /* two-level: level-1 candidate fraction; 0 -> 0.25 */
   int32_t scan_mode;       /* QUAKE_SCAN_PLAIN: per-(query, partition) scans;
                               QUAKE_SCAN_BATCHED: queries grouped per partition (Sec. 7.4, "Multi-Query Processing") */
-  int32_t scan_dtype;      /* QUAKE_F32, or the index's reduced-precision copy */
+  int32_t scan_dtype;      /* QUAKE_F32, or the index's reduced-precision copy (batched scan), or
+                              QUAKE_PQ8 (plain scan over product codes: rows are scored from a
+                              per-query table of query-to-codeword values, APS runs on those scores,
+                              rerank_factor * k rows (<= 64) are kept and re-scored in FP32; an index
+                              built with pq_m > 0; not for quake_search_noalloc or the server) */
   int32_t rerank_factor;   /* reduced precision: keep rerank_factor*k candidates, rerank in FP32;
                               0 -> 4; -1: no rerank, the k best by the 16-bit path's own values
                               (IP: the MFMA dot of the rounded query and row, FP32 accumulation;
@@ -205,6 +221,13 @@ int quake_describe(const quake_index* index, int32_t* d, int32_t* metric, int32_
  * float32), and for every live vector its id and partition (device int64
  * ids[n_live], int32 part[n_live], in store order).  Any pointer may be NULL. */
 int quake_export(const quake_index* index, float* centroids, int64_t* ids, int32_t* part, void* stream);
+
+/* Export the product quantization of level 0 (Sec. 8, "Vector Compression")
+ * for checking: *m (host) receives pq_m (0 when the index keeps no codes);
+ * codebook[pq_m][256][d / pq_m] (device float32) and, for every live vector
+ * in the order quake_export lists them, its codes[n_live][pq_m] (device
+ * uint8).  Any pointer may be NULL.  Errors: STATE, DEVICE. */
+int quake_export_pq(const quake_index* index, int32_t* m, float* codebook, uint8_t* codes, void* stream);
 
 /* Save the index to a file: the level-0 centroids, every live vector with
  * its id and partition (partition by partition, in store order), the

@@ -21,7 +21,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libquake_mi355x.so")
 
 HIP_SOURCES = ["k_centroids.hip", "k_scan.hip", "k_store.hip", "k_batched.hip", "k_rerank.hip", "k_update.hip",
-               "k_serve.hip", "k_noalloc.hip", "k_maintain.hip"]
+               "k_serve.hip", "k_noalloc.hip", "k_maintain.hip", "k_pq.hip"]
 CPP_SOURCES = ["capi.cpp", "cap_table.cpp", "serve.cpp", "maintain.cpp", "persist.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]

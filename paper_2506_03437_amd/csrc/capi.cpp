@@ -269,7 +269,13 @@ void kmeans(qk::DeviceMemory& mem, const float* xpad, int64_t n, int dp, int64_t
 
 // ---------------------------------------------------------------- the store
 
-void alloc_store_arrays(quake_index* idx, Store& st, int64_t tiles, int dtype16, bool f32_tiles, hipStream_t s) {
+// A level-0 store, or a copy of one (not an upper level).
+bool is_leaf(const quake_index* idx, const Store& st) { return &st != &idx->L1 && &st != &idx->L2; }
+
+// `leaf`: the arrays are for a level-0 store (or a copy of one), which also
+// holds the label bits and the product codes when the index has them.
+void alloc_store_arrays(quake_index* idx, Store& st, int64_t tiles, int dtype16, bool f32_tiles, bool leaf,
+                        hipStream_t s) {
   auto& mem = idx->mem;
   const size_t slots = (size_t)tiles * qk::TILE;
   if (f32_tiles) {
@@ -286,9 +292,19 @@ void alloc_store_arrays(quake_index* idx, Store& st, int64_t tiles, int dtype16,
     st.rows32 = mem.alloc<float>(slots * st.dp);
     QK_HIP(hipMemsetAsync(st.rows32, 0, slots * st.dp * sizeof(float), s));
   }
+  if (leaf && idx->pq_m > 0) {
+    // the rerank of a search over codes reads the row-major FP32 copy
+    if (!st.rows32) {
+      st.rows32 = mem.alloc<float>(slots * st.dp);
+      QK_HIP(hipMemsetAsync(st.rows32, 0, slots * st.dp * sizeof(float), s));
+    }
+    st.pq_m = idx->pq_m;
+    st.codes = mem.alloc<uint32_t>(slots * (idx->pq_m / 4));
+    QK_HIP(hipMemsetAsync(st.codes, 0, slots * (idx->pq_m / 4) * sizeof(uint32_t), s));
+  }
   st.ids = mem.alloc<int64_t>(slots);
   QK_HIP(hipMemsetAsync(st.ids, 0xff, slots * sizeof(int64_t), s));
-  if (idx->labelled && &st != &idx->L1 && &st != &idx->L2) {
+  if (idx->labelled && leaf) {
     st.attr = mem.alloc<uint32_t>(slots);
     QK_HIP(hipMemsetAsync(st.attr, 0, slots * sizeof(uint32_t), s));
   }
@@ -311,6 +327,33 @@ void upload_table(Store& st, hipStream_t s) {
 // Place rows into a fresh store: partition p gets capacity for its rows plus
 // slack, rounded up to whole tiles; rows keep their input order within a
 // partition.
+// Product-quantization codebook of rows x[n][d] into idx->pq_book
+// [pq_m][256][pq_ds]: Lloyd's k-means (squared L2, from 256 distinct rows)
+// in each subspace over the same seeded sample of at most 65,536 rows.
+void train_codebook(quake_index* idx, const float* x, int64_t n, int iters, uint64_t seed, hipStream_t s) {
+  const int M = idx->pq_m, ds = idx->pq_ds, d = idx->d;
+  const int dsp = (int)round_up(ds, 8);
+  const int64_t nt = std::min<int64_t>(n, 65536);
+  std::vector<int64_t> rows(n);
+  std::iota(rows.begin(), rows.end(), 0);
+  if (nt < n) {
+    std::mt19937_64 rng(seed);
+    for (int64_t i = 0; i < nt; ++i) std::swap(rows[i], rows[i + (int64_t)(rng() % (uint64_t)(n - i))]);
+    rows.resize(nt);
+    std::sort(rows.begin(), rows.end());
+  }
+  Tmp<int64_t> d_rows(idx->mem, nt);
+  Tmp<float> sub(idx->mem, (size_t)nt * dsp), cent(idx->mem, (size_t)256 * dsp);
+  QK_HIP(hipMemcpyAsync(d_rows.p, rows.data(), nt * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  for (int m = 0; m < M; ++m) {
+    qk::launch_pq_subspace(x, nt, d, d_rows.p, m * ds, ds, dsp, sub.p, s);
+    kmeans(idx->mem, sub.p, nt, dsp, 256, iters, seed + (uint64_t)m, QUAKE_L2, cent.p, s);
+    QK_HIP(hipMemcpy2DAsync(idx->pq_book + (size_t)m * 256 * ds, ds * sizeof(float), cent.p, dsp * sizeof(float),
+                            ds * sizeof(float), 256, hipMemcpyDeviceToDevice, s));
+  }
+  QK_HIP(hipStreamSynchronize(s));
+}
+
 void build_store(quake_index* idx, Store& st, const float* xin, int d, const int64_t* ids, int64_t n,
                  const int32_t* d_assign, double slack, int dtype16, bool f32_tiles, hipStream_t s,
                  const uint32_t* attrs = nullptr) {
@@ -344,7 +387,7 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
   // partitions that outgrow their capacity (so that the first overflowing
   // inserts do not have to grow, and copy, the whole arena)
   const int64_t spare = slack > 0 ? (int64_t)std::ceil(tiles * slack) : 0;
-  alloc_store_arrays(idx, st, std::max<int64_t>(tiles + spare, 1), dtype16, f32_tiles, s);
+  alloc_store_arrays(idx, st, std::max<int64_t>(tiles + spare, 1), dtype16, f32_tiles, is_leaf(idx, st), s);
   st.tile_part.resize(std::max<int64_t>(tiles + spare, 1), -1);
   st.used_tiles = tiles;
   st.d_off = idx->mem.alloc<int64_t>(N);
@@ -365,6 +408,7 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
     qk::launch_scatter(xin, n, d, st.dp, st.dp16, ids, d_slot.p, st.v32, st.v16, dtype16, st.rows32, st.ids, s);
     qk::launch_norm16(st, dtype16, s);
     if (st.attr && attrs) qk::launch_put_u32(attrs, d_slot.p, n, st.attr, s);
+    if (st.codes) qk::launch_pq_encode(xin, n, d, d_slot.p, idx->pq_book, st.pq_m, idx->pq_ds, st.codes, s);
     QK_HIP(hipStreamSynchronize(s));
   }
   st.live = n;
@@ -378,7 +422,7 @@ void repack_arena(quake_index* idx, Store& st, int64_t tiles, hipStream_t s) {
   fresh.d = st.d;
   fresh.dp = st.dp;
   fresh.dp16 = st.dp16;
-  alloc_store_arrays(idx, fresh, tiles, st.v16 ? idx->storage : QUAKE_F32, st.v32 != nullptr, s);
+  alloc_store_arrays(idx, fresh, tiles, st.v16 ? idx->storage : QUAKE_F32, st.v32 != nullptr, is_leaf(idx, st), s);
   std::vector<int64_t> off(st.nlist);
   std::vector<int32_t> tile_part(tiles, -1);
   int64_t next = 0;
@@ -400,11 +444,16 @@ void repack_arena(quake_index* idx, Store& st, int64_t tiles, hipStream_t s) {
                               hipMemcpyDeviceToDevice, s));
       QK_HIP(hipMemcpyAsync(fresh.ids + b, st.ids + a, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
       if (st.attr) QK_HIP(hipMemcpyAsync(fresh.attr + b, st.attr + a, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+      if (st.codes) {
+        const size_t w = (size_t)st.pq_m / 4;  // code words per slot (tile-aligned ranges)
+        QK_HIP(hipMemcpyAsync(fresh.codes + b * w, st.codes + a * w, n * w * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+      }
     }
     next += st.cap[p] / qk::TILE;
   }
   QK_HIP(hipStreamSynchronize(s));
-  for (void* p : {(void*)st.v32, (void*)st.v16, (void*)st.v16n, (void*)st.rows32, (void*)st.ids, (void*)st.attr})
+  for (void* p : {(void*)st.v32, (void*)st.v16, (void*)st.v16n, (void*)st.rows32, (void*)st.ids, (void*)st.attr,
+                  (void*)st.codes})
     idx->mem.release(p);
   st.v32 = fresh.v32;
   st.v16 = fresh.v16;
@@ -412,6 +461,7 @@ void repack_arena(quake_index* idx, Store& st, int64_t tiles, hipStream_t s) {
   st.rows32 = fresh.rows32;
   st.ids = fresh.ids;
   st.attr = fresh.attr;
+  st.codes = fresh.codes;
   st.tiles = tiles;
   st.used_tiles = next;
   st.off.swap(off);
@@ -441,7 +491,7 @@ bool grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s, bool r
   fresh.d = st.d;
   fresh.dp = st.dp;
   fresh.dp16 = st.dp16;
-  alloc_store_arrays(idx, fresh, tiles, st.v16 ? idx->storage : QUAKE_F32, st.v32 != nullptr, s);
+  alloc_store_arrays(idx, fresh, tiles, st.v16 ? idx->storage : QUAKE_F32, st.v32 != nullptr, is_leaf(idx, st), s);
   const size_t used = (size_t)st.used_tiles * qk::TILE;
   if (st.v32) QK_HIP(hipMemcpyAsync(fresh.v32, st.v32, used * st.dp * sizeof(float), hipMemcpyDeviceToDevice, s));
   if (st.v16) QK_HIP(hipMemcpyAsync(fresh.v16, st.v16, used * st.dp16 * sizeof(uint16_t), hipMemcpyDeviceToDevice, s));
@@ -449,8 +499,11 @@ bool grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s, bool r
   if (st.rows32) QK_HIP(hipMemcpyAsync(fresh.rows32, st.rows32, used * st.dp * sizeof(float), hipMemcpyDeviceToDevice, s));
   QK_HIP(hipMemcpyAsync(fresh.ids, st.ids, used * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
   if (st.attr) QK_HIP(hipMemcpyAsync(fresh.attr, st.attr, used * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  if (st.codes)
+    QK_HIP(hipMemcpyAsync(fresh.codes, st.codes, used * (st.pq_m / 4) * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   QK_HIP(hipStreamSynchronize(s));
-  for (void* p : {(void*)st.v32, (void*)st.v16, (void*)st.v16n, (void*)st.rows32, (void*)st.ids, (void*)st.attr})
+  for (void* p : {(void*)st.v32, (void*)st.v16, (void*)st.v16n, (void*)st.rows32, (void*)st.ids, (void*)st.attr,
+                  (void*)st.codes})
     idx->mem.release(p);
   st.v32 = fresh.v32;
   st.v16 = fresh.v16;
@@ -458,6 +511,7 @@ bool grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s, bool r
   st.rows32 = fresh.rows32;
   st.ids = fresh.ids;
   st.attr = fresh.attr;
+  st.codes = fresh.codes;
   st.tiles = tiles;
   st.tile_part.resize(tiles, -1);
   return false;
@@ -483,6 +537,10 @@ void relocate(Store& st, int64_t p, int32_t cap, hipStream_t s) {
                             hipMemcpyDeviceToDevice, s));
     QK_HIP(hipMemcpyAsync(st.ids + b, st.ids + a, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     if (st.attr) QK_HIP(hipMemcpyAsync(st.attr + b, st.attr + a, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    if (st.codes) {
+      const size_t w = (size_t)st.pq_m / 4;
+      QK_HIP(hipMemcpyAsync(st.codes + b * w, st.codes + a * w, n * w * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    }
     // the old slots no longer hold the partition's vectors
     QK_HIP(hipMemsetAsync(st.ids + a, 0xff, (size_t)st.cap[p] * sizeof(int64_t), s));
   }
@@ -665,6 +723,7 @@ void insert_rows(quake_index* idx, Store& st, IdMap& map, const float* x, const 
   launch_scatter(x, n, idx->d, dp, st.dp16, ids, d_slot.p, st.v32, st.v16, st.v16 ? idx->storage : QUAKE_F32,
                  st.rows32, st.ids, s);
   launch_norm16_slots(st, d_slot.p, n, idx->storage, s);
+  if (st.codes) launch_pq_encode(x, n, idx->d, d_slot.p, idx->pq_book, st.pq_m, idx->pq_ds, st.codes, s);
   if (st.attr) {
     launch_put_u32(attrs, d_slot.p, n, st.attr, s);
     st.attr_dirty = true;
@@ -735,8 +794,9 @@ Job resolve(const quake_index* idx, const Store& st, const quake_search_params* 
   QK_CHECK(!has_rt || p->recall_target <= 1.0, QUAKE_E_INVALID, "recall_target must be in (0, 1]");
   QK_CHECK(p->scan_mode == QUAKE_SCAN_PLAIN || p->scan_mode == QUAKE_SCAN_BATCHED, QUAKE_E_INVALID,
            "unknown scan_mode");
-  QK_CHECK(p->scan_dtype == QUAKE_F32 || (p->scan_dtype == idx->storage && st.v16), QUAKE_E_INVALID,
-           "scan_dtype needs the matching reduced-precision copy in the index");
+  const bool pq = p->scan_dtype == QUAKE_PQ8;
+  QK_CHECK(p->scan_dtype == QUAKE_F32 || (p->scan_dtype == idx->storage && st.v16) || (pq && st.codes),
+           QUAKE_E_INVALID, "scan_dtype needs the matching reduced-precision copy (or product codes) in the index");
   QK_CHECK(p->f_M >= 0 && p->tau_rho >= 0 && p->upper_f_M >= 0 && p->upper_recall_target >= 0 &&
                p->upper_recall_target <= 1.0 && p->window >= 0,
            QUAKE_E_INVALID, "negative or out-of-range search parameter");
@@ -745,15 +805,17 @@ Job resolve(const quake_index* idx, const Store& st, const quake_search_params* 
   r.k = p->k;
   r.batched = p->scan_mode == QUAKE_SCAN_BATCHED ? 1 : 0;
   r.dtype16 = p->scan_dtype;
-  QK_CHECK(r.batched == (p->scan_dtype != QUAKE_F32 ? 1 : 0), QUAKE_E_INVALID,
-           "the batched scan runs on the 16-bit copy (scan_dtype BF16/F16) and the plain scan on FP32");
-  QK_CHECK(r.batched || st.v32, QUAKE_E_INVALID,
-           "the index keeps no FP32 tile copy (drop_f32_tiles): search with the batched scan");
+  QK_CHECK(r.batched == (p->scan_dtype != QUAKE_F32 && !pq ? 1 : 0), QUAKE_E_INVALID,
+           "the batched scan runs on the 16-bit copy (scan_dtype BF16/F16) and the plain scan on FP32 or on "
+           "product codes (PQ8)");
+  QK_CHECK(r.batched || pq || st.v32, QUAKE_E_INVALID,
+           "the index keeps no FP32 tile copy (drop_f32_tiles): search with the batched scan or product codes");
   QK_CHECK(p->rerank_factor >= -1, QUAKE_E_INVALID, "rerank_factor must be >= -1");
   QK_CHECK(p->rerank_factor >= 0 || r.batched, QUAKE_E_INVALID, "rerank_factor -1 is for the batched scan");
   r.rerank = p->rerank_factor >= 0 ? 1 : 0;
-  r.kk = r.batched ? (r.rerank ? std::max(p->rerank_factor > 0 ? p->rerank_factor : 4, 1) * r.k : r.k) : r.k;
-  QK_CHECK(!r.batched || r.kk <= 64, QUAKE_E_INVALID, "the batched scan keeps at most 64 candidates per query");
+  r.kk = r.batched || pq ? (r.rerank ? std::max(p->rerank_factor > 0 ? p->rerank_factor : 4, 1) * r.k : r.k) : r.k;
+  QK_CHECK(!(r.batched || pq) || r.kk <= 64, QUAKE_E_INVALID,
+           "the batched scan and the scan over product codes keep at most 64 candidates per query");
   QK_CHECK(!r.batched || st.dp16 <= 1024, QUAKE_E_INVALID, "the batched scan supports d <= 1024");
   r.aps = has_rt ? 1 : 0;
   r.tau_r = p->recall_target;
@@ -919,7 +981,8 @@ void launch_rounds(quake_index* idx, const Store& st, const Job& job, const Roun
         launch_emit(w, st, a, s);
       }
       ProfileScope ps(idx->prof, QUAKE_PROF_SCAN, s);
-      launch_scan_f32(w, st, a, s);
+      if (job.dtype16 == QUAKE_PQ8) launch_scan_pq(w, st, a, s);
+      else launch_scan_f32(w, st, a, s);
     }
     {
       ProfileScope ps(idx->prof, QUAKE_PROF_COMMIT, s);
@@ -951,6 +1014,9 @@ std::vector<uint64_t> graph_key(const quake_index* idx, const Store& st, const J
   k.push_back((uint64_t)a.est);
   k.push_back(u(a.qmask));
   k.push_back(u(a.attr));
+  k.push_back(u(st.codes));
+  k.push_back((uint64_t)st.pq_m);
+  k.push_back(u(w.lut));
   k.push_back(u(a.attr_cnt));
   return k;
 }
@@ -1147,6 +1213,18 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
     qk::launch_candidates(st, w.q, w.scores, nq, idx->dp, job.M, job.aps, idx->metric, w.mq, w.sel, w.cand, w.h, s);
   }
   if (job.batched) qk::launch_queries16(w, nq, idx->dp, st.dp16, job.dtype16, s);
+  const bool pq = job.dtype16 == QUAKE_PQ8;
+  if (pq) {
+    const int64_t need = nq * (int64_t)st.pq_m * 256;
+    if (need > w.lut_cap || !w.lut) {
+      idx->mem.release(w.lut);
+      w.lut = nullptr;
+      w.lut = idx->mem.alloc<float>(std::max<int64_t>(need, 1));
+      w.lut_cap = need;
+    }
+    qk::ProfileScope ps(idx->prof, QUAKE_PROF_SELECT, s);
+    qk::launch_pq_lut(w.q, nq, idx->dp, idx->pq_book, st.pq_m, idx->pq_ds, idx->metric, w.lut, s);
+  }
   qk::RoundArgs a{};
   a.nq = nq;
   a.M = job.M;
@@ -1156,7 +1234,8 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
   a.chunk_tiles = chunk_tiles;
   a.wmax = job.wmax;
   a.wscale = idx->tune.window_scale > 0 ? idx->tune.window_scale : 100;
-  a.slot_ids = job.batched && st.tiles * qk::TILE < (int64_t{1} << 31) ? 1 : 0;
+  // the batched scan and the scan over codes carry store slots (the rerank reads rows by slot)
+  a.slot_ids = (job.batched || pq) && st.tiles * qk::TILE < (int64_t{1} << 31) ? 1 : 0;
   a.metric = idx->metric;
   a.dim = idx->d;
   a.tau_r = job.tau_r;
@@ -1199,7 +1278,7 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
     rounds += R;
     chunk = std::min(chunk * 2, 8);
   }
-  if (job.batched) {
+  if (job.batched || pq) {
     {
       qk::ProfileScope ps(idx->prof, QUAKE_PROF_RERANK, s);
       qk::launch_rerank(w, st, a, s, job.rerank != 0);
@@ -1220,6 +1299,8 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
     idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[4] * idx->d * 2.0, (double)w.h_total[5] * idx->d * 2.0);
     idx->prof.add(QUAKE_PROF_SCAN_SETS, (double)w.h_total[9] * idx->d * 2.0, 0.0);
   }
+  else if (idx->prof.on && pq)  // one code byte and one table add per subspace and row
+    idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[6] * st.pq_m, (double)w.h_total[6] * st.pq_m);
   else if (idx->prof.on)
     idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[6] * idx->d * sizeof(float),
                   (double)w.h_total[6] * idx->d * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
@@ -1327,6 +1408,7 @@ void search_in_scratch(quake_index* idx, const float* q, int64_t nq, const quake
   QK_CHECK(idx->n_levels == 1, QUAKE_E_STATE, "the allocation-free search is for single-level indexes");
   const Store& L0 = idx->L0;
   const Job job = resolve(idx, L0, params);
+  QK_CHECK(job.dtype16 != QUAKE_PQ8, QUAKE_E_INVALID, "the allocation-free search does not scan product codes");
   if (nq == 0) return;
   QK_CHECK(q && out_ids && out_dist, QUAKE_E_INVALID, "q, out_ids and out_dist are required");
   const int64_t items = search_items(idx, L0, job, nq);
@@ -1478,8 +1560,16 @@ quake_index* qk::build_index(const float* x, const int64_t* ids, int64_t n, int3
   if (params->n_levels == 2)
     QK_CHECK(params->nlist_top >= 1 && params->nlist_top <= params->nlist, QUAKE_E_INVALID,
              "nlist_top must be in [1, nlist]");
-  QK_CHECK(params->drop_f32_tiles == 0 || (params->drop_f32_tiles == 1 && params->storage_dtype != QUAKE_F32),
-           QUAKE_E_INVALID, "drop_f32_tiles needs a 16-bit copy (storage_dtype BF16 or F16)");
+  QK_CHECK(params->pq_m >= 0 && (params->pq_m > 0 || !params->pq_codebook), QUAKE_E_INVALID,
+           "pq_m must be >= 0 (a pq_codebook needs pq_m > 0)");
+  if (params->pq_m > 0) {
+    QK_CHECK(params->pq_m % 4 == 0 && d % params->pq_m == 0 && d / params->pq_m <= qk::PQ_MAX_SUB, QUAKE_E_INVALID,
+             "pq_m must be a multiple of 4 that divides d, with d / pq_m <= 32");
+    QK_CHECK(params->pq_codebook || n >= 256, QUAKE_E_INVALID, "training a codebook needs at least 256 rows");
+  }
+  QK_CHECK(params->drop_f32_tiles == 0 ||
+               (params->drop_f32_tiles == 1 && (params->storage_dtype != QUAKE_F32 || params->pq_m > 0)),
+           QUAKE_E_INVALID, "drop_f32_tiles needs a 16-bit copy (storage_dtype BF16 or F16) or product codes");
   const bool f32_tiles = params->drop_f32_tiles == 0;
   std::unique_ptr<quake_index> idx(new quake_index());
   if (allocator && allocator->alloc) idx->mem.user = *allocator;
@@ -1519,6 +1609,20 @@ quake_index* qk::build_index(const float* x, const int64_t* ids, int64_t n, int3
     xpad_buf.reset(new Tmp<float>(idx->mem, (size_t)n * dp));
     qk::launch_pad_rows(x, n, d, dp, xpad_buf->p, nullptr, s);
     xpad = xpad_buf->p;
+  }
+
+  if (params->pq_m > 0) {
+    // the codebook comes before the store: build_store encodes the rows
+    idx->pq_m = params->pq_m;
+    idx->pq_ds = d / params->pq_m;
+    const size_t book = (size_t)idx->pq_m * 256 * idx->pq_ds;
+    idx->pq_book = idx->mem.alloc<float>(book);
+    if (params->pq_codebook) {
+      require_finite(idx.get(), params->pq_codebook, (int64_t)book, "pq_codebook", s);
+      QK_HIP(hipMemcpyAsync(idx->pq_book, params->pq_codebook, book * sizeof(float), hipMemcpyDeviceToDevice, s));
+    } else {
+      train_codebook(idx.get(), x, n, params->kmeans_iters, params->seed, s);
+    }
   }
 
   Store& L0 = idx->L0;
@@ -1897,6 +2001,34 @@ int quake_export(const quake_index* cidx, float* centroids, int64_t* ids, int32_
       QK_HIP(hipMemcpyAsync(ids, o_ids.data(), o_ids.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
     if (part && !o_part.empty())
       QK_HIP(hipMemcpyAsync(part, o_part.data(), o_part.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  }
+  QK_HIP(hipStreamSynchronize(s));
+  API_END
+}
+
+int quake_export_pq(const quake_index* cidx, int32_t* m, float* codebook, uint8_t* codes, void* stream) {
+  API_BEGIN
+  check_index(cidx);
+  quake_index* idx = const_cast<quake_index*>(cidx);
+  hipStream_t s = as_stream(stream);
+  const Store& st = idx->L0;
+  if (m) *m = idx->pq_m;
+  if (idx->pq_m > 0 && codebook)
+    QK_HIP(hipMemcpyAsync(codebook, idx->pq_book, (size_t)idx->pq_m * 256 * idx->pq_ds * sizeof(float),
+                          hipMemcpyDeviceToDevice, s));
+  if (idx->pq_m > 0 && codes && st.live > 0) {
+    // live slots partition by partition, as quake_export lists the rows
+    std::vector<int64_t> sid((size_t)st.tiles * qk::TILE);
+    QK_HIP(hipMemcpyAsync(sid.data(), st.ids, sid.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+    std::vector<int64_t> slots;
+    slots.reserve(st.live);
+    for (int64_t p = 0; p < st.nlist; ++p)
+      for (int64_t j = 0; j < st.size[p]; ++j)
+        if (sid[st.off[p] * qk::TILE + j] >= 0) slots.push_back(st.off[p] * qk::TILE + j);
+    Tmp<int64_t> d_slots(idx->mem, slots.size());
+    QK_HIP(hipMemcpyAsync(d_slots.p, slots.data(), slots.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    qk::launch_pq_export(st, d_slots.p, (int64_t)slots.size(), codes, s);
   }
   QK_HIP(hipStreamSynchronize(s));
   API_END

@@ -45,6 +45,7 @@ inline int padded_dim16(int d) {
   return 32 * need;
 }
 constexpr int MAX_DIM = 4096;
+constexpr int PQ_MAX_SUB = 32;    // dimensions per product-quantization subspace
 constexpr int COUNTERS = 32;      // device counters of a search (Workspace::total)
 constexpr int MAX_CANDIDATES = 4096;   // APS candidate set M (and nprobe) upper bound
 
@@ -103,6 +104,8 @@ struct Store {
   int64_t* ids = nullptr;       // [tiles * 64], -1 = empty or deleted
   uint32_t* attr = nullptr;     // [tiles * 64] label bits of every slot (level 0 of a labelled index), or null
   uint32_t* d_attr_cnt = nullptr;  // [nlist][33]: live rows carrying each label bit, then live rows
+  int32_t pq_m = 0;             // subspaces of the product-quantized copy (level 0), 0 = none
+  uint32_t* codes = nullptr;    // [tiles][pq_m/4][64]: four one-byte codes of a slot per word, or null
   mutable bool attr_dirty = true;  // d_attr_cnt must be recounted before the next filtered search
   int64_t live = 0;
   std::vector<int32_t> tomb;     // deleted slots still inside size[p]
@@ -126,6 +129,8 @@ struct Workspace {
   int32_t* mq1 = nullptr;       // [nq] their number
   int64_t cand1_cap = 0, mq1_cap = 0;
   float* h = nullptr;           // [nq][M] bisector distances in scan order
+  float* lut = nullptr;         // [nq][pq_m][256] per-query code tables of a search over product codes
+  int64_t lut_cap = 0;
   int32_t* st_m = nullptr;      // committed partitions
   int32_t* st_w = nullptr;      // window the query asks for in the next round
   int32_t* st_weff = nullptr;   // window it got in the current round
@@ -226,6 +231,8 @@ struct quake_index {
   quake_tuning tune{};
   double slack = 0.0;           // capacity_slack of the build (kept for save / load)
   bool labelled = false;        // level-0 rows carry label bits (filtered searches)
+  int32_t pq_m = 0, pq_ds = 0;  // product quantization: subspaces and dimensions per subspace (0 = none)
+  float* pq_book = nullptr;     // [pq_m][256][pq_ds] codebook of level 0's codes
   int cu_count = 0;
   // captured scan rounds, keyed by every argument their kernels take
   struct Graph {
@@ -313,6 +320,16 @@ void launch_round_init(Workspace& ws, const RoundArgs& a, int w0, hipStream_t s)
 void launch_demand(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
 void launch_emit(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
 void launch_scan_f32(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
+// Product quantization: subspace columns of sampled rows, codes at store
+// slots, per-query tables, the scan over codes, and codes by slot.
+void launch_pq_subspace(const float* x, int64_t nr, int d, const int64_t* rows, int col0, int ds, int dsp, float* out,
+                        hipStream_t s);
+void launch_pq_encode(const float* x, int64_t n, int d, const int64_t* slot, const float* book, int M, int ds,
+                      uint32_t* codes, hipStream_t s);
+void launch_pq_lut(const float* q, int64_t nq, int dp, const float* book, int M, int ds, int metric, float* lut,
+                   hipStream_t s);
+void launch_scan_pq(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
+void launch_pq_export(const Store& st, const int64_t* slots, int64_t n, uint8_t* out, hipStream_t s);
 void launch_commit(Workspace& ws, const Store& st, const RoundArgs& a, const double* table, hipStream_t s);
 void launch_finalize(Workspace& ws, const RoundArgs& a, int64_t* out_ids, float* out_dist,
                      int32_t* out_nscanned, double* out_recall, hipStream_t s);

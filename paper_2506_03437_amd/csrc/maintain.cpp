@@ -687,6 +687,9 @@ int quake_profile_latency(quake_index* index, const int32_t* sizes, int32_t poin
       quake_build_params bp{};
       bp.metric = index->metric;
       bp.storage_dtype = index->storage;
+      // the same product codes (same codebook): a search over codes profiles lambda for that scan
+      bp.pq_m = index->pq_m;
+      bp.pq_codebook = index->pq_book;
       bp.n_levels = 1;
       bp.nlist = PARTS;
       bp.assign = assign.p;

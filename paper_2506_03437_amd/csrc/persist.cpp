@@ -4,15 +4,19 @@
 // level-0 centroids, the access statistics, a two-level index's level 1
 // (its centroids and the top partition of every level-0 centroid), and every
 // live vector with its id, partition and (for a labelled index) label bits,
-// partition by partition in store order.  Loading builds a fresh store from that content with the given
+// partition by partition in store order, and the product-quantization
+// codebook when the index keeps codes (loading re-encodes the rows with it,
+// which gives the same codes).  Loading builds a fresh store from that content with the given
 // centroids and assignment, so each partition keeps its rows in the saved
 // order (deleted slots and relocation gaps are gone) and every search on the
 // loaded index sees the same partitions, centroids and rows.
 //
 // Layout (little-endian): a 128-byte header (magic "QUAKEIX1", version,
 // sizes, metric, storage, capacity slack, scheduling knobs, access window),
-// then the sections above as flat arrays, then the 64-bit FNV-1a hash of all
-// bytes before it.  A file is written to "<path>.tmp" and renamed into place.
+// from version 2 a 16-byte extension (product-quantization subspaces and
+// their width), then the sections above as flat arrays, then the 64-bit
+// FNV-1a hash of all bytes before it.  Version 1 files (no extension, no
+// codes) still load.  A file is written to "<path>.tmp" and renamed into place.
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
@@ -27,7 +31,7 @@ namespace qk {
 namespace {
 
 constexpr char kMagic[8] = {'Q', 'U', 'A', 'K', 'E', 'I', 'X', '1'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 constexpr int64_t kChunkRows = 65536;  // rows per device <-> host transfer
 
 struct FileHeader {
@@ -41,6 +45,13 @@ struct FileHeader {
   int64_t nlist_top2;  // level-2 partitions of a three-level index, else 0
 };
 static_assert(sizeof(FileHeader) == 128, "file header is 128 bytes");
+
+// Version 2 and later: follows the header.
+struct FileHeaderExt {
+  int32_t pq_m, pq_ds;  // product quantization (0, 0 = none)
+  int64_t reserved;
+};
+static_assert(sizeof(FileHeaderExt) == 16, "header extension is 16 bytes");
 
 // 64-bit FNV-1a over the bytes written or read so far.
 struct Hash {
@@ -159,6 +170,8 @@ void save(quake_index* idx, const char* path, hipStream_t s) {
   QK_CHECK(file.f, QUAKE_E_IO, "cannot open " + tmp + " for writing");
   Writer w{file.f, {}};
   w.put(&hd, sizeof(hd));
+  FileHeaderExt ext{idx->pq_m, idx->pq_ds, 0};
+  w.put(&ext, sizeof(ext));
   const std::vector<float> C0 = strip_rows(st.centroids, st.nlist, d, dp, s);
   w.put(C0.data(), C0.size() * sizeof(float));
   std::vector<uint32_t> hits(st.nlist);
@@ -191,6 +204,12 @@ void save(quake_index* idx, const char* path, hipStream_t s) {
       w.put(h.data(), h.size() * sizeof(float));
     }
   }
+  if (idx->pq_m > 0) {
+    std::vector<float> book((size_t)idx->pq_m * 256 * idx->pq_ds);
+    QK_HIP(hipMemcpyAsync(book.data(), idx->pq_book, book.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+    w.put(book.data(), book.size() * sizeof(float));
+  }
   const uint64_t sum = w.hash.h;
   QK_CHECK(std::fwrite(&sum, 1, 8, file.f) == 8, QUAKE_E_IO, "write failed");
   QK_CHECK(std::fflush(file.f) == 0, QUAKE_E_IO, "write failed");
@@ -208,13 +227,19 @@ quake_index* load(const char* path, const quake_allocator* allocator, size_t hbm
   FileHeader hd;
   r.get(&hd, sizeof(hd));
   QK_CHECK(std::memcmp(hd.magic, kMagic, 8) == 0, QUAKE_E_INVALID, "not a saved index (magic)");
-  QK_CHECK(hd.version == kVersion && hd.header_bytes == sizeof(FileHeader), QUAKE_E_INVALID,
+  QK_CHECK((hd.version == 1 || hd.version == kVersion) && hd.header_bytes == sizeof(FileHeader), QUAKE_E_INVALID,
            "unsupported file version");
+  FileHeaderExt ext{0, 0, 0};
+  if (hd.version >= 2) r.get(&ext, sizeof(ext));
   QK_CHECK(hd.d >= 1 && hd.d <= MAX_DIM && hd.nlist >= 1 && hd.nlist <= INT32_MAX && hd.n_live >= 1 &&
                (hd.n_levels == 1 || (hd.n_levels >= 2 && hd.n_levels <= 3 && hd.nlist_top >= 1 && hd.nlist_top <= hd.nlist)) &&
                (hd.n_levels == 3 ? hd.nlist_top2 >= 1 && hd.nlist_top2 <= hd.nlist_top : hd.nlist_top2 == 0) &&
                hd.capacity_slack >= 0 && hd.window >= 0 && (hd.labelled == 0 || hd.labelled == 1),
            QUAKE_E_INVALID, "corrupt header");
+  QK_CHECK(ext.pq_m == 0 ? ext.pq_ds == 0
+                         : ext.pq_m > 0 && ext.pq_m % 4 == 0 && hd.d % ext.pq_m == 0 && ext.pq_ds == hd.d / ext.pq_m &&
+                               ext.pq_ds <= PQ_MAX_SUB,
+           QUAKE_E_INVALID, "corrupt header (product quantization)");
   const int d = hd.d;
   const int64_t n = hd.n_live, N = hd.nlist;
 
@@ -259,6 +284,11 @@ quake_index* load(const char* path, const quake_allocator* allocator, size_t hbm
   }
   Buf<float> x(tmp, (size_t)n * d);
   to_device(x.p, (size_t)n * d * sizeof(float));
+  std::unique_ptr<Buf<float>> book;
+  if (ext.pq_m > 0) {
+    book.reset(new Buf<float>(tmp, (size_t)ext.pq_m * 256 * ext.pq_ds));
+    to_device(book->p, (size_t)ext.pq_m * 256 * ext.pq_ds * sizeof(float));
+  }
   const uint64_t expect = r.hash.h;
   uint64_t sum = 0;
   QK_CHECK(std::fread(&sum, 1, 8, file.f) == 8, QUAKE_E_INVALID, "the file ends early: not a complete saved index");
@@ -277,6 +307,8 @@ quake_index* load(const char* path, const quake_allocator* allocator, size_t hbm
   bp.capacity_slack = hd.capacity_slack;
   bp.drop_f32_tiles = hd.drop_f32_tiles;
   bp.attrs = attr ? attr->p : nullptr;
+  bp.pq_m = ext.pq_m;
+  bp.pq_codebook = book ? book->p : nullptr;
   std::unique_ptr<quake_index> idx(
       build_index(x.p, ids.p, n, d, &bp, C1 ? C1->p : nullptr, top ? top->p : nullptr, allocator, s));
   if (hd.n_levels == 3) {

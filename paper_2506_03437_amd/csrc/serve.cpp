@@ -87,6 +87,7 @@ void clone_store(qk::DeviceMemory& mem, const qk::Store& a, const qk::IdMap& am,
     t.rows32 = dup(mem, got, a.rows32, slots * a.dp, s);
     t.ids = dup(mem, got, a.ids, slots, s);
     t.attr = dup(mem, got, a.attr, slots, s);
+    t.codes = dup(mem, got, a.codes, slots * (a.pq_m / 4), s);
     t.d_attr_cnt = dup(mem, got, a.d_attr_cnt, N * 33, s);
     qk::IdMap tm = am;
     tm.keys = dup(mem, got, am.keys, (size_t)am.mask + 1, s);
@@ -103,7 +104,7 @@ void clone_store(qk::DeviceMemory& mem, const qk::Store& a, const qk::IdMap& am,
 void free_store(qk::DeviceMemory& mem, qk::Store& b, qk::IdMap& bm) {
   for (void* p : {(void*)b.centroids, (void*)b.d_off, (void*)b.d_size, (void*)b.d_cap, (void*)b.d_order,
                   (void*)b.v32, (void*)b.v16, (void*)b.v16n, (void*)b.rows32, (void*)b.ids, (void*)b.attr,
-                  (void*)b.d_attr_cnt, (void*)bm.keys, (void*)bm.vals})
+                  (void*)b.d_attr_cnt, (void*)b.codes, (void*)bm.keys, (void*)bm.vals})
     mem.release(p);
   b = qk::Store();
   bm = qk::IdMap();
@@ -638,6 +639,7 @@ int quake_server_create(quake_index* idx, const quake_server_params* params, qua
   QK_CHECK(idx->n_levels == 1, QUAKE_E_INVALID, "the serving loop runs on single-level indexes");
   QK_CHECK(params->max_slots >= 0, QUAKE_E_INVALID, "max_slots must be >= 0");
   QK_CHECK(!params->search.filter, QUAKE_E_INVALID, "the serving loop takes no filter (requests carry no masks)");
+  QK_CHECK(params->search.scan_dtype != QUAKE_PQ8, QUAKE_E_INVALID, "the serving loop does not scan product codes");
   QK_CHECK(params->overlap_updates == 0 || params->overlap_updates == 1, QUAKE_E_INVALID,
            "overlap_updates must be 0 or 1");
   std::unique_ptr<quake_server> srv(new quake_server());

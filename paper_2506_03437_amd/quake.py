@@ -20,10 +20,12 @@ LIB_PATH = os.path.join(_HERE, "libquake_mi355x.so")
 OK, E_INVALID, E_NOMEM, E_NOTFOUND, E_DUPLICATE, E_DEVICE, E_STATE, E_IO = 0, -1, -2, -3, -4, -5, -6, -7
 L2, IP = 0, 1
 F32, BF16, F16 = 0, 1, 2
+PQ8 = 3   # scan_dtype of a search over product codes
 SCAN_PLAIN, SCAN_BATCHED = 0, 1
 
 _METRIC = {"l2": L2, "ip": IP}
 _DTYPE = {"f32": F32, "bf16": BF16, "f16": F16}
+_SCAN_DTYPE = dict(_DTYPE, pq8=PQ8)
 _MODE = {"plain": SCAN_PLAIN, "batched": SCAN_BATCHED}
 
 EXPORTED = ("quake_build", "quake_search", "quake_search_noalloc", "quake_insert", "quake_delete", "quake_stats", "quake_export",
@@ -32,7 +34,7 @@ EXPORTED = ("quake_build", "quake_search", "quake_search_noalloc", "quake_insert
             "quake_server_delete", "quake_server_wait", "quake_server_stats", "quake_server_destroy",
             "quake_access_stats", "quake_maintain", "quake_profile_latency", "quake_describe", "quake_save",
             "quake_load", "quake_insert_attrs", "quake_add_level", "quake_remove_level", "quake_adjust_levels",
-            "quake_export_level", "quake_level_sizes")
+            "quake_export_level", "quake_level_sizes", "quake_export_pq")
 PROF_KINDS = ("centroids", "select", "plan", "scan", "commit", "rerank", "scan_sets", "upper")
 
 
@@ -47,7 +49,8 @@ class BuildParams(ctypes.Structure):
                 ("kmeans_iters", ctypes.c_int32), ("nlist", ctypes.c_int64), ("nlist_top", ctypes.c_int64),
                 ("seed", ctypes.c_uint64), ("centroids", ctypes.c_void_p), ("assign", ctypes.c_void_p),
                 ("hbm_budget_bytes", ctypes.c_size_t), ("capacity_slack", ctypes.c_double),
-                ("drop_f32_tiles", ctypes.c_int32), ("attrs", ctypes.c_void_p)]
+                ("drop_f32_tiles", ctypes.c_int32), ("attrs", ctypes.c_void_p), ("pq_m", ctypes.c_int32),
+                ("pq_codebook", ctypes.c_void_p)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -158,6 +161,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.quake_delete.argtypes = [vp, vp, i64, vp]
     lib.quake_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_size_t)]
     lib.quake_export.argtypes = [vp, vp, vp, vp, vp]
+    lib.quake_export_pq.argtypes = [vp, ctypes.POINTER(i32), vp, vp, vp]
     lib.quake_export_top.argtypes = [vp, vp, vp, vp]
     lib.quake_describe.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                                    ctypes.POINTER(i32)]
@@ -234,9 +238,11 @@ def quake_cap_table(d: int) -> np.ndarray:
 
 def quake_build(x, ids=None, *, metric="l2", nlist=256, storage="f32", n_levels=1, nlist_top=0, kmeans_iters=10,
                 seed=0, centroids=None, assign=None, hbm_budget_bytes=0, capacity_slack=0.0,
-                allocator="torch", f32_tiles=True, attrs=None) -> int:
+                allocator="torch", f32_tiles=True, attrs=None, pq_m=0, pq_codebook=None) -> int:
     """allocator: "torch" (the caching allocator of x's device, the default) or "hip" (hipMalloc).
-    f32_tiles=False (with a 16-bit storage copy): no FP32 tile copy, batched searches only."""
+    f32_tiles=False (with a 16-bit storage copy or product codes): no FP32 tile copy.
+    pq_m > 0: also keep product codes of pq_m subspaces (searched with scan_dtype="pq8"), with the
+    codebook pq_codebook (device f32 [pq_m, 256, d / pq_m]) or one trained on x."""
     import torch
     _dev(x, torch.float32)
     if ids is not None:
@@ -247,9 +253,11 @@ def quake_build(x, ids=None, *, metric="l2", nlist=256, storage="f32", n_levels=
         _dev(assign, torch.int32)
     if attrs is not None:
         _labels(attrs)
+    if pq_codebook is not None:
+        _dev(pq_codebook, torch.float32)
     p = BuildParams(_METRIC[metric], _DTYPE[storage], n_levels, kmeans_iters, nlist, nlist_top, seed,
                     _ptr(centroids), _ptr(assign), hbm_budget_bytes, capacity_slack, 0 if f32_tiles else 1,
-                    _ptr(attrs))
+                    _ptr(attrs), pq_m, _ptr(pq_codebook))
     if allocator not in ("torch", "hip"):
         raise ValueError(f"allocator must be 'torch' or 'hip', not {allocator!r}")
     alloc = ctypes.byref(torch_allocator(x.device.index or 0)) if allocator == "torch" else None
@@ -270,7 +278,7 @@ def _search_params(k=10, nprobe=0, recall_target=0.0, f_M=0.0, tau_rho=0.0, uppe
                    estimator="aps", filter=None) -> SearchParams:
     est = ESTIMATORS[estimator] if isinstance(estimator, str) else int(estimator)
     return SearchParams(k, nprobe, recall_target, f_M, tau_rho, upper_recall_target, upper_f_M, _MODE[scan_mode],
-                        _DTYPE[scan_dtype], rerank_factor, window, est,
+                        _SCAN_DTYPE[scan_dtype], rerank_factor, window, est,
                         None if filter is None else _labels(filter).data_ptr())
 
 
@@ -346,6 +354,23 @@ def quake_export(handle: int, d: int):
     part = torch.empty((max(n_live, 1),), dtype=torch.int32, device=dev)
     _check(load_library().quake_export(handle, _ptr(C), _ptr(ids), _ptr(part), _stream()))
     return C, ids[:n_live], part[:n_live]
+
+
+def quake_export_pq(handle: int, d: int):
+    """(codebook f32 [m, 256, d / m], codes uint8 [n_live, m]) of the index's product
+    quantization, codes in quake_export's row order; (None, None) without codes."""
+    import torch
+    lib = load_library()
+    m = ctypes.c_int32()
+    _check(lib.quake_export_pq(handle, ctypes.byref(m), None, None, _stream()))
+    if m.value == 0:
+        return None, None
+    n_live, _, _ = quake_stats(handle)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    book = torch.empty((m.value, 256, d // m.value), dtype=torch.float32, device=dev)
+    codes = torch.empty((max(n_live, 1), m.value), dtype=torch.uint8, device=dev)
+    _check(lib.quake_export_pq(handle, ctypes.byref(m), _ptr(book), _ptr(codes), _stream()))
+    return book, codes[:n_live]
 
 
 def quake_export_top(handle: int, d: int, nlist_top: int):
@@ -663,6 +688,9 @@ class Index:
 
     def export(self):
         return quake_export(self.handle, self.d)
+
+    def export_pq(self):
+        return quake_export_pq(self.handle, self.d)
 
     def candidates(self, q, f_M=0.05, **upper_kw):
         return quake_candidates(self.handle, q, f_M, **upper_kw)

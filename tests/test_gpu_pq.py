@@ -1,0 +1,318 @@
+"""Product-quantized rows on the device against the oracle (Sec. 8, "Vector
+Compression"; readings P1-P4).
+
+The device's codes are the oracle's nearest codewords (up to FP32 near-ties),
+for a given codebook and for one the device trained; they follow their rows
+through inserts, deletes, maintenance and a save and load.  With a lossless
+codebook on small-integer rows the scan over codes scores every row exactly,
+and the search equals the plain FP32 search decision for decision.  On
+real-valued rows each query's results are checked against the oracle's
+scores over the partitions the device scanned (the kept candidates are the
+best r * k by score up to FP32 near-ties, re-scored exactly), and the stop
+counts and recall estimates replay the oracle's adaptive search over the
+scores.  lambda is profiled on the scan over codes.  Unsupported
+combinations are refused.
+"""
+
+import numpy as np
+import pytest
+
+import gpu_util as gu
+import parity
+import synth
+from oracle import aps as oaps
+from oracle import ivf as oivf
+from oracle import knn as oknn
+from oracle import pq as opq
+
+pytestmark = pytest.mark.gpu
+
+M = 16   # subspaces of the 64-dimensional workloads (4 dimensions each)
+
+
+def _f32(a):
+    return gu.to_dev(np.ascontiguousarray(a, dtype=np.float32))
+
+
+def codes_by_row(idx, n):
+    """Codebook (FP64 of the device's FP32 values) and codes [n][m] by row (ids are rows)."""
+    book, codes = idx.export_pq()
+    _, eids, _ = idx.export()
+    out = np.empty((n, codes.shape[1]), dtype=np.uint8)
+    out[eids.cpu().numpy()] = codes.cpu().numpy()
+    return book.cpu().numpy().astype(np.float64), out
+
+
+def code_violations(X, codes, books):
+    """(row, subspace) pairs whose code is not the nearest codeword beyond
+    FP32 rounding of the distances."""
+    m, _, ds = books.shape
+    bad = []
+    for s in range(m):
+        sub = np.asarray(X, dtype=np.float64)[:, s * ds:(s + 1) * ds]
+        dist = ((sub[:, None, :] - books[s][None]) ** 2).sum(-1)
+        got = dist[np.arange(sub.shape[0]), codes[:, s].astype(np.int64)]
+        best = dist.min(1)
+        scale = (sub ** 2).sum(1) + (books[s] ** 2).sum(1).max()
+        bad += [(int(r), s) for r in np.nonzero(got - best > 1e-5 * scale + 1e-12)[0]]
+    return bad
+
+
+def check_pq_results(q, X, ps, codes, books, parts, kk, k, metric, gi, gv, where):
+    """One query's device results against the oracle's scores over the
+    partitions `parts`: every result is among the best kk rows by score
+    (up to FP32 rounding of the scores), carries its exact value, and no row
+    surely among those kk with a better exact value than the k-th result is
+    missing."""
+    rows = np.concatenate([ps.members[int(p)] for p in parts])
+    T = opq.tables(q, books, metric)
+    s = opq.asymmetric(q, codes[rows], books, metric)
+    key = -s if metric == "ip" else s
+    stol = 1e-5 * float(np.abs(T).max(1).sum()) + 1e-6
+    b = np.sort(key)[min(kk, key.size) - 1]
+    n_res = min(k, rows.size)
+    live = gi[gi >= 0]
+    assert live.size == n_res, f"{where}: {live.size} results, expected {n_res}"
+    assert len(set(live.tolist())) == live.size, f"{where}: repeated ids"
+    pos = {int(ps.ids[r]): j for j, r in enumerate(rows)}
+    assert all(int(i) in pos for i in live), f"{where}: a result outside the scanned partitions"
+    rkey = np.array([key[pos[int(i)]] for i in live])
+    assert (rkey <= b + stol).all(), f"{where}: a result is not among the best {kk} scores"
+    id_to_row = {int(i): r for r, i in enumerate(ps.ids.tolist())}
+    tv = parity.true_values(q, X, id_to_row, live, metric)
+    tol = parity.value_tol(q, X, metric, tv)
+    assert (np.abs(gv[:n_res] - tv) <= tol).all(), f"{where}: reported values are not the exact ones"
+    ek = parity.key_of(gv[:n_res], metric)
+    assert (np.diff(ek) >= 0).all(), f"{where}: results are not sorted"
+    sure = rows[key < b - stol]
+    if sure.size:
+        ex = parity.key_of(oknn.distances(q[None], X[sure], metric)[0], metric)
+        ktol = float(parity.value_tol(q, X, metric, np.array([gv[n_res - 1]]))[0])
+        must = set(int(ps.ids[r]) for r, e in zip(sure, ex) if e < ek[-1] - ktol)
+        assert must <= set(live.tolist()), f"{where}: missing {sorted(must - set(live.tolist()))[:5]}"
+
+
+@pytest.fixture(scope="module", params=["l2", "ip"])
+def real(request):
+    metric = request.param
+    spec = synth.MixtureSpec(key=71, n=30_000, d=64, n_components=40, zipf_s=1.1, unit_norm=metric == "ip")
+    X = synth.database(spec)
+    Q = synth.queries(spec, 200)
+    print(f"[build] product codes {metric} n={X.shape[0]} d=64 m={M} nlist=100 (codebook trained on the device)",
+          flush=True)
+    idx = gu.build(X, metric=metric, nlist=100, kmeans_iters=4, seed=3, pq_m=M)
+    ps = gu.oracle_view(idx, X)
+    books, codes = codes_by_row(idx, X.shape[0])
+    yield metric, X, Q, idx, ps, books, codes
+    idx.free()
+
+
+def test_trained_codes_are_nearest_codewords(real):
+    metric, X, Q, idx, ps, books, codes = real
+    assert books.shape == (M, 256, 4)
+    sample = np.random.default_rng(1).choice(X.shape[0], 4000, replace=False)
+    bad = code_violations(X[sample], codes[sample], books)
+    assert not bad, f"{len(bad)} codes are not the nearest codeword, e.g. {bad[:3]}"
+    # training found structure: the codes beat one codeword per subspace by far
+    err = ((X[sample] - opq.decode(codes[sample], books)) ** 2).sum(1).mean()
+    spread = ((X[sample] - X[sample].mean(0)) ** 2).sum(1).mean()
+    assert err < 0.5 * spread
+
+
+@pytest.mark.parametrize("tau", [0.8, 0.95])
+def test_adaptive_search_over_codes_follows_the_oracle(real, tau):
+    metric, X, Q, idx, ps, books, codes = real
+    f_M, k, r = 0.2, 10, 4
+    gi, gv, ns, rec = gu.search(idx, Q, k=k, recall_target=tau, f_M=f_M, scan_dtype="pq8", rerank_factor=r)
+    order, h = idx.candidates(gu.to_dev(Q), f_M)
+    order, h = order.cpu().numpy(), h.cpu().numpy()
+    table = oaps.CapTable(X.shape[1])
+    params = oaps.APSParams(k=k, recall_target=tau, f_M=f_M, metric=metric)
+    ordered = margin = 0
+    for i in range(Q.shape[0]):
+        m = int(ns[i])
+        check_pq_results(Q[i], X, ps, codes, books, order[i, :m], r * k, k, metric, gi[i], gv[i], f"query {i}")
+        if not parity.check_candidate_order(Q[i], ps.C, f_M, metric, order[i], h[i]):
+            continue
+        ordered += 1
+        vals = oknn.distances(Q[i][None], ps.C, metric)[0]
+        h_ref = oaps.bisector_distances(Q[i], ps.C, vals, int(order[i, 0]), order[i, 1:].astype(np.int64), metric)
+        _, _, res = opq.pq_search_one(ps, codes, books, Q[i], params, table, r * k, order=order[i].astype(np.int64),
+                                      h=h_ref)
+        if res.m != m:
+            assert parity.replay_margin(res, tau, 0.01, max(res.m, m)), f"query {i}: device {m}, oracle {res.m}"
+            margin += 1
+        else:
+            assert abs(rec[i] - res.steps[-1].recall) < 1e-4, f"query {i}: estimate {rec[i]} vs {res.steps[-1].recall}"
+    assert ordered >= 0.95 * Q.shape[0]
+    assert margin <= max(2, 0.01 * Q.shape[0])
+
+
+def test_fixed_nprobe_over_codes(real):
+    metric, X, Q, idx, ps, books, codes = real
+    gi, gv, ns, _ = gu.search(idx, Q, k=10, nprobe=5, scan_dtype="pq8", rerank_factor=3)
+    checked = 0
+    for i in range(Q.shape[0]):
+        key = np.sort(oknn.sort_key(oknn.distances(Q[i][None], ps.C, metric)[0], metric))
+        if abs(key[5] - key[4]) <= 1e-5 * max(abs(key[4]), 1e-6):
+            continue  # the fifth and sixth centroids tie in FP32
+        _, order = oivf.centroid_ranking(Q[i], ps.C, metric)
+        check_pq_results(Q[i], X, ps, codes, books, order[:5], 30, 10, metric, gi[i], gv[i], f"query {i}")
+        checked += 1
+    assert checked >= 0.97 * Q.shape[0]
+
+
+def lossless_rows(rng, n, m, ds, distinct=200, lo=-6, hi=6):
+    books = np.empty((m, 256, ds))
+    X = np.empty((n, m * ds))
+    comp = rng.integers(0, 12, n)       # twelve clusters: rows of one cluster share most subvectors
+    for s in range(m):
+        vals = set()
+        while len(vals) < distinct:
+            vals.add(tuple(rng.integers(lo, hi + 1, ds).tolist()))
+        vals = np.array(sorted(vals), dtype=np.float64)
+        books[s, :distinct] = vals
+        books[s, distinct:] = 1000.0 + np.arange(256 - distinct)[:, None]
+        home = rng.integers(0, distinct, 12)
+        pick = np.where(rng.random(n) < 0.7, home[comp], rng.integers(0, distinct, n))
+        X[:, s * ds:(s + 1) * ds] = vals[pick]
+    return X.astype(np.float32), books
+
+
+def test_lossless_codes_give_the_plain_search():
+    """Small-integer rows with a codebook that holds every subvector: every
+    score is the exact FP32 distance, so the search over codes decides as
+    the plain FP32 search does and replays the oracle's exact search."""
+    rng = np.random.default_rng(72)
+    X, books = lossless_rows(rng, 20_000, 8, 4)
+    Q = rng.integers(-6, 7, (256, 32)).astype(np.float32)
+    print("[build] lossless product codes l2 n=20000 d=32 m=8 nlist=40", flush=True)
+    idx = gu.build(X, metric="l2", nlist=40, kmeans_iters=4, seed=5, pq_m=8, pq_codebook=_f32(books))
+    b, codes = codes_by_row(idx, X.shape[0])
+    np.testing.assert_array_equal(b, books.astype(np.float32).astype(np.float64))
+    np.testing.assert_array_equal(opq.decode(codes, b), X)
+    ps = gu.oracle_view(idx, X)
+    kw = dict(k=10, recall_target=0.9, f_M=0.3)
+    gi, gv, ns, rec = gu.search(idx, Q, scan_dtype="pq8", rerank_factor=4, **kw)
+    fi, fv, fns, frec = gu.search(idx, Q, **kw)
+    assert (ns == fns).all() and (rec == frec).all() and (gv == fv).all()
+    order, h = idx.candidates(gu.to_dev(Q), 0.3)
+    parity.check_aps(X, Q, ps, gi, gv, ns, rec, order.cpu().numpy(), h.cpu().numpy(), "l2", 0.3, 0.9, 10)
+    idx.free()
+
+
+def test_codes_follow_rows_through_updates_maintenance_and_save_load(tmp_path):
+    from paper_2506_03437_amd import Index
+    spec = synth.MixtureSpec(key=73, n=20_000, d=64, n_components=30, zipf_s=1.1)
+    X = synth.database(spec)
+    Q = synth.queries(spec, 200)
+    rng = np.random.default_rng(8)
+    print("[build] product codes under updates n=20000 d=64 m=16 nlist=40", flush=True)
+    idx = gu.build(X, metric="l2", nlist=40, kmeans_iters=4, seed=6, pq_m=M)
+    books, before = codes_by_row(idx, X.shape[0])
+    # inserts that overflow partitions (relocations move the codes), deletes that compact them
+    Xn = (X[rng.choice(X.shape[0], 3000, replace=False)] + 0.05 * rng.standard_normal((3000, 64))).astype(np.float32)
+    ids_n = np.arange(X.shape[0], X.shape[0] + 3000, dtype=np.int64)
+    idx.insert(gu.to_dev(Xn), gu.to_dev(ids_n))
+    dead = rng.choice(X.shape[0], 6000, replace=False).astype(np.int64)
+    idx.delete(gu.to_dev(dead))
+    Xa = np.concatenate([X, Xn])
+    keep = np.setdiff1d(np.arange(Xa.shape[0]), dead)
+
+    def check_codes(where):
+        b2, c2 = codes_by_row(idx, Xa.shape[0])
+        np.testing.assert_array_equal(b2, books)
+        old = keep[keep < X.shape[0]]
+        assert (c2[old] == before[old]).all(), f"{where}: a row's codes changed"
+        bad = code_violations(Xn, c2[ids_n], books)   # (no inserted row is deleted)
+        assert not bad, f"{where}: inserted rows' codes are not the nearest codewords: {bad[:3]}"
+        return c2
+
+    codes = check_codes("after updates")
+    # a maintenance pass that splits the hot partitions (moves rows between partitions)
+    hits = np.full(40, 50, dtype=np.int64)
+    hits[:4] = 1000
+    rep, _ = idx.maintain([1, 100, 1000, 10000], [1.0, 3.0, 60.0, 1000.0], tau=0.0, hits=hits, window=1000,
+                          refine_radius=4, refine_iters=1, merge_below=0)
+    assert rep["splits"] >= 1
+    codes = check_codes("after maintenance")
+    ids_all = np.arange(Xa.shape[0])
+    ps = gu.oracle_view(idx, Xa[keep], ids_all[keep])
+    codes_rows = codes[keep]
+    gi, gv, ns, rec = gu.search(idx, Q, k=10, nprobe=4, scan_dtype="pq8", rerank_factor=4)
+    for i in range(0, Q.shape[0], 5):
+        key = np.sort(oknn.distances(Q[i][None], ps.C, "l2")[0])
+        if key[4] - key[3] <= 1e-5 * key[3]:
+            continue
+        _, order = oivf.centroid_ranking(Q[i], ps.C, "l2")
+        check_pq_results(Q[i], Xa[keep], ps, codes_rows, books, order[:4], 40, 10, "l2", gi[i], gv[i], f"query {i}")
+    # a save and load keeps the codebook and every row's codes
+    path = str(tmp_path / "pq.qk")
+    a = gu.search(idx, Q, k=10, recall_target=0.9, f_M=0.2, scan_dtype="pq8")
+    idx.save(path)
+    b = Index.load(path)
+    b_books, b_codes = b.export_pq()
+    np.testing.assert_array_equal(b_books.cpu().numpy().astype(np.float64), books)
+    np.testing.assert_array_equal(b_codes.cpu().numpy(), idx.export_pq()[1].cpu().numpy())
+    r = gu.search(b, Q, k=10, recall_target=0.9, f_M=0.2, scan_dtype="pq8")
+    # same scores, so the same stops; only the order of equal scores (store slots) may differ
+    assert (a[2] == r[2]).all() and (a[3] == r[3]).all()
+    assert (a[0] == r[0]).all(axis=1).mean() >= 0.98
+    b.free()
+    idx.free()
+
+
+def test_without_fp32_tiles_and_lambda_profile():
+    spec = synth.MixtureSpec(key=74, n=20_000, d=64, n_components=20)
+    X = synth.database(spec)
+    Q = synth.queries(spec, 100)
+    print("[build] product codes without FP32 tiles", flush=True)
+    full = gu.build(X, metric="l2", nlist=32, kmeans_iters=3, seed=2, pq_m=M)
+    book, _ = full.export_pq()
+    C, _, _ = full.export()
+    lean = gu.build(X, metric="l2", nlist=32, kmeans_iters=3, seed=2, pq_m=M, pq_codebook=book, centroids=C,
+                    f32_tiles=False)
+    kw = dict(k=10, recall_target=0.9, f_M=0.2, scan_dtype="pq8")
+    for x, y in zip(gu.search(full, Q, **kw), gu.search(lean, Q, **kw)):
+        assert (x == y).all()
+    from paper_2506_03437_amd import quake
+    with pytest.raises(quake.QuakeError) as e:
+        gu.search(lean, Q, k=10, recall_target=0.9)      # no FP32 tiles for the plain FP32 scan
+    assert e.value.code == quake.E_INVALID
+    lam = full.profile_latency([64, 1024], nq=512, reps=2, k=10, scan_dtype="pq8")
+    assert np.isfinite(lam).all() and (lam >= 0).all() and lam[-1] > 0
+    full.free()
+    lean.free()
+
+
+def test_unsupported_combinations_are_refused():
+    import torch
+    from paper_2506_03437_amd import quake
+    spec = synth.MixtureSpec(key=75, n=4_000, d=32, n_components=10)
+    X = synth.database(spec)
+    Q = synth.queries(spec, 8)
+    print("[build] product-code refusals", flush=True)
+    plain = gu.build(X, metric="l2", nlist=10, kmeans_iters=2, seed=1)
+    coded = gu.build(X, metric="l2", nlist=10, kmeans_iters=2, seed=1, pq_m=8)
+    qd = gu.to_dev(Q)
+    outs = (torch.empty((8, 10), dtype=torch.int64, device=qd.device), torch.empty((8, 10), device=qd.device),
+            torch.empty(8, dtype=torch.int32, device=qd.device), torch.empty(8, dtype=torch.float64, device=qd.device))
+    book = _f32(np.zeros((8, 256, 4)))
+    for call in (
+        lambda: gu.search(plain, Q, k=10, recall_target=0.9, scan_dtype="pq8"),                 # no codes
+        lambda: gu.search(coded, Q, k=10, recall_target=0.9, scan_dtype="pq8", scan_mode="batched"),
+        lambda: gu.search(coded, Q, k=10, recall_target=0.9, scan_dtype="pq8", rerank_factor=-1),
+        lambda: gu.search(coded, Q, k=20, recall_target=0.9, scan_dtype="pq8"),                 # 80 candidates
+        lambda: quake.quake_search_noalloc(coded.handle, qd, outputs=outs, k=10, recall_target=0.9, scan_dtype="pq8"),
+        lambda: quake.quake_server_create(coded.handle, k=10, recall_target=0.9, scan_dtype="pq8"),
+        lambda: gu.build(X, metric="l2", nlist=10, pq_m=6),                                      # not a multiple of 4
+        lambda: gu.build(X[:, :30].copy(), metric="l2", nlist=10, pq_m=8),                       # does not divide d
+        lambda: gu.build(X, metric="l2", nlist=10, pq_m=0, pq_codebook=book),                    # codebook, no pq_m
+        lambda: gu.build(np.concatenate([X] * 5, 1), metric="l2", nlist=10, pq_m=4),            # 40 > 32 per subspace
+        lambda: gu.build(X[:200].copy(), metric="l2", nlist=4, pq_m=8),                          # too few rows to train
+    ):
+        with pytest.raises(quake.QuakeError) as e:
+            call()
+        assert e.value.code == quake.E_INVALID
+    plain.free()
+    coded.free()
