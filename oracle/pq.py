@@ -9,22 +9,26 @@ Product quantization (Jegou, Douze and Schmid, IEEE TPAMI 33(1), 2011): the
 d dimensions are split into M subspaces of d / M consecutive dimensions; in
 each, a codebook of 256 codewords; a vector is stored as the M indices of
 its nearest codewords.  A query is compared with a stored vector through
-the vector its codes decode to, summed subspace by subspace from a table of
-query-to-codeword values ("asymmetric distance": the query is not
-quantized).
+the vector its codes decode to ("asymmetric distance": the query is not
+quantized).  In a partitioned index the codes quantize each row's residual
+to its partition's centroid (the paper's IVFADC), so a row decodes to
+centroid + decoded residual.
 
 Readings of points the paper leaves open (each is also listed with its
 reason in the design notes):
-* P1  the codes quantize the vectors themselves, not their residuals to the
-      partition centroid, with one codebook for the whole index: a row's
-      code does not depend on its partition, so splits, merges and moves
-      carry it unchanged.
+* P1  the codes quantize residuals to the partition centroid, with one
+      codebook for the whole index; a row whose partition or centroid
+      changes (split, merge, refinement) is encoded again.  (Codes of the
+      vectors themselves spend the 256 codewords of a subspace on the
+      spread of the cluster centres and cannot rank rows inside one
+      cluster.)
 * P2  each subspace's codebook is trained by Lloyd's k-means in squared
-      Euclidean distance (for either metric), started from 256 distinct
-      rows; a codeword left without rows keeps its value.  A row's code in
-      a subspace is its nearest codeword, ties to the lower index.
+      Euclidean distance (for either metric) over residuals, started from
+      256 distinct rows; a codeword left without rows keeps its value.  A
+      row's code in a subspace is its nearest codeword, ties to the lower
+      index.
 * P3  the scan scores a row by the asymmetric value: squared L2 distance or
-      inner product of the query and the decoded row.
+      inner product of the query and the row's decoded vector.
 * P4  APS runs unchanged on the scanned scores: rho comes from the k-th
       best score so far; the scan keeps the best r * k rows by score, and
       once the search stops those candidates are scored exactly and the
@@ -62,9 +66,14 @@ def _sq_dist(A: np.ndarray, B: np.ndarray) -> np.ndarray:
     return (diff * diff).sum(-1)
 
 
+def residuals(ps: PartitionedSet) -> np.ndarray:
+    """Every row of ps minus its partition's centroid (FP64)."""
+    return np.asarray(ps.X, dtype=np.float64) - ps.C[ps.assign]
+
+
 def train(X: np.ndarray, m: int, iters: int, seed: int) -> Tuple[np.ndarray, List[np.ndarray]]:
-    """Codebooks [m][256][d/m] (FP64) by Lloyd's k-means in every subspace
-    (reading P2), and each subspace's distortion (mean squared error of the
+    """Codebooks [m][256][d/m] (FP64) of the rows X (residuals, reading P2)
+    by Lloyd's k-means in every subspace, and each subspace's distortion (mean squared error of the
     rows against their nearest codeword) before the first and after every
     iteration.  All subspaces start from the same 256 distinct rows."""
     X = np.asarray(X, dtype=np.float64)
@@ -94,10 +103,14 @@ def train(X: np.ndarray, m: int, iters: int, seed: int) -> Tuple[np.ndarray, Lis
     return books, history
 
 
-def encode(X: np.ndarray, books: np.ndarray) -> np.ndarray:
-    """[n][m] uint8 codes: the nearest codeword of every subspace, ties to
-    the lower index (np.argmin keeps the first of equal values)."""
+def encode(X: np.ndarray, books: np.ndarray, base: Optional[np.ndarray] = None) -> np.ndarray:
+    """[n][m] uint8 codes of X - base (base: each row's partition centroid,
+    or None for the rows themselves): the nearest codeword of every
+    subspace, ties to the lower index (np.argmin keeps the first of equal
+    values)."""
     X = np.asarray(X, dtype=np.float64)
+    if base is not None:
+        X = X - np.asarray(base, dtype=np.float64)
     m, _, ds = books.shape
     codes = np.empty((X.shape[0], m), dtype=np.uint8)
     for s in range(m):
@@ -105,12 +118,14 @@ def encode(X: np.ndarray, books: np.ndarray) -> np.ndarray:
     return codes
 
 
-def decode(codes: np.ndarray, books: np.ndarray) -> np.ndarray:
-    """[n][d] FP64 vectors the codes stand for."""
+def decode(codes: np.ndarray, books: np.ndarray, base: Optional[np.ndarray] = None) -> np.ndarray:
+    """[n][d] FP64 vectors the codes stand for (plus base when given)."""
     m, _, ds = books.shape
     out = np.empty((codes.shape[0], m * ds))
     for s in range(m):
         out[:, s * ds:(s + 1) * ds] = books[s][codes[:, s].astype(np.int64)]
+    if base is not None:
+        out += np.asarray(base, dtype=np.float64)
     return out
 
 
@@ -130,12 +145,11 @@ def tables(q: np.ndarray, books: np.ndarray, metric: str) -> np.ndarray:
     return T
 
 
-def asymmetric(q: np.ndarray, codes: np.ndarray, books: np.ndarray, metric: str) -> np.ndarray:
-    """Value of every coded row for the query: the sum over subspaces of the
-    table entry its code selects."""
-    T = tables(q, books, metric)
-    m = books.shape[0]
-    return T[np.arange(m)[None, :], codes.astype(np.int64)].sum(1)
+def asymmetric(q: np.ndarray, codes: np.ndarray, books: np.ndarray, metric: str,
+               base: Optional[np.ndarray] = None) -> np.ndarray:
+    """Value of every coded row for the query (reading P3): the exact value
+    of the query and the row's decoded vector (base + decoded residual)."""
+    return distances(np.asarray(q)[None, :], decode(codes, books, base), metric)[0]
 
 
 def rerank(q: np.ndarray, ps: PartitionedSet, ids: np.ndarray, k: int, metric: str):
@@ -152,11 +166,11 @@ def pq_search_one(ps: PartitionedSet, codes: np.ndarray, books: np.ndarray, q: n
                   table: CapTable, keep: int, order: Optional[np.ndarray] = None,
                   h: Optional[np.ndarray] = None):
     """APS over the compressed rows (reading P4): ``codes`` [n][m] are the
-    codes of ps.X's rows.  Returns (ids [k], values [k], the APS result over
+    codes of ps.X's rows' residuals to their partitions' centroids.  Returns (ids [k], values [k], the APS result over
     the scores, whose ids are the ``keep`` candidates)."""
     res: APSResult = aps_search_one(
         ps, q, params, table, order, h,
-        row_values=lambda rows: asymmetric(q, codes[rows], books, params.metric), keep=keep)
+        row_values=lambda rows: asymmetric(q, codes[rows], books, params.metric, ps.C[ps.assign[rows]]), keep=keep)
     ri, rv = rerank(q, ps, res.ids, params.k, params.metric)
     return ri, rv, res
 
@@ -168,6 +182,7 @@ def pq_nprobe_one(ps: PartitionedSet, codes: np.ndarray, books: np.ndarray, q: n
     the best k of them by exact value.  Returns (ids, values, candidates)."""
     parts = centroid_ranking(q, ps.C, metric)[1][:nprobe]
     rows = np.concatenate([ps.members[int(p)] for p in parts])
-    ci, _ = select_topk(asymmetric(q, codes[rows], books, metric), ps.ids[rows], keep, metric)
+    ci, _ = select_topk(asymmetric(q, codes[rows], books, metric, ps.C[ps.assign[rows]]), ps.ids[rows], keep,
+                        metric)
     ri, rv = rerank(q, ps, ci, k, metric)
     return ri, rv, ci

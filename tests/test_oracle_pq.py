@@ -3,11 +3,12 @@ readings P1-P4).
 
 The codes are pinned by brute force (every codeword tried, ties to the
 lower index) and by a lossless codebook that decodes every row exactly; the
-asymmetric value by the exact distance to the decoded row (a summation that
-shares nothing with the table); training by Lloyd's monotone distortion and
-by the case where the codebook is the rows themselves; the search by its
-reduction to the plain adaptive search when the codes are lossless, and by
-brute force over the rows of the partitions it scanned.
+asymmetric value (the exact value of the decoded row) by the per-subspace
+table sums of the product-quantization paper, which share nothing with it;
+training by Lloyd's monotone distortion and by the case where the codebook
+is the rows themselves; the search by its reduction to the plain adaptive
+search when the codes are lossless, and by brute force over the rows of the
+partitions it scanned.
 """
 
 import numpy as np
@@ -16,7 +17,7 @@ import pytest
 from oracle import aps, ivf, kmeans, knn, pq
 
 
-def lossless(rng, n, m, ds, distinct=200):
+def lossless(rng, n, m, ds, distinct=200, lo=-4, hi=4):
     """Rows whose subvectors in each subspace are drawn from `distinct`
     small-integer vectors, and a codebook holding exactly those vectors
     (the other codewords far away)."""
@@ -25,7 +26,7 @@ def lossless(rng, n, m, ds, distinct=200):
     for s in range(m):
         vals = set()
         while len(vals) < distinct:
-            vals.add(tuple(rng.integers(-4, 5, ds).tolist()))
+            vals.add(tuple(rng.integers(lo, hi + 1, ds).tolist()))
         vals = np.array(sorted(vals), dtype=np.float64)
         books[s, :distinct] = vals
         books[s, distinct:] = 1000.0 + np.arange(256 - distinct)[:, None]
@@ -54,26 +55,39 @@ def test_encode_is_the_nearest_codeword_by_brute_force():
 
 def test_lossless_codebook_decodes_every_row():
     rng = np.random.default_rng(2)
-    X, books = lossless(rng, 500, 4, 3)
-    codes = pq.encode(X, books)
-    np.testing.assert_array_equal(pq.decode(codes, books), X.astype(np.float64))
+    R, books = lossless(rng, 500, 4, 3)
+    base = rng.integers(-20, 21, (500, 12)).astype(np.float64)   # integer centroids of the rows
+    X = R + base
+    codes = pq.encode(X, books, base)
+    np.testing.assert_array_equal(codes, pq.encode(R, books))
+    np.testing.assert_array_equal(pq.decode(codes, books, base), X)
     q = rng.integers(-4, 5, 12).astype(np.float32)
     for metric in ("l2", "ip"):
-        np.testing.assert_array_equal(pq.asymmetric(q, codes, books, metric), knn.distances(q[None], X, metric)[0])
+        np.testing.assert_array_equal(pq.asymmetric(q, codes, books, metric, base),
+                                      knn.distances(q[None], X, metric)[0])
 
 
 @pytest.mark.parametrize("metric", ["l2", "ip"])
-def test_asymmetric_value_is_the_value_of_the_decoded_row(metric):
+def test_asymmetric_value_is_the_sum_of_table_entries(metric):
+    """With one centroid c for the rows, the value of q and c + decoded
+    residual is, per subspace, a table entry of q - c (L2), or <q, c> plus
+    table entries of q (IP)."""
     rng = np.random.default_rng(3)
     m, ds = 4, 4
     books = rng.standard_normal((m, 256, ds))
     codes = rng.integers(0, 256, (300, m)).astype(np.uint8)
     q = rng.standard_normal(m * ds)
-    got = pq.asymmetric(q, codes, books, metric)
-    want = knn.distances(q[None], pq.decode(codes, books), metric)[0]
+    c = rng.standard_normal(m * ds)
+    got = pq.asymmetric(q, codes, books, metric, np.tile(c, (300, 1)))
+    if metric == "l2":
+        T = pq.tables(q - c, books, "l2")
+        want = np.array([sum(T[t, codes[r, t]] for t in range(m)) for r in range(300)])
+    else:
+        T = pq.tables(q, books, "ip")
+        want = np.array([float(q @ c) + sum(T[t, codes[r, t]] for t in range(m)) for r in range(300)])
     np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12)
     # the subspaces are not interchangeable: reversing them changes the values
-    assert not np.allclose(pq.asymmetric(q, codes[:, ::-1], books, metric), want)
+    assert not np.allclose(pq.asymmetric(q, codes[:, ::-1], books, metric, np.tile(c, (300, 1))), want)
 
 
 def test_training_lowers_the_distortion():
@@ -107,13 +121,19 @@ def _index(X, nlist, seed):
 
 
 def test_lossless_codes_give_the_plain_adaptive_search():
-    # (L2: the inner-product radius assumes unit-norm rows, which integer rows are not)
+    """Integer centroids and residuals from a lossless codebook: every score
+    is the exact distance.  (L2: the inner-product radius assumes unit-norm
+    rows, which integer rows are not.)"""
     metric = "l2"
     rng = np.random.default_rng(7)
-    X, books = lossless(rng, 3000, 4, 4)
-    ps = _index(X, 30, 8)
-    codes = pq.encode(ps.X, books)
-    Q = rng.integers(-4, 5, (25, 16)).astype(np.float32)
+    R, books = lossless(rng, 3000, 4, 4, lo=-2, hi=2)
+    C = rng.integers(-12, 13, (30, 16)).astype(np.float64)
+    assign = rng.integers(0, 30, 3000)
+    X = (R + C[assign]).astype(np.float32)
+    ps = ivf.PartitionedSet(X, np.arange(3000, dtype=np.int64) + 7, assign, C)
+    codes = pq.encode(ps.X, books, ps.C[ps.assign])
+    np.testing.assert_array_equal(pq.decode(codes, books, ps.C[ps.assign]), X)
+    Q = rng.integers(-12, 13, (25, 16)).astype(np.float32)
     tab = aps.CapTable(16)
     prm = aps.APSParams(k=10, recall_target=0.9, f_M=0.5, metric=metric)
     for q in Q:
@@ -135,8 +155,8 @@ def test_wide_scan_is_the_exact_rerank_of_the_best_scores(metric):
         X /= np.linalg.norm(X, axis=1, keepdims=True)   # the radius assumes unit-norm rows
     X = X.astype(np.float32)
     ps = _index(X, 16, 10)
-    books, _ = pq.train(ps.X, 4, 2, seed=3)
-    codes = pq.encode(ps.X, books)
+    books, _ = pq.train(pq.residuals(ps), 4, 2, seed=3)
+    codes = pq.encode(ps.X, books, ps.C[ps.assign])
     tab = aps.CapTable(8)
     prm = aps.APSParams(k=5, recall_target=1.0, f_M=1.0, metric=metric)
     for q in rng.standard_normal((15, 8)).astype(np.float32):
@@ -144,7 +164,7 @@ def test_wide_scan_is_the_exact_rerank_of_the_best_scores(metric):
         # (the estimate may reach 1 before the last candidates: their caps are empty)
         rows = np.nonzero(np.isin(ps.assign, res.order[:res.m]))[0]
         # brute force: the 20 best scores of those rows, then the 5 best exact values among them
-        s = pq.asymmetric(q, codes[rows], books, metric)
+        s = pq.asymmetric(q, codes[rows], books, metric, ps.C[ps.assign[rows]])
         key = -s if metric == "ip" else s
         cand = rows[np.lexsort((ps.ids[rows], key))[:20]]
         ex = knn.distances(q[None], ps.X[cand], metric)[0]
@@ -161,15 +181,15 @@ def test_fixed_nprobe_by_brute_force():
     rng = np.random.default_rng(11)
     X = rng.standard_normal((1500, 8)).astype(np.float32)
     ps = _index(X, 12, 12)
-    books, _ = pq.train(ps.X, 2, 2, seed=4)
-    codes = pq.encode(ps.X, books)
+    books, _ = pq.train(pq.residuals(ps), 2, 2, seed=4)
+    codes = pq.encode(ps.X, books, ps.C[ps.assign])
     for q in rng.standard_normal((10, 8)).astype(np.float32):
         ri, rv, ci = pq.pq_nprobe_one(ps, codes, books, q, 5, 3, "l2", 15)
         d0 = ((ps.C - q.astype(np.float64)) ** 2).sum(1)
         parts = np.argsort(d0, kind="stable")[:3]
         rows = np.nonzero(np.isin(ps.assign, parts))[0]
-        s = np.array([sum(float(((books[t, codes[r, t]] - q[4 * t:4 * t + 4]) ** 2).sum()) for t in range(2))
-                      for r in rows])
+        s = np.array([sum(float(((ps.C[ps.assign[r], 4 * t:4 * t + 4] + books[t, codes[r, t]]
+                                  - q[4 * t:4 * t + 4]) ** 2).sum()) for t in range(2)) for r in rows])
         cand = rows[np.lexsort((ps.ids[rows], s))[:15]]
         assert sorted(ci.tolist()) == sorted(ps.ids[cand].tolist())
         ex = ((ps.X[cand].astype(np.float64) - q) ** 2).sum(1)
