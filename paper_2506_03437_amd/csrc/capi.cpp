@@ -299,8 +299,8 @@ void alloc_store_arrays(quake_index* idx, Store& st, int64_t tiles, int dtype16,
       QK_HIP(hipMemsetAsync(st.rows32, 0, slots * st.dp * sizeof(float), s));
     }
     st.pq_m = idx->pq_m;
-    st.codes = mem.alloc<uint32_t>(slots * (idx->pq_m / 4));
-    QK_HIP(hipMemsetAsync(st.codes, 0, slots * (idx->pq_m / 4) * sizeof(uint32_t), s));
+    st.codes = mem.alloc<uint32_t>(slots * qk::pq_words(idx->pq_m));
+    QK_HIP(hipMemsetAsync(st.codes, 0, slots * qk::pq_words(idx->pq_m) * sizeof(uint32_t), s));
   }
   st.ids = mem.alloc<int64_t>(slots);
   QK_HIP(hipMemsetAsync(st.ids, 0xff, slots * sizeof(int64_t), s));
@@ -327,10 +327,12 @@ void upload_table(Store& st, hipStream_t s) {
 // Place rows into a fresh store: partition p gets capacity for its rows plus
 // slack, rounded up to whole tiles; rows keep their input order within a
 // partition.
-// Product-quantization codebook of rows x[n][d] into idx->pq_book
-// [pq_m][256][pq_ds]: Lloyd's k-means (squared L2, from 256 distinct rows)
-// in each subspace over the same seeded sample of at most 65,536 rows.
-void train_codebook(quake_index* idx, const float* x, int64_t n, int iters, uint64_t seed, hipStream_t s) {
+// Product-quantization codebook of the residuals of rows x[n][d] to their
+// centroids C[assign[i]] ([.][dp]) into idx->pq_book [pq_m][256][pq_ds]:
+// Lloyd's k-means (squared L2, from 256 distinct rows) in each subspace over
+// the same seeded sample of at most 65,536 rows.
+void train_codebook(quake_index* idx, const float* x, int64_t n, const int32_t* assign, const float* C, int iters,
+                    uint64_t seed, hipStream_t s) {
   const int M = idx->pq_m, ds = idx->pq_ds, d = idx->d;
   const int dsp = (int)round_up(ds, 8);
   const int64_t nt = std::min<int64_t>(n, 65536);
@@ -346,7 +348,7 @@ void train_codebook(quake_index* idx, const float* x, int64_t n, int iters, uint
   Tmp<float> sub(idx->mem, (size_t)nt * dsp), cent(idx->mem, (size_t)256 * dsp);
   QK_HIP(hipMemcpyAsync(d_rows.p, rows.data(), nt * sizeof(int64_t), hipMemcpyHostToDevice, s));
   for (int m = 0; m < M; ++m) {
-    qk::launch_pq_subspace(x, nt, d, d_rows.p, m * ds, ds, dsp, sub.p, s);
+    qk::launch_pq_subspace(x, nt, d, d_rows.p, assign, C, idx->dp, m * ds, ds, dsp, sub.p, s);
     kmeans(idx->mem, sub.p, nt, dsp, 256, iters, seed + (uint64_t)m, QUAKE_L2, cent.p, s);
     QK_HIP(hipMemcpy2DAsync(idx->pq_book + (size_t)m * 256 * ds, ds * sizeof(float), cent.p, dsp * sizeof(float),
                             ds * sizeof(float), 256, hipMemcpyDeviceToDevice, s));
@@ -408,7 +410,7 @@ void build_store(quake_index* idx, Store& st, const float* xin, int d, const int
     qk::launch_scatter(xin, n, d, st.dp, st.dp16, ids, d_slot.p, st.v32, st.v16, dtype16, st.rows32, st.ids, s);
     qk::launch_norm16(st, dtype16, s);
     if (st.attr && attrs) qk::launch_put_u32(attrs, d_slot.p, n, st.attr, s);
-    if (st.codes) qk::launch_pq_encode(xin, n, d, d_slot.p, idx->pq_book, st.pq_m, idx->pq_ds, st.codes, s);
+    if (st.codes) qk::encode_rows(idx, st, d_slot.p, d_assign, n, s);
     QK_HIP(hipStreamSynchronize(s));
   }
   st.live = n;
@@ -445,7 +447,7 @@ void repack_arena(quake_index* idx, Store& st, int64_t tiles, hipStream_t s) {
       QK_HIP(hipMemcpyAsync(fresh.ids + b, st.ids + a, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
       if (st.attr) QK_HIP(hipMemcpyAsync(fresh.attr + b, st.attr + a, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
       if (st.codes) {
-        const size_t w = (size_t)st.pq_m / 4;  // code words per slot (tile-aligned ranges)
+        const size_t w = (size_t)qk::pq_words(st.pq_m);  // code words per slot (tile-aligned ranges)
         QK_HIP(hipMemcpyAsync(fresh.codes + b * w, st.codes + a * w, n * w * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
       }
     }
@@ -500,7 +502,8 @@ bool grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s, bool r
   QK_HIP(hipMemcpyAsync(fresh.ids, st.ids, used * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
   if (st.attr) QK_HIP(hipMemcpyAsync(fresh.attr, st.attr, used * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
   if (st.codes)
-    QK_HIP(hipMemcpyAsync(fresh.codes, st.codes, used * (st.pq_m / 4) * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    QK_HIP(hipMemcpyAsync(fresh.codes, st.codes, used * qk::pq_words(st.pq_m) * sizeof(uint32_t),
+                          hipMemcpyDeviceToDevice, s));
   QK_HIP(hipStreamSynchronize(s));
   for (void* p : {(void*)st.v32, (void*)st.v16, (void*)st.v16n, (void*)st.rows32, (void*)st.ids, (void*)st.attr,
                   (void*)st.codes})
@@ -538,7 +541,7 @@ void relocate(Store& st, int64_t p, int32_t cap, hipStream_t s) {
     QK_HIP(hipMemcpyAsync(st.ids + b, st.ids + a, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     if (st.attr) QK_HIP(hipMemcpyAsync(st.attr + b, st.attr + a, n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     if (st.codes) {
-      const size_t w = (size_t)st.pq_m / 4;
+      const size_t w = (size_t)qk::pq_words(st.pq_m);
       QK_HIP(hipMemcpyAsync(st.codes + b * w, st.codes + a * w, n * w * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     }
     // the old slots no longer hold the partition's vectors
@@ -650,6 +653,40 @@ void require_finite(quake_index* idx, const float* x, int64_t count, const char*
 
 namespace qk {
 
+// Product codes of the rows at `slots` (partition parts[i]): their residuals
+// to the partition centroids, read from the row-major FP32 copy.
+void encode_rows(quake_index* idx, const Store& st, const int64_t* slots, const int32_t* parts, int64_t n,
+                     hipStream_t s) {
+  if (!st.codes || n <= 0) return;
+  qk::launch_pq_encode(st.rows32, st.dp, slots, parts, n, st.centroids, idx->pq_book, st.pq_m, idx->pq_ds,
+                       idx->metric, st.codes, s);
+}
+
+// Product codes of every live row of `st` again (after its partitions or
+// centroids changed).
+void encode_store(quake_index* idx, const Store& st, hipStream_t s) {
+  if (!st.codes || st.live <= 0) return;
+  std::vector<int64_t> sid((size_t)st.tiles * qk::TILE);
+  QK_HIP(hipMemcpyAsync(sid.data(), st.ids, sid.size() * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  std::vector<int64_t> slots;
+  std::vector<int32_t> parts;
+  slots.reserve(st.live);
+  parts.reserve(st.live);
+  for (int64_t p = 0; p < st.nlist; ++p)
+    for (int64_t j = 0; j < st.size[p]; ++j)
+      if (sid[st.off[p] * qk::TILE + j] >= 0) {
+        slots.push_back(st.off[p] * qk::TILE + j);
+        parts.push_back((int32_t)p);
+      }
+  Tmp<int64_t> d_slots(idx->mem, std::max<size_t>(slots.size(), 1));
+  Tmp<int32_t> d_parts(idx->mem, std::max<size_t>(parts.size(), 1));
+  QK_HIP(hipMemcpyAsync(d_slots.p, slots.data(), slots.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  QK_HIP(hipMemcpyAsync(d_parts.p, parts.data(), parts.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  encode_rows(idx, st, d_slots.p, d_parts.p, (int64_t)slots.size(), s);
+  QK_HIP(hipStreamSynchronize(s));
+}
+
 void store_grow_arena(quake_index* idx, Store& st, int64_t need, hipStream_t s) { grow_arena(idx, st, need, s, false); }
 void store_relocate(Store& st, int64_t p, int32_t cap, hipStream_t s) { relocate(st, p, cap, s); }
 void store_upload_table(Store& st, hipStream_t s) { upload_table(st, s); }
@@ -723,7 +760,12 @@ void insert_rows(quake_index* idx, Store& st, IdMap& map, const float* x, const 
   launch_scatter(x, n, idx->d, dp, st.dp16, ids, d_slot.p, st.v32, st.v16, st.v16 ? idx->storage : QUAKE_F32,
                  st.rows32, st.ids, s);
   launch_norm16_slots(st, d_slot.p, n, idx->storage, s);
-  if (st.codes) launch_pq_encode(x, n, idx->d, d_slot.p, idx->pq_book, st.pq_m, idx->pq_ds, st.codes, s);
+  std::unique_ptr<Tmp<int32_t>> d_part;
+  if (st.codes) {
+    d_part.reset(new Tmp<int32_t>(idx->mem, n));
+    QK_HIP(hipMemcpyAsync(d_part->p, part.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    encode_rows(idx, st, d_slot.p, d_part->p, n, s);
+  }
   if (st.attr) {
     launch_put_u32(attrs, d_slot.p, n, st.attr, s);
     st.attr_dirty = true;
@@ -1611,20 +1653,6 @@ quake_index* qk::build_index(const float* x, const int64_t* ids, int64_t n, int3
     xpad = xpad_buf->p;
   }
 
-  if (params->pq_m > 0) {
-    // the codebook comes before the store: build_store encodes the rows
-    idx->pq_m = params->pq_m;
-    idx->pq_ds = d / params->pq_m;
-    const size_t book = (size_t)idx->pq_m * 256 * idx->pq_ds;
-    idx->pq_book = idx->mem.alloc<float>(book);
-    if (params->pq_codebook) {
-      require_finite(idx.get(), params->pq_codebook, (int64_t)book, "pq_codebook", s);
-      QK_HIP(hipMemcpyAsync(idx->pq_book, params->pq_codebook, book * sizeof(float), hipMemcpyDeviceToDevice, s));
-    } else {
-      train_codebook(idx.get(), x, n, params->kmeans_iters, params->seed, s);
-    }
-  }
-
   Store& L0 = idx->L0;
   L0.d = d;
   L0.dp = dp;
@@ -1648,15 +1676,29 @@ quake_index* qk::build_index(const float* x, const int64_t* ids, int64_t n, int3
   } else {
     kmeans(idx->mem, xpad, n, dp, L0.nlist, params->kmeans_iters, params->seed, idx->metric, L0.centroids, s);
   }
-  if (params->assign) {
-    build_store(idx.get(), L0, x, d, ids, n, params->assign, params->capacity_slack, params->storage_dtype,
-                f32_tiles, s, params->attrs);
-  } else {
-    Tmp<int32_t> assign(idx->mem, n);
-    qk::launch_assign(xpad, n, dp, L0.centroids, L0.nlist, idx->metric, assign.p, s);
-    build_store(idx.get(), L0, x, d, ids, n, assign.p, params->capacity_slack, params->storage_dtype, f32_tiles,
-                s, params->attrs);
+  std::unique_ptr<Tmp<int32_t>> assign_buf;
+  const int32_t* assign = params->assign;
+  if (!assign) {
+    assign_buf.reset(new Tmp<int32_t>(idx->mem, n));
+    qk::launch_assign(xpad, n, dp, L0.centroids, L0.nlist, idx->metric, assign_buf->p, s);
+    assign = assign_buf->p;
   }
+  if (params->pq_m > 0) {
+    // the codebook comes before the store (build_store encodes the rows'
+    // residuals to their centroids); without one given it is trained on them
+    idx->pq_m = params->pq_m;
+    idx->pq_ds = d / params->pq_m;
+    const size_t book = (size_t)idx->pq_m * 256 * idx->pq_ds;
+    idx->pq_book = idx->mem.alloc<float>(book);
+    if (params->pq_codebook) {
+      require_finite(idx.get(), params->pq_codebook, (int64_t)book, "pq_codebook", s);
+      QK_HIP(hipMemcpyAsync(idx->pq_book, params->pq_codebook, book * sizeof(float), hipMemcpyDeviceToDevice, s));
+    } else {
+      train_codebook(idx.get(), x, n, assign, L0.centroids, params->kmeans_iters, params->seed, s);
+    }
+  }
+  build_store(idx.get(), L0, x, d, ids, n, assign, params->capacity_slack, params->storage_dtype, f32_tiles, s,
+              params->attrs);
   map_rebuild(idx.get(), idx->idmap, idx->L0, n, s);
 
   if (idx->n_levels == 2)

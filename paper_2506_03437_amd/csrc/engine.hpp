@@ -89,6 +89,11 @@ void build_top_level(quake_index* idx, int level, int64_t nlist_top, int32_t kme
 // Level 1 rebuilt over the current level-0 centroids (their nearest level-1
 // partitions; level-1 centroids unchanged) after level 0 changed (capi.cpp).
 void rebuild_level1(quake_index* idx, hipStream_t s);
+// Product codes of the rows at `slots` of `st` (partition parts[i]), or of
+// every live row of `st` (after its partitions or centroids changed).
+void encode_rows(quake_index* idx, const Store& st, const int64_t* slots, const int32_t* parts, int64_t n,
+                 hipStream_t s);
+void encode_store(quake_index* idx, const Store& st, hipStream_t s);
 // The maintenance pass behind quake_maintain (maintain.cpp).
 void maintain(quake_index* idx, const quake_maintain_params& p, quake_maintain_report* report, hipStream_t s);
 

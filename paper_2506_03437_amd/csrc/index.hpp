@@ -46,6 +46,9 @@ inline int padded_dim16(int d) {
 }
 constexpr int MAX_DIM = 4096;
 constexpr int PQ_MAX_SUB = 32;    // dimensions per product-quantization subspace
+// 32-bit words per slot of the product-code array: the codes of pq_m
+// subspaces, four per word, then the slot's FP32 residual term
+inline int pq_words(int pq_m) { return pq_m / 4 + 1; }
 constexpr int COUNTERS = 32;      // device counters of a search (Workspace::total)
 constexpr int MAX_CANDIDATES = 4096;   // APS candidate set M (and nprobe) upper bound
 
@@ -105,7 +108,8 @@ struct Store {
   uint32_t* attr = nullptr;     // [tiles * 64] label bits of every slot (level 0 of a labelled index), or null
   uint32_t* d_attr_cnt = nullptr;  // [nlist][33]: live rows carrying each label bit, then live rows
   int32_t pq_m = 0;             // subspaces of the product-quantized copy (level 0), 0 = none
-  uint32_t* codes = nullptr;    // [tiles][pq_m/4][64]: four one-byte codes of a slot per word, or null
+  uint32_t* codes = nullptr;    // [tiles][pq_words(pq_m)][64]: four one-byte codes of a slot per word, then
+                                // its residual term |r^|^2 + 2 <c, r^> (FP32 bits), or null
   mutable bool attr_dirty = true;  // d_attr_cnt must be recounted before the next filtered search
   int64_t live = 0;
   std::vector<int32_t> tomb;     // deleted slots still inside size[p]
@@ -322,10 +326,10 @@ void launch_emit(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t
 void launch_scan_f32(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);
 // Product quantization: subspace columns of sampled rows, codes at store
 // slots, per-query tables, the scan over codes, and codes by slot.
-void launch_pq_subspace(const float* x, int64_t nr, int d, const int64_t* rows, int col0, int ds, int dsp, float* out,
-                        hipStream_t s);
-void launch_pq_encode(const float* x, int64_t n, int d, const int64_t* slot, const float* book, int M, int ds,
-                      uint32_t* codes, hipStream_t s);
+void launch_pq_subspace(const float* x, int64_t nr, int d, const int64_t* rows, const int32_t* part, const float* C,
+                        int dp, int col0, int ds, int dsp, float* out, hipStream_t s);
+void launch_pq_encode(const float* rows32, int dp, const int64_t* slot, const int32_t* part, int64_t n,
+                      const float* C, const float* book, int M, int ds, int metric, uint32_t* codes, hipStream_t s);
 void launch_pq_lut(const float* q, int64_t nq, int dp, const float* book, int M, int ds, int metric, float* lut,
                    hipStream_t s);
 void launch_scan_pq(Workspace& ws, const Store& st, const RoundArgs& a, hipStream_t s);

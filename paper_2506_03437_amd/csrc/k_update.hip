@@ -137,8 +137,8 @@ void launch_mark_deleted(Store& st, const int64_t* slots, int64_t n, hipStream_t
 
 // Move vector src[i] to slot dst[i] within the store (every copy of it, its
 // label bits, product codes and id), leaving src[i] empty.  Sources and
-// destinations are disjoint.  A row's code words (cw = pq_m / 4 <= dp / 4
-// of them) are moved by the row's first cw threads.
+// destinations are disjoint.  Thread c4 of a row moves its code words c4,
+// c4 + dp/4, ... (cw of them).
 __global__ __launch_bounds__(256) void k_move_slots(const int64_t* __restrict__ src, const int64_t* __restrict__ dst,
                                                      int64_t n, int dp, int dp16, float* __restrict__ v32,
                                                      uint16_t* __restrict__ v16, float* __restrict__ v16n,
@@ -167,7 +167,8 @@ __global__ __launch_bounds__(256) void k_move_slots(const int64_t* __restrict__ 
   }
   if (rows32)
     *reinterpret_cast<float4*>(rows32 + b * dp + c4 * 4) = *reinterpret_cast<const float4*>(rows32 + a * dp + c4 * 4);
-  if (codes && c4 < cw) codes[(tb * cw + c4) * TILE + lb] = codes[(ta * cw + c4) * TILE + la];
+  if (codes)
+    for (int w = c4; w < cw; w += nch4) codes[(tb * cw + w) * TILE + lb] = codes[(ta * cw + w) * TILE + la];
   if (c4 == 0) {
     if (v16n) v16n[b] = v16n[a];
     if (attr) attr[b] = attr[a];
@@ -180,7 +181,7 @@ void launch_move_slots(Store& st, const int64_t* src, const int64_t* dst, int64_
   const int64_t total = n * (st.dp >> 2);
   if (total <= 0) return;
   hipLaunchKernelGGL(k_move_slots, grid_of(total), dim3(256), 0, s, src, dst, n, st.dp, st.dp16, st.v32, st.v16,
-                     st.v16n, st.rows32, st.ids, st.attr, st.codes, st.pq_m / 4);
+                     st.v16n, st.rows32, st.ids, st.attr, st.codes, pq_words(st.pq_m));
 }
 
 __global__ __launch_bounds__(256) void k_put_u32(const uint32_t* __restrict__ src, const int64_t* __restrict__ slot,

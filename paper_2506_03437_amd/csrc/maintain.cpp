@@ -599,6 +599,9 @@ void maintain(quake_index* idx, const quake_maintain_params& p, quake_maintain_r
   launch_fill_i32(reinterpret_cast<int32_t*>(st.d_hits), std::max<int64_t>(st.nlist, 1), 0, s);
   st.window = 0;
   st.attr_dirty = true;
+  // product codes hold residuals to the centroids: rows that changed partition
+  // and partitions whose centroid moved are encoded again (all rows, once)
+  if (st.codes && (n_split > 0 || n_delete > 0 || moved > 0)) encode_store(idx, st, s);
   QK_HIP(hipStreamSynchronize(s));
   if (idx->n_levels >= 2) rebuild_level1(idx, s);
   release_graphs(idx);

