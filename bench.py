@@ -920,6 +920,13 @@ def main():
                               args.serving_hbm_budget, args.rerank_factor, args.serving_overlap,
                               args.serving_compare)
 
+    pq = results.get("plain_pq8")
+    if pq is not None:
+        # algorithmic bytes: every (query, row) pair's codes and residual term;
+        # the per-query code tables are gathered through L1 / L2 besides
+        pq["roofline"] = {"bound": "hbm", "kernel": "k_scan_pq", "achieved": pq["scan_algorithmic_gbs"],
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": pq["scan_algorithmic_gbs"] / HBM_PEAK_GBS,
+                          "traffic": None}
     roof = None
     if batched is not None:
         ms = batched["scan_ms_per_launch"]
@@ -945,7 +952,7 @@ def main():
                              "algorithmic_gbs": plain["scan_algorithmic_gbs"],
                              "algorithmic_note": "every (query, vector) read counted; caches serve most re-reads"}
     gap = []
-    if len(ladder) == 2:
+    if "plain_fp32" in ladder and bkey in ladder:
         for tau in REPORT_TARGETS:
             a = [e for e in ladder["plain_fp32"] if e["recall_target"] == tau]
             b = [e for e in ladder[bkey] if e["recall_target"] == tau]
@@ -953,7 +960,7 @@ def main():
                 gap.append({"recall_target": tau, "fp32": a[0]["recall_at_10"],
                             f"{w.storage}_rerank": b[0]["recall_at_10"],
                             "gap": b[0]["recall_at_10"] - a[0]["recall_at_10"]})
-    head = batched or plain
+    head = batched or plain or next(iter(results.values()))
     line = {
         "metric": METRIC_NAME,
         "value": head["qps"],
@@ -980,6 +987,7 @@ def main():
         f"recall_gap_{w.storage}_minus_fp32": gap,
         bkey: batched,
         "plain_fp32": plain,
+        "plain_pq8": results.get("plain_pq8"),
         "serving": serving,
         "maintenance": maint,
         "ablation": ablation,

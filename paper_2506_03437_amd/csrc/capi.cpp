@@ -1341,8 +1341,9 @@ void run_search(quake_index* idx, const Store& st, const Job& job, int64_t nq, i
     idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[4] * idx->d * 2.0, (double)w.h_total[5] * idx->d * 2.0);
     idx->prof.add(QUAKE_PROF_SCAN_SETS, (double)w.h_total[9] * idx->d * 2.0, 0.0);
   }
-  else if (idx->prof.on && pq)  // one code byte and one table add per subspace and row
-    idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[6] * st.pq_m, (double)w.h_total[6] * st.pq_m);
+  else if (idx->prof.on && pq)  // a code byte and a table add per subspace and row, and (L2) the residual term
+    idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[6] * (st.pq_m + (idx->metric == QUAKE_L2 ? 4 : 0)),
+                  (double)w.h_total[6] * st.pq_m);
   else if (idx->prof.on)
     idx->prof.add(QUAKE_PROF_SCAN, (double)w.h_total[6] * idx->d * sizeof(float),
                   (double)w.h_total[6] * idx->d * (idx->metric == QUAKE_L2 ? 3.0 : 2.0));
