@@ -156,3 +156,6 @@ def test_level_and_label_entry_points_check_the_handle():
     assert lib.quake_level_sizes(None, out) == quake.E_STATE
     assert lib.quake_insert_attrs(None, None, None, None, 1, None) == quake.E_INVALID  # attrs missing
     assert lib.quake_insert_attrs(None, None, None, ctypes.c_void_p(8), 1, None) == quake.E_STATE
+    m = ctypes.c_int32(5)
+    assert lib.quake_export_pq(None, ctypes.byref(m), None, None, None) == quake.E_STATE
+    assert m.value == 5   # nothing written on a refused call
